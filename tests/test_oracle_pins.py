@@ -1,0 +1,292 @@
+"""Pins of the FP64 CPU oracle against facts that do not come from the
+oracle itself: values printed in the paper, closed forms, conservation laws,
+a dense direct solve, the Laplace law of a static drop, the equilibrium
+meniscus of a wetting or non-wetting phase, plane Poiseuille flow, exact
+symmetries and exact special cases.  Each test names the plausible mistake it
+would catch."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle.pyoracle import Oracle, dt_brackbill, dt_cfl, velocity_from_ca
+from paper_2105_10576_amd import cases
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _drop_case(dim, n, R, w, mu=1e-3, sigma=0.07, h=1e-5):
+    ax = np.arange(n) + 0.5
+    if dim == 2:
+        Y, X = np.meshgrid(ax, ax, indexing="ij")
+        r = np.sqrt((X - n / 2) ** 2 + (Y - n / 2) ** 2)
+        nz = 1
+    else:
+        Z, Y, X = np.meshgrid(ax, ax, ax, indexing="ij")
+        r = np.sqrt((X - n / 2) ** 2 + (Y - n / 2) ** 2 + (Z - n / 2) ** 2)
+        nz = n
+    a = (0.5 * (1 - np.tanh((r - R) / w))).reshape(-1)
+    fl = dict(rho=1000.0, mu=mu)
+    c = cases._case("drop", dim, n, n, nz, h, fl, fl, sigma, 90.0, [cases.BC_OUTLET] * 6, 0.0,
+                    np.zeros(n ** dim, np.uint8), a, 1e-6, 1, 1, 1e-6)
+    return c, r.reshape(-1)
+
+
+# ---------------------------------------------------------------------------
+# closed forms (paper Section 2.2 and the printed inlet speeds of Section 5.1)
+# ---------------------------------------------------------------------------
+
+def test_closed_forms_against_printed_values():
+    """Ca -> U reproduces the printed bench-1 inlet speeds; dt_B matches a
+    hand evaluation and scales as h^1.5; dt_CFL = h/u.  Catches a swapped
+    mu/sigma, a missing 2*pi or a wrong power of h."""
+    g = json.load(open(os.path.join(GOLD, "paper_closed_forms.json")))
+    for row in g["ca_to_speed"]:
+        u = velocity_from_ca(row["ca"], row["mu"], row["sigma"])
+        assert float("%.*g" % (row["digits"], u)) == pytest.approx(row["u_printed"], rel=1e-12)
+    for row in g["brackbill"]:
+        dtb = dt_brackbill(row["rho1"], row["rho2"], row["h"], row["sigma"])
+        assert dtb == pytest.approx(row["dt_b"], rel=row["rel"])
+        assert dt_brackbill(row["rho1"], row["rho2"], 4 * row["h"], row["sigma"]) == pytest.approx(8 * dtb, rel=1e-12)
+    assert dt_cfl(5e-6, 0.06) == pytest.approx(5e-6 / 0.06, rel=1e-15)
+
+
+def test_case_recipe_agrees_with_oracle_closed_forms():
+    """The input recipe's time steps use the same closed forms as the oracle."""
+    c = cases.channel_bubble()
+    assert c["u_inlet"] == pytest.approx(velocity_from_ca(1e-2, 1e-3, 0.07), rel=1e-14)
+    assert c["dt_vd"] == pytest.approx(0.25 * dt_cfl(1e-6, c["u_inlet"]), rel=1e-14)
+    dtb = dt_brackbill(c["rho1"], c["rho2"], c["h"], c["sigma"])
+    assert c["dt_vd"] / c["n_sub"] < dtb
+    n = cases.smallest_substeps(c["dt_vd"], dtb)
+    assert c["dt_vd"] / n < dtb and c["dt_vd"] / (n - 1) >= dtb
+
+
+# ---------------------------------------------------------------------------
+# Laplace law: curvature sign/magnitude and balanced-force pressure
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("dim,n,R,tol", [(2, 64, 16, 0.05), (3, 40, 10, 0.03)])
+def test_static_drop_laplace_jump(dim, n, R, tol):
+    """A smooth drop of phase 1 (tanh profile, width 1.5 cells) in a box
+    with open (p = 0) sides: the first capillary pressure solve gives
+    p_in - p_out = sigma/R (2D) or 2 sigma/R (3D).  Catches a sign error in
+    kappa (negative jump), a factor 2 in the gradient or the face force, or a
+    mismatch between the force and the pressure face operators."""
+    c, r = _drop_case(dim, n, R, 1.5)
+    o = Oracle(c)
+    dtb = dt_brackbill(1000.0, 1000.0, c["h"], c["sigma"])
+    rc, kf, E = o.capillary_relax(1e-3 * dtb, 1, 1, 0.0)
+    assert rc == 0 and kf == 1
+    p = o.get("p_cr")
+    jump = p[r < R - 6].mean() - p[r > R + 6].mean()
+    expected = (dim - 1) * c["sigma"] / (R * c["h"])
+    assert abs(jump / expected - 1.0) < tol
+    kappa = o.get("kappa")
+    band = (r > R - 1) & (r < R + 1)
+    assert kappa[band].mean() * R * c["h"] == pytest.approx(dim - 1, rel=0.1)
+
+
+# ---------------------------------------------------------------------------
+# wall adhesion (contact angle) sign and magnitude
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("theta", [60.0, 120.0])
+def test_meniscus_contact_angle(theta):
+    """Phase 1 fills the left half of a 2D slot of width W open at x- (p=0)
+    and closed at x+; walls at y+-.  The wall condition n.n_wall = cos(theta)
+    drives the meniscus toward p2 - p1 = 2 sigma cos(theta) / W.  Catches the
+    contact angle measured through the wrong phase (sign flip) or a wall
+    normal pointing the wrong way."""
+    h, nx, ny, mu = 1e-5, 32, 16, 0.01
+    ax = np.arange(nx) + 0.5
+    a = np.broadcast_to((0.5 * (1 - np.tanh((ax - nx / 2) / 1.5)))[None, :], (ny, nx)).reshape(-1)
+    fl = dict(rho=1000.0, mu=mu)
+    c = cases._case("men", 2, nx, ny, 1, h, fl, fl, 0.07, theta,
+                    [cases.BC_OUTLET, cases.BC_WALL, cases.BC_WALL, cases.BC_WALL, 0, 0], 0.0,
+                    np.zeros(nx * ny, np.uint8), a.copy(), 1e-6, 1, 1, 1e-6)
+    o = Oracle(c)
+    dtb = dt_brackbill(1000.0, 1000.0, h, 0.07)
+    o.capillary_relax(0.5 * dtb * 300, 300, 300, 1e-9)
+    p = o.get("p_cr").reshape(ny, nx)
+    dp = p[:, -6:].mean() - p[:, :6].mean()
+    expected = 2 * 0.07 * math.cos(math.radians(theta)) / (ny * h)
+    assert np.sign(dp) == np.sign(expected)
+    assert 0.8 < dp / expected < 1.1
+
+
+# ---------------------------------------------------------------------------
+# viscous operator and PISO: plane Poiseuille flow
+# ---------------------------------------------------------------------------
+
+def _poiseuille(ny, steps=60):
+    h, nx, mu, u = 1e-5, 48, 0.1, 0.01
+    fl = dict(rho=1000.0, mu=mu)
+    c = cases._case("pois", 2, nx, ny, 1, h, fl, fl, 0.07, 90.0,
+                    [cases.BC_INLET, cases.BC_OUTLET, cases.BC_WALL, cases.BC_WALL, 0, 0], u,
+                    np.zeros(nx * ny, np.uint8), np.zeros(nx * ny), 1e-6, 1, 1, 1e-6)
+    o = Oracle(c)
+    for _ in range(steps):
+        assert o.viscous_step(0.25 * h / u) == 0
+    U = o.get("U_vd").reshape(2, ny, nx)
+    p = o.get("p_vd").reshape(ny, nx)
+    H = ny * h
+    y = (np.arange(ny) + 0.5) * h
+    exact = 6 * u * y * (H - y) / H ** 2
+    col = nx // 2
+    err = np.abs(U[0, :, col] - exact).max() / exact.max()
+    dpdx = (p[:, col + 8] - p[:, col - 8]).mean() / (16 * h)
+    return err, dpdx / (-12 * mu * u / H ** 2), U[0, :, col].mean() / u
+
+
+def test_plane_poiseuille_second_order():
+    """Fully developed channel flow between no-slip walls: parabolic profile
+    of mean u_in and dp/dx = -12 mu u_in / H^2, with the error falling ~4x
+    per grid doubling.  Catches a wrong wall distance (h instead of h/2), a
+    missing viscous neighbour term, or H/A scaled by the cell volume."""
+    e8, g8, m8 = _poiseuille(8)
+    e16, g16, m16 = _poiseuille(16)
+    assert m8 == pytest.approx(1.0, abs=1e-6) and m16 == pytest.approx(1.0, abs=1e-6)
+    assert e16 < 0.01 and abs(g16 - 1) < 0.015
+    assert 2.5 < e8 / e16 < 6.0
+
+
+# ---------------------------------------------------------------------------
+# pressure equation and PCG against a dense direct solve
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("which", [0, 1])
+@pytest.mark.parametrize("shape", [(8, 6, 1, 2), (4, 4, 3, 3)])
+def test_pcg_matches_dense_lu(shape, which):
+    """PCG to rtol 1e-14 agrees with Gaussian elimination of the same system
+    on a tiny grid with a solid cell, random alpha, velocity and fluxes.
+    Catches a non-symmetric or mis-signed matrix, a wrong Jacobi diagonal or
+    a broken CG recurrence."""
+    nx, ny, nz, dim = shape
+    solid = ((3, 2, 0),) if dim == 2 else ((1, 1, 1),)
+    c = cases.tiny_box(nx=nx, ny=ny, nz=nz, dim=dim, seed=7, solid_cells=solid)
+    o = Oracle(c)
+    f = cases.random_fields(c, seed=11)
+    o.set("U_vd" if which == 0 else "U_cr", f["U"])
+    rc, it, res = o.pressure_solve(which, 1e-5, 1e-14, 5000)
+    assert rc == 0 and res < 1e-13
+    p = o.get("p_vd" if which == 0 else "p_cr")
+    p_lu = o.dense_solve()
+    assert np.abs(p - p_lu).max() <= 1e-10 * np.abs(p_lu).max()
+    assert np.abs(p_lu).max() > 0
+
+
+# ---------------------------------------------------------------------------
+# transport: conservation, boundedness, exact special cases
+# ---------------------------------------------------------------------------
+
+def test_channel_bubble_mass_bounds_and_split():
+    """Two OSCAR steps of the scaled channel bubble: phase mass changes only
+    by the boundary flux (to 1e-12 of the mass), alpha stays in [0,1] within
+    1e-10, and the global fields are exactly U_vd + (1/N) sum u_cr and
+    p_vd + p_cr (the additive split)."""
+    c = cases.channel_bubble(nx=64, ny=16, n_sub=12)
+    o = Oracle(c)
+    m0 = o.stats()["mass"]
+    for _ in range(2):
+        rc1, rc2, kf, E = o.step()
+        assert rc1 == 0 and rc2 == 0 and 1 <= kf <= c["max_iters"]
+    s = o.stats()
+    assert s["mass_defect"] <= 1e-12 * m0
+    a = o.get("alpha")
+    assert a.min() >= -1e-10 and a.max() <= 1 + 1e-10
+    U = o.get("U")
+    assert np.array_equal(U, o.get("U_vd") + o.get("U_sum") / c["n_sub"])
+    assert np.array_equal(o.get("p"), o.get("p_vd") + o.get("p_cr"))
+
+
+def test_mirror_symmetry():
+    """The channel bubble is symmetric about the channel axis; after two steps
+    alpha and p are even and U_y is odd in y to round-off.  Catches an index
+    or orientation error in any stencil."""
+    c = cases.channel_bubble(nx=64, ny=16, n_sub=12, max_iters=4)
+    c["pcg_rtol"] = 1e-14   # the only asymmetric operation is the order of the CG sums
+    o = Oracle(c)
+    for _ in range(2):
+        o.step()
+    nx, ny = c["nx"], c["ny"]
+    a = o.get("alpha").reshape(ny, nx)
+    p = o.get("p").reshape(ny, nx)
+    U = o.get("U").reshape(2, ny, nx)
+    # round-off asymmetry is amplified by the impulsive start of the first
+    # step and then saturates near 1e-11 (alpha, p) and 1e-9 (U)
+    assert np.abs(a - a[::-1]).max() <= 1e-10
+    assert np.abs(p - p[::-1]).max() <= 1e-10 * np.abs(p).max()
+    assert np.abs(U[1] + U[1][::-1]).max() <= 1e-8 * np.abs(U).max()
+    assert np.abs(U[0] - U[0][::-1]).max() <= 1e-8 * np.abs(U).max()
+
+
+def test_flat_interface_is_exactly_at_rest():
+    """A planar interface on a cell face between 90-degree walls has zero
+    force: E_0 = 0, k_f = 1 and u_cr, p_cr stay exactly zero."""
+    nx, ny = 32, 16
+    a = np.zeros((ny, nx))
+    a[:, : nx // 2] = 1.0
+    c = cases._case("flat", 2, nx, ny, 1, 1e-5, cases.AIR, cases.WATER, 0.07, 90.0,
+                    [cases.BC_WALL, cases.BC_OUTLET, cases.BC_WALL, cases.BC_WALL, 0, 0], 0.0,
+                    np.zeros(nx * ny, np.uint8), a, 1e-6, 1, 1, 1e-6)
+    o = Oracle(c)
+    dtb = dt_brackbill(1.0, 1000.0, 1e-5, 0.07)
+    rc, kf, E = o.capillary_relax(dtb * 5, 10, 10, 1e-4)
+    assert rc == 0 and kf == 1 and E[0] == 0.0
+    assert not o.get("U_cr").any() and not o.get("p_cr").any()
+    assert np.array_equal(o.get("alpha"), a.reshape(-1))
+
+
+def test_no_surface_tension_no_relaxation():
+    """sigma = 0: the relaxation sees no forcing, E_0 = 0, k_f = 1 and u_cr
+    stays zero while the viscous step still drives the flow."""
+    c = cases.channel_bubble(nx=32, ny=8, n_sub=4)
+    c["sigma"] = 0.0
+    o = Oracle(c)
+    assert o.viscous_step(c["dt_vd"]) == 0
+    rc, kf, E = o.capillary_relax(c["dt_vd"], 4, 4, 1e-4)
+    assert rc == 0 and kf == 1 and E[0] == 0.0
+    assert not o.get("U_cr").any()
+    assert np.abs(o.get("U_vd")).max() > 0
+
+
+def _uniform_x_flux(c, u):
+    nx, ny, nz, h = c["nx"], c["ny"], c["nz"], c["h"]
+    nfx = (nx + 1) * ny * nz
+    nfy = nx * (ny + 1) * nz
+    phi = np.zeros(nfx + nfy)
+    phi[:nfx] = u * h
+    return phi
+
+
+def test_transport_of_a_front():
+    """A sharp front carried by a uniform x-flux (Courant 0.4) from an inlet
+    that feeds alpha = 1: the mass grows by exactly the inflow, alpha stays in
+    [0,1], a uniform region stays exactly uniform, and interface compression
+    keeps the front within 3 cells.  Catches a missing limiter, a wrong
+    boundary flux, or compression of the wrong sign."""
+    nx, ny, h, u = 48, 4, 1e-5, 1e-3
+    a = np.zeros((ny, nx))
+    a[:, :8] = 1.0
+    c = cases._case("front", 2, nx, ny, 1, h, cases.WATER, cases.OIL, 0.0, 90.0,
+                    [cases.BC_INLET, cases.BC_OUTLET, cases.BC_WALL, cases.BC_WALL, 0, 0], 0.0,
+                    np.zeros(nx * ny, np.uint8), a, 1e-6, 1, 1, 1e-6)
+    o = Oracle(c)
+    dt = 0.4 * h / u
+    m0 = o.stats()["mass"]
+    phi = _uniform_x_flux(c, u)
+    for s in range(30):
+        o.set("phi_cr", phi)
+        rc, kf, E = o.capillary_relax(dt, 1, 1, 0.0)
+        assert rc == 0
+    al = o.get("alpha").reshape(ny, nx)
+    m1 = o.stats()["mass"]
+    assert m1 - m0 == pytest.approx(30 * dt * u * h * ny, rel=1e-12)
+    assert al.min() >= -1e-14 and al.max() <= 1 + 1e-14
+    assert np.all(al[:, :10] == 1.0) and np.all(al[:, -10:] == 0.0)
+    band = ((al > 0.01) & (al < 0.99)).sum(axis=1)
+    assert band.max() <= 3
+    assert (al.sum(axis=1) - 8).mean() == pytest.approx(30 * 0.4, rel=1e-9)
