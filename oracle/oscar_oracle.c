@@ -782,7 +782,9 @@ int32_t orc_pressure_solve(orc_t *o, int32_t which, double dt, double rtol, int3
   memcpy(o->alpha_old, o->alpha, sizeof(double) * o->nc);
   double *U = which ? o->U_cr : o->U_vd, *p = which ? o->p_cr : o->p_vd;
   double ub = which ? 0.0 : o->prm.u_inlet;
-  const double *phiv = which ? o->phi_vd_prev : o->phi_vd;
+  /* a viscous step convects with u_vd^n: keep it as the previous flux */
+  if (!which) memcpy(o->phi_vd_prev, o->phi_vd, sizeof(double) * o->nftot);
+  const double *phiv = o->phi_vd_prev;
   if (which) curvature(o);
   for (long f = 0; f < o->nftot; ++f) o->phic[f] = phiv[f] + o->phi_cr[f];
   assemble(o, o->phic, U, ub, dt);

@@ -1,0 +1,708 @@
+// Host side of the OSCAR library: descriptor validation, workspace layout,
+// the stream-ordered orchestration of the viscous step and of the capillary
+// relaxation (arXiv 2105.10576, Section 3), and the C ABI of include/oscar.h.
+//
+// Control flow stays on the device where it decides the arithmetic: the
+// conjugate-gradient convergence test and the iteration count live in the
+// per-slot device state, and every CG kernel returns at once when its slot
+// is converged, so the host enqueues CG iterations in chunks and reads one
+// small status block per chunk instead of one scalar per iteration.
+#include "oscar_internal.h"
+#include "../../include/oscar.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using namespace oscar;
+
+namespace {
+
+thread_local std::string g_err = "no error";
+
+constexpr uint64_t ALIGN = 256;
+
+uint64_t up(uint64_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
+
+struct Dims {
+  int d;
+  int64_t nc, nf0, nf1, nf2, nft;
+  int nblocks;
+};
+
+Dims dims_of(const oscar_desc &D) {
+  Dims g;
+  g.d = D.dim;
+  g.nc = (int64_t)D.nx * D.ny * D.nz;
+  g.nf0 = (int64_t)(D.nx + 1) * D.ny * D.nz;
+  g.nf1 = (int64_t)D.nx * (D.ny + 1) * D.nz;
+  g.nf2 = D.dim == 3 ? (int64_t)D.nx * D.ny * (D.nz + 1) : 0;
+  g.nft = g.nf0 + g.nf1 + g.nf2;
+  g.nblocks = (int)((g.nc + BLOCK - 1) / BLOCK);
+  return g;
+}
+
+// Carve a workspace: every array on its own 256-byte boundary.
+struct Carver {
+  uint64_t off = 0;
+  char *base = nullptr;
+  void *take(uint64_t bytes) {
+    void *p = base ? base + off : nullptr;
+    off += up(bytes ? bytes : 1);
+    return p;
+  }
+};
+
+// Lay out one slot's arrays (and, with `ctl_block`, its table entries).
+void layout(const oscar_desc &D, Carver &cv, Slot *s, bool ctl_block) {
+  Dims g = dims_of(D);
+  uint64_t w = D.precision == OSCAR_MIXED ? 4 : 8;
+  const int64_t nc = g.nc, d = g.d, nf = g.nft;
+  s->flags = (const uint8_t *)cv.take(nc);
+  void **cell1[] = {&s->alpha, &s->alpha_old, &s->kappa, &s->aP, &s->rAU, &s->Rp, &s->Rm,
+                    &s->invD, &s->r, &s->z, &s->d0, &s->d1, &s->q, &s->e};
+  for (void **p : cell1) *p = cv.take(w * nc);
+  void **celld[] = {&s->U_vd, &s->U_cr, &s->U_sum, &s->U, &s->grad, &s->HbyA, &s->b};
+  for (void **p : celld) *p = cv.take(w * nc * d);
+  s->gradU = cv.take(w * nc * d * d);
+  void **face[] = {&s->phi_vd, &s->phi_prev, &s->phi_cr, &s->nhatf, &s->Fm, &s->phiH, &s->FL, &s->Af};
+  for (void **p : face) *p = cv.take(w * nf);
+  double **dbl[] = {&s->p_vd, &s->p_cr, &s->p, &s->rhs, &s->Mp};
+  for (double **p : dbl) *p = (double *)cv.take(8 * nc);
+  s->r64 = nullptr;
+  s->partials = (double *)cv.take(8ull * NRED * g.nblocks);
+  s->ticket = (uint32_t *)cv.take(4);
+  s->st = (SlotState *)cv.take(sizeof(SlotState));
+  s->ctl = (SlotCtl *)cv.take(sizeof(SlotCtl));
+  (void)ctl_block;
+}
+
+int check_desc(const oscar_desc *D, std::string &why) {
+  if (!D) { why = "descriptor is NULL"; return OSCAR_E_ARG; }
+  if (D->dim != 2 && D->dim != 3) { why = "dim must be 2 or 3"; return OSCAR_E_ARG; }
+  if (D->nx < 1 || D->ny < 1 || D->nz < 1) { why = "grid sizes must be >= 1"; return OSCAR_E_ARG; }
+  if (D->dim == 2 && D->nz != 1) { why = "nz must be 1 when dim = 2"; return OSCAR_E_ARG; }
+  if ((int64_t)D->nx * D->ny * D->nz > (int64_t)1 << 31) { why = "grid too large"; return OSCAR_E_ARG; }
+  if (!(D->h > 0.0) || !std::isfinite(D->h)) { why = "h must be > 0"; return OSCAR_E_ARG; }
+  if (!(D->rho1 > 0) || !(D->rho2 > 0) || !(D->mu1 > 0) || !(D->mu2 > 0)) { why = "densities and viscosities must be > 0"; return OSCAR_E_ARG; }
+  if (!(D->sigma >= 0) || !std::isfinite(D->sigma)) { why = "sigma must be >= 0"; return OSCAR_E_ARG; }
+  if (!std::isfinite(D->theta_deg) || !std::isfinite(D->u_inlet)) { why = "theta and u_inlet must be finite"; return OSCAR_E_ARG; }
+  if (D->precision != OSCAR_FP64 && D->precision != OSCAR_MIXED) { why = "unknown precision"; return OSCAR_E_ARG; }
+  if (D->n_corr < 1 || D->n_corr > 64) { why = "n_corr must be in [1, 64]"; return OSCAR_E_ARG; }
+  if (!(D->pcg_rtol > 0) || D->pcg_max_it < 1) { why = "pcg_rtol must be > 0 and pcg_max_it >= 1"; return OSCAR_E_ARG; }
+  for (int f = 0; f < 2 * D->dim; ++f)
+    if (D->bc[f] < OSCAR_BC_WALL || D->bc[f] > OSCAR_BC_OUTLET) { why = "unknown boundary type"; return OSCAR_E_ARG; }
+  return OSCAR_OK;
+}
+
+// per-cell face flags (bit f: neighbour across face f is fluid and inside the
+// box; bit 6: solid) and the outlet-connectivity check
+int build_flags(const oscar_desc &D, std::vector<uint8_t> &fl, int64_t &n_fluid, std::string &why) {
+  const int64_t nx = D.nx, ny = D.ny, nz = D.nz, nc = nx * ny * nz;
+  fl.assign(nc, 0);
+  n_fluid = 0;
+  auto id = [&](int64_t i, int64_t j, int64_t k) { return i + nx * (j + ny * k); };
+  for (int64_t k = 0; k < nz; ++k)
+    for (int64_t j = 0; j < ny; ++j)
+      for (int64_t i = 0; i < nx; ++i) {
+        int64_t P = id(i, j, k);
+        if (D.mask[P]) { fl[P] = 0x40; continue; }
+        n_fluid++;
+        uint8_t b = 0;
+        int64_t c[3] = {i, j, k}, n[3] = {nx, ny, nz};
+        for (int f = 0; f < 2 * D.dim; ++f) {
+          int e = f >> 1;
+          int64_t q[3] = {c[0], c[1], c[2]};
+          q[e] += (f & 1) ? 1 : -1;
+          if (q[e] < 0 || q[e] >= n[e]) continue;
+          if (!D.mask[id(q[0], q[1], q[2])]) b |= (uint8_t)(1u << f);
+        }
+        fl[P] = b;
+      }
+  if (n_fluid == 0) { why = "the mask has no fluid cell"; return OSCAR_E_MASK; }
+  // flood fill from every fluid cell that owns an outlet face
+  std::vector<uint8_t> seen(nc, 0);
+  std::vector<int64_t> stack;
+  for (int64_t k = 0; k < nz; ++k)
+    for (int64_t j = 0; j < ny; ++j)
+      for (int64_t i = 0; i < nx; ++i) {
+        int64_t P = id(i, j, k);
+        if (fl[P] & 0x40) continue;
+        int64_t c[3] = {i, j, k}, n[3] = {nx, ny, nz};
+        bool out = false;
+        for (int f = 0; f < 2 * D.dim; ++f) {
+          int e = f >> 1;
+          bool edge = (f & 1) ? c[e] == n[e] - 1 : c[e] == 0;
+          if (edge && D.bc[f] == OSCAR_BC_OUTLET) out = true;
+        }
+        if (out) { seen[P] = 1; stack.push_back(P); }
+      }
+  while (!stack.empty()) {
+    int64_t P = stack.back();
+    stack.pop_back();
+    int64_t i = P % nx, j = (P / nx) % ny, k = P / (nx * ny);
+    for (int f = 0; f < 2 * D.dim; ++f) {
+      if (!(fl[P] & (1u << f))) continue;
+      int64_t q[3] = {i, j, k};
+      q[f >> 1] += (f & 1) ? 1 : -1;
+      int64_t N = id(q[0], q[1], q[2]);
+      if (!seen[N]) { seen[N] = 1; stack.push_back(N); }
+    }
+  }
+  for (int64_t P = 0; P < nc; ++P)
+    if (!(fl[P] & 0x40) && !seen[P]) {
+      char buf[160];
+      snprintf(buf, sizeof buf, "fluid cell %lld (i=%lld j=%lld k=%lld) cannot reach an outlet", (long long)P,
+               (long long)(P % nx), (long long)((P / nx) % ny), (long long)(P / (nx * ny)));
+      why = buf;
+      return OSCAR_E_MASK;
+    }
+  return OSCAR_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// context
+// ---------------------------------------------------------------------------
+
+struct oscar_ctx {
+  oscar_desc D;
+  Dims g;
+  Slot s;                  // host copy of the slot (device pointers)
+  Slot *d_slot = nullptr;  // device copy
+  int2 *d_btab = nullptr;
+  hipStream_t stream = nullptr;
+  SlotState *h_state = nullptr;   // pinned readback
+  std::string err = "no error";
+  int64_t n_fluid = 0;
+  // host bookkeeping
+  std::vector<double> Ehist;
+  int k_f = 0;
+  double last_E = 0.0, last_res = 0.0;
+  int last_pcg = 0, pcg_call = 0, refine_call = 0, maxit_hits = 0;
+  int pcg_pred = 32;
+
+  Launch L() const {
+    Launch l;
+    l.slots = d_slot;
+    l.btab = d_btab;
+    l.nblocks = g.nblocks;
+    l.stream = stream;
+    return l;
+  }
+  bool mixed() const { return D.precision == OSCAR_MIXED; }
+};
+
+static int hip_fail(oscar_ctx *c, hipError_t e, const char *what) {
+  char buf[256];
+  snprintf(buf, sizeof buf, "%s: %s", what, hipGetErrorString(e));
+  if (c) c->err = buf;
+  else g_err = buf;
+  return OSCAR_E_HIP;
+}
+
+#define HIPCHK(c, x)                                       \
+  do {                                                     \
+    hipError_t _e = (x);                                   \
+    if (_e != hipSuccess) return hip_fail((c), _e, #x);   \
+  } while (0)
+
+static int set_ctl(oscar_ctx *c, const SlotCtl &ctl) {
+  CtlUpdate u;
+  memset(&u, 0, sizeof u);
+  u.n = 1;
+  u.slot[0] = 0;
+  u.ctl[0] = ctl;
+  launch_ctl_update(c->L(), u);
+  HIPCHK(c, hipGetLastError());
+  return OSCAR_OK;
+}
+
+static int read_state(oscar_ctx *c) {
+  HIPCHK(c, hipMemcpyAsync(c->h_state, c->s.st, sizeof(SlotState), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return OSCAR_OK;
+}
+
+extern "C" double oscar_dt_brackbill(double rho1, double rho2, double h, double sigma) {
+  const double pi = 3.14159265358979323846;
+  double rbar = 0.5 * (rho1 + rho2);
+  return std::sqrt(rbar * h * h * h / (2.0 * pi * sigma));
+}
+
+extern "C" int32_t oscar_workspace_size(const oscar_desc *desc, uint64_t *bytes) {
+  std::string why;
+  if (!bytes) { g_err = "bytes is NULL"; return OSCAR_E_ARG; }
+  int rc = check_desc(desc, why);
+  if (rc) { g_err = why; return rc; }
+  Carver cv;
+  Slot s;
+  layout(*desc, cv, &s, true);
+  cv.take(sizeof(Slot));
+  cv.take(sizeof(int2) * (uint64_t)dims_of(*desc).nblocks);
+  *bytes = cv.off;
+  return OSCAR_OK;
+}
+
+extern "C" int32_t oscar_create(const oscar_desc *desc, void *ws, uint64_t bytes, void *hip_stream,
+                                oscar_ctx **out) {
+  if (!out) { g_err = "out is NULL"; return OSCAR_E_ARG; }
+  *out = nullptr;
+  std::string why;
+  int rc = check_desc(desc, why);
+  if (rc) { g_err = why; return rc; }
+  if (!desc->mask || !desc->alpha0) { g_err = "mask and alpha0 must be non-NULL"; return OSCAR_E_ARG; }
+  uint64_t need = 0;
+  oscar_workspace_size(desc, &need);
+  if (!ws || bytes < need || ((uintptr_t)ws % ALIGN) != 0) {
+    char buf[160];
+    snprintf(buf, sizeof buf, "workspace %p of %llu bytes; need %llu bytes, 256-byte aligned", ws,
+             (unsigned long long)bytes, (unsigned long long)need);
+    g_err = buf;
+    return OSCAR_E_WORKSPACE;
+  }
+  std::vector<uint8_t> fl;
+  int64_t n_fluid = 0;
+  rc = build_flags(*desc, fl, n_fluid, why);
+  if (rc) { g_err = why; return rc; }
+  const int64_t nc = (int64_t)desc->nx * desc->ny * desc->nz;
+  for (int64_t P = 0; P < nc; ++P)
+    if (!desc->mask[P] && !std::isfinite(desc->alpha0[P])) { g_err = "alpha0 has a non-finite value"; return OSCAR_E_ARG; }
+
+  oscar_ctx *c = new oscar_ctx();
+  c->D = *desc;
+  c->D.mask = nullptr;
+  c->D.alpha0 = nullptr;
+  c->g = dims_of(*desc);
+  c->stream = (hipStream_t)hip_stream;
+  c->n_fluid = n_fluid;
+  Carver cv;
+  cv.base = (char *)ws;
+  Slot &s = c->s;
+  memset(&s, 0, sizeof s);
+  layout(*desc, cv, &s, true);
+  c->d_slot = (Slot *)cv.take(sizeof(Slot));
+  c->d_btab = (int2 *)cv.take(sizeof(int2) * (uint64_t)c->g.nblocks);
+  s.dim = desc->dim;
+  s.nx = desc->nx;
+  s.ny = desc->ny;
+  s.nz = desc->nz;
+  s.nc = c->g.nc;
+  s.nf0 = c->g.nf0;
+  s.nf1 = c->g.nf1;
+  s.nf2 = c->g.nf2;
+  s.nftot = c->g.nft;
+  s.block0 = 0;
+  s.nblocks = c->g.nblocks;
+  s.n_fluid = (int32_t)n_fluid;
+  s.precision = desc->precision;
+  for (int f = 0; f < 6; ++f)
+    s.bcf[f] = desc->bc[f] == OSCAR_BC_INLET ? F_INLET : (desc->bc[f] == OSCAR_BC_OUTLET ? F_OUTLET : F_WALL);
+  const double h = desc->h;
+  s.h = h;
+  s.V = desc->dim == 3 ? h * h * h : h * h;
+  s.S = desc->dim == 3 ? h * h : h;
+  s.Sh = s.S / h;
+  s.hh = 0.5 * h;
+  s.S2h = s.S / s.hh;
+  s.delta = 1e-8 / h;
+  // cos and sin of theta from the complementary angle, exact at 90 degrees
+  const double pi = 3.14159265358979323846;
+  double comp = (90.0 - desc->theta_deg) * (pi / 180.0);
+  s.cos_t = std::sin(comp);
+  s.sin_t = std::cos(comp);
+  s.rho1 = desc->rho1;
+  s.mu1 = desc->mu1;
+  s.rho2 = desc->rho2;
+  s.mu2 = desc->mu2;
+  s.sigma = desc->sigma;
+  s.u_inlet = desc->u_inlet;
+
+  auto fail = [&](hipError_t e, const char *what) {
+    hip_fail(nullptr, e, what);
+    if (c->h_state) (void)hipHostFree(c->h_state);
+    delete c;
+    return OSCAR_E_HIP;
+  };
+  hipError_t e;
+  if ((e = hipHostMalloc((void **)&c->h_state, sizeof(SlotState), hipHostMallocDefault)) != hipSuccess)
+    return fail(e, "hipHostMalloc");
+  if ((e = hipMemsetAsync(ws, 0, cv.off, c->stream)) != hipSuccess) return fail(e, "hipMemsetAsync");
+  if ((e = hipMemcpyAsync((void *)s.flags, fl.data(), nc, hipMemcpyHostToDevice, c->stream)) != hipSuccess)
+    return fail(e, "upload mask");
+  std::vector<int2> bt(c->g.nblocks);
+  for (int b = 0; b < c->g.nblocks; ++b) bt[b] = make_int2(0, b);
+  if ((e = hipMemcpyAsync(c->d_btab, bt.data(), sizeof(int2) * bt.size(), hipMemcpyHostToDevice, c->stream)) != hipSuccess)
+    return fail(e, "upload block table");
+  if ((e = hipMemcpyAsync(c->d_slot, &s, sizeof(Slot), hipMemcpyHostToDevice, c->stream)) != hipSuccess)
+    return fail(e, "upload slot");
+  if (desc->precision == OSCAR_MIXED) {
+    std::vector<float> a(nc);
+    for (int64_t P = 0; P < nc; ++P) a[P] = desc->mask[P] ? 0.f : (float)desc->alpha0[P];
+    e = hipMemcpyAsync(s.alpha, a.data(), 4 * nc, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  } else {
+    std::vector<double> a(nc);
+    for (int64_t P = 0; P < nc; ++P) a[P] = desc->mask[P] ? 0.0 : desc->alpha0[P];
+    e = hipMemcpyAsync(s.alpha, a.data(), 8 * nc, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  }
+  if (e != hipSuccess) return fail(e, "upload alpha0");
+  *out = c;
+  return OSCAR_OK;
+}
+
+extern "C" void oscar_destroy(oscar_ctx *c) {
+  if (!c) return;
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  if (c->h_state) (void)hipHostFree(c->h_state);
+  delete c;
+}
+
+extern "C" const char *oscar_last_error(const oscar_ctx *c) { return c ? c->err.c_str() : g_err.c_str(); }
+
+// ---------------------------------------------------------------------------
+// orchestration
+// ---------------------------------------------------------------------------
+
+// Solve the assembled pressure equation of the current corrector on the
+// device: chunks of CG iterations until the slot's done flag is set; in mixed
+// precision, FP32 inner solves wrapped in FP64 refinement.
+template <typename R>
+static int solve_pressure(oscar_ctx *c, int &iters) {
+  Launch L = c->L();
+  int rc = read_state(c);
+  if (rc) return rc;
+  int start_total = c->h_state->total_it;
+  const int max_it = c->D.pcg_max_it;
+  auto inner = [&]() -> int {
+    int chunk = c->pcg_pred > 4 ? c->pcg_pred : 4;
+    int guard = 0;
+    while (!c->h_state->done) {
+      launch_pcg_iters<R>(L, chunk);
+      HIPCHK(c, hipGetLastError());
+      int r = read_state(c);
+      if (r) return r;
+      chunk = chunk < 64 ? 64 : chunk;
+      if (++guard > 4 + max_it / 4) { c->err = "conjugate gradient did not terminate"; return OSCAR_E_HIP; }
+    }
+    return OSCAR_OK;
+  };
+  if (!c->mixed()) {
+    rc = inner();
+    if (rc) return rc;
+  } else {
+    int outer = 0;
+    while (!c->h_state->done) {
+      rc = inner();
+      if (rc) return rc;
+      launch_refine<R>(L);
+      HIPCHK(c, hipGetLastError());
+      rc = read_state(c);
+      if (rc) return rc;
+      if (++outer >= 60) break;
+    }
+    c->refine_call += outer;
+  }
+  iters = c->h_state->total_it - start_total;
+  // predicted chunk for the next solve: this solve's count rounded up
+  int pred = iters + 4;
+  c->pcg_pred = pred > 512 ? 512 : pred;
+  return OSCAR_OK;
+}
+
+template <typename R>
+static int run_correctors(oscar_ctx *c, bool cr, double &E, int &warn) {
+  Launch L = c->L();
+  for (int j = 0; j < c->D.n_corr; ++j) {
+    launch_predictor<R>(L);
+    launch_pressure_setup<R>(L, cr && j == 0);
+    HIPCHK(c, hipGetLastError());
+    int it = 0;
+    int rc = solve_pressure<R>(c, it);
+    if (rc) return rc;
+    if (cr && j == 0) E = c->h_state->E;
+    c->last_pcg = it;
+    c->pcg_call += it;
+    if (c->h_state->maxit_hit) warn = OSCAR_W_PCG_MAXIT;
+    launch_correct<R>(L, j == c->D.n_corr - 1);
+    HIPCHK(c, hipGetLastError());
+  }
+  return OSCAR_OK;
+}
+
+static SlotCtl make_ctl(const oscar_ctx *c, int mode, double dt, int n_sub) {
+  SlotCtl k;
+  memset(&k, 0, sizeof k);
+  k.active = 1;
+  k.mode = mode;
+  k.dt = dt;
+  k.ub = mode ? 0.0 : c->D.u_inlet;
+  k.with_st = mode;
+  k.rtol = c->D.pcg_rtol;
+  k.rtol_inner = 1e-3;
+  k.max_it = c->D.pcg_max_it;
+  k.n_sub = n_sub;
+  return k;
+}
+
+static int finish_call(oscar_ctx *c, int warn) {
+  int rc = read_state(c);
+  if (rc) return rc;
+  const SlotState &st = *c->h_state;
+  c->maxit_hits += st.maxit_hit;
+  c->last_res = c->mixed() ? (st.bn64 > 0 ? st.rn64 / st.bn64 : 0.0) : (st.bn > 0 ? st.rn / st.bn : 0.0);
+  if (st.nonfinite) { c->err = "non-finite velocity"; return OSCAR_E_NONFINITE; }
+  if (st.unstable) { c->err = "transport Courant number above 1"; return OSCAR_E_UNSTABLE; }
+  return warn;
+}
+
+template <typename R>
+static int viscous_step_t(oscar_ctx *c, double dt) {
+  Launch L = c->L();
+  int rc = set_ctl(c, make_ctl(c, 0, dt, 1));
+  if (rc) return rc;
+  launch_state_reset(L, 1, 0);
+  c->pcg_call = 0;
+  c->refine_call = 0;
+  launch_copy_phi_prev<R>(L);
+  launch_normals<R>(L, false);
+  launch_advect<R>(L);
+  launch_assemble<R>(L);
+  HIPCHK(c, hipGetLastError());
+  double E = 0.0;
+  int warn = OSCAR_OK;
+  rc = run_correctors<R>(c, false, E, warn);
+  if (rc) return rc;
+  return finish_call(c, warn);
+}
+
+template <typename R>
+static int relax_t(oscar_ctx *c, double dt_vd, int n_sub, int max_iters, double tol) {
+  Launch L = c->L();
+  double dt = dt_vd / (double)n_sub;
+  int rc = set_ctl(c, make_ctl(c, 1, dt, n_sub));
+  if (rc) return rc;
+  launch_state_reset(L, 1, 1);
+  launch_zero_usum<R>(L);
+  HIPCHK(c, hipGetLastError());
+  c->pcg_call = 0;
+  c->refine_call = 0;
+  c->Ehist.clear();
+  int warn = OSCAR_OK;
+  int kf = max_iters;
+  for (int k = 0; k < max_iters; ++k) {
+    launch_normals<R>(L, false);
+    launch_advect<R>(L);
+    launch_normals<R>(L, true);
+    launch_assemble<R>(L);
+    HIPCHK(c, hipGetLastError());
+    double E = 0.0;
+    rc = run_correctors<R>(c, true, E, warn);
+    if (rc) return rc;
+    c->Ehist.push_back(E);
+    c->last_E = E;
+    if (c->h_state->nonfinite) break;
+    if (E < tol) { kf = k + 1; break; }
+  }
+  c->k_f = kf;
+  launch_finalize<R>(L);
+  HIPCHK(c, hipGetLastError());
+  return finish_call(c, warn);
+}
+
+extern "C" int32_t oscar_viscous_step(oscar_ctx *c, double dt_vd) {
+  if (!c) { g_err = "ctx is NULL"; return OSCAR_E_ARG; }
+  if (!(dt_vd > 0.0) || !std::isfinite(dt_vd)) { c->err = "dt_vd must be > 0"; return OSCAR_E_ARG; }
+  return c->mixed() ? viscous_step_t<float>(c, dt_vd) : viscous_step_t<double>(c, dt_vd);
+}
+
+extern "C" int32_t oscar_capillary_relax(oscar_ctx *c, double dt_vd, int32_t n_sub, int32_t max_iters, double tol,
+                                         int32_t *k_f, double *E_last) {
+  if (!c) { g_err = "ctx is NULL"; return OSCAR_E_ARG; }
+  if (!(dt_vd > 0.0) || !std::isfinite(dt_vd) || n_sub < 1 || max_iters < 1 || max_iters > n_sub || !(tol >= 0.0)) {
+    c->err = "need dt_vd > 0, n_sub >= 1, 1 <= max_iters <= n_sub, tol >= 0";
+    return OSCAR_E_ARG;
+  }
+  double dt = dt_vd / (double)n_sub;
+  if (c->D.sigma > 0.0 && !(dt < oscar_dt_brackbill(c->D.rho1, c->D.rho2, c->D.h, c->D.sigma))) {
+    char buf[160];
+    snprintf(buf, sizeof buf, "dt_vd/n_sub = %.4g s is not below the Brackbill limit %.4g s", dt,
+             oscar_dt_brackbill(c->D.rho1, c->D.rho2, c->D.h, c->D.sigma));
+    c->err = buf;
+    return OSCAR_E_UNSTABLE;
+  }
+  int rc = c->mixed() ? relax_t<float>(c, dt_vd, n_sub, max_iters, tol) : relax_t<double>(c, dt_vd, n_sub, max_iters, tol);
+  if (k_f) *k_f = c->k_f;
+  if (E_last) *E_last = c->last_E;
+  return rc;
+}
+
+extern "C" int32_t oscar_relax_history(const oscar_ctx *c, double *E, int32_t cap, int32_t *n) {
+  if (!c || (!E && cap > 0)) return OSCAR_E_ARG;
+  int m = (int)c->Ehist.size() < cap ? (int)c->Ehist.size() : cap;
+  for (int x = 0; x < m; ++x) E[x] = c->Ehist[x];
+  if (n) *n = m;
+  return OSCAR_OK;
+}
+
+template <typename R>
+static int pressure_solve_t(oscar_ctx *c, int which, double dt, double rtol, int max_it, int *iters, double *res) {
+  Launch L = c->L();
+  SlotCtl k = make_ctl(c, which, dt, 1);
+  k.rtol = rtol;
+  k.max_it = max_it;
+  int rc = set_ctl(c, k);
+  if (rc) return rc;
+  launch_state_reset(L, 1, 0);
+  // alpha_old = alpha (no transport), then curvature, momentum, predictor, solve
+  int saved_pred = c->pcg_pred;
+  int saved_max = c->D.pcg_max_it;
+  c->D.pcg_max_it = max_it;
+  if (which == 0) launch_copy_phi_prev<R>(L);
+  hipError_t e = hipMemcpyAsync(c->s.alpha_old, c->s.alpha, (c->mixed() ? 4 : 8) * c->g.nc, hipMemcpyDeviceToDevice, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "copy alpha");
+  if (which) launch_normals<R>(L, true);
+  launch_assemble<R>(L);
+  launch_predictor<R>(L);
+  launch_pressure_setup<R>(L, false);
+  HIPCHK(c, hipGetLastError());
+  int it = 0;
+  rc = solve_pressure<R>(c, it);
+  c->D.pcg_max_it = saved_max;
+  c->pcg_pred = saved_pred;
+  if (rc) return rc;
+  int warn = c->h_state->maxit_hit ? OSCAR_W_PCG_MAXIT : OSCAR_OK;
+  if (iters) *iters = it;
+  if (res) {
+    // FP64 relative residual of the final pressure
+    SlotCtl k2 = k;
+    (void)k2;
+    const SlotState &st = *c->h_state;
+    if (c->mixed()) *res = st.bn64 > 0 ? st.rn64 / st.bn64 : 0.0;
+    else {
+      // recompute ||b - M p|| in FP64 with the setup kernel (it also refreshes rhs)
+      launch_pressure_setup<R>(L, false);
+      rc = read_state(c);
+      if (rc) return rc;
+      *res = st.bn > 0 ? st.rn / st.bn : 0.0;
+    }
+  }
+  return warn;
+}
+
+extern "C" int32_t oscar_pressure_solve(oscar_ctx *c, int32_t which, double dt, double rtol, int32_t max_it,
+                                        int32_t *iters, double *rel_residual_fp64) {
+  if (!c) { g_err = "ctx is NULL"; return OSCAR_E_ARG; }
+  if ((which != 0 && which != 1) || !(dt > 0.0) || !(rtol > 0.0) || max_it < 1) {
+    c->err = "need which in {0,1}, dt > 0, rtol > 0, max_it >= 1";
+    return OSCAR_E_ARG;
+  }
+  int it = 0;
+  double res = 0.0;
+  int rc = c->mixed() ? pressure_solve_t<float>(c, which, dt, rtol, max_it, &it, &res)
+                      : pressure_solve_t<double>(c, which, dt, rtol, max_it, &it, &res);
+  if (iters) *iters = it;
+  if (rel_residual_fp64) *rel_residual_fp64 = res;
+  return rc;
+}
+
+// ---------------------------------------------------------------------------
+// fields and statistics
+// ---------------------------------------------------------------------------
+
+static void *field_ptr(oscar_ctx *c, int id, int64_t &len, bool &dbl) {
+  const Slot &s = c->s;
+  const int64_t nc = c->g.nc, dn = c->g.d * c->g.nc, nf = c->g.nft;
+  dbl = false;
+  switch (id) {
+    case OSCAR_FIELD_ALPHA: len = nc; return s.alpha;
+    case OSCAR_FIELD_U: len = dn; return s.U;
+    case OSCAR_FIELD_P: len = nc; dbl = true; return s.p;
+    case OSCAR_FIELD_U_VD: len = dn; return s.U_vd;
+    case OSCAR_FIELD_P_VD: len = nc; dbl = true; return s.p_vd;
+    case OSCAR_FIELD_U_CR: len = dn; return s.U_cr;
+    case OSCAR_FIELD_P_CR: len = nc; dbl = true; return s.p_cr;
+    case OSCAR_FIELD_PHI_VD: len = nf; return s.phi_vd;
+    case OSCAR_FIELD_PHI_VD_PREV: len = nf; return s.phi_prev;
+    case OSCAR_FIELD_PHI_CR: len = nf; return s.phi_cr;
+    case OSCAR_FIELD_KAPPA: len = nc; return s.kappa;
+    case OSCAR_FIELD_RAU: len = nc; return s.rAU;
+    case OSCAR_FIELD_RHS: len = nc; dbl = true; return s.rhs;
+    case OSCAR_FIELD_U_SUM: len = dn; return s.U_sum;
+    case OSCAR_FIELD_HBYA: len = dn; return s.HbyA;
+    case OSCAR_FIELD_NHATF: len = nf; return s.nhatf;
+    default: len = -1; return nullptr;
+  }
+}
+
+extern "C" int64_t oscar_field_len(const oscar_ctx *c, int32_t id) {
+  if (!c) return -1;
+  int64_t len;
+  bool dbl;
+  field_ptr(const_cast<oscar_ctx *>(c), id, len, dbl);
+  return len;
+}
+
+extern "C" int32_t oscar_get_field(oscar_ctx *c, int32_t id, double *dst) {
+  if (!c) { g_err = "ctx is NULL"; return OSCAR_E_ARG; }
+  int64_t len;
+  bool dbl;
+  void *src = field_ptr(c, id, len, dbl);
+  if (!src || !dst) { c->err = "unknown field or NULL destination"; return OSCAR_E_ARG; }
+  if (dbl || !c->mixed()) {
+    HIPCHK(c, hipMemcpyAsync(dst, src, 8 * len, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+  } else {
+    std::vector<float> t(len);
+    HIPCHK(c, hipMemcpyAsync(t.data(), src, 4 * len, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (int64_t x = 0; x < len; ++x) dst[x] = t[x];
+  }
+  return OSCAR_OK;
+}
+
+extern "C" int32_t oscar_set_field(oscar_ctx *c, int32_t id, const double *src) {
+  if (!c) { g_err = "ctx is NULL"; return OSCAR_E_ARG; }
+  int64_t len;
+  bool dbl;
+  void *dst = field_ptr(c, id, len, dbl);
+  if (!dst || !src) { c->err = "unknown field or NULL source"; return OSCAR_E_ARG; }
+  for (int64_t x = 0; x < len; ++x)
+    if (!std::isfinite(src[x])) { c->err = "non-finite value in the field"; return OSCAR_E_NONFINITE; }
+  if (dbl || !c->mixed()) {
+    HIPCHK(c, hipMemcpyAsync(dst, src, 8 * len, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+  } else {
+    std::vector<float> t(len);
+    for (int64_t x = 0; x < len; ++x) t[x] = (float)src[x];
+    HIPCHK(c, hipMemcpyAsync(dst, t.data(), 4 * len, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+  }
+  return OSCAR_OK;
+}
+
+extern "C" int32_t oscar_stats(oscar_ctx *c, oscar_stats_t *o) {
+  if (!c || !o) return OSCAR_E_ARG;
+  int rc = read_state(c);
+  if (rc) return rc;
+  const SlotState &st = *c->h_state;
+  memset(o, 0, sizeof *o);
+  o->mass_phase1 = st.mass1;
+  o->max_courant = st.comax;
+  o->mass_defect = st.mass_defect;
+  o->last_E = c->last_E;
+  o->last_res = c->last_res;
+  o->last_pcg_iters = c->last_pcg;
+  o->pcg_iters_call = c->pcg_call;
+  o->refine_steps_call = c->refine_call;
+  o->k_f = c->k_f;
+  o->n_fluid = (int32_t)c->n_fluid;
+  o->pcg_maxit_hits = c->maxit_hits;
+  return OSCAR_OK;
+}

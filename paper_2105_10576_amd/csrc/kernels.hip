@@ -1,0 +1,1174 @@
+// OSCAR relaxation-path kernels for gfx950 (CDNA4).
+//
+// Discretisation (arXiv 2105.10576, Sections 2-4): cell-centred finite
+// volumes on a uniform voxel grid, explicit alpha transport with van Leer
+// (1974) face values, interface compression and a Zalesak (1979) limiter,
+// continuum surface force with the Brackbill (1992) wall-adhesion normal,
+// implicit-Euler momentum with upwind + linear-upwind convection and the
+// transpose viscous term, PISO (Issa 1985) pressure correction in the
+// balanced-force face form, Jacobi-preconditioned conjugate gradient.
+//
+// Layout: cells x-fastest, idx = i + nx*(j + ny*k); face arrays per
+// direction (x-faces (nx+1)*ny*nz first, then y, then z), a face indexed by
+// its high-side cell coordinates; vector fields component-major.
+//
+// Execution: one thread per cell, 256-thread workgroups; a thread also owns
+// the low face of its cell in every direction and the far boundary face when
+// it sits on the last layer.  Memory-bound stencil work: every kernel streams
+// each array once; neighbour reuse comes from the L1/L2 caches.  Arithmetic is
+// written operation by operation (no fused multiply-add: built with
+// -ffp-contract=off) so that the FP64 instantiation rounds exactly like the
+// sequential double-precision reference.
+#include "oscar_internal.h"
+
+namespace oscar {
+
+// ---------------------------------------------------------------------------
+// indexing and boundary classification
+// ---------------------------------------------------------------------------
+
+struct Cell {
+  int64_t P;
+  int i, j, k;
+  bool valid;
+};
+
+struct Block {
+  const Slot *s;
+  const SlotCtl *ctl;
+  SlotState *st;
+  int lb;
+};
+
+__device__ __forceinline__ Block block_of(const Slot *slots, const int2 *btab) {
+  int2 t = btab[blockIdx.x];
+  Block b;
+  b.s = slots + t.x;
+  b.ctl = b.s->ctl;
+  b.st = b.s->st;
+  b.lb = t.y;
+  return b;
+}
+
+__device__ __forceinline__ Cell cell_of(const Slot &s, int lb) {
+  Cell c;
+  int64_t g = (int64_t)lb * BLOCK + threadIdx.x;
+  c.valid = g < s.nc;
+  c.P = g;
+  c.i = c.j = c.k = 0;
+  if (c.valid) {
+    c.i = (int)(g % s.nx);
+    int64_t t = g / s.nx;
+    c.j = (int)(t % s.ny);
+    c.k = (int)(t / s.ny);
+  }
+  return c;
+}
+
+__device__ __forceinline__ int64_t cidx(const Slot &s, int i, int j, int k) {
+  return i + (int64_t)s.nx * (j + (int64_t)s.ny * k);
+}
+
+__device__ __forceinline__ int64_t fidx(const Slot &s, int e, int i, int j, int k) {
+  if (e == 0) return i + (int64_t)(s.nx + 1) * (j + (int64_t)s.ny * k);
+  if (e == 1) return s.nf0 + i + (int64_t)s.nx * (j + (int64_t)(s.ny + 1) * k);
+  return s.nf0 + s.nf1 + i + (int64_t)s.nx * (j + (int64_t)s.ny * k);
+}
+
+__device__ __forceinline__ bool solid_at(const Slot &s, int64_t P) { return (s.flags[P] & 0x40) != 0; }
+
+// face f (0..5 = x-,x+,y-,y+,z-,z+) of a fluid cell
+struct CFace {
+  int type;
+  int64_t nb, fi;
+};
+
+__device__ __forceinline__ CFace cell_face(const Slot &s, uint8_t fl, int i, int j, int k, int f) {
+  CFace c;
+  int e = f >> 1, hi = f & 1;
+  c.nb = -1;
+  c.fi = -1;
+  if (e >= s.dim) { c.type = F_NONE; return c; }
+  int ii = i + (e == 0 ? (hi ? 1 : -1) : 0);
+  int jj = j + (e == 1 ? (hi ? 1 : -1) : 0);
+  int kk = k + (e == 2 ? (hi ? 1 : -1) : 0);
+  c.fi = hi ? fidx(s, e, ii, jj, kk) : fidx(s, e, i, j, k);
+  if (fl & (1u << f)) { c.type = F_INT; c.nb = cidx(s, ii, jj, kk); return c; }
+  bool inbox = ii >= 0 && ii < s.nx && jj >= 0 && jj < s.ny && kk >= 0 && kk < s.nz;
+  c.type = inbox ? F_WALL : s.bcf[f];
+  return c;
+}
+
+// face of direction e whose high-side cell is (i,j,k) (coordinate along e in [0, n_e])
+struct FView {
+  int type;
+  int64_t lo, hi, P;
+  double sf;   // orientation sign seen from the fluid cell (WALL / INLET / OUTLET)
+};
+
+__device__ __forceinline__ FView face_view(const Slot &s, int e, int i, int j, int k) {
+  FView v;
+  int li = i - (e == 0), lj = j - (e == 1), lk = k - (e == 2);
+  bool loin = (e == 0 ? li >= 0 : (e == 1 ? lj >= 0 : lk >= 0));
+  bool hiin = (e == 0 ? i < s.nx : (e == 1 ? j < s.ny : k < s.nz));
+  v.lo = loin ? cidx(s, li, lj, lk) : -1;
+  v.hi = hiin ? cidx(s, i, j, k) : -1;
+  bool lof = loin && !solid_at(s, v.lo);
+  bool hif = hiin && !solid_at(s, v.hi);
+  v.type = F_NONE;
+  v.P = -1;
+  v.sf = 0.0;
+  if (lof && hif) { v.type = F_INT; return v; }
+  if (!lof && !hif) return v;
+  if (lof) { v.P = v.lo; v.sf = 1.0; } else { v.P = v.hi; v.sf = -1.0; }
+  if (loin && hiin) { v.type = F_WALL; return v; }
+  v.type = s.bcf[2 * e + (lof ? 1 : 0)];
+  return v;
+}
+
+// visit the faces owned by the thread of cell c: (e, fi, view)
+template <class Fn>
+__device__ __forceinline__ void for_owned_faces(const Slot &s, const Cell &c, Fn &&fn) {
+  for (int e = 0; e < s.dim; ++e) {
+    fn(e, fidx(s, e, c.i, c.j, c.k), face_view(s, e, c.i, c.j, c.k));
+    bool last = e == 0 ? c.i == s.nx - 1 : (e == 1 ? c.j == s.ny - 1 : c.k == s.nz - 1);
+    if (last) {
+      int i = c.i + (e == 0), j = c.j + (e == 1), k = c.k + (e == 2);
+      fn(e, fidx(s, e, i, j, k), face_view(s, e, i, j, k));
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// deterministic per-slot reductions
+// ---------------------------------------------------------------------------
+
+template <unsigned MAXMASK, int M>
+__device__ __forceinline__ void wave_reduce(double (&v)[M]) {
+#pragma unroll
+  for (int m = 0; m < M; ++m) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      double o = __shfl_down(v[m], off, 64);
+      if ((MAXMASK >> m) & 1u) v[m] = o > v[m] ? o : v[m];
+      else v[m] = v[m] + o;
+    }
+  }
+}
+
+// Reduce v over the block, publish the block partial, and return true in the
+// block that arrives last for its slot; there thread 0 holds the slot totals.
+template <unsigned MAXMASK, int M>
+__device__ bool reduce_last(const Slot &s, int lb, double (&v)[M]) {
+  __shared__ double sh[M][BLOCK / 64];
+  __shared__ int amlast;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  wave_reduce<MAXMASK>(v);
+  if (lane == 0)
+#pragma unroll
+    for (int m = 0; m < M; ++m) sh[m][w] = v[m];
+  __syncthreads();
+  if (tid == 0) {
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      double t = sh[m][0];
+      for (int x = 1; x < BLOCK / 64; ++x) t = ((MAXMASK >> m) & 1u) ? (sh[m][x] > t ? sh[m][x] : t) : t + sh[m][x];
+      s.partials[(int64_t)lb * NRED + m] = t;
+    }
+    __threadfence();
+    unsigned tk = atomicAdd(s.ticket, 1u);
+    amlast = (tk == (unsigned)(s.nblocks - 1));
+  }
+  __syncthreads();
+  if (!amlast) return false;
+  __threadfence();
+#pragma unroll
+  for (int m = 0; m < M; ++m) {
+    double t = 0.0;
+    for (int b = tid; b < s.nblocks; b += BLOCK) {
+      double x = s.partials[(int64_t)b * NRED + m];
+      t = ((MAXMASK >> m) & 1u) ? (x > t ? x : t) : t + x;
+    }
+    v[m] = t;
+  }
+  wave_reduce<MAXMASK>(v);
+  __syncthreads();
+  if (lane == 0)
+#pragma unroll
+    for (int m = 0; m < M; ++m) sh[m][w] = v[m];
+  __syncthreads();
+  if (tid == 0) {
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      double t = sh[m][0];
+      for (int x = 1; x < BLOCK / 64; ++x) t = ((MAXMASK >> m) & 1u) ? (sh[m][x] > t ? sh[m][x] : t) : t + sh[m][x];
+      v[m] = t;
+    }
+    *s.ticket = 0u;
+  }
+  return true;
+}
+
+// ---------------------------------------------------------------------------
+// mixture properties
+// ---------------------------------------------------------------------------
+
+template <typename R>
+__device__ __forceinline__ R rho_of(const Slot &s, R a) {
+  return a * (R)s.rho1 + ((R)1 - a) * (R)s.rho2;
+}
+template <typename R>
+__device__ __forceinline__ R mu_of(const Slot &s, R a) {
+  return a * (R)s.mu1 + ((R)1 - a) * (R)s.mu2;
+}
+
+template <typename R>
+__device__ __forceinline__ R vnorm(const R *v, int d) {
+  R t = v[0] * v[0] + v[1] * v[1];
+  if (d == 3) t = t + v[2] * v[2];
+  return sqrt(t);
+}
+
+// ---------------------------------------------------------------------------
+// control kernels
+// ---------------------------------------------------------------------------
+
+__global__ void k_ctl_update(Slot *slots, CtlUpdate u) {
+  int t = threadIdx.x;
+  if (t < u.n) *slots[u.slot[t]].ctl = u.ctl[t];
+}
+
+__global__ void k_state_reset(const Slot *slots, int nslots, int relax) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nslots) return;
+  const Slot &s = slots[t];
+  if (!s.ctl->active) return;
+  SlotState *st = s.st;
+  st->nonfinite = 0;
+  st->unstable = 0;
+  st->maxit_hit = 0;
+  st->total_it = 0;
+  st->refine_steps = 0;
+  if (relax) {
+    st->relax_done = 0;
+    st->k = 0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// viscous step prologue: keep u_vd^n (face fluxes) for the transport and the
+// convecting velocity of this global step
+// ---------------------------------------------------------------------------
+
+template <typename R>
+__global__ void __launch_bounds__(BLOCK) k_copy_phi_prev(const Slot *slots, const int2 *btab) {
+  Block B = block_of(slots, btab);
+  const Slot &s = *B.s;
+  if (!B.ctl->active || B.ctl->mode != 0) return;
+  Cell c = cell_of(s, B.lb);
+  if (!c.valid) return;
+  const R *src = (const R *)s.phi_vd;
+  R *dst = (R *)s.phi_prev;
+  for_owned_faces(s, c, [&](int, int64_t fi, const FView &) { dst[fi] = src[fi]; });
+}
+
+// ---------------------------------------------------------------------------
+// interface normal and curvature
+// ---------------------------------------------------------------------------
+
+template <typename R>
+__global__ void __launch_bounds__(BLOCK) k_grad_alpha(const Slot *slots, const int2 *btab, int only_cr) {
+  Block B = block_of(slots, btab);
+  const Slot &s = *B.s;
+  if (!B.ctl->active || (only_cr && B.ctl->mode != 1)) return;
+  Cell c = cell_of(s, B.lb);
+  if (!c.valid) return;
+  const R *a = (const R *)s.alpha;
+  R *g = (R *)s.grad;
+  uint8_t fl = s.flags[c.P];
+  for (int e = 0; e < s.dim; ++e) {
+    R ge = (R)0;
+    if (!(fl & 0x40)) {
+      CFace lo = cell_face(s, fl, c.i, c.j, c.k, 2 * e), hi = cell_face(s, fl, c.i, c.j, c.k, 2 * e + 1);
+      R alo = lo.type == F_INT ? (R)0.5 * (a[c.P] + a[lo.nb]) : a[c.P];
+      R ahi = hi.type == F_INT ? (R)0.5 * (a[c.P] + a[hi.nb]) : a[c.P];
+      ge = (ahi - alo) / (R)s.h;
+    }
+    g[e * s.nc + c.P] = ge;
+  }
+}
+
+template <typename R>
+__global__ void __launch_bounds__(BLOCK) k_face_normals(const Slot *slots, const int2 *btab, int only_cr) {
+  Block B = block_of(slots, btab);
+  const Slot &s = *B.s;
+  if (!B.ctl->active || (only_cr && B.ctl->mode != 1)) return;
+  Cell c = cell_of(s, B.lb);
+  if (!c.valid) return;
+  const R *g = (const R *)s.grad;
+  R *nh = (R *)s.nhatf;
+  const int d = s.dim;
+  const R delta = (R)s.delta;
+  for_owned_faces(s, c, [&](int e, int64_t fi, const FView &v) {
+    R G[3] = {(R)0, (R)0, (R)0};
+    R out = (R)0;
+    if (v.type == F_INT) {
+      for (int cc = 0; cc < d; ++cc) G[cc] = (R)0.5 * (g[cc * s.nc + v.lo] + g[cc * s.nc + v.hi]);
+      out = G[e] / (vnorm(G, d) + delta);
+    } else if (v.type == F_INLET || v.type == F_OUTLET) {
+      for (int cc = 0; cc < d; ++cc) G[cc] = g[cc * s.nc + v.P];
+      out = G[e] / (vnorm(G, d) + delta);
+    } else if (v.type == F_WALL) {
+      for (int cc = 0; cc < d; ++cc) G[cc] = g[cc * s.nc + v.P];
+      R mg = vnorm(G, d);
+      if (mg <= delta) {
+        out = (R)0;
+      } else {
+        // Brackbill wall adhesion: n = cos(theta) n_w + sin(theta) t/|t|,
+        // n_w the unit normal from the fluid into the wall
+        R nw[3] = {(R)0, (R)0, (R)0}, m[3] = {(R)0, (R)0, (R)0}, t[3] = {(R)0, (R)0, (R)0};
+        nw[e] = (R)v.sf;
+        for (int cc = 0; cc < d; ++cc) m[cc] = G[cc] / (mg + delta);
+        R mn = (R)0;
+        for (int cc = 0; cc < d; ++cc) mn = mn + m[cc] * nw[cc];
+        for (int cc = 0; cc < d; ++cc) t[cc] = m[cc] - mn * nw[cc];
+        R tm = vnorm(t, d);
+        if (tm <= (R)1e-12) out = m[e];
+        else out = (R)s.cos_t * nw[e] + (R)s.sin_t * t[e] / tm;
+      }
+    }
+    nh[fi] = out;
+  });
+}
+
+template <typename R>
+__global__ void __launch_bounds__(BLOCK) k_curvature(const Slot *slots, const int2 *btab) {
+  Block B = block_of(slots, btab);
+  const Slot &s = *B.s;
+  if (!B.ctl->active || B.ctl->mode != 1) return;
+  Cell c = cell_of(s, B.lb);
+  if (!c.valid) return;
+  const R *nh = (const R *)s.nhatf;
+  R *kap = (R *)s.kappa;
+  uint8_t fl = s.flags[c.P];
+  R out = (R)0;
+  if (!(fl & 0x40)) {
+    R acc = (R)0;
+    for (int e = 0; e < s.dim; ++e) {
+      CFace lo = cell_face(s, fl, c.i, c.j, c.k, 2 * e), hi = cell_face(s, fl, c.i, c.j, c.k, 2 * e + 1);
+      acc = acc + (nh[hi.fi] - nh[lo.fi]);
+    }
+    out = -acc / (R)s.h;
+  }
+  kap[c.P] = out;
+}
+
+// surface-tension face term sigma*kappa_f*(alpha_hi - alpha_lo)/h
+template <typename R>
+__device__ __forceinline__ R st_face(const Slot &s, const R *kap, const R *a, int64_t lo, int64_t hi) {
+  return ((R)s.sigma * ((R)0.5 * (kap[lo] + kap[hi]))) * ((a[hi] - a[lo]) / (R)s.h);
+}
+
+// ---------------------------------------------------------------------------
+// alpha transport: upwind + van Leer/compression, Zalesak limiter
+// ---------------------------------------------------------------------------
+
+template <typename R>
+__global__ void __launch_bounds__(BLOCK) k_mules_flux(const Slot *slots, const int2 *btab) {
+  Block B = block_of(slots, btab);
+  const Slot &s = *B.s;
+  const SlotCtl &ctl = *B.ctl;
+  if (!ctl.active) return;
+  Cell c = cell_of(s, B.lb);
+  const R *a = (const R *)s.alpha;
+  const R *phi = (const R *)(ctl.mode ? s.phi_cr : s.phi_prev);
+  const R *nh = (const R *)s.nhatf;
+  double red[2] = {0.0, 0.0};   // max Courant, sum alpha
+  if (c.valid) {
+    uint8_t fl = s.flags[c.P];
+    ((R *)s.alpha_old)[c.P] = a[c.P];
+    R *FL = (R *)s.FL, *Af = (R *)s.Af;
+    for_owned_faces(s, c, [&](int e, int64_t fi, const FView &v) {
+      R fl_ = (R)0, af = (R)0, ph = phi[fi];
+      if (v.type == F_INT) {
+        int64_t C = ph >= (R)0 ? v.lo : v.hi;
+        int64_t D = ph >= (R)0 ? v.hi : v.lo;
+        // cell beyond C, away from D
+        int ci = (int)(C % s.nx);
+        int64_t t = C / s.nx;
+        int cj = (int)(t % s.ny), ck = (int)(t / s.ny);
+        int step = ph >= (R)0 ? -1 : 1;
+        int ui = ci + (e == 0 ? step : 0), uj = cj + (e == 1 ? step : 0), uk = ck + (e == 2 ? step : 0);
+        R aUU = a[C];
+        if (ui >= 0 && ui < s.nx && uj >= 0 && uj < s.ny && uk >= 0 && uk < s.nz) {
+          int64_t U = cidx(s, ui, uj, uk);
+          if (!solid_at(s, U)) aUU = a[U];
+        }
+        R dD = a[D] - a[C], dU = a[C] - aUU;
+        R avl = a[C] + (dU * dD > (R)0 ? (dU * dD) / (dU + dD) : (R)0);
+        R abar = (R)0.5 * (a[v.lo] + a[v.hi]);
+        R phir = fabs(ph) * nh[fi];
+        R Fc = (phir * abar) * ((R)1 - abar);
+        R FH = ph * avl + Fc;
+        fl_ = ph * a[C];
+        af = FH - fl_;
+      } else if (v.type == F_INLET || v.type == F_OUTLET) {
+        fl_ = ph * a[v.P];
+      }
+      FL[fi] = fl_;
+      Af[fi] = af;
+    });
+    if (!(fl & 0x40)) {
+      R acc = (R)0;
+      for (int f = 0; f < 2 * s.dim; ++f) {
+        CFace cf = cell_face(s, fl, c.i, c.j, c.k, f);
+        if (cf.type == F_NONE) continue;
+        R sp = ((f & 1) ? (R)1 : (R)-1) * phi[cf.fi];
+        if (sp > (R)0) acc = acc + sp;
+      }
+      red[0] = (double)(acc * ((R)ctl.dt / (R)s.V));
+      red[1] = (double)a[c.P];
+    }
+  }
+  if (reduce_last<1u>(s, B.lb, red) && threadIdx.x == 0) {
+    B.st->comax = red[0];
+    B.st->mass0 = red[1] * s.V;
+    if (red[0] > 1.0) B.st->unstable = 1;
+  }
+}
+
+template <typename R>
+__global__ void __launch_bounds__(BLOCK) k_mules_limiter(const Slot *slots, const int2 *btab) {
+  Block B = block_of(slots, btab);
+  const Slot &s = *B.s;
+  const SlotCtl &ctl = *B.ctl;
+  if (!ctl.active) return;
+  Cell c = cell_of(s, B.lb);
+  if (!c.valid) return;
+  const R *a = (const R *)s.alpha;
+  const R *FL = (const R *)s.FL, *Af = (const R *)s.Af;
+  R *Rp = (R *)s.Rp, *Rm = (R *)s.Rm;
+  uint8_t fl = s.flags[c.P];
+  R rp = (R)0, rm = (R)0;
+  if (!(fl & 0x40)) {
+    const R dtV = (R)ctl.dt / (R)s.V, Vdt = (R)s.V / (R)ctl.dt;
+    R sumL = (R)0, Pp = (R)0, Pm = (R)0, amax = a[c.P], amin = a[c.P];
+    for (int f = 0; f < 2 * s.dim; ++f) {
+      CFace cf = cell_face(s, fl, c.i, c.j, c.k, f);
+      if (cf.type == F_NONE) continue;
+      R sg = (f & 1) ? (R)1 : (R)-1;
+      sumL = sumL + sg * FL[cf.fi];
+      R sA = sg * Af[cf.fi];
+      Pp = Pp + (sA < (R)0 ? -sA : (R)0);
+      Pm = Pm + (sA > (R)0 ? sA : (R)0);
+      if (cf.type == F_INT) {
+        R an = a[cf.nb];
+        if (an > amax) amax = an;
+        if (an < amin) amin = an;
+      }
+    }
+    R aL = a[c.P] - dtV * sumL;
+    if (amax > (R)1) amax = (R)1;
+    if (amin < (R)0) amin = (R)0;
+    R Qp = Vdt * (amax - aL > (R)0 ? amax - aL : (R)0);
+    R Qm = Vdt * (aL - amin > (R)0 ? aL - amin : (R)0);
+    rp = Pp > (R)0 ? (Qp / Pp < (R)1 ? Qp / Pp : (R)1) : (R)0;
+    rm = Pm > (R)0 ? (Qm / Pm < (R)1 ? Qm / Pm : (R)1) : (R)0;
+  }
+  Rp[c.P] = rp;
+  Rm[c.P] = rm;
+}
+
+template <typename R>
+__global__ void __launch_bounds__(BLOCK) k_mules_update(const Slot *slots, const int2 *btab) {
+  Block B = block_of(slots, btab);
+  const Slot &s = *B.s;
+  const SlotCtl &ctl = *B.ctl;
+  if (!ctl.active) return;
+  Cell c = cell_of(s, B.lb);
+  double red[2] = {0.0, 0.0};   // sum alpha_new, boundary flux
+  if (c.valid) {
+    R *a = (R *)s.alpha;
+    const R *FL = (const R *)s.FL, *Af = (const R *)s.Af, *Rp = (const R *)s.Rp, *Rm = (const R *)s.Rm;
+    uint8_t fl = s.flags[c.P];
+    if (!(fl & 0x40)) {
+      const R dtV = (R)ctl.dt / (R)s.V;
+      R acc = (R)0, bfl = (R)0;
+      for (int f = 0; f < 2 * s.dim; ++f) {
+        CFace cf = cell_face(s, fl, c.i, c.j, c.k, f);
+        if (cf.type == F_NONE) continue;
+        R sg = (f & 1) ? (R)1 : (R)-1;
+        R lam = (R)0;
+        if (cf.type == F_INT) {
+          int64_t lo = (f & 1) ? c.P : cf.nb, hi = (f & 1) ? cf.nb : c.P;
+          R A = Af[cf.fi];
+          R x1 = A >= (R)0 ? Rm[lo] : Rp[lo];
+          R x2 = A >= (R)0 ? Rp[hi] : Rm[hi];
+          lam = x1 < x2 ? x1 : x2;
+        } else {
+          bfl = bfl + sg * FL[cf.fi];
+        }
+        acc = acc + sg * (FL[cf.fi] + lam * Af[cf.fi]);
+      }
+      R an = a[c.P] - dtV * acc;
+      a[c.P] = an;
+      red[0] = (double)an;
+      red[1] = (double)bfl;
+    }
+  }
+  if (reduce_last<0u>(s, B.lb, red) && threadIdx.x == 0) {
+    SlotState *st = B.st;
+    st->mass1 = red[0] * s.V;
+    st->bflux = red[1];
+    double defect = fabs(st->mass1 - st->mass0 + ctl.dt * red[1]);
+    if (defect > st->mass_defect) st->mass_defect = defect;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// momentum matrix
+// ---------------------------------------------------------------------------
+
+template <typename R>
+__device__ __forceinline__ R inlet_u(int cc, int e, R sg, R ub) {
+  return cc == e ? -sg * ub : (R)0;
+}
+
+template <typename R>
+__global__ void __launch_bounds__(BLOCK) k_grad_u(const Slot *slots, const int2 *btab) {
+  Block B = block_of(slots, btab);
+  const Slot &s = *B.s;
+  const SlotCtl &ctl = *B.ctl;
+  if (!ctl.active) return;
+  Cell c = cell_of(s, B.lb);
+  if (!c.valid) return;
+  const int d = s.dim;
+  const R *Uo = (const R *)(ctl.mode ? s.U_cr : s.U_vd);
+  R *gU = (R *)s.gradU;
+  uint8_t fl = s.flags[c.P];
+  const R ub = (R)ctl.ub;
+  for (int e = 0; e < d; ++e) {
+    CFace fc[2];
+    fc[0] = cell_face(s, fl, c.i, c.j, c.k, 2 * e);
+    fc[1] = cell_face(s, fl, c.i, c.j, c.k, 2 * e + 1);
+    for (int cc = 0; cc < d; ++cc) {
+      const R *Uc = Uo + cc * s.nc;
+      R out = (R)0;
+      if (!(fl & 0x40)) {
+        R fv[2];
+        for (int sd = 0; sd < 2; ++sd) {
+          const CFace &cf = fc[sd];
+          if (cf.type == F_INT) fv[sd] = (R)0.5 * (Uc[c.P] + Uc[cf.nb]);
+          else if (cf.type == F_WALL) fv[sd] = (R)0;
+          else if (cf.type == F_INLET) fv[sd] = inlet_u<R>(cc, e, sd ? (R)1 : (R)-1, ub);
+          else fv[sd] = Uc[c.P];
+        }
+        out = (fv[1] - fv[0]) / (R)s.h;
+      }
+      gU[(cc * d + e) * s.nc + c.P] = out;
+    }
+  }
+}
+
+template <typename R>
+__global__ void __launch_bounds__(BLOCK) k_mass_flux(const Slot *slots, const int2 *btab) {
+  Block B = block_of(slots, btab);
+  const Slot &s = *B.s;
+  if (!B.ctl->active) return;
+  Cell c = cell_of(s, B.lb);
+  if (!c.valid) return;
+  const R *a = (const R *)s.alpha;
+  const R *pa = (const R *)s.phi_prev, *pc = (const R *)s.phi_cr;
+  R *Fm = (R *)s.Fm;
+  for_owned_faces(s, c, [&](int, int64_t fi, const FView &v) {
+    R phic = pa[fi] + pc[fi];
+    R F = (R)0;
+    if (v.type == F_INT) F = rho_of<R>(s, (R)0.5 * (a[v.lo] + a[v.hi])) * phic;
+    else if (v.type == F_INLET || v.type == F_OUTLET) F = rho_of<R>(s, a[v.P]) * phic;
+    Fm[fi] = F;
+  });
+}
+
+template <typename R>
+__global__ void __launch_bounds__(BLOCK) k_assemble(const Slot *slots, const int2 *btab) {
+  Block B = block_of(slots, btab);
+  const Slot &s = *B.s;
+  const SlotCtl &ctl = *B.ctl;
+  if (!ctl.active) return;
+  Cell c = cell_of(s, B.lb);
+  if (!c.valid) return;
+  const int d = s.dim;
+  const int64_t nc = s.nc;
+  const R *an = (const R *)s.alpha, *ao = (const R *)s.alpha_old;
+  const R *Uo = (const R *)(ctl.mode ? s.U_cr : s.U_vd);
+  const R *gU = (const R *)s.gradU, *Fm = (const R *)s.Fm;
+  R *aPo = (R *)s.aP, *rAUo = (R *)s.rAU, *bo = (R *)s.b;
+  uint8_t fl = s.flags[c.P];
+  if (fl & 0x40) {
+    aPo[c.P] = (R)0;
+    rAUo[c.P] = (R)0;
+    for (int cc = 0; cc < d; ++cc) bo[cc * nc + c.P] = (R)0;
+    return;
+  }
+  const R Vdt = (R)s.V / (R)ctl.dt;
+  const R hh = (R)s.hh, Sh = (R)s.Sh, S = (R)s.S, S2h = (R)s.S2h, ub = (R)ctl.ub;
+  R rho_o = rho_of<R>(s, ao[c.P]), rho_n = rho_of<R>(s, an[c.P]), mu_n = mu_of<R>(s, an[c.P]);
+  R aP = rho_n * Vdt;
+  R b[3];
+  for (int cc = 0; cc < d; ++cc) b[cc] = (rho_o * Uo[cc * nc + c.P]) * Vdt;
+  for (int f = 0; f < 2 * d; ++f) {
+    CFace cf = cell_face(s, fl, c.i, c.j, c.k, f);
+    int e = f >> 1;
+    R sg = (f & 1) ? (R)1 : (R)-1;
+    if (cf.type == F_INT) {
+      R F = Fm[cf.fi], sF = sg * F;
+      R muf = mu_of<R>(s, (R)0.5 * (an[c.P] + an[cf.nb]));
+      R D = muf * Sh;
+      aP = aP + (sF > (R)0 ? sF : (R)0);
+      aP = aP + D;
+      int64_t lo = (f & 1) ? c.P : cf.nb, hi = (f & 1) ? cf.nb : c.P;
+      for (int cc = 0; cc < d; ++cc) {
+        R lu = F >= (R)0 ? hh * gU[(cc * d + e) * nc + lo] : -(hh * gU[(cc * d + e) * nc + hi]);
+        b[cc] = b[cc] - sg * (F * lu);
+        R tv = (muf * S) * ((R)0.5 * (gU[(e * d + cc) * nc + c.P] + gU[(e * d + cc) * nc + cf.nb]));
+        b[cc] = b[cc] + sg * tv;
+      }
+    } else if (cf.type == F_WALL) {
+      aP = aP + mu_n * S2h;
+    } else if (cf.type == F_INLET) {
+      R F = Fm[cf.fi];
+      aP = aP + mu_n * S2h;
+      for (int cc = 0; cc < d; ++cc) {
+        R ubc = inlet_u<R>(cc, e, sg, ub);
+        b[cc] = b[cc] + (mu_n * S2h) * ubc;
+        b[cc] = b[cc] - sg * (F * ubc);
+      }
+    } else if (cf.type == F_OUTLET) {
+      aP = aP + sg * Fm[cf.fi];
+    }
+  }
+  aPo[c.P] = aP;
+  rAUo[c.P] = (R)s.V / aP;
+  for (int cc = 0; cc < d; ++cc) bo[cc * nc + c.P] = b[cc];
+}
+
+// ---------------------------------------------------------------------------
+// PISO corrector
+// ---------------------------------------------------------------------------
+
+template <typename R>
+__global__ void __launch_bounds__(BLOCK) k_predictor(const Slot *slots, const int2 *btab) {
+  Block B = block_of(slots, btab);
+  const Slot &s = *B.s;
+  const SlotCtl &ctl = *B.ctl;
+  if (!ctl.active) return;
+  Cell c = cell_of(s, B.lb);
+  if (!c.valid) return;
+  const int d = s.dim;
+  const int64_t nc = s.nc;
+  const R *an = (const R *)s.alpha, *U = (const R *)(ctl.mode ? s.U_cr : s.U_vd);
+  const R *Fm = (const R *)s.Fm, *b = (const R *)s.b, *aPv = (const R *)s.aP;
+  R *HbyA = (R *)s.HbyA;
+  uint8_t fl = s.flags[c.P];
+  if (fl & 0x40) {
+    for (int cc = 0; cc < d; ++cc) HbyA[cc * nc + c.P] = (R)0;
+    return;
+  }
+  R H[3];
+  for (int cc = 0; cc < d; ++cc) H[cc] = b[cc * nc + c.P];
+  for (int f = 0; f < 2 * d; ++f) {
+    CFace cf = cell_face(s, fl, c.i, c.j, c.k, f);
+    if (cf.type != F_INT) continue;
+    R sF = ((f & 1) ? (R)1 : (R)-1) * Fm[cf.fi];
+    R D = mu_of<R>(s, (R)0.5 * (an[c.P] + an[cf.nb])) * (R)s.Sh;
+    R aN = (sF < (R)0 ? sF : (R)0) - D;
+    for (int cc = 0; cc < d; ++cc) H[cc] = H[cc] - aN * U[cc * nc + cf.nb];
+  }
+  R aP = aPv[c.P];
+  for (int cc = 0; cc < d; ++cc) HbyA[cc * nc + c.P] = H[cc] / aP;
+}
+
+template <typename R>
+__global__ void __launch_bounds__(BLOCK) k_phiH(const Slot *slots, const int2 *btab) {
+  Block B = block_of(slots, btab);
+  const Slot &s = *B.s;
+  const SlotCtl &ctl = *B.ctl;
+  if (!ctl.active) return;
+  Cell c = cell_of(s, B.lb);
+  if (!c.valid) return;
+  const int64_t nc = s.nc;
+  const R *HbyA = (const R *)s.HbyA, *rAU = (const R *)s.rAU, *kap = (const R *)s.kappa, *a = (const R *)s.alpha;
+  R *phiH = (R *)s.phiH;
+  const R S = (R)s.S, ub = (R)ctl.ub;
+  const int with_st = ctl.with_st;
+  for_owned_faces(s, c, [&](int e, int64_t fi, const FView &v) {
+    R ph = (R)0;
+    if (v.type == F_INT) {
+      ph = ((R)0.5 * (HbyA[e * nc + v.lo] + HbyA[e * nc + v.hi])) * S;
+      if (with_st) {
+        R rAUf = (R)0.5 * (rAU[v.lo] + rAU[v.hi]);
+        ph = ph + (rAUf * st_face<R>(s, kap, a, v.lo, v.hi)) * S;
+      }
+    } else if (v.type == F_INLET) {
+      ph = -(R)v.sf * (ub * S);
+    } else if (v.type == F_OUTLET) {
+      ph = HbyA[e * nc + v.P] * S;
+    }
+    phiH[fi] = ph;
+  });
+}
+
+// pressure coefficient of face f of fluid cell P in precision X
+template <typename X, typename R>
+__device__ __forceinline__ X pcoef(const Slot &s, const R *rAU, int64_t P, const CFace &cf) {
+  if (cf.type == F_INT) return ((X)0.5 * ((X)rAU[P] + (X)rAU[cf.nb])) * (X)s.Sh;
+  if (cf.type == F_OUTLET) return (X)rAU[P] * (X)s.S2h;
+  return (X)0;
+}
+
+// (M x)_P in precision X, with x read through a functor xv(index)
+template <typename X, typename R, class XV>
+__device__ __forceinline__ X matvec_row(const Slot &s, const R *rAU, const Cell &c, uint8_t fl, XV &&xv) {
+  X acc = (X)0;
+  X xP = xv(c.P);
+  for (int f = 0; f < 2 * s.dim; ++f) {
+    CFace cf = cell_face(s, fl, c.i, c.j, c.k, f);
+    if (cf.type == F_INT) acc = acc + pcoef<X, R>(s, rAU, c.P, cf) * (xP - xv(cf.nb));
+    else if (cf.type == F_OUTLET) acc = acc + pcoef<X, R>(s, rAU, c.P, cf) * xP;
+  }
+  return acc;
+}
+
+// rhs = -div(phiH), r = rhs - M p, Jacobi diagonal, initial CG vectors
+template <typename R>
+__global__ void __launch_bounds__(BLOCK) k_pressure_setup(const Slot *slots, const int2 *btab) {
+  using T = R;
+  Block B = block_of(slots, btab);
+  const Slot &s = *B.s;
+  const SlotCtl &ctl = *B.ctl;
+  if (!ctl.active) return;
+  Cell c = cell_of(s, B.lb);
+  const R *rAU = (const R *)s.rAU, *phiH = (const R *)s.phiH;
+  const double *p = ctl.mode ? s.p_cr : s.p_vd;
+  const bool mixed = s.precision != 0;
+  double red[4] = {0.0, 0.0, 0.0, 0.0};   // |rhs|^2, |r|^2 (r of the solved system), r.z, sum p
+  if (c.valid) {
+    uint8_t fl = s.flags[c.P];
+    T *r = (T *)s.r, *z = (T *)s.z, *invD = (T *)s.invD;
+    if (fl & 0x40) {
+      s.rhs[c.P] = 0.0;
+      s.Mp[c.P] = 0.0;
+      r[c.P] = (T)0;
+      z[c.P] = (T)0;
+      invD[c.P] = (T)0;
+      if (mixed) ((T *)s.e)[c.P] = (T)0;
+    } else {
+      double acc = 0.0;
+      T dg = (T)0;
+      for (int f = 0; f < 2 * s.dim; ++f) {
+        CFace cf = cell_face(s, fl, c.i, c.j, c.k, f);
+        if (cf.type == F_NONE) continue;
+        acc = acc + ((f & 1) ? 1.0 : -1.0) * (double)phiH[cf.fi];
+        if (cf.type == F_INT || cf.type == F_OUTLET) dg = dg + pcoef<T, R>(s, rAU, c.P, cf);
+      }
+      double rhs = -acc;
+      double Mp = matvec_row<double, R>(s, rAU, c, fl, [&](int64_t x) { return p[x]; });
+      double r64 = rhs - Mp;
+      T id = (T)1 / dg;
+      T rr = (T)r64;
+      T zz = rr * id;
+      s.rhs[c.P] = rhs;
+      s.Mp[c.P] = Mp;
+      r[c.P] = rr;
+      z[c.P] = zz;
+      invD[c.P] = id;
+      if (mixed) ((T *)s.e)[c.P] = (T)0;
+      red[0] = rhs * rhs;
+      red[1] = mixed ? r64 * r64 : (double)(rr * rr);
+      red[2] = (double)(rr * zz);
+      red[3] = p[c.P];
+    }
+  }
+  if (reduce_last<0u>(s, B.lb, red) && threadIdx.x == 0) {
+    SlotState *st = B.st;
+    double bn = sqrt(red[0]);
+    double rn = sqrt(red[1]);
+    st->pbar = red[3] / (double)s.n_fluid;
+    st->rz = red[2];
+    st->it = 0;
+    st->zero_rhs = bn == 0.0;
+    if (mixed) {
+      // outer (FP64) residual; the inner system is M e = r32
+      st->bn64 = bn;
+      st->rn64 = rn;
+      st->bn = rn;    // refined below by k_refine_res when needed
+      st->rn = rn;
+      st->done = (bn == 0.0) || (rn <= ctl.rtol * bn);
+    } else {
+      st->bn = bn;
+      st->rn = rn;
+      st->done = (bn == 0.0) || (rn <= ctl.rtol * bn);
+    }
+  }
+}
+
+// p = 0 when the right-hand side vanishes (the unique solution)
+__global__ void __launch_bounds__(BLOCK) k_zero_rhs_p(const Slot *slots, const int2 *btab) {
+  Block B = block_of(slots, btab);
+  const Slot &s = *B.s;
+  const SlotCtl &ctl = *B.ctl;
+  if (!ctl.active || !B.st->zero_rhs) return;
+  Cell c = cell_of(s, B.lb);
+  if (!c.valid) return;
+  double *p = ctl.mode ? s.p_cr : s.p_vd;
+  p[c.P] = 0.0;
+}
+
+// normalised residual E = sum|b - Mp| / (sum(|Mp - M pbar| + |b - M pbar|) + 1e-20)
+template <typename R>
+__global__ void __launch_bounds__(BLOCK) k_normres(const Slot *slots, const int2 *btab) {
+  Block B = block_of(slots, btab);
+  const Slot &s = *B.s;
+  const SlotCtl &ctl = *B.ctl;
+  if (!ctl.active || ctl.mode != 1) return;
+  Cell c = cell_of(s, B.lb);
+  const R *rAU = (const R *)s.rAU;
+  const double pbar = B.st->pbar;
+  double red[2] = {0.0, 0.0};
+  if (c.valid) {
+    uint8_t fl = s.flags[c.P];
+    if (!(fl & 0x40)) {
+      double Mpb = matvec_row<double, R>(s, rAU, c, fl, [&](int64_t) { return pbar; });
+      double rhs = s.rhs[c.P], Mp = s.Mp[c.P];
+      red[0] = fabs(rhs - Mp);
+      red[1] = fabs(Mp - Mpb) + fabs(rhs - Mpb);
+    }
+  }
+  if (reduce_last<0u>(s, B.lb, red) && threadIdx.x == 0) B.st->E = red[0] / (red[1] + 1e-20);
+}
+
+// conjugate gradient, pass 1: d = z + beta d_old (d = z on the first
+// iteration), q = M d, <d, q>
+template <typename R>
+__global__ void __launch_bounds__(BLOCK) k_pcg1(const Slot *slots, const int2 *btab) {
+  using T = R;
+  Block B = block_of(slots, btab);
+  const Slot &s = *B.s;
+  const SlotCtl &ctl = *B.ctl;
+  if (!ctl.active) return;
+  const SlotState &st0 = *B.st;
+  if (st0.done) return;
+  const int it = st0.it;
+  const bool first = it == 0;
+  const T beta = (T)st0.beta;
+  Cell c = cell_of(s, B.lb);
+  const R *rAU = (const R *)s.rAU;
+  const T *z = (const T *)s.z;
+  const T *dold = (const T *)((it & 1) ? s.d1 : s.d0);
+  T *dnew = (T *)((it & 1) ? s.d0 : s.d1);
+  T *q = (T *)s.q;
+  double red[1] = {0.0};
+  if (c.valid) {
+    uint8_t fl = s.flags[c.P];
+    if (fl & 0x40) {
+      dnew[c.P] = (T)0;
+      q[c.P] = (T)0;
+    } else {
+      auto dv = [&](int64_t x) -> T { return first ? z[x] : z[x] + beta * dold[x]; };
+      T dP = dv(c.P);
+      T qq = matvec_row<T, R>(s, rAU, c, fl, dv);
+      dnew[c.P] = dP;
+      q[c.P] = qq;
+      red[0] = (double)(dP * qq);
+    }
+  }
+  if (reduce_last<0u>(s, B.lb, red) && threadIdx.x == 0) {
+    B.st->dq = red[0];
+    B.st->cg_alpha = B.st->rz / red[0];
+  }
+}
+
+// pass 2: x += a d, r -= a q, z = D^-1 r, |r|^2, <r, z>; convergence test
+template <typename R>
+__global__ void __launch_bounds__(BLOCK) k_pcg2(const Slot *slots, const int2 *btab) {
+  using T = R;
+  Block B = block_of(slots, btab);
+  const Slot &s = *B.s;
+  const SlotCtl &ctl = *B.ctl;
+  if (!ctl.active) return;
+  const SlotState &st0 = *B.st;
+  if (st0.done) return;
+  const int it = st0.it;
+  const bool mixed = s.precision != 0;
+  const T al = (T)st0.cg_alpha;
+  Cell c = cell_of(s, B.lb);
+  const T *d = (const T *)((it & 1) ? s.d0 : s.d1);
+  const T *q = (const T *)s.q, *invD = (const T *)s.invD;
+  T *r = (T *)s.r, *z = (T *)s.z;
+  double red[2] = {0.0, 0.0};
+  if (c.valid && !solid_at(s, c.P)) {
+    if (mixed) {
+      T *x = (T *)s.e;
+      x[c.P] = x[c.P] + al * d[c.P];
+    } else {
+      double *x = ctl.mode ? s.p_cr : s.p_vd;
+      x[c.P] = x[c.P] + (double)al * (double)d[c.P];
+    }
+    T rr = r[c.P] - al * q[c.P];
+    T zz = rr * invD[c.P];
+    r[c.P] = rr;
+    z[c.P] = zz;
+    red[0] = (double)(rr * rr);
+    red[1] = (double)(rr * zz);
+  }
+  if (reduce_last<0u>(s, B.lb, red) && threadIdx.x == 0) {
+    SlotState *st = B.st;
+    double rn = sqrt(red[0]);
+    st->rn = rn;
+    st->it = it + 1;
+    st->total_it = st->total_it + 1;
+    double rtol = mixed ? ctl.rtol_inner : ctl.rtol;
+    if (rn <= rtol * st->bn) {
+      st->done = 1;
+    } else if (it + 1 >= ctl.max_it) {
+      st->done = 1;
+      st->maxit_hit = st->maxit_hit + 1;
+    } else {
+      st->beta = red[1] / st->rz;
+      st->rz = red[1];
+    }
+  }
+}
+
+// mixed precision, outer refinement: p += e, e = 0
+template <typename R>
+__global__ void __launch_bounds__(BLOCK) k_refine_x(const Slot *slots, const int2 *btab) {
+  Block B = block_of(slots, btab);
+  const Slot &s = *B.s;
+  const SlotCtl &ctl = *B.ctl;
+  if (!ctl.active || s.precision == 0 || B.st->zero_rhs) return;
+  Cell c = cell_of(s, B.lb);
+  if (!c.valid || solid_at(s, c.P)) return;
+  double *p = ctl.mode ? s.p_cr : s.p_vd;
+  R *e = (R *)s.e;
+  p[c.P] = p[c.P] + (double)e[c.P];
+  e[c.P] = (R)0;
+}
+
+// mixed precision: r64 = rhs - M p in FP64; restart the FP32 inner solve on it
+template <typename R>
+__global__ void __launch_bounds__(BLOCK) k_refine_res(const Slot *slots, const int2 *btab) {
+  using T = R;
+  Block B = block_of(slots, btab);
+  const Slot &s = *B.s;
+  const SlotCtl &ctl = *B.ctl;
+  if (!ctl.active || s.precision == 0 || B.st->zero_rhs) return;
+  Cell c = cell_of(s, B.lb);
+  const R *rAU = (const R *)s.rAU;
+  const double *p = ctl.mode ? s.p_cr : s.p_vd;
+  double red[3] = {0.0, 0.0, 0.0};
+  if (c.valid) {
+    uint8_t fl = s.flags[c.P];
+    T *r = (T *)s.r, *z = (T *)s.z;
+    const T *invD = (const T *)s.invD;
+    if (!(fl & 0x40)) {
+      double Mp = matvec_row<double, R>(s, rAU, c, fl, [&](int64_t x) { return p[x]; });
+      double r64 = s.rhs[c.P] - Mp;
+      T rr = (T)r64;
+      T zz = rr * invD[c.P];
+      r[c.P] = rr;
+      z[c.P] = zz;
+      red[0] = r64 * r64;
+      red[1] = (double)(rr * rr);
+      red[2] = (double)(rr * zz);
+    }
+  }
+  if (reduce_last<0u>(s, B.lb, red) && threadIdx.x == 0) {
+    SlotState *st = B.st;
+    st->rn64 = sqrt(red[0]);
+    st->bn = sqrt(red[1]);
+    st->rn = st->bn;
+    st->rz = red[2];
+    st->it = 0;
+    st->refine_steps = st->refine_steps + 1;
+    st->done = st->rn64 <= ctl.rtol * st->bn64;
+  }
+}
+
+// phi = phiH - rAU_f S/h (p_hi - p_lo); u = HbyA + rAU * mean of the face
+// accelerations (f - grad p) of the two faces of each direction
+template <typename R>
+__global__ void __launch_bounds__(BLOCK) k_correct(const Slot *slots, const int2 *btab, int last) {
+  Block B = block_of(slots, btab);
+  const Slot &s = *B.s;
+  const SlotCtl &ctl = *B.ctl;
+  if (!ctl.active) return;
+  Cell c = cell_of(s, B.lb);
+  if (!c.valid) return;
+  const int d = s.dim;
+  const int64_t nc = s.nc;
+  const double *p = ctl.mode ? s.p_cr : s.p_vd;
+  const R *phiH = (const R *)s.phiH, *rAU = (const R *)s.rAU, *HbyA = (const R *)s.HbyA;
+  const R *kap = (const R *)s.kappa, *a = (const R *)s.alpha;
+  R *phi = (R *)(ctl.mode ? s.phi_cr : s.phi_vd);
+  R *U = (R *)(ctl.mode ? s.U_cr : s.U_vd);
+  const R Sh = (R)s.Sh, S2h = (R)s.S2h, h = (R)s.h, hh = (R)s.hh;
+  const int with_st = ctl.with_st;
+  for_owned_faces(s, c, [&](int, int64_t fi, const FView &v) {
+    R ph = phiH[fi];
+    if (v.type == F_INT) {
+      R cf = ((R)0.5 * (rAU[v.lo] + rAU[v.hi])) * Sh;
+      ph = ph - cf * (R)(p[v.hi] - p[v.lo]);
+    } else if (v.type == F_OUTLET) {
+      R cf = rAU[v.P] * S2h;
+      ph = ph + (R)v.sf * (cf * (R)p[v.P]);
+    }
+    phi[fi] = ph;
+  });
+  uint8_t fl = s.flags[c.P];
+  R *Us = (R *)s.U_sum;
+  bool bad = false;
+  for (int cc = 0; cc < d; ++cc) {
+    R u = (R)0;
+    if (!(fl & 0x40)) {
+      R qv[2];
+      for (int sd = 0; sd < 2; ++sd) {
+        CFace cf = cell_face(s, fl, c.i, c.j, c.k, 2 * cc + sd);
+        R qq = (R)0;
+        if (cf.type == F_INT) {
+          int64_t lo = sd ? c.P : cf.nb, hi = sd ? cf.nb : c.P;
+          R ff = with_st ? st_face<R>(s, kap, a, lo, hi) : (R)0;
+          qq = ff - (R)(p[hi] - p[lo]) / h;
+        } else if (cf.type == F_OUTLET) {
+          R pplus = sd ? (R)0 : (R)p[c.P], pminus = sd ? (R)p[c.P] : (R)0;
+          qq = -(pplus - pminus) / hh;
+        }
+        qv[sd] = qq;
+      }
+      u = HbyA[cc * nc + c.P] + rAU[c.P] * ((R)0.5 * (qv[0] + qv[1]));
+      if (!(u == u) || fabs(u) > (R)1e30) bad = true;
+    }
+    U[cc * nc + c.P] = u;
+    if (last && ctl.mode == 1) Us[cc * nc + c.P] = Us[cc * nc + c.P] + u;
+  }
+  if (bad) atomicOr(&B.st->nonfinite, 1);
+}
+
+// U = U_vd + (1/N) sum u_cr, p = p_vd + p_cr
+template <typename R>
+__global__ void __launch_bounds__(BLOCK) k_finalize(const Slot *slots, const int2 *btab) {
+  Block B = block_of(slots, btab);
+  const Slot &s = *B.s;
+  const SlotCtl &ctl = *B.ctl;
+  if (!ctl.active || ctl.mode != 1) return;
+  Cell c = cell_of(s, B.lb);
+  if (!c.valid) return;
+  const R *Uvd = (const R *)s.U_vd, *Us = (const R *)s.U_sum;
+  R *U = (R *)s.U;
+  for (int cc = 0; cc < s.dim; ++cc) {
+    int64_t x = cc * s.nc + c.P;
+    U[x] = Uvd[x] + Us[x] / (R)ctl.n_sub;
+  }
+  s.p[c.P] = s.p_vd[c.P] + s.p_cr[c.P];
+}
+
+template <typename R>
+__global__ void __launch_bounds__(BLOCK) k_zero_usum(const Slot *slots, const int2 *btab) {
+  Block B = block_of(slots, btab);
+  const Slot &s = *B.s;
+  if (!B.ctl->active || B.ctl->mode != 1) return;
+  Cell c = cell_of(s, B.lb);
+  if (!c.valid) return;
+  R *Us = (R *)s.U_sum;
+  for (int cc = 0; cc < s.dim; ++cc) Us[cc * s.nc + c.P] = (R)0;
+}
+
+// ---------------------------------------------------------------------------
+// host launchers
+// ---------------------------------------------------------------------------
+
+#define GRID(L) dim3((unsigned)(L).nblocks), dim3(BLOCK), 0, (L).stream
+
+template <typename R> void launch_copy_phi_prev(const Launch &L) {
+  hipLaunchKernelGGL(k_copy_phi_prev<R>, GRID(L), L.slots, L.btab);
+}
+
+template <typename R> void launch_normals(const Launch &L, bool curvature) {
+  int only_cr = curvature ? 1 : 0;
+  hipLaunchKernelGGL(k_grad_alpha<R>, GRID(L), L.slots, L.btab, only_cr);
+  hipLaunchKernelGGL(k_face_normals<R>, GRID(L), L.slots, L.btab, only_cr);
+  if (curvature) hipLaunchKernelGGL(k_curvature<R>, GRID(L), L.slots, L.btab);
+}
+
+template <typename R> void launch_advect(const Launch &L) {
+  hipLaunchKernelGGL(k_mules_flux<R>, GRID(L), L.slots, L.btab);
+  hipLaunchKernelGGL(k_mules_limiter<R>, GRID(L), L.slots, L.btab);
+  hipLaunchKernelGGL(k_mules_update<R>, GRID(L), L.slots, L.btab);
+}
+
+template <typename R> void launch_assemble(const Launch &L) {
+  hipLaunchKernelGGL(k_grad_u<R>, GRID(L), L.slots, L.btab);
+  hipLaunchKernelGGL(k_mass_flux<R>, GRID(L), L.slots, L.btab);
+  hipLaunchKernelGGL(k_assemble<R>, GRID(L), L.slots, L.btab);
+}
+
+template <typename R> void launch_predictor(const Launch &L) {
+  hipLaunchKernelGGL(k_predictor<R>, GRID(L), L.slots, L.btab);
+  hipLaunchKernelGGL(k_phiH<R>, GRID(L), L.slots, L.btab);
+}
+
+template <typename R> void launch_pressure_setup(const Launch &L, bool normres) {
+  hipLaunchKernelGGL(k_pressure_setup<R>, GRID(L), L.slots, L.btab);
+  hipLaunchKernelGGL(k_zero_rhs_p, GRID(L), L.slots, L.btab);
+  if (normres) hipLaunchKernelGGL(k_normres<R>, GRID(L), L.slots, L.btab);
+}
+
+template <typename R> void launch_pcg_iters(const Launch &L, int n) {
+  for (int x = 0; x < n; ++x) {
+    hipLaunchKernelGGL(k_pcg1<R>, GRID(L), L.slots, L.btab);
+    hipLaunchKernelGGL(k_pcg2<R>, GRID(L), L.slots, L.btab);
+  }
+}
+
+template <typename R> void launch_refine(const Launch &L) {
+  hipLaunchKernelGGL(k_refine_x<R>, GRID(L), L.slots, L.btab);
+  hipLaunchKernelGGL(k_refine_res<R>, GRID(L), L.slots, L.btab);
+}
+
+template <typename R> void launch_correct(const Launch &L, int last) {
+  hipLaunchKernelGGL(k_correct<R>, GRID(L), L.slots, L.btab, last);
+}
+
+template <typename R> void launch_finalize(const Launch &L) {
+  hipLaunchKernelGGL(k_finalize<R>, GRID(L), L.slots, L.btab);
+}
+
+template <typename R> void launch_zero_usum(const Launch &L) {
+  hipLaunchKernelGGL(k_zero_usum<R>, GRID(L), L.slots, L.btab);
+}
+
+void launch_ctl_update(const Launch &L, const CtlUpdate &u) {
+  hipLaunchKernelGGL(k_ctl_update, dim3(1), dim3(64), 0, L.stream, const_cast<Slot *>(L.slots), u);
+}
+
+void launch_state_reset(const Launch &L, int nslots, int relax) {
+  hipLaunchKernelGGL(k_state_reset, dim3((nslots + 63) / 64), dim3(64), 0, L.stream, L.slots, nslots, relax);
+}
+
+#define INST(R)                                                   \
+  template void launch_copy_phi_prev<R>(const Launch &);          \
+  template void launch_normals<R>(const Launch &, bool);          \
+  template void launch_advect<R>(const Launch &);                 \
+  template void launch_assemble<R>(const Launch &);               \
+  template void launch_predictor<R>(const Launch &);              \
+  template void launch_pressure_setup<R>(const Launch &, bool);   \
+  template void launch_pcg_iters<R>(const Launch &, int);         \
+  template void launch_refine<R>(const Launch &);                 \
+  template void launch_correct<R>(const Launch &, int);           \
+  template void launch_finalize<R>(const Launch &);               \
+  template void launch_zero_usum<R>(const Launch &);
+
+INST(double)
+INST(float)
+
+}  // namespace oscar

@@ -1,0 +1,92 @@
+// Internal declarations of the OSCAR HIP library (gfx950).
+//
+// One "slot" is one OSCAR instance (one grid, its fields and its solver
+// state).  Every kernel takes the device array of slots of a batch plus a
+// block table that maps each workgroup to (slot, block within the slot), so a
+// single launch advances every slot of a batch; a single instance is a batch
+// of one.  All per-slot reductions go through per-block partials and a
+// last-block finaliser with a fixed combination order, so a slot's results do
+// not depend on which other slots share the launch.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace oscar {
+
+enum : int { F_NONE = 0, F_INT = 1, F_WALL = 2, F_INLET = 3, F_OUTLET = 4 };
+
+constexpr int BLOCK = 256;   // threads per workgroup, one cell per thread
+constexpr int NRED = 4;      // doubles per block partial
+
+// Per-slot scalars written by the last-block finalisers and read by later
+// kernels (uniform loads).  Only device code writes it; the host reads it back.
+struct SlotState {
+  double bn, rn, rz, dq, cg_alpha, beta;  // conjugate gradient
+  double pbar, E;                          // normalised residual
+  double comax, mass0, mass1, bflux;       // transport
+  double rn64, bn64;                       // refinement (mixed precision)
+  double mass_defect;
+  int32_t it, done, zero_rhs, total_it;
+  int32_t nonfinite, unstable, maxit_hit, refine_steps;
+  int32_t relax_done, k, pad0, pad1;
+};
+
+// Per-slot step parameters, written by a small kernel from host values.
+struct SlotCtl {
+  double dt, ub, rtol, rtol_inner;
+  int32_t active, mode, with_st, max_it;
+  int32_t last_corr, first_corr, n_sub, pad;
+  double tol;
+};
+
+struct Slot {
+  int32_t dim, nx, ny, nz;
+  int64_t nc, nf0, nf1, nf2, nftot;
+  int32_t block0, nblocks, n_fluid, precision;
+  int32_t bcf[6];               // face type of each box side
+  double h, V, S, Sh, S2h, hh, delta, cos_t, sin_t;
+  double rho1, mu1, rho2, mu2, sigma, u_inlet;
+  const uint8_t *flags;         // bit f: face f interior; bit 6: solid
+  // fields (element type R = double in FP64 mode, float in mixed mode)
+  void *alpha, *alpha_old, *U_vd, *U_cr, *U_sum, *U, *phi_vd, *phi_prev, *phi_cr;
+  double *p_vd, *p_cr, *p;
+  void *kappa, *nhatf, *grad, *gradU, *Fm, *aP, *rAU, *b, *HbyA, *phiH, *FL, *Af, *Rp, *Rm;
+  double *rhs, *Mp, *r64;
+  // conjugate-gradient vectors (element type T = R)
+  void *invD, *r, *z, *d0, *d1, *q, *e;
+  double *partials;             // NRED per block
+  uint32_t *ticket;
+  SlotState *st;
+  SlotCtl *ctl;
+};
+
+struct CtlUpdate {
+  static constexpr int MAXN = 32;
+  int32_t n;
+  int32_t slot[MAXN];
+  SlotCtl ctl[MAXN];
+};
+
+// host launchers (kernels.hip); all enqueue on `stream`
+struct Launch {
+  const Slot *slots;       // device
+  const int2 *btab;        // device block table
+  int nblocks;             // total blocks
+  hipStream_t stream;
+};
+
+template <typename R> void launch_copy_phi_prev(const Launch &L);
+template <typename R> void launch_normals(const Launch &L, bool curvature);
+template <typename R> void launch_advect(const Launch &L);
+template <typename R> void launch_assemble(const Launch &L);
+template <typename R> void launch_predictor(const Launch &L);
+template <typename R> void launch_pressure_setup(const Launch &L, bool normres);
+template <typename R> void launch_pcg_iters(const Launch &L, int n);
+template <typename R> void launch_refine(const Launch &L);
+template <typename R> void launch_correct(const Launch &L, int last);
+template <typename R> void launch_finalize(const Launch &L);
+template <typename R> void launch_zero_usum(const Launch &L);
+void launch_ctl_update(const Launch &L, const CtlUpdate &u);
+void launch_state_reset(const Launch &L, int nslots, int relax);
+
+}  // namespace oscar
