@@ -171,6 +171,16 @@ void oscar_destroy(oscar_ctx *ctx);
  * oscar_create / engine failure when ctx is NULL.  Never NULL. */
 const char *oscar_last_error(const oscar_ctx *ctx);
 
+/* Measurement hook (not part of the method): when enabled, every launch of
+ * the two conjugate-gradient kernels is bracketed by HIP events on the
+ * context's stream.  oscar_timing(ctx, 1) resets and starts the totals,
+ * oscar_timing(ctx, 0) stops.  oscar_timing_read returns the summed
+ * kernel time [ms] and the launch count of kernel 0 (pass 1: search
+ * direction, q = M d, <d,q>) or kernel 1 (pass 2: x, r, z updates, <r,r>,
+ * <r,z>); it synchronises the stream. */
+int32_t oscar_timing(oscar_ctx *ctx, int32_t enable);
+int32_t oscar_timing_read(oscar_ctx *ctx, int32_t kernel, double *total_ms, int64_t *launches);
+
 /* Brackbill capillary time-step limit sqrt(rho_bar h^3 / (2 pi sigma)),
  * rho_bar = (rho1 + rho2)/2 (Section 2.2). */
 double oscar_dt_brackbill(double rho1, double rho2, double h, double sigma);

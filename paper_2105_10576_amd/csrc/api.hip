@@ -14,6 +14,7 @@
 
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -42,7 +43,7 @@ Dims dims_of(const oscar_desc &D) {
   g.nf1 = (int64_t)D.nx * (D.ny + 1) * D.nz;
   g.nf2 = D.dim == 3 ? (int64_t)D.nx * D.ny * (D.nz + 1) : 0;
   g.nft = g.nf0 + g.nf1 + g.nf2;
-  g.nblocks = (int)((g.nc + BLOCK - 1) / BLOCK);
+  g.nblocks = blocks_for(g.nc);
   return g;
 }
 
@@ -74,8 +75,7 @@ void layout(const oscar_desc &D, Carver &cv, Slot *s, bool ctl_block) {
   double **dbl[] = {&s->p_vd, &s->p_cr, &s->p, &s->rhs, &s->Mp};
   for (double **p : dbl) *p = (double *)cv.take(8 * nc);
   s->r64 = nullptr;
-  s->partials = (double *)cv.take(8ull * NRED * g.nblocks);
-  s->ticket = (uint32_t *)cv.take(4);
+  s->part = (double *)cv.take(8ull * NCH * NVAL * g.nblocks);
   s->st = (SlotState *)cv.take(sizeof(SlotState));
   s->ctl = (SlotCtl *)cv.take(sizeof(SlotCtl));
   (void)ctl_block;
@@ -185,13 +185,21 @@ struct oscar_ctx {
   int k_f = 0;
   double last_E = 0.0, last_res = 0.0;
   int last_pcg = 0, pcg_call = 0, refine_call = 0, maxit_hits = 0;
-  int pcg_pred = 32;
+  int pcg_pred = 32;        // predicted CG iterations of the next solve (FP64)
+  int pcg_pred_inner = 16;  // same for an FP32 inner solve (mixed)
+  // optional per-kernel timing of the two conjugate-gradient passes
+  bool timing = false;
+  std::vector<hipEvent_t> ev;
+  size_t ev_used = 0;
+  double t_ms[2] = {0.0, 0.0};
+  int64_t t_cnt[2] = {0, 0};
 
   Launch L() const {
     Launch l;
     l.slots = d_slot;
     l.btab = d_btab;
     l.nblocks = g.nblocks;
+    l.nslots = 1;
     l.stream = stream;
     return l;
   }
@@ -223,10 +231,60 @@ static int set_ctl(oscar_ctx *c, const SlotCtl &ctl) {
   return OSCAR_OK;
 }
 
+// fold the completed event pairs (start, end of one CG pass) into the totals
+static int harvest_timing(oscar_ctx *c) {
+  for (size_t x = 0; x + 1 < c->ev_used; x += 2) {
+    float ms = 0.f;
+    HIPCHK(c, hipEventElapsedTime(&ms, c->ev[x], c->ev[x + 1]));
+    int pass = (int)((x / 2) & 1);
+    c->t_ms[pass] += ms;
+    c->t_cnt[pass] += 1;
+  }
+  c->ev_used = 0;
+  return OSCAR_OK;
+}
+
 static int read_state(oscar_ctx *c) {
   HIPCHK(c, hipMemcpyAsync(c->h_state, c->s.st, sizeof(SlotState), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (c->timing && c->ev_used) return harvest_timing(c);
   return OSCAR_OK;
+}
+
+// conjugate-gradient iterations it0 .. it0+n-1; with timing on, each pass is
+// bracketed by events
+template <typename R>
+static int enqueue_pcg(oscar_ctx *c, int it0, int n) {
+  Launch L = c->L();
+  if (!c->timing) {
+    launch_pcg_iters<R>(L, it0, n);
+    HIPCHK(c, hipGetLastError());
+    return OSCAR_OK;
+  }
+  size_t need = c->ev_used + 4 * (size_t)n;
+  while (c->ev.size() < need) {
+    hipEvent_t e;
+    HIPCHK(c, hipEventCreate(&e));
+    c->ev.push_back(e);
+  }
+  for (int x = 0; x < n; ++x)
+    for (int pass = 0; pass < 2; ++pass) {
+      HIPCHK(c, hipEventRecord(c->ev[c->ev_used++], c->stream));
+      launch_pcg_pass<R>(L, it0 + x, pass);
+      HIPCHK(c, hipGetLastError());
+      HIPCHK(c, hipEventRecord(c->ev[c->ev_used++], c->stream));
+    }
+  return OSCAR_OK;
+}
+
+int oscar::blocks_for(int64_t nc) {
+  static int cap = [] {
+    const char *e = getenv("OSCAR_MAX_BLOCKS");
+    int v = e ? atoi(e) : 1024;
+    return v >= 1 ? v : 1024;
+  }();
+  int64_t n = (nc + BLOCK - 1) / BLOCK;
+  return (int)(n < cap ? n : cap);
 }
 
 extern "C" double oscar_dt_brackbill(double rho1, double rho2, double h, double sigma) {
@@ -360,6 +418,7 @@ extern "C" int32_t oscar_create(const oscar_desc *desc, void *ws, uint64_t bytes
 extern "C" void oscar_destroy(oscar_ctx *c) {
   if (!c) return;
   if (c->stream) (void)hipStreamSynchronize(c->stream);
+  for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
   if (c->h_state) (void)hipHostFree(c->h_state);
   delete c;
 }
@@ -375,33 +434,36 @@ extern "C" const char *oscar_last_error(const oscar_ctx *c) { return c ? c->err.
 // precision, FP32 inner solves wrapped in FP64 refinement.
 template <typename R>
 static int solve_pressure(oscar_ctx *c, int &iters) {
-  Launch L = c->L();
   int rc = read_state(c);
   if (rc) return rc;
   int start_total = c->h_state->total_it;
   const int max_it = c->D.pcg_max_it;
-  auto inner = [&]() -> int {
-    int chunk = c->pcg_pred > 4 ? c->pcg_pred : 4;
-    int guard = 0;
+  // one CG solve: chunks of iterations from index 0 until the device flags it done
+  auto inner = [&](int &pred) -> int {
+    int it0 = 0;
+    int chunk = pred > 2 ? pred : 2;
     while (!c->h_state->done) {
-      launch_pcg_iters<R>(L, chunk);
-      HIPCHK(c, hipGetLastError());
-      int r = read_state(c);
+      if (it0 > max_it + 1) { c->err = "conjugate gradient did not terminate"; return OSCAR_E_HIP; }
+      int r = enqueue_pcg<R>(c, it0, chunk);
       if (r) return r;
-      chunk = chunk < 64 ? 64 : chunk;
-      if (++guard > 4 + max_it / 4) { c->err = "conjugate gradient did not terminate"; return OSCAR_E_HIP; }
+      it0 += chunk;
+      r = read_state(c);
+      if (r) return r;
+      chunk = 16;
     }
+    int used = c->h_state->it;
+    pred = used + 2 < 2048 ? used + 2 : 2048;
     return OSCAR_OK;
   };
   if (!c->mixed()) {
-    rc = inner();
+    rc = inner(c->pcg_pred);
     if (rc) return rc;
   } else {
     int outer = 0;
     while (!c->h_state->done) {
-      rc = inner();
+      rc = inner(c->pcg_pred_inner);
       if (rc) return rc;
-      launch_refine<R>(L);
+      launch_refine<R>(c->L());
       HIPCHK(c, hipGetLastError());
       rc = read_state(c);
       if (rc) return rc;
@@ -410,9 +472,6 @@ static int solve_pressure(oscar_ctx *c, int &iters) {
     c->refine_call += outer;
   }
   iters = c->h_state->total_it - start_total;
-  // predicted chunk for the next solve: this solve's count rounded up
-  int pred = iters + 4;
-  c->pcg_pred = pred > 512 ? 512 : pred;
   return OSCAR_OK;
 }
 
@@ -467,7 +526,7 @@ static int viscous_step_t(oscar_ctx *c, double dt) {
   Launch L = c->L();
   int rc = set_ctl(c, make_ctl(c, 0, dt, 1));
   if (rc) return rc;
-  launch_state_reset(L, 1, 0);
+  launch_state_reset(L, 1);
   c->pcg_call = 0;
   c->refine_call = 0;
   launch_copy_phi_prev<R>(L);
@@ -488,7 +547,7 @@ static int relax_t(oscar_ctx *c, double dt_vd, int n_sub, int max_iters, double 
   double dt = dt_vd / (double)n_sub;
   int rc = set_ctl(c, make_ctl(c, 1, dt, n_sub));
   if (rc) return rc;
-  launch_state_reset(L, 1, 1);
+  launch_state_reset(L, 1);
   launch_zero_usum<R>(L);
   HIPCHK(c, hipGetLastError());
   c->pcg_call = 0;
@@ -559,9 +618,9 @@ static int pressure_solve_t(oscar_ctx *c, int which, double dt, double rtol, int
   k.max_it = max_it;
   int rc = set_ctl(c, k);
   if (rc) return rc;
-  launch_state_reset(L, 1, 0);
+  launch_state_reset(L, 1);
   // alpha_old = alpha (no transport), then curvature, momentum, predictor, solve
-  int saved_pred = c->pcg_pred;
+  int saved_pred = c->pcg_pred, saved_inner = c->pcg_pred_inner;
   int saved_max = c->D.pcg_max_it;
   c->D.pcg_max_it = max_it;
   if (which == 0) launch_copy_phi_prev<R>(L);
@@ -576,6 +635,7 @@ static int pressure_solve_t(oscar_ctx *c, int which, double dt, double rtol, int
   rc = solve_pressure<R>(c, it);
   c->D.pcg_max_it = saved_max;
   c->pcg_pred = saved_pred;
+  c->pcg_pred_inner = saved_inner;
   if (rc) return rc;
   int warn = c->h_state->maxit_hit ? OSCAR_W_PCG_MAXIT : OSCAR_OK;
   if (iters) *iters = it;
@@ -704,5 +764,32 @@ extern "C" int32_t oscar_stats(oscar_ctx *c, oscar_stats_t *o) {
   o->k_f = c->k_f;
   o->n_fluid = (int32_t)c->n_fluid;
   o->pcg_maxit_hits = c->maxit_hits;
+  return OSCAR_OK;
+}
+
+extern "C" int32_t oscar_timing(oscar_ctx *c, int32_t enable) {
+  if (!c) return OSCAR_E_ARG;
+  if (c->timing && c->ev_used) {
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    int rc = harvest_timing(c);
+    if (rc) return rc;
+  }
+  c->timing = enable != 0;
+  if (c->timing) {
+    c->t_ms[0] = c->t_ms[1] = 0.0;
+    c->t_cnt[0] = c->t_cnt[1] = 0;
+  }
+  return OSCAR_OK;
+}
+
+extern "C" int32_t oscar_timing_read(oscar_ctx *c, int32_t kernel, double *total_ms, int64_t *launches) {
+  if (!c || kernel < 0 || kernel > 1) return OSCAR_E_ARG;
+  if (c->ev_used) {
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    int rc = harvest_timing(c);
+    if (rc) return rc;
+  }
+  if (total_ms) *total_ms = c->t_ms[kernel];
+  if (launches) *launches = c->t_cnt[kernel];
   return OSCAR_OK;
 }

@@ -50,19 +50,22 @@ __device__ __forceinline__ Block block_of(const Slot *slots, const int2 *btab) {
   return b;
 }
 
-__device__ __forceinline__ Cell cell_of(const Slot &s, int lb) {
+__device__ __forceinline__ Cell cell_at(const Slot &s, int64_t g) {
   Cell c;
-  int64_t g = (int64_t)lb * BLOCK + threadIdx.x;
-  c.valid = g < s.nc;
+  c.valid = true;
   c.P = g;
-  c.i = c.j = c.k = 0;
-  if (c.valid) {
-    c.i = (int)(g % s.nx);
-    int64_t t = g / s.nx;
-    c.j = (int)(t % s.ny);
-    c.k = (int)(t / s.ny);
-  }
+  c.i = (int)(g % s.nx);
+  int64_t t = g / s.nx;
+  c.j = (int)(t % s.ny);
+  c.k = (int)(t / s.ny);
   return c;
+}
+
+// grid-stride loop over the cells of the slot handled by block lb
+template <class Fn>
+__device__ __forceinline__ void for_cells(const Slot &s, int lb, Fn &&fn) {
+  const int64_t stride = (int64_t)s.nblocks * BLOCK;
+  for (int64_t g = (int64_t)lb * BLOCK + threadIdx.x; g < s.nc; g += stride) fn(cell_at(s, g));
 }
 
 __device__ __forceinline__ int64_t cidx(const Slot &s, int i, int j, int k) {
@@ -156,57 +159,48 @@ __device__ __forceinline__ void wave_reduce(double (&v)[M]) {
   }
 }
 
-// Reduce v over the block, publish the block partial, and return true in the
-// block that arrives last for its slot; there thread 0 holds the slot totals.
+// Block-level reduction of v (fixed order); every thread receives the totals.
 template <unsigned MAXMASK, int M>
-__device__ bool reduce_last(const Slot &s, int lb, double (&v)[M]) {
+__device__ __forceinline__ void block_reduce(double (&v)[M]) {
   __shared__ double sh[M][BLOCK / 64];
-  __shared__ int amlast;
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   wave_reduce<MAXMASK>(v);
+  __syncthreads();
   if (lane == 0)
 #pragma unroll
     for (int m = 0; m < M; ++m) sh[m][w] = v[m];
   __syncthreads();
-  if (tid == 0) {
-#pragma unroll
-    for (int m = 0; m < M; ++m) {
-      double t = sh[m][0];
-      for (int x = 1; x < BLOCK / 64; ++x) t = ((MAXMASK >> m) & 1u) ? (sh[m][x] > t ? sh[m][x] : t) : t + sh[m][x];
-      s.partials[(int64_t)lb * NRED + m] = t;
-    }
-    __threadfence();
-    unsigned tk = atomicAdd(s.ticket, 1u);
-    amlast = (tk == (unsigned)(s.nblocks - 1));
-  }
-  __syncthreads();
-  if (!amlast) return false;
-  __threadfence();
 #pragma unroll
   for (int m = 0; m < M; ++m) {
+    double t = sh[m][0];
+    for (int x = 1; x < BLOCK / 64; ++x) t = ((MAXMASK >> m) & 1u) ? (sh[m][x] > t ? sh[m][x] : t) : t + sh[m][x];
+    v[m] = t;
+  }
+}
+
+// publish this block's partials of channel ch
+template <unsigned MAXMASK, int M>
+__device__ __forceinline__ void put_partials(const Slot &s, int lb, int ch, double (&v)[M]) {
+  block_reduce<MAXMASK>(v);
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int m = 0; m < M; ++m) s.part[(int64_t)(ch * NVAL + m) * s.nblocks + lb] = v[m];
+}
+
+// totals of channel ch over the slot's blocks, in every thread (fixed order)
+template <unsigned MAXMASK, int M>
+__device__ __forceinline__ void get_totals(const Slot &s, int ch, double (&v)[M]) {
+#pragma unroll
+  for (int m = 0; m < M; ++m) {
+    const double *p = s.part + (int64_t)(ch * NVAL + m) * s.nblocks;
     double t = 0.0;
-    for (int b = tid; b < s.nblocks; b += BLOCK) {
-      double x = s.partials[(int64_t)b * NRED + m];
+    for (int b = threadIdx.x; b < s.nblocks; b += BLOCK) {
+      double x = p[b];
       t = ((MAXMASK >> m) & 1u) ? (x > t ? x : t) : t + x;
     }
     v[m] = t;
   }
-  wave_reduce<MAXMASK>(v);
-  __syncthreads();
-  if (lane == 0)
-#pragma unroll
-    for (int m = 0; m < M; ++m) sh[m][w] = v[m];
-  __syncthreads();
-  if (tid == 0) {
-#pragma unroll
-    for (int m = 0; m < M; ++m) {
-      double t = sh[m][0];
-      for (int x = 1; x < BLOCK / 64; ++x) t = ((MAXMASK >> m) & 1u) ? (sh[m][x] > t ? sh[m][x] : t) : t + sh[m][x];
-      v[m] = t;
-    }
-    *s.ticket = 0u;
-  }
-  return true;
+  block_reduce<MAXMASK>(v);
 }
 
 // ---------------------------------------------------------------------------
@@ -238,7 +232,7 @@ __global__ void k_ctl_update(Slot *slots, CtlUpdate u) {
   if (t < u.n) *slots[u.slot[t]].ctl = u.ctl[t];
 }
 
-__global__ void k_state_reset(const Slot *slots, int nslots, int relax) {
+__global__ void k_state_reset(const Slot *slots, int nslots) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= nslots) return;
   const Slot &s = slots[t];
@@ -249,10 +243,6 @@ __global__ void k_state_reset(const Slot *slots, int nslots, int relax) {
   st->maxit_hit = 0;
   st->total_it = 0;
   st->refine_steps = 0;
-  if (relax) {
-    st->relax_done = 0;
-    st->k = 0;
-  }
 }
 
 // ---------------------------------------------------------------------------
@@ -265,11 +255,11 @@ __global__ void __launch_bounds__(BLOCK) k_copy_phi_prev(const Slot *slots, cons
   Block B = block_of(slots, btab);
   const Slot &s = *B.s;
   if (!B.ctl->active || B.ctl->mode != 0) return;
-  Cell c = cell_of(s, B.lb);
-  if (!c.valid) return;
   const R *src = (const R *)s.phi_vd;
   R *dst = (R *)s.phi_prev;
-  for_owned_faces(s, c, [&](int, int64_t fi, const FView &) { dst[fi] = src[fi]; });
+  for_cells(s, B.lb, [&](const Cell &c) {
+    for_owned_faces(s, c, [&](int, int64_t fi, const FView &) { dst[fi] = src[fi]; });
+  });
 }
 
 // ---------------------------------------------------------------------------
@@ -281,21 +271,21 @@ __global__ void __launch_bounds__(BLOCK) k_grad_alpha(const Slot *slots, const i
   Block B = block_of(slots, btab);
   const Slot &s = *B.s;
   if (!B.ctl->active || (only_cr && B.ctl->mode != 1)) return;
-  Cell c = cell_of(s, B.lb);
-  if (!c.valid) return;
   const R *a = (const R *)s.alpha;
   R *g = (R *)s.grad;
-  uint8_t fl = s.flags[c.P];
-  for (int e = 0; e < s.dim; ++e) {
-    R ge = (R)0;
-    if (!(fl & 0x40)) {
-      CFace lo = cell_face(s, fl, c.i, c.j, c.k, 2 * e), hi = cell_face(s, fl, c.i, c.j, c.k, 2 * e + 1);
-      R alo = lo.type == F_INT ? (R)0.5 * (a[c.P] + a[lo.nb]) : a[c.P];
-      R ahi = hi.type == F_INT ? (R)0.5 * (a[c.P] + a[hi.nb]) : a[c.P];
-      ge = (ahi - alo) / (R)s.h;
+  for_cells(s, B.lb, [&](const Cell &c) {
+    uint8_t fl = s.flags[c.P];
+    for (int e = 0; e < s.dim; ++e) {
+      R ge = (R)0;
+      if (!(fl & 0x40)) {
+        CFace lo = cell_face(s, fl, c.i, c.j, c.k, 2 * e), hi = cell_face(s, fl, c.i, c.j, c.k, 2 * e + 1);
+        R alo = lo.type == F_INT ? (R)0.5 * (a[c.P] + a[lo.nb]) : a[c.P];
+        R ahi = hi.type == F_INT ? (R)0.5 * (a[c.P] + a[hi.nb]) : a[c.P];
+        ge = (ahi - alo) / (R)s.h;
+      }
+      g[e * s.nc + c.P] = ge;
     }
-    g[e * s.nc + c.P] = ge;
-  }
+  });
 }
 
 template <typename R>
@@ -303,41 +293,41 @@ __global__ void __launch_bounds__(BLOCK) k_face_normals(const Slot *slots, const
   Block B = block_of(slots, btab);
   const Slot &s = *B.s;
   if (!B.ctl->active || (only_cr && B.ctl->mode != 1)) return;
-  Cell c = cell_of(s, B.lb);
-  if (!c.valid) return;
   const R *g = (const R *)s.grad;
   R *nh = (R *)s.nhatf;
   const int d = s.dim;
   const R delta = (R)s.delta;
-  for_owned_faces(s, c, [&](int e, int64_t fi, const FView &v) {
-    R G[3] = {(R)0, (R)0, (R)0};
-    R out = (R)0;
-    if (v.type == F_INT) {
-      for (int cc = 0; cc < d; ++cc) G[cc] = (R)0.5 * (g[cc * s.nc + v.lo] + g[cc * s.nc + v.hi]);
-      out = G[e] / (vnorm(G, d) + delta);
-    } else if (v.type == F_INLET || v.type == F_OUTLET) {
-      for (int cc = 0; cc < d; ++cc) G[cc] = g[cc * s.nc + v.P];
-      out = G[e] / (vnorm(G, d) + delta);
-    } else if (v.type == F_WALL) {
-      for (int cc = 0; cc < d; ++cc) G[cc] = g[cc * s.nc + v.P];
-      R mg = vnorm(G, d);
-      if (mg <= delta) {
-        out = (R)0;
-      } else {
-        // Brackbill wall adhesion: n = cos(theta) n_w + sin(theta) t/|t|,
-        // n_w the unit normal from the fluid into the wall
-        R nw[3] = {(R)0, (R)0, (R)0}, m[3] = {(R)0, (R)0, (R)0}, t[3] = {(R)0, (R)0, (R)0};
-        nw[e] = (R)v.sf;
-        for (int cc = 0; cc < d; ++cc) m[cc] = G[cc] / (mg + delta);
-        R mn = (R)0;
-        for (int cc = 0; cc < d; ++cc) mn = mn + m[cc] * nw[cc];
-        for (int cc = 0; cc < d; ++cc) t[cc] = m[cc] - mn * nw[cc];
-        R tm = vnorm(t, d);
-        if (tm <= (R)1e-12) out = m[e];
-        else out = (R)s.cos_t * nw[e] + (R)s.sin_t * t[e] / tm;
+  for_cells(s, B.lb, [&](const Cell &c) {
+    for_owned_faces(s, c, [&](int e, int64_t fi, const FView &v) {
+      R G[3] = {(R)0, (R)0, (R)0};
+      R out = (R)0;
+      if (v.type == F_INT) {
+        for (int cc = 0; cc < d; ++cc) G[cc] = (R)0.5 * (g[cc * s.nc + v.lo] + g[cc * s.nc + v.hi]);
+        out = G[e] / (vnorm(G, d) + delta);
+      } else if (v.type == F_INLET || v.type == F_OUTLET) {
+        for (int cc = 0; cc < d; ++cc) G[cc] = g[cc * s.nc + v.P];
+        out = G[e] / (vnorm(G, d) + delta);
+      } else if (v.type == F_WALL) {
+        for (int cc = 0; cc < d; ++cc) G[cc] = g[cc * s.nc + v.P];
+        R mg = vnorm(G, d);
+        if (mg <= delta) {
+          out = (R)0;
+        } else {
+          // Brackbill wall adhesion: n = cos(theta) n_w + sin(theta) t/|t|,
+          // n_w the unit normal from the fluid into the wall
+          R nw[3] = {(R)0, (R)0, (R)0}, m[3] = {(R)0, (R)0, (R)0}, t[3] = {(R)0, (R)0, (R)0};
+          nw[e] = (R)v.sf;
+          for (int cc = 0; cc < d; ++cc) m[cc] = G[cc] / (mg + delta);
+          R mn = (R)0;
+          for (int cc = 0; cc < d; ++cc) mn = mn + m[cc] * nw[cc];
+          for (int cc = 0; cc < d; ++cc) t[cc] = m[cc] - mn * nw[cc];
+          R tm = vnorm(t, d);
+          if (tm <= (R)1e-12) out = m[e];
+          else out = (R)s.cos_t * nw[e] + (R)s.sin_t * t[e] / tm;
+        }
       }
-    }
-    nh[fi] = out;
+      nh[fi] = out;
+    });
   });
 }
 
@@ -346,21 +336,21 @@ __global__ void __launch_bounds__(BLOCK) k_curvature(const Slot *slots, const in
   Block B = block_of(slots, btab);
   const Slot &s = *B.s;
   if (!B.ctl->active || B.ctl->mode != 1) return;
-  Cell c = cell_of(s, B.lb);
-  if (!c.valid) return;
   const R *nh = (const R *)s.nhatf;
   R *kap = (R *)s.kappa;
-  uint8_t fl = s.flags[c.P];
-  R out = (R)0;
-  if (!(fl & 0x40)) {
-    R acc = (R)0;
-    for (int e = 0; e < s.dim; ++e) {
-      CFace lo = cell_face(s, fl, c.i, c.j, c.k, 2 * e), hi = cell_face(s, fl, c.i, c.j, c.k, 2 * e + 1);
-      acc = acc + (nh[hi.fi] - nh[lo.fi]);
+  for_cells(s, B.lb, [&](const Cell &c) {
+    uint8_t fl = s.flags[c.P];
+    R out = (R)0;
+    if (!(fl & 0x40)) {
+      R acc = (R)0;
+      for (int e = 0; e < s.dim; ++e) {
+        CFace lo = cell_face(s, fl, c.i, c.j, c.k, 2 * e), hi = cell_face(s, fl, c.i, c.j, c.k, 2 * e + 1);
+        acc = acc + (nh[hi.fi] - nh[lo.fi]);
+      }
+      out = -acc / (R)s.h;
     }
-    out = -acc / (R)s.h;
-  }
-  kap[c.P] = out;
+    kap[c.P] = out;
+  });
 }
 
 // surface-tension face term sigma*kappa_f*(alpha_hi - alpha_lo)/h
@@ -379,15 +369,14 @@ __global__ void __launch_bounds__(BLOCK) k_mules_flux(const Slot *slots, const i
   const Slot &s = *B.s;
   const SlotCtl &ctl = *B.ctl;
   if (!ctl.active) return;
-  Cell c = cell_of(s, B.lb);
   const R *a = (const R *)s.alpha;
   const R *phi = (const R *)(ctl.mode ? s.phi_cr : s.phi_prev);
   const R *nh = (const R *)s.nhatf;
+  R *FL = (R *)s.FL, *Af = (R *)s.Af, *aold = (R *)s.alpha_old;
   double red[2] = {0.0, 0.0};   // max Courant, sum alpha
-  if (c.valid) {
+  for_cells(s, B.lb, [&](const Cell &c) {
     uint8_t fl = s.flags[c.P];
-    ((R *)s.alpha_old)[c.P] = a[c.P];
-    R *FL = (R *)s.FL, *Af = (R *)s.Af;
+    aold[c.P] = a[c.P];
     for_owned_faces(s, c, [&](int e, int64_t fi, const FView &v) {
       R fl_ = (R)0, af = (R)0, ph = phi[fi];
       if (v.type == F_INT) {
@@ -426,15 +415,12 @@ __global__ void __launch_bounds__(BLOCK) k_mules_flux(const Slot *slots, const i
         R sp = ((f & 1) ? (R)1 : (R)-1) * phi[cf.fi];
         if (sp > (R)0) acc = acc + sp;
       }
-      red[0] = (double)(acc * ((R)ctl.dt / (R)s.V));
-      red[1] = (double)a[c.P];
+      double co = (double)(acc * ((R)ctl.dt / (R)s.V));
+      red[0] = co > red[0] ? co : red[0];
+      red[1] = red[1] + (double)a[c.P];
     }
-  }
-  if (reduce_last<1u>(s, B.lb, red) && threadIdx.x == 0) {
-    B.st->comax = red[0];
-    B.st->mass0 = red[1] * s.V;
-    if (red[0] > 1.0) B.st->unstable = 1;
-  }
+  });
+  put_partials<1u>(s, B.lb, CH_ADV1, red);
 }
 
 template <typename R>
@@ -443,40 +429,40 @@ __global__ void __launch_bounds__(BLOCK) k_mules_limiter(const Slot *slots, cons
   const Slot &s = *B.s;
   const SlotCtl &ctl = *B.ctl;
   if (!ctl.active) return;
-  Cell c = cell_of(s, B.lb);
-  if (!c.valid) return;
   const R *a = (const R *)s.alpha;
   const R *FL = (const R *)s.FL, *Af = (const R *)s.Af;
   R *Rp = (R *)s.Rp, *Rm = (R *)s.Rm;
-  uint8_t fl = s.flags[c.P];
-  R rp = (R)0, rm = (R)0;
-  if (!(fl & 0x40)) {
-    const R dtV = (R)ctl.dt / (R)s.V, Vdt = (R)s.V / (R)ctl.dt;
-    R sumL = (R)0, Pp = (R)0, Pm = (R)0, amax = a[c.P], amin = a[c.P];
-    for (int f = 0; f < 2 * s.dim; ++f) {
-      CFace cf = cell_face(s, fl, c.i, c.j, c.k, f);
-      if (cf.type == F_NONE) continue;
-      R sg = (f & 1) ? (R)1 : (R)-1;
-      sumL = sumL + sg * FL[cf.fi];
-      R sA = sg * Af[cf.fi];
-      Pp = Pp + (sA < (R)0 ? -sA : (R)0);
-      Pm = Pm + (sA > (R)0 ? sA : (R)0);
-      if (cf.type == F_INT) {
-        R an = a[cf.nb];
-        if (an > amax) amax = an;
-        if (an < amin) amin = an;
+  const R dtV = (R)ctl.dt / (R)s.V, Vdt = (R)s.V / (R)ctl.dt;
+  for_cells(s, B.lb, [&](const Cell &c) {
+    uint8_t fl = s.flags[c.P];
+    R rp = (R)0, rm = (R)0;
+    if (!(fl & 0x40)) {
+      R sumL = (R)0, Pp = (R)0, Pm = (R)0, amax = a[c.P], amin = a[c.P];
+      for (int f = 0; f < 2 * s.dim; ++f) {
+        CFace cf = cell_face(s, fl, c.i, c.j, c.k, f);
+        if (cf.type == F_NONE) continue;
+        R sg = (f & 1) ? (R)1 : (R)-1;
+        sumL = sumL + sg * FL[cf.fi];
+        R sA = sg * Af[cf.fi];
+        Pp = Pp + (sA < (R)0 ? -sA : (R)0);
+        Pm = Pm + (sA > (R)0 ? sA : (R)0);
+        if (cf.type == F_INT) {
+          R an = a[cf.nb];
+          if (an > amax) amax = an;
+          if (an < amin) amin = an;
+        }
       }
+      R aL = a[c.P] - dtV * sumL;
+      if (amax > (R)1) amax = (R)1;
+      if (amin < (R)0) amin = (R)0;
+      R Qp = Vdt * (amax - aL > (R)0 ? amax - aL : (R)0);
+      R Qm = Vdt * (aL - amin > (R)0 ? aL - amin : (R)0);
+      rp = Pp > (R)0 ? (Qp / Pp < (R)1 ? Qp / Pp : (R)1) : (R)0;
+      rm = Pm > (R)0 ? (Qm / Pm < (R)1 ? Qm / Pm : (R)1) : (R)0;
     }
-    R aL = a[c.P] - dtV * sumL;
-    if (amax > (R)1) amax = (R)1;
-    if (amin < (R)0) amin = (R)0;
-    R Qp = Vdt * (amax - aL > (R)0 ? amax - aL : (R)0);
-    R Qm = Vdt * (aL - amin > (R)0 ? aL - amin : (R)0);
-    rp = Pp > (R)0 ? (Qp / Pp < (R)1 ? Qp / Pp : (R)1) : (R)0;
-    rm = Pm > (R)0 ? (Qm / Pm < (R)1 ? Qm / Pm : (R)1) : (R)0;
-  }
-  Rp[c.P] = rp;
-  Rm[c.P] = rm;
+    Rp[c.P] = rp;
+    Rm[c.P] = rm;
+  });
 }
 
 template <typename R>
@@ -485,42 +471,54 @@ __global__ void __launch_bounds__(BLOCK) k_mules_update(const Slot *slots, const
   const Slot &s = *B.s;
   const SlotCtl &ctl = *B.ctl;
   if (!ctl.active) return;
-  Cell c = cell_of(s, B.lb);
+  R *a = (R *)s.alpha;
+  const R *FL = (const R *)s.FL, *Af = (const R *)s.Af, *Rp = (const R *)s.Rp, *Rm = (const R *)s.Rm;
+  const R dtV = (R)ctl.dt / (R)s.V;
   double red[2] = {0.0, 0.0};   // sum alpha_new, boundary flux
-  if (c.valid) {
-    R *a = (R *)s.alpha;
-    const R *FL = (const R *)s.FL, *Af = (const R *)s.Af, *Rp = (const R *)s.Rp, *Rm = (const R *)s.Rm;
+  for_cells(s, B.lb, [&](const Cell &c) {
     uint8_t fl = s.flags[c.P];
-    if (!(fl & 0x40)) {
-      const R dtV = (R)ctl.dt / (R)s.V;
-      R acc = (R)0, bfl = (R)0;
-      for (int f = 0; f < 2 * s.dim; ++f) {
-        CFace cf = cell_face(s, fl, c.i, c.j, c.k, f);
-        if (cf.type == F_NONE) continue;
-        R sg = (f & 1) ? (R)1 : (R)-1;
-        R lam = (R)0;
-        if (cf.type == F_INT) {
-          int64_t lo = (f & 1) ? c.P : cf.nb, hi = (f & 1) ? cf.nb : c.P;
-          R A = Af[cf.fi];
-          R x1 = A >= (R)0 ? Rm[lo] : Rp[lo];
-          R x2 = A >= (R)0 ? Rp[hi] : Rm[hi];
-          lam = x1 < x2 ? x1 : x2;
-        } else {
-          bfl = bfl + sg * FL[cf.fi];
-        }
-        acc = acc + sg * (FL[cf.fi] + lam * Af[cf.fi]);
+    if (fl & 0x40) return;
+    R acc = (R)0, bfl = (R)0;
+    for (int f = 0; f < 2 * s.dim; ++f) {
+      CFace cf = cell_face(s, fl, c.i, c.j, c.k, f);
+      if (cf.type == F_NONE) continue;
+      R sg = (f & 1) ? (R)1 : (R)-1;
+      R lam = (R)0;
+      if (cf.type == F_INT) {
+        int64_t lo = (f & 1) ? c.P : cf.nb, hi = (f & 1) ? cf.nb : c.P;
+        R A = Af[cf.fi];
+        R x1 = A >= (R)0 ? Rm[lo] : Rp[lo];
+        R x2 = A >= (R)0 ? Rp[hi] : Rm[hi];
+        lam = x1 < x2 ? x1 : x2;
+      } else {
+        bfl = bfl + sg * FL[cf.fi];
       }
-      R an = a[c.P] - dtV * acc;
-      a[c.P] = an;
-      red[0] = (double)an;
-      red[1] = (double)bfl;
+      acc = acc + sg * (FL[cf.fi] + lam * Af[cf.fi]);
     }
-  }
-  if (reduce_last<0u>(s, B.lb, red) && threadIdx.x == 0) {
-    SlotState *st = B.st;
-    st->mass1 = red[0] * s.V;
-    st->bflux = red[1];
-    double defect = fabs(st->mass1 - st->mass0 + ctl.dt * red[1]);
+    R an = a[c.P] - dtV * acc;
+    a[c.P] = an;
+    red[0] = red[0] + (double)an;
+    red[1] = red[1] + (double)bfl;
+  });
+  put_partials<0u>(s, B.lb, CH_ADV2, red);
+}
+
+// one block per slot: Courant number, phase mass before/after, boundary flux
+__global__ void __launch_bounds__(BLOCK) k_transport_fin(const Slot *slots) {
+  const Slot &s = slots[blockIdx.x];
+  const SlotCtl &ctl = *s.ctl;
+  if (!ctl.active) return;
+  double v1[2], v2[2];
+  get_totals<1u>(s, CH_ADV1, v1);
+  get_totals<0u>(s, CH_ADV2, v2);
+  if (threadIdx.x == 0) {
+    SlotState *st = s.st;
+    st->comax = v1[0];
+    st->mass0 = v1[1] * s.V;
+    st->mass1 = v2[0] * s.V;
+    st->bflux = v2[1];
+    if (v1[0] > 1.0) st->unstable = 1;
+    double defect = fabs(st->mass1 - st->mass0 + ctl.dt * v2[1]);
     if (defect > st->mass_defect) st->mass_defect = defect;
   }
 }
@@ -540,34 +538,34 @@ __global__ void __launch_bounds__(BLOCK) k_grad_u(const Slot *slots, const int2 
   const Slot &s = *B.s;
   const SlotCtl &ctl = *B.ctl;
   if (!ctl.active) return;
-  Cell c = cell_of(s, B.lb);
-  if (!c.valid) return;
   const int d = s.dim;
   const R *Uo = (const R *)(ctl.mode ? s.U_cr : s.U_vd);
   R *gU = (R *)s.gradU;
-  uint8_t fl = s.flags[c.P];
   const R ub = (R)ctl.ub;
-  for (int e = 0; e < d; ++e) {
-    CFace fc[2];
-    fc[0] = cell_face(s, fl, c.i, c.j, c.k, 2 * e);
-    fc[1] = cell_face(s, fl, c.i, c.j, c.k, 2 * e + 1);
-    for (int cc = 0; cc < d; ++cc) {
-      const R *Uc = Uo + cc * s.nc;
-      R out = (R)0;
-      if (!(fl & 0x40)) {
-        R fv[2];
-        for (int sd = 0; sd < 2; ++sd) {
-          const CFace &cf = fc[sd];
-          if (cf.type == F_INT) fv[sd] = (R)0.5 * (Uc[c.P] + Uc[cf.nb]);
-          else if (cf.type == F_WALL) fv[sd] = (R)0;
-          else if (cf.type == F_INLET) fv[sd] = inlet_u<R>(cc, e, sd ? (R)1 : (R)-1, ub);
-          else fv[sd] = Uc[c.P];
+  for_cells(s, B.lb, [&](const Cell &c) {
+    uint8_t fl = s.flags[c.P];
+    for (int e = 0; e < d; ++e) {
+      CFace fc[2];
+      fc[0] = cell_face(s, fl, c.i, c.j, c.k, 2 * e);
+      fc[1] = cell_face(s, fl, c.i, c.j, c.k, 2 * e + 1);
+      for (int cc = 0; cc < d; ++cc) {
+        const R *Uc = Uo + cc * s.nc;
+        R out = (R)0;
+        if (!(fl & 0x40)) {
+          R fv[2];
+          for (int sd = 0; sd < 2; ++sd) {
+            const CFace &cf = fc[sd];
+            if (cf.type == F_INT) fv[sd] = (R)0.5 * (Uc[c.P] + Uc[cf.nb]);
+            else if (cf.type == F_WALL) fv[sd] = (R)0;
+            else if (cf.type == F_INLET) fv[sd] = inlet_u<R>(cc, e, sd ? (R)1 : (R)-1, ub);
+            else fv[sd] = Uc[c.P];
+          }
+          out = (fv[1] - fv[0]) / (R)s.h;
         }
-        out = (fv[1] - fv[0]) / (R)s.h;
+        gU[(cc * d + e) * s.nc + c.P] = out;
       }
-      gU[(cc * d + e) * s.nc + c.P] = out;
     }
-  }
+  });
 }
 
 template <typename R>
@@ -575,17 +573,17 @@ __global__ void __launch_bounds__(BLOCK) k_mass_flux(const Slot *slots, const in
   Block B = block_of(slots, btab);
   const Slot &s = *B.s;
   if (!B.ctl->active) return;
-  Cell c = cell_of(s, B.lb);
-  if (!c.valid) return;
   const R *a = (const R *)s.alpha;
   const R *pa = (const R *)s.phi_prev, *pc = (const R *)s.phi_cr;
   R *Fm = (R *)s.Fm;
-  for_owned_faces(s, c, [&](int, int64_t fi, const FView &v) {
-    R phic = pa[fi] + pc[fi];
-    R F = (R)0;
-    if (v.type == F_INT) F = rho_of<R>(s, (R)0.5 * (a[v.lo] + a[v.hi])) * phic;
-    else if (v.type == F_INLET || v.type == F_OUTLET) F = rho_of<R>(s, a[v.P]) * phic;
-    Fm[fi] = F;
+  for_cells(s, B.lb, [&](const Cell &c) {
+    for_owned_faces(s, c, [&](int, int64_t fi, const FView &v) {
+      R phic = pa[fi] + pc[fi];
+      R F = (R)0;
+      if (v.type == F_INT) F = rho_of<R>(s, (R)0.5 * (a[v.lo] + a[v.hi])) * phic;
+      else if (v.type == F_INLET || v.type == F_OUTLET) F = rho_of<R>(s, a[v.P]) * phic;
+      Fm[fi] = F;
+    });
   });
 }
 
@@ -595,61 +593,61 @@ __global__ void __launch_bounds__(BLOCK) k_assemble(const Slot *slots, const int
   const Slot &s = *B.s;
   const SlotCtl &ctl = *B.ctl;
   if (!ctl.active) return;
-  Cell c = cell_of(s, B.lb);
-  if (!c.valid) return;
   const int d = s.dim;
   const int64_t nc = s.nc;
   const R *an = (const R *)s.alpha, *ao = (const R *)s.alpha_old;
   const R *Uo = (const R *)(ctl.mode ? s.U_cr : s.U_vd);
   const R *gU = (const R *)s.gradU, *Fm = (const R *)s.Fm;
   R *aPo = (R *)s.aP, *rAUo = (R *)s.rAU, *bo = (R *)s.b;
-  uint8_t fl = s.flags[c.P];
-  if (fl & 0x40) {
-    aPo[c.P] = (R)0;
-    rAUo[c.P] = (R)0;
-    for (int cc = 0; cc < d; ++cc) bo[cc * nc + c.P] = (R)0;
-    return;
-  }
   const R Vdt = (R)s.V / (R)ctl.dt;
   const R hh = (R)s.hh, Sh = (R)s.Sh, S = (R)s.S, S2h = (R)s.S2h, ub = (R)ctl.ub;
-  R rho_o = rho_of<R>(s, ao[c.P]), rho_n = rho_of<R>(s, an[c.P]), mu_n = mu_of<R>(s, an[c.P]);
-  R aP = rho_n * Vdt;
-  R b[3];
-  for (int cc = 0; cc < d; ++cc) b[cc] = (rho_o * Uo[cc * nc + c.P]) * Vdt;
-  for (int f = 0; f < 2 * d; ++f) {
-    CFace cf = cell_face(s, fl, c.i, c.j, c.k, f);
-    int e = f >> 1;
-    R sg = (f & 1) ? (R)1 : (R)-1;
-    if (cf.type == F_INT) {
-      R F = Fm[cf.fi], sF = sg * F;
-      R muf = mu_of<R>(s, (R)0.5 * (an[c.P] + an[cf.nb]));
-      R D = muf * Sh;
-      aP = aP + (sF > (R)0 ? sF : (R)0);
-      aP = aP + D;
-      int64_t lo = (f & 1) ? c.P : cf.nb, hi = (f & 1) ? cf.nb : c.P;
-      for (int cc = 0; cc < d; ++cc) {
-        R lu = F >= (R)0 ? hh * gU[(cc * d + e) * nc + lo] : -(hh * gU[(cc * d + e) * nc + hi]);
-        b[cc] = b[cc] - sg * (F * lu);
-        R tv = (muf * S) * ((R)0.5 * (gU[(e * d + cc) * nc + c.P] + gU[(e * d + cc) * nc + cf.nb]));
-        b[cc] = b[cc] + sg * tv;
-      }
-    } else if (cf.type == F_WALL) {
-      aP = aP + mu_n * S2h;
-    } else if (cf.type == F_INLET) {
-      R F = Fm[cf.fi];
-      aP = aP + mu_n * S2h;
-      for (int cc = 0; cc < d; ++cc) {
-        R ubc = inlet_u<R>(cc, e, sg, ub);
-        b[cc] = b[cc] + (mu_n * S2h) * ubc;
-        b[cc] = b[cc] - sg * (F * ubc);
-      }
-    } else if (cf.type == F_OUTLET) {
-      aP = aP + sg * Fm[cf.fi];
+  for_cells(s, B.lb, [&](const Cell &c) {
+    uint8_t fl = s.flags[c.P];
+    if (fl & 0x40) {
+      aPo[c.P] = (R)0;
+      rAUo[c.P] = (R)0;
+      for (int cc = 0; cc < d; ++cc) bo[cc * nc + c.P] = (R)0;
+      return;
     }
-  }
-  aPo[c.P] = aP;
-  rAUo[c.P] = (R)s.V / aP;
-  for (int cc = 0; cc < d; ++cc) bo[cc * nc + c.P] = b[cc];
+    R rho_o = rho_of<R>(s, ao[c.P]), rho_n = rho_of<R>(s, an[c.P]), mu_n = mu_of<R>(s, an[c.P]);
+    R aP = rho_n * Vdt;
+    R b[3];
+    for (int cc = 0; cc < d; ++cc) b[cc] = (rho_o * Uo[cc * nc + c.P]) * Vdt;
+    for (int f = 0; f < 2 * d; ++f) {
+      CFace cf = cell_face(s, fl, c.i, c.j, c.k, f);
+      int e = f >> 1;
+      R sg = (f & 1) ? (R)1 : (R)-1;
+      if (cf.type == F_INT) {
+        R F = Fm[cf.fi], sF = sg * F;
+        R muf = mu_of<R>(s, (R)0.5 * (an[c.P] + an[cf.nb]));
+        R D = muf * Sh;
+        aP = aP + (sF > (R)0 ? sF : (R)0);
+        aP = aP + D;
+        int64_t lo = (f & 1) ? c.P : cf.nb, hi = (f & 1) ? cf.nb : c.P;
+        for (int cc = 0; cc < d; ++cc) {
+          R lu = F >= (R)0 ? hh * gU[(cc * d + e) * nc + lo] : -(hh * gU[(cc * d + e) * nc + hi]);
+          b[cc] = b[cc] - sg * (F * lu);
+          R tv = (muf * S) * ((R)0.5 * (gU[(e * d + cc) * nc + c.P] + gU[(e * d + cc) * nc + cf.nb]));
+          b[cc] = b[cc] + sg * tv;
+        }
+      } else if (cf.type == F_WALL) {
+        aP = aP + mu_n * S2h;
+      } else if (cf.type == F_INLET) {
+        R F = Fm[cf.fi];
+        aP = aP + mu_n * S2h;
+        for (int cc = 0; cc < d; ++cc) {
+          R ubc = inlet_u<R>(cc, e, sg, ub);
+          b[cc] = b[cc] + (mu_n * S2h) * ubc;
+          b[cc] = b[cc] - sg * (F * ubc);
+        }
+      } else if (cf.type == F_OUTLET) {
+        aP = aP + sg * Fm[cf.fi];
+      }
+    }
+    aPo[c.P] = aP;
+    rAUo[c.P] = (R)s.V / aP;
+    for (int cc = 0; cc < d; ++cc) bo[cc * nc + c.P] = b[cc];
+  });
 }
 
 // ---------------------------------------------------------------------------
@@ -662,30 +660,30 @@ __global__ void __launch_bounds__(BLOCK) k_predictor(const Slot *slots, const in
   const Slot &s = *B.s;
   const SlotCtl &ctl = *B.ctl;
   if (!ctl.active) return;
-  Cell c = cell_of(s, B.lb);
-  if (!c.valid) return;
   const int d = s.dim;
   const int64_t nc = s.nc;
   const R *an = (const R *)s.alpha, *U = (const R *)(ctl.mode ? s.U_cr : s.U_vd);
   const R *Fm = (const R *)s.Fm, *b = (const R *)s.b, *aPv = (const R *)s.aP;
   R *HbyA = (R *)s.HbyA;
-  uint8_t fl = s.flags[c.P];
-  if (fl & 0x40) {
-    for (int cc = 0; cc < d; ++cc) HbyA[cc * nc + c.P] = (R)0;
-    return;
-  }
-  R H[3];
-  for (int cc = 0; cc < d; ++cc) H[cc] = b[cc * nc + c.P];
-  for (int f = 0; f < 2 * d; ++f) {
-    CFace cf = cell_face(s, fl, c.i, c.j, c.k, f);
-    if (cf.type != F_INT) continue;
-    R sF = ((f & 1) ? (R)1 : (R)-1) * Fm[cf.fi];
-    R D = mu_of<R>(s, (R)0.5 * (an[c.P] + an[cf.nb])) * (R)s.Sh;
-    R aN = (sF < (R)0 ? sF : (R)0) - D;
-    for (int cc = 0; cc < d; ++cc) H[cc] = H[cc] - aN * U[cc * nc + cf.nb];
-  }
-  R aP = aPv[c.P];
-  for (int cc = 0; cc < d; ++cc) HbyA[cc * nc + c.P] = H[cc] / aP;
+  for_cells(s, B.lb, [&](const Cell &c) {
+    uint8_t fl = s.flags[c.P];
+    if (fl & 0x40) {
+      for (int cc = 0; cc < d; ++cc) HbyA[cc * nc + c.P] = (R)0;
+      return;
+    }
+    R H[3];
+    for (int cc = 0; cc < d; ++cc) H[cc] = b[cc * nc + c.P];
+    for (int f = 0; f < 2 * d; ++f) {
+      CFace cf = cell_face(s, fl, c.i, c.j, c.k, f);
+      if (cf.type != F_INT) continue;
+      R sF = ((f & 1) ? (R)1 : (R)-1) * Fm[cf.fi];
+      R D = mu_of<R>(s, (R)0.5 * (an[c.P] + an[cf.nb])) * (R)s.Sh;
+      R aN = (sF < (R)0 ? sF : (R)0) - D;
+      for (int cc = 0; cc < d; ++cc) H[cc] = H[cc] - aN * U[cc * nc + cf.nb];
+    }
+    R aP = aPv[c.P];
+    for (int cc = 0; cc < d; ++cc) HbyA[cc * nc + c.P] = H[cc] / aP;
+  });
 }
 
 template <typename R>
@@ -694,27 +692,27 @@ __global__ void __launch_bounds__(BLOCK) k_phiH(const Slot *slots, const int2 *b
   const Slot &s = *B.s;
   const SlotCtl &ctl = *B.ctl;
   if (!ctl.active) return;
-  Cell c = cell_of(s, B.lb);
-  if (!c.valid) return;
   const int64_t nc = s.nc;
   const R *HbyA = (const R *)s.HbyA, *rAU = (const R *)s.rAU, *kap = (const R *)s.kappa, *a = (const R *)s.alpha;
   R *phiH = (R *)s.phiH;
   const R S = (R)s.S, ub = (R)ctl.ub;
   const int with_st = ctl.with_st;
-  for_owned_faces(s, c, [&](int e, int64_t fi, const FView &v) {
-    R ph = (R)0;
-    if (v.type == F_INT) {
-      ph = ((R)0.5 * (HbyA[e * nc + v.lo] + HbyA[e * nc + v.hi])) * S;
-      if (with_st) {
-        R rAUf = (R)0.5 * (rAU[v.lo] + rAU[v.hi]);
-        ph = ph + (rAUf * st_face<R>(s, kap, a, v.lo, v.hi)) * S;
+  for_cells(s, B.lb, [&](const Cell &c) {
+    for_owned_faces(s, c, [&](int e, int64_t fi, const FView &v) {
+      R ph = (R)0;
+      if (v.type == F_INT) {
+        ph = ((R)0.5 * (HbyA[e * nc + v.lo] + HbyA[e * nc + v.hi])) * S;
+        if (with_st) {
+          R rAUf = (R)0.5 * (rAU[v.lo] + rAU[v.hi]);
+          ph = ph + (rAUf * st_face<R>(s, kap, a, v.lo, v.hi)) * S;
+        }
+      } else if (v.type == F_INLET) {
+        ph = -(R)v.sf * (ub * S);
+      } else if (v.type == F_OUTLET) {
+        ph = HbyA[e * nc + v.P] * S;
       }
-    } else if (v.type == F_INLET) {
-      ph = -(R)v.sf * (ub * S);
-    } else if (v.type == F_OUTLET) {
-      ph = HbyA[e * nc + v.P] * S;
-    }
-    phiH[fi] = ph;
+      phiH[fi] = ph;
+    });
   });
 }
 
@@ -747,68 +745,71 @@ __global__ void __launch_bounds__(BLOCK) k_pressure_setup(const Slot *slots, con
   const Slot &s = *B.s;
   const SlotCtl &ctl = *B.ctl;
   if (!ctl.active) return;
-  Cell c = cell_of(s, B.lb);
   const R *rAU = (const R *)s.rAU, *phiH = (const R *)s.phiH;
   const double *p = ctl.mode ? s.p_cr : s.p_vd;
   const bool mixed = s.precision != 0;
-  double red[4] = {0.0, 0.0, 0.0, 0.0};   // |rhs|^2, |r|^2 (r of the solved system), r.z, sum p
-  if (c.valid) {
+  T *r = (T *)s.r, *z = (T *)s.z, *invD = (T *)s.invD, *e = (T *)s.e;
+  double red[4] = {0.0, 0.0, 0.0, 0.0};   // |rhs|^2, |r|^2 (FP64 r in mixed), r.z, sum p
+  for_cells(s, B.lb, [&](const Cell &c) {
     uint8_t fl = s.flags[c.P];
-    T *r = (T *)s.r, *z = (T *)s.z, *invD = (T *)s.invD;
     if (fl & 0x40) {
       s.rhs[c.P] = 0.0;
       s.Mp[c.P] = 0.0;
       r[c.P] = (T)0;
       z[c.P] = (T)0;
       invD[c.P] = (T)0;
-      if (mixed) ((T *)s.e)[c.P] = (T)0;
-    } else {
-      double acc = 0.0;
-      T dg = (T)0;
-      for (int f = 0; f < 2 * s.dim; ++f) {
-        CFace cf = cell_face(s, fl, c.i, c.j, c.k, f);
-        if (cf.type == F_NONE) continue;
-        acc = acc + ((f & 1) ? 1.0 : -1.0) * (double)phiH[cf.fi];
-        if (cf.type == F_INT || cf.type == F_OUTLET) dg = dg + pcoef<T, R>(s, rAU, c.P, cf);
-      }
-      double rhs = -acc;
-      double Mp = matvec_row<double, R>(s, rAU, c, fl, [&](int64_t x) { return p[x]; });
-      double r64 = rhs - Mp;
-      T id = (T)1 / dg;
-      T rr = (T)r64;
-      T zz = rr * id;
-      s.rhs[c.P] = rhs;
-      s.Mp[c.P] = Mp;
-      r[c.P] = rr;
-      z[c.P] = zz;
-      invD[c.P] = id;
-      if (mixed) ((T *)s.e)[c.P] = (T)0;
-      red[0] = rhs * rhs;
-      red[1] = mixed ? r64 * r64 : (double)(rr * rr);
-      red[2] = (double)(rr * zz);
-      red[3] = p[c.P];
+      if (mixed) e[c.P] = (T)0;
+      return;
     }
-  }
-  if (reduce_last<0u>(s, B.lb, red) && threadIdx.x == 0) {
-    SlotState *st = B.st;
-    double bn = sqrt(red[0]);
-    double rn = sqrt(red[1]);
-    st->pbar = red[3] / (double)s.n_fluid;
-    st->rz = red[2];
+    double acc = 0.0;
+    T dg = (T)0;
+    for (int f = 0; f < 2 * s.dim; ++f) {
+      CFace cf = cell_face(s, fl, c.i, c.j, c.k, f);
+      if (cf.type == F_NONE) continue;
+      acc = acc + ((f & 1) ? 1.0 : -1.0) * (double)phiH[cf.fi];
+      if (cf.type == F_INT || cf.type == F_OUTLET) dg = dg + pcoef<T, R>(s, rAU, c.P, cf);
+    }
+    double rhs = -acc;
+    double Mp = matvec_row<double, R>(s, rAU, c, fl, [&](int64_t x) { return p[x]; });
+    double r64 = rhs - Mp;
+    T id = (T)1 / dg;
+    T rr = (T)r64;
+    T zz = rr * id;
+    s.rhs[c.P] = rhs;
+    s.Mp[c.P] = Mp;
+    r[c.P] = rr;
+    z[c.P] = zz;
+    invD[c.P] = id;
+    if (mixed) e[c.P] = (T)0;
+    red[0] = red[0] + rhs * rhs;
+    red[1] = red[1] + (mixed ? r64 * r64 : (double)(rr * rr));
+    red[2] = red[2] + (double)(rr * zz);
+    red[3] = red[3] + p[c.P];
+  });
+  put_partials<0u>(s, B.lb, CH_SETUP, red);
+}
+
+// one block per slot: norms of the pressure equation, initial convergence test
+__global__ void __launch_bounds__(BLOCK) k_setup_fin(const Slot *slots) {
+  const Slot &s = slots[blockIdx.x];
+  const SlotCtl &ctl = *s.ctl;
+  if (!ctl.active) return;
+  double v[4];
+  get_totals<0u>(s, CH_SETUP, v);
+  if (threadIdx.x == 0) {
+    SlotState *st = s.st;
+    double bn = sqrt(v[0]);
+    double rn = sqrt(v[1]);
+    st->pbar = v[3] / (double)s.n_fluid;
+    st->rz0 = v[2];
     st->it = 0;
     st->zero_rhs = bn == 0.0;
-    if (mixed) {
-      // outer (FP64) residual; the inner system is M e = r32
-      st->bn64 = bn;
-      st->rn64 = rn;
-      st->bn = rn;    // refined below by k_refine_res when needed
-      st->rn = rn;
-      st->done = (bn == 0.0) || (rn <= ctl.rtol * bn);
-    } else {
-      st->bn = bn;
-      st->rn = rn;
-      st->done = (bn == 0.0) || (rn <= ctl.rtol * bn);
-    }
+    st->done = (bn == 0.0) || (rn <= ctl.rtol * bn);
+    st->rn = rn;
+    st->bn64 = bn;
+    st->rn64 = rn;
+    // mixed precision: the FP32 inner system is M e = r, measured against |r|
+    st->bn = s.precision != 0 ? rn : bn;
   }
 }
 
@@ -818,10 +819,8 @@ __global__ void __launch_bounds__(BLOCK) k_zero_rhs_p(const Slot *slots, const i
   const Slot &s = *B.s;
   const SlotCtl &ctl = *B.ctl;
   if (!ctl.active || !B.st->zero_rhs) return;
-  Cell c = cell_of(s, B.lb);
-  if (!c.valid) return;
   double *p = ctl.mode ? s.p_cr : s.p_vd;
-  p[c.P] = 0.0;
+  for_cells(s, B.lb, [&](const Cell &c) { p[c.P] = 0.0; });
 }
 
 // normalised residual E = sum|b - Mp| / (sum(|Mp - M pbar| + |b - M pbar|) + 1e-20)
@@ -831,113 +830,127 @@ __global__ void __launch_bounds__(BLOCK) k_normres(const Slot *slots, const int2
   const Slot &s = *B.s;
   const SlotCtl &ctl = *B.ctl;
   if (!ctl.active || ctl.mode != 1) return;
-  Cell c = cell_of(s, B.lb);
   const R *rAU = (const R *)s.rAU;
   const double pbar = B.st->pbar;
   double red[2] = {0.0, 0.0};
-  if (c.valid) {
+  for_cells(s, B.lb, [&](const Cell &c) {
     uint8_t fl = s.flags[c.P];
-    if (!(fl & 0x40)) {
-      double Mpb = matvec_row<double, R>(s, rAU, c, fl, [&](int64_t) { return pbar; });
-      double rhs = s.rhs[c.P], Mp = s.Mp[c.P];
-      red[0] = fabs(rhs - Mp);
-      red[1] = fabs(Mp - Mpb) + fabs(rhs - Mpb);
-    }
-  }
-  if (reduce_last<0u>(s, B.lb, red) && threadIdx.x == 0) B.st->E = red[0] / (red[1] + 1e-20);
+    if (fl & 0x40) return;
+    double Mpb = matvec_row<double, R>(s, rAU, c, fl, [&](int64_t) { return pbar; });
+    double rhs = s.rhs[c.P], Mp = s.Mp[c.P];
+    red[0] = red[0] + fabs(rhs - Mp);
+    red[1] = red[1] + (fabs(Mp - Mpb) + fabs(rhs - Mpb));
+  });
+  put_partials<0u>(s, B.lb, CH_NORM, red);
 }
 
-// conjugate gradient, pass 1: d = z + beta d_old (d = z on the first
-// iteration), q = M d, <d, q>
+__global__ void __launch_bounds__(BLOCK) k_norm_fin(const Slot *slots) {
+  const Slot &s = slots[blockIdx.x];
+  const SlotCtl &ctl = *s.ctl;
+  if (!ctl.active || ctl.mode != 1) return;
+  double v[2];
+  get_totals<0u>(s, CH_NORM, v);
+  if (threadIdx.x == 0) s.st->E = v[0] / (v[1] + 1e-20);
+}
+
+// Conjugate gradient, pass 1 of iteration it (0-based): for it > 0, sum the
+// previous pass 2's <r,r>, <r,z>, apply the convergence test and form beta;
+// then d = z + beta d_old (d = z when it = 0), q = M d and <d, q>.
 template <typename R>
-__global__ void __launch_bounds__(BLOCK) k_pcg1(const Slot *slots, const int2 *btab) {
+__global__ void __launch_bounds__(BLOCK) k_pcg1(const Slot *slots, const int2 *btab, int it) {
   using T = R;
   Block B = block_of(slots, btab);
   const Slot &s = *B.s;
   const SlotCtl &ctl = *B.ctl;
-  if (!ctl.active) return;
-  const SlotState &st0 = *B.st;
-  if (st0.done) return;
-  const int it = st0.it;
+  if (!ctl.active || B.st->done) return;
+  SlotState *st = B.st;
+  const bool mixed = s.precision != 0;
+  double rz_cur, beta = 0.0;
+  if (it == 0) {
+    rz_cur = st->rz0;
+  } else {
+    double v[2];
+    get_totals<0u>(s, CH_CG2, v);
+    double rn = sqrt(v[0]);
+    double rtol = mixed ? ctl.rtol_inner : ctl.rtol;
+    bool conv = rn <= rtol * st->bn;
+    bool cap = !conv && it >= ctl.max_it;
+    if (conv || cap) {
+      if (B.lb == 0 && threadIdx.x == 0) {
+        st->rn = rn;
+        st->it = it;
+        st->done = 1;
+        if (cap) st->maxit_hit = st->maxit_hit + 1;
+      }
+      return;
+    }
+    rz_cur = v[1];
+    beta = rz_cur / st->rzbuf[(it - 1) & 1];
+    if (B.lb == 0 && threadIdx.x == 0) st->rn = rn;
+  }
+  if (B.lb == 0 && threadIdx.x == 0) st->rzbuf[it & 1] = rz_cur;
   const bool first = it == 0;
-  const T beta = (T)st0.beta;
-  Cell c = cell_of(s, B.lb);
+  const T tb = (T)beta;
   const R *rAU = (const R *)s.rAU;
   const T *z = (const T *)s.z;
   const T *dold = (const T *)((it & 1) ? s.d1 : s.d0);
   T *dnew = (T *)((it & 1) ? s.d0 : s.d1);
   T *q = (T *)s.q;
   double red[1] = {0.0};
-  if (c.valid) {
+  for_cells(s, B.lb, [&](const Cell &c) {
     uint8_t fl = s.flags[c.P];
     if (fl & 0x40) {
       dnew[c.P] = (T)0;
       q[c.P] = (T)0;
-    } else {
-      auto dv = [&](int64_t x) -> T { return first ? z[x] : z[x] + beta * dold[x]; };
-      T dP = dv(c.P);
-      T qq = matvec_row<T, R>(s, rAU, c, fl, dv);
-      dnew[c.P] = dP;
-      q[c.P] = qq;
-      red[0] = (double)(dP * qq);
+      return;
     }
-  }
-  if (reduce_last<0u>(s, B.lb, red) && threadIdx.x == 0) {
-    B.st->dq = red[0];
-    B.st->cg_alpha = B.st->rz / red[0];
-  }
+    auto dv = [&](int64_t x) -> T { return first ? z[x] : z[x] + tb * dold[x]; };
+    T dP = dv(c.P);
+    T qq = matvec_row<T, R>(s, rAU, c, fl, dv);
+    dnew[c.P] = dP;
+    q[c.P] = qq;
+    red[0] = red[0] + (double)(dP * qq);
+  });
+  put_partials<0u>(s, B.lb, CH_CG1, red);
 }
 
-// pass 2: x += a d, r -= a q, z = D^-1 r, |r|^2, <r, z>; convergence test
+// pass 2: alpha = <r,z>/<d,q>; x += alpha d, r -= alpha q, z = D^-1 r;
+// partial <r,r>, <r,z> for the next pass 1
 template <typename R>
-__global__ void __launch_bounds__(BLOCK) k_pcg2(const Slot *slots, const int2 *btab) {
+__global__ void __launch_bounds__(BLOCK) k_pcg2(const Slot *slots, const int2 *btab, int it) {
   using T = R;
   Block B = block_of(slots, btab);
   const Slot &s = *B.s;
   const SlotCtl &ctl = *B.ctl;
-  if (!ctl.active) return;
-  const SlotState &st0 = *B.st;
-  if (st0.done) return;
-  const int it = st0.it;
+  if (!ctl.active || B.st->done) return;
+  SlotState *st = B.st;
   const bool mixed = s.precision != 0;
-  const T al = (T)st0.cg_alpha;
-  Cell c = cell_of(s, B.lb);
+  double v[1];
+  get_totals<0u>(s, CH_CG1, v);
+  const double alpha = st->rzbuf[it & 1] / v[0];
+  if (B.lb == 0 && threadIdx.x == 0) {
+    st->it = it + 1;
+    st->total_it = st->total_it + 1;
+  }
+  const T al = (T)alpha;
   const T *d = (const T *)((it & 1) ? s.d0 : s.d1);
   const T *q = (const T *)s.q, *invD = (const T *)s.invD;
   T *r = (T *)s.r, *z = (T *)s.z;
+  T *xe = (T *)s.e;
+  double *xp = ctl.mode ? s.p_cr : s.p_vd;
   double red[2] = {0.0, 0.0};
-  if (c.valid && !solid_at(s, c.P)) {
-    if (mixed) {
-      T *x = (T *)s.e;
-      x[c.P] = x[c.P] + al * d[c.P];
-    } else {
-      double *x = ctl.mode ? s.p_cr : s.p_vd;
-      x[c.P] = x[c.P] + (double)al * (double)d[c.P];
-    }
+  for_cells(s, B.lb, [&](const Cell &c) {
+    if (solid_at(s, c.P)) return;
+    if (mixed) xe[c.P] = xe[c.P] + al * d[c.P];
+    else xp[c.P] = xp[c.P] + (double)al * (double)d[c.P];
     T rr = r[c.P] - al * q[c.P];
     T zz = rr * invD[c.P];
     r[c.P] = rr;
     z[c.P] = zz;
-    red[0] = (double)(rr * rr);
-    red[1] = (double)(rr * zz);
-  }
-  if (reduce_last<0u>(s, B.lb, red) && threadIdx.x == 0) {
-    SlotState *st = B.st;
-    double rn = sqrt(red[0]);
-    st->rn = rn;
-    st->it = it + 1;
-    st->total_it = st->total_it + 1;
-    double rtol = mixed ? ctl.rtol_inner : ctl.rtol;
-    if (rn <= rtol * st->bn) {
-      st->done = 1;
-    } else if (it + 1 >= ctl.max_it) {
-      st->done = 1;
-      st->maxit_hit = st->maxit_hit + 1;
-    } else {
-      st->beta = red[1] / st->rz;
-      st->rz = red[1];
-    }
-  }
+    red[0] = red[0] + (double)(rr * rr);
+    red[1] = red[1] + (double)(rr * zz);
+  });
+  put_partials<0u>(s, B.lb, CH_CG2, red);
 }
 
 // mixed precision, outer refinement: p += e, e = 0
@@ -947,12 +960,13 @@ __global__ void __launch_bounds__(BLOCK) k_refine_x(const Slot *slots, const int
   const Slot &s = *B.s;
   const SlotCtl &ctl = *B.ctl;
   if (!ctl.active || s.precision == 0 || B.st->zero_rhs) return;
-  Cell c = cell_of(s, B.lb);
-  if (!c.valid || solid_at(s, c.P)) return;
   double *p = ctl.mode ? s.p_cr : s.p_vd;
   R *e = (R *)s.e;
-  p[c.P] = p[c.P] + (double)e[c.P];
-  e[c.P] = (R)0;
+  for_cells(s, B.lb, [&](const Cell &c) {
+    if (solid_at(s, c.P)) return;
+    p[c.P] = p[c.P] + (double)e[c.P];
+    e[c.P] = (R)0;
+  });
 }
 
 // mixed precision: r64 = rhs - M p in FP64; restart the FP32 inner solve on it
@@ -963,32 +977,39 @@ __global__ void __launch_bounds__(BLOCK) k_refine_res(const Slot *slots, const i
   const Slot &s = *B.s;
   const SlotCtl &ctl = *B.ctl;
   if (!ctl.active || s.precision == 0 || B.st->zero_rhs) return;
-  Cell c = cell_of(s, B.lb);
   const R *rAU = (const R *)s.rAU;
   const double *p = ctl.mode ? s.p_cr : s.p_vd;
+  T *r = (T *)s.r, *z = (T *)s.z;
+  const T *invD = (const T *)s.invD;
   double red[3] = {0.0, 0.0, 0.0};
-  if (c.valid) {
+  for_cells(s, B.lb, [&](const Cell &c) {
     uint8_t fl = s.flags[c.P];
-    T *r = (T *)s.r, *z = (T *)s.z;
-    const T *invD = (const T *)s.invD;
-    if (!(fl & 0x40)) {
-      double Mp = matvec_row<double, R>(s, rAU, c, fl, [&](int64_t x) { return p[x]; });
-      double r64 = s.rhs[c.P] - Mp;
-      T rr = (T)r64;
-      T zz = rr * invD[c.P];
-      r[c.P] = rr;
-      z[c.P] = zz;
-      red[0] = r64 * r64;
-      red[1] = (double)(rr * rr);
-      red[2] = (double)(rr * zz);
-    }
-  }
-  if (reduce_last<0u>(s, B.lb, red) && threadIdx.x == 0) {
-    SlotState *st = B.st;
-    st->rn64 = sqrt(red[0]);
-    st->bn = sqrt(red[1]);
+    if (fl & 0x40) return;
+    double Mp = matvec_row<double, R>(s, rAU, c, fl, [&](int64_t x) { return p[x]; });
+    double r64 = s.rhs[c.P] - Mp;
+    T rr = (T)r64;
+    T zz = rr * invD[c.P];
+    r[c.P] = rr;
+    z[c.P] = zz;
+    red[0] = red[0] + r64 * r64;
+    red[1] = red[1] + (double)(rr * rr);
+    red[2] = red[2] + (double)(rr * zz);
+  });
+  put_partials<0u>(s, B.lb, CH_REF, red);
+}
+
+__global__ void __launch_bounds__(BLOCK) k_refine_fin(const Slot *slots) {
+  const Slot &s = slots[blockIdx.x];
+  const SlotCtl &ctl = *s.ctl;
+  if (!ctl.active || s.precision == 0 || s.st->zero_rhs) return;
+  double v[3];
+  get_totals<0u>(s, CH_REF, v);
+  if (threadIdx.x == 0) {
+    SlotState *st = s.st;
+    st->rn64 = sqrt(v[0]);
+    st->bn = sqrt(v[1]);
     st->rn = st->bn;
-    st->rz = red[2];
+    st->rz0 = v[2];
     st->it = 0;
     st->refine_steps = st->refine_steps + 1;
     st->done = st->rn64 <= ctl.rtol * st->bn64;
@@ -1003,8 +1024,6 @@ __global__ void __launch_bounds__(BLOCK) k_correct(const Slot *slots, const int2
   const Slot &s = *B.s;
   const SlotCtl &ctl = *B.ctl;
   if (!ctl.active) return;
-  Cell c = cell_of(s, B.lb);
-  if (!c.valid) return;
   const int d = s.dim;
   const int64_t nc = s.nc;
   const double *p = ctl.mode ? s.p_cr : s.p_vd;
@@ -1012,46 +1031,48 @@ __global__ void __launch_bounds__(BLOCK) k_correct(const Slot *slots, const int2
   const R *kap = (const R *)s.kappa, *a = (const R *)s.alpha;
   R *phi = (R *)(ctl.mode ? s.phi_cr : s.phi_vd);
   R *U = (R *)(ctl.mode ? s.U_cr : s.U_vd);
+  R *Us = (R *)s.U_sum;
   const R Sh = (R)s.Sh, S2h = (R)s.S2h, h = (R)s.h, hh = (R)s.hh;
   const int with_st = ctl.with_st;
-  for_owned_faces(s, c, [&](int, int64_t fi, const FView &v) {
-    R ph = phiH[fi];
-    if (v.type == F_INT) {
-      R cf = ((R)0.5 * (rAU[v.lo] + rAU[v.hi])) * Sh;
-      ph = ph - cf * (R)(p[v.hi] - p[v.lo]);
-    } else if (v.type == F_OUTLET) {
-      R cf = rAU[v.P] * S2h;
-      ph = ph + (R)v.sf * (cf * (R)p[v.P]);
-    }
-    phi[fi] = ph;
-  });
-  uint8_t fl = s.flags[c.P];
-  R *Us = (R *)s.U_sum;
   bool bad = false;
-  for (int cc = 0; cc < d; ++cc) {
-    R u = (R)0;
-    if (!(fl & 0x40)) {
-      R qv[2];
-      for (int sd = 0; sd < 2; ++sd) {
-        CFace cf = cell_face(s, fl, c.i, c.j, c.k, 2 * cc + sd);
-        R qq = (R)0;
-        if (cf.type == F_INT) {
-          int64_t lo = sd ? c.P : cf.nb, hi = sd ? cf.nb : c.P;
-          R ff = with_st ? st_face<R>(s, kap, a, lo, hi) : (R)0;
-          qq = ff - (R)(p[hi] - p[lo]) / h;
-        } else if (cf.type == F_OUTLET) {
-          R pplus = sd ? (R)0 : (R)p[c.P], pminus = sd ? (R)p[c.P] : (R)0;
-          qq = -(pplus - pminus) / hh;
-        }
-        qv[sd] = qq;
+  for_cells(s, B.lb, [&](const Cell &c) {
+    for_owned_faces(s, c, [&](int, int64_t fi, const FView &v) {
+      R ph = phiH[fi];
+      if (v.type == F_INT) {
+        R cf = ((R)0.5 * (rAU[v.lo] + rAU[v.hi])) * Sh;
+        ph = ph - cf * (R)(p[v.hi] - p[v.lo]);
+      } else if (v.type == F_OUTLET) {
+        R cf = rAU[v.P] * S2h;
+        ph = ph + (R)v.sf * (cf * (R)p[v.P]);
       }
-      u = HbyA[cc * nc + c.P] + rAU[c.P] * ((R)0.5 * (qv[0] + qv[1]));
-      if (!(u == u) || fabs(u) > (R)1e30) bad = true;
+      phi[fi] = ph;
+    });
+    uint8_t fl = s.flags[c.P];
+    for (int cc = 0; cc < d; ++cc) {
+      R u = (R)0;
+      if (!(fl & 0x40)) {
+        R qv[2];
+        for (int sd = 0; sd < 2; ++sd) {
+          CFace cf = cell_face(s, fl, c.i, c.j, c.k, 2 * cc + sd);
+          R qq = (R)0;
+          if (cf.type == F_INT) {
+            int64_t lo = sd ? c.P : cf.nb, hi = sd ? cf.nb : c.P;
+            R ff = with_st ? st_face<R>(s, kap, a, lo, hi) : (R)0;
+            qq = ff - (R)(p[hi] - p[lo]) / h;
+          } else if (cf.type == F_OUTLET) {
+            R pplus = sd ? (R)0 : (R)p[c.P], pminus = sd ? (R)p[c.P] : (R)0;
+            qq = -(pplus - pminus) / hh;
+          }
+          qv[sd] = qq;
+        }
+        u = HbyA[cc * nc + c.P] + rAU[c.P] * ((R)0.5 * (qv[0] + qv[1]));
+        if (!(u == u) || fabs(u) > (R)1e30) bad = true;
+      }
+      U[cc * nc + c.P] = u;
+      if (last && ctl.mode == 1) Us[cc * nc + c.P] = Us[cc * nc + c.P] + u;
     }
-    U[cc * nc + c.P] = u;
-    if (last && ctl.mode == 1) Us[cc * nc + c.P] = Us[cc * nc + c.P] + u;
-  }
-  if (bad) atomicOr(&B.st->nonfinite, 1);
+  });
+  if (bad) B.st->nonfinite = 1;
 }
 
 // U = U_vd + (1/N) sum u_cr, p = p_vd + p_cr
@@ -1061,15 +1082,15 @@ __global__ void __launch_bounds__(BLOCK) k_finalize(const Slot *slots, const int
   const Slot &s = *B.s;
   const SlotCtl &ctl = *B.ctl;
   if (!ctl.active || ctl.mode != 1) return;
-  Cell c = cell_of(s, B.lb);
-  if (!c.valid) return;
   const R *Uvd = (const R *)s.U_vd, *Us = (const R *)s.U_sum;
   R *U = (R *)s.U;
-  for (int cc = 0; cc < s.dim; ++cc) {
-    int64_t x = cc * s.nc + c.P;
-    U[x] = Uvd[x] + Us[x] / (R)ctl.n_sub;
-  }
-  s.p[c.P] = s.p_vd[c.P] + s.p_cr[c.P];
+  for_cells(s, B.lb, [&](const Cell &c) {
+    for (int cc = 0; cc < s.dim; ++cc) {
+      int64_t x = cc * s.nc + c.P;
+      U[x] = Uvd[x] + Us[x] / (R)ctl.n_sub;
+    }
+    s.p[c.P] = s.p_vd[c.P] + s.p_cr[c.P];
+  });
 }
 
 template <typename R>
@@ -1077,10 +1098,10 @@ __global__ void __launch_bounds__(BLOCK) k_zero_usum(const Slot *slots, const in
   Block B = block_of(slots, btab);
   const Slot &s = *B.s;
   if (!B.ctl->active || B.ctl->mode != 1) return;
-  Cell c = cell_of(s, B.lb);
-  if (!c.valid) return;
   R *Us = (R *)s.U_sum;
-  for (int cc = 0; cc < s.dim; ++cc) Us[cc * s.nc + c.P] = (R)0;
+  for_cells(s, B.lb, [&](const Cell &c) {
+    for (int cc = 0; cc < s.dim; ++cc) Us[cc * s.nc + c.P] = (R)0;
+  });
 }
 
 // ---------------------------------------------------------------------------
@@ -1088,6 +1109,7 @@ __global__ void __launch_bounds__(BLOCK) k_zero_usum(const Slot *slots, const in
 // ---------------------------------------------------------------------------
 
 #define GRID(L) dim3((unsigned)(L).nblocks), dim3(BLOCK), 0, (L).stream
+#define SLOTGRID(L) dim3((unsigned)(L).nslots), dim3(BLOCK), 0, (L).stream
 
 template <typename R> void launch_copy_phi_prev(const Launch &L) {
   hipLaunchKernelGGL(k_copy_phi_prev<R>, GRID(L), L.slots, L.btab);
@@ -1104,6 +1126,7 @@ template <typename R> void launch_advect(const Launch &L) {
   hipLaunchKernelGGL(k_mules_flux<R>, GRID(L), L.slots, L.btab);
   hipLaunchKernelGGL(k_mules_limiter<R>, GRID(L), L.slots, L.btab);
   hipLaunchKernelGGL(k_mules_update<R>, GRID(L), L.slots, L.btab);
+  hipLaunchKernelGGL(k_transport_fin, SLOTGRID(L), L.slots);
 }
 
 template <typename R> void launch_assemble(const Launch &L) {
@@ -1119,20 +1142,30 @@ template <typename R> void launch_predictor(const Launch &L) {
 
 template <typename R> void launch_pressure_setup(const Launch &L, bool normres) {
   hipLaunchKernelGGL(k_pressure_setup<R>, GRID(L), L.slots, L.btab);
+  hipLaunchKernelGGL(k_setup_fin, SLOTGRID(L), L.slots);
   hipLaunchKernelGGL(k_zero_rhs_p, GRID(L), L.slots, L.btab);
-  if (normres) hipLaunchKernelGGL(k_normres<R>, GRID(L), L.slots, L.btab);
+  if (normres) {
+    hipLaunchKernelGGL(k_normres<R>, GRID(L), L.slots, L.btab);
+    hipLaunchKernelGGL(k_norm_fin, SLOTGRID(L), L.slots);
+  }
 }
 
-template <typename R> void launch_pcg_iters(const Launch &L, int n) {
+template <typename R> void launch_pcg_iters(const Launch &L, int it0, int n) {
   for (int x = 0; x < n; ++x) {
-    hipLaunchKernelGGL(k_pcg1<R>, GRID(L), L.slots, L.btab);
-    hipLaunchKernelGGL(k_pcg2<R>, GRID(L), L.slots, L.btab);
+    hipLaunchKernelGGL(k_pcg1<R>, GRID(L), L.slots, L.btab, it0 + x);
+    hipLaunchKernelGGL(k_pcg2<R>, GRID(L), L.slots, L.btab, it0 + x);
   }
+}
+
+template <typename R> void launch_pcg_pass(const Launch &L, int it, int pass) {
+  if (pass == 0) hipLaunchKernelGGL(k_pcg1<R>, GRID(L), L.slots, L.btab, it);
+  else hipLaunchKernelGGL(k_pcg2<R>, GRID(L), L.slots, L.btab, it);
 }
 
 template <typename R> void launch_refine(const Launch &L) {
   hipLaunchKernelGGL(k_refine_x<R>, GRID(L), L.slots, L.btab);
   hipLaunchKernelGGL(k_refine_res<R>, GRID(L), L.slots, L.btab);
+  hipLaunchKernelGGL(k_refine_fin, SLOTGRID(L), L.slots);
 }
 
 template <typename R> void launch_correct(const Launch &L, int last) {
@@ -1151,8 +1184,8 @@ void launch_ctl_update(const Launch &L, const CtlUpdate &u) {
   hipLaunchKernelGGL(k_ctl_update, dim3(1), dim3(64), 0, L.stream, const_cast<Slot *>(L.slots), u);
 }
 
-void launch_state_reset(const Launch &L, int nslots, int relax) {
-  hipLaunchKernelGGL(k_state_reset, dim3((nslots + 63) / 64), dim3(64), 0, L.stream, L.slots, nslots, relax);
+void launch_state_reset(const Launch &L, int nslots) {
+  hipLaunchKernelGGL(k_state_reset, dim3((nslots + 63) / 64), dim3(64), 0, L.stream, L.slots, nslots);
 }
 
 #define INST(R)                                                   \
@@ -1162,7 +1195,8 @@ void launch_state_reset(const Launch &L, int nslots, int relax) {
   template void launch_assemble<R>(const Launch &);               \
   template void launch_predictor<R>(const Launch &);              \
   template void launch_pressure_setup<R>(const Launch &, bool);   \
-  template void launch_pcg_iters<R>(const Launch &, int);         \
+  template void launch_pcg_iters<R>(const Launch &, int, int);    \
+  template void launch_pcg_pass<R>(const Launch &, int, int);     \
   template void launch_refine<R>(const Launch &);                 \
   template void launch_correct<R>(const Launch &, int);           \
   template void launch_finalize<R>(const Launch &);               \

@@ -4,9 +4,9 @@
 // state).  Every kernel takes the device array of slots of a batch plus a
 // block table that maps each workgroup to (slot, block within the slot), so a
 // single launch advances every slot of a batch; a single instance is a batch
-// of one.  All per-slot reductions go through per-block partials and a
-// last-block finaliser with a fixed combination order, so a slot's results do
-// not depend on which other slots share the launch.
+// of one.  All per-slot reductions go through per-block partials summed
+// in a fixed order, so a slot's results do not depend on which other slots
+// share the launch.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -15,23 +15,27 @@ namespace oscar {
 
 enum : int { F_NONE = 0, F_INT = 1, F_WALL = 2, F_INLET = 3, F_OUTLET = 4 };
 
-constexpr int BLOCK = 256;   // threads per workgroup, one cell per thread
-constexpr int NRED = 4;      // doubles per block partial
+constexpr int BLOCK = 256;   // threads per workgroup
+constexpr int NVAL = 4;      // values per reduction channel
 
-// Per-slot scalars written by the last-block finalisers and read by later
-// kernels (uniform loads).  Only device code writes it; the host reads it back.
+// Reduction channels: a producing kernel writes one partial per block and
+// value at part[(ch*NVAL + m)*nblocks + block]; the consumer (the next
+// kernel that needs the total, or a one-block-per-slot finaliser) sums the
+// partials of its slot in a fixed order.  No atomics, no cache flushes.
+enum : int { CH_ADV1 = 0, CH_ADV2 = 1, CH_SETUP = 2, CH_NORM = 3, CH_CG1 = 4, CH_CG2 = 5, CH_REF = 6, NCH = 7 };
+
+// Per-slot scalars written by one block (block 0 of a kernel, or a
+// finaliser) and read by later kernels.
 struct SlotState {
-  double bn, rn, rz, dq, cg_alpha, beta;  // conjugate gradient
+  double bn, rn, rz0, rzbuf[2];            // conjugate gradient
   double pbar, E;                          // normalised residual
   double comax, mass0, mass1, bflux;       // transport
   double rn64, bn64;                       // refinement (mixed precision)
   double mass_defect;
   int32_t it, done, zero_rhs, total_it;
   int32_t nonfinite, unstable, maxit_hit, refine_steps;
-  int32_t relax_done, k, pad0, pad1;
 };
 
-// Per-slot step parameters, written by a small kernel from host values.
 struct SlotCtl {
   double dt, ub, rtol, rtol_inner;
   int32_t active, mode, with_st, max_it;
@@ -54,8 +58,7 @@ struct Slot {
   double *rhs, *Mp, *r64;
   // conjugate-gradient vectors (element type T = R)
   void *invD, *r, *z, *d0, *d1, *q, *e;
-  double *partials;             // NRED per block
-  uint32_t *ticket;
+  double *part;                 // NCH * NVAL * nblocks reduction partials
   SlotState *st;
   SlotCtl *ctl;
 };
@@ -72,6 +75,7 @@ struct Launch {
   const Slot *slots;       // device
   const int2 *btab;        // device block table
   int nblocks;             // total blocks
+  int nslots;              // slots in the table (per-slot finalisers use one block each)
   hipStream_t stream;
 };
 
@@ -81,12 +85,16 @@ template <typename R> void launch_advect(const Launch &L);
 template <typename R> void launch_assemble(const Launch &L);
 template <typename R> void launch_predictor(const Launch &L);
 template <typename R> void launch_pressure_setup(const Launch &L, bool normres);
-template <typename R> void launch_pcg_iters(const Launch &L, int n);
+template <typename R> void launch_pcg_iters(const Launch &L, int it0, int n);
+template <typename R> void launch_pcg_pass(const Launch &L, int it, int pass);
 template <typename R> void launch_refine(const Launch &L);
 template <typename R> void launch_correct(const Launch &L, int last);
 template <typename R> void launch_finalize(const Launch &L);
 template <typename R> void launch_zero_usum(const Launch &L);
 void launch_ctl_update(const Launch &L, const CtlUpdate &u);
-void launch_state_reset(const Launch &L, int nslots, int relax);
+void launch_state_reset(const Launch &L, int nslots);
+
+// blocks per slot: ceil(cells/BLOCK), capped (grid-stride beyond the cap)
+int blocks_for(int64_t nc);
 
 }  // namespace oscar

@@ -20,7 +20,8 @@ FIELDS = dict(alpha=0, U=1, p=2, U_vd=3, p_vd=4, U_cr=5, p_cr=6, phi_vd=7, phi_v
 
 EXPORTS = ["oscar_workspace_size", "oscar_create", "oscar_viscous_step", "oscar_capillary_relax",
            "oscar_relax_history", "oscar_pressure_solve", "oscar_get_field", "oscar_set_field",
-           "oscar_field_len", "oscar_stats", "oscar_destroy", "oscar_last_error", "oscar_dt_brackbill"]
+           "oscar_field_len", "oscar_stats", "oscar_destroy", "oscar_last_error", "oscar_dt_brackbill",
+           "oscar_timing", "oscar_timing_read"]
 
 
 class Desc(C.Structure):
@@ -74,6 +75,10 @@ def lib():
         L.oscar_last_error.restype = C.c_char_p
         L.oscar_dt_brackbill.argtypes = [C.c_double] * 4
         L.oscar_dt_brackbill.restype = C.c_double
+        L.oscar_timing.argtypes = [vp, C.c_int32]
+        L.oscar_timing.restype = C.c_int32
+        L.oscar_timing_read.argtypes = [vp, C.c_int32, dp, C.POINTER(C.c_int64)]
+        L.oscar_timing_read.restype = C.c_int32
         for name in ("oscar_workspace_size", "oscar_create", "oscar_viscous_step", "oscar_capillary_relax",
                      "oscar_relax_history", "oscar_pressure_solve", "oscar_get_field", "oscar_set_field",
                      "oscar_stats"):
@@ -209,6 +214,15 @@ class Oscar:
         a = np.ascontiguousarray(arr, dtype=np.float64)
         assert a.size == lib().oscar_field_len(self.ctx, fid)
         self._check(lib().oscar_set_field(self.ctx, fid, a.ctypes.data_as(C.POINTER(C.c_double))))
+
+    def timing(self, enable):
+        self._check(lib().oscar_timing(self.ctx, int(bool(enable))))
+
+    def timing_read(self, kernel):
+        ms = C.c_double(0.0)
+        n = C.c_int64(0)
+        self._check(lib().oscar_timing_read(self.ctx, int(kernel), C.byref(ms), C.byref(n)))
+        return ms.value, n.value
 
     def stats(self):
         s = Stats()

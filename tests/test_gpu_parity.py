@@ -107,3 +107,37 @@ def test_channel_bubble_few_steps_fp64(nx, ny):
     so = r.stats()
     assert abs(sg["mass_phase1"] - so["mass"]) <= 1e-12 * so["mass"]
     assert sg["mass_defect"] <= 1e-12 * so["mass"]
+
+
+def interface_crossings(alpha, nx, ny):
+    """x-positions of the alpha = 0.5 crossings along every grid row (linear
+    interpolation between cell centres), row by row."""
+    a = alpha.reshape(ny, nx)
+    out = []
+    for j in range(ny):
+        row = a[j]
+        s = np.nonzero((row[:-1] - 0.5) * (row[1:] - 0.5) < 0)[0]
+        out.append(s + (0.5 - row[s]) / (row[s + 1] - row[s]))
+    return out
+
+
+def test_channel_bubble_mixed_precision():
+    """Mixed path (FP32 fields and CG, FP64 refinement) after three OSCAR
+    steps of the scaled channel bubble: pressure and velocity within 1e-5
+    relative of the FP64 oracle, interface within 0.01 cells along every row,
+    final pressure residual (FP64) below 1e-8."""
+    c = cases.channel_bubble(nx=64, ny=16, n_sub=12, max_iters=12)
+    c["pcg_rtol"] = 1e-10
+    g, r, c = _pair(c, precision=1)
+    for step in range(3):
+        g.step()
+        r.step()
+    assert g.stats()["last_res"] <= 1e-8
+    for fld in ("p", "U"):
+        assert rel_linf(g.get(fld), r.get(fld)) <= 1e-5, fld
+    xg = interface_crossings(g.get("alpha"), c["nx"], c["ny"])
+    xo = interface_crossings(r.get("alpha"), c["nx"], c["ny"])
+    for a, b in zip(xg, xo):
+        assert len(a) == len(b)
+        if len(a):
+            assert np.abs(a - b).max() <= 0.01
