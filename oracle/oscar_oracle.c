@@ -208,18 +208,17 @@ static void face_normals(orc_t *o, const double *a) {
         for (int c = 0; c < o->d; ++c) G[c] = o->grad[c * o->nc + v.P];
         o->nhatf[fi] = G[e] / (vnorm(G, o->d) + o->delta);
       } else if (v.type == F_WALL) {
-        double g[3] = {0, 0, 0}, m[3] = {0, 0, 0}, t[3] = {0, 0, 0}, nw[3] = {0, 0, 0};
+        /* Wall adhesion: the wall condition n.n_w = cos(theta) fixes the
+         * wall-normal component of the unit interface normal at the wall
+         * face (the tangential part of the Brackbill construction has no
+         * component along the face normal).  It is scaled by the same
+         * regularisation |g|/(|g| + delta) as the interior normals, so it
+         * fades out continuously away from an interface. */
+        double g[3] = {0, 0, 0};
         for (int c = 0; c < o->d; ++c) g[c] = o->grad[c * o->nc + v.P];
         double mg = vnorm(g, o->d);
-        if (mg <= o->delta) { o->nhatf[fi] = 0.0; continue; }
-        nw[e] = v.s_fluid;   /* unit normal pointing out of the fluid, into the wall */
-        for (int c = 0; c < o->d; ++c) m[c] = g[c] / (mg + o->delta);
-        double mn = 0.0;
-        for (int c = 0; c < o->d; ++c) mn = mn + m[c] * nw[c];
-        for (int c = 0; c < o->d; ++c) t[c] = m[c] - mn * nw[c];
-        double tm = vnorm(t, o->d);
-        if (tm <= 1e-12) o->nhatf[fi] = m[e];
-        else o->nhatf[fi] = o->cos_t * nw[e] + o->sin_t * t[e] / tm;
+        double nw = v.s_fluid;   /* n_w . e: from the fluid into the wall */
+        o->nhatf[fi] = (mg / (mg + o->delta)) * (o->cos_t * nw);
       }
     }
   }

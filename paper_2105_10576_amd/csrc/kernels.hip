@@ -308,23 +308,11 @@ __global__ void __launch_bounds__(BLOCK) k_face_normals(const Slot *slots, const
         for (int cc = 0; cc < d; ++cc) G[cc] = g[cc * s.nc + v.P];
         out = G[e] / (vnorm(G, d) + delta);
       } else if (v.type == F_WALL) {
+        // wall adhesion n.n_w = cos(theta): the wall-normal component of the
+        // interface normal at the wall face, faded like the interior normals
         for (int cc = 0; cc < d; ++cc) G[cc] = g[cc * s.nc + v.P];
         R mg = vnorm(G, d);
-        if (mg <= delta) {
-          out = (R)0;
-        } else {
-          // Brackbill wall adhesion: n = cos(theta) n_w + sin(theta) t/|t|,
-          // n_w the unit normal from the fluid into the wall
-          R nw[3] = {(R)0, (R)0, (R)0}, m[3] = {(R)0, (R)0, (R)0}, t[3] = {(R)0, (R)0, (R)0};
-          nw[e] = (R)v.sf;
-          for (int cc = 0; cc < d; ++cc) m[cc] = G[cc] / (mg + delta);
-          R mn = (R)0;
-          for (int cc = 0; cc < d; ++cc) mn = mn + m[cc] * nw[cc];
-          for (int cc = 0; cc < d; ++cc) t[cc] = m[cc] - mn * nw[cc];
-          R tm = vnorm(t, d);
-          if (tm <= (R)1e-12) out = m[e];
-          else out = (R)s.cos_t * nw[e] + (R)s.sin_t * t[e] / tm;
-        }
+        out = (mg / (mg + delta)) * ((R)s.cos_t * (R)v.sf);
       }
       nh[fi] = out;
     });
@@ -737,7 +725,7 @@ __device__ __forceinline__ X matvec_row(const Slot &s, const R *rAU, const Cell 
   return acc;
 }
 
-// rhs = -div(phiH), r = rhs - M p, Jacobi diagonal, initial CG vectors
+// rhs = -div(phiH), r = rhs - M p, Jacobi diagonal
 template <typename R>
 __global__ void __launch_bounds__(BLOCK) k_pressure_setup(const Slot *slots, const int2 *btab) {
   using T = R;
@@ -748,15 +736,14 @@ __global__ void __launch_bounds__(BLOCK) k_pressure_setup(const Slot *slots, con
   const R *rAU = (const R *)s.rAU, *phiH = (const R *)s.phiH;
   const double *p = ctl.mode ? s.p_cr : s.p_vd;
   const bool mixed = s.precision != 0;
-  T *r = (T *)s.r, *z = (T *)s.z, *invD = (T *)s.invD, *e = (T *)s.e;
-  double red[4] = {0.0, 0.0, 0.0, 0.0};   // |rhs|^2, |r|^2 (FP64 r in mixed), r.z, sum p
+  T *r = (T *)s.cr[0], *invD = (T *)s.invD, *e = (T *)s.e;
+  double red[3] = {0.0, 0.0, 0.0};   // |rhs|^2, |rhs - M p|^2, sum p
   for_cells(s, B.lb, [&](const Cell &c) {
     uint8_t fl = s.flags[c.P];
     if (fl & 0x40) {
       s.rhs[c.P] = 0.0;
       s.Mp[c.P] = 0.0;
       r[c.P] = (T)0;
-      z[c.P] = (T)0;
       invD[c.P] = (T)0;
       if (mixed) e[c.P] = (T)0;
       return;
@@ -772,19 +759,15 @@ __global__ void __launch_bounds__(BLOCK) k_pressure_setup(const Slot *slots, con
     double rhs = -acc;
     double Mp = matvec_row<double, R>(s, rAU, c, fl, [&](int64_t x) { return p[x]; });
     double r64 = rhs - Mp;
-    T id = (T)1 / dg;
     T rr = (T)r64;
-    T zz = rr * id;
     s.rhs[c.P] = rhs;
     s.Mp[c.P] = Mp;
     r[c.P] = rr;
-    z[c.P] = zz;
-    invD[c.P] = id;
+    invD[c.P] = (T)1 / dg;
     if (mixed) e[c.P] = (T)0;
     red[0] = red[0] + rhs * rhs;
     red[1] = red[1] + (mixed ? r64 * r64 : (double)(rr * rr));
-    red[2] = red[2] + (double)(rr * zz);
-    red[3] = red[3] + p[c.P];
+    red[2] = red[2] + p[c.P];
   });
   put_partials<0u>(s, B.lb, CH_SETUP, red);
 }
@@ -794,14 +777,13 @@ __global__ void __launch_bounds__(BLOCK) k_setup_fin(const Slot *slots) {
   const Slot &s = slots[blockIdx.x];
   const SlotCtl &ctl = *s.ctl;
   if (!ctl.active) return;
-  double v[4];
+  double v[3];
   get_totals<0u>(s, CH_SETUP, v);
   if (threadIdx.x == 0) {
     SlotState *st = s.st;
     double bn = sqrt(v[0]);
     double rn = sqrt(v[1]);
-    st->pbar = v[3] / (double)s.n_fluid;
-    st->rz0 = v[2];
+    st->pbar = v[2] / (double)s.n_fluid;
     st->it = 0;
     st->zero_rhs = bn == 0.0;
     st->done = (bn == 0.0) || (rn <= ctl.rtol * bn);
@@ -853,11 +835,49 @@ __global__ void __launch_bounds__(BLOCK) k_norm_fin(const Slot *slots) {
   if (threadIdx.x == 0) s.st->E = v[0] / (v[1] + 1e-20);
 }
 
-// Conjugate gradient, pass 1 of iteration it (0-based): for it > 0, sum the
-// previous pass 2's <r,r>, <r,z>, apply the convergence test and form beta;
-// then d = z + beta d_old (d = z when it = 0), q = M d and <d, q>.
+// Conjugate gradient in the single-reduction form of Chronopoulos and Gear
+// (1989), Jacobi preconditioner u = D^-1 r, w = A u, s = A p:
+//   p_i = u_i + beta_i p_{i-1},  s_i = w_i + beta_i s_{i-1},
+//   x_{i+1} = x_i + alpha_i p_i,  r_{i+1} = r_i - alpha_i s_i,
+//   gamma = <r,u>, delta = <w,u>, beta_{i+1} = gamma_{i+1} / gamma_i,
+//   alpha_{i+1} = gamma_{i+1} / (delta_{i+1} - beta_{i+1} gamma_{i+1} / alpha_i).
+// Equal to the Hestenes-Stiefel recurrences in exact arithmetic; one launch
+// and one reduction (<r,u>, <w,u>, <r,r>) per iteration.
+
+// w_0 = A D^-1 r_0 and the first reduction
 template <typename R>
-__global__ void __launch_bounds__(BLOCK) k_pcg1(const Slot *slots, const int2 *btab, int it) {
+__global__ void __launch_bounds__(BLOCK) k_cg_init(const Slot *slots, const int2 *btab) {
+  using T = R;
+  Block B = block_of(slots, btab);
+  const Slot &s = *B.s;
+  const SlotCtl &ctl = *B.ctl;
+  if (!ctl.active || B.st->done) return;
+  const R *rAU = (const R *)s.rAU;
+  const T *r = (const T *)s.cr[0], *invD = (const T *)s.invD;
+  T *w = (T *)s.cw[0];
+  double red[3] = {0.0, 0.0, 0.0};   // <r,u>, <w,u>, <r,r>
+  for_cells(s, B.lb, [&](const Cell &c) {
+    uint8_t fl = s.flags[c.P];
+    if (fl & 0x40) {
+      w[c.P] = (T)0;
+      return;
+    }
+    auto uv = [&](int64_t x) -> T { return invD[x] * r[x]; };
+    T u = uv(c.P);
+    T ww = matvec_row<T, R>(s, rAU, c, fl, uv);
+    w[c.P] = ww;
+    T rr = r[c.P];
+    red[0] = red[0] + (double)(rr * u);
+    red[1] = red[1] + (double)(ww * u);
+    red[2] = red[2] + (double)(rr * rr);
+  });
+  put_partials<0u>(s, B.lb, CH_CG, red);
+}
+
+// iteration it (0-based): scalars from the previous reduction, convergence
+// test (it > 0), vector updates, w_{it+1} = A D^-1 r_{it+1}, next reduction
+template <typename R>
+__global__ void __launch_bounds__(BLOCK) k_cg(const Slot *slots, const int2 *btab, int it) {
   using T = R;
   Block B = block_of(slots, btab);
   const Slot &s = *B.s;
@@ -865,13 +885,14 @@ __global__ void __launch_bounds__(BLOCK) k_pcg1(const Slot *slots, const int2 *b
   if (!ctl.active || B.st->done) return;
   SlotState *st = B.st;
   const bool mixed = s.precision != 0;
-  double rz_cur, beta = 0.0;
+  double v[3];
+  get_totals<0u>(s, CH_CG, v);
+  const double gam = v[0], del = v[1];
+  double alpha, beta = 0.0;
   if (it == 0) {
-    rz_cur = st->rz0;
+    alpha = gam / del;
   } else {
-    double v[2];
-    get_totals<0u>(s, CH_CG2, v);
-    double rn = sqrt(v[0]);
+    double rn = sqrt(v[2]);
     double rtol = mixed ? ctl.rtol_inner : ctl.rtol;
     bool conv = rn <= rtol * st->bn;
     bool cap = !conv && it >= ctl.max_it;
@@ -884,73 +905,54 @@ __global__ void __launch_bounds__(BLOCK) k_pcg1(const Slot *slots, const int2 *b
       }
       return;
     }
-    rz_cur = v[1];
-    beta = rz_cur / st->rzbuf[(it - 1) & 1];
+    beta = gam / st->gam[(it - 1) & 1];
+    alpha = gam / (del - beta * gam / st->alp[(it - 1) & 1]);
     if (B.lb == 0 && threadIdx.x == 0) st->rn = rn;
   }
-  if (B.lb == 0 && threadIdx.x == 0) st->rzbuf[it & 1] = rz_cur;
-  const bool first = it == 0;
-  const T tb = (T)beta;
-  const R *rAU = (const R *)s.rAU;
-  const T *z = (const T *)s.z;
-  const T *dold = (const T *)((it & 1) ? s.d1 : s.d0);
-  T *dnew = (T *)((it & 1) ? s.d0 : s.d1);
-  T *q = (T *)s.q;
-  double red[1] = {0.0};
-  for_cells(s, B.lb, [&](const Cell &c) {
-    uint8_t fl = s.flags[c.P];
-    if (fl & 0x40) {
-      dnew[c.P] = (T)0;
-      q[c.P] = (T)0;
-      return;
-    }
-    auto dv = [&](int64_t x) -> T { return first ? z[x] : z[x] + tb * dold[x]; };
-    T dP = dv(c.P);
-    T qq = matvec_row<T, R>(s, rAU, c, fl, dv);
-    dnew[c.P] = dP;
-    q[c.P] = qq;
-    red[0] = red[0] + (double)(dP * qq);
-  });
-  put_partials<0u>(s, B.lb, CH_CG1, red);
-}
-
-// pass 2: alpha = <r,z>/<d,q>; x += alpha d, r -= alpha q, z = D^-1 r;
-// partial <r,r>, <r,z> for the next pass 1
-template <typename R>
-__global__ void __launch_bounds__(BLOCK) k_pcg2(const Slot *slots, const int2 *btab, int it) {
-  using T = R;
-  Block B = block_of(slots, btab);
-  const Slot &s = *B.s;
-  const SlotCtl &ctl = *B.ctl;
-  if (!ctl.active || B.st->done) return;
-  SlotState *st = B.st;
-  const bool mixed = s.precision != 0;
-  double v[1];
-  get_totals<0u>(s, CH_CG1, v);
-  const double alpha = st->rzbuf[it & 1] / v[0];
   if (B.lb == 0 && threadIdx.x == 0) {
+    st->gam[it & 1] = gam;
+    st->alp[it & 1] = alpha;
     st->it = it + 1;
     st->total_it = st->total_it + 1;
   }
-  const T al = (T)alpha;
-  const T *d = (const T *)((it & 1) ? s.d0 : s.d1);
-  const T *q = (const T *)s.q, *invD = (const T *)s.invD;
-  T *r = (T *)s.r, *z = (T *)s.z;
-  T *xe = (T *)s.e;
+  const bool first = it == 0;
+  const T al = (T)alpha, be = (T)beta;
+  const R *rAU = (const R *)s.rAU;
+  const T *invD = (const T *)s.invD;
+  const T *r0 = (const T *)s.cr[it & 1], *w0 = (const T *)s.cw[it & 1], *so = (const T *)s.cs[(it + 1) & 1];
+  T *r1 = (T *)s.cr[(it + 1) & 1], *w1 = (T *)s.cw[(it + 1) & 1], *sn = (T *)s.cs[it & 1];
+  T *pv = (T *)s.cp, *xe = (T *)s.e;
   double *xp = ctl.mode ? s.p_cr : s.p_vd;
-  double red[2] = {0.0, 0.0};
+  double red[3] = {0.0, 0.0, 0.0};
   for_cells(s, B.lb, [&](const Cell &c) {
-    if (solid_at(s, c.P)) return;
-    if (mixed) xe[c.P] = xe[c.P] + al * d[c.P];
-    else xp[c.P] = xp[c.P] + (double)al * (double)d[c.P];
-    T rr = r[c.P] - al * q[c.P];
-    T zz = rr * invD[c.P];
-    r[c.P] = rr;
-    z[c.P] = zz;
-    red[0] = red[0] + (double)(rr * rr);
-    red[1] = red[1] + (double)(rr * zz);
+    uint8_t fl = s.flags[c.P];
+    if (fl & 0x40) {
+      r1[c.P] = (T)0;
+      w1[c.P] = (T)0;
+      sn[c.P] = (T)0;
+      return;
+    }
+    // s = w + beta s_old and the updated residual, at any fluid cell
+    auto s_at = [&](int64_t x) -> T { return first ? w0[x] : w0[x] + be * so[x]; };
+    auto u_new = [&](int64_t x) -> T { return invD[x] * (r0[x] - al * s_at(x)); };
+    const int64_t P = c.P;
+    T u0 = invD[P] * r0[P];
+    T pn = first ? u0 : u0 + be * pv[P];
+    T sP = s_at(P);
+    T rn = r0[P] - al * sP;
+    T un = invD[P] * rn;
+    T wn = matvec_row<T, R>(s, rAU, c, fl, u_new);
+    pv[P] = pn;
+    sn[P] = sP;
+    r1[P] = rn;
+    w1[P] = wn;
+    if (mixed) xe[P] = xe[P] + al * pn;
+    else xp[P] = xp[P] + (double)al * (double)pn;
+    red[0] = red[0] + (double)(rn * un);
+    red[1] = red[1] + (double)(wn * un);
+    red[2] = red[2] + (double)(rn * rn);
   });
-  put_partials<0u>(s, B.lb, CH_CG2, red);
+  put_partials<0u>(s, B.lb, CH_CG, red);
 }
 
 // mixed precision, outer refinement: p += e, e = 0
@@ -979,21 +981,17 @@ __global__ void __launch_bounds__(BLOCK) k_refine_res(const Slot *slots, const i
   if (!ctl.active || s.precision == 0 || B.st->zero_rhs) return;
   const R *rAU = (const R *)s.rAU;
   const double *p = ctl.mode ? s.p_cr : s.p_vd;
-  T *r = (T *)s.r, *z = (T *)s.z;
-  const T *invD = (const T *)s.invD;
-  double red[3] = {0.0, 0.0, 0.0};
+  T *r = (T *)s.cr[0];
+  double red[2] = {0.0, 0.0};
   for_cells(s, B.lb, [&](const Cell &c) {
     uint8_t fl = s.flags[c.P];
     if (fl & 0x40) return;
     double Mp = matvec_row<double, R>(s, rAU, c, fl, [&](int64_t x) { return p[x]; });
     double r64 = s.rhs[c.P] - Mp;
     T rr = (T)r64;
-    T zz = rr * invD[c.P];
     r[c.P] = rr;
-    z[c.P] = zz;
     red[0] = red[0] + r64 * r64;
     red[1] = red[1] + (double)(rr * rr);
-    red[2] = red[2] + (double)(rr * zz);
   });
   put_partials<0u>(s, B.lb, CH_REF, red);
 }
@@ -1002,14 +1000,13 @@ __global__ void __launch_bounds__(BLOCK) k_refine_fin(const Slot *slots) {
   const Slot &s = slots[blockIdx.x];
   const SlotCtl &ctl = *s.ctl;
   if (!ctl.active || s.precision == 0 || s.st->zero_rhs) return;
-  double v[3];
+  double v[2];
   get_totals<0u>(s, CH_REF, v);
   if (threadIdx.x == 0) {
     SlotState *st = s.st;
     st->rn64 = sqrt(v[0]);
     st->bn = sqrt(v[1]);
     st->rn = st->bn;
-    st->rz0 = v[2];
     st->it = 0;
     st->refine_steps = st->refine_steps + 1;
     st->done = st->rn64 <= ctl.rtol * st->bn64;
@@ -1150,16 +1147,12 @@ template <typename R> void launch_pressure_setup(const Launch &L, bool normres) 
   }
 }
 
-template <typename R> void launch_pcg_iters(const Launch &L, int it0, int n) {
-  for (int x = 0; x < n; ++x) {
-    hipLaunchKernelGGL(k_pcg1<R>, GRID(L), L.slots, L.btab, it0 + x);
-    hipLaunchKernelGGL(k_pcg2<R>, GRID(L), L.slots, L.btab, it0 + x);
-  }
+template <typename R> void launch_cg_init(const Launch &L) {
+  hipLaunchKernelGGL(k_cg_init<R>, GRID(L), L.slots, L.btab);
 }
 
-template <typename R> void launch_pcg_pass(const Launch &L, int it, int pass) {
-  if (pass == 0) hipLaunchKernelGGL(k_pcg1<R>, GRID(L), L.slots, L.btab, it);
-  else hipLaunchKernelGGL(k_pcg2<R>, GRID(L), L.slots, L.btab, it);
+template <typename R> void launch_cg_iters(const Launch &L, int it0, int n) {
+  for (int x = 0; x < n; ++x) hipLaunchKernelGGL(k_cg<R>, GRID(L), L.slots, L.btab, it0 + x);
 }
 
 template <typename R> void launch_refine(const Launch &L) {
@@ -1195,8 +1188,8 @@ void launch_state_reset(const Launch &L, int nslots) {
   template void launch_assemble<R>(const Launch &);               \
   template void launch_predictor<R>(const Launch &);              \
   template void launch_pressure_setup<R>(const Launch &, bool);   \
-  template void launch_pcg_iters<R>(const Launch &, int, int);    \
-  template void launch_pcg_pass<R>(const Launch &, int, int);     \
+  template void launch_cg_init<R>(const Launch &);                \
+  template void launch_cg_iters<R>(const Launch &, int, int);     \
   template void launch_refine<R>(const Launch &);                 \
   template void launch_correct<R>(const Launch &, int);           \
   template void launch_finalize<R>(const Launch &);               \
