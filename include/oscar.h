@@ -44,6 +44,7 @@ extern "C" {
 /* status codes */
 #define OSCAR_OK 0
 #define OSCAR_W_PCG_MAXIT 1        /* a pressure solve hit its iteration cap */
+#define OSCAR_W_REFINE_STALL 2     /* mixed precision: FP64 refinement stopped improving above pcg_rtol */
 #define OSCAR_E_ARG (-1)           /* bad argument or descriptor */
 #define OSCAR_E_WORKSPACE (-2)     /* workspace too small or misaligned */
 #define OSCAR_E_MASK (-3)          /* a fluid region cannot reach an outlet */
@@ -172,12 +173,11 @@ void oscar_destroy(oscar_ctx *ctx);
 const char *oscar_last_error(const oscar_ctx *ctx);
 
 /* Measurement hook (not part of the method): when enabled, every launch of
- * the two conjugate-gradient kernels is bracketed by HIP events on the
+ * the conjugate-gradient iteration kernel is bracketed by HIP events on the
  * context's stream.  oscar_timing(ctx, 1) resets and starts the totals,
- * oscar_timing(ctx, 0) stops.  oscar_timing_read returns the summed
- * kernel time [ms] and the launch count of kernel 0 (pass 1: search
- * direction, q = M d, <d,q>) or kernel 1 (pass 2: x, r, z updates, <r,r>,
- * <r,z>); it synchronises the stream. */
+ * oscar_timing(ctx, 0) stops.  oscar_timing_read(ctx, 0, ...) returns the
+ * summed kernel time [ms] and the launch count of that kernel (kernel 1 is
+ * reserved and reads zero); it synchronises the stream. */
 int32_t oscar_timing(oscar_ctx *ctx, int32_t enable);
 int32_t oscar_timing_read(oscar_ctx *ctx, int32_t kernel, double *total_ms, int64_t *launches);
 

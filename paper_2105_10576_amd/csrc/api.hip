@@ -64,14 +64,15 @@ void layout(const oscar_desc &D, Carver &cv, Slot *s, bool ctl_block) {
   uint64_t w = D.precision == OSCAR_MIXED ? 4 : 8;
   const int64_t nc = g.nc, d = g.d, nf = g.nft;
   s->flags = (const uint8_t *)cv.take(nc);
-  void **cell1[] = {&s->alpha, &s->alpha_old, &s->kappa, &s->aP, &s->rAU, &s->Rp, &s->Rm,
-                    &s->invD, &s->r, &s->z, &s->d0, &s->d1, &s->q, &s->e};
+  void **cell1[] = {&s->alpha, &s->alpha_old, &s->kappa, &s->aP, &s->rAU, &s->Rp, &s->Rm, &s->invD,
+                    &s->cr[0], &s->cr[1], &s->cw[0], &s->cw[1], &s->cs[0], &s->cs[1], &s->cp, &s->e};
   for (void **p : cell1) *p = cv.take(w * nc);
   void **celld[] = {&s->U_vd, &s->U_cr, &s->U_sum, &s->U, &s->grad, &s->HbyA, &s->b};
   for (void **p : celld) *p = cv.take(w * nc * d);
   s->gradU = cv.take(w * nc * d * d);
-  void **face[] = {&s->phi_vd, &s->phi_prev, &s->phi_cr, &s->nhatf, &s->Fm, &s->phiH, &s->FL, &s->Af};
+  void **face[] = {&s->phi_vd, &s->phi_prev, &s->phi_cr, &s->nhatf, &s->Fm, &s->FL, &s->Af};
   for (void **p : face) *p = cv.take(w * nf);
+  s->phiH = (double *)cv.take(8 * nf);
   double **dbl[] = {&s->p_vd, &s->p_cr, &s->p, &s->rhs, &s->Mp};
   for (double **p : dbl) *p = (double *)cv.take(8 * nc);
   s->r64 = nullptr;
@@ -187,6 +188,7 @@ struct oscar_ctx {
   int last_pcg = 0, pcg_call = 0, refine_call = 0, maxit_hits = 0;
   int pcg_pred = 32;        // predicted CG iterations of the next solve (FP64)
   int pcg_pred_inner = 16;  // same for an FP32 inner solve (mixed)
+  bool refine_stall = false;  // an outer refinement stopped short of its tolerance
   // optional per-kernel timing of the two conjugate-gradient passes
   bool timing = false;
   std::vector<hipEvent_t> ev;
@@ -236,9 +238,8 @@ static int harvest_timing(oscar_ctx *c) {
   for (size_t x = 0; x + 1 < c->ev_used; x += 2) {
     float ms = 0.f;
     HIPCHK(c, hipEventElapsedTime(&ms, c->ev[x], c->ev[x + 1]));
-    int pass = (int)((x / 2) & 1);
-    c->t_ms[pass] += ms;
-    c->t_cnt[pass] += 1;
+    c->t_ms[0] += ms;
+    c->t_cnt[0] += 1;
   }
   c->ev_used = 0;
   return OSCAR_OK;
@@ -251,29 +252,28 @@ static int read_state(oscar_ctx *c) {
   return OSCAR_OK;
 }
 
-// conjugate-gradient iterations it0 .. it0+n-1; with timing on, each pass is
-// bracketed by events
+// conjugate-gradient iterations it0 .. it0+n-1; with timing on, each launch
+// is bracketed by events
 template <typename R>
-static int enqueue_pcg(oscar_ctx *c, int it0, int n) {
+static int enqueue_cg(oscar_ctx *c, int it0, int n) {
   Launch L = c->L();
   if (!c->timing) {
-    launch_pcg_iters<R>(L, it0, n);
+    launch_cg_iters<R>(L, it0, n);
     HIPCHK(c, hipGetLastError());
     return OSCAR_OK;
   }
-  size_t need = c->ev_used + 4 * (size_t)n;
+  size_t need = c->ev_used + 2 * (size_t)n;
   while (c->ev.size() < need) {
     hipEvent_t e;
     HIPCHK(c, hipEventCreate(&e));
     c->ev.push_back(e);
   }
-  for (int x = 0; x < n; ++x)
-    for (int pass = 0; pass < 2; ++pass) {
-      HIPCHK(c, hipEventRecord(c->ev[c->ev_used++], c->stream));
-      launch_pcg_pass<R>(L, it0 + x, pass);
-      HIPCHK(c, hipGetLastError());
-      HIPCHK(c, hipEventRecord(c->ev[c->ev_used++], c->stream));
-    }
+  for (int x = 0; x < n; ++x) {
+    HIPCHK(c, hipEventRecord(c->ev[c->ev_used++], c->stream));
+    launch_cg_iters<R>(L, it0 + x, 1);
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipEventRecord(c->ev[c->ev_used++], c->stream));
+  }
   return OSCAR_OK;
 }
 
@@ -436,23 +436,27 @@ template <typename R>
 static int solve_pressure(oscar_ctx *c, int &iters) {
   int rc = read_state(c);
   if (rc) return rc;
+  c->refine_stall = false;
   int start_total = c->h_state->total_it;
   const int max_it = c->D.pcg_max_it;
-  // one CG solve: chunks of iterations from index 0 until the device flags it done
+  // one CG solve: w_0 = A D^-1 r_0, then chunks of iterations from index 0
+  // until the device flags the solve done
   auto inner = [&](int &pred) -> int {
+    launch_cg_init<R>(c->L());
+    HIPCHK(c, hipGetLastError());
     int it0 = 0;
     int chunk = pred > 2 ? pred : 2;
     while (!c->h_state->done) {
       if (it0 > max_it + 1) { c->err = "conjugate gradient did not terminate"; return OSCAR_E_HIP; }
-      int r = enqueue_pcg<R>(c, it0, chunk);
+      int r = enqueue_cg<R>(c, it0, chunk);
       if (r) return r;
       it0 += chunk;
       r = read_state(c);
       if (r) return r;
-      chunk = 16;
+      chunk = 8;
     }
     int used = c->h_state->it;
-    pred = used + 2 < 2048 ? used + 2 : 2048;
+    pred = used > 2 ? used : 2;
     return OSCAR_OK;
   };
   if (!c->mixed()) {
@@ -460,6 +464,7 @@ static int solve_pressure(oscar_ctx *c, int &iters) {
     if (rc) return rc;
   } else {
     int outer = 0;
+    double last = c->h_state->rn64;
     while (!c->h_state->done) {
       rc = inner(c->pcg_pred_inner);
       if (rc) return rc;
@@ -467,7 +472,15 @@ static int solve_pressure(oscar_ctx *c, int &iters) {
       HIPCHK(c, hipGetLastError());
       rc = read_state(c);
       if (rc) return rc;
-      if (++outer >= 60) break;
+      ++outer;
+      // stop when an outer step no longer halves the FP64 residual: the
+      // requested tolerance is below what the FP32 inner solve can deliver
+      double now = c->h_state->rn64;
+      if (!c->h_state->done && (!(now < 0.5 * last) || outer >= 60)) {
+        c->refine_stall = true;
+        break;
+      }
+      last = now;
     }
     c->refine_call += outer;
   }
@@ -489,6 +502,7 @@ static int run_correctors(oscar_ctx *c, bool cr, double &E, int &warn) {
     c->last_pcg = it;
     c->pcg_call += it;
     if (c->h_state->maxit_hit) warn = OSCAR_W_PCG_MAXIT;
+    else if (c->refine_stall && warn == OSCAR_OK) warn = OSCAR_W_REFINE_STALL;
     launch_correct<R>(L, j == c->D.n_corr - 1);
     HIPCHK(c, hipGetLastError());
   }
@@ -637,7 +651,7 @@ static int pressure_solve_t(oscar_ctx *c, int which, double dt, double rtol, int
   c->pcg_pred = saved_pred;
   c->pcg_pred_inner = saved_inner;
   if (rc) return rc;
-  int warn = c->h_state->maxit_hit ? OSCAR_W_PCG_MAXIT : OSCAR_OK;
+  int warn = c->h_state->maxit_hit ? OSCAR_W_PCG_MAXIT : (c->refine_stall ? OSCAR_W_REFINE_STALL : OSCAR_OK);
   if (iters) *iters = it;
   if (res) {
     // FP64 relative residual of the final pressure

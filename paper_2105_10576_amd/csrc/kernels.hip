@@ -341,10 +341,11 @@ __global__ void __launch_bounds__(BLOCK) k_curvature(const Slot *slots, const in
   });
 }
 
-// surface-tension face term sigma*kappa_f*(alpha_hi - alpha_lo)/h
+// surface-tension face term sigma*kappa_f*(alpha_hi - alpha_lo)/h, in FP64
+// (it is balanced against the pressure gradient on the same face)
 template <typename R>
-__device__ __forceinline__ R st_face(const Slot &s, const R *kap, const R *a, int64_t lo, int64_t hi) {
-  return ((R)s.sigma * ((R)0.5 * (kap[lo] + kap[hi]))) * ((a[hi] - a[lo]) / (R)s.h);
+__device__ __forceinline__ double st_face(const Slot &s, const R *kap, const R *a, int64_t lo, int64_t hi) {
+  return (s.sigma * (0.5 * ((double)kap[lo] + (double)kap[hi]))) * (((double)a[hi] - (double)a[lo]) / s.h);
 }
 
 // ---------------------------------------------------------------------------
@@ -682,22 +683,22 @@ __global__ void __launch_bounds__(BLOCK) k_phiH(const Slot *slots, const int2 *b
   if (!ctl.active) return;
   const int64_t nc = s.nc;
   const R *HbyA = (const R *)s.HbyA, *rAU = (const R *)s.rAU, *kap = (const R *)s.kappa, *a = (const R *)s.alpha;
-  R *phiH = (R *)s.phiH;
-  const R S = (R)s.S, ub = (R)ctl.ub;
+  double *phiH = s.phiH;
+  const double S = s.S, ub = ctl.ub;
   const int with_st = ctl.with_st;
   for_cells(s, B.lb, [&](const Cell &c) {
     for_owned_faces(s, c, [&](int e, int64_t fi, const FView &v) {
-      R ph = (R)0;
+      double ph = 0.0;
       if (v.type == F_INT) {
-        ph = ((R)0.5 * (HbyA[e * nc + v.lo] + HbyA[e * nc + v.hi])) * S;
+        ph = (0.5 * ((double)HbyA[e * nc + v.lo] + (double)HbyA[e * nc + v.hi])) * S;
         if (with_st) {
-          R rAUf = (R)0.5 * (rAU[v.lo] + rAU[v.hi]);
+          double rAUf = 0.5 * ((double)rAU[v.lo] + (double)rAU[v.hi]);
           ph = ph + (rAUf * st_face<R>(s, kap, a, v.lo, v.hi)) * S;
         }
       } else if (v.type == F_INLET) {
-        ph = -(R)v.sf * (ub * S);
+        ph = -v.sf * (ub * S);
       } else if (v.type == F_OUTLET) {
-        ph = HbyA[e * nc + v.P] * S;
+        ph = (double)HbyA[e * nc + v.P] * S;
       }
       phiH[fi] = ph;
     });
@@ -733,7 +734,8 @@ __global__ void __launch_bounds__(BLOCK) k_pressure_setup(const Slot *slots, con
   const Slot &s = *B.s;
   const SlotCtl &ctl = *B.ctl;
   if (!ctl.active) return;
-  const R *rAU = (const R *)s.rAU, *phiH = (const R *)s.phiH;
+  const R *rAU = (const R *)s.rAU;
+  const double *phiH = s.phiH;
   const double *p = ctl.mode ? s.p_cr : s.p_vd;
   const bool mixed = s.precision != 0;
   T *r = (T *)s.cr[0], *invD = (T *)s.invD, *e = (T *)s.e;
@@ -753,7 +755,7 @@ __global__ void __launch_bounds__(BLOCK) k_pressure_setup(const Slot *slots, con
     for (int f = 0; f < 2 * s.dim; ++f) {
       CFace cf = cell_face(s, fl, c.i, c.j, c.k, f);
       if (cf.type == F_NONE) continue;
-      acc = acc + ((f & 1) ? 1.0 : -1.0) * (double)phiH[cf.fi];
+      acc = acc + ((f & 1) ? 1.0 : -1.0) * phiH[cf.fi];
       if (cf.type == F_INT || cf.type == F_OUTLET) dg = dg + pcoef<T, R>(s, rAU, c.P, cf);
     }
     double rhs = -acc;
@@ -1024,46 +1026,48 @@ __global__ void __launch_bounds__(BLOCK) k_correct(const Slot *slots, const int2
   const int d = s.dim;
   const int64_t nc = s.nc;
   const double *p = ctl.mode ? s.p_cr : s.p_vd;
-  const R *phiH = (const R *)s.phiH, *rAU = (const R *)s.rAU, *HbyA = (const R *)s.HbyA;
+  const double *phiH = s.phiH;
+  const R *rAU = (const R *)s.rAU, *HbyA = (const R *)s.HbyA;
   const R *kap = (const R *)s.kappa, *a = (const R *)s.alpha;
   R *phi = (R *)(ctl.mode ? s.phi_cr : s.phi_vd);
   R *U = (R *)(ctl.mode ? s.U_cr : s.U_vd);
   R *Us = (R *)s.U_sum;
-  const R Sh = (R)s.Sh, S2h = (R)s.S2h, h = (R)s.h, hh = (R)s.hh;
+  const double Sh = s.Sh, S2h = s.S2h, h = s.h, hh = s.hh;
   const int with_st = ctl.with_st;
   bool bad = false;
   for_cells(s, B.lb, [&](const Cell &c) {
     for_owned_faces(s, c, [&](int, int64_t fi, const FView &v) {
-      R ph = phiH[fi];
+      double ph = phiH[fi];
       if (v.type == F_INT) {
-        R cf = ((R)0.5 * (rAU[v.lo] + rAU[v.hi])) * Sh;
-        ph = ph - cf * (R)(p[v.hi] - p[v.lo]);
+        double cf = (0.5 * ((double)rAU[v.lo] + (double)rAU[v.hi])) * Sh;
+        ph = ph - cf * (p[v.hi] - p[v.lo]);
       } else if (v.type == F_OUTLET) {
-        R cf = rAU[v.P] * S2h;
-        ph = ph + (R)v.sf * (cf * (R)p[v.P]);
+        double cf = (double)rAU[v.P] * S2h;
+        ph = ph + v.sf * (cf * p[v.P]);
       }
-      phi[fi] = ph;
+      phi[fi] = (R)ph;
     });
     uint8_t fl = s.flags[c.P];
     for (int cc = 0; cc < d; ++cc) {
       R u = (R)0;
       if (!(fl & 0x40)) {
-        R qv[2];
+        double qv[2];
         for (int sd = 0; sd < 2; ++sd) {
           CFace cf = cell_face(s, fl, c.i, c.j, c.k, 2 * cc + sd);
-          R qq = (R)0;
+          double qq = 0.0;
           if (cf.type == F_INT) {
             int64_t lo = sd ? c.P : cf.nb, hi = sd ? cf.nb : c.P;
-            R ff = with_st ? st_face<R>(s, kap, a, lo, hi) : (R)0;
-            qq = ff - (R)(p[hi] - p[lo]) / h;
+            double ff = with_st ? st_face<R>(s, kap, a, lo, hi) : 0.0;
+            qq = ff - (p[hi] - p[lo]) / h;
           } else if (cf.type == F_OUTLET) {
-            R pplus = sd ? (R)0 : (R)p[c.P], pminus = sd ? (R)p[c.P] : (R)0;
+            double pplus = sd ? 0.0 : p[c.P], pminus = sd ? p[c.P] : 0.0;
             qq = -(pplus - pminus) / hh;
           }
           qv[sd] = qq;
         }
-        u = HbyA[cc * nc + c.P] + rAU[c.P] * ((R)0.5 * (qv[0] + qv[1]));
-        if (!(u == u) || fabs(u) > (R)1e30) bad = true;
+        double uu = (double)HbyA[cc * nc + c.P] + (double)rAU[c.P] * (0.5 * (qv[0] + qv[1]));
+        u = (R)uu;
+        if (!(uu == uu) || fabs(uu) > 1e30) bad = true;
       }
       U[cc * nc + c.P] = u;
       if (last && ctl.mode == 1) Us[cc * nc + c.P] = Us[cc * nc + c.P] + u;

@@ -22,12 +22,12 @@ constexpr int NVAL = 4;      // values per reduction channel
 // value at part[(ch*NVAL + m)*nblocks + block]; the consumer (the next
 // kernel that needs the total, or a one-block-per-slot finaliser) sums the
 // partials of its slot in a fixed order.  No atomics, no cache flushes.
-enum : int { CH_ADV1 = 0, CH_ADV2 = 1, CH_SETUP = 2, CH_NORM = 3, CH_CG1 = 4, CH_CG2 = 5, CH_REF = 6, NCH = 7 };
+enum : int { CH_ADV1 = 0, CH_ADV2 = 1, CH_SETUP = 2, CH_NORM = 3, CH_CG = 4, CH_REF = 5, NCH = 6 };
 
 // Per-slot scalars written by one block (block 0 of a kernel, or a
 // finaliser) and read by later kernels.
 struct SlotState {
-  double bn, rn, rz0, rzbuf[2];            // conjugate gradient
+  double bn, rn, gam[2], alp[2];           // conjugate gradient (iteration-parity buffers)
   double pbar, E;                          // normalised residual
   double comax, mass0, mass1, bflux;       // transport
   double rn64, bn64;                       // refinement (mixed precision)
@@ -54,10 +54,13 @@ struct Slot {
   // fields (element type R = double in FP64 mode, float in mixed mode)
   void *alpha, *alpha_old, *U_vd, *U_cr, *U_sum, *U, *phi_vd, *phi_prev, *phi_cr;
   double *p_vd, *p_cr, *p;
-  void *kappa, *nhatf, *grad, *gradU, *Fm, *aP, *rAU, *b, *HbyA, *phiH, *FL, *Af, *Rp, *Rm;
-  double *rhs, *Mp, *r64;
-  // conjugate-gradient vectors (element type T = R)
-  void *invD, *r, *z, *d0, *d1, *q, *e;
+  void *kappa, *nhatf, *grad, *gradU, *Fm, *aP, *rAU, *b, *HbyA, *FL, *Af, *Rp, *Rm;
+  // balanced-force face sums (pressure gradient against surface tension)
+  // are formed in FP64 in both modes: predicted flux, right-hand side
+  double *phiH, *rhs, *Mp, *r64;
+  // conjugate-gradient vectors (element type T = R): residual r, w = A M^-1 r
+  // and s = A p in ping-pong pairs, search direction p, FP32 correction e
+  void *invD, *cr[2], *cw[2], *cs[2], *cp, *e;
   double *part;                 // NCH * NVAL * nblocks reduction partials
   SlotState *st;
   SlotCtl *ctl;
@@ -85,8 +88,8 @@ template <typename R> void launch_advect(const Launch &L);
 template <typename R> void launch_assemble(const Launch &L);
 template <typename R> void launch_predictor(const Launch &L);
 template <typename R> void launch_pressure_setup(const Launch &L, bool normres);
-template <typename R> void launch_pcg_iters(const Launch &L, int it0, int n);
-template <typename R> void launch_pcg_pass(const Launch &L, int it, int pass);
+template <typename R> void launch_cg_init(const Launch &L);
+template <typename R> void launch_cg_iters(const Launch &L, int it0, int n);
 template <typename R> void launch_refine(const Launch &L);
 template <typename R> void launch_correct(const Launch &L, int last);
 template <typename R> void launch_finalize(const Launch &L);

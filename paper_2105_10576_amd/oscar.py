@@ -12,7 +12,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboscar.so")
 
-OK, W_PCG_MAXIT = 0, 1
+OK, W_PCG_MAXIT, W_REFINE_STALL = 0, 1, 2
 E_ARG, E_WORKSPACE, E_MASK, E_UNSTABLE, E_NONFINITE, E_HIP, E_CAPACITY = -1, -2, -3, -4, -5, -6, -7
 FP64, MIXED = 0, 1
 FIELDS = dict(alpha=0, U=1, p=2, U_vd=3, p_vd=4, U_cr=5, p_cr=6, phi_vd=7, phi_vd_prev=8, phi_cr=9,
@@ -160,7 +160,7 @@ class Oscar:
         except Exception:
             pass
 
-    def _check(self, rc, allow=(OK, W_PCG_MAXIT)):
+    def _check(self, rc, allow=(OK, W_PCG_MAXIT, W_REFINE_STALL)):
         if rc not in allow:
             raise OscarError(rc, lib().oscar_last_error(self.ctx).decode())
         return rc

@@ -1,0 +1,105 @@
+"""Host-side checks of the C ABI (no GPU): the shared library loads, exports
+every function include/oscar.h declares, and rejects bad descriptors and
+masks before touching a device."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2105_10576_amd import cases
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _header_functions():
+    txt = open(os.path.join(ROOT, "include", "oscar.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(oscar_[a-z_0-9]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_function():
+    from paper_2105_10576_amd import oscar
+    lib = oscar.lib()
+    names = _header_functions()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(lib, n), n
+        assert n in oscar.EXPORTS, n
+
+
+def _desc(case, precision=0):
+    from paper_2105_10576_amd import oscar
+    return oscar.make_desc(case, precision)
+
+
+def _size(d):
+    from paper_2105_10576_amd import oscar
+    n = C.c_uint64(0)
+    rc = oscar.lib().oscar_workspace_size(C.byref(d), C.byref(n))
+    return rc, n.value
+
+
+def test_workspace_size_scales_with_grid_and_precision():
+    c1 = cases.channel_bubble(nx=64, ny=16)
+    c2 = cases.channel_bubble(nx=128, ny=32)
+    d1, k1 = _desc(c1)
+    d2, k2 = _desc(c2)
+    d3, k3 = _desc(c2, precision=1)
+    (r1, n1), (r2, n2), (r3, n3) = _size(d1), _size(d2), _size(d3)
+    assert r1 == r2 == r3 == 0
+    assert 3.5 < n2 / n1 < 4.5
+    assert n3 < n2
+
+
+@pytest.mark.parametrize("field,value", [("dim", 4), ("nx", 0), ("h", -1.0), ("rho1", 0.0), ("mu2", -1.0),
+                                         ("sigma", -0.1), ("n_corr", 0), ("pcg_rtol", 0.0), ("precision", 7)])
+def test_bad_descriptor_rejected(field, value):
+    from paper_2105_10576_amd import oscar
+    c = cases.channel_bubble(nx=32, ny=8)
+    c[field] = value
+    d, keep = _desc(c, precision=c.get("precision", 0) if field == "precision" else 0)
+    rc, _ = _size(d)
+    assert rc == oscar.E_ARG
+    assert len(oscar.lib().oscar_last_error(None)) > 0
+
+
+def test_isolated_pocket_and_workspace_errors_before_any_device_call():
+    """An enclosed fluid pocket (no path to an outlet) is OSCAR_E_MASK; a too
+    small or misaligned workspace is OSCAR_E_WORKSPACE.  Both are decided on
+    the host before the workspace is touched."""
+    from paper_2105_10576_amd import oscar
+    L = oscar.lib()
+    c = cases.channel_bubble(nx=32, ny=8)
+    m = c["mask"].reshape(8, 32).copy()
+    m[2:6, 10] = 1
+    m[2:6, 14] = 1
+    m[2, 10:15] = 1
+    m[5, 10:15] = 1          # a closed box of solid around cells (11..13, 3..4)
+    c["mask"] = m.reshape(-1)
+    d, keep = _desc(c)
+    rc, need = _size(d)
+    assert rc == 0
+    ctx = C.c_void_p(None)
+    fake = C.c_void_p(1 << 30)   # aligned, never dereferenced before validation
+    rc = L.oscar_create(C.byref(d), fake, need, None, C.byref(ctx))
+    assert rc == oscar.E_MASK and not ctx.value
+    assert b"cannot reach an outlet" in L.oscar_last_error(None)
+    c2 = cases.channel_bubble(nx=32, ny=8)
+    d2, keep2 = _desc(c2)
+    rc, need = _size(d2)
+    assert L.oscar_create(C.byref(d2), fake, need - 256, None, C.byref(ctx)) == oscar.E_WORKSPACE
+    assert L.oscar_create(C.byref(d2), C.c_void_p((1 << 30) + 8), need, None, C.byref(ctx)) == oscar.E_WORKSPACE
+
+
+def test_null_safety_and_brackbill_helper():
+    from paper_2105_10576_amd import oscar
+    L = oscar.lib()
+    L.oscar_destroy(None)
+    assert L.oscar_viscous_step(None, 1e-6) == oscar.E_ARG
+    assert L.oscar_last_error(None)
+    # the library's Brackbill limit follows the paper's closed form
+    dtb = L.oscar_dt_brackbill(1.0, 1000.0, 1e-6, 0.07)
+    assert dtb == pytest.approx(3.3734e-8, rel=1e-4)
+    assert L.oscar_dt_brackbill(1.0, 1000.0, 4e-6, 0.07) == pytest.approx(8 * dtb, rel=1e-12)

@@ -80,6 +80,8 @@ def test_static_drop_laplace_jump(dim, n, R, tol):
     dtb = dt_brackbill(1000.0, 1000.0, c["h"], c["sigma"])
     rc, kf, E = o.capillary_relax(1e-3 * dtb, 1, 1, 0.0)
     assert rc == 0 and kf == 1
+    # from rest (p = 0) the normalised residual is sum|b| / (sum|b| + 1e-20) = 1
+    assert E[0] == pytest.approx(1.0, abs=1e-9)
     p = o.get("p_cr")
     jump = p[r < R - 6].mean() - p[r > R + 6].mean()
     expected = (dim - 1) * c["sigma"] / (R * c["h"])
