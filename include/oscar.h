@@ -181,6 +181,61 @@ const char *oscar_last_error(const oscar_ctx *ctx);
 int32_t oscar_timing(oscar_ctx *ctx, int32_t enable);
 int32_t oscar_timing_read(oscar_ctx *ctx, int32_t kernel, double *total_ms, int64_t *launches);
 
+/* ------------------------------------------------------------------------
+ * Serving engine: continuous batching of independent relaxation requests.
+ *
+ * A request is one grid (descriptor) advanced by one viscous-drag step
+ * followed by one capillary relaxation (Section 3) and fetched.  The engine
+ * owns one caller-provided device workspace: a table part (see
+ * oscar_engine_table_bytes) and a heap from which each admitted request
+ * takes exactly oscar_workspace_size bytes.  Fields stay resident on the
+ * device from admission to release.  oscar_engine_run advances every
+ * resident request by one step per tick in shared launches (a viscous step
+ * for a newly admitted request, a capillary sub-step otherwise); requests
+ * admitted between ticks join the next tick.  Each request's arithmetic
+ * depends only on its own data, so its results are bitwise the same alone
+ * and in any mix.  All engine precision is fixed at creation (OSCAR_FP64 or
+ * OSCAR_MIXED).  One host thread per engine.
+ * ------------------------------------------------------------------------ */
+typedef struct oscar_engine oscar_engine;
+
+/* Bytes of the table part of an engine workspace for max_slots requests. */
+int32_t oscar_engine_table_bytes(int32_t max_slots, uint64_t *bytes);
+
+/* dev_workspace: caller-owned, 256-byte aligned, >= table bytes; the rest is
+ * the request heap.  OSCAR_E_WORKSPACE if too small or misaligned. */
+int32_t oscar_engine_create(int32_t max_slots, int32_t precision, void *dev_workspace, uint64_t bytes,
+                            void *hip_stream, oscar_engine **out);
+
+/* Admit a request if a slot is free and its footprint fits a free heap
+ * region (else OSCAR_E_CAPACITY, nothing changed).  The descriptor is
+ * validated as in oscar_create (its precision must equal the engine's);
+ * dt_vd, n_sub, max_iters, tol as in oscar_capillary_relax.  Host arrays are
+ * read during the call only.  *slot receives the slot index. */
+int32_t oscar_engine_admit(oscar_engine *eng, const oscar_desc *desc, double dt_vd, int32_t n_sub,
+                           int32_t max_iters, double tol, int32_t *slot);
+
+/* Run `ticks` ticks (returns at once when nothing is resident). */
+int32_t oscar_engine_run(oscar_engine *eng, int32_t ticks);
+
+/* Slots whose request has finished (up to cap), and the number still running. */
+int32_t oscar_engine_poll(const oscar_engine *eng, int32_t *done_slots, int32_t cap, int32_t *n_done,
+                          int32_t *n_active);
+
+/* Copy a finished request's alpha (cells), p = p_vd + p_cr (cells) and
+ * U = U_vd + (1/N) sum u_cr (dim*cells) to host arrays (any may be NULL),
+ * with its completed sub-steps k_f and its status (OSCAR_* of the request). */
+int32_t oscar_engine_fetch(oscar_engine *eng, int32_t slot, double *alpha, double *p, double *U, int32_t *k_f,
+                           int32_t *status);
+
+/* Free a slot and its heap region (a running request is cancelled). */
+int32_t oscar_engine_release(oscar_engine *eng, int32_t slot);
+
+int32_t oscar_engine_free_bytes(const oscar_engine *eng, uint64_t *largest_region, int32_t *free_slots);
+int32_t oscar_engine_stats(const oscar_engine *eng, int64_t *ticks, int64_t *cg_iters);
+void oscar_engine_destroy(oscar_engine *eng);   /* NULL-safe; does not free the workspace */
+const char *oscar_engine_last_error(const oscar_engine *eng);
+
 /* Brackbill capillary time-step limit sqrt(rho_bar h^3 / (2 pi sigma)),
  * rho_bar = (rho1 + rho2)/2 (Section 2.2). */
 double oscar_dt_brackbill(double rho1, double rho2, double h, double sigma);

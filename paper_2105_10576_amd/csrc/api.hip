@@ -12,6 +12,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -805,5 +806,543 @@ extern "C" int32_t oscar_timing_read(oscar_ctx *c, int32_t kernel, double *total
   }
   if (total_ms) *total_ms = c->t_ms[kernel];
   if (launches) *launches = c->t_cnt[kernel];
+  return OSCAR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Serving engine: continuous batching of independent OSCAR requests.
+//
+// A request (descriptor + dt_vd, N, max_iters, tol) is admitted into a free
+// slot when its workspace footprint fits a free region of the engine's
+// workspace; its fields stay resident until released.  Each tick advances
+// every resident request by one step in lockstep launches: a viscous step
+// for a new request, a capillary sub-step otherwise.  Conjugate-gradient
+// convergence, refinement and the E_k stop rule are per slot; a request that
+// finishes is finalised (U, p) and waits for fetch/release while the others
+// keep running.  Every per-slot quantity depends only on that slot's data and
+// size, so a request's results are the same alone and in any mix.
+// ---------------------------------------------------------------------------
+
+namespace {
+
+enum { ES_FREE = 0, ES_VD = 1, ES_CR = 2, ES_DONE = 3 };
+
+struct EngSlot {
+  int state = ES_FREE;
+  oscar_desc D;
+  Dims g;
+  Slot s;
+  uint64_t off = 0, bytes = 0;
+  double dt_vd = 0.0, tol = 0.0;
+  int n_sub = 1, max_iters = 1, k = 0, k_f = 0, status = OSCAR_OK;
+  double last_E = 0.0;
+  int64_t n_fluid = 0;
+  int pred = 32, pred_inner = 16;
+};
+
+struct Region {
+  uint64_t off, bytes;
+};
+
+}  // namespace
+
+struct oscar_engine {
+  int max_slots = 0, precision = OSCAR_FP64;
+  char *ws = nullptr;
+  uint64_t bytes = 0, heap_off = 0;
+  hipStream_t stream = nullptr;
+  Slot *d_slots = nullptr;
+  int2 *d_btab = nullptr, *d_btab2 = nullptr;
+  SlotState *d_states = nullptr;   // gathered copy of the slots' states
+  int btab_cap = 0;
+  SlotState *h_states = nullptr;
+  std::vector<EngSlot> slots;
+  std::vector<Region> free_list;
+  std::vector<int2> bt, bt2;
+  std::string err = "no error";
+  int64_t ticks = 0, cg_iters = 0;
+};
+
+static int eng_fail(oscar_engine *e, hipError_t x, const char *what) {
+  char buf[256];
+  snprintf(buf, sizeof buf, "%s: %s", what, hipGetErrorString(x));
+  if (e) e->err = buf;
+  g_err = buf;
+  return OSCAR_E_HIP;
+}
+
+#define EHIP(e, x)                                        \
+  do {                                                    \
+    hipError_t _x = (x);                                  \
+    if (_x != hipSuccess) return eng_fail((e), _x, #x);   \
+  } while (0)
+
+static uint64_t eng_table_bytes(int max_slots, int btab_cap) {
+  return up(sizeof(Slot) * (uint64_t)max_slots) + 2 * up(sizeof(int2) * (uint64_t)btab_cap) +
+         up(sizeof(SlotState) * (uint64_t)max_slots);
+}
+
+extern "C" int32_t oscar_engine_table_bytes(int32_t max_slots, uint64_t *bytes) {
+  if (max_slots < 1 || max_slots > 4096 || !bytes) { g_err = "need 1 <= max_slots <= 4096"; return OSCAR_E_ARG; }
+  *bytes = eng_table_bytes(max_slots, max_slots * blocks_for((int64_t)1 << 40));
+  return OSCAR_OK;
+}
+
+extern "C" int32_t oscar_engine_create(int32_t max_slots, int32_t precision, void *ws, uint64_t bytes,
+                                       void *hip_stream, oscar_engine **out) {
+  if (!out) { g_err = "out is NULL"; return OSCAR_E_ARG; }
+  *out = nullptr;
+  if (max_slots < 1 || max_slots > 4096 || (precision != OSCAR_FP64 && precision != OSCAR_MIXED)) {
+    g_err = "need 1 <= max_slots <= 4096 and a known precision";
+    return OSCAR_E_ARG;
+  }
+  const int btab_cap = max_slots * blocks_for((int64_t)1 << 40);
+  uint64_t tb = eng_table_bytes(max_slots, btab_cap);
+  if (!ws || ((uintptr_t)ws % ALIGN) != 0 || bytes < tb) {
+    g_err = "engine workspace too small or not 256-byte aligned";
+    return OSCAR_E_WORKSPACE;
+  }
+  oscar_engine *e = new oscar_engine();
+  e->max_slots = max_slots;
+  e->precision = precision;
+  e->ws = (char *)ws;
+  e->bytes = bytes;
+  e->stream = (hipStream_t)hip_stream;
+  e->btab_cap = btab_cap;
+  e->d_slots = (Slot *)ws;
+  e->d_btab = (int2 *)(e->ws + up(sizeof(Slot) * (uint64_t)max_slots));
+  e->d_btab2 = (int2 *)((char *)e->d_btab + up(sizeof(int2) * (uint64_t)btab_cap));
+  e->d_states = (SlotState *)((char *)e->d_btab2 + up(sizeof(int2) * (uint64_t)btab_cap));
+  e->heap_off = tb;
+  e->slots.resize(max_slots);
+  e->free_list.push_back(Region{tb, bytes - tb});
+  hipError_t x = hipHostMalloc((void **)&e->h_states, sizeof(SlotState) * max_slots, hipHostMallocDefault);
+  if (x != hipSuccess) { eng_fail(nullptr, x, "hipHostMalloc"); delete e; return OSCAR_E_HIP; }
+  // every table entry starts inactive: point each slot's ctl at a zeroed word
+  x = hipMemsetAsync(ws, 0, tb, e->stream);
+  if (x == hipSuccess) x = hipStreamSynchronize(e->stream);
+  if (x != hipSuccess) { eng_fail(nullptr, x, "engine init"); (void)hipHostFree(e->h_states); delete e; return OSCAR_E_HIP; }
+  *out = e;
+  return OSCAR_OK;
+}
+
+extern "C" void oscar_engine_destroy(oscar_engine *e) {
+  if (!e) return;
+  if (e->stream) (void)hipStreamSynchronize(e->stream);
+  if (e->h_states) (void)hipHostFree(e->h_states);
+  delete e;
+}
+
+extern "C" const char *oscar_engine_last_error(const oscar_engine *e) { return e ? e->err.c_str() : g_err.c_str(); }
+
+static bool eng_alloc(oscar_engine *e, uint64_t need, uint64_t &off) {
+  for (size_t i = 0; i < e->free_list.size(); ++i) {
+    Region &r = e->free_list[i];
+    if (r.bytes >= need) {
+      off = r.off;
+      r.off += need;
+      r.bytes -= need;
+      if (r.bytes == 0) e->free_list.erase(e->free_list.begin() + i);
+      return true;
+    }
+  }
+  return false;
+}
+
+static void eng_free(oscar_engine *e, uint64_t off, uint64_t bytes) {
+  e->free_list.push_back(Region{off, bytes});
+  std::sort(e->free_list.begin(), e->free_list.end(), [](const Region &a, const Region &b) { return a.off < b.off; });
+  std::vector<Region> merged;
+  for (const Region &r : e->free_list) {
+    if (!merged.empty() && merged.back().off + merged.back().bytes == r.off) merged.back().bytes += r.bytes;
+    else merged.push_back(r);
+  }
+  e->free_list.swap(merged);
+}
+
+extern "C" int32_t oscar_engine_free_bytes(const oscar_engine *e, uint64_t *largest, int32_t *free_slots) {
+  if (!e) return OSCAR_E_ARG;
+  uint64_t m = 0;
+  for (const Region &r : e->free_list) m = r.bytes > m ? r.bytes : m;
+  int f = 0;
+  for (const EngSlot &s : e->slots) f += s.state == ES_FREE;
+  if (largest) *largest = m;
+  if (free_slots) *free_slots = f;
+  return OSCAR_OK;
+}
+
+extern "C" int32_t oscar_engine_admit(oscar_engine *e, const oscar_desc *desc, double dt_vd, int32_t n_sub,
+                                      int32_t max_iters, double tol, int32_t *slot_out) {
+  if (!e) { g_err = "engine is NULL"; return OSCAR_E_ARG; }
+  std::string why;
+  int rc = check_desc(desc, why);
+  if (rc) { e->err = why; return rc; }
+  if (desc->precision != e->precision) { e->err = "descriptor precision differs from the engine's"; return OSCAR_E_ARG; }
+  if (!desc->mask || !desc->alpha0) { e->err = "mask and alpha0 must be non-NULL"; return OSCAR_E_ARG; }
+  if (!(dt_vd > 0.0) || n_sub < 1 || max_iters < 1 || max_iters > n_sub || !(tol >= 0.0)) {
+    e->err = "need dt_vd > 0, n_sub >= 1, 1 <= max_iters <= n_sub, tol >= 0";
+    return OSCAR_E_ARG;
+  }
+  double dt = dt_vd / (double)n_sub;
+  if (desc->sigma > 0.0 && !(dt < oscar_dt_brackbill(desc->rho1, desc->rho2, desc->h, desc->sigma))) {
+    e->err = "dt_vd/n_sub is not below the Brackbill limit";
+    return OSCAR_E_UNSTABLE;
+  }
+  std::vector<uint8_t> fl;
+  int64_t n_fluid = 0;
+  rc = build_flags(*desc, fl, n_fluid, why);
+  if (rc) { e->err = why; return rc; }
+  int idx = -1;
+  for (int i = 0; i < e->max_slots; ++i)
+    if (e->slots[i].state == ES_FREE) { idx = i; break; }
+  Carver probe;
+  Slot tmp;
+  layout(*desc, probe, &tmp, true);
+  uint64_t need = probe.off, off = 0;
+  if (idx < 0 || !eng_alloc(e, need, off)) { e->err = "no free slot or workspace region"; return OSCAR_E_CAPACITY; }
+  EngSlot &es = e->slots[idx];
+  es = EngSlot();
+  es.D = *desc;
+  es.D.mask = nullptr;
+  es.D.alpha0 = nullptr;
+  es.g = dims_of(*desc);
+  es.off = off;
+  es.bytes = need;
+  es.dt_vd = dt_vd;
+  es.n_sub = n_sub;
+  es.max_iters = max_iters;
+  es.tol = tol;
+  es.n_fluid = n_fluid;
+  Carver cv;
+  cv.base = e->ws + off;
+  Slot &s = es.s;
+  memset(&s, 0, sizeof s);
+  layout(*desc, cv, &s, true);
+  s.dim = desc->dim;
+  s.nx = desc->nx;
+  s.ny = desc->ny;
+  s.nz = desc->nz;
+  s.nc = es.g.nc;
+  s.nf0 = es.g.nf0;
+  s.nf1 = es.g.nf1;
+  s.nf2 = es.g.nf2;
+  s.nftot = es.g.nft;
+  s.nblocks = es.g.nblocks;
+  s.n_fluid = (int32_t)n_fluid;
+  s.precision = desc->precision;
+  for (int f = 0; f < 6; ++f)
+    s.bcf[f] = desc->bc[f] == OSCAR_BC_INLET ? F_INLET : (desc->bc[f] == OSCAR_BC_OUTLET ? F_OUTLET : F_WALL);
+  const double h = desc->h;
+  s.h = h;
+  s.V = desc->dim == 3 ? h * h * h : h * h;
+  s.S = desc->dim == 3 ? h * h : h;
+  s.Sh = s.S / h;
+  s.hh = 0.5 * h;
+  s.S2h = s.S / s.hh;
+  s.delta = 1e-8 / h;
+  const double pi = 3.14159265358979323846;
+  double comp = (90.0 - desc->theta_deg) * (pi / 180.0);
+  s.cos_t = std::sin(comp);
+  s.sin_t = std::cos(comp);
+  s.rho1 = desc->rho1;
+  s.mu1 = desc->mu1;
+  s.rho2 = desc->rho2;
+  s.mu2 = desc->mu2;
+  s.sigma = desc->sigma;
+  s.u_inlet = desc->u_inlet;
+  const int64_t nc = es.g.nc;
+  hipError_t x = hipMemsetAsync(e->ws + off, 0, need, e->stream);
+  if (x == hipSuccess) x = hipMemcpyAsync((void *)s.flags, fl.data(), nc, hipMemcpyHostToDevice, e->stream);
+  std::vector<double> a64;
+  std::vector<float> a32;
+  if (x == hipSuccess) {
+    if (e->precision == OSCAR_MIXED) {
+      a32.resize(nc);
+      for (int64_t P = 0; P < nc; ++P) a32[P] = desc->mask[P] ? 0.f : (float)desc->alpha0[P];
+      x = hipMemcpyAsync(s.alpha, a32.data(), 4 * nc, hipMemcpyHostToDevice, e->stream);
+    } else {
+      a64.resize(nc);
+      for (int64_t P = 0; P < nc; ++P) a64[P] = desc->mask[P] ? 0.0 : desc->alpha0[P];
+      x = hipMemcpyAsync(s.alpha, a64.data(), 8 * nc, hipMemcpyHostToDevice, e->stream);
+    }
+  }
+  if (x == hipSuccess) x = hipMemcpyAsync(e->d_slots + idx, &s, sizeof(Slot), hipMemcpyHostToDevice, e->stream);
+  if (x == hipSuccess) x = hipStreamSynchronize(e->stream);
+  if (x != hipSuccess) {
+    eng_free(e, off, need);
+    es.state = ES_FREE;
+    return eng_fail(e, x, "admit upload");
+  }
+  es.state = ES_VD;
+  if (slot_out) *slot_out = idx;
+  return OSCAR_OK;
+}
+
+static SlotCtl eng_ctl(const EngSlot &es, int mode, int precision) {
+  SlotCtl k;
+  memset(&k, 0, sizeof k);
+  k.active = 1;
+  k.mode = mode;
+  k.dt = mode ? es.dt_vd / (double)es.n_sub : es.dt_vd;
+  k.ub = mode ? 0.0 : es.D.u_inlet;
+  k.with_st = mode;
+  k.rtol = es.D.pcg_rtol;
+  k.rtol_inner = 1e-3;
+  k.max_it = es.D.pcg_max_it;
+  k.n_sub = es.n_sub;
+  k.substep = es.k;
+  k.tol = es.tol;
+  (void)precision;
+  return k;
+}
+
+static int eng_set_ctl(oscar_engine *e, const std::vector<std::pair<int, SlotCtl>> &upd) {
+  Launch L;
+  L.slots = e->d_slots;
+  L.btab = e->d_btab;
+  L.nblocks = 0;
+  L.nslots = e->max_slots;
+  L.stream = e->stream;
+  for (size_t i = 0; i < upd.size(); i += CtlUpdate::MAXN) {
+    CtlUpdate u;
+    memset(&u, 0, sizeof u);
+    u.n = 0;
+    for (size_t j = i; j < upd.size() && u.n < CtlUpdate::MAXN; ++j) {
+      u.slot[u.n] = upd[j].first;
+      u.ctl[u.n] = upd[j].second;
+      u.n++;
+    }
+    launch_ctl_update(L, u);
+    EHIP(e, hipGetLastError());
+  }
+  return OSCAR_OK;
+}
+
+static int eng_read_states(oscar_engine *e) {
+  Launch L;
+  L.slots = e->d_slots;
+  L.btab = e->d_btab;
+  L.nblocks = 0;
+  L.nslots = e->max_slots;
+  L.stream = e->stream;
+  launch_gather_states(L, e->max_slots, e->d_states);
+  EHIP(e, hipGetLastError());
+  EHIP(e, hipMemcpyAsync(e->h_states, e->d_states, sizeof(SlotState) * e->max_slots, hipMemcpyDeviceToHost, e->stream));
+  EHIP(e, hipStreamSynchronize(e->stream));
+  return OSCAR_OK;
+}
+
+template <typename R>
+static int eng_tick(oscar_engine *e) {
+  // active slots and their block table
+  std::vector<int> act;
+  e->bt.clear();
+  for (int i = 0; i < e->max_slots; ++i) {
+    EngSlot &es = e->slots[i];
+    if (es.state != ES_VD && es.state != ES_CR) continue;
+    act.push_back(i);
+    for (int b = 0; b < es.g.nblocks; ++b) e->bt.push_back(make_int2(i, b));
+  }
+  if (act.empty()) return OSCAR_OK;
+  if ((int)e->bt.size() > e->btab_cap) { e->err = "block table overflow"; return OSCAR_E_CAPACITY; }
+  EHIP(e, hipMemcpyAsync(e->d_btab, e->bt.data(), sizeof(int2) * e->bt.size(), hipMemcpyHostToDevice, e->stream));
+  std::vector<std::pair<int, SlotCtl>> upd;
+  for (int i : act) upd.push_back({i, eng_ctl(e->slots[i], e->slots[i].state == ES_CR ? 1 : 0, e->precision)});
+  int rc = eng_set_ctl(e, upd);
+  if (rc) return rc;
+  Launch L;
+  L.slots = e->d_slots;
+  L.btab = e->d_btab;
+  L.nblocks = (int)e->bt.size();
+  L.nslots = e->max_slots;
+  L.stream = e->stream;
+  launch_state_reset(L, e->max_slots);
+  launch_zero_usum<R>(L);
+  launch_copy_phi_prev<R>(L);
+  launch_normals<R>(L, false);
+  launch_advect<R>(L);
+  launch_normals<R>(L, true);
+  launch_assemble<R>(L);
+  EHIP(e, hipGetLastError());
+  const bool mixed = e->precision == OSCAR_MIXED;
+  const int n_corr = e->slots[act[0]].D.n_corr;
+  std::vector<double> E(e->max_slots, 0.0);
+  for (int j = 0; j < n_corr; ++j) {
+    launch_predictor<R>(L);
+    launch_pressure_setup<R>(L, j == 0);
+    EHIP(e, hipGetLastError());
+    rc = eng_read_states(e);
+    if (rc) return rc;
+    auto all_done = [&]() {
+      for (int i : act)
+        if (!e->h_states[i].done) return false;
+      return true;
+    };
+    auto inner = [&]() -> int {
+      launch_cg_init<R>(L);
+      EHIP(e, hipGetLastError());
+      int it0 = 0, chunk = 2;
+      for (int i : act) {
+        int p = mixed ? e->slots[i].pred_inner : e->slots[i].pred;
+        chunk = p > chunk ? p : chunk;
+      }
+      int max_it = 0;
+      for (int i : act) max_it = e->slots[i].D.pcg_max_it > max_it ? e->slots[i].D.pcg_max_it : max_it;
+      while (!all_done()) {
+        if (it0 > max_it + 1) { e->err = "conjugate gradient did not terminate"; return OSCAR_E_HIP; }
+        launch_cg_iters<R>(L, it0, chunk);
+        EHIP(e, hipGetLastError());
+        it0 += chunk;
+        int r2 = eng_read_states(e);
+        if (r2) return r2;
+        chunk = 8;
+      }
+      for (int i : act) {
+        int used = e->h_states[i].it;
+        if (mixed) e->slots[i].pred_inner = used > 2 ? used : 2;
+        else e->slots[i].pred = used > 2 ? used : 2;
+      }
+      return OSCAR_OK;
+    };
+    if (!mixed) {
+      rc = inner();
+      if (rc) return rc;
+    } else {
+      for (int outer = 0; outer < 30 && !all_done(); ++outer) {
+        rc = inner();
+        if (rc) return rc;
+        launch_refine<R>(L);
+        EHIP(e, hipGetLastError());
+        rc = eng_read_states(e);
+        if (rc) return rc;
+      }
+    }
+    if (j == 0)
+      for (int i : act) E[i] = e->h_states[i].E;
+    launch_correct<R>(L, j == n_corr - 1);
+    EHIP(e, hipGetLastError());
+  }
+  rc = eng_read_states(e);
+  if (rc) return rc;
+  // state transitions; finishing relaxations are finalised with their own table
+  e->bt2.clear();
+  std::vector<std::pair<int, SlotCtl>> off;
+  for (int i : act) {
+    EngSlot &es = e->slots[i];
+    const SlotState &st = e->h_states[i];
+    e->cg_iters += st.total_it;
+    if (st.nonfinite) es.status = OSCAR_E_NONFINITE;
+    else if (st.unstable && es.status == OSCAR_OK) es.status = OSCAR_E_UNSTABLE;
+    else if (st.maxit_hit && es.status == OSCAR_OK) es.status = OSCAR_W_PCG_MAXIT;
+    if (es.state == ES_VD) {
+      es.state = ES_CR;
+      es.k = 0;
+      if (es.status < 0) {
+        es.state = ES_DONE;
+        off.push_back({i, SlotCtl()});
+      }
+      continue;
+    }
+    es.last_E = E[i];
+    bool stop = E[i] < es.tol || es.k + 1 >= es.max_iters || es.status < 0;
+    if (!stop) {
+      es.k++;
+      continue;
+    }
+    es.k_f = es.k + 1;
+    es.state = ES_DONE;
+    off.push_back({i, SlotCtl()});
+    for (int b = 0; b < es.g.nblocks; ++b) e->bt2.push_back(make_int2(i, b));
+  }
+  if (!e->bt2.empty()) {
+    EHIP(e, hipMemcpyAsync(e->d_btab2, e->bt2.data(), sizeof(int2) * e->bt2.size(), hipMemcpyHostToDevice, e->stream));
+    Launch F = L;
+    F.btab = e->d_btab2;
+    F.nblocks = (int)e->bt2.size();
+    launch_finalize<R>(F);
+    EHIP(e, hipGetLastError());
+  }
+  if (!off.empty()) {
+    rc = eng_set_ctl(e, off);
+    if (rc) return rc;
+  }
+  EHIP(e, hipStreamSynchronize(e->stream));
+  e->ticks++;
+  return OSCAR_OK;
+}
+
+extern "C" int32_t oscar_engine_run(oscar_engine *e, int32_t ticks) {
+  if (!e || ticks < 1) return OSCAR_E_ARG;
+  for (int t = 0; t < ticks; ++t) {
+    int rc = e->precision == OSCAR_MIXED ? eng_tick<float>(e) : eng_tick<double>(e);
+    if (rc) return rc;
+  }
+  return OSCAR_OK;
+}
+
+extern "C" int32_t oscar_engine_poll(const oscar_engine *e, int32_t *done_slots, int32_t cap, int32_t *n_done,
+                                     int32_t *n_active) {
+  if (!e || (!done_slots && cap > 0)) return OSCAR_E_ARG;
+  int n = 0, a = 0;
+  for (int i = 0; i < e->max_slots; ++i) {
+    int st = e->slots[i].state;
+    if (st == ES_DONE && n < cap) done_slots[n++] = i;
+    if (st == ES_VD || st == ES_CR) a++;
+  }
+  if (n_done) *n_done = n;
+  if (n_active) *n_active = a;
+  return OSCAR_OK;
+}
+
+extern "C" int32_t oscar_engine_fetch(oscar_engine *e, int32_t slot, double *alpha, double *p, double *U,
+                                      int32_t *k_f, int32_t *status) {
+  if (!e || slot < 0 || slot >= e->max_slots) return OSCAR_E_ARG;
+  EngSlot &es = e->slots[slot];
+  if (es.state != ES_DONE) { e->err = "slot has no finished request"; return OSCAR_E_ARG; }
+  const int64_t nc = es.g.nc, dn = es.g.d * es.g.nc;
+  const bool mixed = e->precision == OSCAR_MIXED;
+  auto get = [&](void *src, double *dst, int64_t len, bool dbl) -> int {
+    if (!dst) return OSCAR_OK;
+    if (dbl || !mixed) {
+      EHIP(e, hipMemcpyAsync(dst, src, 8 * len, hipMemcpyDeviceToHost, e->stream));
+      EHIP(e, hipStreamSynchronize(e->stream));
+    } else {
+      std::vector<float> t(len);
+      EHIP(e, hipMemcpyAsync(t.data(), src, 4 * len, hipMemcpyDeviceToHost, e->stream));
+      EHIP(e, hipStreamSynchronize(e->stream));
+      for (int64_t x = 0; x < len; ++x) dst[x] = t[x];
+    }
+    return OSCAR_OK;
+  };
+  int rc = get(es.s.alpha, alpha, nc, false);
+  if (!rc) rc = get(es.s.p, p, nc, true);
+  if (!rc) rc = get(es.s.U, U, dn, false);
+  if (k_f) *k_f = es.k_f;
+  if (status) *status = es.status;
+  return rc;
+}
+
+extern "C" int32_t oscar_engine_release(oscar_engine *e, int32_t slot) {
+  if (!e || slot < 0 || slot >= e->max_slots) return OSCAR_E_ARG;
+  EngSlot &es = e->slots[slot];
+  if (es.state == ES_FREE) return OSCAR_OK;
+  if (es.state == ES_VD || es.state == ES_CR) {
+    std::vector<std::pair<int, SlotCtl>> off{{slot, SlotCtl()}};
+    int rc = eng_set_ctl(e, off);
+    if (rc) return rc;
+  }
+  // clear the table entry (its pointers would reach into memory that the
+  // next admission may reuse) before the region goes back to the free list
+  EHIP(e, hipMemsetAsync(e->d_slots + slot, 0, sizeof(Slot), e->stream));
+  EHIP(e, hipStreamSynchronize(e->stream));
+  eng_free(e, es.off, es.bytes);
+  es = EngSlot();
+  return OSCAR_OK;
+}
+
+extern "C" int32_t oscar_engine_stats(const oscar_engine *e, int64_t *ticks, int64_t *cg_iters) {
+  if (!e) return OSCAR_E_ARG;
+  if (ticks) *ticks = e->ticks;
+  if (cg_iters) *cg_iters = e->cg_iters;
   return OSCAR_OK;
 }

@@ -232,11 +232,20 @@ __global__ void k_ctl_update(Slot *slots, CtlUpdate u) {
   if (t < u.n) *slots[u.slot[t]].ctl = u.ctl[t];
 }
 
+// copy every used slot's state into one array (one host read per poll)
+__global__ void k_gather_states(const Slot *slots, int nslots, SlotState *out) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nslots) return;
+  const Slot &s = slots[t];
+  if (!s.st) return;
+  out[t] = *s.st;
+}
+
 __global__ void k_state_reset(const Slot *slots, int nslots) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= nslots) return;
   const Slot &s = slots[t];
-  if (!s.ctl->active) return;
+  if (!s.ctl || !s.ctl->active) return;
   SlotState *st = s.st;
   st->nonfinite = 0;
   st->unstable = 0;
@@ -495,6 +504,7 @@ __global__ void __launch_bounds__(BLOCK) k_mules_update(const Slot *slots, const
 // one block per slot: Courant number, phase mass before/after, boundary flux
 __global__ void __launch_bounds__(BLOCK) k_transport_fin(const Slot *slots) {
   const Slot &s = slots[blockIdx.x];
+  if (!s.ctl) return;   // unused table entry
   const SlotCtl &ctl = *s.ctl;
   if (!ctl.active) return;
   double v1[2], v2[2];
@@ -777,6 +787,7 @@ __global__ void __launch_bounds__(BLOCK) k_pressure_setup(const Slot *slots, con
 // one block per slot: norms of the pressure equation, initial convergence test
 __global__ void __launch_bounds__(BLOCK) k_setup_fin(const Slot *slots) {
   const Slot &s = slots[blockIdx.x];
+  if (!s.ctl) return;   // unused table entry
   const SlotCtl &ctl = *s.ctl;
   if (!ctl.active) return;
   double v[3];
@@ -830,6 +841,7 @@ __global__ void __launch_bounds__(BLOCK) k_normres(const Slot *slots, const int2
 
 __global__ void __launch_bounds__(BLOCK) k_norm_fin(const Slot *slots) {
   const Slot &s = slots[blockIdx.x];
+  if (!s.ctl) return;   // unused table entry
   const SlotCtl &ctl = *s.ctl;
   if (!ctl.active || ctl.mode != 1) return;
   double v[2];
@@ -1000,6 +1012,7 @@ __global__ void __launch_bounds__(BLOCK) k_refine_res(const Slot *slots, const i
 
 __global__ void __launch_bounds__(BLOCK) k_refine_fin(const Slot *slots) {
   const Slot &s = slots[blockIdx.x];
+  if (!s.ctl) return;   // unused table entry
   const SlotCtl &ctl = *s.ctl;
   if (!ctl.active || s.precision == 0 || s.st->zero_rhs) return;
   double v[2];
@@ -1098,7 +1111,7 @@ template <typename R>
 __global__ void __launch_bounds__(BLOCK) k_zero_usum(const Slot *slots, const int2 *btab) {
   Block B = block_of(slots, btab);
   const Slot &s = *B.s;
-  if (!B.ctl->active || B.ctl->mode != 1) return;
+  if (!B.ctl->active || B.ctl->mode != 1 || B.ctl->substep != 0) return;
   R *Us = (R *)s.U_sum;
   for_cells(s, B.lb, [&](const Cell &c) {
     for (int cc = 0; cc < s.dim; ++cc) Us[cc * s.nc + c.P] = (R)0;
@@ -1179,6 +1192,10 @@ template <typename R> void launch_zero_usum(const Launch &L) {
 
 void launch_ctl_update(const Launch &L, const CtlUpdate &u) {
   hipLaunchKernelGGL(k_ctl_update, dim3(1), dim3(64), 0, L.stream, const_cast<Slot *>(L.slots), u);
+}
+
+void launch_gather_states(const Launch &L, int nslots, SlotState *out) {
+  hipLaunchKernelGGL(k_gather_states, dim3((nslots + 63) / 64), dim3(64), 0, L.stream, L.slots, nslots, out);
 }
 
 void launch_state_reset(const Launch &L, int nslots) {

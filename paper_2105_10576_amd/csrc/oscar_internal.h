@@ -39,7 +39,7 @@ struct SlotState {
 struct SlotCtl {
   double dt, ub, rtol, rtol_inner;
   int32_t active, mode, with_st, max_it;
-  int32_t last_corr, first_corr, n_sub, pad;
+  int32_t last_corr, substep, n_sub, pad;   // substep: index within the relaxation
   double tol;
 };
 
@@ -96,6 +96,7 @@ template <typename R> void launch_finalize(const Launch &L);
 template <typename R> void launch_zero_usum(const Launch &L);
 void launch_ctl_update(const Launch &L, const CtlUpdate &u);
 void launch_state_reset(const Launch &L, int nslots);
+void launch_gather_states(const Launch &L, int nslots, SlotState *out);
 
 // blocks per slot: ceil(cells/BLOCK), capped (grid-stride beyond the cap)
 int blocks_for(int64_t nc);

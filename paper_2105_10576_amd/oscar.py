@@ -228,3 +228,137 @@ class Oscar:
         s = Stats()
         self._check(lib().oscar_stats(self.ctx, C.byref(s)))
         return {k: getattr(s, k) for k, _ in Stats._fields_}
+
+
+ENGINE_EXPORTS = ["oscar_engine_table_bytes", "oscar_engine_create", "oscar_engine_admit", "oscar_engine_run",
+                  "oscar_engine_poll", "oscar_engine_fetch", "oscar_engine_release", "oscar_engine_free_bytes",
+                  "oscar_engine_stats", "oscar_engine_destroy", "oscar_engine_last_error"]
+EXPORTS = EXPORTS + ENGINE_EXPORTS
+
+
+def _engine_sigs(L):
+    vp, ip = C.c_void_p, C.POINTER(C.c_int32)
+    dp = C.POINTER(C.c_double)
+    L.oscar_engine_table_bytes.argtypes = [C.c_int32, C.POINTER(C.c_uint64)]
+    L.oscar_engine_create.argtypes = [C.c_int32, C.c_int32, vp, C.c_uint64, vp, C.POINTER(vp)]
+    L.oscar_engine_admit.argtypes = [vp, C.POINTER(Desc), C.c_double, C.c_int32, C.c_int32, C.c_double, ip]
+    L.oscar_engine_run.argtypes = [vp, C.c_int32]
+    L.oscar_engine_poll.argtypes = [vp, ip, C.c_int32, ip, ip]
+    L.oscar_engine_fetch.argtypes = [vp, C.c_int32, dp, dp, dp, ip, ip]
+    L.oscar_engine_release.argtypes = [vp, C.c_int32]
+    L.oscar_engine_free_bytes.argtypes = [vp, C.POINTER(C.c_uint64), ip]
+    L.oscar_engine_stats.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+    L.oscar_engine_destroy.argtypes = [vp]
+    L.oscar_engine_destroy.restype = None
+    L.oscar_engine_last_error.argtypes = [vp]
+    L.oscar_engine_last_error.restype = C.c_char_p
+    for n in ENGINE_EXPORTS:
+        if n not in ("oscar_engine_destroy", "oscar_engine_last_error"):
+            getattr(L, n).restype = C.c_int32
+
+
+def engine_table_bytes(max_slots):
+    L = lib()
+    _engine_sigs(L)
+    n = C.c_uint64(0)
+    rc = L.oscar_engine_table_bytes(int(max_slots), C.byref(n))
+    if rc != OK:
+        raise OscarError(rc, L.oscar_last_error(None).decode())
+    return n.value
+
+
+class Engine:
+    """Continuous-batching engine over one torch device workspace of
+    table bytes + heap_bytes (the HBM budget for resident requests)."""
+
+    def __init__(self, max_slots, heap_bytes, precision=FP64, device="cuda:0", stream=None):
+        import torch
+
+        L = lib()
+        _engine_sigs(L)
+        self.precision = precision
+        self.max_slots = int(max_slots)
+        self.table = engine_table_bytes(max_slots)
+        self.bytes = self.table + int(heap_bytes)
+        self.ws = torch.empty(self.bytes, dtype=torch.uint8, device=device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(torch.device(device))
+        self.h = C.c_void_p(None)
+        with torch.cuda.device(torch.device(device)):
+            rc = L.oscar_engine_create(self.max_slots, int(precision), C.c_void_p(self.ws.data_ptr()), self.bytes,
+                                       C.c_void_p(self.stream.cuda_stream), C.byref(self.h))
+        if rc != OK:
+            raise OscarError(rc, L.oscar_last_error(None).decode())
+        self.meta = {}
+
+    def close(self):
+        if getattr(self, "h", None) and self.h.value:
+            lib().oscar_engine_destroy(self.h)
+            self.h = C.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _err(self, rc):
+        raise OscarError(rc, lib().oscar_engine_last_error(self.h).decode())
+
+    def admit(self, case, dt_vd=None, n_sub=None, max_iters=None, tol=None):
+        """Admit a request; returns the slot, or None when it does not fit now."""
+        d, keep = make_desc(case, self.precision)
+        slot = C.c_int32(-1)
+        rc = lib().oscar_engine_admit(self.h, C.byref(d), float(case["dt_vd"] if dt_vd is None else dt_vd),
+                                      int(case["n_sub"] if n_sub is None else n_sub),
+                                      int(case["max_iters"] if max_iters is None else max_iters),
+                                      float(case["tol"] if tol is None else tol), C.byref(slot))
+        if rc == E_CAPACITY:
+            return None
+        if rc != OK:
+            self._err(rc)
+        self.meta[slot.value] = (int(case["nx"]) * int(case["ny"]) * int(case["nz"]), int(case["dim"]))
+        return slot.value
+
+    def run(self, ticks=1):
+        rc = lib().oscar_engine_run(self.h, int(ticks))
+        if rc != OK:
+            self._err(rc)
+
+    def poll(self):
+        buf = (C.c_int32 * self.max_slots)()
+        n = C.c_int32(0)
+        a = C.c_int32(0)
+        lib().oscar_engine_poll(self.h, buf, self.max_slots, C.byref(n), C.byref(a))
+        return [buf[i] for i in range(n.value)], a.value
+
+    def fetch(self, slot):
+        nc, dim = self.meta[slot]
+        alpha = np.empty(nc)
+        p = np.empty(nc)
+        U = np.empty(dim * nc)
+        kf = C.c_int32(0)
+        st = C.c_int32(0)
+        dp = C.POINTER(C.c_double)
+        rc = lib().oscar_engine_fetch(self.h, int(slot), alpha.ctypes.data_as(dp), p.ctypes.data_as(dp),
+                                      U.ctypes.data_as(dp), C.byref(kf), C.byref(st))
+        if rc != OK:
+            self._err(rc)
+        return dict(alpha=alpha, p=p, U=U, k_f=kf.value, status=st.value)
+
+    def release(self, slot):
+        rc = lib().oscar_engine_release(self.h, int(slot))
+        if rc != OK:
+            self._err(rc)
+        self.meta.pop(slot, None)
+
+    def free(self):
+        m = C.c_uint64(0)
+        f = C.c_int32(0)
+        lib().oscar_engine_free_bytes(self.h, C.byref(m), C.byref(f))
+        return m.value, f.value
+
+    def stats(self):
+        t = C.c_int64(0)
+        it = C.c_int64(0)
+        lib().oscar_engine_stats(self.h, C.byref(t), C.byref(it))
+        return dict(ticks=t.value, cg_iters=it.value)

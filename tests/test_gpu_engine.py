@@ -1,0 +1,114 @@
+"""The batched serving engine on the GPU: the same request gives bitwise the
+same results through the engine as through a context, alone and inside a
+mix with continuous admissions; capacity limits and release behave."""
+import numpy as np
+import pytest
+
+from paper_2105_10576_amd import cases
+
+pytestmark = pytest.mark.gpu
+
+
+def _reqs():
+    return [
+        cases.channel_bubble(nx=64, ny=16, n_sub=12, max_iters=6),
+        cases.channel_bubble(nx=96, ny=32, n_sub=None, max_iters=5, ca=1e-3),
+        cases.micromodel(nx=160, ny=64, seed=11, r_lo=4, r_hi=8, inlet_cols=8, buffer=16, max_iters=4, ca=1e-4),
+        cases.channel_bubble(nx=50, ny=14, n_sub=12, max_iters=3),
+    ]
+
+
+def _run_alone(oscar, c, precision):
+    e = oscar.Engine(2, 4 * oscar.workspace_size(c, precision), precision=precision)
+    s = e.admit(c)
+    assert s is not None
+    for _ in range(10000):
+        done, act = e.poll()
+        if done:
+            break
+        e.run(1)
+    out = e.fetch(s)
+    e.release(s)
+    e.close()
+    return out
+
+
+def test_engine_matches_context_fp64():
+    from paper_2105_10576_amd import oscar
+    c = _reqs()[0]
+    g = oscar.Oscar(c, precision=0)
+    g.viscous_step(c["dt_vd"])
+    rc, kf, E = g.capillary_relax(c["dt_vd"], c["n_sub"], c["max_iters"], c["tol"])
+    out = _run_alone(oscar, c, 0)
+    assert out["k_f"] == kf
+    for f in ("alpha", "p", "U"):
+        assert np.array_equal(out[f], g.get(f)), f
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_alone_equals_mix_with_continuous_admission(precision):
+    from paper_2105_10576_amd import oscar
+    reqs = _reqs()
+    if precision == 1:
+        for c in reqs:
+            c["pcg_rtol"] = 1e-8
+    alone = [_run_alone(oscar, c, precision) for c in reqs]
+    heap = sum(oscar.workspace_size(c, precision) for c in reqs) + (1 << 20)
+    e = oscar.Engine(8, heap, precision=precision)
+    slots = {}
+    slots[e.admit(reqs[0])] = 0
+    slots[e.admit(reqs[1])] = 1
+    e.run(2)
+    slots[e.admit(reqs[2])] = 2           # joins while the first two are mid-relaxation
+    e.run(1)
+    slots[e.admit(reqs[3])] = 3
+    got = {}
+    for _ in range(10000):
+        done, act = e.poll()
+        for s in done:
+            got[slots[s]] = e.fetch(s)
+            e.release(s)
+        if len(got) == len(reqs):
+            break
+        e.run(1)
+    assert len(got) == len(reqs)
+    for i, a in enumerate(alone):
+        assert got[i]["k_f"] == a["k_f"]
+        for f in ("alpha", "p", "U"):
+            assert np.array_equal(got[i][f], a[f]), (i, f)
+
+
+def test_capacity_and_release():
+    from paper_2105_10576_amd import oscar
+    c = _reqs()[0]
+    need = oscar.workspace_size(c, 0)
+    e = oscar.Engine(4, 2 * need + 1000, precision=0)
+    s1, s2 = e.admit(c), e.admit(c)
+    assert s1 is not None and s2 is not None
+    assert e.admit(c) is None                  # heap full
+    e.release(s1)                              # cancel a resident request
+    s3 = e.admit(c)
+    assert s3 is not None
+    for _ in range(1000):
+        done, act = e.poll()
+        if len(done) == 2:
+            break
+        e.run(1)
+    assert sorted(done) == sorted([s2, s3])
+    a, b = e.fetch(s2), e.fetch(s3)
+    for f in ("alpha", "p", "U"):
+        assert np.array_equal(a[f], b[f])
+
+
+def test_serving_loop_end_to_end():
+    from paper_2105_10576_amd import oscar
+    from paper_2105_10576_amd.serve import Server
+    reqs = _reqs()
+    heap = 2 * max(oscar.workspace_size(c, 0) for c in reqs)
+    e = oscar.Engine(4, heap, precision=0)
+    srv = Server(e, lambda c: oscar.workspace_size(c, 0), heap_bytes=heap)
+    res, summ = srv.run(reqs, [0.0, 0.01, 0.02, 0.03], keep_fields=True, max_wall=120)
+    assert summ["served"] == 4 and summ["peak_resident_bytes"] <= heap
+    for r in res:
+        a = _run_alone(oscar, reqs[r["request"]], 0)
+        assert np.array_equal(r["alpha"], a["alpha"]) and np.array_equal(r["U"], a["U"])
