@@ -26,15 +26,14 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 
-def cg_bytes_per_fluid_cell(precision, pass_):
-    """Algorithmic bytes one conjugate-gradient kernel moves per fluid cell:
-    pass 1 reads z, d_old, rAU and the face-flag byte and writes d, q;
-    pass 2 reads x, d, q, r, D^-1 and writes x, r, z (x is the FP64 pressure in
-    the FP64 path, the FP32 correction in the mixed path)."""
+def cg_bytes_per_fluid_cell(precision):
+    """Algorithmic bytes the conjugate-gradient iteration kernel moves per
+    fluid cell: it reads r, w = A D^-1 r, s_old, D^-1, p_old, rAU and x and
+    writes p, s, r, w and x (x is the FP64 pressure in the FP64 path, the FP32
+    correction in the mixed path); every cell also reads its face-flag byte."""
     w = 4 if precision == 1 else 8
-    if pass_ == 0:
-        return 3 * w + 1 + 2 * w
-    return (8 if precision == 0 else 4) + 4 * w + (8 if precision == 0 else 4) + 2 * w
+    x = 8 if precision == 0 else 4
+    return 6 * w + x + 4 * w + x
 
 
 def run_gpu(case, precision, steps, warmup, timing=True):
@@ -60,7 +59,7 @@ def run_gpu(case, precision, steps, warmup, timing=True):
         assert kf == n_sub
     torch.cuda.synchronize()
     t = time.perf_counter() - t0
-    kt = [g.timing_read(k) for k in (0, 1)] if timing else None
+    kt = g.timing_read(0) if timing else None
     if timing:
         g.timing(False)
     st = g.stats()
@@ -93,7 +92,23 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 path beside the mixed path")
+    ap.add_argument("--no-serving", action="store_true", help="skip the batched-serving measurement")
+    ap.add_argument("--pmc-calibration", type=int, default=0, metavar="MIB",
+                    help="only copy MIB MiB device-to-device (calibrates rocprofv3 FETCH_SIZE/WRITE_SIZE)")
+    ap.add_argument("--serving-requests", type=int, default=64)
+    ap.add_argument("--serving-max-iters", type=int, default=40,
+                    help="cap on relaxation sub-steps per serving request (the mix allows up to 200)")
     args = ap.parse_args()
+    if args.pmc_calibration:
+        import torch
+
+        a = torch.ones(args.pmc_calibration << 20, dtype=torch.uint8, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"pmc_calibration_copy_bytes": a.numel(), "copies": 3}))
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (see DESIGN.md, sharding)",
               file=sys.stderr)
@@ -105,6 +120,7 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     case = cases.constricted_channel(tol=0.0)
+    case["pcg_rtol"] = 1e-8   # pressure solves to a 1e-8 relative residual on both paths
     nc = case["nx"] * case["ny"] * case["nz"]
     n_fluid = int((case["mask"] == 0).sum())
     n_sub = case["n_sub"]
@@ -113,12 +129,10 @@ def main():
     value = mixed["iters"] * nc / mixed["seconds"] / 1e6
     ms_step = 1e3 * mixed["seconds"] / args.steps
 
-    # dominant kernel: the conjugate-gradient pass with the larger total time
-    kt = mixed["kernel_times"]
-    dom = 0 if kt[0][0] >= kt[1][0] else 1
-    ms_tot, launches = kt[dom]
+    # dominant kernel: the conjugate-gradient iteration kernel
+    ms_tot, launches = mixed["kernel_times"]
     avg_s = ms_tot / 1e3 / max(launches, 1)
-    alg_bytes = n_fluid * cg_bytes_per_fluid_cell(1, dom) + (nc if dom == 1 else 0)
+    alg_bytes = n_fluid * cg_bytes_per_fluid_cell(1) + nc
     achieved = alg_bytes / avg_s / 1e9
 
     out = {
@@ -136,13 +150,13 @@ def main():
         "data": "synthetic (seeded constricted-channel geometry and CO2 slug)",
         "config": {
             "workload": "3D constricted channel 128x64x64 (524288 voxels, %d fluid), Ca=1e-4, N=%d sub-steps, "
-                        "1 viscous + %d relaxation iterations per step, tol=0" % (n_fluid, n_sub, n_sub),
+                        "1 viscous + %d relaxation iterations per step, tol=0, pressure rtol 1e-8" % (n_fluid, n_sub, n_sub),
             "precision": "mixed",
             "pcg_iters_per_step": round(mixed["pcg_iters"] / args.steps, 1),
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_pcg%d" % (dom + 1),
+            "kernel": "k_cg",
             "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
@@ -155,19 +169,23 @@ def main():
     }
     if not args.no_fp64:
         f = run_gpu(case, 0, args.fp64_steps, 1)
-        kt64 = f["kernel_times"]
-        d64 = 0 if kt64[0][0] >= kt64[1][0] else 1
-        avg64 = kt64[d64][0] / 1e3 / max(kt64[d64][1], 1)
-        b64 = n_fluid * cg_bytes_per_fluid_cell(0, d64) + (nc if d64 == 1 else 0)
+        ms64, n64 = f["kernel_times"]
+        avg64 = ms64 / 1e3 / max(n64, 1)
+        b64 = n_fluid * cg_bytes_per_fluid_cell(0) + nc
         out["fp64"] = {
             "value": round(f["iters"] * nc / f["seconds"] / 1e6, 3),
             "ms_per_step": round(1e3 * f["seconds"] / args.fp64_steps, 3),
             "steps": args.fp64_steps,
             "pcg_iters_per_step": round(f["pcg_iters"] / args.fp64_steps, 1),
-            "dominant_kernel": "k_pcg%d" % (d64 + 1),
+            "dominant_kernel": "k_cg",
             "achieved_GBs": round(b64 / avg64 / 1e9, 1),
             "avg_launch_us": round(avg64 * 1e6, 3),
         }
+    if not args.no_serving:
+        from paper_2105_10576_amd import serving_bench
+
+        out["serving"] = serving_bench.run(n_requests=args.serving_requests, max_iters=args.serving_max_iters,
+                                           log=lambda m: print("[serving] " + m, file=sys.stderr, flush=True))
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(case)
     print(json.dumps(out), flush=True)

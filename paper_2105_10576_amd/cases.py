@@ -102,33 +102,47 @@ def _capsule_alpha(nx, ny, x0, x1, yc, rad, sub=16):
     return inside.reshape(ny, sub, nx, sub).mean(axis=(1, 3))
 
 
-def _disc_pack(rng, nx, ny, x_lo, x_hi, r_lo, r_hi, gap, target_solid, max_tries=400000):
+def _disc_pack(rng, nx, ny, x_lo, x_hi, r_lo, r_hi, gap, target_solid, max_tries=200000, batch=512):
     """Random sequential addition of non-overlapping discs with a minimum gap,
     in cell units, inside x in [x_lo, x_hi) and at least `gap` from y walls,
-    until the solid fraction of the zone reaches target_solid."""
-    cx, cy, cr = [], [], []
+    until the solid fraction of the zone reaches target_solid.  Candidates
+    are drawn in batches (radius, then centre); each is accepted in draw
+    order if it keeps the gap to every disc accepted before it."""
+    cx = np.zeros(0)
+    cy = np.zeros(0)
+    cr = np.zeros(0)
     zone = (x_hi - x_lo) * ny
     area = 0.0
     tries = 0
     while area / zone < target_solid and tries < max_tries:
-        tries += 1
-        r = rng.uniform(r_lo, r_hi)
-        x = rng.uniform(x_lo + r, x_hi - r)
-        y = rng.uniform(r + gap, ny - r - gap)
-        if cx:
-            d2 = (np.asarray(cx) - x) ** 2 + (np.asarray(cy) - y) ** 2
-            if np.any(d2 < (np.asarray(cr) + r + gap) ** 2):
-                continue
-        cx.append(x)
-        cy.append(y)
-        cr.append(r)
-        area += math.pi * r * r
+        r = rng.uniform(r_lo, r_hi, size=batch)
+        x = x_lo + r + rng.uniform(size=batch) * np.maximum(x_hi - x_lo - 2 * r, 0.0)
+        y = r + gap + rng.uniform(size=batch) * np.maximum(ny - 2 * (r + gap), 0.0)
+        tries += batch
+        if cx.size:
+            d2 = (x[:, None] - cx[None, :]) ** 2 + (y[:, None] - cy[None, :]) ** 2
+            ok = np.all(d2 >= (r[:, None] + cr[None, :] + gap) ** 2, axis=1)
+        else:
+            ok = np.ones(batch, dtype=bool)
+        n_before = cx.size
+        for t in np.nonzero(ok)[0]:
+            if area / zone >= target_solid:
+                break
+            # against discs accepted earlier in this batch
+            if cx.size > n_before:
+                dd = (x[t] - cx[n_before:]) ** 2 + (y[t] - cy[n_before:]) ** 2
+                if np.any(dd < (r[t] + cr[n_before:] + gap) ** 2):
+                    continue
+            cx = np.append(cx, x[t])
+            cy = np.append(cy, y[t])
+            cr = np.append(cr, r[t])
+            area += math.pi * r[t] * r[t]
     X, Y = np.meshgrid(np.arange(nx) + 0.5, np.arange(ny) + 0.5, indexing="xy")
     solid = np.zeros((ny, nx), dtype=bool)
-    for x, y, r in zip(cx, cy, cr):
-        i0, i1 = max(0, int(x - r) - 1), min(nx, int(x + r) + 2)
-        j0, j1 = max(0, int(y - r) - 1), min(ny, int(y + r) + 2)
-        sub = (X[j0:j1, i0:i1] - x) ** 2 + (Y[j0:j1, i0:i1] - y) ** 2 <= r * r
+    for x0, y0, r0 in zip(cx, cy, cr):
+        i0, i1 = max(0, int(x0 - r0) - 1), min(nx, int(x0 + r0) + 2)
+        j0, j1 = max(0, int(y0 - r0) - 1), min(ny, int(y0 + r0) + 2)
+        sub = (X[j0:j1, i0:i1] - x0) ** 2 + (Y[j0:j1, i0:i1] - y0) ** 2 <= r0 * r0
         solid[j0:j1, i0:i1] |= sub
     return solid
 

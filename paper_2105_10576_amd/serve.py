@@ -36,9 +36,10 @@ class Server:
         self.sleep = sleep
         self.heap_bytes = heap_bytes
 
-    def run(self, requests, arrivals, keep_fields=False, max_wall=None):
+    def run(self, requests, arrivals, keep_fields=False, max_wall=None, progress=None, progress_every=25):
         """Serve `requests` arriving at times `arrivals` (seconds after the
-        start, non-decreasing).  Returns (results, summary)."""
+        start, non-decreasing).  Returns (results, summary).  progress(msg)
+        is called every `progress_every` ticks."""
         order = sorted(range(len(requests)), key=lambda i: arrivals[i])
         queue = []             # arrived, waiting for admission (FIFO)
         resident = {}          # slot -> request index
@@ -77,6 +78,10 @@ class Server:
             if resident:
                 self.engine.run(1)
                 ticks += 1
+                if progress is not None and ticks % progress_every == 0:
+                    n_done = sum(1 for r in results if r is not None)
+                    progress("tick %d t=%.1fs resident=%d queued=%d done=%d" % (ticks, self.clock() - t0, len(resident),
+                                                                                len(queue), n_done))
                 done, _ = self.engine.poll()
                 for slot in done:
                     i = resident.pop(slot)

@@ -1,0 +1,58 @@
+"""Batched-serving measurement: the seeded 64-request mix of 2D channel and
+micromodel relaxation requests (cases.serving_requests), served by the GPU
+engine with admission by HBM footprint.  A burst pass (all requests at t=0)
+measures the saturated throughput; a second pass draws exponential
+inter-arrival gaps (seed 4) at 0.8 of that rate.  Reports p50/p99 latency by
+nearest rank (p99 of 64 samples is the maximum) and aggregate Mcell-iter/s
+(one viscous + k_f relaxation iterations per cell and request)."""
+from __future__ import annotations
+
+import time
+
+from . import cases, oscar
+from .serve import Server
+
+
+def run(n_requests=64, max_slots=32, heap_mb=512, precision=oscar.MIXED, max_iters=None, rate_frac=0.8,
+        device="cuda:0", log=None):
+    reqs = cases.serving_requests(n=n_requests)
+    for c in reqs:
+        if max_iters is not None:
+            c["max_iters"] = min(c["max_iters"], max_iters)
+        if precision == oscar.MIXED:
+            c["pcg_rtol"] = 1e-8
+    heap = heap_mb << 20
+    fp = lambda c: oscar.workspace_size(c, precision)
+    out = {}
+    # burst pass
+    eng = oscar.Engine(max_slots, heap, precision=precision, device=device)
+    srv = Server(eng, fp, heap_bytes=heap)
+    res, summ = srv.run(reqs, [0.0] * len(reqs), max_wall=600, progress=log)
+    eng.close()
+    sat_rate = summ["served"] / summ["wall_s"]
+    out["burst"] = {k: summ[k] for k in ("served", "wall_s", "ticks", "p50_latency_s", "p99_latency_s",
+                                         "mcell_iter_per_s", "peak_resident_bytes")}
+    if log:
+        log("burst: %s" % out["burst"])
+    # Poisson pass at rate_frac of the saturated rate
+    lam = rate_frac * sat_rate
+    t = 0.0
+    arrivals = []
+    for c in reqs:
+        t += c["arrival_gap"] / lam
+        arrivals.append(t)
+    eng = oscar.Engine(max_slots, heap, precision=precision, device=device)
+    srv = Server(eng, fp, heap_bytes=heap)
+    res, summ = srv.run(reqs, arrivals, max_wall=600, progress=log)
+    eng.close()
+    out["poisson"] = {k: summ[k] for k in ("served", "wall_s", "ticks", "p50_latency_s", "p99_latency_s",
+                                           "mcell_iter_per_s", "peak_resident_bytes")}
+    out["poisson"]["rate_per_s"] = lam
+    out["requests"] = n_requests
+    out["max_slots"] = max_slots
+    out["heap_mb"] = heap_mb
+    out["mean_k_f"] = sum(r["k_f"] for r in res if r and not r["rejected"]) / max(1, summ["served"])
+    out["cells_min_max"] = [min(r["cells"] for r in res), max(r["cells"] for r in res)]
+    if log:
+        log("poisson: %s" % out["poisson"])
+    return out
