@@ -176,8 +176,10 @@ const char *oscar_last_error(const oscar_ctx *ctx);
  * the conjugate-gradient iteration kernel is bracketed by HIP events on the
  * context's stream.  oscar_timing(ctx, 1) resets and starts the totals,
  * oscar_timing(ctx, 0) stops.  oscar_timing_read(ctx, 0, ...) returns the
- * summed kernel time [ms] and the launch count of that kernel (kernel 1 is
- * reserved and reads zero); it synchronises the stream. */
+ * summed kernel time [ms] and the number of launches that performed an
+ * iteration (launches enqueued past the device-side convergence test exit
+ * at once and are not counted); kernel 1 is reserved and reads zero.  It
+ * synchronises the stream. */
 int32_t oscar_timing(oscar_ctx *ctx, int32_t enable);
 int32_t oscar_timing_read(oscar_ctx *ctx, int32_t kernel, double *total_ms, int64_t *launches);
 

@@ -88,7 +88,14 @@ int check_desc(const oscar_desc *D, std::string &why) {
   if (D->dim != 2 && D->dim != 3) { why = "dim must be 2 or 3"; return OSCAR_E_ARG; }
   if (D->nx < 1 || D->ny < 1 || D->nz < 1) { why = "grid sizes must be >= 1"; return OSCAR_E_ARG; }
   if (D->dim == 2 && D->nz != 1) { why = "nz must be 1 when dim = 2"; return OSCAR_E_ARG; }
-  if ((int64_t)D->nx * D->ny * D->nz > (int64_t)1 << 31) { why = "grid too large"; return OSCAR_E_ARG; }
+  {
+    // 32-bit indexing in the kernels: face arrays and the velocity gradient
+    // (dim^2 components per cell) must stay below 2^31 entries
+    int64_t nc = (int64_t)D->nx * D->ny * D->nz;
+    int64_t nft = (int64_t)(D->nx + 1) * D->ny * D->nz + (int64_t)D->nx * (D->ny + 1) * D->nz +
+                  (int64_t)D->nx * D->ny * (D->nz + 1);
+    if (nft >= ((int64_t)1 << 31) || 9 * nc >= ((int64_t)1 << 31)) { why = "grid too large"; return OSCAR_E_ARG; }
+  }
   if (!(D->h > 0.0) || !std::isfinite(D->h)) { why = "h must be > 0"; return OSCAR_E_ARG; }
   if (!(D->rho1 > 0) || !(D->rho2 > 0) || !(D->mu1 > 0) || !(D->mu2 > 0)) { why = "densities and viscosities must be > 0"; return OSCAR_E_ARG; }
   if (!(D->sigma >= 0) || !std::isfinite(D->sigma)) { why = "sigma must be >= 0"; return OSCAR_E_ARG; }
@@ -178,6 +185,7 @@ struct oscar_ctx {
   Slot s;                  // host copy of the slot (device pointers)
   Slot *d_slot = nullptr;  // device copy
   int2 *d_btab = nullptr;
+  int btab_len = 0;
   hipStream_t stream = nullptr;
   SlotState *h_state = nullptr;   // pinned readback
   std::string err = "no error";
@@ -196,12 +204,13 @@ struct oscar_ctx {
   size_t ev_used = 0;
   double t_ms[2] = {0.0, 0.0};
   int64_t t_cnt[2] = {0, 0};
+  int t_chunk_it0 = -1, t_chunk_n = 0;   // the chunk whose events are pending
 
   Launch L() const {
     Launch l;
     l.slots = d_slot;
     l.btab = d_btab;
-    l.nblocks = g.nblocks;
+    l.nblocks = btab_len;
     l.nslots = 1;
     l.stream = stream;
     return l;
@@ -234,15 +243,25 @@ static int set_ctl(oscar_ctx *c, const SlotCtl &ctl) {
   return OSCAR_OK;
 }
 
-// fold the completed event pairs (start, end of one CG pass) into the totals
+// fold the completed event pairs (start, end of one CG launch) into the
+// totals; launches after the device-side convergence test (they exit at
+// once) are left out: a chunk of n launches from iteration it0 did
+// min(n, it - it0) iterations, `it` read from the device state
 static int harvest_timing(oscar_ctx *c) {
-  for (size_t x = 0; x + 1 < c->ev_used; x += 2) {
+  int real = c->t_chunk_n;
+  if (c->t_chunk_it0 >= 0) {
+    int done_its = c->h_state->it - c->t_chunk_it0;
+    real = done_its < 0 ? 0 : (done_its < c->t_chunk_n ? done_its : c->t_chunk_n);
+  }
+  for (size_t x = 0; x + 1 < c->ev_used && (int)(x / 2) < real; x += 2) {
     float ms = 0.f;
     HIPCHK(c, hipEventElapsedTime(&ms, c->ev[x], c->ev[x + 1]));
     c->t_ms[0] += ms;
     c->t_cnt[0] += 1;
   }
   c->ev_used = 0;
+  c->t_chunk_it0 = -1;
+  c->t_chunk_n = 0;
   return OSCAR_OK;
 }
 
@@ -263,6 +282,12 @@ static int enqueue_cg(oscar_ctx *c, int it0, int n) {
     HIPCHK(c, hipGetLastError());
     return OSCAR_OK;
   }
+  if (c->ev_used) {   // fold a previous chunk first (its state was read)
+    int rc = harvest_timing(c);
+    if (rc) return rc;
+  }
+  c->t_chunk_it0 = it0;
+  c->t_chunk_n = n;
   size_t need = c->ev_used + 2 * (size_t)n;
   while (c->ev.size() < need) {
     hipEvent_t e;
@@ -276,6 +301,34 @@ static int enqueue_cg(oscar_ctx *c, int it0, int n) {
     HIPCHK(c, hipEventRecord(c->ev[c->ev_used++], c->stream));
   }
   return OSCAR_OK;
+}
+
+// Block-table segment of one slot: workgroups are dealt round-robin to the
+// 8 XCDs (each with its own L2), so position p of a segment that starts on a
+// multiple of 8 runs on XCD p % 8.  Each XCD gets a contiguous run of the
+// slot's blocks (neighbouring cells share its L2); the segment is padded to
+// a multiple of 8 with entries (slot, -1) that kernels skip.
+static void append_segment(std::vector<int2> &bt, int slot, int nb) {
+  const int X = 8;
+  while (bt.size() % X) bt.push_back(make_int2(slot, -1));
+  int q = nb / X, rem = nb % X;
+  int padded = (nb + X - 1) / X * X;
+  for (int p = 0; p < padded; ++p) {
+    int x = p % X, i = p / X;
+    int cnt = q + (x < rem ? 1 : 0);
+    int start = x * q + (x < rem ? x : rem);
+    bt.push_back(make_int2(slot, i < cnt ? start + i : -1));
+  }
+}
+
+// relative tolerance of each FP32 inner solve of the mixed-precision path
+static double inner_rtol() {
+  static double v = [] {
+    const char *e = getenv("OSCAR_INNER_RTOL");
+    double x = e ? atof(e) : 1e-3;
+    return x > 0 && x < 1 ? x : 1e-3;
+  }();
+  return v;
 }
 
 int oscar::blocks_for(int64_t nc) {
@@ -303,7 +356,7 @@ extern "C" int32_t oscar_workspace_size(const oscar_desc *desc, uint64_t *bytes)
   Slot s;
   layout(*desc, cv, &s, true);
   cv.take(sizeof(Slot));
-  cv.take(sizeof(int2) * (uint64_t)dims_of(*desc).nblocks);
+  cv.take(sizeof(int2) * (uint64_t)(dims_of(*desc).nblocks + 8));
   *bytes = cv.off;
   return OSCAR_OK;
 }
@@ -346,16 +399,17 @@ extern "C" int32_t oscar_create(const oscar_desc *desc, void *ws, uint64_t bytes
   memset(&s, 0, sizeof s);
   layout(*desc, cv, &s, true);
   c->d_slot = (Slot *)cv.take(sizeof(Slot));
-  c->d_btab = (int2 *)cv.take(sizeof(int2) * (uint64_t)c->g.nblocks);
+  c->d_btab = (int2 *)cv.take(sizeof(int2) * (uint64_t)(c->g.nblocks + 8));
   s.dim = desc->dim;
   s.nx = desc->nx;
   s.ny = desc->ny;
   s.nz = desc->nz;
-  s.nc = c->g.nc;
-  s.nf0 = c->g.nf0;
-  s.nf1 = c->g.nf1;
-  s.nf2 = c->g.nf2;
-  s.nftot = c->g.nft;
+  s.nc = (int32_t)c->g.nc;
+  s.nf0 = (int32_t)c->g.nf0;
+  s.nf1 = (int32_t)c->g.nf1;
+  s.nf2 = (int32_t)c->g.nf2;
+  s.nftot = (int32_t)c->g.nft;
+  s.nxy = desc->nx * desc->ny;
   s.block0 = 0;
   s.nblocks = c->g.nblocks;
   s.n_fluid = (int32_t)n_fluid;
@@ -394,8 +448,9 @@ extern "C" int32_t oscar_create(const oscar_desc *desc, void *ws, uint64_t bytes
   if ((e = hipMemsetAsync(ws, 0, cv.off, c->stream)) != hipSuccess) return fail(e, "hipMemsetAsync");
   if ((e = hipMemcpyAsync((void *)s.flags, fl.data(), nc, hipMemcpyHostToDevice, c->stream)) != hipSuccess)
     return fail(e, "upload mask");
-  std::vector<int2> bt(c->g.nblocks);
-  for (int b = 0; b < c->g.nblocks; ++b) bt[b] = make_int2(0, b);
+  std::vector<int2> bt;
+  append_segment(bt, 0, c->g.nblocks);
+  c->btab_len = (int)bt.size();
   if ((e = hipMemcpyAsync(c->d_btab, bt.data(), sizeof(int2) * bt.size(), hipMemcpyHostToDevice, c->stream)) != hipSuccess)
     return fail(e, "upload block table");
   if ((e = hipMemcpyAsync(c->d_slot, &s, sizeof(Slot), hipMemcpyHostToDevice, c->stream)) != hipSuccess)
@@ -519,7 +574,7 @@ static SlotCtl make_ctl(const oscar_ctx *c, int mode, double dt, int n_sub) {
   k.ub = mode ? 0.0 : c->D.u_inlet;
   k.with_st = mode;
   k.rtol = c->D.pcg_rtol;
-  k.rtol_inner = 1e-3;
+  k.rtol_inner = inner_rtol();
   k.max_it = c->D.pcg_max_it;
   k.n_sub = n_sub;
   return k;
@@ -884,7 +939,7 @@ static uint64_t eng_table_bytes(int max_slots, int btab_cap) {
 
 extern "C" int32_t oscar_engine_table_bytes(int32_t max_slots, uint64_t *bytes) {
   if (max_slots < 1 || max_slots > 4096 || !bytes) { g_err = "need 1 <= max_slots <= 4096"; return OSCAR_E_ARG; }
-  *bytes = eng_table_bytes(max_slots, max_slots * blocks_for((int64_t)1 << 40));
+  *bytes = eng_table_bytes(max_slots, max_slots * (blocks_for((int64_t)1 << 40) + 16));
   return OSCAR_OK;
 }
 
@@ -896,7 +951,7 @@ extern "C" int32_t oscar_engine_create(int32_t max_slots, int32_t precision, voi
     g_err = "need 1 <= max_slots <= 4096 and a known precision";
     return OSCAR_E_ARG;
   }
-  const int btab_cap = max_slots * blocks_for((int64_t)1 << 40);
+  const int btab_cap = max_slots * (blocks_for((int64_t)1 << 40) + 16);
   uint64_t tb = eng_table_bytes(max_slots, btab_cap);
   if (!ws || ((uintptr_t)ws % ALIGN) != 0 || bytes < tb) {
     g_err = "engine workspace too small or not 256-byte aligned";
@@ -1022,11 +1077,12 @@ extern "C" int32_t oscar_engine_admit(oscar_engine *e, const oscar_desc *desc, d
   s.nx = desc->nx;
   s.ny = desc->ny;
   s.nz = desc->nz;
-  s.nc = es.g.nc;
-  s.nf0 = es.g.nf0;
-  s.nf1 = es.g.nf1;
-  s.nf2 = es.g.nf2;
-  s.nftot = es.g.nft;
+  s.nc = (int32_t)es.g.nc;
+  s.nf0 = (int32_t)es.g.nf0;
+  s.nf1 = (int32_t)es.g.nf1;
+  s.nf2 = (int32_t)es.g.nf2;
+  s.nftot = (int32_t)es.g.nft;
+  s.nxy = desc->nx * desc->ny;
   s.nblocks = es.g.nblocks;
   s.n_fluid = (int32_t)n_fluid;
   s.precision = desc->precision;
@@ -1087,7 +1143,7 @@ static SlotCtl eng_ctl(const EngSlot &es, int mode, int precision) {
   k.ub = mode ? 0.0 : es.D.u_inlet;
   k.with_st = mode;
   k.rtol = es.D.pcg_rtol;
-  k.rtol_inner = 1e-3;
+  k.rtol_inner = inner_rtol();
   k.max_it = es.D.pcg_max_it;
   k.n_sub = es.n_sub;
   k.substep = es.k;
@@ -1141,7 +1197,7 @@ static int eng_tick(oscar_engine *e) {
     EngSlot &es = e->slots[i];
     if (es.state != ES_VD && es.state != ES_CR) continue;
     act.push_back(i);
-    for (int b = 0; b < es.g.nblocks; ++b) e->bt.push_back(make_int2(i, b));
+    append_segment(e->bt, i, es.g.nblocks);
   }
   if (act.empty()) return OSCAR_OK;
   if ((int)e->bt.size() > e->btab_cap) { e->err = "block table overflow"; return OSCAR_E_CAPACITY; }
@@ -1252,7 +1308,7 @@ static int eng_tick(oscar_engine *e) {
     es.k_f = es.k + 1;
     es.state = ES_DONE;
     off.push_back({i, SlotCtl()});
-    for (int b = 0; b < es.g.nblocks; ++b) e->bt2.push_back(make_int2(i, b));
+    append_segment(e->bt2, i, es.g.nblocks);
   }
   if (!e->bt2.empty()) {
     EHIP(e, hipMemcpyAsync(e->d_btab2, e->bt2.data(), sizeof(int2) * e->bt2.size(), hipMemcpyHostToDevice, e->stream));

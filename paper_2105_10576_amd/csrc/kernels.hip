@@ -28,8 +28,8 @@ namespace oscar {
 // ---------------------------------------------------------------------------
 
 struct Cell {
-  int64_t P;
-  int i, j, k;
+  int P;
+  int i, j, k, row;   // row = j + ny*k
   bool valid;
 };
 
@@ -40,72 +40,90 @@ struct Block {
   int lb;
 };
 
+// a zeroed (inactive) control block for padding entries of a block table
+__device__ SlotCtl g_padding_ctl;
+
 __device__ __forceinline__ Block block_of(const Slot *slots, const int2 *btab) {
   int2 t = btab[blockIdx.x];
   Block b;
   b.s = slots + t.x;
-  b.ctl = b.s->ctl;
+  b.ctl = t.y < 0 ? &g_padding_ctl : b.s->ctl;
   b.st = b.s->st;
   b.lb = t.y;
   return b;
 }
 
-__device__ __forceinline__ Cell cell_at(const Slot &s, int64_t g) {
+// cell coordinates from the linear index (32-bit unsigned arithmetic)
+__device__ __forceinline__ Cell cell_at(const Slot &s, int g) {
   Cell c;
   c.valid = true;
   c.P = g;
-  c.i = (int)(g % s.nx);
-  int64_t t = g / s.nx;
-  c.j = (int)(t % s.ny);
-  c.k = (int)(t / s.ny);
+  unsigned ug = (unsigned)g, nx = (unsigned)s.nx, ny = (unsigned)s.ny;
+  unsigned row = ug / nx;
+  c.i = (int)(ug - row * nx);
+  c.row = (int)row;
+  unsigned k = row / ny;
+  c.j = (int)(row - k * ny);
+  c.k = (int)k;
   return c;
 }
 
 // grid-stride loop over the cells of the slot handled by block lb
 template <class Fn>
 __device__ __forceinline__ void for_cells(const Slot &s, int lb, Fn &&fn) {
-  const int64_t stride = (int64_t)s.nblocks * BLOCK;
-  for (int64_t g = (int64_t)lb * BLOCK + threadIdx.x; g < s.nc; g += stride) fn(cell_at(s, g));
+  const int stride = s.nblocks * BLOCK;
+  for (int g = lb * BLOCK + (int)threadIdx.x; g < s.nc; g += stride) fn(cell_at(s, g));
 }
 
-__device__ __forceinline__ int64_t cidx(const Slot &s, int i, int j, int k) {
-  return i + (int64_t)s.nx * (j + (int64_t)s.ny * k);
+__device__ __forceinline__ int cidx(const Slot &s, int i, int j, int k) { return i + s.nx * (j + s.ny * k); }
+
+__device__ __forceinline__ int fidx(const Slot &s, int e, int i, int j, int k) {
+  if (e == 0) return i + (s.nx + 1) * (j + s.ny * k);
+  if (e == 1) return s.nf0 + i + s.nx * (j + (s.ny + 1) * k);
+  return s.nf0 + s.nf1 + i + s.nx * (j + s.ny * k);
 }
 
-__device__ __forceinline__ int64_t fidx(const Slot &s, int e, int i, int j, int k) {
-  if (e == 0) return i + (int64_t)(s.nx + 1) * (j + (int64_t)s.ny * k);
-  if (e == 1) return s.nf0 + i + (int64_t)s.nx * (j + (int64_t)(s.ny + 1) * k);
-  return s.nf0 + s.nf1 + i + (int64_t)s.nx * (j + (int64_t)s.ny * k);
+__device__ __forceinline__ bool solid_at(const Slot &s, int P) { return (s.flags[P] & 0x40) != 0; }
+
+// offset between a cell and its neighbour across face f
+__device__ __forceinline__ int nb_step(const Slot &s, int f) {
+  int e = f >> 1;
+  int st = e == 0 ? 1 : (e == 1 ? s.nx : s.nxy);
+  return (f & 1) ? st : -st;
 }
 
-__device__ __forceinline__ bool solid_at(const Slot &s, int64_t P) { return (s.flags[P] & 0x40) != 0; }
+// face f of the cell lies on the box side (no neighbour inside the box)
+__device__ __forceinline__ bool on_edge(const Slot &s, const Cell &c, int f) {
+  int e = f >> 1;
+  if (e == 0) return (f & 1) ? c.i == s.nx - 1 : c.i == 0;
+  if (e == 1) return (f & 1) ? c.j == s.ny - 1 : c.j == 0;
+  return (f & 1) ? c.k == s.nz - 1 : c.k == 0;
+}
 
 // face f (0..5 = x-,x+,y-,y+,z-,z+) of a fluid cell
 struct CFace {
   int type;
-  int64_t nb, fi;
+  int nb, fi;
 };
 
-__device__ __forceinline__ CFace cell_face(const Slot &s, uint8_t fl, int i, int j, int k, int f) {
-  CFace c;
+__device__ __forceinline__ CFace cell_face(const Slot &s, uint8_t fl, const Cell &c, int f) {
+  CFace r;
   int e = f >> 1, hi = f & 1;
-  c.nb = -1;
-  c.fi = -1;
-  if (e >= s.dim) { c.type = F_NONE; return c; }
-  int ii = i + (e == 0 ? (hi ? 1 : -1) : 0);
-  int jj = j + (e == 1 ? (hi ? 1 : -1) : 0);
-  int kk = k + (e == 2 ? (hi ? 1 : -1) : 0);
-  c.fi = hi ? fidx(s, e, ii, jj, kk) : fidx(s, e, i, j, k);
-  if (fl & (1u << f)) { c.type = F_INT; c.nb = cidx(s, ii, jj, kk); return c; }
-  bool inbox = ii >= 0 && ii < s.nx && jj >= 0 && jj < s.ny && kk >= 0 && kk < s.nz;
-  c.type = inbox ? F_WALL : s.bcf[f];
-  return c;
+  r.nb = -1;
+  r.fi = -1;
+  if (e >= s.dim) { r.type = F_NONE; return r; }
+  if (e == 0) r.fi = c.P + c.row + hi;
+  else if (e == 1) r.fi = s.nf0 + c.P + s.nx * c.k + (hi ? s.nx : 0);
+  else r.fi = s.nf0 + s.nf1 + c.P + (hi ? s.nxy : 0);
+  if (fl & (1u << f)) { r.type = F_INT; r.nb = c.P + nb_step(s, f); return r; }
+  r.type = on_edge(s, c, f) ? s.bcf[f] : F_WALL;
+  return r;
 }
 
 // face of direction e whose high-side cell is (i,j,k) (coordinate along e in [0, n_e])
 struct FView {
   int type;
-  int64_t lo, hi, P;
+  int lo, hi, P;
   double sf;   // orientation sign seen from the fluid cell (WALL / INLET / OUTLET)
 };
 
@@ -184,7 +202,7 @@ __device__ __forceinline__ void put_partials(const Slot &s, int lb, int ch, doub
   block_reduce<MAXMASK>(v);
   if (threadIdx.x == 0)
 #pragma unroll
-    for (int m = 0; m < M; ++m) s.part[(int64_t)(ch * NVAL + m) * s.nblocks + lb] = v[m];
+    for (int m = 0; m < M; ++m) s.part[(int)(ch * NVAL + m) * s.nblocks + lb] = v[m];
 }
 
 // totals of channel ch over the slot's blocks, in every thread (fixed order)
@@ -192,7 +210,7 @@ template <unsigned MAXMASK, int M>
 __device__ __forceinline__ void get_totals(const Slot &s, int ch, double (&v)[M]) {
 #pragma unroll
   for (int m = 0; m < M; ++m) {
-    const double *p = s.part + (int64_t)(ch * NVAL + m) * s.nblocks;
+    const double *p = s.part + (int)(ch * NVAL + m) * s.nblocks;
     double t = 0.0;
     for (int b = threadIdx.x; b < s.nblocks; b += BLOCK) {
       double x = p[b];
@@ -267,7 +285,7 @@ __global__ void __launch_bounds__(BLOCK) k_copy_phi_prev(const Slot *slots, cons
   const R *src = (const R *)s.phi_vd;
   R *dst = (R *)s.phi_prev;
   for_cells(s, B.lb, [&](const Cell &c) {
-    for_owned_faces(s, c, [&](int, int64_t fi, const FView &) { dst[fi] = src[fi]; });
+    for_owned_faces(s, c, [&](int, int fi, const FView &) { dst[fi] = src[fi]; });
   });
 }
 
@@ -287,7 +305,7 @@ __global__ void __launch_bounds__(BLOCK) k_grad_alpha(const Slot *slots, const i
     for (int e = 0; e < s.dim; ++e) {
       R ge = (R)0;
       if (!(fl & 0x40)) {
-        CFace lo = cell_face(s, fl, c.i, c.j, c.k, 2 * e), hi = cell_face(s, fl, c.i, c.j, c.k, 2 * e + 1);
+        CFace lo = cell_face(s, fl, c, 2 * e), hi = cell_face(s, fl, c, 2 * e + 1);
         R alo = lo.type == F_INT ? (R)0.5 * (a[c.P] + a[lo.nb]) : a[c.P];
         R ahi = hi.type == F_INT ? (R)0.5 * (a[c.P] + a[hi.nb]) : a[c.P];
         ge = (ahi - alo) / (R)s.h;
@@ -307,7 +325,7 @@ __global__ void __launch_bounds__(BLOCK) k_face_normals(const Slot *slots, const
   const int d = s.dim;
   const R delta = (R)s.delta;
   for_cells(s, B.lb, [&](const Cell &c) {
-    for_owned_faces(s, c, [&](int e, int64_t fi, const FView &v) {
+    for_owned_faces(s, c, [&](int e, int fi, const FView &v) {
       R G[3] = {(R)0, (R)0, (R)0};
       R out = (R)0;
       if (v.type == F_INT) {
@@ -341,7 +359,7 @@ __global__ void __launch_bounds__(BLOCK) k_curvature(const Slot *slots, const in
     if (!(fl & 0x40)) {
       R acc = (R)0;
       for (int e = 0; e < s.dim; ++e) {
-        CFace lo = cell_face(s, fl, c.i, c.j, c.k, 2 * e), hi = cell_face(s, fl, c.i, c.j, c.k, 2 * e + 1);
+        CFace lo = cell_face(s, fl, c, 2 * e), hi = cell_face(s, fl, c, 2 * e + 1);
         acc = acc + (nh[hi.fi] - nh[lo.fi]);
       }
       out = -acc / (R)s.h;
@@ -353,7 +371,7 @@ __global__ void __launch_bounds__(BLOCK) k_curvature(const Slot *slots, const in
 // surface-tension face term sigma*kappa_f*(alpha_hi - alpha_lo)/h, in FP64
 // (it is balanced against the pressure gradient on the same face)
 template <typename R>
-__device__ __forceinline__ double st_face(const Slot &s, const R *kap, const R *a, int64_t lo, int64_t hi) {
+__device__ __forceinline__ double st_face(const Slot &s, const R *kap, const R *a, int lo, int hi) {
   return (s.sigma * (0.5 * ((double)kap[lo] + (double)kap[hi]))) * (((double)a[hi] - (double)a[lo]) / s.h);
 }
 
@@ -375,20 +393,20 @@ __global__ void __launch_bounds__(BLOCK) k_mules_flux(const Slot *slots, const i
   for_cells(s, B.lb, [&](const Cell &c) {
     uint8_t fl = s.flags[c.P];
     aold[c.P] = a[c.P];
-    for_owned_faces(s, c, [&](int e, int64_t fi, const FView &v) {
+    for_owned_faces(s, c, [&](int e, int fi, const FView &v) {
       R fl_ = (R)0, af = (R)0, ph = phi[fi];
       if (v.type == F_INT) {
-        int64_t C = ph >= (R)0 ? v.lo : v.hi;
-        int64_t D = ph >= (R)0 ? v.hi : v.lo;
+        int C = ph >= (R)0 ? v.lo : v.hi;
+        int D = ph >= (R)0 ? v.hi : v.lo;
         // cell beyond C, away from D
         int ci = (int)(C % s.nx);
-        int64_t t = C / s.nx;
+        int t = C / s.nx;
         int cj = (int)(t % s.ny), ck = (int)(t / s.ny);
         int step = ph >= (R)0 ? -1 : 1;
         int ui = ci + (e == 0 ? step : 0), uj = cj + (e == 1 ? step : 0), uk = ck + (e == 2 ? step : 0);
         R aUU = a[C];
         if (ui >= 0 && ui < s.nx && uj >= 0 && uj < s.ny && uk >= 0 && uk < s.nz) {
-          int64_t U = cidx(s, ui, uj, uk);
+          int U = cidx(s, ui, uj, uk);
           if (!solid_at(s, U)) aUU = a[U];
         }
         R dD = a[D] - a[C], dU = a[C] - aUU;
@@ -408,7 +426,7 @@ __global__ void __launch_bounds__(BLOCK) k_mules_flux(const Slot *slots, const i
     if (!(fl & 0x40)) {
       R acc = (R)0;
       for (int f = 0; f < 2 * s.dim; ++f) {
-        CFace cf = cell_face(s, fl, c.i, c.j, c.k, f);
+        CFace cf = cell_face(s, fl, c, f);
         if (cf.type == F_NONE) continue;
         R sp = ((f & 1) ? (R)1 : (R)-1) * phi[cf.fi];
         if (sp > (R)0) acc = acc + sp;
@@ -437,7 +455,7 @@ __global__ void __launch_bounds__(BLOCK) k_mules_limiter(const Slot *slots, cons
     if (!(fl & 0x40)) {
       R sumL = (R)0, Pp = (R)0, Pm = (R)0, amax = a[c.P], amin = a[c.P];
       for (int f = 0; f < 2 * s.dim; ++f) {
-        CFace cf = cell_face(s, fl, c.i, c.j, c.k, f);
+        CFace cf = cell_face(s, fl, c, f);
         if (cf.type == F_NONE) continue;
         R sg = (f & 1) ? (R)1 : (R)-1;
         sumL = sumL + sg * FL[cf.fi];
@@ -478,12 +496,12 @@ __global__ void __launch_bounds__(BLOCK) k_mules_update(const Slot *slots, const
     if (fl & 0x40) return;
     R acc = (R)0, bfl = (R)0;
     for (int f = 0; f < 2 * s.dim; ++f) {
-      CFace cf = cell_face(s, fl, c.i, c.j, c.k, f);
+      CFace cf = cell_face(s, fl, c, f);
       if (cf.type == F_NONE) continue;
       R sg = (f & 1) ? (R)1 : (R)-1;
       R lam = (R)0;
       if (cf.type == F_INT) {
-        int64_t lo = (f & 1) ? c.P : cf.nb, hi = (f & 1) ? cf.nb : c.P;
+        int lo = (f & 1) ? c.P : cf.nb, hi = (f & 1) ? cf.nb : c.P;
         R A = Af[cf.fi];
         R x1 = A >= (R)0 ? Rm[lo] : Rp[lo];
         R x2 = A >= (R)0 ? Rp[hi] : Rm[hi];
@@ -545,8 +563,8 @@ __global__ void __launch_bounds__(BLOCK) k_grad_u(const Slot *slots, const int2 
     uint8_t fl = s.flags[c.P];
     for (int e = 0; e < d; ++e) {
       CFace fc[2];
-      fc[0] = cell_face(s, fl, c.i, c.j, c.k, 2 * e);
-      fc[1] = cell_face(s, fl, c.i, c.j, c.k, 2 * e + 1);
+      fc[0] = cell_face(s, fl, c, 2 * e);
+      fc[1] = cell_face(s, fl, c, 2 * e + 1);
       for (int cc = 0; cc < d; ++cc) {
         const R *Uc = Uo + cc * s.nc;
         R out = (R)0;
@@ -576,7 +594,7 @@ __global__ void __launch_bounds__(BLOCK) k_mass_flux(const Slot *slots, const in
   const R *pa = (const R *)s.phi_prev, *pc = (const R *)s.phi_cr;
   R *Fm = (R *)s.Fm;
   for_cells(s, B.lb, [&](const Cell &c) {
-    for_owned_faces(s, c, [&](int, int64_t fi, const FView &v) {
+    for_owned_faces(s, c, [&](int, int fi, const FView &v) {
       R phic = pa[fi] + pc[fi];
       R F = (R)0;
       if (v.type == F_INT) F = rho_of<R>(s, (R)0.5 * (a[v.lo] + a[v.hi])) * phic;
@@ -593,7 +611,7 @@ __global__ void __launch_bounds__(BLOCK) k_assemble(const Slot *slots, const int
   const SlotCtl &ctl = *B.ctl;
   if (!ctl.active) return;
   const int d = s.dim;
-  const int64_t nc = s.nc;
+  const int nc = s.nc;
   const R *an = (const R *)s.alpha, *ao = (const R *)s.alpha_old;
   const R *Uo = (const R *)(ctl.mode ? s.U_cr : s.U_vd);
   const R *gU = (const R *)s.gradU, *Fm = (const R *)s.Fm;
@@ -613,7 +631,7 @@ __global__ void __launch_bounds__(BLOCK) k_assemble(const Slot *slots, const int
     R b[3];
     for (int cc = 0; cc < d; ++cc) b[cc] = (rho_o * Uo[cc * nc + c.P]) * Vdt;
     for (int f = 0; f < 2 * d; ++f) {
-      CFace cf = cell_face(s, fl, c.i, c.j, c.k, f);
+      CFace cf = cell_face(s, fl, c, f);
       int e = f >> 1;
       R sg = (f & 1) ? (R)1 : (R)-1;
       if (cf.type == F_INT) {
@@ -622,7 +640,7 @@ __global__ void __launch_bounds__(BLOCK) k_assemble(const Slot *slots, const int
         R D = muf * Sh;
         aP = aP + (sF > (R)0 ? sF : (R)0);
         aP = aP + D;
-        int64_t lo = (f & 1) ? c.P : cf.nb, hi = (f & 1) ? cf.nb : c.P;
+        int lo = (f & 1) ? c.P : cf.nb, hi = (f & 1) ? cf.nb : c.P;
         for (int cc = 0; cc < d; ++cc) {
           R lu = F >= (R)0 ? hh * gU[(cc * d + e) * nc + lo] : -(hh * gU[(cc * d + e) * nc + hi]);
           b[cc] = b[cc] - sg * (F * lu);
@@ -660,7 +678,7 @@ __global__ void __launch_bounds__(BLOCK) k_predictor(const Slot *slots, const in
   const SlotCtl &ctl = *B.ctl;
   if (!ctl.active) return;
   const int d = s.dim;
-  const int64_t nc = s.nc;
+  const int nc = s.nc;
   const R *an = (const R *)s.alpha, *U = (const R *)(ctl.mode ? s.U_cr : s.U_vd);
   const R *Fm = (const R *)s.Fm, *b = (const R *)s.b, *aPv = (const R *)s.aP;
   R *HbyA = (R *)s.HbyA;
@@ -673,7 +691,7 @@ __global__ void __launch_bounds__(BLOCK) k_predictor(const Slot *slots, const in
     R H[3];
     for (int cc = 0; cc < d; ++cc) H[cc] = b[cc * nc + c.P];
     for (int f = 0; f < 2 * d; ++f) {
-      CFace cf = cell_face(s, fl, c.i, c.j, c.k, f);
+      CFace cf = cell_face(s, fl, c, f);
       if (cf.type != F_INT) continue;
       R sF = ((f & 1) ? (R)1 : (R)-1) * Fm[cf.fi];
       R D = mu_of<R>(s, (R)0.5 * (an[c.P] + an[cf.nb])) * (R)s.Sh;
@@ -691,13 +709,13 @@ __global__ void __launch_bounds__(BLOCK) k_phiH(const Slot *slots, const int2 *b
   const Slot &s = *B.s;
   const SlotCtl &ctl = *B.ctl;
   if (!ctl.active) return;
-  const int64_t nc = s.nc;
+  const int nc = s.nc;
   const R *HbyA = (const R *)s.HbyA, *rAU = (const R *)s.rAU, *kap = (const R *)s.kappa, *a = (const R *)s.alpha;
   double *phiH = s.phiH;
   const double S = s.S, ub = ctl.ub;
   const int with_st = ctl.with_st;
   for_cells(s, B.lb, [&](const Cell &c) {
-    for_owned_faces(s, c, [&](int e, int64_t fi, const FView &v) {
+    for_owned_faces(s, c, [&](int e, int fi, const FView &v) {
       double ph = 0.0;
       if (v.type == F_INT) {
         ph = (0.5 * ((double)HbyA[e * nc + v.lo] + (double)HbyA[e * nc + v.hi])) * S;
@@ -717,21 +735,28 @@ __global__ void __launch_bounds__(BLOCK) k_phiH(const Slot *slots, const int2 *b
 
 // pressure coefficient of face f of fluid cell P in precision X
 template <typename X, typename R>
-__device__ __forceinline__ X pcoef(const Slot &s, const R *rAU, int64_t P, const CFace &cf) {
+__device__ __forceinline__ X pcoef(const Slot &s, const R *rAU, int P, const CFace &cf) {
   if (cf.type == F_INT) return ((X)0.5 * ((X)rAU[P] + (X)rAU[cf.nb])) * (X)s.Sh;
   if (cf.type == F_OUTLET) return (X)rAU[P] * (X)s.S2h;
   return (X)0;
 }
 
-// (M x)_P in precision X, with x read through a functor xv(index)
+// (M x)_P in precision X, with x read through a functor xv(index).  The
+// neighbour values are read at a safe index (the cell itself when the face
+// is not interior) before the face type is known, so the loads do not wait
+// for the flag byte; the arithmetic is that of pcoef.
 template <typename X, typename R, class XV>
 __device__ __forceinline__ X matvec_row(const Slot &s, const R *rAU, const Cell &c, uint8_t fl, XV &&xv) {
   X acc = (X)0;
-  X xP = xv(c.P);
+  const X xP = xv(c.P);
+  const X rP = (X)rAU[c.P];
   for (int f = 0; f < 2 * s.dim; ++f) {
-    CFace cf = cell_face(s, fl, c.i, c.j, c.k, f);
-    if (cf.type == F_INT) acc = acc + pcoef<X, R>(s, rAU, c.P, cf) * (xP - xv(cf.nb));
-    else if (cf.type == F_OUTLET) acc = acc + pcoef<X, R>(s, rAU, c.P, cf) * xP;
+    const bool in = (fl >> f) & 1u;
+    const int n = in ? c.P + nb_step(s, f) : c.P;
+    const X xn = xv(n);
+    const X rn = (X)rAU[n];
+    if (in) acc = acc + (((X)0.5 * (rP + rn)) * (X)s.Sh) * (xP - xn);
+    else if (on_edge(s, c, f) && s.bcf[f] == F_OUTLET) acc = acc + (rP * (X)s.S2h) * xP;
   }
   return acc;
 }
@@ -763,13 +788,13 @@ __global__ void __launch_bounds__(BLOCK) k_pressure_setup(const Slot *slots, con
     double acc = 0.0;
     T dg = (T)0;
     for (int f = 0; f < 2 * s.dim; ++f) {
-      CFace cf = cell_face(s, fl, c.i, c.j, c.k, f);
+      CFace cf = cell_face(s, fl, c, f);
       if (cf.type == F_NONE) continue;
       acc = acc + ((f & 1) ? 1.0 : -1.0) * phiH[cf.fi];
       if (cf.type == F_INT || cf.type == F_OUTLET) dg = dg + pcoef<T, R>(s, rAU, c.P, cf);
     }
     double rhs = -acc;
-    double Mp = matvec_row<double, R>(s, rAU, c, fl, [&](int64_t x) { return p[x]; });
+    double Mp = matvec_row<double, R>(s, rAU, c, fl, [&](int x) { return p[x]; });
     double r64 = rhs - Mp;
     T rr = (T)r64;
     s.rhs[c.P] = rhs;
@@ -831,7 +856,7 @@ __global__ void __launch_bounds__(BLOCK) k_normres(const Slot *slots, const int2
   for_cells(s, B.lb, [&](const Cell &c) {
     uint8_t fl = s.flags[c.P];
     if (fl & 0x40) return;
-    double Mpb = matvec_row<double, R>(s, rAU, c, fl, [&](int64_t) { return pbar; });
+    double Mpb = matvec_row<double, R>(s, rAU, c, fl, [&](int) { return pbar; });
     double rhs = s.rhs[c.P], Mp = s.Mp[c.P];
     red[0] = red[0] + fabs(rhs - Mp);
     red[1] = red[1] + (fabs(Mp - Mpb) + fabs(rhs - Mpb));
@@ -872,11 +897,8 @@ __global__ void __launch_bounds__(BLOCK) k_cg_init(const Slot *slots, const int2
   double red[3] = {0.0, 0.0, 0.0};   // <r,u>, <w,u>, <r,r>
   for_cells(s, B.lb, [&](const Cell &c) {
     uint8_t fl = s.flags[c.P];
-    if (fl & 0x40) {
-      w[c.P] = (T)0;
-      return;
-    }
-    auto uv = [&](int64_t x) -> T { return invD[x] * r[x]; };
+    if (fl & 0x40) return;   // solid entries of the CG vectors are never read
+    auto uv = [&](int x) -> T { return invD[x] * r[x]; };
     T u = uv(c.P);
     T ww = matvec_row<T, R>(s, rAU, c, fl, uv);
     w[c.P] = ww;
@@ -885,7 +907,7 @@ __global__ void __launch_bounds__(BLOCK) k_cg_init(const Slot *slots, const int2
     red[1] = red[1] + (double)(ww * u);
     red[2] = red[2] + (double)(rr * rr);
   });
-  put_partials<0u>(s, B.lb, CH_CG, red);
+  put_partials<0u>(s, B.lb, CH_CG1, red);   // read by iteration 0
 }
 
 // iteration it (0-based): scalars from the previous reduction, convergence
@@ -900,7 +922,7 @@ __global__ void __launch_bounds__(BLOCK) k_cg(const Slot *slots, const int2 *bta
   SlotState *st = B.st;
   const bool mixed = s.precision != 0;
   double v[3];
-  get_totals<0u>(s, CH_CG, v);
+  get_totals<0u>(s, CH_CG0 + ((it + 1) & 1), v);   // written by iteration it - 1
   const double gam = v[0], del = v[1];
   double alpha, beta = 0.0;
   if (it == 0) {
@@ -940,16 +962,11 @@ __global__ void __launch_bounds__(BLOCK) k_cg(const Slot *slots, const int2 *bta
   double red[3] = {0.0, 0.0, 0.0};
   for_cells(s, B.lb, [&](const Cell &c) {
     uint8_t fl = s.flags[c.P];
-    if (fl & 0x40) {
-      r1[c.P] = (T)0;
-      w1[c.P] = (T)0;
-      sn[c.P] = (T)0;
-      return;
-    }
+    if (fl & 0x40) return;   // solid entries of the CG vectors are never read
     // s = w + beta s_old and the updated residual, at any fluid cell
-    auto s_at = [&](int64_t x) -> T { return first ? w0[x] : w0[x] + be * so[x]; };
-    auto u_new = [&](int64_t x) -> T { return invD[x] * (r0[x] - al * s_at(x)); };
-    const int64_t P = c.P;
+    auto s_at = [&](int x) -> T { return first ? w0[x] : w0[x] + be * so[x]; };
+    auto u_new = [&](int x) -> T { return invD[x] * (r0[x] - al * s_at(x)); };
+    const int P = c.P;
     T u0 = invD[P] * r0[P];
     T pn = first ? u0 : u0 + be * pv[P];
     T sP = s_at(P);
@@ -966,7 +983,7 @@ __global__ void __launch_bounds__(BLOCK) k_cg(const Slot *slots, const int2 *bta
     red[1] = red[1] + (double)(wn * un);
     red[2] = red[2] + (double)(rn * rn);
   });
-  put_partials<0u>(s, B.lb, CH_CG, red);
+  put_partials<0u>(s, B.lb, CH_CG0 + (it & 1), red);
 }
 
 // mixed precision, outer refinement: p += e, e = 0
@@ -1000,7 +1017,7 @@ __global__ void __launch_bounds__(BLOCK) k_refine_res(const Slot *slots, const i
   for_cells(s, B.lb, [&](const Cell &c) {
     uint8_t fl = s.flags[c.P];
     if (fl & 0x40) return;
-    double Mp = matvec_row<double, R>(s, rAU, c, fl, [&](int64_t x) { return p[x]; });
+    double Mp = matvec_row<double, R>(s, rAU, c, fl, [&](int x) { return p[x]; });
     double r64 = s.rhs[c.P] - Mp;
     T rr = (T)r64;
     r[c.P] = rr;
@@ -1037,7 +1054,7 @@ __global__ void __launch_bounds__(BLOCK) k_correct(const Slot *slots, const int2
   const SlotCtl &ctl = *B.ctl;
   if (!ctl.active) return;
   const int d = s.dim;
-  const int64_t nc = s.nc;
+  const int nc = s.nc;
   const double *p = ctl.mode ? s.p_cr : s.p_vd;
   const double *phiH = s.phiH;
   const R *rAU = (const R *)s.rAU, *HbyA = (const R *)s.HbyA;
@@ -1049,7 +1066,7 @@ __global__ void __launch_bounds__(BLOCK) k_correct(const Slot *slots, const int2
   const int with_st = ctl.with_st;
   bool bad = false;
   for_cells(s, B.lb, [&](const Cell &c) {
-    for_owned_faces(s, c, [&](int, int64_t fi, const FView &v) {
+    for_owned_faces(s, c, [&](int, int fi, const FView &v) {
       double ph = phiH[fi];
       if (v.type == F_INT) {
         double cf = (0.5 * ((double)rAU[v.lo] + (double)rAU[v.hi])) * Sh;
@@ -1066,10 +1083,10 @@ __global__ void __launch_bounds__(BLOCK) k_correct(const Slot *slots, const int2
       if (!(fl & 0x40)) {
         double qv[2];
         for (int sd = 0; sd < 2; ++sd) {
-          CFace cf = cell_face(s, fl, c.i, c.j, c.k, 2 * cc + sd);
+          CFace cf = cell_face(s, fl, c, 2 * cc + sd);
           double qq = 0.0;
           if (cf.type == F_INT) {
-            int64_t lo = sd ? c.P : cf.nb, hi = sd ? cf.nb : c.P;
+            int lo = sd ? c.P : cf.nb, hi = sd ? cf.nb : c.P;
             double ff = with_st ? st_face<R>(s, kap, a, lo, hi) : 0.0;
             qq = ff - (p[hi] - p[lo]) / h;
           } else if (cf.type == F_OUTLET) {
@@ -1100,7 +1117,7 @@ __global__ void __launch_bounds__(BLOCK) k_finalize(const Slot *slots, const int
   R *U = (R *)s.U;
   for_cells(s, B.lb, [&](const Cell &c) {
     for (int cc = 0; cc < s.dim; ++cc) {
-      int64_t x = cc * s.nc + c.P;
+      int x = cc * s.nc + c.P;
       U[x] = Uvd[x] + Us[x] / (R)ctl.n_sub;
     }
     s.p[c.P] = s.p_vd[c.P] + s.p_cr[c.P];

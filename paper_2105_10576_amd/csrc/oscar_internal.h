@@ -22,7 +22,9 @@ constexpr int NVAL = 4;      // values per reduction channel
 // value at part[(ch*NVAL + m)*nblocks + block]; the consumer (the next
 // kernel that needs the total, or a one-block-per-slot finaliser) sums the
 // partials of its slot in a fixed order.  No atomics, no cache flushes.
-enum : int { CH_ADV1 = 0, CH_ADV2 = 1, CH_SETUP = 2, CH_NORM = 3, CH_CG = 4, CH_REF = 5, NCH = 6 };
+// CH_CG0/CH_CG1: the CG reduction of iteration it goes to CH_CG0 + (it & 1)
+// and is read by iteration it + 1, so no launch reads a channel it writes.
+enum : int { CH_ADV1 = 0, CH_ADV2 = 1, CH_SETUP = 2, CH_NORM = 3, CH_CG0 = 4, CH_CG1 = 5, CH_REF = 6, NCH = 7 };
 
 // Per-slot scalars written by one block (block 0 of a kernel, or a
 // finaliser) and read by later kernels.
@@ -45,7 +47,7 @@ struct SlotCtl {
 
 struct Slot {
   int32_t dim, nx, ny, nz;
-  int64_t nc, nf0, nf1, nf2, nftot;
+  int32_t nc, nf0, nf1, nf2, nftot, nxy;   // counts (the host keeps them below 2^31)
   int32_t block0, nblocks, n_fluid, precision;
   int32_t bcf[6];               // face type of each box side
   double h, V, S, Sh, S2h, hh, delta, cos_t, sin_t;
