@@ -36,12 +36,12 @@ def cg_bytes_per_fluid_cell(precision):
     return 6 * w + x + 4 * w + x
 
 
-def run_gpu(case, precision, steps, warmup, timing=True):
+def run_gpu(case, precision, steps, warmup, timing=True, precond=0):
     import torch
 
     from paper_2105_10576_amd import oscar
 
-    g = oscar.Oscar(case, precision=precision, device="cuda:0")
+    g = oscar.Oscar(case, precision=precision, device="cuda:0", precond=precond)
     n_sub = case["n_sub"]
     for _ in range(warmup):
         g.step(max_iters=n_sub, tol=0.0)
@@ -95,6 +95,8 @@ def main():
     ap.add_argument("--no-serving", action="store_true", help="skip the batched-serving measurement")
     ap.add_argument("--pmc-calibration", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device-to-device (calibrates rocprofv3 FETCH_SIZE/WRITE_SIZE)")
+    ap.add_argument("--precond", choices=["mg", "jacobi"], default="mg",
+                    help="preconditioner of the pressure conjugate gradient")
     ap.add_argument("--serving-requests", type=int, default=64)
     ap.add_argument("--serving-max-iters", type=int, default=40,
                     help="cap on relaxation sub-steps per serving request (the mix allows up to 200)")
@@ -125,7 +127,8 @@ def main():
     n_fluid = int((case["mask"] == 0).sum())
     n_sub = case["n_sub"]
 
-    mixed = run_gpu(case, 1, args.steps, args.warmup)
+    pc = 1 if args.precond == "mg" else 0
+    mixed = run_gpu(case, 1, args.steps, args.warmup, precond=pc)
     value = mixed["iters"] * nc / mixed["seconds"] / 1e6
     ms_step = 1e3 * mixed["seconds"] / args.steps
 
@@ -168,7 +171,7 @@ def main():
         },
     }
     if not args.no_fp64:
-        f = run_gpu(case, 0, args.fp64_steps, 1)
+        f = run_gpu(case, 0, args.fp64_steps, 1, precond=pc)
         ms64, n64 = f["kernel_times"]
         avg64 = ms64 / 1e3 / max(n64, 1)
         b64 = n_fluid * cg_bytes_per_fluid_cell(0) + nc

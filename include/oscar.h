@@ -62,6 +62,11 @@ extern "C" {
 #define OSCAR_FP64 0               /* every field and solve in double precision */
 #define OSCAR_MIXED 1              /* FP32 fields, stencils and CG; FP64 pressure, refinement residual, dots, mass sums */
 
+/* preconditioner of the pressure conjugate gradient (oscar_desc.precond) */
+#define OSCAR_PC_JACOBI 0          /* diagonal scaling */
+#define OSCAR_PC_MG 1              /* one geometric multigrid V-cycle: 2^dim-cell aggregation, damped Jacobi
+                                      smoothing, coefficients re-coarsened at every solve */
+
 /* field identifiers for oscar_get_field / oscar_set_field */
 #define OSCAR_FIELD_ALPHA 0        /* cells */
 #define OSCAR_FIELD_U 1            /* global velocity U_vd + (1/N) sum u_cr (dim*cells) */
@@ -96,6 +101,8 @@ typedef struct {
   int32_t n_corr;                   /* PISO correctors per step (the paper uses 3), >= 1 */
   double pcg_rtol;                  /* relative 2-norm residual of each pressure solve (mixed: of the FP64 refinement) */
   int32_t pcg_max_it;               /* conjugate-gradient iteration cap per solve */
+  int32_t precond;                  /* OSCAR_PC_JACOBI (also the zero value) or OSCAR_PC_MG; the serving
+                                       engine accepts OSCAR_PC_JACOBI only */
 } oscar_desc;
 
 typedef struct {
@@ -172,14 +179,15 @@ void oscar_destroy(oscar_ctx *ctx);
  * oscar_create / engine failure when ctx is NULL.  Never NULL. */
 const char *oscar_last_error(const oscar_ctx *ctx);
 
-/* Measurement hook (not part of the method): when enabled, every launch of
- * the conjugate-gradient iteration kernel is bracketed by HIP events on the
- * context's stream.  oscar_timing(ctx, 1) resets and starts the totals,
- * oscar_timing(ctx, 0) stops.  oscar_timing_read(ctx, 0, ...) returns the
- * summed kernel time [ms] and the number of launches that performed an
- * iteration (launches enqueued past the device-side convergence test exit
- * at once and are not counted); kernel 1 is reserved and reads zero.  It
- * synchronises the stream. */
+/* Measurement hook (not part of the method): when enabled, every
+ * conjugate-gradient iteration is bracketed by HIP events on the context's
+ * stream (with OSCAR_PC_JACOBI the one iteration kernel; with OSCAR_PC_MG
+ * the search-direction kernel and the launches of one V-cycle).
+ * oscar_timing(ctx, 1) resets and starts the totals, oscar_timing(ctx, 0)
+ * stops.  oscar_timing_read(ctx, 0, ...) returns the summed time [ms] and
+ * the number of bracketed iterations that did work (iterations enqueued past
+ * the device-side convergence test exit at once and are not counted);
+ * kernel 1 is reserved and reads zero.  It synchronises the stream. */
 int32_t oscar_timing(oscar_ctx *ctx, int32_t enable);
 int32_t oscar_timing_read(oscar_ctx *ctx, int32_t kernel, double *total_ms, int64_t *launches);
 

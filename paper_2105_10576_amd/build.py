@@ -9,7 +9,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liboscar.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["kernels.hip", "api.hip"]
+SOURCES = ["kernels.hip", "mg.hip", "api.hip"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     # no fused multiply-add: every operation rounds once, like the FP64 reference
@@ -20,7 +20,7 @@ FLAGS = [
 ]
 
 
-def build(verbose=False, jobs=2):
+def build(verbose=False):
     objs = []
     procs = []
     for src in SOURCES:

@@ -59,6 +59,29 @@ struct Carver {
   }
 };
 
+// Multigrid hierarchy: halve every dimension (rounding up) until a level
+// has at most MG_COARSEST cells (at most MG_MAXL levels); levels of at most
+// MG_TAIL_CELLS cells are run by the single-workgroup tail kernel.
+void mg_levels(const oscar_desc &D, MGInfo &mg) {
+  int nx = D.nx, ny = D.ny, nz = D.nz;
+  mg.L = 0;
+  mg.tail = 0;
+  do {
+    nx = (nx + 1) / 2;
+    ny = (ny + 1) / 2;
+    nz = D.dim == 3 ? (nz + 1) / 2 : 1;
+    MGLevel &v = mg.lv[++mg.L];
+    v.nx = nx;
+    v.ny = ny;
+    v.nz = nz;
+    v.nxy = nx * ny;
+    v.nc = nx * ny * nz;
+    v.nblocks = 0;
+    if (!mg.tail && v.nc <= MG_TAIL_CELLS) mg.tail = mg.L;
+  } while (mg.lv[mg.L].nc > MG_COARSEST && mg.L < MG_MAXL);
+  if (!mg.tail) mg.tail = mg.L;
+}
+
 // Lay out one slot's arrays (and, with `ctl_block`, its table entries).
 void layout(const oscar_desc &D, Carver &cv, Slot *s, bool ctl_block) {
   Dims g = dims_of(D);
@@ -77,6 +100,16 @@ void layout(const oscar_desc &D, Carver &cv, Slot *s, bool ctl_block) {
   double **dbl[] = {&s->p_vd, &s->p_cr, &s->p, &s->rhs, &s->Mp};
   for (double **p : dbl) *p = (double *)cv.take(8 * nc);
   s->r64 = nullptr;
+  memset(&s->mg, 0, sizeof s->mg);
+  if (D.precond == OSCAR_PC_MG) {
+    mg_levels(D, s->mg);
+    for (int l = 1; l <= s->mg.L; ++l) {
+      MGLevel &v = s->mg.lv[l];
+      for (int e = 0; e < d; ++e) v.cf[e] = cv.take(w * v.nc);
+      void **arr[] = {&v.cout, &v.invD, &v.b, &v.x, &v.t};
+      for (void **p : arr) *p = cv.take(w * v.nc);
+    }
+  }
   s->part = (double *)cv.take(8ull * NCH * NVAL * g.nblocks);
   s->st = (SlotState *)cv.take(sizeof(SlotState));
   s->ctl = (SlotCtl *)cv.take(sizeof(SlotCtl));
@@ -101,11 +134,25 @@ int check_desc(const oscar_desc *D, std::string &why) {
   if (!(D->sigma >= 0) || !std::isfinite(D->sigma)) { why = "sigma must be >= 0"; return OSCAR_E_ARG; }
   if (!std::isfinite(D->theta_deg) || !std::isfinite(D->u_inlet)) { why = "theta and u_inlet must be finite"; return OSCAR_E_ARG; }
   if (D->precision != OSCAR_FP64 && D->precision != OSCAR_MIXED) { why = "unknown precision"; return OSCAR_E_ARG; }
+  if (D->precond != OSCAR_PC_JACOBI && D->precond != OSCAR_PC_MG) { why = "unknown preconditioner"; return OSCAR_E_ARG; }
+  if (D->precond == OSCAR_PC_MG) {
+    MGInfo mg;
+    mg_levels(*D, mg);
+    if (mg.lv[mg.L].nc > MG_LDS_CELLS) { why = "grid too large for the multigrid hierarchy"; return OSCAR_E_ARG; }
+  }
   if (D->n_corr < 1 || D->n_corr > 64) { why = "n_corr must be in [1, 64]"; return OSCAR_E_ARG; }
   if (!(D->pcg_rtol > 0) || D->pcg_max_it < 1) { why = "pcg_rtol must be > 0 and pcg_max_it >= 1"; return OSCAR_E_ARG; }
   for (int f = 0; f < 2 * D->dim; ++f)
     if (D->bc[f] < OSCAR_BC_WALL || D->bc[f] > OSCAR_BC_OUTLET) { why = "unknown boundary type"; return OSCAR_E_ARG; }
   return OSCAR_OK;
+}
+
+// bit f set when box side f (f < 2*dim) is an outlet
+uint32_t outlet_mask(const Slot &s) {
+  uint32_t m = 0;
+  for (int f = 0; f < 2 * s.dim; ++f)
+    if (s.bcf[f] == F_OUTLET) m |= 1u << f;
+  return m;
 }
 
 // per-cell face flags (bit f: neighbour across face f is fluid and inside the
@@ -275,10 +322,20 @@ static int read_state(oscar_ctx *c) {
 // conjugate-gradient iterations it0 .. it0+n-1; with timing on, each launch
 // is bracketed by events
 template <typename R>
+static void launch_iteration(oscar_ctx *c, const Launch &L, int it) {
+  if (c->D.precond == OSCAR_PC_MG) {
+    launch_mg_dir<R>(L, it);
+    launch_mg_vcycle<R>(c->s, L, it);
+  } else {
+    launch_cg_iters<R>(L, it, 1);
+  }
+}
+
+template <typename R>
 static int enqueue_cg(oscar_ctx *c, int it0, int n) {
   Launch L = c->L();
   if (!c->timing) {
-    launch_cg_iters<R>(L, it0, n);
+    for (int x = 0; x < n; ++x) launch_iteration<R>(c, L, it0 + x);
     HIPCHK(c, hipGetLastError());
     return OSCAR_OK;
   }
@@ -296,7 +353,7 @@ static int enqueue_cg(oscar_ctx *c, int it0, int n) {
   }
   for (int x = 0; x < n; ++x) {
     HIPCHK(c, hipEventRecord(c->ev[c->ev_used++], c->stream));
-    launch_cg_iters<R>(L, it0 + x, 1);
+    launch_iteration<R>(c, L, it0 + x);
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipEventRecord(c->ev[c->ev_used++], c->stream));
   }
@@ -416,6 +473,7 @@ extern "C" int32_t oscar_create(const oscar_desc *desc, void *ws, uint64_t bytes
   s.precision = desc->precision;
   for (int f = 0; f < 6; ++f)
     s.bcf[f] = desc->bc[f] == OSCAR_BC_INLET ? F_INLET : (desc->bc[f] == OSCAR_BC_OUTLET ? F_OUTLET : F_WALL);
+  s.outlet = outlet_mask(s);
   const double h = desc->h;
   s.h = h;
   s.V = desc->dim == 3 ? h * h * h : h * h;
@@ -495,10 +553,16 @@ static int solve_pressure(oscar_ctx *c, int &iters) {
   c->refine_stall = false;
   int start_total = c->h_state->total_it;
   const int max_it = c->D.pcg_max_it;
-  // one CG solve: w_0 = A D^-1 r_0, then chunks of iterations from index 0
-  // until the device flags the solve done
+  // one CG solve: w_0 = A D^-1 r_0 (Jacobi) or the V-cycle of r_0 (MG),
+  // then chunks of iterations from index 0 until the device flags it done
+  const bool mg = c->D.precond == OSCAR_PC_MG;
+  if (mg) {   // coarse operators of this equation's coefficients
+    launch_mg_setup<R>(c->s, c->d_slot, c->stream);
+    HIPCHK(c, hipGetLastError());
+  }
   auto inner = [&](int &pred) -> int {
-    launch_cg_init<R>(c->L());
+    if (mg) launch_mg_vcycle<R>(c->s, c->L(), -1);   // z_0 = B r_0
+    else launch_cg_init<R>(c->L());
     HIPCHK(c, hipGetLastError());
     int it0 = 0;
     int chunk = pred > 2 ? pred : 2;
@@ -1033,6 +1097,7 @@ extern "C" int32_t oscar_engine_admit(oscar_engine *e, const oscar_desc *desc, d
   int rc = check_desc(desc, why);
   if (rc) { e->err = why; return rc; }
   if (desc->precision != e->precision) { e->err = "descriptor precision differs from the engine's"; return OSCAR_E_ARG; }
+  if (desc->precond != OSCAR_PC_JACOBI) { e->err = "the engine runs Jacobi-preconditioned solves only"; return OSCAR_E_ARG; }
   if (!desc->mask || !desc->alpha0) { e->err = "mask and alpha0 must be non-NULL"; return OSCAR_E_ARG; }
   if (!(dt_vd > 0.0) || n_sub < 1 || max_iters < 1 || max_iters > n_sub || !(tol >= 0.0)) {
     e->err = "need dt_vd > 0, n_sub >= 1, 1 <= max_iters <= n_sub, tol >= 0";
@@ -1088,6 +1153,7 @@ extern "C" int32_t oscar_engine_admit(oscar_engine *e, const oscar_desc *desc, d
   s.precision = desc->precision;
   for (int f = 0; f < 6; ++f)
     s.bcf[f] = desc->bc[f] == OSCAR_BC_INLET ? F_INLET : (desc->bc[f] == OSCAR_BC_OUTLET ? F_OUTLET : F_WALL);
+  s.outlet = outlet_mask(s);
   const double h = desc->h;
   s.h = h;
   s.V = desc->dim == 3 ? h * h * h : h * h;

@@ -1,0 +1,330 @@
+// Device helpers shared by the OSCAR kernels: indexing and boundary
+// classification of a slot's voxel grid, deterministic block/slot
+// reductions, mixture properties, and the matrix-free pressure operator.
+#pragma once
+#include "oscar_internal.h"
+
+namespace oscar {
+
+struct Cell {
+  int P;
+  int i, j, k, row;   // row = j + ny*k
+  bool valid;
+};
+
+// A kernel's register copy of a slot's grid constants, read once at kernel
+// start: stores through the field pointers may alias the slot record, so
+// reading the record inside a loop would force a memory round trip per use.
+struct Grid {
+  int dim, nx, ny, nz, nxy, nc, nblocks;
+  uint32_t outlet;   // bit f: box side f is an outlet
+  double Sh, S2h;
+};
+
+__device__ __forceinline__ Grid grid_of(const Slot &s) {
+  Grid g;
+  g.dim = s.dim;
+  g.nx = s.nx;
+  g.ny = s.ny;
+  g.nz = s.nz;
+  g.nxy = s.nxy;
+  g.nc = s.nc;
+  g.nblocks = s.nblocks;
+  g.outlet = s.outlet;
+  g.Sh = s.Sh;
+  g.S2h = s.S2h;
+  return g;
+}
+
+struct Block {
+  const Slot *s;
+  const SlotCtl *ctl;
+  SlotState *st;
+  int lb;
+};
+
+// cell coordinates from the linear index (32-bit unsigned arithmetic)
+__device__ __forceinline__ Cell cell_at(const Slot &s, int g) {
+  Cell c;
+  c.valid = true;
+  c.P = g;
+  unsigned ug = (unsigned)g, nx = (unsigned)s.nx, ny = (unsigned)s.ny;
+  unsigned row = ug / nx;
+  c.i = (int)(ug - row * nx);
+  c.row = (int)row;
+  unsigned k = row / ny;
+  c.j = (int)(row - k * ny);
+  c.k = (int)k;
+  return c;
+}
+
+// grid-stride loop over the cells of the slot handled by block lb
+template <class Fn>
+__device__ __forceinline__ void for_cells(const Slot &s, int lb, Fn &&fn) {
+  const int stride = s.nblocks * BLOCK, nc = s.nc;
+  for (int g = lb * BLOCK + (int)threadIdx.x; g < nc; g += stride) fn(cell_at(s, g));
+}
+
+__device__ __forceinline__ Cell cell_at(const Grid &G, int g) {
+  Cell c;
+  c.valid = true;
+  c.P = g;
+  unsigned ug = (unsigned)g, nx = (unsigned)G.nx, ny = (unsigned)G.ny;
+  unsigned row = ug / nx;
+  c.i = (int)(ug - row * nx);
+  c.row = (int)row;
+  unsigned k = row / ny;
+  c.j = (int)(row - k * ny);
+  c.k = (int)k;
+  return c;
+}
+
+template <class Fn>
+__device__ __forceinline__ void for_cells(const Grid &G, int lb, Fn &&fn) {
+  const int stride = G.nblocks * BLOCK;
+  for (int g = lb * BLOCK + (int)threadIdx.x; g < G.nc; g += stride) fn(cell_at(G, g));
+}
+
+__device__ __forceinline__ int cidx(const Slot &s, int i, int j, int k) { return i + s.nx * (j + s.ny * k); }
+
+__device__ __forceinline__ int fidx(const Slot &s, int e, int i, int j, int k) {
+  if (e == 0) return i + (s.nx + 1) * (j + s.ny * k);
+  if (e == 1) return s.nf0 + i + s.nx * (j + (s.ny + 1) * k);
+  return s.nf0 + s.nf1 + i + s.nx * (j + s.ny * k);
+}
+
+__device__ __forceinline__ bool solid_at(const Slot &s, int P) { return (s.flags[P] & 0x40) != 0; }
+
+// offset between a cell and its neighbour across face f
+__device__ __forceinline__ int nb_step(const Slot &s, int f) {
+  int e = f >> 1;
+  int st = e == 0 ? 1 : (e == 1 ? s.nx : s.nxy);
+  return (f & 1) ? st : -st;
+}
+
+// face f of the cell lies on the box side (no neighbour inside the box)
+__device__ __forceinline__ bool on_edge(const Slot &s, const Cell &c, int f) {
+  int e = f >> 1;
+  if (e == 0) return (f & 1) ? c.i == s.nx - 1 : c.i == 0;
+  if (e == 1) return (f & 1) ? c.j == s.ny - 1 : c.j == 0;
+  return (f & 1) ? c.k == s.nz - 1 : c.k == 0;
+}
+
+// face f (0..5 = x-,x+,y-,y+,z-,z+) of a fluid cell
+struct CFace {
+  int type;
+  int nb, fi;
+};
+
+__device__ __forceinline__ CFace cell_face(const Slot &s, uint8_t fl, const Cell &c, int f) {
+  CFace r;
+  int e = f >> 1, hi = f & 1;
+  r.nb = -1;
+  r.fi = -1;
+  if (e >= s.dim) { r.type = F_NONE; return r; }
+  if (e == 0) r.fi = c.P + c.row + hi;
+  else if (e == 1) r.fi = s.nf0 + c.P + s.nx * c.k + (hi ? s.nx : 0);
+  else r.fi = s.nf0 + s.nf1 + c.P + (hi ? s.nxy : 0);
+  if (fl & (1u << f)) { r.type = F_INT; r.nb = c.P + nb_step(s, f); return r; }
+  r.type = on_edge(s, c, f) ? s.bcf[f] : F_WALL;
+  return r;
+}
+
+// face of direction e whose high-side cell is (i,j,k) (coordinate along e in [0, n_e])
+struct FView {
+  int type;
+  int lo, hi, P;
+  double sf;   // orientation sign seen from the fluid cell (WALL / INLET / OUTLET)
+};
+
+__device__ __forceinline__ FView face_view(const Slot &s, int e, int i, int j, int k) {
+  FView v;
+  int li = i - (e == 0), lj = j - (e == 1), lk = k - (e == 2);
+  bool loin = (e == 0 ? li >= 0 : (e == 1 ? lj >= 0 : lk >= 0));
+  bool hiin = (e == 0 ? i < s.nx : (e == 1 ? j < s.ny : k < s.nz));
+  v.lo = loin ? cidx(s, li, lj, lk) : -1;
+  v.hi = hiin ? cidx(s, i, j, k) : -1;
+  bool lof = loin && !solid_at(s, v.lo);
+  bool hif = hiin && !solid_at(s, v.hi);
+  v.type = F_NONE;
+  v.P = -1;
+  v.sf = 0.0;
+  if (lof && hif) { v.type = F_INT; return v; }
+  if (!lof && !hif) return v;
+  if (lof) { v.P = v.lo; v.sf = 1.0; } else { v.P = v.hi; v.sf = -1.0; }
+  if (loin && hiin) { v.type = F_WALL; return v; }
+  v.type = s.bcf[2 * e + (lof ? 1 : 0)];
+  return v;
+}
+
+// visit the faces owned by the thread of cell c: (e, fi, view)
+template <class Fn>
+__device__ __forceinline__ void for_owned_faces(const Slot &s, const Cell &c, Fn &&fn) {
+  for (int e = 0; e < s.dim; ++e) {
+    fn(e, fidx(s, e, c.i, c.j, c.k), face_view(s, e, c.i, c.j, c.k));
+    bool last = e == 0 ? c.i == s.nx - 1 : (e == 1 ? c.j == s.ny - 1 : c.k == s.nz - 1);
+    if (last) {
+      int i = c.i + (e == 0), j = c.j + (e == 1), k = c.k + (e == 2);
+      fn(e, fidx(s, e, i, j, k), face_view(s, e, i, j, k));
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// deterministic per-slot reductions
+// ---------------------------------------------------------------------------
+
+template <unsigned MAXMASK, int M>
+__device__ __forceinline__ void wave_reduce(double (&v)[M]) {
+#pragma unroll
+  for (int m = 0; m < M; ++m) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      double o = __shfl_down(v[m], off, 64);
+      if ((MAXMASK >> m) & 1u) v[m] = o > v[m] ? o : v[m];
+      else v[m] = v[m] + o;
+    }
+  }
+}
+
+// Block-level reduction of v (fixed order); every thread receives the totals.
+template <unsigned MAXMASK, int M>
+__device__ __forceinline__ void block_reduce(double (&v)[M]) {
+  __shared__ double sh[M][BLOCK / 64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  wave_reduce<MAXMASK>(v);
+  __syncthreads();
+  if (lane == 0)
+#pragma unroll
+    for (int m = 0; m < M; ++m) sh[m][w] = v[m];
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < M; ++m) {
+    double t = sh[m][0];
+    for (int x = 1; x < BLOCK / 64; ++x) t = ((MAXMASK >> m) & 1u) ? (sh[m][x] > t ? sh[m][x] : t) : t + sh[m][x];
+    v[m] = t;
+  }
+}
+
+// publish this block's partials of channel ch
+template <unsigned MAXMASK, int M>
+__device__ __forceinline__ void put_partials(const Slot &s, int lb, int ch, double (&v)[M]) {
+  block_reduce<MAXMASK>(v);
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int m = 0; m < M; ++m) s.part[(int)(ch * NVAL + m) * s.nblocks + lb] = v[m];
+}
+
+// totals of channel ch over the slot's blocks, in every thread (fixed
+// order: each thread sums blocks tid, tid + BLOCK, ... in turn; the loads of
+// four strides are issued together)
+template <unsigned MAXMASK, int M>
+__device__ __forceinline__ void get_totals(const Slot &s, int ch, double (&v)[M]) {
+  const int nb = s.nblocks;
+  const double *base = s.part + (int)(ch * NVAL) * nb;
+  double t[M];
+#pragma unroll
+  for (int m = 0; m < M; ++m) t[m] = 0.0;
+  int b = threadIdx.x;
+  for (; b + 3 * BLOCK < nb; b += 4 * BLOCK) {
+    double x[M][4];
+#pragma unroll
+    for (int m = 0; m < M; ++m)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) x[m][u] = base[m * nb + b + u * BLOCK];
+#pragma unroll
+    for (int m = 0; m < M; ++m)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) t[m] = ((MAXMASK >> m) & 1u) ? (x[m][u] > t[m] ? x[m][u] : t[m]) : t[m] + x[m][u];
+  }
+  for (; b < nb; b += BLOCK)
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      double x = base[m * nb + b];
+      t[m] = ((MAXMASK >> m) & 1u) ? (x > t[m] ? x : t[m]) : t[m] + x;
+    }
+#pragma unroll
+  for (int m = 0; m < M; ++m) v[m] = t[m];
+  block_reduce<MAXMASK>(v);
+}
+
+// ---------------------------------------------------------------------------
+// mixture properties
+// ---------------------------------------------------------------------------
+
+template <typename R>
+__device__ __forceinline__ R rho_of(const Slot &s, R a) {
+  return a * (R)s.rho1 + ((R)1 - a) * (R)s.rho2;
+}
+template <typename R>
+__device__ __forceinline__ R mu_of(const Slot &s, R a) {
+  return a * (R)s.mu1 + ((R)1 - a) * (R)s.mu2;
+}
+
+template <typename R>
+__device__ __forceinline__ R vnorm(const R *v, int d) {
+  R t = v[0] * v[0] + v[1] * v[1];
+  if (d == 3) t = t + v[2] * v[2];
+  return sqrt(t);
+}
+
+// surface-tension face term sigma*kappa_f*(alpha_hi - alpha_lo)/h, in FP64
+// (it is balanced against the pressure gradient on the same face)
+template <typename R>
+__device__ __forceinline__ double st_face(const Slot &s, const R *kap, const R *a, int lo, int hi) {
+  return (s.sigma * (0.5 * ((double)kap[lo] + (double)kap[hi]))) * (((double)a[hi] - (double)a[lo]) / s.h);
+}
+
+// pressure coefficient of face f of fluid cell P in precision X
+template <typename X, typename R>
+__device__ __forceinline__ X pcoef(const Slot &s, const R *rAU, int P, const CFace &cf) {
+  if (cf.type == F_INT) return ((X)0.5 * ((X)rAU[P] + (X)rAU[cf.nb])) * (X)s.Sh;
+  if (cf.type == F_OUTLET) return (X)rAU[P] * (X)s.S2h;
+  return (X)0;
+}
+
+// face f of cell c lies on the box side
+__device__ __forceinline__ bool on_edge(const Grid &G, const Cell &c, int f) {
+  int e = f >> 1;
+  if (e == 0) return (f & 1) ? c.i == G.nx - 1 : c.i == 0;
+  if (e == 1) return (f & 1) ? c.j == G.ny - 1 : c.j == 0;
+  return (f & 1) ? c.k == G.nz - 1 : c.k == 0;
+}
+
+// (M x)_P in precision X, with x read through a functor xv(index).  All six
+// faces are unrolled and every neighbour value is read unconditionally, at
+// the cell itself where the face is not interior (faces 4 and 5 in 2D), so
+// the loads issue together; the sum is taken face by face in the order
+// x-, x+, y-, y+, z-, z+, adding only interior and outlet terms, which is
+// the operation order of the sequential reference.
+// Same, with x read through xf(index, f): f = -1 for the cell itself, else
+// the face across which the (interior) neighbour lies.
+template <typename X, typename R, class XF>
+__device__ __forceinline__ X matvec_row_f(const Grid &G, const R *rAU, const Cell &c, uint8_t fl, XF &&xf) {
+  const int P = c.P;
+  const int st[6] = {-1, 1, -G.nx, G.nx, -G.nxy, G.nxy};
+  const X xP = xf(P, -1);
+  const X rP = (X)rAU[P];
+  X xn[6], rn[6];
+#pragma unroll
+  for (int f = 0; f < 6; ++f) {
+    const bool in = (fl >> f) & 1u;
+    const int n = in ? P + st[f] : P;
+    xn[f] = xf(n, in ? f : -1);
+    rn[f] = (X)rAU[n];
+  }
+  X acc = (X)0;
+#pragma unroll
+  for (int f = 0; f < 6; ++f) {
+    if ((fl >> f) & 1u) acc = acc + (((X)0.5 * (rP + rn[f])) * (X)G.Sh) * (xP - xn[f]);
+    else if (((G.outlet >> f) & 1u) && on_edge(G, c, f)) acc = acc + (rP * (X)G.S2h) * xP;
+  }
+  return acc;
+}
+
+template <typename X, typename R, class XV>
+__device__ __forceinline__ X matvec_row(const Grid &G, const R *rAU, const Cell &c, uint8_t fl, XV &&xv) {
+  return matvec_row_f<X, R>(G, rAU, c, fl, [&](int n, int) { return xv(n); });
+}
+
+}  // namespace oscar

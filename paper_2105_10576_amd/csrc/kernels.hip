@@ -19,26 +19,13 @@
 // written operation by operation (no fused multiply-add: built with
 // -ffp-contract=off) so that the FP64 instantiation rounds exactly like the
 // sequential double-precision reference.
-#include "oscar_internal.h"
+#include "device_common.h"
 
 namespace oscar {
 
 // ---------------------------------------------------------------------------
 // indexing and boundary classification
 // ---------------------------------------------------------------------------
-
-struct Cell {
-  int P;
-  int i, j, k, row;   // row = j + ny*k
-  bool valid;
-};
-
-struct Block {
-  const Slot *s;
-  const SlotCtl *ctl;
-  SlotState *st;
-  int lb;
-};
 
 // a zeroed (inactive) control block for padding entries of a block table
 __device__ SlotCtl g_padding_ctl;
@@ -51,194 +38,6 @@ __device__ __forceinline__ Block block_of(const Slot *slots, const int2 *btab) {
   b.st = b.s->st;
   b.lb = t.y;
   return b;
-}
-
-// cell coordinates from the linear index (32-bit unsigned arithmetic)
-__device__ __forceinline__ Cell cell_at(const Slot &s, int g) {
-  Cell c;
-  c.valid = true;
-  c.P = g;
-  unsigned ug = (unsigned)g, nx = (unsigned)s.nx, ny = (unsigned)s.ny;
-  unsigned row = ug / nx;
-  c.i = (int)(ug - row * nx);
-  c.row = (int)row;
-  unsigned k = row / ny;
-  c.j = (int)(row - k * ny);
-  c.k = (int)k;
-  return c;
-}
-
-// grid-stride loop over the cells of the slot handled by block lb
-template <class Fn>
-__device__ __forceinline__ void for_cells(const Slot &s, int lb, Fn &&fn) {
-  const int stride = s.nblocks * BLOCK;
-  for (int g = lb * BLOCK + (int)threadIdx.x; g < s.nc; g += stride) fn(cell_at(s, g));
-}
-
-__device__ __forceinline__ int cidx(const Slot &s, int i, int j, int k) { return i + s.nx * (j + s.ny * k); }
-
-__device__ __forceinline__ int fidx(const Slot &s, int e, int i, int j, int k) {
-  if (e == 0) return i + (s.nx + 1) * (j + s.ny * k);
-  if (e == 1) return s.nf0 + i + s.nx * (j + (s.ny + 1) * k);
-  return s.nf0 + s.nf1 + i + s.nx * (j + s.ny * k);
-}
-
-__device__ __forceinline__ bool solid_at(const Slot &s, int P) { return (s.flags[P] & 0x40) != 0; }
-
-// offset between a cell and its neighbour across face f
-__device__ __forceinline__ int nb_step(const Slot &s, int f) {
-  int e = f >> 1;
-  int st = e == 0 ? 1 : (e == 1 ? s.nx : s.nxy);
-  return (f & 1) ? st : -st;
-}
-
-// face f of the cell lies on the box side (no neighbour inside the box)
-__device__ __forceinline__ bool on_edge(const Slot &s, const Cell &c, int f) {
-  int e = f >> 1;
-  if (e == 0) return (f & 1) ? c.i == s.nx - 1 : c.i == 0;
-  if (e == 1) return (f & 1) ? c.j == s.ny - 1 : c.j == 0;
-  return (f & 1) ? c.k == s.nz - 1 : c.k == 0;
-}
-
-// face f (0..5 = x-,x+,y-,y+,z-,z+) of a fluid cell
-struct CFace {
-  int type;
-  int nb, fi;
-};
-
-__device__ __forceinline__ CFace cell_face(const Slot &s, uint8_t fl, const Cell &c, int f) {
-  CFace r;
-  int e = f >> 1, hi = f & 1;
-  r.nb = -1;
-  r.fi = -1;
-  if (e >= s.dim) { r.type = F_NONE; return r; }
-  if (e == 0) r.fi = c.P + c.row + hi;
-  else if (e == 1) r.fi = s.nf0 + c.P + s.nx * c.k + (hi ? s.nx : 0);
-  else r.fi = s.nf0 + s.nf1 + c.P + (hi ? s.nxy : 0);
-  if (fl & (1u << f)) { r.type = F_INT; r.nb = c.P + nb_step(s, f); return r; }
-  r.type = on_edge(s, c, f) ? s.bcf[f] : F_WALL;
-  return r;
-}
-
-// face of direction e whose high-side cell is (i,j,k) (coordinate along e in [0, n_e])
-struct FView {
-  int type;
-  int lo, hi, P;
-  double sf;   // orientation sign seen from the fluid cell (WALL / INLET / OUTLET)
-};
-
-__device__ __forceinline__ FView face_view(const Slot &s, int e, int i, int j, int k) {
-  FView v;
-  int li = i - (e == 0), lj = j - (e == 1), lk = k - (e == 2);
-  bool loin = (e == 0 ? li >= 0 : (e == 1 ? lj >= 0 : lk >= 0));
-  bool hiin = (e == 0 ? i < s.nx : (e == 1 ? j < s.ny : k < s.nz));
-  v.lo = loin ? cidx(s, li, lj, lk) : -1;
-  v.hi = hiin ? cidx(s, i, j, k) : -1;
-  bool lof = loin && !solid_at(s, v.lo);
-  bool hif = hiin && !solid_at(s, v.hi);
-  v.type = F_NONE;
-  v.P = -1;
-  v.sf = 0.0;
-  if (lof && hif) { v.type = F_INT; return v; }
-  if (!lof && !hif) return v;
-  if (lof) { v.P = v.lo; v.sf = 1.0; } else { v.P = v.hi; v.sf = -1.0; }
-  if (loin && hiin) { v.type = F_WALL; return v; }
-  v.type = s.bcf[2 * e + (lof ? 1 : 0)];
-  return v;
-}
-
-// visit the faces owned by the thread of cell c: (e, fi, view)
-template <class Fn>
-__device__ __forceinline__ void for_owned_faces(const Slot &s, const Cell &c, Fn &&fn) {
-  for (int e = 0; e < s.dim; ++e) {
-    fn(e, fidx(s, e, c.i, c.j, c.k), face_view(s, e, c.i, c.j, c.k));
-    bool last = e == 0 ? c.i == s.nx - 1 : (e == 1 ? c.j == s.ny - 1 : c.k == s.nz - 1);
-    if (last) {
-      int i = c.i + (e == 0), j = c.j + (e == 1), k = c.k + (e == 2);
-      fn(e, fidx(s, e, i, j, k), face_view(s, e, i, j, k));
-    }
-  }
-}
-
-// ---------------------------------------------------------------------------
-// deterministic per-slot reductions
-// ---------------------------------------------------------------------------
-
-template <unsigned MAXMASK, int M>
-__device__ __forceinline__ void wave_reduce(double (&v)[M]) {
-#pragma unroll
-  for (int m = 0; m < M; ++m) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-      double o = __shfl_down(v[m], off, 64);
-      if ((MAXMASK >> m) & 1u) v[m] = o > v[m] ? o : v[m];
-      else v[m] = v[m] + o;
-    }
-  }
-}
-
-// Block-level reduction of v (fixed order); every thread receives the totals.
-template <unsigned MAXMASK, int M>
-__device__ __forceinline__ void block_reduce(double (&v)[M]) {
-  __shared__ double sh[M][BLOCK / 64];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  wave_reduce<MAXMASK>(v);
-  __syncthreads();
-  if (lane == 0)
-#pragma unroll
-    for (int m = 0; m < M; ++m) sh[m][w] = v[m];
-  __syncthreads();
-#pragma unroll
-  for (int m = 0; m < M; ++m) {
-    double t = sh[m][0];
-    for (int x = 1; x < BLOCK / 64; ++x) t = ((MAXMASK >> m) & 1u) ? (sh[m][x] > t ? sh[m][x] : t) : t + sh[m][x];
-    v[m] = t;
-  }
-}
-
-// publish this block's partials of channel ch
-template <unsigned MAXMASK, int M>
-__device__ __forceinline__ void put_partials(const Slot &s, int lb, int ch, double (&v)[M]) {
-  block_reduce<MAXMASK>(v);
-  if (threadIdx.x == 0)
-#pragma unroll
-    for (int m = 0; m < M; ++m) s.part[(int)(ch * NVAL + m) * s.nblocks + lb] = v[m];
-}
-
-// totals of channel ch over the slot's blocks, in every thread (fixed order)
-template <unsigned MAXMASK, int M>
-__device__ __forceinline__ void get_totals(const Slot &s, int ch, double (&v)[M]) {
-#pragma unroll
-  for (int m = 0; m < M; ++m) {
-    const double *p = s.part + (int)(ch * NVAL + m) * s.nblocks;
-    double t = 0.0;
-    for (int b = threadIdx.x; b < s.nblocks; b += BLOCK) {
-      double x = p[b];
-      t = ((MAXMASK >> m) & 1u) ? (x > t ? x : t) : t + x;
-    }
-    v[m] = t;
-  }
-  block_reduce<MAXMASK>(v);
-}
-
-// ---------------------------------------------------------------------------
-// mixture properties
-// ---------------------------------------------------------------------------
-
-template <typename R>
-__device__ __forceinline__ R rho_of(const Slot &s, R a) {
-  return a * (R)s.rho1 + ((R)1 - a) * (R)s.rho2;
-}
-template <typename R>
-__device__ __forceinline__ R mu_of(const Slot &s, R a) {
-  return a * (R)s.mu1 + ((R)1 - a) * (R)s.mu2;
-}
-
-template <typename R>
-__device__ __forceinline__ R vnorm(const R *v, int d) {
-  R t = v[0] * v[0] + v[1] * v[1];
-  if (d == 3) t = t + v[2] * v[2];
-  return sqrt(t);
 }
 
 // ---------------------------------------------------------------------------
@@ -366,13 +165,6 @@ __global__ void __launch_bounds__(BLOCK) k_curvature(const Slot *slots, const in
     }
     kap[c.P] = out;
   });
-}
-
-// surface-tension face term sigma*kappa_f*(alpha_hi - alpha_lo)/h, in FP64
-// (it is balanced against the pressure gradient on the same face)
-template <typename R>
-__device__ __forceinline__ double st_face(const Slot &s, const R *kap, const R *a, int lo, int hi) {
-  return (s.sigma * (0.5 * ((double)kap[lo] + (double)kap[hi]))) * (((double)a[hi] - (double)a[lo]) / s.h);
 }
 
 // ---------------------------------------------------------------------------
@@ -733,40 +525,14 @@ __global__ void __launch_bounds__(BLOCK) k_phiH(const Slot *slots, const int2 *b
   });
 }
 
-// pressure coefficient of face f of fluid cell P in precision X
-template <typename X, typename R>
-__device__ __forceinline__ X pcoef(const Slot &s, const R *rAU, int P, const CFace &cf) {
-  if (cf.type == F_INT) return ((X)0.5 * ((X)rAU[P] + (X)rAU[cf.nb])) * (X)s.Sh;
-  if (cf.type == F_OUTLET) return (X)rAU[P] * (X)s.S2h;
-  return (X)0;
-}
-
-// (M x)_P in precision X, with x read through a functor xv(index).  The
-// neighbour values are read at a safe index (the cell itself when the face
-// is not interior) before the face type is known, so the loads do not wait
-// for the flag byte; the arithmetic is that of pcoef.
-template <typename X, typename R, class XV>
-__device__ __forceinline__ X matvec_row(const Slot &s, const R *rAU, const Cell &c, uint8_t fl, XV &&xv) {
-  X acc = (X)0;
-  const X xP = xv(c.P);
-  const X rP = (X)rAU[c.P];
-  for (int f = 0; f < 2 * s.dim; ++f) {
-    const bool in = (fl >> f) & 1u;
-    const int n = in ? c.P + nb_step(s, f) : c.P;
-    const X xn = xv(n);
-    const X rn = (X)rAU[n];
-    if (in) acc = acc + (((X)0.5 * (rP + rn)) * (X)s.Sh) * (xP - xn);
-    else if (on_edge(s, c, f) && s.bcf[f] == F_OUTLET) acc = acc + (rP * (X)s.S2h) * xP;
-  }
-  return acc;
-}
-
 // rhs = -div(phiH), r = rhs - M p, Jacobi diagonal
 template <typename R>
 __global__ void __launch_bounds__(BLOCK) k_pressure_setup(const Slot *slots, const int2 *btab) {
   using T = R;
   Block B = block_of(slots, btab);
   const Slot &s = *B.s;
+  const Grid G = grid_of(s);
+  const uint8_t *flags = s.flags;
   const SlotCtl &ctl = *B.ctl;
   if (!ctl.active) return;
   const R *rAU = (const R *)s.rAU;
@@ -775,8 +541,8 @@ __global__ void __launch_bounds__(BLOCK) k_pressure_setup(const Slot *slots, con
   const bool mixed = s.precision != 0;
   T *r = (T *)s.cr[0], *invD = (T *)s.invD, *e = (T *)s.e;
   double red[3] = {0.0, 0.0, 0.0};   // |rhs|^2, |rhs - M p|^2, sum p
-  for_cells(s, B.lb, [&](const Cell &c) {
-    uint8_t fl = s.flags[c.P];
+  for_cells(G, B.lb, [&](const Cell &c) {
+    uint8_t fl = flags[c.P];
     if (fl & 0x40) {
       s.rhs[c.P] = 0.0;
       s.Mp[c.P] = 0.0;
@@ -794,7 +560,7 @@ __global__ void __launch_bounds__(BLOCK) k_pressure_setup(const Slot *slots, con
       if (cf.type == F_INT || cf.type == F_OUTLET) dg = dg + pcoef<T, R>(s, rAU, c.P, cf);
     }
     double rhs = -acc;
-    double Mp = matvec_row<double, R>(s, rAU, c, fl, [&](int x) { return p[x]; });
+    double Mp = matvec_row<double, R>(G, rAU, c, fl, [&](int x) { return p[x]; });
     double r64 = rhs - Mp;
     T rr = (T)r64;
     s.rhs[c.P] = rhs;
@@ -848,15 +614,17 @@ template <typename R>
 __global__ void __launch_bounds__(BLOCK) k_normres(const Slot *slots, const int2 *btab) {
   Block B = block_of(slots, btab);
   const Slot &s = *B.s;
+  const Grid G = grid_of(s);
+  const uint8_t *flags = s.flags;
   const SlotCtl &ctl = *B.ctl;
   if (!ctl.active || ctl.mode != 1) return;
   const R *rAU = (const R *)s.rAU;
   const double pbar = B.st->pbar;
   double red[2] = {0.0, 0.0};
-  for_cells(s, B.lb, [&](const Cell &c) {
-    uint8_t fl = s.flags[c.P];
+  for_cells(G, B.lb, [&](const Cell &c) {
+    uint8_t fl = flags[c.P];
     if (fl & 0x40) return;
-    double Mpb = matvec_row<double, R>(s, rAU, c, fl, [&](int) { return pbar; });
+    double Mpb = matvec_row<double, R>(G, rAU, c, fl, [&](int) { return pbar; });
     double rhs = s.rhs[c.P], Mp = s.Mp[c.P];
     red[0] = red[0] + fabs(rhs - Mp);
     red[1] = red[1] + (fabs(Mp - Mpb) + fabs(rhs - Mpb));
@@ -889,18 +657,20 @@ __global__ void __launch_bounds__(BLOCK) k_cg_init(const Slot *slots, const int2
   using T = R;
   Block B = block_of(slots, btab);
   const Slot &s = *B.s;
+  const Grid G = grid_of(s);
+  const uint8_t *flags = s.flags;
   const SlotCtl &ctl = *B.ctl;
   if (!ctl.active || B.st->done) return;
   const R *rAU = (const R *)s.rAU;
   const T *r = (const T *)s.cr[0], *invD = (const T *)s.invD;
   T *w = (T *)s.cw[0];
   double red[3] = {0.0, 0.0, 0.0};   // <r,u>, <w,u>, <r,r>
-  for_cells(s, B.lb, [&](const Cell &c) {
-    uint8_t fl = s.flags[c.P];
+  for_cells(G, B.lb, [&](const Cell &c) {
+    uint8_t fl = flags[c.P];
     if (fl & 0x40) return;   // solid entries of the CG vectors are never read
     auto uv = [&](int x) -> T { return invD[x] * r[x]; };
     T u = uv(c.P);
-    T ww = matvec_row<T, R>(s, rAU, c, fl, uv);
+    T ww = matvec_row<T, R>(G, rAU, c, fl, uv);
     w[c.P] = ww;
     T rr = r[c.P];
     red[0] = red[0] + (double)(rr * u);
@@ -917,6 +687,8 @@ __global__ void __launch_bounds__(BLOCK) k_cg(const Slot *slots, const int2 *bta
   using T = R;
   Block B = block_of(slots, btab);
   const Slot &s = *B.s;
+  const Grid G = grid_of(s);
+  const uint8_t *flags = s.flags;
   const SlotCtl &ctl = *B.ctl;
   if (!ctl.active || B.st->done) return;
   SlotState *st = B.st;
@@ -955,24 +727,28 @@ __global__ void __launch_bounds__(BLOCK) k_cg(const Slot *slots, const int2 *bta
   const T al = (T)alpha, be = (T)beta;
   const R *rAU = (const R *)s.rAU;
   const T *invD = (const T *)s.invD;
-  const T *r0 = (const T *)s.cr[it & 1], *w0 = (const T *)s.cw[it & 1], *so = (const T *)s.cs[(it + 1) & 1];
+  // s = w + beta s_old; on the first iteration beta = 0 and s_old = w, so
+  // s = w exactly and every load is unconditional
+  const T *r0 = (const T *)s.cr[it & 1], *w0 = (const T *)s.cw[it & 1];
+  const T *so = first ? w0 : (const T *)s.cs[(it + 1) & 1];
   T *r1 = (T *)s.cr[(it + 1) & 1], *w1 = (T *)s.cw[(it + 1) & 1], *sn = (T *)s.cs[it & 1];
   T *pv = (T *)s.cp, *xe = (T *)s.e;
   double *xp = ctl.mode ? s.p_cr : s.p_vd;
   double red[3] = {0.0, 0.0, 0.0};
-  for_cells(s, B.lb, [&](const Cell &c) {
-    uint8_t fl = s.flags[c.P];
+  for_cells(G, B.lb, [&](const Cell &c) {
+    uint8_t fl = flags[c.P];
     if (fl & 0x40) return;   // solid entries of the CG vectors are never read
     // s = w + beta s_old and the updated residual, at any fluid cell
-    auto s_at = [&](int x) -> T { return first ? w0[x] : w0[x] + be * so[x]; };
+    auto s_at = [&](int x) -> T { return w0[x] + be * so[x]; };
     auto u_new = [&](int x) -> T { return invD[x] * (r0[x] - al * s_at(x)); };
     const int P = c.P;
     T u0 = invD[P] * r0[P];
-    T pn = first ? u0 : u0 + be * pv[P];
+    const T pold = pv[P];
+    T pn = first ? u0 : u0 + be * pold;
     T sP = s_at(P);
     T rn = r0[P] - al * sP;
     T un = invD[P] * rn;
-    T wn = matvec_row<T, R>(s, rAU, c, fl, u_new);
+    T wn = matvec_row<T, R>(G, rAU, c, fl, u_new);
     pv[P] = pn;
     sn[P] = sP;
     r1[P] = rn;
@@ -1008,16 +784,18 @@ __global__ void __launch_bounds__(BLOCK) k_refine_res(const Slot *slots, const i
   using T = R;
   Block B = block_of(slots, btab);
   const Slot &s = *B.s;
+  const Grid G = grid_of(s);
+  const uint8_t *flags = s.flags;
   const SlotCtl &ctl = *B.ctl;
   if (!ctl.active || s.precision == 0 || B.st->zero_rhs) return;
   const R *rAU = (const R *)s.rAU;
   const double *p = ctl.mode ? s.p_cr : s.p_vd;
   T *r = (T *)s.cr[0];
   double red[2] = {0.0, 0.0};
-  for_cells(s, B.lb, [&](const Cell &c) {
-    uint8_t fl = s.flags[c.P];
+  for_cells(G, B.lb, [&](const Cell &c) {
+    uint8_t fl = flags[c.P];
     if (fl & 0x40) return;
-    double Mp = matvec_row<double, R>(s, rAU, c, fl, [&](int x) { return p[x]; });
+    double Mp = matvec_row<double, R>(G, rAU, c, fl, [&](int x) { return p[x]; });
     double r64 = s.rhs[c.P] - Mp;
     T rr = (T)r64;
     r[c.P] = rr;

@@ -1,0 +1,627 @@
+// Geometric multigrid preconditioner for the pressure equation of the PISO
+// correctors (Section 2.2) on the voxel grid, and the conjugate gradient it
+// preconditions (Hestenes-Stiefel recurrences: one search-direction launch
+// plus one V-cycle per iteration).
+//
+// Hierarchy: coarse cell = 2 x 2 (x 2) block of the finer level.  A coarse
+// face coefficient is half the sum of the fine face coefficients crossing it
+// (the piecewise-constant Galerkin product scaled to match a rediscretisation
+// on the doubled spacing); outlet coefficients are aggregated the same way.
+// Cycle: one damped Jacobi sweep (omega = 0.8) from zero before restriction
+// and one after prolongation on every level, a fixed number of Jacobi sweeps
+// on the coarsest level; the cycle is a symmetric linear operator, as the
+// conjugate gradient needs.
+//
+// Execution: the pre-smoothing kernels walk their level in child order (the
+// 2^dim cells of one coarser cell are consecutive lanes of a wavefront), so
+// the restriction of the residual is a lane-shuffle sum inside the same
+// kernel and no restriction launch or residual array exists.  The small
+// levels (from the one the host marks as the tail down to the coarsest) run
+// inside one workgroup; the coarsest level is solved in LDS with its
+// operator held in registers.  No atomics.
+#include "device_common.h"
+
+namespace oscar {
+
+constexpr int MG_TAIL_THREADS = 1024;   // workgroup of the tail kernel
+constexpr int MG_COARSE_SWEEPS = 48;    // Jacobi sweeps on the coarsest level
+constexpr double MG_OMEGA = 0.8;        // Jacobi damping
+
+static_assert(MG_LDS_CELLS <= MG_TAIL_THREADS, "one coarsest-level cell per tail thread");
+
+struct LCell {
+  int P, i, j, k;
+};
+
+__device__ __forceinline__ LCell lcell(const MGLevel &L, int g) {
+  LCell c;
+  unsigned ug = (unsigned)g, nx = (unsigned)L.nx, ny = (unsigned)L.ny;
+  unsigned row = ug / nx;
+  c.P = g;
+  c.i = (int)(ug - row * nx);
+  unsigned k = row / ny;
+  c.j = (int)(row - k * ny);
+  c.k = (int)k;
+  return c;
+}
+
+// A kernel's register copy of one level: dimensions and array pointers.
+template <typename T>
+struct LV {
+  int nx, ny, nz, nxy, nc;
+  const T *cf[3];
+  const T *cout, *invD;
+  T *b, *x, *t;
+};
+
+template <typename T>
+__device__ __forceinline__ LV<T> lview(const MGLevel &L) {
+  LV<T> v;
+  v.nx = L.nx;
+  v.ny = L.ny;
+  v.nz = L.nz;
+  v.nxy = L.nxy;
+  v.nc = L.nc;
+  for (int e = 0; e < 3; ++e) v.cf[e] = (const T *)L.cf[e];
+  v.cout = (const T *)L.cout;
+  v.invD = (const T *)L.invD;
+  v.b = (T *)L.b;
+  v.x = (T *)L.x;
+  v.t = (T *)L.t;
+  return v;
+}
+
+__device__ __forceinline__ LCell lcell(int nx, int ny, int g) {
+  LCell c;
+  unsigned ug = (unsigned)g, row = ug / (unsigned)nx;
+  c.P = g;
+  c.i = (int)(ug - row * (unsigned)nx);
+  unsigned k = row / (unsigned)ny;
+  c.j = (int)(row - k * (unsigned)ny);
+  c.k = (int)k;
+  return c;
+}
+
+// (A x)_P on a coarse level, unrolled over the DIM directions.  xv(n, e,
+// side) returns x at cell n: the neighbour across the low (side = -1) or
+// high (+1) face of direction e, or the cell itself (side = 0), which is
+// also read where a neighbour is missing (its coefficient is zero), so all
+// loads are unconditional.
+template <int DIM, typename T, class XV>
+__device__ __forceinline__ T lmatvec(const LV<T> &L, const LCell &c, XV &&xv) {
+  const int st[3] = {1, L.nx, L.nxy};
+  const int q[3] = {c.i, c.j, c.k};
+  const int n[3] = {L.nx, L.ny, L.nz};
+  const T xP = xv(c.P, 0, 0);
+  T cl[DIM], ch[DIM], xl[DIM], xh[DIM];
+#pragma unroll
+  for (int e = 0; e < DIM; ++e) {
+    const bool lo = q[e] > 0, hi = q[e] < n[e] - 1;
+    const int pl = lo ? c.P - st[e] : c.P, ph = hi ? c.P + st[e] : c.P;
+    cl[e] = L.cf[e][c.P];
+    const T chv = L.cf[e][ph];
+    ch[e] = hi ? chv : (T)0;
+    xl[e] = xv(pl, e, lo ? -1 : 0);
+    xh[e] = xv(ph, e, hi ? 1 : 0);
+  }
+  const T co = L.cout[c.P];
+  T acc = (T)0;
+#pragma unroll
+  for (int e = 0; e < DIM; ++e) {
+    acc = acc + cl[e] * (xP - xl[e]);
+    acc = acc + ch[e] * (xP - xh[e]);
+  }
+  acc = acc + co * xP;
+  return acc;
+}
+
+// parent on the next coarser level of the neighbour across a face: moving
+// up from coordinate q changes the parent iff q is odd, down iff q is even
+__device__ __forceinline__ int parent_shift(int q, int side, int cstep) {
+  if (side > 0) return (q & 1) ? cstep : 0;
+  if (side < 0) return (q & 1) ? 0 : -cstep;
+  return 0;
+}
+
+// Child order: thread tau of a level with dims (nx, ny, nz) whose parents
+// have dims (cnx, cny, .) is child (tau mod 2^dim) of parent (tau >> dim);
+// children beyond an odd dimension are invalid and contribute zero.
+struct Kid {
+  int P, i, j, k, parent;
+  bool valid, lead;
+};
+
+__device__ __forceinline__ Kid kid_at(unsigned tau, int dim, int nx, int ny, int nz, int cnx, int cny) {
+  Kid q;
+  const unsigned ch = tau & ((1u << dim) - 1u), C = tau >> dim;
+  const unsigned crow = C / (unsigned)cnx, ck = crow / (unsigned)cny;
+  const int ci = (int)(C - crow * (unsigned)cnx), cj = (int)(crow - ck * (unsigned)cny);
+  q.i = 2 * ci + (int)(ch & 1u);
+  q.j = 2 * cj + (int)((ch >> 1) & 1u);
+  q.k = dim == 3 ? 2 * (int)ck + (int)(ch >> 2) : 0;
+  q.valid = q.i < nx && q.j < ny && q.k < nz;
+  q.P = q.i + nx * (q.j + ny * q.k);
+  q.parent = (int)C;
+  q.lead = ch == 0;
+  return q;
+}
+
+// sum over the 2^dim lanes of one parent (lanes tau ^ 1, ^ 2, ^ 4); every
+// lane of the group must call it
+template <typename T>
+__device__ __forceinline__ T kid_sum(T v, int dim) {
+  v = v + __shfl_xor(v, 1, 64);
+  v = v + __shfl_xor(v, 2, 64);
+  if (dim == 3) v = v + __shfl_xor(v, 4, 64);
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// setup: coefficients of level l from level l-1 (l = 1 from rAU and flags)
+// ---------------------------------------------------------------------------
+
+template <typename T, typename R>
+__device__ void setup_cell(const Slot &s, int l, int g) {
+  const MGLevel &C = s.mg.lv[l];
+  const LCell c = lcell(C, g);
+  const int dim = s.dim;
+  int nf[3], f0[3], f1[3];
+  if (l == 1) { nf[0] = s.nx; nf[1] = s.ny; nf[2] = s.nz; }
+  else { nf[0] = s.mg.lv[l - 1].nx; nf[1] = s.mg.lv[l - 1].ny; nf[2] = s.mg.lv[l - 1].nz; }
+  const int cc[3] = {c.i, c.j, c.k};
+  for (int e = 0; e < 3; ++e) {
+    f0[e] = e < dim ? 2 * cc[e] : 0;
+    f1[e] = e < dim ? (2 * cc[e] + 1 < nf[e] ? 2 * cc[e] + 1 : 2 * cc[e]) : 0;
+  }
+  const int fnx = nf[0], fnxy = nf[0] * nf[1];
+  const R *rAU = (const R *)s.rAU;
+  // fine low-face coefficient of fine cell F in direction e
+  auto fine_low = [&](int F, int e) -> T {
+    if (l == 1) {
+      uint8_t fl = s.flags[F];
+      if (!(fl & (1u << (2 * e)))) return (T)0;
+      int st = e == 0 ? 1 : (e == 1 ? s.nx : s.nxy);
+      return ((T)0.5 * ((T)rAU[F] + (T)rAU[F - st])) * (T)s.Sh;
+    }
+    return ((const T *)s.mg.lv[l - 1].cf[e])[F];
+  };
+  auto fine_out = [&](int F, int fi, int fj, int fk) -> T {
+    if (l == 1) {
+      uint8_t fl = s.flags[F];
+      if (fl & 0x40) return (T)0;
+      T acc = (T)0;
+      const int q[3] = {fi, fj, fk}, n[3] = {s.nx, s.ny, s.nz};
+      for (int f = 0; f < 2 * dim; ++f) {
+        int e = f >> 1;
+        bool edge = (f & 1) ? q[e] == n[e] - 1 : q[e] == 0;
+        if (edge && s.bcf[f] == F_OUTLET) acc = acc + (T)rAU[F] * (T)s.S2h;
+      }
+      return acc;
+    }
+    return ((const T *)s.mg.lv[l - 1].cout)[F];
+  };
+  T low[3] = {(T)0, (T)0, (T)0}, high[3] = {(T)0, (T)0, (T)0}, out = (T)0;
+  for (int fk = f0[2]; fk <= f1[2]; ++fk)
+    for (int fj = f0[1]; fj <= f1[1]; ++fj)
+      for (int fi = f0[0]; fi <= f1[0]; ++fi) {
+        const int F = fi + fnx * fj + fnxy * fk;
+        const int q[3] = {fi, fj, fk};
+        out = out + fine_out(F, fi, fj, fk);
+        for (int e = 0; e < dim; ++e) {
+          const int st = e == 0 ? 1 : (e == 1 ? fnx : fnxy);
+          // lowest child layer: its low face is the coarse low face (inside the box)
+          if (q[e] == f0[e] && cc[e] > 0) low[e] = low[e] + fine_low(F, e);
+          // highest child layer (a second layer exists): its high face
+          if (q[e] == 2 * cc[e] + 1 && q[e] + 1 < nf[e]) high[e] = high[e] + fine_low(F + st, e);
+        }
+      }
+  T diag = (T)0;
+  for (int e = 0; e < 3; ++e) {
+    if (e < dim) ((T *)C.cf[e])[g] = (T)0.5 * low[e];
+    diag = diag + (T)0.5 * low[e] + (T)0.5 * high[e];
+  }
+  ((T *)C.cout)[g] = (T)0.5 * out;
+  diag = diag + (T)0.5 * out;
+  ((T *)C.invD)[g] = diag > (T)0 ? (T)1 / diag : (T)0;
+}
+
+template <typename T, typename R>
+__global__ void __launch_bounds__(BLOCK) k_mg_setup(const Slot *slot, int l) {
+  const Slot &s = *slot;
+  const MGLevel &C = s.mg.lv[l];
+  for (int g = blockIdx.x * BLOCK + threadIdx.x; g < C.nc; g += gridDim.x * BLOCK) setup_cell<T, R>(s, l, g);
+}
+
+// ---------------------------------------------------------------------------
+// cycle pieces on coarse levels (DIM = 2 or 3)
+// ---------------------------------------------------------------------------
+
+// Pre-smoothing from zero on level L in child order, with the restriction:
+// x = w D^-1 b, t = b - A x, b_next[parent] = sum of the children's t.
+// (cnx, cny, cnc) are the dimensions of the next coarser level; bnext may
+// point to global memory or to LDS.
+template <int DIM, typename T>
+__device__ __forceinline__ void smooth_restrict(const LV<T> &L, int cnx, int cny, int cnc, T *bnext, unsigned start,
+                                                unsigned stride) {
+  const T w = (T)MG_OMEGA;
+  const unsigned total = (unsigned)cnc << DIM;
+  for (unsigned tau = start; tau < total; tau += stride) {
+    const Kid q = kid_at(tau, DIM, L.nx, L.ny, L.nz, cnx, cny);
+    T tv = (T)0;
+    if (q.valid) {
+      LCell c;
+      c.P = q.P;
+      c.i = q.i;
+      c.j = q.j;
+      c.k = q.k;
+      auto xv = [&](int n, int, int) -> T { return w * (L.invD[n] * L.b[n]); };
+      const T Ax = lmatvec<DIM, T>(L, c, xv);
+      L.x[c.P] = xv(c.P, 0, 0);
+      tv = L.b[c.P] - Ax;
+    }
+    tv = kid_sum(tv, DIM);
+    if (q.lead) bnext[q.parent] = tv;
+  }
+}
+
+// prolongation and post-smoothing on level L: x' = x + P xc (xc on the next
+// coarser level, of dims (cnx, ., .) and plane size cnxy; global memory or
+// LDS), out = x' + w D^-1 (b - A x')
+template <int DIM, typename T>
+__device__ __forceinline__ void up_range(const LV<T> &L, int cnx, int cnxy, const T *xc, T *out, int start, int stride) {
+  const T w = (T)MG_OMEGA;
+  const int cst[3] = {1, cnx, cnxy};
+  for (int g = start; g < L.nc; g += stride) {
+    const LCell c = lcell(L.nx, L.ny, g);
+    const int pP = (c.i >> 1) + cnx * (c.j >> 1) + cnxy * (c.k >> 1);
+    const int q[3] = {c.i, c.j, c.k};
+    auto xv = [&](int n, int e, int side) -> T { return L.x[n] + xc[pP + parent_shift(q[e], side, cst[e])]; };
+    const T xp = xv(g, 0, 0);
+    const T Ax = lmatvec<DIM, T>(L, c, xv);
+    out[g] = xp + w * (L.invD[g] * (L.b[g] - Ax));
+  }
+}
+
+__device__ __forceinline__ bool mg_idle(const Slot &s) { return !s.ctl->active || s.st->done; }
+
+template <int DIM, typename T>
+__global__ void __launch_bounds__(BLOCK) k_mg_smooth(const Slot *slot, int l) {
+  const Slot &s = *slot;
+  if (mg_idle(s)) return;
+  const LV<T> L = lview<T>(s.mg.lv[l]);
+  const MGLevel &C = s.mg.lv[l + 1];
+  smooth_restrict<DIM, T>(L, C.nx, C.ny, C.nc, (T *)C.b, blockIdx.x * BLOCK + threadIdx.x, gridDim.x * BLOCK);
+}
+
+// final correction of level l goes to t_l (x_l keeps the pre-smoothed one)
+template <int DIM, typename T>
+__global__ void __launch_bounds__(BLOCK) k_mg_up(const Slot *slot, int l) {
+  const Slot &s = *slot;
+  if (mg_idle(s)) return;
+  const LV<T> L = lview<T>(s.mg.lv[l]);
+  const MGLevel &C = s.mg.lv[l + 1];
+  up_range<DIM, T>(L, C.nx, C.nxy, (const T *)C.t, L.t, blockIdx.x * BLOCK + threadIdx.x, gridDim.x * BLOCK);
+}
+
+// Levels tail..L in one workgroup: the down-sweep to the coarsest level
+// (whose right-hand side goes straight to LDS), Jacobi sweeps on the
+// coarsest level with each thread's row of the operator in registers and the
+// iterates in LDS, the up-sweep back to the tail level.
+template <int DIM, typename T>
+__global__ void __launch_bounds__(MG_TAIL_THREADS) k_mg_tail(const Slot *slot) {
+  const Slot &s = *slot;
+  if (mg_idle(s)) return;
+  const int tl = s.mg.tail, L = s.mg.L;
+  const int t0 = threadIdx.x, ns = MG_TAIL_THREADS;
+  const LV<T> C = lview<T>(s.mg.lv[L]);
+  if (C.nc > MG_LDS_CELLS) return;   // excluded by the host's hierarchy check
+  __shared__ T sb[MG_LDS_CELLS];
+  __shared__ T sx[2][MG_LDS_CELLS];
+  for (int l = tl; l < L; ++l) {
+    const MGLevel &N = s.mg.lv[l + 1];
+    smooth_restrict<DIM, T>(lview<T>(s.mg.lv[l]), N.nx, N.ny, N.nc, l + 1 == L ? sb : (T *)N.b, t0, ns);
+    __syncthreads();
+  }
+  // this thread's row of the coarsest operator (absent neighbours: the cell
+  // itself with a zero coefficient)
+  const bool mine = t0 < C.nc;
+  int nb[2 * DIM];
+  T cc[2 * DIM], co = (T)0, id = (T)0, bb = (T)0;
+#pragma unroll
+  for (int f = 0; f < 2 * DIM; ++f) {
+    nb[f] = mine ? t0 : 0;
+    cc[f] = (T)0;
+  }
+  if (mine) {
+    const LCell c = lcell(C.nx, C.ny, t0);
+    const int st[3] = {1, C.nx, C.nxy}, q[3] = {c.i, c.j, c.k}, n[3] = {C.nx, C.ny, C.nz};
+#pragma unroll
+    for (int e = 0; e < DIM; ++e) {
+      if (q[e] > 0) {
+        nb[2 * e] = t0 - st[e];
+        cc[2 * e] = C.cf[e][t0];
+      }
+      if (q[e] < n[e] - 1) {
+        nb[2 * e + 1] = t0 + st[e];
+        cc[2 * e + 1] = C.cf[e][t0 + st[e]];
+      }
+    }
+    co = C.cout[t0];
+    id = C.invD[t0];
+    bb = L > tl ? sb[t0] : C.b[t0];
+    sx[0][t0] = (T)0;
+  }
+  __syncthreads();
+  const T w = (T)MG_OMEGA;
+  for (int sw = 0; sw < MG_COARSE_SWEEPS; ++sw) {
+    const T *xi = sx[sw & 1];
+    T *xo = sx[(sw + 1) & 1];
+    if (mine) {
+      const T xP = xi[t0];
+      T xn[2 * DIM];
+#pragma unroll
+      for (int f = 0; f < 2 * DIM; ++f) xn[f] = xi[nb[f]];
+      T acc = (T)0;
+#pragma unroll
+      for (int f = 0; f < 2 * DIM; ++f) acc = acc + cc[f] * (xP - xn[f]);
+      acc = acc + co * xP;
+      xo[t0] = xP + w * (id * (bb - acc));
+    }
+    __syncthreads();
+  }
+  const T *xL = sx[MG_COARSE_SWEEPS & 1];
+  if (L == tl) {   // no level of the tail above the coarsest: hand the result on in global memory
+    if (mine) C.t[t0] = xL[t0];
+    return;
+  }
+  for (int l = L - 1; l >= tl; --l) {
+    const MGLevel &N = s.mg.lv[l + 1];
+    const LV<T> Lv = lview<T>(s.mg.lv[l]);
+    up_range<DIM, T>(Lv, N.nx, N.nxy, l == L - 1 ? xL : (const T *)N.t, Lv.t, t0, ns);
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// fine level: conjugate-gradient pieces fused with the cycle's fine steps
+// (block-table launches like the other fine-grid kernels)
+// ---------------------------------------------------------------------------
+
+struct FBlock {
+  const Slot *s;
+  int lb;
+};
+
+__device__ __forceinline__ bool fine_block(const Slot *slots, const int2 *btab, FBlock &b) {
+  int2 t = btab[blockIdx.x];
+  if (t.y < 0) return false;   // padding entry of the block table
+  b.s = slots + t.x;
+  b.lb = t.y;
+  return b.s->ctl->active && !b.s->st->done;
+}
+
+// Search direction of iteration it: gamma_it = <r,z> and |r|^2 from the
+// previous cycle's reduction, convergence test (it > 0), beta, d = z + beta
+// d_old (d = z when it = 0), q = A d and <d,q>.
+template <typename R>
+__global__ void __launch_bounds__(BLOCK) k_mgcg_dir(const Slot *slots, const int2 *btab, int it) {
+  using T = R;
+  FBlock B;
+  if (!fine_block(slots, btab, B)) return;
+  const Slot &s = *B.s;
+  const Grid G = grid_of(s);
+  const SlotCtl &ctl = *s.ctl;
+  SlotState *st = s.st;
+  const bool mixed = s.precision != 0;
+  const int lb = B.lb;
+  double v[2];
+  get_totals<0u>(s, CH_CG0 + ((it + 1) & 1), v);   // written by the cycle of iteration it - 1
+  const double gam = v[0];
+  double beta = 0.0;
+  if (it > 0) {
+    double rn = sqrt(v[1]);
+    double rtol = mixed ? ctl.rtol_inner : ctl.rtol;
+    bool conv = rn <= rtol * st->bn;
+    bool cap = !conv && it >= ctl.max_it;
+    if (conv || cap) {
+      if (lb == 0 && threadIdx.x == 0) {
+        st->rn = rn;
+        st->it = it;
+        st->done = 1;
+        if (cap) st->maxit_hit = st->maxit_hit + 1;
+      }
+      return;
+    }
+    beta = gam / st->gam[(it - 1) & 1];
+    if (lb == 0 && threadIdx.x == 0) st->rn = rn;
+  }
+  if (lb == 0 && threadIdx.x == 0) st->gam[it & 1] = gam;
+  // d = z + beta d_old; on the first iteration beta = 0 and d_old = z, so
+  // d = z exactly and every load is unconditional
+  const bool first = it == 0;
+  const T be = (T)beta;
+  const R *rAU = (const R *)s.rAU;
+  const uint8_t *flags = s.flags;
+  const T *z = (const T *)s.cw[0], *dold = first ? z : (const T *)s.cs[(it + 1) & 1];
+  T *dn = (T *)s.cs[it & 1], *q = (T *)s.cp;
+  double red[1] = {0.0};
+  for_cells(G, lb, [&](const Cell &c) {
+    uint8_t fl = flags[c.P];
+    if (fl & 0x40) return;
+    auto dv = [&](int x) -> T { return z[x] + be * dold[x]; };
+    T dP = dv(c.P);
+    T qq = matvec_row<T, R>(G, rAU, c, fl, dv);
+    dn[c.P] = dP;
+    q[c.P] = qq;
+    red[0] = red[0] + (double)(dP * qq);
+  });
+  put_partials<0u>(s, lb, CH_DQ, red);
+}
+
+// Iteration it >= 0: alpha = gamma / <d,q>, x += alpha d, r -= alpha q; for
+// it = -1 (the cycle before the first iteration) r is the initial residual.
+// Then the cycle's fine pre-smoothing z0 = w D^-1 r and the restriction of
+// its residual r - A z0 into level 1, walking the fine grid in child order.
+template <typename R>
+__global__ void __launch_bounds__(BLOCK) k_mg_fine_down(const Slot *slots, const int2 *btab, int it) {
+  using T = R;
+  FBlock B;
+  if (!fine_block(slots, btab, B)) return;
+  const Slot &s = *B.s;
+  const Grid G = grid_of(s);
+  const SlotCtl &ctl = *s.ctl;
+  SlotState *st = s.st;
+  const bool mixed = s.precision != 0;
+  const int lb = B.lb;
+  const bool upd = it >= 0;
+  T al = (T)0;
+  if (upd) {
+    double v[1];
+    get_totals<0u>(s, CH_DQ, v);
+    al = (T)(st->gam[it & 1] / v[0]);
+    if (lb == 0 && threadIdx.x == 0) {
+      st->it = it + 1;
+      st->total_it = st->total_it + 1;
+    }
+  }
+  const R *rAU = (const R *)s.rAU;
+  const T *invD = (const T *)s.invD;
+  // r_new = r - alpha q; for the initial cycle alpha = 0 and q = r, so
+  // r_new = r exactly and every load is unconditional
+  const T *r0 = (const T *)s.cr[upd ? (it & 1) : 0];
+  T *r1 = (T *)s.cr[upd ? ((it + 1) & 1) : 0];
+  const T *d = (const T *)s.cs[upd ? (it & 1) : 0], *q = upd ? (const T *)s.cp : r0;
+  T *z0 = (T *)s.cw[1];
+  T *xe = (T *)s.e;
+  double *xp = ctl.mode ? s.p_cr : s.p_vd;
+  const int cnx = s.mg.lv[1].nx, cny = s.mg.lv[1].ny;
+  T *b1 = (T *)s.mg.lv[1].b;
+  const uint8_t *flags = s.flags;
+  const T w = (T)MG_OMEGA;
+  const int dim = G.dim;
+  const unsigned total = (unsigned)s.mg.lv[1].nc << dim;
+  for (unsigned tau = (unsigned)(lb * BLOCK) + threadIdx.x; tau < total; tau += (unsigned)(G.nblocks * BLOCK)) {
+    const Kid k = kid_at(tau, dim, G.nx, G.ny, G.nz, cnx, cny);
+    T tv = (T)0;
+    const uint8_t fl = k.valid ? flags[k.P] : (uint8_t)0x40;
+    if (!(fl & 0x40)) {
+      Cell c;
+      c.P = k.P;
+      c.i = k.i;
+      c.j = k.j;
+      c.k = k.k;
+      c.row = k.j + G.ny * k.k;
+      c.valid = true;
+      auto rv = [&](int x) -> T { return r0[x] - al * q[x]; };
+      auto zv = [&](int x) -> T { return w * (invD[x] * rv(x)); };
+      const int P = c.P;
+      T rn = rv(P);
+      T zz = zv(P);
+      T Az = matvec_row<T, R>(G, rAU, c, fl, zv);
+      if (upd) {
+        if (mixed) xe[P] = xe[P] + al * d[P];
+        else xp[P] = xp[P] + (double)al * (double)d[P];
+        r1[P] = rn;
+      }
+      z0[P] = zz;
+      tv = rn - Az;
+    }
+    tv = kid_sum(tv, dim);
+    if (k.lead) b1[k.parent] = tv;
+  }
+}
+
+// Last step of the cycle: z' = z0 + P x1, z = z' + w D^-1 (r - A z'); the
+// reduction <r,z>, |r|^2 for the next search direction.
+template <typename R>
+__global__ void __launch_bounds__(BLOCK) k_mg_fine_up(const Slot *slots, const int2 *btab, int it) {
+  using T = R;
+  FBlock B;
+  if (!fine_block(slots, btab, B)) return;
+  const Slot &s = *B.s;
+  const Grid G = grid_of(s);
+  const int lb = B.lb;
+  const uint8_t *flags = s.flags;
+  const R *rAU = (const R *)s.rAU;
+  const T *invD = (const T *)s.invD;
+  const T *r = (const T *)s.cr[(it + 1) & 1];
+  const T *z0 = (const T *)s.cw[1];
+  T *z = (T *)s.cw[0];
+  const int cnx = s.mg.lv[1].nx, cnxy = s.mg.lv[1].nxy;
+  const T *xc = (const T *)s.mg.lv[1].t;
+  const T w = (T)MG_OMEGA;
+  double red[2] = {0.0, 0.0};
+  for_cells(G, lb, [&](const Cell &c) {
+    const int P = c.P;
+    uint8_t fl = flags[P];
+    if (fl & 0x40) return;
+    const int pP = (c.i >> 1) + cnx * (c.j >> 1) + cnxy * (c.k >> 1);
+    const int q[3] = {c.i, c.j, c.k};
+    const int cst[3] = {1, cnx, cnxy};
+    // z' at the cell (f = -1) or at its neighbour across face f
+    auto zp = [&](int n, int f) -> T {
+      const int pn = f < 0 ? pP : pP + parent_shift(q[f >> 1], (f & 1) ? 1 : -1, cst[f >> 1]);
+      return z0[n] + xc[pn];
+    };
+    const T zP = zp(P, -1);
+    const T Az = matvec_row_f<T, R>(G, rAU, c, fl, zp);
+    T rr = r[P];
+    T zn = zP + w * (invD[P] * (rr - Az));
+    z[P] = zn;
+    red[0] = red[0] + (double)(rr * zn);
+    red[1] = red[1] + (double)(rr * rr);
+  });
+  put_partials<0u>(s, lb, CH_CG0 + (it & 1), red);
+}
+
+// ---------------------------------------------------------------------------
+// host launchers (one slot: L.slots[0])
+// ---------------------------------------------------------------------------
+
+static unsigned lvl_grid(int nc) {
+  int n = (nc + BLOCK - 1) / BLOCK;
+  return (unsigned)(n < 1024 ? (n > 0 ? n : 1) : 1024);
+}
+
+#define FGRID(L) dim3((unsigned)(L).nblocks), dim3(BLOCK), 0, (L).stream
+
+template <typename R>
+void launch_mg_setup(const Slot &hs, const Slot *ds, hipStream_t stream) {
+  for (int l = 1; l <= hs.mg.L; ++l)
+    hipLaunchKernelGGL((k_mg_setup<R, R>), dim3(lvl_grid(hs.mg.lv[l].nc)), dim3(BLOCK), 0, stream, ds, l);
+}
+
+template <typename R>
+void launch_mg_dir(const Launch &L, int it) {
+  hipLaunchKernelGGL(k_mgcg_dir<R>, FGRID(L), L.slots, L.btab, it);
+}
+
+template <int DIM, typename R>
+static void vcycle_levels(const Slot &hs, const Launch &L) {
+  const Slot *ds = L.slots;
+  const int tl = hs.mg.tail;
+  for (int l = 1; l < tl; ++l)
+    hipLaunchKernelGGL((k_mg_smooth<DIM, R>), dim3(lvl_grid(hs.mg.lv[l + 1].nc << DIM)), dim3(BLOCK), 0, L.stream, ds, l);
+  hipLaunchKernelGGL((k_mg_tail<DIM, R>), dim3(1), dim3(MG_TAIL_THREADS), 0, L.stream, ds);
+  for (int l = tl - 1; l >= 1; --l)
+    hipLaunchKernelGGL((k_mg_up<DIM, R>), dim3(lvl_grid(hs.mg.lv[l].nc)), dim3(BLOCK), 0, L.stream, ds, l);
+}
+
+// the cycle of iteration it (it = -1: the cycle of the initial residual)
+template <typename R>
+void launch_mg_vcycle(const Slot &hs, const Launch &L, int it) {
+  const Slot *ds = L.slots;
+  hipLaunchKernelGGL(k_mg_fine_down<R>, FGRID(L), ds, L.btab, it);
+  if (hs.dim == 3) vcycle_levels<3, R>(hs, L);
+  else vcycle_levels<2, R>(hs, L);
+  hipLaunchKernelGGL(k_mg_fine_up<R>, FGRID(L), ds, L.btab, it);
+}
+
+template void launch_mg_setup<double>(const Slot &, const Slot *, hipStream_t);
+template void launch_mg_setup<float>(const Slot &, const Slot *, hipStream_t);
+template void launch_mg_dir<double>(const Launch &, int);
+template void launch_mg_dir<float>(const Launch &, int);
+template void launch_mg_vcycle<double>(const Slot &, const Launch &, int);
+template void launch_mg_vcycle<float>(const Slot &, const Launch &, int);
+
+}  // namespace oscar

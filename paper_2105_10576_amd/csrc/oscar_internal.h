@@ -24,7 +24,7 @@ constexpr int NVAL = 4;      // values per reduction channel
 // partials of its slot in a fixed order.  No atomics, no cache flushes.
 // CH_CG0/CH_CG1: the CG reduction of iteration it goes to CH_CG0 + (it & 1)
 // and is read by iteration it + 1, so no launch reads a channel it writes.
-enum : int { CH_ADV1 = 0, CH_ADV2 = 1, CH_SETUP = 2, CH_NORM = 3, CH_CG0 = 4, CH_CG1 = 5, CH_REF = 6, NCH = 7 };
+enum : int { CH_ADV1 = 0, CH_ADV2 = 1, CH_SETUP = 2, CH_NORM = 3, CH_CG0 = 4, CH_CG1 = 5, CH_REF = 6, CH_DQ = 7, NCH = 8 };
 
 // Per-slot scalars written by one block (block 0 of a kernel, or a
 // finaliser) and read by later kernels.
@@ -45,11 +45,33 @@ struct SlotCtl {
   double tol;
 };
 
+// Geometric multigrid hierarchy of the pressure matrix (preconditioner):
+// every dimension halved (rounding up) per level until a level has at most
+// MG_COARSEST cells; levels of at most MG_TAIL_CELLS cells run in one
+// workgroup; the coarsest level must fit the LDS arrays of MG_LDS_CELLS.
+constexpr int MG_MAXL = 12;
+constexpr int MG_COARSEST = 128;
+constexpr int MG_TAIL_CELLS = 4096;
+constexpr int MG_LDS_CELLS = 512;
+struct MGLevel {
+  int32_t nx, ny, nz, nc, nxy, nblocks;
+  void *cf[3];        // coefficient of each cell's low face per direction (T)
+  void *cout;         // outlet coefficient of the cell (T)
+  void *invD;         // inverse diagonal (T, 0 for cells without fluid)
+  void *b, *x, *t;    // right-hand side, pre-smoothed correction, final correction (T)
+};
+struct MGInfo {
+  int32_t L;          // coarsest level (levels 1..L); 0 = no hierarchy
+  int32_t tail;       // first level handled by the single-workgroup tail kernel
+  MGLevel lv[MG_MAXL + 1];
+};
+
 struct Slot {
   int32_t dim, nx, ny, nz;
   int32_t nc, nf0, nf1, nf2, nftot, nxy;   // counts (the host keeps them below 2^31)
   int32_t block0, nblocks, n_fluid, precision;
   int32_t bcf[6];               // face type of each box side
+  uint32_t outlet;              // bit f: box side f is an outlet (f < 2*dim)
   double h, V, S, Sh, S2h, hh, delta, cos_t, sin_t;
   double rho1, mu1, rho2, mu2, sigma, u_inlet;
   const uint8_t *flags;         // bit f: face f interior; bit 6: solid
@@ -64,6 +86,7 @@ struct Slot {
   // and s = A p in ping-pong pairs, search direction p, FP32 correction e
   void *invD, *cr[2], *cw[2], *cs[2], *cp, *e;
   double *part;                 // NCH * NVAL * nblocks reduction partials
+  MGInfo mg;
   SlotState *st;
   SlotCtl *ctl;
 };
@@ -98,6 +121,11 @@ template <typename R> void launch_finalize(const Launch &L);
 template <typename R> void launch_zero_usum(const Launch &L);
 void launch_ctl_update(const Launch &L, const CtlUpdate &u);
 void launch_state_reset(const Launch &L, int nslots);
+
+// multigrid-preconditioned CG (single slot; mg.hip)
+template <typename R> void launch_mg_setup(const Slot &hs, const Slot *dslot, hipStream_t st);
+template <typename R> void launch_mg_vcycle(const Slot &hs, const Launch &L, int it);
+template <typename R> void launch_mg_dir(const Launch &L, int it);
 void launch_gather_states(const Launch &L, int nslots, SlotState *out);
 
 // blocks per slot: ceil(cells/BLOCK), capped (grid-stride beyond the cap)

@@ -15,6 +15,7 @@ LIB_PATH = os.path.join(HERE, "liboscar.so")
 OK, W_PCG_MAXIT, W_REFINE_STALL = 0, 1, 2
 E_ARG, E_WORKSPACE, E_MASK, E_UNSTABLE, E_NONFINITE, E_HIP, E_CAPACITY = -1, -2, -3, -4, -5, -6, -7
 FP64, MIXED = 0, 1
+PC_JACOBI, PC_MG = 0, 1
 FIELDS = dict(alpha=0, U=1, p=2, U_vd=3, p_vd=4, U_cr=5, p_cr=6, phi_vd=7, phi_vd_prev=8, phi_cr=9,
               kappa=10, rAU=11, rhs=12, U_sum=13, HbyA=14, nhatf=15)
 
@@ -30,7 +31,7 @@ class Desc(C.Structure):
                 ("rho1", C.c_double), ("mu1", C.c_double), ("rho2", C.c_double), ("mu2", C.c_double),
                 ("sigma", C.c_double), ("theta_deg", C.c_double), ("bc", C.c_int32 * 6),
                 ("u_inlet", C.c_double), ("precision", C.c_int32), ("n_corr", C.c_int32),
-                ("pcg_rtol", C.c_double), ("pcg_max_it", C.c_int32)]
+                ("pcg_rtol", C.c_double), ("pcg_max_it", C.c_int32), ("precond", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -88,7 +89,8 @@ def lib():
 
 
 def make_desc(case, precision=FP64):
-    """Fill an oscar_desc from a case dictionary; returns (desc, keep-alive arrays)."""
+    """Fill an oscar_desc from a case dictionary (key "precond": PC_JACOBI,
+    the default, or PC_MG); returns (desc, keep-alive arrays)."""
     d = Desc()
     for k in ("dim", "nx", "ny", "nz", "n_corr", "pcg_max_it"):
         setattr(d, k, int(case[k]))
@@ -97,6 +99,7 @@ def make_desc(case, precision=FP64):
     for i in range(6):
         d.bc[i] = int(case["bc"][i])
     d.precision = int(precision)
+    d.precond = int(case.get("precond", PC_JACOBI))
     mask = np.ascontiguousarray(case["mask"], dtype=np.uint8)
     a0 = np.ascontiguousarray(case["alpha0"], dtype=np.float64)
     d.mask = mask.ctypes.data_as(C.POINTER(C.c_uint8))
