@@ -3,14 +3,25 @@
 Workload (default): the 3D constricted channel, 128 x 64 x 64 voxels at
 5 um with a cosine throat of radius 0.4 R, a CO2 slug in the first 30 % of the
 channel, Ca = 1e-4, dt_vd = 0.1 dt_CFL, N = 12 capillary sub-steps below
-the Brackbill limit; mixed precision (FP32 fields and CG, FP64 pressure,
-refinement residual, dots and mass sums), with the FP64 path timed beside it.
+the Brackbill limit; mixed precision (FP32 fields, stencils, preconditioner
+and inner CG; FP64 pressure, refinement residual, dots and mass sums), with
+the FP64 path timed beside it.  Pressure solves: conjugate gradient with the
+geometric multigrid preconditioner (--precond jacobi for diagonal scaling)
+to a 1e-8 relative FP64 residual.
 
 One timed step = one OSCAR global step = one viscous-drag step followed by
 the capillary relaxation with max_iters = N and tol = 0, so every sub-step
 runs.  The metric counts (1 + N) cell-iterations per cell and step (the
 viscous step counts as one iteration); value = total cell-iterations / wall
 time of the K timed steps / 1e6, inputs resident on the device.
+
+Kernel timing: inside the timed steps every 8th conjugate-gradient iteration
+is sampled by the library's timing hook (its kernels stamp the device wall
+clock at the start and end of every workgroup), giving the average execution
+time of each part of an iteration; the roofline entry is the fine-grid
+kernel with the largest share, its algorithmic bytes (each array it must
+read or write counted once per fluid cell, the face-flag byte once per cell)
+over that average duration.
 
 Prints one JSON line.
 """
@@ -24,19 +35,48 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+TIMING_PERIOD = 8
+
+# parts of a CG iteration reported by the timing hook (index: kernel name)
+MG_PARTS = {1: "k_mgcg_dir", 2: "k_mg_fine_down", 3: "coarse levels (k_mg_smooth, k_mg_tail, k_mg_up)",
+            4: "k_mg_fine_up"}
 
 
-def cg_bytes_per_fluid_cell(precision):
-    """Algorithmic bytes the conjugate-gradient iteration kernel moves per
-    fluid cell: it reads r, w = A D^-1 r, s_old, D^-1, p_old, rAU and x and
-    writes p, s, r, w and x (x is the FP64 pressure in the FP64 path, the FP32
-    correction in the mixed path); every cell also reads its face-flag byte."""
-    w = 4 if precision == 1 else 8
+def word(precision):
+    return 4 if precision == 1 else 8
+
+
+def jacobi_cg_bytes(precision, n_fluid, nc):
+    """k_cg: reads r, w = A D^-1 r, s_old, D^-1, p_old, rAU and x and writes
+    p, s, r, w and x (x: the FP64 pressure in the FP64 path, the FP32
+    correction in the mixed path); the face-flag byte of every cell."""
+    w = word(precision)
     x = 8 if precision == 0 else 4
-    return 6 * w + x + 4 * w + x
+    return n_fluid * (6 * w + x + 4 * w + x) + nc
 
 
-def run_gpu(case, precision, steps, warmup, timing=True, precond=0):
+def mg_part_bytes(part, precision, n_fluid, nc, nc1):
+    """Algorithmic bytes of the fine-grid kernels of one multigrid-preconditioned
+    iteration (nc1: cells of the first coarse level).
+      k_mgcg_dir:     reads z, d_old, rAU; writes d, q                   5 w
+      k_mg_fine_down: reads r, q, D^-1, rAU, d and x; writes x, r_new, z0
+                      (x: FP64 pressure or FP32 correction, read and written)
+                      7 w + 2 |x|, + the level-1 right-hand side (nc1 w)
+      k_mg_fine_up:   reads z0, rAU, r, D^-1; writes z                   5 w
+                      + the level-1 correction (nc1 w)
+    plus the face-flag byte of every cell."""
+    w = word(precision)
+    if part == 1:
+        return n_fluid * 5 * w + nc
+    if part == 2:
+        x = 16 if precision == 0 else 2 * w
+        return n_fluid * (7 * w + x) + nc1 * w + nc
+    if part == 4:
+        return n_fluid * 5 * w + nc1 * w + nc
+    return None
+
+
+def run_gpu(case, precision, steps, warmup, precond=1, timing_period=TIMING_PERIOD):
     import torch
 
     from paper_2105_10576_amd import oscar
@@ -46,27 +86,59 @@ def run_gpu(case, precision, steps, warmup, timing=True, precond=0):
     for _ in range(warmup):
         g.step(max_iters=n_sub, tol=0.0)
     torch.cuda.synchronize()
-    if timing:
-        g.timing(True)
+    if timing_period:
+        g.timing(timing_period)
     t0 = time.perf_counter()
     pcg = 0
+    refine = 0
     for _ in range(steps):
         g.viscous_step(case["dt_vd"])
-        pcg += g.stats()["pcg_iters_call"]
+        st = g.stats()
+        pcg += st["pcg_iters_call"]
+        refine += st["refine_steps_call"]
         rc, kf, E = g.capillary_relax(case["dt_vd"], n_sub, n_sub, 0.0)
         st = g.stats()
         pcg += st["pcg_iters_call"]
+        refine += st["refine_steps_call"]
         assert kf == n_sub
     torch.cuda.synchronize()
     t = time.perf_counter() - t0
-    kt = g.timing_read(0) if timing else None
-    if timing:
-        g.timing(False)
+    parts = {k: g.timing_read(k) for k in range(5)} if timing_period else None
+    if timing_period:
+        g.timing(0)
     st = g.stats()
-    res = dict(seconds=t, pcg_iters=pcg, kernel_times=kt, stats=st,
-               iters=steps * (1 + n_sub))
+    res = dict(seconds=t, pcg_iters=pcg, refine_steps=refine, parts=parts, stats=st, iters=steps * (1 + n_sub))
     g.close()
     return res
+
+
+def kernel_table(r, precision, precond, n_fluid, nc, nc1):
+    """Per-part average durations [us] and, for the fine-grid kernels, GB/s."""
+    out = {}
+    names = MG_PARTS if precond == 1 else {1: "k_cg"}
+    for k, name in names.items():
+        ms, n = r["parts"][k]
+        if n == 0:
+            continue
+        avg = ms / 1e3 / n
+        e = {"avg_us": round(avg * 1e6, 3), "launches_timed": n}
+        b = mg_part_bytes(k, precision, n_fluid, nc, nc1) if precond == 1 else jacobi_cg_bytes(precision, n_fluid, nc)
+        if b is not None:
+            e["alg_bytes"] = b
+            e["GBs"] = round(b / avg / 1e9, 1)
+        out[name] = e
+    ms, n = r["parts"][0]
+    out["iteration"] = {"avg_us": round(ms * 1e3 / max(n, 1), 3), "launches_timed": n}
+    return out
+
+
+def dominant(table):
+    """the fine-grid kernel (one with algorithmic bytes) of largest average duration"""
+    best = None
+    for name, e in table.items():
+        if "alg_bytes" in e and (best is None or e["avg_us"] > table[best]["avg_us"]):
+            best = name
+    return best
 
 
 def cpu_baseline(case):
@@ -89,14 +161,14 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--fp64-steps", type=int, default=2)
+    ap.add_argument("--fp64-steps", type=int, default=3)
+    ap.add_argument("--precond", choices=["mg", "jacobi"], default="mg",
+                    help="preconditioner of the pressure conjugate gradient")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 path beside the mixed path")
     ap.add_argument("--no-serving", action="store_true", help="skip the batched-serving measurement")
     ap.add_argument("--pmc-calibration", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device-to-device (calibrates rocprofv3 FETCH_SIZE/WRITE_SIZE)")
-    ap.add_argument("--precond", choices=["mg", "jacobi"], default="mg",
-                    help="preconditioner of the pressure conjugate gradient")
     ap.add_argument("--serving-requests", type=int, default=64)
     ap.add_argument("--serving-max-iters", type=int, default=40,
                     help="cap on relaxation sub-steps per serving request (the mix allows up to 200)")
@@ -123,20 +195,20 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     case = cases.constricted_channel(tol=0.0)
     case["pcg_rtol"] = 1e-8   # pressure solves to a 1e-8 relative residual on both paths
-    nc = case["nx"] * case["ny"] * case["nz"]
+    nx, ny, nz = case["nx"], case["ny"], case["nz"]
+    nc = nx * ny * nz
+    nc1 = ((nx + 1) // 2) * ((ny + 1) // 2) * ((nz + 1) // 2)
     n_fluid = int((case["mask"] == 0).sum())
     n_sub = case["n_sub"]
-
     pc = 1 if args.precond == "mg" else 0
+
     mixed = run_gpu(case, 1, args.steps, args.warmup, precond=pc)
     value = mixed["iters"] * nc / mixed["seconds"] / 1e6
     ms_step = 1e3 * mixed["seconds"] / args.steps
-
-    # dominant kernel: the conjugate-gradient iteration kernel
-    ms_tot, launches = mixed["kernel_times"]
-    avg_s = ms_tot / 1e3 / max(launches, 1)
-    alg_bytes = n_fluid * cg_bytes_per_fluid_cell(1) + nc
-    achieved = alg_bytes / avg_s / 1e9
+    ktab = kernel_table(mixed, 1, pc, n_fluid, nc, nc1)
+    dom = dominant(ktab)
+    d = ktab[dom]
+    achieved = d["GBs"]
 
     out = {
         "metric": "relaxation Mcell-iter/s (mixed FP32 + FP64 refinement), HBM GB/s of the dominant kernel",
@@ -153,36 +225,40 @@ def main():
         "data": "synthetic (seeded constricted-channel geometry and CO2 slug)",
         "config": {
             "workload": "3D constricted channel 128x64x64 (524288 voxels, %d fluid), Ca=1e-4, N=%d sub-steps, "
-                        "1 viscous + %d relaxation iterations per step, tol=0, pressure rtol 1e-8" % (n_fluid, n_sub, n_sub),
+                        "1 viscous + %d relaxation iterations per step, tol=0, pressure rtol 1e-8, "
+                        "%s-preconditioned CG" % (n_fluid, n_sub, n_sub, "multigrid" if pc else "Jacobi"),
             "precision": "mixed",
             "pcg_iters_per_step": round(mixed["pcg_iters"] / args.steps, 1),
+            "refine_steps_per_step": round(mixed["refine_steps"] / args.steps, 1),
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_cg",
-            "achieved": round(achieved, 1),
+            "kernel": dom,
+            "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": None,
-            "avg_launch_us": round(avg_s * 1e6, 3),
-            "alg_bytes_per_launch": alg_bytes,
-            "launches": launches,
+            "avg_launch_us": d["avg_us"],
+            "alg_bytes_per_launch": d["alg_bytes"],
+            "launches_timed": d["launches_timed"],
+            "timing": "device wall-clock stamps of every %d-th CG iteration of the timed steps" % TIMING_PERIOD,
         },
+        "kernels": ktab,
     }
     if not args.no_fp64:
         f = run_gpu(case, 0, args.fp64_steps, 1, precond=pc)
-        ms64, n64 = f["kernel_times"]
-        avg64 = ms64 / 1e3 / max(n64, 1)
-        b64 = n_fluid * cg_bytes_per_fluid_cell(0) + nc
+        ftab = kernel_table(f, 0, pc, n_fluid, nc, nc1)
+        fdom = dominant(ftab)
         out["fp64"] = {
             "value": round(f["iters"] * nc / f["seconds"] / 1e6, 3),
             "ms_per_step": round(1e3 * f["seconds"] / args.fp64_steps, 3),
             "steps": args.fp64_steps,
             "pcg_iters_per_step": round(f["pcg_iters"] / args.fp64_steps, 1),
-            "dominant_kernel": "k_cg",
-            "achieved_GBs": round(b64 / avg64 / 1e9, 1),
-            "avg_launch_us": round(avg64 * 1e6, 3),
+            "dominant_kernel": fdom,
+            "achieved_GBs": ftab[fdom]["GBs"],
+            "frac": round(ftab[fdom]["GBs"] / HBM_PEAK_GBS, 4),
+            "kernels": ftab,
         }
     if not args.no_serving:
         from paper_2105_10576_amd import serving_bench

@@ -179,16 +179,30 @@ void oscar_destroy(oscar_ctx *ctx);
  * oscar_create / engine failure when ctx is NULL.  Never NULL. */
 const char *oscar_last_error(const oscar_ctx *ctx);
 
-/* Measurement hook (not part of the method): when enabled, every
- * conjugate-gradient iteration is bracketed by HIP events on the context's
- * stream (with OSCAR_PC_JACOBI the one iteration kernel; with OSCAR_PC_MG
- * the search-direction kernel and the launches of one V-cycle).
- * oscar_timing(ctx, 1) resets and starts the totals, oscar_timing(ctx, 0)
- * stops.  oscar_timing_read(ctx, 0, ...) returns the summed time [ms] and
- * the number of bracketed iterations that did work (iterations enqueued past
- * the device-side convergence test exit at once and are not counted);
- * kernel 1 is reserved and reads zero.  It synchronises the stream. */
-int32_t oscar_timing(oscar_ctx *ctx, int32_t enable);
+/* Measurement hook (not part of the method).  oscar_timing(ctx, period)
+ * with period >= 1 resets the totals and samples every period-th
+ * conjugate-gradient iteration of each solve (iteration index divisible by
+ * period): its kernels stamp the device's constant-rate wall clock at the
+ * start and end of every workgroup, and a part's duration is the span from
+ * its first workgroup start to its last workgroup end (the kernel execution
+ * time, without launch gaps); period = 0 stops.  The first enable allocates
+ * 0.5 MiB of device memory per launch of a CG iteration (1 with
+ * OSCAR_PC_JACOBI; about 8 with OSCAR_PC_MG) and a small pinned host
+ * buffer, freed by oscar_destroy; OSCAR_E_ARG if a launch has more than 1040
+ * workgroups.  While timing, at most 32 sampled iterations are enqueued
+ * between two reads of the solver state.
+ * oscar_timing_read(ctx, k, ...) returns the summed time [ms] and the number
+ * of sampled iterations that did work (iterations enqueued past the
+ * device-side convergence test exit at once and are not counted) for part k:
+ *   k = 0  the whole iteration;
+ *   k = 1  the search-direction kernel (OSCAR_PC_JACOBI: the iteration kernel);
+ *   k = 2  OSCAR_PC_MG: fine-grid pre-smoothing with the restriction and the
+ *          vector updates;
+ *   k = 3  OSCAR_PC_MG: the coarse levels of the V-cycle;
+ *   k = 4  OSCAR_PC_MG: fine-grid prolongation, post-smoothing, reduction.
+ * Parts 2-4 read zero with OSCAR_PC_JACOBI.  Reading synchronises the
+ * stream. */
+int32_t oscar_timing(oscar_ctx *ctx, int32_t period);
 int32_t oscar_timing_read(oscar_ctx *ctx, int32_t kernel, double *total_ms, int64_t *launches);
 
 /* ------------------------------------------------------------------------

@@ -109,6 +109,8 @@ void layout(const oscar_desc &D, Carver &cv, Slot *s, bool ctl_block) {
       void **arr[] = {&v.cout, &v.invD, &v.b, &v.x, &v.t};
       for (void **p : arr) *p = cv.take(w * v.nc);
     }
+    const uint64_t ncl = (uint64_t)s->mg.lv[s->mg.L].nc;
+    s->mg.Ainv = cv.take(w * ncl * ncl);
   }
   s->part = (double *)cv.take(8ull * NCH * NVAL * g.nblocks);
   s->st = (SlotState *)cv.take(sizeof(SlotState));
@@ -138,7 +140,7 @@ int check_desc(const oscar_desc *D, std::string &why) {
   if (D->precond == OSCAR_PC_MG) {
     MGInfo mg;
     mg_levels(*D, mg);
-    if (mg.lv[mg.L].nc > MG_LDS_CELLS) { why = "grid too large for the multigrid hierarchy"; return OSCAR_E_ARG; }
+    if (mg.lv[mg.L].nc > MG_DENSE_MAX) { why = "grid too large for the multigrid hierarchy"; return OSCAR_E_ARG; }
   }
   if (D->n_corr < 1 || D->n_corr > 64) { why = "n_corr must be in [1, 64]"; return OSCAR_E_ARG; }
   if (!(D->pcg_rtol > 0) || D->pcg_max_it < 1) { why = "pcg_rtol must be > 0 and pcg_max_it >= 1"; return OSCAR_E_ARG; }
@@ -242,17 +244,33 @@ struct oscar_ctx {
   int k_f = 0;
   double last_E = 0.0, last_res = 0.0;
   int last_pcg = 0, pcg_call = 0, refine_call = 0, maxit_hits = 0;
-  int pcg_pred = 32;        // predicted CG iterations of the next solve (FP64)
-  int pcg_pred_inner = 16;  // same for an FP32 inner solve (mixed)
+  // Predicted CG iterations of the next solve of each kind: [viscous step,
+  // capillary sub-step, stand-alone solve][corrector][first / later inner
+  // solve of the mixed refinement].  The first chunk enqueues that many
+  // iterations, later chunks PRED_STEP more: iterations enqueued past
+  // convergence still cost their (early-exit) launches.
+  static constexpr int PRED_STEP = 4;
+  int pred[3][64][2];
   bool refine_stall = false;  // an outer refinement stopped short of its tolerance
-  // optional per-kernel timing of the two conjugate-gradient passes
+  // optional timing of sampled conjugate-gradient iterations: every
+  // t_period-th iteration of a solve gives each part a stamp pair (earliest
+  // block start as a complement, latest block end) in a small device buffer
+  static constexpr int NT = 5;   // whole iteration, search direction, fine down, coarse levels, fine up
+  static constexpr int TS_CAP = 32;    // sampled iterations per chunk (chunks are cut to TS_CAP periods)
+  int ts_reg = 0;                       // stamp regions per sample: the launches of one iteration
   bool timing = false;
-  std::vector<hipEvent_t> ev;
-  size_t ev_used = 0;
-  double t_ms[2] = {0.0, 0.0};
-  int64_t t_cnt[2] = {0, 0};
-  int t_chunk_it0 = -1, t_chunk_n = 0;   // the chunk whose events are pending
-
+  int t_period = 1;
+  unsigned long long *d_ts = nullptr;   // TS_CAP x ts_reg regions of TS_WORDS words (device)
+  unsigned long long *d_span = nullptr; // TS_CAP x ts_reg spans (device)
+  unsigned long long *h_span = nullptr; // pinned copy of the spans
+  double wall_hz = 0.0;                 // wall-clock rate
+  struct Sample {
+    int it;     // iteration index within the current solve
+    int slot;   // index into the stamp buffer
+  };
+  std::vector<Sample> samples;   // pending (enqueued, not yet folded)
+  double t_ms[NT] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  int64_t t_cnt[NT] = {0, 0, 0, 0, 0};
   Launch L() const {
     Launch l;
     l.slots = d_slot;
@@ -290,73 +308,102 @@ static int set_ctl(oscar_ctx *c, const SlotCtl &ctl) {
   return OSCAR_OK;
 }
 
-// fold the completed event pairs (start, end of one CG launch) into the
-// totals; launches after the device-side convergence test (they exit at
-// once) are left out: a chunk of n launches from iteration it0 did
-// min(n, it - it0) iterations, `it` read from the device state
+// Fold the pending samples into the totals (from the spans of their stamp
+// regions).  Iterations enqueued past the device-side convergence test exit
+// at once and are left out: the device state's `it` counts the iterations
+// the current solve completed.
 static int harvest_timing(oscar_ctx *c) {
-  int real = c->t_chunk_n;
-  if (c->t_chunk_it0 >= 0) {
-    int done_its = c->h_state->it - c->t_chunk_it0;
-    real = done_its < 0 ? 0 : (done_its < c->t_chunk_n ? done_its : c->t_chunk_n);
+  const int done_its = c->h_state->it;
+  const bool mg = c->D.precond == OSCAR_PC_MG;
+  const int ncoarse = mg ? mg_part_launches(c->s, 1) : 0;
+  // parts as ranges of stamp regions: search direction, fine down, coarse levels, fine up
+  const int p0[4] = {0, 1, 2, 2 + ncoarse}, p1[4] = {1, 2, 2 + ncoarse, 3 + ncoarse};
+  const int parts = mg ? 4 : 1;
+  for (const oscar_ctx::Sample &x : c->samples) {
+    if (x.it >= done_its) continue;
+    const unsigned long long *t = c->h_span + 2 * (size_t)c->ts_reg * x.slot;
+    unsigned long long first = ~0ull, last = 0ull;
+    for (int k = 0; k < parts; ++k) {
+      unsigned long long lo = ~0ull, hi = 0ull;
+      for (int r = p0[k]; r < p1[k]; ++r) {
+        lo = t[2 * r] < lo ? t[2 * r] : lo;
+        hi = t[2 * r + 1] > hi ? t[2 * r + 1] : hi;
+      }
+      if (hi <= lo) continue;   // a part that stamped nothing
+      c->t_ms[1 + k] += 1e3 * (double)(hi - lo) / c->wall_hz;
+      c->t_cnt[1 + k] += 1;
+      first = lo < first ? lo : first;
+      last = hi > last ? hi : last;
+    }
+    if (last > first) {
+      c->t_ms[0] += 1e3 * (double)(last - first) / c->wall_hz;
+      c->t_cnt[0] += 1;
+    }
   }
-  for (size_t x = 0; x + 1 < c->ev_used && (int)(x / 2) < real; x += 2) {
-    float ms = 0.f;
-    HIPCHK(c, hipEventElapsedTime(&ms, c->ev[x], c->ev[x + 1]));
-    c->t_ms[0] += ms;
-    c->t_cnt[0] += 1;
-  }
-  c->ev_used = 0;
-  c->t_chunk_it0 = -1;
-  c->t_chunk_n = 0;
+  c->samples.clear();
   return OSCAR_OK;
 }
 
 static int read_state(oscar_ctx *c) {
   HIPCHK(c, hipMemcpyAsync(c->h_state, c->s.st, sizeof(SlotState), hipMemcpyDeviceToHost, c->stream));
+  const bool fold = c->timing && !c->samples.empty();
+  if (fold) {
+    const int nreg = (int)c->samples.size() * c->ts_reg;
+    launch_ts_span(c->d_ts, nreg, c->d_span, c->stream);
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipMemcpyAsync(c->h_span, c->d_span, sizeof(unsigned long long) * 2 * nreg, hipMemcpyDeviceToHost,
+                             c->stream));
+  }
   HIPCHK(c, hipStreamSynchronize(c->stream));
-  if (c->timing && c->ev_used) return harvest_timing(c);
+  if (fold) return harvest_timing(c);
   return OSCAR_OK;
 }
 
-// conjugate-gradient iterations it0 .. it0+n-1; with timing on, each launch
-// is bracketed by events
+// one conjugate-gradient iteration; `ts` (or null): its stamp regions
+// (multigrid: search direction, fine down, the coarse launches, fine up)
 template <typename R>
-static void launch_iteration(oscar_ctx *c, const Launch &L, int it) {
+static void launch_iteration(oscar_ctx *c, const Launch &L, int it, unsigned long long *ts) {
+  auto region = [&](int r) -> unsigned long long * { return ts ? ts + (size_t)TS_WORDS * r : nullptr; };
   if (c->D.precond == OSCAR_PC_MG) {
-    launch_mg_dir<R>(L, it);
-    launch_mg_vcycle<R>(c->s, L, it);
+    const int ncoarse = mg_part_launches(c->s, 1);
+    launch_mg_dir<R>(L, it, region(0));
+    launch_mg_cycle_part<R>(c->s, L, it, 0, region(1));
+    launch_mg_cycle_part<R>(c->s, L, it, 1, region(2));
+    launch_mg_cycle_part<R>(c->s, L, it, 2, region(2 + ncoarse));
   } else {
-    launch_cg_iters<R>(L, it, 1);
+    launch_cg_iters<R>(L, it, 1, region(0));
   }
 }
 
+// conjugate-gradient iterations it0 .. it0+n-1 (with timing on, every
+// t_period-th iteration is sampled; the stamp words of the chunk's samples
+// are zeroed first)
 template <typename R>
 static int enqueue_cg(oscar_ctx *c, int it0, int n) {
   Launch L = c->L();
-  if (!c->timing) {
-    for (int x = 0; x < n; ++x) launch_iteration<R>(c, L, it0 + x);
-    HIPCHK(c, hipGetLastError());
-    return OSCAR_OK;
-  }
-  if (c->ev_used) {   // fold a previous chunk first (its state was read)
-    int rc = harvest_timing(c);
+  if (c->timing && !c->samples.empty()) {   // fold a previous chunk first (the stamp buffer is reused)
+    int rc = read_state(c);
     if (rc) return rc;
   }
-  c->t_chunk_it0 = it0;
-  c->t_chunk_n = n;
-  size_t need = c->ev_used + 2 * (size_t)n;
-  while (c->ev.size() < need) {
-    hipEvent_t e;
-    HIPCHK(c, hipEventCreate(&e));
-    c->ev.push_back(e);
+  int ns = 0;
+  if (c->timing) {
+    for (int x = 0; x < n; ++x)
+      if ((it0 + x) % c->t_period == 0 && ns < oscar_ctx::TS_CAP) ++ns;
+    if (ns)
+      HIPCHK(c, hipMemsetAsync(c->d_ts, 0, sizeof(unsigned long long) * TS_WORDS * c->ts_reg * ns, c->stream));
   }
+  int used = 0;
   for (int x = 0; x < n; ++x) {
-    HIPCHK(c, hipEventRecord(c->ev[c->ev_used++], c->stream));
-    launch_iteration<R>(c, L, it0 + x);
-    HIPCHK(c, hipGetLastError());
-    HIPCHK(c, hipEventRecord(c->ev[c->ev_used++], c->stream));
+    const int it = it0 + x;
+    unsigned long long *ts = nullptr;
+    if (c->timing && it % c->t_period == 0 && used < ns) {
+      ts = c->d_ts + (size_t)TS_WORDS * c->ts_reg * used;
+      c->samples.push_back({it, used});
+      ++used;
+    }
+    launch_iteration<R>(c, L, it, ts);
   }
+  HIPCHK(c, hipGetLastError());
   return OSCAR_OK;
 }
 
@@ -378,12 +425,14 @@ static void append_segment(std::vector<int2> &bt, int slot, int nb) {
   }
 }
 
-// relative tolerance of each FP32 inner solve of the mixed-precision path
+// smallest relative residual reduction asked of one FP32 inner solve of the
+// mixed-precision path (each inner solve otherwise stops at the residual the
+// FP64 test needs)
 static double inner_rtol() {
   static double v = [] {
     const char *e = getenv("OSCAR_INNER_RTOL");
-    double x = e ? atof(e) : 1e-3;
-    return x > 0 && x < 1 ? x : 1e-3;
+    double x = e ? atof(e) : 1e-5;
+    return x > 0 && x < 1 ? x : 1e-5;
   }();
   return v;
 }
@@ -444,6 +493,8 @@ extern "C" int32_t oscar_create(const oscar_desc *desc, void *ws, uint64_t bytes
     if (!desc->mask[P] && !std::isfinite(desc->alpha0[P])) { g_err = "alpha0 has a non-finite value"; return OSCAR_E_ARG; }
 
   oscar_ctx *c = new oscar_ctx();
+  for (auto &kind : c->pred)
+    for (auto &corr : kind) corr[0] = corr[1] = 16;
   c->D = *desc;
   c->D.mask = nullptr;
   c->D.alpha0 = nullptr;
@@ -532,7 +583,9 @@ extern "C" int32_t oscar_create(const oscar_desc *desc, void *ws, uint64_t bytes
 extern "C" void oscar_destroy(oscar_ctx *c) {
   if (!c) return;
   if (c->stream) (void)hipStreamSynchronize(c->stream);
-  for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+  if (c->d_ts) (void)hipFree(c->d_ts);
+  if (c->d_span) (void)hipFree(c->d_span);
+  if (c->h_span) (void)hipHostFree(c->h_span);
   if (c->h_state) (void)hipHostFree(c->h_state);
   delete c;
 }
@@ -547,7 +600,7 @@ extern "C" const char *oscar_last_error(const oscar_ctx *c) { return c ? c->err.
 // device: chunks of CG iterations until the slot's done flag is set; in mixed
 // precision, FP32 inner solves wrapped in FP64 refinement.
 template <typename R>
-static int solve_pressure(oscar_ctx *c, int &iters) {
+static int solve_pressure(oscar_ctx *c, int &iters, int kind, int corr) {
   int rc = read_state(c);
   if (rc) return rc;
   c->refine_stall = false;
@@ -561,32 +614,36 @@ static int solve_pressure(oscar_ctx *c, int &iters) {
     HIPCHK(c, hipGetLastError());
   }
   auto inner = [&](int &pred) -> int {
-    if (mg) launch_mg_vcycle<R>(c->s, c->L(), -1);   // z_0 = B r_0
+    if (mg)   // z_0 = B r_0
+      for (int part = 0; part < 3; ++part) launch_mg_cycle_part<R>(c->s, c->L(), -1, part);
     else launch_cg_init<R>(c->L());
     HIPCHK(c, hipGetLastError());
     int it0 = 0;
-    int chunk = pred > 2 ? pred : 2;
+    int chunk = pred > 1 ? pred : 1;
     while (!c->h_state->done) {
       if (it0 > max_it + 1) { c->err = "conjugate gradient did not terminate"; return OSCAR_E_HIP; }
-      int r = enqueue_cg<R>(c, it0, chunk);
+      // with timing on, a chunk holds at most TS_CAP samples
+      const int n = c->timing && chunk > oscar_ctx::TS_CAP * c->t_period ? oscar_ctx::TS_CAP * c->t_period : chunk;
+      int r = enqueue_cg<R>(c, it0, n);
       if (r) return r;
-      it0 += chunk;
+      it0 += n;
       r = read_state(c);
       if (r) return r;
-      chunk = 8;
+      chunk = oscar_ctx::PRED_STEP;
     }
     int used = c->h_state->it;
-    pred = used > 2 ? used : 2;
+    pred = used > 1 ? used : 1;
     return OSCAR_OK;
   };
+  int (&pr)[2] = c->pred[kind][corr < 63 ? corr : 63];
   if (!c->mixed()) {
-    rc = inner(c->pcg_pred);
+    rc = inner(pr[0]);
     if (rc) return rc;
   } else {
     int outer = 0;
     double last = c->h_state->rn64;
     while (!c->h_state->done) {
-      rc = inner(c->pcg_pred_inner);
+      rc = inner(pr[outer > 0 ? 1 : 0]);
       if (rc) return rc;
       launch_refine<R>(c->L());
       HIPCHK(c, hipGetLastError());
@@ -616,7 +673,7 @@ static int run_correctors(oscar_ctx *c, bool cr, double &E, int &warn) {
     launch_pressure_setup<R>(L, cr && j == 0);
     HIPCHK(c, hipGetLastError());
     int it = 0;
-    int rc = solve_pressure<R>(c, it);
+    int rc = solve_pressure<R>(c, it, cr ? 1 : 0, j);
     if (rc) return rc;
     if (cr && j == 0) E = c->h_state->E;
     c->last_pcg = it;
@@ -754,7 +811,6 @@ static int pressure_solve_t(oscar_ctx *c, int which, double dt, double rtol, int
   if (rc) return rc;
   launch_state_reset(L, 1);
   // alpha_old = alpha (no transport), then curvature, momentum, predictor, solve
-  int saved_pred = c->pcg_pred, saved_inner = c->pcg_pred_inner;
   int saved_max = c->D.pcg_max_it;
   c->D.pcg_max_it = max_it;
   if (which == 0) launch_copy_phi_prev<R>(L);
@@ -766,10 +822,8 @@ static int pressure_solve_t(oscar_ctx *c, int which, double dt, double rtol, int
   launch_pressure_setup<R>(L, false);
   HIPCHK(c, hipGetLastError());
   int it = 0;
-  rc = solve_pressure<R>(c, it);
+  rc = solve_pressure<R>(c, it, 2, 0);
   c->D.pcg_max_it = saved_max;
-  c->pcg_pred = saved_pred;
-  c->pcg_pred_inner = saved_inner;
   if (rc) return rc;
   int warn = c->h_state->maxit_hit ? OSCAR_W_PCG_MAXIT : (c->refine_stall ? OSCAR_W_REFINE_STALL : OSCAR_OK);
   if (iters) *iters = it;
@@ -901,26 +955,46 @@ extern "C" int32_t oscar_stats(oscar_ctx *c, oscar_stats_t *o) {
   return OSCAR_OK;
 }
 
-extern "C" int32_t oscar_timing(oscar_ctx *c, int32_t enable) {
-  if (!c) return OSCAR_E_ARG;
-  if (c->timing && c->ev_used) {
-    HIPCHK(c, hipStreamSynchronize(c->stream));
-    int rc = harvest_timing(c);
+extern "C" int32_t oscar_timing(oscar_ctx *c, int32_t period) {
+  if (!c || period < 0) return OSCAR_E_ARG;
+  if (c->timing && !c->samples.empty()) {
+    int rc = read_state(c);
     if (rc) return rc;
   }
-  c->timing = enable != 0;
+  if (period && c->btab_len > TS_WORDS / 2) {
+    c->err = "timing supports at most 1040 workgroups per launch";
+    return OSCAR_E_ARG;
+  }
+  if (period && !c->d_ts) {   // measurement buffers, kept until oscar_destroy
+    int dev = 0, khz = 0;
+    HIPCHK(c, hipGetDevice(&dev));
+    HIPCHK(c, hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+    if (khz <= 0) {
+      c->err = "device reports no wall-clock rate";
+      return OSCAR_E_HIP;
+    }
+    c->wall_hz = 1e3 * (double)khz;
+    c->ts_reg = c->D.precond == OSCAR_PC_MG ? 3 + mg_part_launches(c->s, 1) : 1;
+    const size_t regions = (size_t)oscar_ctx::TS_CAP * c->ts_reg;
+    HIPCHK(c, hipMalloc((void **)&c->d_ts, sizeof(unsigned long long) * TS_WORDS * regions));
+    HIPCHK(c, hipMalloc((void **)&c->d_span, sizeof(unsigned long long) * 2 * regions));
+    HIPCHK(c, hipHostMalloc((void **)&c->h_span, sizeof(unsigned long long) * 2 * regions, hipHostMallocDefault));
+  }
+  c->timing = period != 0;
   if (c->timing) {
-    c->t_ms[0] = c->t_ms[1] = 0.0;
-    c->t_cnt[0] = c->t_cnt[1] = 0;
+    c->t_period = period;
+    for (int k = 0; k < oscar_ctx::NT; ++k) {
+      c->t_ms[k] = 0.0;
+      c->t_cnt[k] = 0;
+    }
   }
   return OSCAR_OK;
 }
 
 extern "C" int32_t oscar_timing_read(oscar_ctx *c, int32_t kernel, double *total_ms, int64_t *launches) {
-  if (!c || kernel < 0 || kernel > 1) return OSCAR_E_ARG;
-  if (c->ev_used) {
-    HIPCHK(c, hipStreamSynchronize(c->stream));
-    int rc = harvest_timing(c);
+  if (!c || kernel < 0 || kernel >= oscar_ctx::NT) return OSCAR_E_ARG;
+  if (!c->samples.empty()) {
+    int rc = read_state(c);
     if (rc) return rc;
   }
   if (total_ms) *total_ms = c->t_ms[kernel];

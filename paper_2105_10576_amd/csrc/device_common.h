@@ -170,6 +170,23 @@ __device__ __forceinline__ void for_owned_faces(const Slot &s, const Cell &c, Fn
   }
 }
 
+// Measurement only: with a non-null ts, workgroup b of the launch writes its
+// start and end on the device's constant-rate wall clock to ts[2b], ts[2b+1]
+// (plain stores: no contention between workgroups).
+struct Stamp {
+  unsigned long long *ts;
+  unsigned long long t0;
+  __device__ __forceinline__ explicit Stamp(unsigned long long *p) : ts(p), t0(p ? wall_clock64() : 0ull) {}
+  __device__ __forceinline__ void done() {
+    if (!ts) return;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      ts[2 * blockIdx.x] = t0;
+      ts[2 * blockIdx.x + 1] = (unsigned long long)wall_clock64();
+    }
+  }
+};
+
 // ---------------------------------------------------------------------------
 // deterministic per-slot reductions
 // ---------------------------------------------------------------------------

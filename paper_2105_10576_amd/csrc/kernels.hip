@@ -575,6 +575,15 @@ __global__ void __launch_bounds__(BLOCK) k_pressure_setup(const Slot *slots, con
   put_partials<0u>(s, B.lb, CH_SETUP, red);
 }
 
+// Mixed precision: the FP32 inner solve of M e = r (|r| = rn) stops at the
+// residual the FP64 test needs, half of rtol |b| (|b| = bn), but is never
+// asked for a relative reduction below rtol_inner, which FP32 reaches
+// reliably; the outer refinement covers the rest.
+__device__ __forceinline__ double inner_target(const SlotCtl &ctl, double bn, double rn) {
+  double need = 0.5 * ctl.rtol * bn, floor = ctl.rtol_inner * rn;
+  return need > floor ? need : floor;
+}
+
 // one block per slot: norms of the pressure equation, initial convergence test
 __global__ void __launch_bounds__(BLOCK) k_setup_fin(const Slot *slots) {
   const Slot &s = slots[blockIdx.x];
@@ -596,6 +605,7 @@ __global__ void __launch_bounds__(BLOCK) k_setup_fin(const Slot *slots) {
     st->rn64 = rn;
     // mixed precision: the FP32 inner system is M e = r, measured against |r|
     st->bn = s.precision != 0 ? rn : bn;
+    st->tgt = inner_target(ctl, bn, rn);
   }
 }
 
@@ -683,8 +693,9 @@ __global__ void __launch_bounds__(BLOCK) k_cg_init(const Slot *slots, const int2
 // iteration it (0-based): scalars from the previous reduction, convergence
 // test (it > 0), vector updates, w_{it+1} = A D^-1 r_{it+1}, next reduction
 template <typename R>
-__global__ void __launch_bounds__(BLOCK) k_cg(const Slot *slots, const int2 *btab, int it) {
+__global__ void __launch_bounds__(BLOCK) k_cg(const Slot *slots, const int2 *btab, int it, unsigned long long *ts) {
   using T = R;
+  Stamp stamp(ts);
   Block B = block_of(slots, btab);
   const Slot &s = *B.s;
   const Grid G = grid_of(s);
@@ -701,8 +712,7 @@ __global__ void __launch_bounds__(BLOCK) k_cg(const Slot *slots, const int2 *bta
     alpha = gam / del;
   } else {
     double rn = sqrt(v[2]);
-    double rtol = mixed ? ctl.rtol_inner : ctl.rtol;
-    bool conv = rn <= rtol * st->bn;
+    bool conv = rn <= (mixed ? st->tgt : ctl.rtol * st->bn);
     bool cap = !conv && it >= ctl.max_it;
     if (conv || cap) {
       if (B.lb == 0 && threadIdx.x == 0) {
@@ -760,6 +770,7 @@ __global__ void __launch_bounds__(BLOCK) k_cg(const Slot *slots, const int2 *bta
     red[2] = red[2] + (double)(rn * rn);
   });
   put_partials<0u>(s, B.lb, CH_CG0 + (it & 1), red);
+  stamp.done();
 }
 
 // mixed precision, outer refinement: p += e, e = 0
@@ -817,6 +828,7 @@ __global__ void __launch_bounds__(BLOCK) k_refine_fin(const Slot *slots) {
     st->rn64 = sqrt(v[0]);
     st->bn = sqrt(v[1]);
     st->rn = st->bn;
+    st->tgt = inner_target(ctl, st->bn64, st->bn);
     st->it = 0;
     st->refine_steps = st->refine_steps + 1;
     st->done = st->rn64 <= ctl.rtol * st->bn64;
@@ -963,8 +975,8 @@ template <typename R> void launch_cg_init(const Launch &L) {
   hipLaunchKernelGGL(k_cg_init<R>, GRID(L), L.slots, L.btab);
 }
 
-template <typename R> void launch_cg_iters(const Launch &L, int it0, int n) {
-  for (int x = 0; x < n; ++x) hipLaunchKernelGGL(k_cg<R>, GRID(L), L.slots, L.btab, it0 + x);
+template <typename R> void launch_cg_iters(const Launch &L, int it0, int n, unsigned long long *ts) {
+  for (int x = 0; x < n; ++x) hipLaunchKernelGGL(k_cg<R>, GRID(L), L.slots, L.btab, it0 + x, ts);
 }
 
 template <typename R> void launch_refine(const Launch &L) {
@@ -993,6 +1005,37 @@ void launch_gather_states(const Launch &L, int nslots, SlotState *out) {
   hipLaunchKernelGGL(k_gather_states, dim3((nslots + 63) / 64), dim3(64), 0, L.stream, L.slots, nslots, out);
 }
 
+// measurement only: span (earliest start, latest end) of each stamp region;
+// workgroups that stamped nothing (zero words) are skipped
+__global__ void __launch_bounds__(BLOCK) k_ts_span(const unsigned long long *ts, unsigned long long *out) {
+  const unsigned long long *r = ts + (size_t)blockIdx.x * TS_WORDS;
+  unsigned long long lo = ~0ull, hi = 0ull;
+  for (int b = threadIdx.x; b < TS_WORDS / 2; b += BLOCK) {
+    const unsigned long long a = r[2 * b], e = r[2 * b + 1];
+    if (a != 0ull && a < lo) lo = a;
+    if (e > hi) hi = e;
+  }
+  __shared__ unsigned long long sl[BLOCK], sh[BLOCK];
+  sl[threadIdx.x] = lo;
+  sh[threadIdx.x] = hi;
+  __syncthreads();
+  for (int w = BLOCK / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      if (sl[threadIdx.x + w] < sl[threadIdx.x]) sl[threadIdx.x] = sl[threadIdx.x + w];
+      if (sh[threadIdx.x + w] > sh[threadIdx.x]) sh[threadIdx.x] = sh[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[2 * blockIdx.x] = sl[0];
+    out[2 * blockIdx.x + 1] = sh[0];
+  }
+}
+
+void launch_ts_span(const unsigned long long *ts, int nregions, unsigned long long *out, hipStream_t stream) {
+  hipLaunchKernelGGL(k_ts_span, dim3((unsigned)nregions), dim3(BLOCK), 0, stream, ts, out);
+}
+
 void launch_state_reset(const Launch &L, int nslots) {
   hipLaunchKernelGGL(k_state_reset, dim3((nslots + 63) / 64), dim3(64), 0, L.stream, L.slots, nslots);
 }
@@ -1005,7 +1048,7 @@ void launch_state_reset(const Launch &L, int nslots) {
   template void launch_predictor<R>(const Launch &);              \
   template void launch_pressure_setup<R>(const Launch &, bool);   \
   template void launch_cg_init<R>(const Launch &);                \
-  template void launch_cg_iters<R>(const Launch &, int, int);     \
+  template void launch_cg_iters<R>(const Launch &, int, int, unsigned long long *); \
   template void launch_refine<R>(const Launch &);                 \
   template void launch_correct<R>(const Launch &, int);           \
   template void launch_finalize<R>(const Launch &);               \

@@ -7,27 +7,36 @@
 // face coefficient is half the sum of the fine face coefficients crossing it
 // (the piecewise-constant Galerkin product scaled to match a rediscretisation
 // on the doubled spacing); outlet coefficients are aggregated the same way.
-// Cycle: one damped Jacobi sweep (omega = 0.8) from zero before restriction
-// and one after prolongation on every level, a fixed number of Jacobi sweeps
-// on the coarsest level; the cycle is a symmetric linear operator, as the
-// conjugate gradient needs.
+// Cycle: damped Jacobi sweeps (omega = 0.9) from zero before restriction and
+// after prolongation, one on the fine grid and MG_NU on the coarse levels,
+// the exact solve on the coarsest level (at most a few dozen cells) with its
+// dense inverse, formed at setup; pre- and post-smoothing are the same
+// sweeps, so the cycle is a symmetric linear operator, as the conjugate
+// gradient needs.  A second sweep is fused into the same launch: each cell
+// re-evaluates the first sweep at its neighbours (a radius-2 stencil) rather
+// than waiting for another launch.
 //
 // Execution: the pre-smoothing kernels walk their level in child order (the
 // 2^dim cells of one coarser cell are consecutive lanes of a wavefront), so
 // the restriction of the residual is a lane-shuffle sum inside the same
 // kernel and no restriction launch or residual array exists.  The small
 // levels (from the one the host marks as the tail down to the coarsest) run
-// inside one workgroup; the coarsest level is solved in LDS with its
-// operator held in registers.  No atomics.
+// inside one workgroup.  No atomics.
 #include "device_common.h"
 
 namespace oscar {
 
-constexpr int MG_TAIL_THREADS = 1024;   // workgroup of the tail kernel
-constexpr int MG_COARSE_SWEEPS = 48;    // Jacobi sweeps on the coarsest level
-constexpr double MG_OMEGA = 0.8;        // Jacobi damping
+// Smoothing sweeps before and after the coarse correction on levels >= 1.
+// Two sweeps cut the CG iterations by a third, but evaluating the first
+// sweep at the neighbours makes the latency-bound coarse kernels (and the
+// single-workgroup tail above all) about three times slower, a net loss on
+// the 128 x 64 x 64 channel; one sweep with omega = 0.9 is the faster choice.
+constexpr int MG_NU = 1;
+constexpr int MG_TAIL_THREADS = MG_NU == 1 ? 1024 : 512;   // workgroup of the tail kernel (register budget)
+constexpr int MG_INV_THREADS = 1024;    // workgroup of the coarse inversion
+constexpr double MG_OMEGA = 0.9;        // Jacobi damping
 
-static_assert(MG_LDS_CELLS <= MG_TAIL_THREADS, "one coarsest-level cell per tail thread");
+static_assert(MG_DENSE_MAX <= MG_TAIL_THREADS, "one coarsest-level cell per tail thread");
 
 struct LCell {
   int P, i, j, k;
@@ -113,6 +122,17 @@ __device__ __forceinline__ T lmatvec(const LV<T> &L, const LCell &c, XV &&xv) {
   }
   acc = acc + co * xP;
   return acc;
+}
+
+// the cell next to c across the low (side = -1) or high (+1) face of
+// direction e; c itself for side = 0
+__device__ __forceinline__ LCell lshift(const LCell &c, int e, int side, const int (&st)[3]) {
+  LCell q = c;
+  q.P += side * st[e];
+  if (e == 0) q.i += side;
+  else if (e == 1) q.j += side;
+  else q.k += side;
+  return q;
 }
 
 // parent on the next coarser level of the neighbour across a face: moving
@@ -232,18 +252,72 @@ __global__ void __launch_bounds__(BLOCK) k_mg_setup(const Slot *slot, int l) {
   for (int g = blockIdx.x * BLOCK + threadIdx.x; g < C.nc; g += gridDim.x * BLOCK) setup_cell<T, R>(s, l, g);
 }
 
+// Dense inverse of the coarsest operator (n <= MG_DENSE_MAX cells) by
+// Gauss-Jordan elimination in LDS without pivoting (the operator is
+// symmetric positive definite on its cells with fluid); a cell without fluid
+// has an empty row and column and gets a zero row and column in the inverse.
+template <typename T>
+__global__ void __launch_bounds__(MG_INV_THREADS) k_mg_coarse_inv(const Slot *slot) {
+  const Slot &s = *slot;
+  const MGLevel &C = s.mg.lv[s.mg.L];
+  const int n = C.nc, dim = s.dim;
+  if (n > MG_DENSE_MAX) return;   // excluded by the host's hierarchy check
+  __shared__ T A[MG_DENSE_MAX * MG_DENSE_MAX];
+  const int nn = n * n;
+  for (int x = threadIdx.x; x < nn; x += MG_INV_THREADS) A[x] = (T)0;
+  __syncthreads();
+  if ((int)threadIdx.x < n) {
+    const int g = threadIdx.x;
+    const LCell c = lcell(C.nx, C.ny, g);
+    const int st[3] = {1, C.nx, C.nxy}, q[3] = {c.i, c.j, c.k}, nd[3] = {C.nx, C.ny, C.nz};
+    T diag = ((const T *)C.cout)[g];
+    for (int e = 0; e < dim; ++e) {
+      const T *cf = (const T *)C.cf[e];
+      const T cl = cf[g];
+      const T ch = q[e] < nd[e] - 1 ? cf[g + st[e]] : (T)0;
+      diag = diag + cl + ch;
+      if (q[e] > 0) A[g * n + g - st[e]] = -cl;
+      if (q[e] < nd[e] - 1) A[g * n + g + st[e]] = -ch;
+    }
+    A[g * n + g] = diag;
+  }
+  __syncthreads();
+  for (int k = 0; k < n; ++k) {
+    const T akk = A[k * n + k];
+    T nv[(MG_DENSE_MAX * MG_DENSE_MAX + MG_INV_THREADS - 1) / MG_INV_THREADS];
+    int m = 0;
+    for (int x = threadIdx.x; x < nn; x += MG_INV_THREADS, ++m) {
+      const int i = x / n, j = x - i * n;
+      const T aij = A[x], aik = A[i * n + k], akj = A[k * n + j];
+      if (akk == (T)0) nv[m] = aij;   // empty row and column: nothing to eliminate
+      else if (i == k && j == k) nv[m] = (T)1 / akk;
+      else if (i == k) nv[m] = akj / akk;
+      else if (j == k) nv[m] = -(aik / akk);
+      else nv[m] = aij - aik * (akj / akk);
+    }
+    __syncthreads();
+    m = 0;
+    for (int x = threadIdx.x; x < nn; x += MG_INV_THREADS, ++m) A[x] = nv[m];
+    __syncthreads();
+  }
+  T *out = (T *)s.mg.Ainv;
+  for (int x = threadIdx.x; x < nn; x += MG_INV_THREADS) out[x] = A[x];
+}
+
 // ---------------------------------------------------------------------------
 // cycle pieces on coarse levels (DIM = 2 or 3)
 // ---------------------------------------------------------------------------
 
 // Pre-smoothing from zero on level L in child order, with the restriction:
-// x = w D^-1 b, t = b - A x, b_next[parent] = sum of the children's t.
-// (cnx, cny, cnc) are the dimensions of the next coarser level; bnext may
-// point to global memory or to LDS.
+// x_1 = w D^-1 b, x_{m+1} = x_m + w D^-1 (b - A x_m) up to MG_NU sweeps,
+// t = b - A x, b_next[parent] = sum of the children's t.  (cnx, cny, cnc)
+// are the dimensions of the next coarser level; bnext may point to global
+// memory or to LDS.
 template <int DIM, typename T>
 __device__ __forceinline__ void smooth_restrict(const LV<T> &L, int cnx, int cny, int cnc, T *bnext, unsigned start,
                                                 unsigned stride) {
   const T w = (T)MG_OMEGA;
+  const int st[3] = {1, L.nx, L.nxy};
   const unsigned total = (unsigned)cnc << DIM;
   for (unsigned tau = start; tau < total; tau += stride) {
     const Kid q = kid_at(tau, DIM, L.nx, L.ny, L.nz, cnx, cny);
@@ -254,9 +328,23 @@ __device__ __forceinline__ void smooth_restrict(const LV<T> &L, int cnx, int cny
       c.i = q.i;
       c.j = q.j;
       c.k = q.k;
-      auto xv = [&](int n, int, int) -> T { return w * (L.invD[n] * L.b[n]); };
-      const T Ax = lmatvec<DIM, T>(L, c, xv);
-      L.x[c.P] = xv(c.P, 0, 0);
+      auto x1 = [&](int n, int, int) -> T { return w * (L.invD[n] * L.b[n]); };
+      T xP;
+      T Ax;
+      if constexpr (MG_NU == 1) {
+        xP = x1(c.P, 0, 0);
+        Ax = lmatvec<DIM, T>(L, c, x1);
+      } else {
+        static_assert(MG_NU == 2, "one or two sweeps");
+        auto x2at = [&](const LCell &p) -> T {
+          const T Ax1 = lmatvec<DIM, T>(L, p, x1);
+          return x1(p.P, 0, 0) + w * (L.invD[p.P] * (L.b[p.P] - Ax1));
+        };
+        xP = x2at(c);
+        auto x2 = [&](int, int e, int side) -> T { return side == 0 ? xP : x2at(lshift(c, e, side, st)); };
+        Ax = lmatvec<DIM, T>(L, c, x2);
+      }
+      L.x[c.P] = xP;
       tv = L.b[c.P] - Ax;
     }
     tv = kid_sum(tv, DIM);
@@ -264,122 +352,100 @@ __device__ __forceinline__ void smooth_restrict(const LV<T> &L, int cnx, int cny
   }
 }
 
-// prolongation and post-smoothing on level L: x' = x + P xc (xc on the next
+// prolongation and post-smoothing on level L: y = x + P xc (xc on the next
 // coarser level, of dims (cnx, ., .) and plane size cnxy; global memory or
-// LDS), out = x' + w D^-1 (b - A x')
+// LDS), then MG_NU sweeps y <- y + w D^-1 (b - A y); out = y
 template <int DIM, typename T>
 __device__ __forceinline__ void up_range(const LV<T> &L, int cnx, int cnxy, const T *xc, T *out, int start, int stride) {
   const T w = (T)MG_OMEGA;
-  const int cst[3] = {1, cnx, cnxy};
+  const int st[3] = {1, L.nx, L.nxy};
   for (int g = start; g < L.nc; g += stride) {
     const LCell c = lcell(L.nx, L.ny, g);
-    const int pP = (c.i >> 1) + cnx * (c.j >> 1) + cnxy * (c.k >> 1);
-    const int q[3] = {c.i, c.j, c.k};
-    auto xv = [&](int n, int e, int side) -> T { return L.x[n] + xc[pP + parent_shift(q[e], side, cst[e])]; };
-    const T xp = xv(g, 0, 0);
-    const T Ax = lmatvec<DIM, T>(L, c, xv);
-    out[g] = xp + w * (L.invD[g] * (L.b[g] - Ax));
+    auto y0at = [&](const LCell &p) -> T { return L.x[p.P] + xc[(p.i >> 1) + cnx * (p.j >> 1) + cnxy * (p.k >> 1)]; };
+    // one sweep evaluated at cell p from y0 at p and its neighbours
+    auto y1at = [&](const LCell &p) -> T {
+      auto y0 = [&](int, int e, int side) -> T { return y0at(lshift(p, e, side, st)); };
+      return y0at(p) + w * (L.invD[p.P] * (L.b[p.P] - lmatvec<DIM, T>(L, p, y0)));
+    };
+    T res;
+    if constexpr (MG_NU == 1) {
+      res = y1at(c);
+    } else {
+      const T y1P = y1at(c);
+      auto y1 = [&](int, int e, int side) -> T { return side == 0 ? y1P : y1at(lshift(c, e, side, st)); };
+      res = y1P + w * (L.invD[g] * (L.b[g] - lmatvec<DIM, T>(L, c, y1)));
+    }
+    out[g] = res;
   }
 }
 
 __device__ __forceinline__ bool mg_idle(const Slot &s) { return !s.ctl->active || s.st->done; }
 
 template <int DIM, typename T>
-__global__ void __launch_bounds__(BLOCK) k_mg_smooth(const Slot *slot, int l) {
+__global__ void __launch_bounds__(BLOCK) k_mg_smooth(const Slot *slot, int l, unsigned long long *ts) {
+  Stamp stamp(ts);
   const Slot &s = *slot;
   if (mg_idle(s)) return;
   const LV<T> L = lview<T>(s.mg.lv[l]);
   const MGLevel &C = s.mg.lv[l + 1];
   smooth_restrict<DIM, T>(L, C.nx, C.ny, C.nc, (T *)C.b, blockIdx.x * BLOCK + threadIdx.x, gridDim.x * BLOCK);
+  stamp.done();
 }
 
 // final correction of level l goes to t_l (x_l keeps the pre-smoothed one)
 template <int DIM, typename T>
-__global__ void __launch_bounds__(BLOCK) k_mg_up(const Slot *slot, int l) {
+__global__ void __launch_bounds__(BLOCK) k_mg_up(const Slot *slot, int l, unsigned long long *ts) {
+  Stamp stamp(ts);
   const Slot &s = *slot;
   if (mg_idle(s)) return;
   const LV<T> L = lview<T>(s.mg.lv[l]);
   const MGLevel &C = s.mg.lv[l + 1];
   up_range<DIM, T>(L, C.nx, C.nxy, (const T *)C.t, L.t, blockIdx.x * BLOCK + threadIdx.x, gridDim.x * BLOCK);
+  stamp.done();
 }
 
 // Levels tail..L in one workgroup: the down-sweep to the coarsest level
-// (whose right-hand side goes straight to LDS), Jacobi sweeps on the
-// coarsest level with each thread's row of the operator in registers and the
-// iterates in LDS, the up-sweep back to the tail level.
+// (whose right-hand side goes straight to LDS), the coarsest solve with the
+// dense inverse, the up-sweep back to the tail level.
 template <int DIM, typename T>
-__global__ void __launch_bounds__(MG_TAIL_THREADS) k_mg_tail(const Slot *slot) {
+__global__ void __launch_bounds__(MG_TAIL_THREADS) k_mg_tail(const Slot *slot, unsigned long long *ts) {
+  Stamp stamp(ts);
   const Slot &s = *slot;
   if (mg_idle(s)) return;
   const int tl = s.mg.tail, L = s.mg.L;
   const int t0 = threadIdx.x, ns = MG_TAIL_THREADS;
   const LV<T> C = lview<T>(s.mg.lv[L]);
-  if (C.nc > MG_LDS_CELLS) return;   // excluded by the host's hierarchy check
-  __shared__ T sb[MG_LDS_CELLS];
-  __shared__ T sx[2][MG_LDS_CELLS];
+  if (C.nc > MG_DENSE_MAX) return;   // excluded by the host's hierarchy check
+  __shared__ T sb[MG_DENSE_MAX];
+  __shared__ T sx[MG_DENSE_MAX];
   for (int l = tl; l < L; ++l) {
     const MGLevel &N = s.mg.lv[l + 1];
     smooth_restrict<DIM, T>(lview<T>(s.mg.lv[l]), N.nx, N.ny, N.nc, l + 1 == L ? sb : (T *)N.b, t0, ns);
     __syncthreads();
   }
-  // this thread's row of the coarsest operator (absent neighbours: the cell
-  // itself with a zero coefficient)
-  const bool mine = t0 < C.nc;
-  int nb[2 * DIM];
-  T cc[2 * DIM], co = (T)0, id = (T)0, bb = (T)0;
-#pragma unroll
-  for (int f = 0; f < 2 * DIM; ++f) {
-    nb[f] = mine ? t0 : 0;
-    cc[f] = (T)0;
-  }
-  if (mine) {
-    const LCell c = lcell(C.nx, C.ny, t0);
-    const int st[3] = {1, C.nx, C.nxy}, q[3] = {c.i, c.j, c.k}, n[3] = {C.nx, C.ny, C.nz};
-#pragma unroll
-    for (int e = 0; e < DIM; ++e) {
-      if (q[e] > 0) {
-        nb[2 * e] = t0 - st[e];
-        cc[2 * e] = C.cf[e][t0];
-      }
-      if (q[e] < n[e] - 1) {
-        nb[2 * e + 1] = t0 + st[e];
-        cc[2 * e + 1] = C.cf[e][t0 + st[e]];
-      }
-    }
-    co = C.cout[t0];
-    id = C.invD[t0];
-    bb = L > tl ? sb[t0] : C.b[t0];
-    sx[0][t0] = (T)0;
+  // coarsest level: x = A^-1 b with the dense inverse (row t0, fixed order)
+  const int n = C.nc;
+  if (t0 < n) {
+    const T *Ai = (const T *)s.mg.Ainv + t0 * n;
+    const T *bL = L > tl ? sb : C.b;
+    T acc = (T)0;
+    for (int m = 0; m < n; ++m) acc = acc + Ai[m] * bL[m];
+    sx[t0] = acc;
   }
   __syncthreads();
-  const T w = (T)MG_OMEGA;
-  for (int sw = 0; sw < MG_COARSE_SWEEPS; ++sw) {
-    const T *xi = sx[sw & 1];
-    T *xo = sx[(sw + 1) & 1];
-    if (mine) {
-      const T xP = xi[t0];
-      T xn[2 * DIM];
-#pragma unroll
-      for (int f = 0; f < 2 * DIM; ++f) xn[f] = xi[nb[f]];
-      T acc = (T)0;
-#pragma unroll
-      for (int f = 0; f < 2 * DIM; ++f) acc = acc + cc[f] * (xP - xn[f]);
-      acc = acc + co * xP;
-      xo[t0] = xP + w * (id * (bb - acc));
-    }
-    __syncthreads();
-  }
-  const T *xL = sx[MG_COARSE_SWEEPS & 1];
   if (L == tl) {   // no level of the tail above the coarsest: hand the result on in global memory
-    if (mine) C.t[t0] = xL[t0];
+    if (t0 < n) C.t[t0] = sx[t0];
+    stamp.done();
     return;
   }
+  const T *xL = sx;
   for (int l = L - 1; l >= tl; --l) {
     const MGLevel &N = s.mg.lv[l + 1];
     const LV<T> Lv = lview<T>(s.mg.lv[l]);
     up_range<DIM, T>(Lv, N.nx, N.nxy, l == L - 1 ? xL : (const T *)N.t, Lv.t, t0, ns);
     __syncthreads();
   }
+  stamp.done();
 }
 
 // ---------------------------------------------------------------------------
@@ -404,8 +470,10 @@ __device__ __forceinline__ bool fine_block(const Slot *slots, const int2 *btab, 
 // previous cycle's reduction, convergence test (it > 0), beta, d = z + beta
 // d_old (d = z when it = 0), q = A d and <d,q>.
 template <typename R>
-__global__ void __launch_bounds__(BLOCK) k_mgcg_dir(const Slot *slots, const int2 *btab, int it) {
+__global__ void __launch_bounds__(BLOCK) k_mgcg_dir(const Slot *slots, const int2 *btab, int it,
+                                                    unsigned long long *ts) {
   using T = R;
+  Stamp stamp(ts);
   FBlock B;
   if (!fine_block(slots, btab, B)) return;
   const Slot &s = *B.s;
@@ -420,8 +488,7 @@ __global__ void __launch_bounds__(BLOCK) k_mgcg_dir(const Slot *slots, const int
   double beta = 0.0;
   if (it > 0) {
     double rn = sqrt(v[1]);
-    double rtol = mixed ? ctl.rtol_inner : ctl.rtol;
-    bool conv = rn <= rtol * st->bn;
+    bool conv = rn <= (mixed ? st->tgt : ctl.rtol * st->bn);
     bool cap = !conv && it >= ctl.max_it;
     if (conv || cap) {
       if (lb == 0 && threadIdx.x == 0) {
@@ -456,6 +523,7 @@ __global__ void __launch_bounds__(BLOCK) k_mgcg_dir(const Slot *slots, const int
     red[0] = red[0] + (double)(dP * qq);
   });
   put_partials<0u>(s, lb, CH_DQ, red);
+  stamp.done();
 }
 
 // Iteration it >= 0: alpha = gamma / <d,q>, x += alpha d, r -= alpha q; for
@@ -463,8 +531,10 @@ __global__ void __launch_bounds__(BLOCK) k_mgcg_dir(const Slot *slots, const int
 // Then the cycle's fine pre-smoothing z0 = w D^-1 r and the restriction of
 // its residual r - A z0 into level 1, walking the fine grid in child order.
 template <typename R>
-__global__ void __launch_bounds__(BLOCK) k_mg_fine_down(const Slot *slots, const int2 *btab, int it) {
+__global__ void __launch_bounds__(BLOCK) k_mg_fine_down(const Slot *slots, const int2 *btab, int it,
+                                                        unsigned long long *ts) {
   using T = R;
+  Stamp stamp(ts);
   FBlock B;
   if (!fine_block(slots, btab, B)) return;
   const Slot &s = *B.s;
@@ -529,13 +599,16 @@ __global__ void __launch_bounds__(BLOCK) k_mg_fine_down(const Slot *slots, const
     tv = kid_sum(tv, dim);
     if (k.lead) b1[k.parent] = tv;
   }
+  stamp.done();
 }
 
 // Last step of the cycle: z' = z0 + P x1, z = z' + w D^-1 (r - A z'); the
 // reduction <r,z>, |r|^2 for the next search direction.
 template <typename R>
-__global__ void __launch_bounds__(BLOCK) k_mg_fine_up(const Slot *slots, const int2 *btab, int it) {
+__global__ void __launch_bounds__(BLOCK) k_mg_fine_up(const Slot *slots, const int2 *btab, int it,
+                                                      unsigned long long *ts) {
   using T = R;
+  Stamp stamp(ts);
   FBlock B;
   if (!fine_block(slots, btab, B)) return;
   const Slot &s = *B.s;
@@ -572,6 +645,7 @@ __global__ void __launch_bounds__(BLOCK) k_mg_fine_up(const Slot *slots, const i
     red[1] = red[1] + (double)(rr * rr);
   });
   put_partials<0u>(s, lb, CH_CG0 + (it & 1), red);
+  stamp.done();
 }
 
 // ---------------------------------------------------------------------------
@@ -583,45 +657,53 @@ static unsigned lvl_grid(int nc) {
   return (unsigned)(n < 1024 ? (n > 0 ? n : 1) : 1024);
 }
 
-#define FGRID(L) dim3((unsigned)(L).nblocks), dim3(BLOCK), 0, (L).stream
 
 template <typename R>
 void launch_mg_setup(const Slot &hs, const Slot *ds, hipStream_t stream) {
   for (int l = 1; l <= hs.mg.L; ++l)
     hipLaunchKernelGGL((k_mg_setup<R, R>), dim3(lvl_grid(hs.mg.lv[l].nc)), dim3(BLOCK), 0, stream, ds, l);
+  hipLaunchKernelGGL(k_mg_coarse_inv<R>, dim3(1), dim3(MG_INV_THREADS), 0, stream, ds);
 }
 
 template <typename R>
-void launch_mg_dir(const Launch &L, int it) {
-  hipLaunchKernelGGL(k_mgcg_dir<R>, FGRID(L), L.slots, L.btab, it);
+void launch_mg_dir(const Launch &L, int it, unsigned long long *ts) {
+  hipLaunchKernelGGL(k_mgcg_dir<R>, dim3((unsigned)L.nblocks), dim3(BLOCK), 0, L.stream, L.slots, L.btab, it, ts);
 }
 
 template <int DIM, typename R>
-static void vcycle_levels(const Slot &hs, const Launch &L) {
+static void vcycle_levels(const Slot &hs, const Launch &L, unsigned long long *ts) {
   const Slot *ds = L.slots;
   const int tl = hs.mg.tail;
+  int m = 0;   // launch index within the part: its stamp region
+  auto next = [&]() -> unsigned long long * { return ts ? ts + (size_t)TS_WORDS * m++ : nullptr; };
   for (int l = 1; l < tl; ++l)
-    hipLaunchKernelGGL((k_mg_smooth<DIM, R>), dim3(lvl_grid(hs.mg.lv[l + 1].nc << DIM)), dim3(BLOCK), 0, L.stream, ds, l);
-  hipLaunchKernelGGL((k_mg_tail<DIM, R>), dim3(1), dim3(MG_TAIL_THREADS), 0, L.stream, ds);
+    hipLaunchKernelGGL((k_mg_smooth<DIM, R>), dim3(lvl_grid(hs.mg.lv[l + 1].nc << DIM)), dim3(BLOCK), 0, L.stream, ds,
+                       l, next());
+  hipLaunchKernelGGL((k_mg_tail<DIM, R>), dim3(1), dim3(MG_TAIL_THREADS), 0, L.stream, ds, next());
   for (int l = tl - 1; l >= 1; --l)
-    hipLaunchKernelGGL((k_mg_up<DIM, R>), dim3(lvl_grid(hs.mg.lv[l].nc)), dim3(BLOCK), 0, L.stream, ds, l);
+    hipLaunchKernelGGL((k_mg_up<DIM, R>), dim3(lvl_grid(hs.mg.lv[l].nc)), dim3(BLOCK), 0, L.stream, ds, l, next());
 }
 
-// the cycle of iteration it (it = -1: the cycle of the initial residual)
+// part of the cycle of iteration it (it = -1: the cycle of the initial residual)
 template <typename R>
-void launch_mg_vcycle(const Slot &hs, const Launch &L, int it) {
+void launch_mg_cycle_part(const Slot &hs, const Launch &L, int it, int part, unsigned long long *ts) {
   const Slot *ds = L.slots;
-  hipLaunchKernelGGL(k_mg_fine_down<R>, FGRID(L), ds, L.btab, it);
-  if (hs.dim == 3) vcycle_levels<3, R>(hs, L);
-  else vcycle_levels<2, R>(hs, L);
-  hipLaunchKernelGGL(k_mg_fine_up<R>, FGRID(L), ds, L.btab, it);
+  const dim3 fg((unsigned)L.nblocks), fb(BLOCK);
+  if (part == 0) {
+    hipLaunchKernelGGL(k_mg_fine_down<R>, fg, fb, 0, L.stream, ds, L.btab, it, ts);
+  } else if (part == 1) {
+    if (hs.dim == 3) vcycle_levels<3, R>(hs, L, ts);
+    else vcycle_levels<2, R>(hs, L, ts);
+  } else {
+    hipLaunchKernelGGL(k_mg_fine_up<R>, fg, fb, 0, L.stream, ds, L.btab, it, ts);
+  }
 }
 
 template void launch_mg_setup<double>(const Slot &, const Slot *, hipStream_t);
 template void launch_mg_setup<float>(const Slot &, const Slot *, hipStream_t);
-template void launch_mg_dir<double>(const Launch &, int);
-template void launch_mg_dir<float>(const Launch &, int);
-template void launch_mg_vcycle<double>(const Slot &, const Launch &, int);
-template void launch_mg_vcycle<float>(const Slot &, const Launch &, int);
+template void launch_mg_dir<double>(const Launch &, int, unsigned long long *);
+template void launch_mg_dir<float>(const Launch &, int, unsigned long long *);
+template void launch_mg_cycle_part<double>(const Slot &, const Launch &, int, int, unsigned long long *);
+template void launch_mg_cycle_part<float>(const Slot &, const Launch &, int, int, unsigned long long *);
 
 }  // namespace oscar

@@ -33,13 +33,14 @@ struct SlotState {
   double pbar, E;                          // normalised residual
   double comax, mass0, mass1, bflux;       // transport
   double rn64, bn64;                       // refinement (mixed precision)
+  double tgt;                              // absolute residual target of the FP32 inner solve
   double mass_defect;
   int32_t it, done, zero_rhs, total_it;
   int32_t nonfinite, unstable, maxit_hit, refine_steps;
 };
 
 struct SlotCtl {
-  double dt, ub, rtol, rtol_inner;
+  double dt, ub, rtol, rtol_inner;   // rtol_inner: smallest relative reduction asked of one FP32 inner solve
   int32_t active, mode, with_st, max_it;
   int32_t last_corr, substep, n_sub, pad;   // substep: index within the relaxation
   double tol;
@@ -47,12 +48,13 @@ struct SlotCtl {
 
 // Geometric multigrid hierarchy of the pressure matrix (preconditioner):
 // every dimension halved (rounding up) per level until a level has at most
-// MG_COARSEST cells; levels of at most MG_TAIL_CELLS cells run in one
-// workgroup; the coarsest level must fit the LDS arrays of MG_LDS_CELLS.
+// MG_COARSEST cells (at most MG_MAXL levels); levels of at most
+// MG_TAIL_CELLS cells run in one workgroup; the coarsest level is solved
+// with its dense inverse, so it may have at most MG_DENSE_MAX cells.
 constexpr int MG_MAXL = 12;
-constexpr int MG_COARSEST = 128;
+constexpr int MG_COARSEST = 16;
 constexpr int MG_TAIL_CELLS = 4096;
-constexpr int MG_LDS_CELLS = 512;
+constexpr int MG_DENSE_MAX = 64;
 struct MGLevel {
   int32_t nx, ny, nz, nc, nxy, nblocks;
   void *cf[3];        // coefficient of each cell's low face per direction (T)
@@ -64,6 +66,7 @@ struct MGInfo {
   int32_t L;          // coarsest level (levels 1..L); 0 = no hierarchy
   int32_t tail;       // first level handled by the single-workgroup tail kernel
   MGLevel lv[MG_MAXL + 1];
+  void *Ainv;         // dense inverse of the coarsest operator, row-major (T)
 };
 
 struct Slot {
@@ -114,7 +117,13 @@ template <typename R> void launch_assemble(const Launch &L);
 template <typename R> void launch_predictor(const Launch &L);
 template <typename R> void launch_pressure_setup(const Launch &L, bool normres);
 template <typename R> void launch_cg_init(const Launch &L);
-template <typename R> void launch_cg_iters(const Launch &L, int it0, int n);
+// Measurement only: a launch given a non-null `ts` (TS_WORDS zeroed 64-bit
+// words) leaves in ts[2b], ts[2b+1] the start and end of its workgroup b on
+// the device's constant-rate wall clock; k_ts_span reduces such regions.
+constexpr int TS_WORDS = 2 * 1040;   // two words per workgroup, at most 1040 workgroups per launch
+void launch_ts_span(const unsigned long long *ts, int nregions, unsigned long long *out, hipStream_t stream);
+// n iterations from it0 (with ts: n = 1)
+template <typename R> void launch_cg_iters(const Launch &L, int it0, int n, unsigned long long *ts = nullptr);
 template <typename R> void launch_refine(const Launch &L);
 template <typename R> void launch_correct(const Launch &L, int last);
 template <typename R> void launch_finalize(const Launch &L);
@@ -124,8 +133,15 @@ void launch_state_reset(const Launch &L, int nslots);
 
 // multigrid-preconditioned CG (single slot; mg.hip)
 template <typename R> void launch_mg_setup(const Slot &hs, const Slot *dslot, hipStream_t st);
-template <typename R> void launch_mg_vcycle(const Slot &hs, const Launch &L, int it);
-template <typename R> void launch_mg_dir(const Launch &L, int it);
+// part 0: fine pre-smoothing with restriction (and the CG update of
+// iteration it >= 0); part 1: the coarse levels; part 2: fine prolongation,
+// post-smoothing and the next reduction
+// (with ts: one TS_WORDS region per launch, launches of part 1 in
+// consecutive regions; mg_part_launches gives their number)
+template <typename R> void launch_mg_cycle_part(const Slot &hs, const Launch &L, int it, int part,
+                                                unsigned long long *ts = nullptr);
+inline int mg_part_launches(const Slot &hs, int part) { return part == 1 ? 2 * (hs.mg.tail - 1) + 1 : 1; }
+template <typename R> void launch_mg_dir(const Launch &L, int it, unsigned long long *ts = nullptr);
 void launch_gather_states(const Launch &L, int nslots, SlotState *out);
 
 // blocks per slot: ceil(cells/BLOCK), capped (grid-stride beyond the cap)

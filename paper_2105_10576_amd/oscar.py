@@ -218,8 +218,9 @@ class Oscar:
         assert a.size == lib().oscar_field_len(self.ctx, fid)
         self._check(lib().oscar_set_field(self.ctx, fid, a.ctypes.data_as(C.POINTER(C.c_double))))
 
-    def timing(self, enable):
-        self._check(lib().oscar_timing(self.ctx, int(bool(enable))))
+    def timing(self, period):
+        """period >= 1: bracket every period-th CG iteration (True = 1); 0 / False: stop."""
+        self._check(lib().oscar_timing(self.ctx, int(period)))
 
     def timing_read(self, kernel):
         ms = C.c_double(0.0)

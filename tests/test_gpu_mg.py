@@ -112,16 +112,30 @@ def test_mg_channel_bubble_steps_fp64():
 
 
 def test_mg_timing_counts_iterations():
-    """The timing hook brackets whole preconditioned iterations and counts
-    only those that did work."""
+    """The timing hook brackets whole preconditioned iterations and their
+    parts, counts only iterations that did work, and samples every
+    period-th iteration."""
     o = _oscar()
     c = cases.tiny_box(nx=48, ny=40, nz=40, dim=3, seed=7, solid_cells=_solid_block(48, 40, 40, 3))
     f = cases.random_fields(c, seed=11)
     g = o.Oscar(c, precision=o.FP64, precond=o.PC_MG)
     g.set("U_cr", f["U"])
     g.set("phi_cr", f["phi"])
-    g.timing(True)
+    g.timing(1)
     rc, it, res = g.pressure_solve(1, 1e-5, 1e-10, 5000)
-    g.timing(False)
-    ms, n = g.timing_read(0)
+    parts = [g.timing_read(k) for k in range(5)]
+    g.timing(0)
+    ms, n = parts[0]
     assert n == it and ms > 0
+    for k in range(1, 5):
+        assert parts[k][1] == it and parts[k][0] > 0
+    # the parts are disjoint intervals inside the whole iteration (kernel
+    # execution times; the launch gaps between them are not in any part)
+    assert sum(parts[k][0] for k in range(1, 5)) <= ms * (1 + 1e-6)
+    # sampling: every 4th iteration (indices 0, 4, 8, ... below it)
+    g.timing(4)
+    g.set("p_cr", np.zeros_like(g.get("p_cr")))
+    rc, it, res = g.pressure_solve(1, 1e-5, 1e-10, 5000)
+    ms4, n4 = g.timing_read(0)
+    g.timing(0)
+    assert n4 == (it + 3) // 4
