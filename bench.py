@@ -141,6 +141,24 @@ def dominant(table):
     return best
 
 
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    passes (profiles/pmc_traffic.json), or None when the kernel's sources
+    changed since the counters were taken."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path)).get(kernel)
+    if not rec:
+        return None
+    h = hashlib.sha256()
+    for f in rec["sources"]:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return rec["bytes_per_launch"] if h.hexdigest() == rec["sources_sha256"] else None
+
+
 def cpu_baseline(case):
     """The FP64 oracle on the host: the first viscous-drag step of the same
     workload (3 PISO correctors with Jacobi-PCG), one cell-iteration per cell."""
@@ -238,7 +256,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None,
+            "traffic": measured_traffic(dom),
             "avg_launch_us": d["avg_us"],
             "alg_bytes_per_launch": d["alg_bytes"],
             "launches_timed": d["launches_timed"],
