@@ -246,9 +246,13 @@ struct oscar_ctx {
   int last_pcg = 0, pcg_call = 0, refine_call = 0, maxit_hits = 0;
   // Predicted CG iterations of the next solve of each kind: [viscous step,
   // capillary sub-step, stand-alone solve][corrector][first / later inner
-  // solve of the mixed refinement].  The first chunk enqueues that many
-  // iterations, later chunks PRED_STEP more: iterations enqueued past
-  // convergence still cost their (early-exit) launches.
+  // solve of the mixed refinement].  The first chunk enqueues PRED_MARGIN
+  // iterations more than that, later chunks PRED_STEP more.  Iterations
+  // enqueued past convergence cost their early-exit launches (about a
+  // microsecond each); one chunk too few costs a host round trip with the
+  // GPU idle, which is far more (measured: margin 2 takes a mixed step of
+  // the 128 x 64 x 64 channel from 73 to 61 ms).
+  static constexpr int PRED_MARGIN = 2;
   static constexpr int PRED_STEP = 4;
   int pred[3][64][2];
   bool refine_stall = false;  // an outer refinement stopped short of its tolerance
@@ -366,7 +370,7 @@ static void launch_iteration(oscar_ctx *c, const Launch &L, int it, unsigned lon
   auto region = [&](int r) -> unsigned long long * { return ts ? ts + (size_t)TS_WORDS * r : nullptr; };
   if (c->D.precond == OSCAR_PC_MG) {
     const int ncoarse = mg_part_launches(c->s, 1);
-    launch_mg_dir<R>(L, it, region(0));
+    launch_mg_dir<R>(c->s, L, it, region(0));
     launch_mg_cycle_part<R>(c->s, L, it, 0, region(1));
     launch_mg_cycle_part<R>(c->s, L, it, 1, region(2));
     launch_mg_cycle_part<R>(c->s, L, it, 2, region(2 + ncoarse));
@@ -610,7 +614,7 @@ static int solve_pressure(oscar_ctx *c, int &iters, int kind, int corr) {
   // then chunks of iterations from index 0 until the device flags it done
   const bool mg = c->D.precond == OSCAR_PC_MG;
   if (mg) {   // coarse operators of this equation's coefficients
-    launch_mg_setup<R>(c->s, c->d_slot, c->stream);
+    launch_mg_setup<R>(c->s, c->stream);
     HIPCHK(c, hipGetLastError());
   }
   auto inner = [&](int &pred) -> int {
@@ -619,7 +623,7 @@ static int solve_pressure(oscar_ctx *c, int &iters, int kind, int corr) {
     else launch_cg_init<R>(c->L());
     HIPCHK(c, hipGetLastError());
     int it0 = 0;
-    int chunk = pred > 1 ? pred : 1;
+    int chunk = pred + oscar_ctx::PRED_MARGIN;
     while (!c->h_state->done) {
       if (it0 > max_it + 1) { c->err = "conjugate gradient did not terminate"; return OSCAR_E_HIP; }
       // with timing on, a chunk holds at most TS_CAP samples

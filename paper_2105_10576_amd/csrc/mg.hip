@@ -246,8 +246,8 @@ __device__ void setup_cell(const Slot &s, int l, int g) {
 }
 
 template <typename T, typename R>
-__global__ void __launch_bounds__(BLOCK) k_mg_setup(const Slot *slot, int l) {
-  const Slot &s = *slot;
+__global__ void __launch_bounds__(BLOCK) k_mg_setup(const Slot S, int l) {
+  const Slot &s = S;
   const MGLevel &C = s.mg.lv[l];
   for (int g = blockIdx.x * BLOCK + threadIdx.x; g < C.nc; g += gridDim.x * BLOCK) setup_cell<T, R>(s, l, g);
 }
@@ -257,8 +257,8 @@ __global__ void __launch_bounds__(BLOCK) k_mg_setup(const Slot *slot, int l) {
 // symmetric positive definite on its cells with fluid); a cell without fluid
 // has an empty row and column and gets a zero row and column in the inverse.
 template <typename T>
-__global__ void __launch_bounds__(MG_INV_THREADS) k_mg_coarse_inv(const Slot *slot) {
-  const Slot &s = *slot;
+__global__ void __launch_bounds__(MG_INV_THREADS) k_mg_coarse_inv(const Slot S) {
+  const Slot &s = S;
   const MGLevel &C = s.mg.lv[s.mg.L];
   const int n = C.nc, dim = s.dim;
   if (n > MG_DENSE_MAX) return;   // excluded by the host's hierarchy check
@@ -379,12 +379,15 @@ __device__ __forceinline__ void up_range(const LV<T> &L, int cnx, int cnxy, cons
   }
 }
 
-__device__ __forceinline__ bool mg_idle(const Slot &s) { return !s.ctl->active || s.st->done; }
+// The multigrid kernels serve one context (its record passed by value: the
+// fields are read from the constant argument segment) whose control block
+// is active during every solve; they return at once after convergence.
+__device__ __forceinline__ bool mg_idle(const Slot &s) { return s.st->done != 0; }
 
 template <int DIM, typename T>
-__global__ void __launch_bounds__(BLOCK) k_mg_smooth(const Slot *slot, int l, unsigned long long *ts) {
+__global__ void __launch_bounds__(BLOCK) k_mg_smooth(const Slot S, int l, unsigned long long *ts) {
   Stamp stamp(ts);
-  const Slot &s = *slot;
+  const Slot &s = S;
   if (mg_idle(s)) return;
   const LV<T> L = lview<T>(s.mg.lv[l]);
   const MGLevel &C = s.mg.lv[l + 1];
@@ -394,9 +397,9 @@ __global__ void __launch_bounds__(BLOCK) k_mg_smooth(const Slot *slot, int l, un
 
 // final correction of level l goes to t_l (x_l keeps the pre-smoothed one)
 template <int DIM, typename T>
-__global__ void __launch_bounds__(BLOCK) k_mg_up(const Slot *slot, int l, unsigned long long *ts) {
+__global__ void __launch_bounds__(BLOCK) k_mg_up(const Slot S, int l, unsigned long long *ts) {
   Stamp stamp(ts);
-  const Slot &s = *slot;
+  const Slot &s = S;
   if (mg_idle(s)) return;
   const LV<T> L = lview<T>(s.mg.lv[l]);
   const MGLevel &C = s.mg.lv[l + 1];
@@ -408,9 +411,9 @@ __global__ void __launch_bounds__(BLOCK) k_mg_up(const Slot *slot, int l, unsign
 // (whose right-hand side goes straight to LDS), the coarsest solve with the
 // dense inverse, the up-sweep back to the tail level.
 template <int DIM, typename T>
-__global__ void __launch_bounds__(MG_TAIL_THREADS) k_mg_tail(const Slot *slot, unsigned long long *ts) {
+__global__ void __launch_bounds__(MG_TAIL_THREADS) k_mg_tail(const Slot S, unsigned long long *ts) {
   Stamp stamp(ts);
-  const Slot &s = *slot;
+  const Slot &s = S;
   if (mg_idle(s)) return;
   const int tl = s.mg.tail, L = s.mg.L;
   const int t0 = threadIdx.x, ns = MG_TAIL_THREADS;
@@ -453,35 +456,30 @@ __global__ void __launch_bounds__(MG_TAIL_THREADS) k_mg_tail(const Slot *slot, u
 // (block-table launches like the other fine-grid kernels)
 // ---------------------------------------------------------------------------
 
-struct FBlock {
-  const Slot *s;
-  int lb;
-};
-
-__device__ __forceinline__ bool fine_block(const Slot *slots, const int2 *btab, FBlock &b) {
-  int2 t = btab[blockIdx.x];
-  if (t.y < 0) return false;   // padding entry of the block table
-  b.s = slots + t.x;
-  b.lb = t.y;
-  return b.s->ctl->active && !b.s->st->done;
+// this workgroup's block within the slot (XCD-ordered block table); false
+// for padding entries and once the solve has converged
+__device__ __forceinline__ bool fine_block(const Slot &s, const int2 *btab, int &lb) {
+  const int done = s.st->done;
+  const int2 t = btab[blockIdx.x];
+  lb = t.y;
+  return !done && t.y >= 0;
 }
 
 // Search direction of iteration it: gamma_it = <r,z> and |r|^2 from the
 // previous cycle's reduction, convergence test (it > 0), beta, d = z + beta
 // d_old (d = z when it = 0), q = A d and <d,q>.
 template <typename R>
-__global__ void __launch_bounds__(BLOCK) k_mgcg_dir(const Slot *slots, const int2 *btab, int it,
+__global__ void __launch_bounds__(BLOCK) k_mgcg_dir(const Slot S, const int2 *btab, int it,
                                                     unsigned long long *ts) {
   using T = R;
   Stamp stamp(ts);
-  FBlock B;
-  if (!fine_block(slots, btab, B)) return;
-  const Slot &s = *B.s;
+  const Slot &s = S;
+  int lb;
+  if (!fine_block(s, btab, lb)) return;
   const Grid G = grid_of(s);
   const SlotCtl &ctl = *s.ctl;
   SlotState *st = s.st;
   const bool mixed = s.precision != 0;
-  const int lb = B.lb;
   double v[2];
   get_totals<0u>(s, CH_CG0 + ((it + 1) & 1), v);   // written by the cycle of iteration it - 1
   const double gam = v[0];
@@ -531,18 +529,17 @@ __global__ void __launch_bounds__(BLOCK) k_mgcg_dir(const Slot *slots, const int
 // Then the cycle's fine pre-smoothing z0 = w D^-1 r and the restriction of
 // its residual r - A z0 into level 1, walking the fine grid in child order.
 template <typename R>
-__global__ void __launch_bounds__(BLOCK) k_mg_fine_down(const Slot *slots, const int2 *btab, int it,
+__global__ void __launch_bounds__(BLOCK) k_mg_fine_down(const Slot S, const int2 *btab, int it,
                                                         unsigned long long *ts) {
   using T = R;
   Stamp stamp(ts);
-  FBlock B;
-  if (!fine_block(slots, btab, B)) return;
-  const Slot &s = *B.s;
+  const Slot &s = S;
+  int lb;
+  if (!fine_block(s, btab, lb)) return;
   const Grid G = grid_of(s);
   const SlotCtl &ctl = *s.ctl;
   SlotState *st = s.st;
   const bool mixed = s.precision != 0;
-  const int lb = B.lb;
   const bool upd = it >= 0;
   T al = (T)0;
   if (upd) {
@@ -605,15 +602,14 @@ __global__ void __launch_bounds__(BLOCK) k_mg_fine_down(const Slot *slots, const
 // Last step of the cycle: z' = z0 + P x1, z = z' + w D^-1 (r - A z'); the
 // reduction <r,z>, |r|^2 for the next search direction.
 template <typename R>
-__global__ void __launch_bounds__(BLOCK) k_mg_fine_up(const Slot *slots, const int2 *btab, int it,
+__global__ void __launch_bounds__(BLOCK) k_mg_fine_up(const Slot S, const int2 *btab, int it,
                                                       unsigned long long *ts) {
   using T = R;
   Stamp stamp(ts);
-  FBlock B;
-  if (!fine_block(slots, btab, B)) return;
-  const Slot &s = *B.s;
+  const Slot &s = S;
+  int lb;
+  if (!fine_block(s, btab, lb)) return;
   const Grid G = grid_of(s);
-  const int lb = B.lb;
   const uint8_t *flags = s.flags;
   const R *rAU = (const R *)s.rAU;
   const T *invD = (const T *)s.invD;
@@ -649,7 +645,7 @@ __global__ void __launch_bounds__(BLOCK) k_mg_fine_up(const Slot *slots, const i
 }
 
 // ---------------------------------------------------------------------------
-// host launchers (one slot: L.slots[0])
+// host launchers (one slot: its record hs passed by value)
 // ---------------------------------------------------------------------------
 
 static unsigned lvl_grid(int nc) {
@@ -659,50 +655,48 @@ static unsigned lvl_grid(int nc) {
 
 
 template <typename R>
-void launch_mg_setup(const Slot &hs, const Slot *ds, hipStream_t stream) {
+void launch_mg_setup(const Slot &hs, hipStream_t stream) {
   for (int l = 1; l <= hs.mg.L; ++l)
-    hipLaunchKernelGGL((k_mg_setup<R, R>), dim3(lvl_grid(hs.mg.lv[l].nc)), dim3(BLOCK), 0, stream, ds, l);
-  hipLaunchKernelGGL(k_mg_coarse_inv<R>, dim3(1), dim3(MG_INV_THREADS), 0, stream, ds);
+    hipLaunchKernelGGL((k_mg_setup<R, R>), dim3(lvl_grid(hs.mg.lv[l].nc)), dim3(BLOCK), 0, stream, hs, l);
+  hipLaunchKernelGGL(k_mg_coarse_inv<R>, dim3(1), dim3(MG_INV_THREADS), 0, stream, hs);
 }
 
 template <typename R>
-void launch_mg_dir(const Launch &L, int it, unsigned long long *ts) {
-  hipLaunchKernelGGL(k_mgcg_dir<R>, dim3((unsigned)L.nblocks), dim3(BLOCK), 0, L.stream, L.slots, L.btab, it, ts);
+void launch_mg_dir(const Slot &hs, const Launch &L, int it, unsigned long long *ts) {
+  hipLaunchKernelGGL(k_mgcg_dir<R>, dim3((unsigned)L.nblocks), dim3(BLOCK), 0, L.stream, hs, L.btab, it, ts);
 }
 
 template <int DIM, typename R>
 static void vcycle_levels(const Slot &hs, const Launch &L, unsigned long long *ts) {
-  const Slot *ds = L.slots;
   const int tl = hs.mg.tail;
   int m = 0;   // launch index within the part: its stamp region
   auto next = [&]() -> unsigned long long * { return ts ? ts + (size_t)TS_WORDS * m++ : nullptr; };
   for (int l = 1; l < tl; ++l)
-    hipLaunchKernelGGL((k_mg_smooth<DIM, R>), dim3(lvl_grid(hs.mg.lv[l + 1].nc << DIM)), dim3(BLOCK), 0, L.stream, ds,
+    hipLaunchKernelGGL((k_mg_smooth<DIM, R>), dim3(lvl_grid(hs.mg.lv[l + 1].nc << DIM)), dim3(BLOCK), 0, L.stream, hs,
                        l, next());
-  hipLaunchKernelGGL((k_mg_tail<DIM, R>), dim3(1), dim3(MG_TAIL_THREADS), 0, L.stream, ds, next());
+  hipLaunchKernelGGL((k_mg_tail<DIM, R>), dim3(1), dim3(MG_TAIL_THREADS), 0, L.stream, hs, next());
   for (int l = tl - 1; l >= 1; --l)
-    hipLaunchKernelGGL((k_mg_up<DIM, R>), dim3(lvl_grid(hs.mg.lv[l].nc)), dim3(BLOCK), 0, L.stream, ds, l, next());
+    hipLaunchKernelGGL((k_mg_up<DIM, R>), dim3(lvl_grid(hs.mg.lv[l].nc)), dim3(BLOCK), 0, L.stream, hs, l, next());
 }
 
 // part of the cycle of iteration it (it = -1: the cycle of the initial residual)
 template <typename R>
 void launch_mg_cycle_part(const Slot &hs, const Launch &L, int it, int part, unsigned long long *ts) {
-  const Slot *ds = L.slots;
   const dim3 fg((unsigned)L.nblocks), fb(BLOCK);
   if (part == 0) {
-    hipLaunchKernelGGL(k_mg_fine_down<R>, fg, fb, 0, L.stream, ds, L.btab, it, ts);
+    hipLaunchKernelGGL(k_mg_fine_down<R>, fg, fb, 0, L.stream, hs, L.btab, it, ts);
   } else if (part == 1) {
     if (hs.dim == 3) vcycle_levels<3, R>(hs, L, ts);
     else vcycle_levels<2, R>(hs, L, ts);
   } else {
-    hipLaunchKernelGGL(k_mg_fine_up<R>, fg, fb, 0, L.stream, ds, L.btab, it, ts);
+    hipLaunchKernelGGL(k_mg_fine_up<R>, fg, fb, 0, L.stream, hs, L.btab, it, ts);
   }
 }
 
-template void launch_mg_setup<double>(const Slot &, const Slot *, hipStream_t);
-template void launch_mg_setup<float>(const Slot &, const Slot *, hipStream_t);
-template void launch_mg_dir<double>(const Launch &, int, unsigned long long *);
-template void launch_mg_dir<float>(const Launch &, int, unsigned long long *);
+template void launch_mg_setup<double>(const Slot &, hipStream_t);
+template void launch_mg_setup<float>(const Slot &, hipStream_t);
+template void launch_mg_dir<double>(const Slot &, const Launch &, int, unsigned long long *);
+template void launch_mg_dir<float>(const Slot &, const Launch &, int, unsigned long long *);
 template void launch_mg_cycle_part<double>(const Slot &, const Launch &, int, int, unsigned long long *);
 template void launch_mg_cycle_part<float>(const Slot &, const Launch &, int, int, unsigned long long *);
 

@@ -132,7 +132,9 @@ void launch_ctl_update(const Launch &L, const CtlUpdate &u);
 void launch_state_reset(const Launch &L, int nslots);
 
 // multigrid-preconditioned CG (single slot; mg.hip)
-template <typename R> void launch_mg_setup(const Slot &hs, const Slot *dslot, hipStream_t st);
+// (the multigrid kernels take the context's slot record by value: `hs`, the
+// host copy, whose pointers are device addresses)
+template <typename R> void launch_mg_setup(const Slot &hs, hipStream_t st);
 // part 0: fine pre-smoothing with restriction (and the CG update of
 // iteration it >= 0); part 1: the coarse levels; part 2: fine prolongation,
 // post-smoothing and the next reduction
@@ -141,7 +143,7 @@ template <typename R> void launch_mg_setup(const Slot &hs, const Slot *dslot, hi
 template <typename R> void launch_mg_cycle_part(const Slot &hs, const Launch &L, int it, int part,
                                                 unsigned long long *ts = nullptr);
 inline int mg_part_launches(const Slot &hs, int part) { return part == 1 ? 2 * (hs.mg.tail - 1) + 1 : 1; }
-template <typename R> void launch_mg_dir(const Launch &L, int it, unsigned long long *ts = nullptr);
+template <typename R> void launch_mg_dir(const Slot &hs, const Launch &L, int it, unsigned long long *ts = nullptr);
 void launch_gather_states(const Launch &L, int nslots, SlotState *out);
 
 // blocks per slot: ceil(cells/BLOCK), capped (grid-stride beyond the cap)
