@@ -194,7 +194,9 @@ const char *oscar_last_error(const oscar_ctx *ctx);
  * oscar_timing_read(ctx, k, ...) returns the summed time [ms] and the number
  * of sampled iterations that did work (iterations enqueued past the
  * device-side convergence test exit at once and are not counted) for part k:
- *   k = 0  the whole iteration;
+ *   k = 0  the whole iteration (when a read of the solver state by the host
+ *          falls between its search-direction launch and the rest, the
+ *          two spans without the gap);
  *   k = 1  the search-direction kernel (OSCAR_PC_JACOBI: the iteration kernel);
  *   k = 2  OSCAR_PC_MG: fine-grid pre-smoothing with the restriction and the
  *          vector updates;

@@ -60,12 +60,12 @@ struct Carver {
 };
 
 // Multigrid hierarchy: halve every dimension (rounding up) until a level
-// has at most MG_COARSEST cells (at most MG_MAXL levels); levels of at most
-// MG_TAIL_CELLS cells are run by the single-workgroup tail kernel.
+// has at most MG_COARSEST cells (at most MG_MAXL levels); the tail (run by
+// one workgroup out of LDS) starts at the first level of at most
+// MG_TAIL_CELLS cells whose block fits MG_TAIL_LDS bytes.
 void mg_levels(const oscar_desc &D, MGInfo &mg) {
   int nx = D.nx, ny = D.ny, nz = D.nz;
   mg.L = 0;
-  mg.tail = 0;
   do {
     nx = (nx + 1) / 2;
     ny = (ny + 1) / 2;
@@ -77,9 +77,15 @@ void mg_levels(const oscar_desc &D, MGInfo &mg) {
     v.nxy = nx * ny;
     v.nc = nx * ny * nz;
     v.nblocks = 0;
-    if (!mg.tail && v.nc <= MG_TAIL_CELLS) mg.tail = mg.L;
   } while (mg.lv[mg.L].nc > MG_COARSEST && mg.L < MG_MAXL);
-  if (!mg.tail) mg.tail = mg.L;
+  const int w = D.precision == OSCAR_MIXED ? 4 : 8;
+  mg.tail = mg.L;
+  for (int l = 1; l < mg.L; ++l)
+    if (mg.lv[l].nc <= MG_TAIL_CELLS && mg_tail_bytes(mg, l, D.dim, w) <= MG_TAIL_LDS) {
+      mg.tail = l;
+      break;
+    }
+  mg.tail_bytes = (int32_t)mg_tail_bytes(mg, mg.tail, D.dim, w);
 }
 
 // Lay out one slot's arrays (and, with `ctl_block`, its table entries).
@@ -103,14 +109,30 @@ void layout(const oscar_desc &D, Carver &cv, Slot *s, bool ctl_block) {
   memset(&s->mg, 0, sizeof s->mg);
   if (D.precond == OSCAR_PC_MG) {
     mg_levels(D, s->mg);
-    for (int l = 1; l <= s->mg.L; ++l) {
-      MGLevel &v = s->mg.lv[l];
+    MGInfo &mg = s->mg;
+    for (int l = 1; l < mg.tail; ++l) {
+      MGLevel &v = mg.lv[l];
       for (int e = 0; e < d; ++e) v.cf[e] = cv.take(w * v.nc);
       void **arr[] = {&v.cout, &v.invD, &v.b, &v.x, &v.t};
       for (void **p : arr) *p = cv.take(w * v.nc);
     }
-    const uint64_t ncl = (uint64_t)s->mg.lv[s->mg.L].nc;
-    s->mg.Ainv = cv.take(w * ncl * ncl);
+    // the tail block, packed: it is copied into LDS as a whole
+    char *tb = (char *)cv.take((uint64_t)mg.tail_bytes);
+    uint64_t at = 0;
+    auto part = [&](uint64_t n) -> void * {
+      void *p = tb ? tb + at : nullptr;
+      at += w * n;
+      return p;
+    };
+    mg.tail_base = tb;
+    const uint64_t ncl = (uint64_t)mg.lv[mg.L].nc;
+    mg.Ainv = part(ncl * ncl);
+    for (int l = mg.tail; l <= mg.L; ++l) {
+      MGLevel &v = mg.lv[l];
+      for (int e = 0; e < d; ++e) v.cf[e] = part(v.nc);
+      void **arr[] = {&v.cout, &v.invD, &v.b, &v.x, &v.t};
+      for (void **p : arr) *p = part(v.nc);
+    }
   }
   s->part = (double *)cv.take(8ull * NCH * NVAL * g.nblocks);
   s->st = (SlotState *)cv.take(sizeof(SlotState));
@@ -246,21 +268,25 @@ struct oscar_ctx {
   int last_pcg = 0, pcg_call = 0, refine_call = 0, maxit_hits = 0;
   // Predicted CG iterations of the next solve of each kind: [viscous step,
   // capillary sub-step, stand-alone solve][corrector][first / later inner
-  // solve of the mixed refinement].  The first chunk enqueues PRED_MARGIN
-  // iterations more than that, later chunks PRED_STEP more.  Iterations
-  // enqueued past convergence cost their early-exit launches (about a
-  // microsecond each); one chunk too few costs a host round trip with the
-  // GPU idle, which is far more (measured: margin 2 takes a mixed step of
-  // the 128 x 64 x 64 channel from 73 to 61 ms).
-  static constexpr int PRED_MARGIN = 2;
-  static constexpr int PRED_STEP = 4;
+  // solve of the mixed refinement].  A chunk of work ends with the
+  // search-direction launch that holds a convergence test; the first chunk
+  // of a solve runs the predicted iterations plus PRED_MARGIN and ends with
+  // the test of the next one, so an exact prediction launches nothing past
+  // convergence; later chunks add PRED_STEP iterations.  A launch past
+  // convergence costs its early exit (about 2.4 us); one chunk too few costs
+  // a host round trip (about 13 us) and the relaunch latency.
+  static constexpr int PRED_MARGIN = 0;
+  static constexpr int PRED_STEP = 2;
   int pred[3][64][2];
   bool refine_stall = false;  // an outer refinement stopped short of its tolerance
+  bool mg_stale = true;       // the multigrid hierarchy predates the current 1/a_P
+  int total_seen = 0;   // device total_it at the last state read (0 after a state reset)
   // optional timing of sampled conjugate-gradient iterations: every
-  // t_period-th iteration of a solve gives each part a stamp pair (earliest
-  // block start as a complement, latest block end) in a small device buffer
+  // t_period-th iteration of a solve gives each of its launches a region of
+  // per-workgroup wall-clock stamps in a small device buffer
   static constexpr int NT = 5;   // whole iteration, search direction, fine down, coarse levels, fine up
-  static constexpr int TS_CAP = 32;    // sampled iterations per chunk (chunks are cut to TS_CAP periods)
+  static constexpr int TS_CAP = 64;       // stamp slots (each ts_reg regions of TS_WORDS words)
+  static constexpr int TS_BATCH = TS_CAP / 4;   // samples per span reduction; also per chunk of iterations
   int ts_reg = 0;                       // stamp regions per sample: the launches of one iteration
   bool timing = false;
   int t_period = 1;
@@ -268,11 +294,16 @@ struct oscar_ctx {
   unsigned long long *d_span = nullptr; // TS_CAP x ts_reg spans (device)
   unsigned long long *h_span = nullptr; // pinned copy of the spans
   double wall_hz = 0.0;                 // wall-clock rate
+  enum { S_OPEN, S_RUN, S_DONE, S_COPIED };
   struct Sample {
-    int it;     // iteration index within the current solve
-    int slot;   // index into the stamp buffer
+    int g;        // the iteration's index among the call's iterations (device total_it when it ran)
+    int slot;     // stamp slot
+    int stage;    // S_OPEN: search direction enqueued, rest of the iteration not yet; S_RUN: all
+                  // enqueued; S_DONE: ran and did work; S_COPIED: span copy enqueued
+    bool split;   // a host read fell between its search direction and the rest
   };
-  std::vector<Sample> samples;   // pending (enqueued, not yet folded)
+  std::vector<Sample> samples;   // not yet folded
+  std::vector<int> ts_free;      // free stamp slots
   double t_ms[NT] = {0.0, 0.0, 0.0, 0.0, 0.0};
   int64_t t_cnt[NT] = {0, 0, 0, 0, 0};
   Launch L() const {
@@ -312,21 +343,44 @@ static int set_ctl(oscar_ctx *c, const SlotCtl &ctl) {
   return OSCAR_OK;
 }
 
-// Fold the pending samples into the totals (from the spans of their stamp
-// regions).  Iterations enqueued past the device-side convergence test exit
-// at once and are left out: the device state's `it` counts the iterations
-// the current solve completed.
-static int harvest_timing(oscar_ctx *c) {
-  const int done_its = c->h_state->it;
+// Timing samples after a synchronisation of the stream: spans whose copy
+// was enqueued earlier are folded into the totals; the other samples have
+// run, and count when their iteration did work (g below the device's
+// iteration count: launches enqueued past the convergence test exit at
+// once).  Once TS_BATCH samples (or, with `flush`, any) await their spans,
+// the spans of every stamp region are reduced and copied to the host in one
+// launch and one copy, stream-ordered, to be folded after the next
+// synchronisation.
+static int settle_samples(oscar_ctx *c, bool flush) {
   const bool mg = c->D.precond == OSCAR_PC_MG;
   const int ncoarse = mg ? mg_part_launches(c->s, 1) : 0;
   // parts as ranges of stamp regions: search direction, fine down, coarse levels, fine up
   const int p0[4] = {0, 1, 2, 2 + ncoarse}, p1[4] = {1, 2, 2 + ncoarse, 3 + ncoarse};
   const int parts = mg ? 4 : 1;
-  for (const oscar_ctx::Sample &x : c->samples) {
-    if (x.it >= done_its) continue;
+  const int total = c->h_state->total_it;
+  std::vector<oscar_ctx::Sample> keep;
+  int waiting = 0;
+  for (oscar_ctx::Sample x : c->samples) {
+    if (x.stage == oscar_ctx::S_OPEN) {   // the rest of its iteration is still to be enqueued
+      keep.push_back(x);
+      continue;
+    }
+    if (x.stage == oscar_ctx::S_RUN) {
+      if (x.g >= total) {   // its launches exited without work
+        c->ts_free.push_back(x.slot);
+        continue;
+      }
+      x.stage = oscar_ctx::S_DONE;
+    }
+    if (x.stage == oscar_ctx::S_DONE) {
+      ++waiting;
+      keep.push_back(x);
+      continue;
+    }
+    c->ts_free.push_back(x.slot);
     const unsigned long long *t = c->h_span + 2 * (size_t)c->ts_reg * x.slot;
-    unsigned long long first = ~0ull, last = 0ull;
+    // first and last stamp of the search direction (part 0) and of the rest
+    unsigned long long first[2] = {~0ull, ~0ull}, last[2] = {0ull, 0ull};
     for (int k = 0; k < parts; ++k) {
       unsigned long long lo = ~0ull, hi = 0ull;
       for (int r = p0[k]; r < p1[k]; ++r) {
@@ -336,76 +390,122 @@ static int harvest_timing(oscar_ctx *c) {
       if (hi <= lo) continue;   // a part that stamped nothing
       c->t_ms[1 + k] += 1e3 * (double)(hi - lo) / c->wall_hz;
       c->t_cnt[1 + k] += 1;
-      first = lo < first ? lo : first;
-      last = hi > last ? hi : last;
+      const int h = k > 0;
+      first[h] = lo < first[h] ? lo : first[h];
+      last[h] = hi > last[h] ? hi : last[h];
     }
-    if (last > first) {
-      c->t_ms[0] += 1e3 * (double)(last - first) / c->wall_hz;
+    // whole iteration: first to last stamp; when a host read fell between
+    // the search direction and the rest, the two spans without the gap
+    const unsigned long long f0 = first[0] < first[1] ? first[0] : first[1];
+    const unsigned long long l0 = last[0] > last[1] ? last[0] : last[1];
+    double whole = l0 > f0 ? (double)(l0 - f0) : 0.0;
+    if (x.split && last[0] > first[0] && last[1] > first[1])
+      whole = (double)(last[0] - first[0]) + (double)(last[1] - first[1]);
+    if (whole > 0.0) {
+      c->t_ms[0] += 1e3 * whole / c->wall_hz;
       c->t_cnt[0] += 1;
     }
   }
-  c->samples.clear();
+  c->samples.swap(keep);
+  if (waiting == 0 || (waiting < oscar_ctx::TS_BATCH && !flush)) return OSCAR_OK;
+  const int nreg = oscar_ctx::TS_CAP * c->ts_reg;
+  launch_ts_span(c->d_ts, nreg, c->d_span, c->stream);
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipMemcpyAsync(c->h_span, c->d_span, sizeof(unsigned long long) * 2 * nreg, hipMemcpyDeviceToHost,
+                           c->stream));
+  for (oscar_ctx::Sample &x : c->samples)
+    if (x.stage == oscar_ctx::S_DONE) x.stage = oscar_ctx::S_COPIED;
   return OSCAR_OK;
 }
 
+// an inner solve ended: search-direction launches whose iteration was never
+// completed (they found convergence) leave their samples
+static void drop_open_samples(oscar_ctx *c) {
+  std::vector<oscar_ctx::Sample> keep;
+  for (const oscar_ctx::Sample &x : c->samples)
+    if (x.stage == oscar_ctx::S_OPEN) c->ts_free.push_back(x.slot);
+    else keep.push_back(x);
+  c->samples.swap(keep);
+}
+
+// synchronisation: the device state into h_state
 static int read_state(oscar_ctx *c) {
   HIPCHK(c, hipMemcpyAsync(c->h_state, c->s.st, sizeof(SlotState), hipMemcpyDeviceToHost, c->stream));
-  const bool fold = c->timing && !c->samples.empty();
-  if (fold) {
-    const int nreg = (int)c->samples.size() * c->ts_reg;
-    launch_ts_span(c->d_ts, nreg, c->d_span, c->stream);
-    HIPCHK(c, hipGetLastError());
-    HIPCHK(c, hipMemcpyAsync(c->h_span, c->d_span, sizeof(unsigned long long) * 2 * nreg, hipMemcpyDeviceToHost,
-                             c->stream));
-  }
   HIPCHK(c, hipStreamSynchronize(c->stream));
-  if (fold) return harvest_timing(c);
+  c->total_seen = c->h_state->total_it;
+  return c->samples.empty() ? OSCAR_OK : settle_samples(c, false);
+}
+
+// every pending sample folded into the totals
+static int drain_samples(oscar_ctx *c) {
+  for (int round = 0; round < 3 && !c->samples.empty(); ++round) {
+    int rc = read_state(c);
+    if (!rc && !c->samples.empty()) rc = settle_samples(c, true);
+    if (rc) return rc;
+  }
   return OSCAR_OK;
 }
 
-// one conjugate-gradient iteration; `ts` (or null): its stamp regions
-// (multigrid: search direction, fine down, the coarse launches, fine up)
-template <typename R>
-static void launch_iteration(oscar_ctx *c, const Launch &L, int it, unsigned long long *ts) {
-  auto region = [&](int r) -> unsigned long long * { return ts ? ts + (size_t)TS_WORDS * r : nullptr; };
-  if (c->D.precond == OSCAR_PC_MG) {
-    const int ncoarse = mg_part_launches(c->s, 1);
-    launch_mg_dir<R>(c->s, L, it, region(0));
-    launch_mg_cycle_part<R>(c->s, L, it, 0, region(1));
-    launch_mg_cycle_part<R>(c->s, L, it, 1, region(2));
-    launch_mg_cycle_part<R>(c->s, L, it, 2, region(2 + ncoarse));
-  } else {
-    launch_cg_iters<R>(L, it, 1, region(0));
-  }
+// a state reset (iteration counts to zero) is enqueued: samples still
+// pending belong to the previous count and are dropped
+static void state_reset(oscar_ctx *c, const Launch &L) {
+  launch_state_reset(L, 1);
+  c->total_seen = 0;
+  for (const oscar_ctx::Sample &x : c->samples) c->ts_free.push_back(x.slot);
+  c->samples.clear();
 }
 
-// conjugate-gradient iterations it0 .. it0+n-1 (with timing on, every
-// t_period-th iteration is sampled; the stamp words of the chunk's samples
-// are zeroed first)
+// Position in the launch sequence of an inner solve after its initial
+// cycle: iteration it is its search-direction launch D(it), which holds the
+// convergence test, and with multigrid the rest of the iteration T(it): fine
+// down, the coarse levels, fine up.  Chunks end right after a D launch.
+struct CgPos {
+  int base = 0;        // iterations of the call before this inner solve
+  int next = 0;        // iteration of the next D launch
+  bool tail = false;   // T(next - 1) is due
+  int tail_slot = -1;  // its stamp slot (-1: not sampled)
+};
+
+// n more D launches, each preceded by the due T launch (with timing on,
+// every t_period-th iteration gets a free stamp slot, zeroed first)
 template <typename R>
-static int enqueue_cg(oscar_ctx *c, int it0, int n) {
+static int enqueue_chunk(oscar_ctx *c, CgPos &q, int n) {
   Launch L = c->L();
-  if (c->timing && !c->samples.empty()) {   // fold a previous chunk first (the stamp buffer is reused)
-    int rc = read_state(c);
-    if (rc) return rc;
-  }
-  int ns = 0;
-  if (c->timing) {
-    for (int x = 0; x < n; ++x)
-      if ((it0 + x) % c->t_period == 0 && ns < oscar_ctx::TS_CAP) ++ns;
-    if (ns)
-      HIPCHK(c, hipMemsetAsync(c->d_ts, 0, sizeof(unsigned long long) * TS_WORDS * c->ts_reg * ns, c->stream));
-  }
-  int used = 0;
+  const bool mg = c->D.precond == OSCAR_PC_MG;
+  const size_t slot_words = (size_t)TS_WORDS * c->ts_reg;
+  const int ncoarse = mg ? mg_part_launches(c->s, 1) : 0;
+  auto region = [&](int slot, int r) -> unsigned long long * {
+    return slot < 0 ? nullptr : c->d_ts + slot_words * slot + (size_t)TS_WORDS * r;
+  };
   for (int x = 0; x < n; ++x) {
-    const int it = it0 + x;
-    unsigned long long *ts = nullptr;
-    if (c->timing && it % c->t_period == 0 && used < ns) {
-      ts = c->d_ts + (size_t)TS_WORDS * c->ts_reg * used;
-      c->samples.push_back({it, used});
-      ++used;
+    if (q.tail) {
+      const int it = q.next - 1;
+      if (q.tail_slot >= 0)
+        for (oscar_ctx::Sample &smp : c->samples)
+          if (smp.slot == q.tail_slot && smp.stage == oscar_ctx::S_OPEN) {
+            smp.stage = oscar_ctx::S_RUN;
+            smp.split = x == 0;   // its D launch ended the previous chunk
+          }
+      launch_mg_cycle_part<R>(c->s, L, it, 0, region(q.tail_slot, 1));
+      launch_mg_cycle_part<R>(c->s, L, it, 1, region(q.tail_slot, 2));
+      launch_mg_cycle_part<R>(c->s, L, it, 2, region(q.tail_slot, 2 + ncoarse));
+      q.tail = false;
     }
-    launch_iteration<R>(c, L, it, ts);
+    const int it = q.next++;
+    int slot = -1;
+    if (c->timing && it % c->t_period == 0 && !c->ts_free.empty()) {
+      slot = c->ts_free.back();
+      c->ts_free.pop_back();
+      HIPCHK(c, hipMemsetAsync(c->d_ts + slot_words * slot, 0, sizeof(unsigned long long) * slot_words, c->stream));
+      c->samples.push_back({q.base + it, slot, mg ? oscar_ctx::S_OPEN : oscar_ctx::S_RUN, false});
+    }
+    if (mg) {
+      launch_mg_dir<R>(c->s, L, it, region(slot, 0));
+      q.tail = true;
+      q.tail_slot = slot;
+    } else {
+      launch_cg_iters<R>(L, it, 1, region(slot, 0));
+    }
   }
   HIPCHK(c, hipGetLastError());
   return OSCAR_OK;
@@ -496,6 +596,21 @@ extern "C" int32_t oscar_create(const oscar_desc *desc, void *ws, uint64_t bytes
   for (int64_t P = 0; P < nc; ++P)
     if (!desc->mask[P] && !std::isfinite(desc->alpha0[P])) { g_err = "alpha0 has a non-finite value"; return OSCAR_E_ARG; }
 
+  if (desc->precond == OSCAR_PC_MG) {   // the multigrid tail runs out of LDS
+    MGInfo mg;
+    mg_levels(*desc, mg);
+    int dev = 0, lds = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    if (e != hipSuccess) return hip_fail(nullptr, e, "hipDeviceGetAttribute");
+    if (lds < mg.tail_bytes) {
+      char buf[160];
+      snprintf(buf, sizeof buf, "the multigrid tail needs %d bytes of LDS per workgroup; the device has %d",
+               (int)mg.tail_bytes, lds);
+      g_err = buf;
+      return OSCAR_E_ARG;
+    }
+  }
   oscar_ctx *c = new oscar_ctx();
   for (auto &kind : c->pred)
     for (auto &corr : kind) corr[0] = corr[1] = 16;
@@ -603,69 +718,73 @@ extern "C" const char *oscar_last_error(const oscar_ctx *c) { return c ? c->err.
 // Solve the assembled pressure equation of the current corrector on the
 // device: chunks of CG iterations until the slot's done flag is set; in mixed
 // precision, FP32 inner solves wrapped in FP64 refinement.
+//
+// The host reads the device state once per chunk.  The first chunk of an
+// inner solve is the iteration count of the same equation (kind, corrector,
+// first or later inner solve) at the previous call plus a margin, so most
+// solves need a single read; in mixed precision the refinement step is
+// enqueued behind every chunk and acts only if the chunk finished the inner
+// solve, so one read also decides the outer step.
 template <typename R>
 static int solve_pressure(oscar_ctx *c, int &iters, int kind, int corr) {
-  int rc = read_state(c);
-  if (rc) return rc;
   c->refine_stall = false;
-  int start_total = c->h_state->total_it;
+  const int start_total = c->total_seen;   // no iterations ran since the last state read
   const int max_it = c->D.pcg_max_it;
-  // one CG solve: w_0 = A D^-1 r_0 (Jacobi) or the V-cycle of r_0 (MG),
-  // then chunks of iterations from index 0 until the device flags it done
   const bool mg = c->D.precond == OSCAR_PC_MG;
-  if (mg) {   // coarse operators of this equation's coefficients
+  const bool mixed = c->mixed();
+  if (mg && c->mg_stale) {   // coarse operators of the coefficients (1/a_P of the current assembly)
     launch_mg_setup<R>(c->s, c->stream);
     HIPCHK(c, hipGetLastError());
+    c->mg_stale = false;
   }
-  auto inner = [&](int &pred) -> int {
+  int (&pr)[2] = c->pred[kind][corr < 63 ? corr : 63];
+  int outer = 0;   // refinement steps taken
+  for (;;) {
+    // one inner solve: w_0 = A D^-1 r_0 (Jacobi) or the V-cycle of r_0 (MG),
+    // then chunks of iterations from index 0 until the device flags it done
+    CgPos q;
+    q.base = c->total_seen;
+    const int base = q.base;
     if (mg)   // z_0 = B r_0
       for (int part = 0; part < 3; ++part) launch_mg_cycle_part<R>(c->s, c->L(), -1, part);
     else launch_cg_init<R>(c->L());
     HIPCHK(c, hipGetLastError());
-    int it0 = 0;
-    int chunk = pred + oscar_ctx::PRED_MARGIN;
-    while (!c->h_state->done) {
-      if (it0 > max_it + 1) { c->err = "conjugate gradient did not terminate"; return OSCAR_E_HIP; }
-      // with timing on, a chunk holds at most TS_CAP samples
-      const int n = c->timing && chunk > oscar_ctx::TS_CAP * c->t_period ? oscar_ctx::TS_CAP * c->t_period : chunk;
-      int r = enqueue_cg<R>(c, it0, n);
+    int &pred = pr[outer > 0 ? 1 : 0];
+    // the predicted iterations, and the convergence test after them
+    int chunk = pred + 1 + oscar_ctx::PRED_MARGIN;
+    for (;;) {
+      if (q.next > max_it + 1) { c->err = "conjugate gradient did not terminate"; return OSCAR_E_HIP; }
+      // with timing on, a chunk holds at most TS_BATCH samples
+      const int cap = oscar_ctx::TS_BATCH * c->t_period;
+      const int n = c->timing && chunk > cap ? cap : chunk;
+      int r = enqueue_chunk<R>(c, q, n);
       if (r) return r;
-      it0 += n;
+      if (mixed) {
+        launch_refine<R>(c->L());
+        HIPCHK(c, hipGetLastError());
+      }
       r = read_state(c);
       if (r) return r;
+      // finished: done (FP64), or the refinement ran (it back to 0) or had
+      // nothing to refine (mixed)
+      if (mixed ? c->h_state->it == 0 : c->h_state->done != 0) break;
       chunk = oscar_ctx::PRED_STEP;
     }
-    int used = c->h_state->it;
-    pred = used > 1 ? used : 1;
-    return OSCAR_OK;
-  };
-  int (&pr)[2] = c->pred[kind][corr < 63 ? corr : 63];
-  if (!c->mixed()) {
-    rc = inner(pr[0]);
-    if (rc) return rc;
-  } else {
-    int outer = 0;
-    double last = c->h_state->rn64;
-    while (!c->h_state->done) {
-      rc = inner(pr[outer > 0 ? 1 : 0]);
-      if (rc) return rc;
-      launch_refine<R>(c->L());
-      HIPCHK(c, hipGetLastError());
-      rc = read_state(c);
-      if (rc) return rc;
-      ++outer;
-      // stop when an outer step no longer halves the FP64 residual: the
-      // requested tolerance is below what the FP32 inner solve can deliver
-      double now = c->h_state->rn64;
-      if (!c->h_state->done && (!(now < 0.5 * last) || outer >= 60)) {
-        c->refine_stall = true;
-        break;
-      }
-      last = now;
+    if (!c->samples.empty()) drop_open_samples(c);
+    const int used = c->h_state->total_it - base;
+    if (used > 0) pred = used;
+    if (!mixed || used == 0) break;   // FP64, or the equation was solved before any iteration
+    ++outer;
+    if (c->h_state->done) break;      // the refinement met the tolerance
+    // stop when an outer step no longer halves the FP64 residual: the
+    // requested tolerance is below what the FP32 inner solve can deliver
+    if (!(c->h_state->rn64 < 0.5 * c->h_state->rn64_prev) || outer >= 60) {
+      c->refine_stall = true;
+      break;
     }
-    c->refine_call += outer;
   }
-  iters = c->h_state->total_it - start_total;
+  c->refine_call += outer;
+  iters = c->total_seen - start_total;
   return OSCAR_OK;
 }
 
@@ -721,13 +840,14 @@ static int viscous_step_t(oscar_ctx *c, double dt) {
   Launch L = c->L();
   int rc = set_ctl(c, make_ctl(c, 0, dt, 1));
   if (rc) return rc;
-  launch_state_reset(L, 1);
+  state_reset(c, L);
   c->pcg_call = 0;
   c->refine_call = 0;
   launch_copy_phi_prev<R>(L);
   launch_normals<R>(L, false);
   launch_advect<R>(L);
   launch_assemble<R>(L);
+  c->mg_stale = true;
   HIPCHK(c, hipGetLastError());
   double E = 0.0;
   int warn = OSCAR_OK;
@@ -742,7 +862,7 @@ static int relax_t(oscar_ctx *c, double dt_vd, int n_sub, int max_iters, double 
   double dt = dt_vd / (double)n_sub;
   int rc = set_ctl(c, make_ctl(c, 1, dt, n_sub));
   if (rc) return rc;
-  launch_state_reset(L, 1);
+  state_reset(c, L);
   launch_zero_usum<R>(L);
   HIPCHK(c, hipGetLastError());
   c->pcg_call = 0;
@@ -755,6 +875,7 @@ static int relax_t(oscar_ctx *c, double dt_vd, int n_sub, int max_iters, double 
     launch_advect<R>(L);
     launch_normals<R>(L, true);
     launch_assemble<R>(L);
+    c->mg_stale = true;
     HIPCHK(c, hipGetLastError());
     double E = 0.0;
     rc = run_correctors<R>(c, true, E, warn);
@@ -813,7 +934,7 @@ static int pressure_solve_t(oscar_ctx *c, int which, double dt, double rtol, int
   k.max_it = max_it;
   int rc = set_ctl(c, k);
   if (rc) return rc;
-  launch_state_reset(L, 1);
+  state_reset(c, L);
   // alpha_old = alpha (no transport), then curvature, momentum, predictor, solve
   int saved_max = c->D.pcg_max_it;
   c->D.pcg_max_it = max_it;
@@ -822,6 +943,7 @@ static int pressure_solve_t(oscar_ctx *c, int which, double dt, double rtol, int
   if (e != hipSuccess) return hip_fail(c, e, "copy alpha");
   if (which) launch_normals<R>(L, true);
   launch_assemble<R>(L);
+  c->mg_stale = true;
   launch_predictor<R>(L);
   launch_pressure_setup<R>(L, false);
   HIPCHK(c, hipGetLastError());
@@ -925,6 +1047,7 @@ extern "C" int32_t oscar_set_field(oscar_ctx *c, int32_t id, const double *src) 
   bool dbl;
   void *dst = field_ptr(c, id, len, dbl);
   if (!dst || !src) { c->err = "unknown field or NULL source"; return OSCAR_E_ARG; }
+  c->mg_stale = true;
   for (int64_t x = 0; x < len; ++x)
     if (!std::isfinite(src[x])) { c->err = "non-finite value in the field"; return OSCAR_E_NONFINITE; }
   if (dbl || !c->mixed()) {
@@ -961,10 +1084,8 @@ extern "C" int32_t oscar_stats(oscar_ctx *c, oscar_stats_t *o) {
 
 extern "C" int32_t oscar_timing(oscar_ctx *c, int32_t period) {
   if (!c || period < 0) return OSCAR_E_ARG;
-  if (c->timing && !c->samples.empty()) {
-    int rc = read_state(c);
-    if (rc) return rc;
-  }
+  int rc = drain_samples(c);
+  if (rc) return rc;
   if (period && c->btab_len > TS_WORDS / 2) {
     c->err = "timing supports at most 1040 workgroups per launch";
     return OSCAR_E_ARG;
@@ -983,6 +1104,7 @@ extern "C" int32_t oscar_timing(oscar_ctx *c, int32_t period) {
     HIPCHK(c, hipMalloc((void **)&c->d_ts, sizeof(unsigned long long) * TS_WORDS * regions));
     HIPCHK(c, hipMalloc((void **)&c->d_span, sizeof(unsigned long long) * 2 * regions));
     HIPCHK(c, hipHostMalloc((void **)&c->h_span, sizeof(unsigned long long) * 2 * regions, hipHostMallocDefault));
+    for (int k = oscar_ctx::TS_CAP - 1; k >= 0; --k) c->ts_free.push_back(k);
   }
   c->timing = period != 0;
   if (c->timing) {
@@ -997,10 +1119,8 @@ extern "C" int32_t oscar_timing(oscar_ctx *c, int32_t period) {
 
 extern "C" int32_t oscar_timing_read(oscar_ctx *c, int32_t kernel, double *total_ms, int64_t *launches) {
   if (!c || kernel < 0 || kernel >= oscar_ctx::NT) return OSCAR_E_ARG;
-  if (!c->samples.empty()) {
-    int rc = read_state(c);
-    if (rc) return rc;
-  }
+  int rc = drain_samples(c);
+  if (rc) return rc;
   if (total_ms) *total_ms = c->t_ms[kernel];
   if (launches) *launches = c->t_cnt[kernel];
   return OSCAR_OK;

@@ -308,28 +308,14 @@ __device__ __forceinline__ bool on_edge(const Grid &G, const Cell &c, int f) {
   return (f & 1) ? c.k == G.nz - 1 : c.k == 0;
 }
 
-// (M x)_P in precision X, with x read through a functor xv(index).  All six
-// faces are unrolled and every neighbour value is read unconditionally, at
-// the cell itself where the face is not interior (faces 4 and 5 in 2D), so
-// the loads issue together; the sum is taken face by face in the order
+// (M x)_P in precision X from preloaded operands: x and rAU at the cell
+// (xP, rP) and across each face f (xn[f], rn[f]; any value where face f is
+// not interior: it is not used).  The sum is taken face by face in the order
 // x-, x+, y-, y+, z-, z+, adding only interior and outlet terms, which is
 // the operation order of the sequential reference.
-// Same, with x read through xf(index, f): f = -1 for the cell itself, else
-// the face across which the (interior) neighbour lies.
-template <typename X, typename R, class XF>
-__device__ __forceinline__ X matvec_row_f(const Grid &G, const R *rAU, const Cell &c, uint8_t fl, XF &&xf) {
-  const int P = c.P;
-  const int st[6] = {-1, 1, -G.nx, G.nx, -G.nxy, G.nxy};
-  const X xP = xf(P, -1);
-  const X rP = (X)rAU[P];
-  X xn[6], rn[6];
-#pragma unroll
-  for (int f = 0; f < 6; ++f) {
-    const bool in = (fl >> f) & 1u;
-    const int n = in ? P + st[f] : P;
-    xn[f] = xf(n, in ? f : -1);
-    rn[f] = (X)rAU[n];
-  }
+template <typename X>
+__device__ __forceinline__ X matvec_pre(const Grid &G, const Cell &c, uint8_t fl, X xP, X rP, const X (&xn)[6],
+                                        const X (&rn)[6]) {
   X acc = (X)0;
 #pragma unroll
   for (int f = 0; f < 6; ++f) {
@@ -337,6 +323,60 @@ __device__ __forceinline__ X matvec_row_f(const Grid &G, const R *rAU, const Cel
     else if (((G.outlet >> f) & 1u) && on_edge(G, c, f)) acc = acc + (rP * (X)G.S2h) * xP;
   }
   return acc;
+}
+
+// neighbour of cell P across face f where the face is interior (flag bit
+// f), else P itself: every index is a valid load address
+__device__ __forceinline__ int nb_at(const Grid &G, int P, uint8_t fl, int f) {
+  const int st = (f >> 1) == 0 ? 1 : ((f >> 1) == 1 ? G.nx : G.nxy);
+  return ((fl >> f) & 1u) ? ((f & 1) ? P + st : P - st) : P;
+}
+
+// (M x)_P in precision X, with x read through xf(index, f): f = -1 for the
+// cell itself, else the face across which the (interior) neighbour lies.
+// All six faces are unrolled and every neighbour value is read
+// unconditionally, at the cell itself where the face is not interior (faces
+// 4 and 5 in 2D), so the loads issue together.
+template <typename X, typename R, class XF>
+__device__ __forceinline__ X matvec_row_f(const Grid &G, const R *rAU, const Cell &c, uint8_t fl, XF &&xf) {
+  const int P = c.P;
+  const X xP = xf(P, -1);
+  const X rP = (X)rAU[P];
+  X xn[6], rn[6];
+#pragma unroll
+  for (int f = 0; f < 6; ++f) {
+    const int n = nb_at(G, P, fl, f);
+    xn[f] = xf(n, ((fl >> f) & 1u) ? f : -1);
+    rn[f] = (X)rAU[n];
+  }
+  return matvec_pre<X>(G, c, fl, xP, rP, xn, rn);
+}
+
+// Grid-stride loop over index range [first, end) in steps of `stride`, NB
+// indices per thread at a time: per batch, flag(o, g) for each index (it
+// reads what decides which operands a cell needs; g may lie past the end),
+// then data(o) for each (the operand loads, all in flight together), then,
+// on the first batch only, pre() (every thread of the block reaches it, so
+// it may hold a block reduction; its loads overlap the batch's; false ends
+// the loop), then use(o) in index order.
+template <int NB, class O, class F, class D, class Pre, class U>
+__device__ __forceinline__ void batched(int first, int stride, int end, F &&flag, D &&data, Pre &&pre, U &&use) {
+  O o[NB];
+  int g = first;
+  bool once = true;
+  do {
+#pragma unroll
+    for (int m = 0; m < NB; ++m) flag(o[m], g + m * stride);
+#pragma unroll
+    for (int m = 0; m < NB; ++m) data(o[m]);
+    if (once) {
+      if (!pre()) return;
+      once = false;
+    }
+#pragma unroll
+    for (int m = 0; m < NB; ++m) use(o[m]);
+    g += NB * stride;
+  } while (g < end);
 }
 
 template <typename X, typename R, class XV>

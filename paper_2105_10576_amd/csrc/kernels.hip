@@ -773,13 +773,22 @@ __global__ void __launch_bounds__(BLOCK) k_cg(const Slot *slots, const int2 *bta
   stamp.done();
 }
 
+// An outer refinement step acts only on a finished inner solve (done after at
+// least one iteration).  Enqueued behind a chunk of iterations that did not
+// reach the inner tolerance, it does nothing; after a refinement that met
+// the outer tolerance (done, it = 0), a further one does nothing either.
+__device__ __forceinline__ bool refine_due(const Slot &s, const SlotCtl &ctl) {
+  const SlotState *st = s.st;
+  return ctl.active && s.precision != 0 && !st->zero_rhs && st->done && st->it > 0;
+}
+
 // mixed precision, outer refinement: p += e, e = 0
 template <typename R>
 __global__ void __launch_bounds__(BLOCK) k_refine_x(const Slot *slots, const int2 *btab) {
   Block B = block_of(slots, btab);
   const Slot &s = *B.s;
   const SlotCtl &ctl = *B.ctl;
-  if (!ctl.active || s.precision == 0 || B.st->zero_rhs) return;
+  if (!refine_due(s, ctl)) return;
   double *p = ctl.mode ? s.p_cr : s.p_vd;
   R *e = (R *)s.e;
   for_cells(s, B.lb, [&](const Cell &c) {
@@ -798,7 +807,7 @@ __global__ void __launch_bounds__(BLOCK) k_refine_res(const Slot *slots, const i
   const Grid G = grid_of(s);
   const uint8_t *flags = s.flags;
   const SlotCtl &ctl = *B.ctl;
-  if (!ctl.active || s.precision == 0 || B.st->zero_rhs) return;
+  if (!refine_due(s, ctl)) return;
   const R *rAU = (const R *)s.rAU;
   const double *p = ctl.mode ? s.p_cr : s.p_vd;
   T *r = (T *)s.cr[0];
@@ -820,11 +829,12 @@ __global__ void __launch_bounds__(BLOCK) k_refine_fin(const Slot *slots) {
   const Slot &s = slots[blockIdx.x];
   if (!s.ctl) return;   // unused table entry
   const SlotCtl &ctl = *s.ctl;
-  if (!ctl.active || s.precision == 0 || s.st->zero_rhs) return;
+  if (!refine_due(s, ctl)) return;   // read by every thread before thread 0 writes below
   double v[2];
   get_totals<0u>(s, CH_REF, v);
   if (threadIdx.x == 0) {
     SlotState *st = s.st;
+    st->rn64_prev = st->rn64;
     st->rn64 = sqrt(v[0]);
     st->bn = sqrt(v[1]);
     st->rn = st->bn;

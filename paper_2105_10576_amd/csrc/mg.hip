@@ -407,47 +407,87 @@ __global__ void __launch_bounds__(BLOCK) k_mg_up(const Slot S, int l, unsigned l
   stamp.done();
 }
 
-// Levels tail..L in one workgroup: the down-sweep to the coarsest level
-// (whose right-hand side goes straight to LDS), the coarsest solve with the
-// dense inverse, the up-sweep back to the tail level.
+// Levels tail..L in one workgroup, out of LDS.  The tail block (the dense
+// inverse of the coarsest operator, then per level the face and outlet
+// coefficients, inverse diagonal, b, x and t) is copied into LDS with one
+// round of 16-byte loads, which brings in the coefficients and the tail
+// level's right-hand side; the down-sweep to the coarsest level, its solve
+// with the dense inverse and the up-sweep then touch LDS only, and the final
+// correction of the tail level goes back to global memory for the next finer
+// level's prolongation.
 template <int DIM, typename T>
 __global__ void __launch_bounds__(MG_TAIL_THREADS) k_mg_tail(const Slot S, unsigned long long *ts) {
   Stamp stamp(ts);
   const Slot &s = S;
   if (mg_idle(s)) return;
+  extern __shared__ uint4 mg_lds[];
   const int tl = s.mg.tail, L = s.mg.L;
   const int t0 = threadIdx.x, ns = MG_TAIL_THREADS;
-  const LV<T> C = lview<T>(s.mg.lv[L]);
-  if (C.nc > MG_DENSE_MAX) return;   // excluded by the host's hierarchy check
-  __shared__ T sb[MG_DENSE_MAX];
-  __shared__ T sx[MG_DENSE_MAX];
-  for (int l = tl; l < L; ++l) {
-    const MGLevel &N = s.mg.lv[l + 1];
-    smooth_restrict<DIM, T>(lview<T>(s.mg.lv[l]), N.nx, N.ny, N.nc, l + 1 == L ? sb : (T *)N.b, t0, ns);
-    __syncthreads();
-  }
-  // coarsest level: x = A^-1 b with the dense inverse (row t0, fixed order)
-  const int n = C.nc;
-  if (t0 < n) {
-    const T *Ai = (const T *)s.mg.Ainv + t0 * n;
-    const T *bL = L > tl ? sb : C.b;
-    T acc = (T)0;
-    for (int m = 0; m < n; ++m) acc = acc + Ai[m] * bL[m];
-    sx[t0] = acc;
+  const char *gbase = (const char *)s.mg.tail_base;
+  {
+    constexpr int U = 8;   // 16-byte loads in flight per thread
+    const uint4 *src = (const uint4 *)gbase;
+    const int n16 = s.mg.tail_bytes >> 4;
+    for (int x0 = t0; x0 < n16; x0 += U * ns) {
+      uint4 v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {   // past the end: reload the first entry (always in the block)
+        const int x = x0 + u * ns;
+        v[u] = src[x < n16 ? x : 0];
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (x0 + u * ns < n16) mg_lds[x0 + u * ns] = v[u];
+    }
   }
   __syncthreads();
-  if (L == tl) {   // no level of the tail above the coarsest: hand the result on in global memory
-    if (t0 < n) C.t[t0] = sx[t0];
-    stamp.done();
-    return;
-  }
-  const T *xL = sx;
-  for (int l = L - 1; l >= tl; --l) {
+  char *lbase = (char *)mg_lds;
+  // an array of the block at its LDS position
+  auto in_lds = [&](const void *g) -> T * { return (T *)(lbase + ((const char *)g - gbase)); };
+  auto lds_view = [&](int l) -> LV<T> {
+    const MGLevel &M = s.mg.lv[l];
+    LV<T> v;
+    v.nx = M.nx;
+    v.ny = M.ny;
+    v.nz = M.nz;
+    v.nxy = M.nxy;
+    v.nc = M.nc;
+#pragma unroll
+    for (int e = 0; e < 3; ++e) v.cf[e] = in_lds(M.cf[e < DIM ? e : 0]);
+    v.cout = in_lds(M.cout);
+    v.invD = in_lds(M.invD);
+    v.b = in_lds(M.b);
+    v.x = in_lds(M.x);
+    v.t = in_lds(M.t);
+    return v;
+  };
+  for (int l = tl; l < L; ++l) {
     const MGLevel &N = s.mg.lv[l + 1];
-    const LV<T> Lv = lview<T>(s.mg.lv[l]);
-    up_range<DIM, T>(Lv, N.nx, N.nxy, l == L - 1 ? xL : (const T *)N.t, Lv.t, t0, ns);
+    smooth_restrict<DIM, T>(lds_view(l), N.nx, N.ny, N.nc, in_lds(N.b), t0, ns);
     __syncthreads();
   }
+  // coarsest level: t = A^-1 b with the dense inverse (row t0, fixed order)
+  {
+    const LV<T> C = lds_view(L);
+    const int n = C.nc;
+    if (t0 < n) {
+      const T *Ai = in_lds(s.mg.Ainv) + t0 * n;
+      T acc = (T)0;
+      for (int m = 0; m < n; ++m) acc = acc + Ai[m] * C.b[m];
+      C.t[t0] = acc;
+    }
+  }
+  __syncthreads();
+  for (int l = L - 1; l >= tl; --l) {
+    const LV<T> Lv = lds_view(l);
+    const MGLevel &N = s.mg.lv[l + 1];
+    up_range<DIM, T>(Lv, N.nx, N.nxy, in_lds(N.t), Lv.t, t0, ns);
+    __syncthreads();
+  }
+  const MGLevel &M = s.mg.lv[tl];
+  const T *tsrc = in_lds(M.t);
+  T *tdst = (T *)M.t;
+  for (int g = t0; g < M.nc; g += ns) tdst[g] = tsrc[g];
   stamp.done();
 }
 
@@ -465,10 +505,22 @@ __device__ __forceinline__ bool fine_block(const Slot &s, const int2 *btab, int 
   return !done && t.y >= 0;
 }
 
+// cells per thread and batch in the fine-grid kernels: two in FP32; one in
+// FP64, whose operands of two cells would exceed the 128 registers that
+// keep four waves per SIMD resident
+template <typename R>
+constexpr int FINE_NB = sizeof(R) == 4 ? 2 : 1;
+
+// The three fine-grid kernels below take each thread's cells NB at a time:
+// the flags of the batch, then all stencil operands of its fluid cells, are
+// loaded before the reduction of the previous launch's partials is read, so
+// a wave waits for about two memory round trips rather than one per cell
+// plus one for the partials.
+
 // Search direction of iteration it: gamma_it = <r,z> and |r|^2 from the
 // previous cycle's reduction, convergence test (it > 0), beta, d = z + beta
 // d_old (d = z when it = 0), q = A d and <d,q>.
-template <typename R>
+template <typename R, int NB>
 __global__ void __launch_bounds__(BLOCK) k_mgcg_dir(const Slot S, const int2 *btab, int it,
                                                     unsigned long long *ts) {
   using T = R;
@@ -480,46 +532,87 @@ __global__ void __launch_bounds__(BLOCK) k_mgcg_dir(const Slot S, const int2 *bt
   const SlotCtl &ctl = *s.ctl;
   SlotState *st = s.st;
   const bool mixed = s.precision != 0;
-  double v[2];
-  get_totals<0u>(s, CH_CG0 + ((it + 1) & 1), v);   // written by the cycle of iteration it - 1
-  const double gam = v[0];
-  double beta = 0.0;
-  if (it > 0) {
-    double rn = sqrt(v[1]);
-    bool conv = rn <= (mixed ? st->tgt : ctl.rtol * st->bn);
-    bool cap = !conv && it >= ctl.max_it;
-    if (conv || cap) {
-      if (lb == 0 && threadIdx.x == 0) {
-        st->rn = rn;
-        st->it = it;
-        st->done = 1;
-        if (cap) st->maxit_hit = st->maxit_hit + 1;
-      }
-      return;
-    }
-    beta = gam / st->gam[(it - 1) & 1];
-    if (lb == 0 && threadIdx.x == 0) st->rn = rn;
-  }
-  if (lb == 0 && threadIdx.x == 0) st->gam[it & 1] = gam;
   // d = z + beta d_old; on the first iteration beta = 0 and d_old = z, so
   // d = z exactly and every load is unconditional
   const bool first = it == 0;
-  const T be = (T)beta;
   const R *rAU = (const R *)s.rAU;
   const uint8_t *flags = s.flags;
   const T *z = (const T *)s.cw[0], *dold = first ? z : (const T *)s.cs[(it + 1) & 1];
   T *dn = (T *)s.cs[it & 1], *q = (T *)s.cp;
+  struct Op {
+    Cell c;
+    uint8_t fl;
+    T z[7], o[7];   // z and d_old across faces 0..5, then at the cell
+    R ra[7];        // rAU likewise
+  };
+  bool stop = false;
+  T be = (T)0;
   double red[1] = {0.0};
-  for_cells(G, lb, [&](const Cell &c) {
-    uint8_t fl = flags[c.P];
-    if (fl & 0x40) return;
-    auto dv = [&](int x) -> T { return z[x] + be * dold[x]; };
-    T dP = dv(c.P);
-    T qq = matvec_row<T, R>(G, rAU, c, fl, dv);
-    dn[c.P] = dP;
-    q[c.P] = qq;
-    red[0] = red[0] + (double)(dP * qq);
-  });
+  batched<NB, Op>(
+      lb * BLOCK + (int)threadIdx.x, G.nblocks * BLOCK, G.nc,
+      [&](Op &o, int g) {
+        o.fl = 0x40;
+        if (g < G.nc) {
+          o.c = cell_at(G, g);
+          o.fl = flags[g];
+        }
+      },
+      [&](Op &o) {
+        if (o.fl & 0x40) return;
+        const int P = o.c.P;
+        o.z[6] = z[P];
+        o.o[6] = dold[P];
+        o.ra[6] = rAU[P];
+#pragma unroll
+        for (int f = 0; f < 6; ++f) {
+          const int n = nb_at(G, P, o.fl, f);
+          o.z[f] = z[n];
+          o.o[f] = dold[n];
+          o.ra[f] = rAU[n];
+        }
+      },
+      [&]() {
+        double v[2];
+        get_totals<0u>(s, CH_CG0 + ((it + 1) & 1), v);   // written by the cycle of iteration it - 1
+        const double gam = v[0];
+        double beta = 0.0;
+        if (it > 0) {
+          double rn = sqrt(v[1]);
+          bool conv = rn <= (mixed ? st->tgt : ctl.rtol * st->bn);
+          bool cap = !conv && it >= ctl.max_it;
+          if (conv || cap) {
+            if (lb == 0 && threadIdx.x == 0) {
+              st->rn = rn;
+              st->it = it;
+              st->done = 1;
+              if (cap) st->maxit_hit = st->maxit_hit + 1;
+            }
+            stop = true;
+            return false;
+          }
+          beta = gam / st->gam[(it - 1) & 1];
+          if (lb == 0 && threadIdx.x == 0) st->rn = rn;
+        }
+        if (lb == 0 && threadIdx.x == 0) st->gam[it & 1] = gam;
+        be = (T)beta;
+        return true;
+      },
+      [&](Op &o) {
+        if (o.fl & 0x40) return;
+        auto dv = [&](int m) -> T { return o.z[m] + be * o.o[m]; };
+        const T dP = dv(6);
+        T xn[6], rn[6];
+#pragma unroll
+        for (int f = 0; f < 6; ++f) {
+          xn[f] = dv(f);
+          rn[f] = (T)o.ra[f];
+        }
+        const T qq = matvec_pre<T>(G, o.c, o.fl, dP, (T)o.ra[6], xn, rn);
+        dn[o.c.P] = dP;
+        q[o.c.P] = qq;
+        red[0] = red[0] + (double)(dP * qq);
+      });
+  if (stop) return;   // uniform: every thread read the same totals
   put_partials<0u>(s, lb, CH_DQ, red);
   stamp.done();
 }
@@ -528,7 +621,7 @@ __global__ void __launch_bounds__(BLOCK) k_mgcg_dir(const Slot S, const int2 *bt
 // it = -1 (the cycle before the first iteration) r is the initial residual.
 // Then the cycle's fine pre-smoothing z0 = w D^-1 r and the restriction of
 // its residual r - A z0 into level 1, walking the fine grid in child order.
-template <typename R>
+template <typename R, int NB>
 __global__ void __launch_bounds__(BLOCK) k_mg_fine_down(const Slot S, const int2 *btab, int it,
                                                         unsigned long long *ts) {
   using T = R;
@@ -541,16 +634,6 @@ __global__ void __launch_bounds__(BLOCK) k_mg_fine_down(const Slot S, const int2
   SlotState *st = s.st;
   const bool mixed = s.precision != 0;
   const bool upd = it >= 0;
-  T al = (T)0;
-  if (upd) {
-    double v[1];
-    get_totals<0u>(s, CH_DQ, v);
-    al = (T)(st->gam[it & 1] / v[0]);
-    if (lb == 0 && threadIdx.x == 0) {
-      st->it = it + 1;
-      st->total_it = st->total_it + 1;
-    }
-  }
   const R *rAU = (const R *)s.rAU;
   const T *invD = (const T *)s.invD;
   // r_new = r - alpha q; for the initial cycle alpha = 0 and q = r, so
@@ -566,42 +649,103 @@ __global__ void __launch_bounds__(BLOCK) k_mg_fine_down(const Slot S, const int2
   const uint8_t *flags = s.flags;
   const T w = (T)MG_OMEGA;
   const int dim = G.dim;
-  const unsigned total = (unsigned)s.mg.lv[1].nc << dim;
-  for (unsigned tau = (unsigned)(lb * BLOCK) + threadIdx.x; tau < total; tau += (unsigned)(G.nblocks * BLOCK)) {
-    const Kid k = kid_at(tau, dim, G.nx, G.ny, G.nz, cnx, cny);
-    T tv = (T)0;
-    const uint8_t fl = k.valid ? flags[k.P] : (uint8_t)0x40;
-    if (!(fl & 0x40)) {
-      Cell c;
-      c.P = k.P;
-      c.i = k.i;
-      c.j = k.j;
-      c.k = k.k;
-      c.row = k.j + G.ny * k.k;
-      c.valid = true;
-      auto rv = [&](int x) -> T { return r0[x] - al * q[x]; };
-      auto zv = [&](int x) -> T { return w * (invD[x] * rv(x)); };
-      const int P = c.P;
-      T rn = rv(P);
-      T zz = zv(P);
-      T Az = matvec_row<T, R>(G, rAU, c, fl, zv);
-      if (upd) {
-        if (mixed) xe[P] = xe[P] + al * d[P];
-        else xp[P] = xp[P] + (double)al * (double)d[P];
-        r1[P] = rn;
-      }
-      z0[P] = zz;
-      tv = rn - Az;
-    }
-    tv = kid_sum(tv, dim);
-    if (k.lead) b1[k.parent] = tv;
-  }
+  const int total = (int)((unsigned)s.mg.lv[1].nc << dim);
+  struct Op {
+    Cell c;
+    int tau, parent;
+    bool lead;
+    uint8_t fl;
+    T r[7], q[7], iD[7];   // r, q, D^-1 across faces 0..5, then at the cell
+    R ra[7];               // rAU likewise
+    T d, xe;               // search direction and FP32 correction at the cell
+    double xp;             // FP64 pressure at the cell
+  };
+  T al = (T)0;
+  batched<NB, Op>(
+      lb * BLOCK + (int)threadIdx.x, G.nblocks * BLOCK, total,
+      [&](Op &o, int tau) {
+        o.tau = tau;
+        o.fl = 0x40;
+        o.lead = false;
+        if (tau < total) {
+          const Kid k = kid_at((unsigned)tau, dim, G.nx, G.ny, G.nz, cnx, cny);
+          o.parent = k.parent;
+          o.lead = k.lead;
+          if (k.valid) {
+            o.c.P = k.P;
+            o.c.i = k.i;
+            o.c.j = k.j;
+            o.c.k = k.k;
+            o.c.row = k.j + G.ny * k.k;
+            o.c.valid = true;
+            o.fl = flags[k.P];
+          }
+        }
+      },
+      [&](Op &o) {
+        if (o.fl & 0x40) return;
+        const int P = o.c.P;
+        o.r[6] = r0[P];
+        o.q[6] = q[P];
+        o.iD[6] = invD[P];
+        o.ra[6] = rAU[P];
+#pragma unroll
+        for (int f = 0; f < 6; ++f) {
+          const int n = nb_at(G, P, o.fl, f);
+          o.r[f] = r0[n];
+          o.q[f] = q[n];
+          o.iD[f] = invD[n];
+          o.ra[f] = rAU[n];
+        }
+        if (upd) {
+          o.d = d[P];
+          if (mixed) o.xe = xe[P];
+          else o.xp = xp[P];
+        }
+      },
+      [&]() {
+        if (!upd) return true;
+        double v[1];
+        get_totals<0u>(s, CH_DQ, v);
+        al = (T)(st->gam[it & 1] / v[0]);
+        if (lb == 0 && threadIdx.x == 0) {
+          st->it = it + 1;
+          st->total_it = st->total_it + 1;
+        }
+        return true;
+      },
+      [&](Op &o) {
+        T tv = (T)0;
+        if (!(o.fl & 0x40)) {
+          const int P = o.c.P;
+          auto rv = [&](int m) -> T { return o.r[m] - al * o.q[m]; };
+          auto zv = [&](int m) -> T { return w * (o.iD[m] * rv(m)); };
+          const T rn = rv(6);
+          const T zz = zv(6);
+          T xn[6], ran[6];
+#pragma unroll
+          for (int f = 0; f < 6; ++f) {
+            xn[f] = zv(f);
+            ran[f] = (T)o.ra[f];
+          }
+          const T Az = matvec_pre<T>(G, o.c, o.fl, zz, (T)o.ra[6], xn, ran);
+          if (upd) {
+            if (mixed) xe[P] = o.xe + al * o.d;
+            else xp[P] = o.xp + (double)al * (double)o.d;
+            r1[P] = rn;
+          }
+          z0[P] = zz;
+          tv = rn - Az;
+        }
+        tv = kid_sum(tv, dim);
+        if (o.lead) b1[o.parent] = tv;
+      });
   stamp.done();
 }
 
 // Last step of the cycle: z' = z0 + P x1, z = z' + w D^-1 (r - A z'); the
 // reduction <r,z>, |r|^2 for the next search direction.
-template <typename R>
+template <typename R, int NB>
 __global__ void __launch_bounds__(BLOCK) k_mg_fine_up(const Slot S, const int2 *btab, int it,
                                                       unsigned long long *ts) {
   using T = R;
@@ -619,27 +763,64 @@ __global__ void __launch_bounds__(BLOCK) k_mg_fine_up(const Slot S, const int2 *
   const int cnx = s.mg.lv[1].nx, cnxy = s.mg.lv[1].nxy;
   const T *xc = (const T *)s.mg.lv[1].t;
   const T w = (T)MG_OMEGA;
+  struct Op {
+    Cell c;
+    uint8_t fl;
+    T z0[7], xc[7];   // z0 and the parent's correction across faces 0..5, then at the cell
+    R ra[7];          // rAU likewise
+    T r, iD;
+  };
   double red[2] = {0.0, 0.0};
-  for_cells(G, lb, [&](const Cell &c) {
-    const int P = c.P;
-    uint8_t fl = flags[P];
-    if (fl & 0x40) return;
-    const int pP = (c.i >> 1) + cnx * (c.j >> 1) + cnxy * (c.k >> 1);
-    const int q[3] = {c.i, c.j, c.k};
-    const int cst[3] = {1, cnx, cnxy};
-    // z' at the cell (f = -1) or at its neighbour across face f
-    auto zp = [&](int n, int f) -> T {
-      const int pn = f < 0 ? pP : pP + parent_shift(q[f >> 1], (f & 1) ? 1 : -1, cst[f >> 1]);
-      return z0[n] + xc[pn];
-    };
-    const T zP = zp(P, -1);
-    const T Az = matvec_row_f<T, R>(G, rAU, c, fl, zp);
-    T rr = r[P];
-    T zn = zP + w * (invD[P] * (rr - Az));
-    z[P] = zn;
-    red[0] = red[0] + (double)(rr * zn);
-    red[1] = red[1] + (double)(rr * rr);
-  });
+  batched<NB, Op>(
+      lb * BLOCK + (int)threadIdx.x, G.nblocks * BLOCK, G.nc,
+      [&](Op &o, int g) {
+        o.fl = 0x40;
+        if (g < G.nc) {
+          o.c = cell_at(G, g);
+          o.fl = flags[g];
+        }
+      },
+      [&](Op &o) {
+        if (o.fl & 0x40) return;
+        const Cell &c = o.c;
+        const int P = c.P;
+        const int pP = (c.i >> 1) + cnx * (c.j >> 1) + cnxy * (c.k >> 1);
+        const int q[3] = {c.i, c.j, c.k};
+        const int cst[3] = {1, cnx, cnxy};
+        o.z0[6] = z0[P];
+        o.xc[6] = xc[pP];
+        o.ra[6] = rAU[P];
+        o.r = r[P];
+        o.iD = invD[P];
+#pragma unroll
+        for (int f = 0; f < 6; ++f) {
+          const bool in = (o.fl >> f) & 1u;
+          const int n = nb_at(G, P, o.fl, f);
+          // parent of the neighbour: it changes across the face iff the face is a parent's face
+          const int pn = in ? pP + parent_shift(q[f >> 1], (f & 1) ? 1 : -1, cst[f >> 1]) : pP;
+          o.z0[f] = z0[n];
+          o.xc[f] = xc[pn];
+          o.ra[f] = rAU[n];
+        }
+      },
+      [&]() { return true; },
+      [&](Op &o) {
+        if (o.fl & 0x40) return;
+        auto zp = [&](int m) -> T { return o.z0[m] + o.xc[m]; };
+        const T zP = zp(6);
+        T xn[6], rn[6];
+#pragma unroll
+        for (int f = 0; f < 6; ++f) {
+          xn[f] = zp(f);
+          rn[f] = (T)o.ra[f];
+        }
+        const T Az = matvec_pre<T>(G, o.c, o.fl, zP, (T)o.ra[6], xn, rn);
+        const T rr = o.r;
+        const T zn = zP + w * (o.iD * (rr - Az));
+        z[o.c.P] = zn;
+        red[0] = red[0] + (double)(rr * zn);
+        red[1] = red[1] + (double)(rr * rr);
+      });
   put_partials<0u>(s, lb, CH_CG0 + (it & 1), red);
   stamp.done();
 }
@@ -663,7 +844,7 @@ void launch_mg_setup(const Slot &hs, hipStream_t stream) {
 
 template <typename R>
 void launch_mg_dir(const Slot &hs, const Launch &L, int it, unsigned long long *ts) {
-  hipLaunchKernelGGL(k_mgcg_dir<R>, dim3((unsigned)L.nblocks), dim3(BLOCK), 0, L.stream, hs, L.btab, it, ts);
+  hipLaunchKernelGGL((k_mgcg_dir<R, FINE_NB<R>>), dim3((unsigned)L.nblocks), dim3(BLOCK), 0, L.stream, hs, L.btab, it, ts);
 }
 
 template <int DIM, typename R>
@@ -674,7 +855,8 @@ static void vcycle_levels(const Slot &hs, const Launch &L, unsigned long long *t
   for (int l = 1; l < tl; ++l)
     hipLaunchKernelGGL((k_mg_smooth<DIM, R>), dim3(lvl_grid(hs.mg.lv[l + 1].nc << DIM)), dim3(BLOCK), 0, L.stream, hs,
                        l, next());
-  hipLaunchKernelGGL((k_mg_tail<DIM, R>), dim3(1), dim3(MG_TAIL_THREADS), 0, L.stream, hs, next());
+  hipLaunchKernelGGL((k_mg_tail<DIM, R>), dim3(1), dim3(MG_TAIL_THREADS), (size_t)hs.mg.tail_bytes, L.stream, hs,
+                     next());
   for (int l = tl - 1; l >= 1; --l)
     hipLaunchKernelGGL((k_mg_up<DIM, R>), dim3(lvl_grid(hs.mg.lv[l].nc)), dim3(BLOCK), 0, L.stream, hs, l, next());
 }
@@ -684,12 +866,12 @@ template <typename R>
 void launch_mg_cycle_part(const Slot &hs, const Launch &L, int it, int part, unsigned long long *ts) {
   const dim3 fg((unsigned)L.nblocks), fb(BLOCK);
   if (part == 0) {
-    hipLaunchKernelGGL(k_mg_fine_down<R>, fg, fb, 0, L.stream, hs, L.btab, it, ts);
+    hipLaunchKernelGGL((k_mg_fine_down<R, FINE_NB<R>>), fg, fb, 0, L.stream, hs, L.btab, it, ts);
   } else if (part == 1) {
     if (hs.dim == 3) vcycle_levels<3, R>(hs, L, ts);
     else vcycle_levels<2, R>(hs, L, ts);
   } else {
-    hipLaunchKernelGGL(k_mg_fine_up<R>, fg, fb, 0, L.stream, hs, L.btab, it, ts);
+    hipLaunchKernelGGL((k_mg_fine_up<R, FINE_NB<R>>), fg, fb, 0, L.stream, hs, L.btab, it, ts);
   }
 }
 

@@ -32,7 +32,7 @@ struct SlotState {
   double bn, rn, gam[2], alp[2];           // conjugate gradient (iteration-parity buffers)
   double pbar, E;                          // normalised residual
   double comax, mass0, mass1, bflux;       // transport
-  double rn64, bn64;                       // refinement (mixed precision)
+  double rn64, bn64, rn64_prev;            // refinement (mixed precision); rn64 before the last refinement
   double tgt;                              // absolute residual target of the FP32 inner solve
   double mass_defect;
   int32_t it, done, zero_rhs, total_it;
@@ -48,13 +48,16 @@ struct SlotCtl {
 
 // Geometric multigrid hierarchy of the pressure matrix (preconditioner):
 // every dimension halved (rounding up) per level until a level has at most
-// MG_COARSEST cells (at most MG_MAXL levels); levels of at most
-// MG_TAIL_CELLS cells run in one workgroup; the coarsest level is solved
-// with its dense inverse, so it may have at most MG_DENSE_MAX cells.
+// MG_COARSEST cells (at most MG_MAXL levels); the coarsest level is solved
+// with its dense inverse, so it may have at most MG_DENSE_MAX cells.  The
+// levels from the first one with at most MG_TAIL_CELLS cells whose arrays
+// fit MG_TAIL_LDS bytes (the tail) run in one workgroup out of LDS; their
+// arrays form one contiguous block (mg_tail_bytes).
 constexpr int MG_MAXL = 12;
 constexpr int MG_COARSEST = 16;
 constexpr int MG_TAIL_CELLS = 4096;
 constexpr int MG_DENSE_MAX = 64;
+constexpr int MG_TAIL_LDS = 160 * 1024;   // LDS of one gfx950 workgroup
 struct MGLevel {
   int32_t nx, ny, nz, nc, nxy, nblocks;
   void *cf[3];        // coefficient of each cell's low face per direction (T)
@@ -67,7 +70,16 @@ struct MGInfo {
   int32_t tail;       // first level handled by the single-workgroup tail kernel
   MGLevel lv[MG_MAXL + 1];
   void *Ainv;         // dense inverse of the coarsest operator, row-major (T)
+  void *tail_base;    // block of Ainv, then per level tail..L: cf[dim], cout, invD, b, x, t
+  int32_t tail_bytes; // its size (a multiple of 16)
 };
+
+// bytes of the tail block when the tail starts at level l (elements of w bytes)
+inline int64_t mg_tail_bytes(const MGInfo &mg, int l, int dim, int w) {
+  int64_t n = (int64_t)mg.lv[mg.L].nc * mg.lv[mg.L].nc;
+  for (int m = l; m <= mg.L; ++m) n += (int64_t)(dim + 5) * mg.lv[m].nc;
+  return (n * w + 15) / 16 * 16;
+}
 
 struct Slot {
   int32_t dim, nx, ny, nz;
