@@ -280,6 +280,7 @@ struct oscar_ctx {
   int pred[3][64][2];
   bool refine_stall = false;  // an outer refinement stopped short of its tolerance
   bool mg_stale = true;       // the multigrid hierarchy predates the current 1/a_P
+  int ctl_mode = 0;           // mode of the control block last set (0 viscous, 1 capillary)
   int total_seen = 0;   // device total_it at the last state read (0 after a state reset)
   // optional timing of sampled conjugate-gradient iterations: every
   // t_period-th iteration of a solve gives each of its launches a region of
@@ -338,6 +339,7 @@ static int set_ctl(oscar_ctx *c, const SlotCtl &ctl) {
   u.n = 1;
   u.slot[0] = 0;
   u.ctl[0] = ctl;
+  c->ctl_mode = ctl.mode;
   launch_ctl_update(c->L(), u);
   HIPCHK(c, hipGetLastError());
   return OSCAR_OK;
@@ -486,9 +488,9 @@ static int enqueue_chunk(oscar_ctx *c, CgPos &q, int n) {
             smp.stage = oscar_ctx::S_RUN;
             smp.split = x == 0;   // its D launch ended the previous chunk
           }
-      launch_mg_cycle_part<R>(c->s, L, it, 0, region(q.tail_slot, 1));
-      launch_mg_cycle_part<R>(c->s, L, it, 1, region(q.tail_slot, 2));
-      launch_mg_cycle_part<R>(c->s, L, it, 2, region(q.tail_slot, 2 + ncoarse));
+      launch_mg_cycle_part<R>(c->s, L, it, 0, c->ctl_mode, region(q.tail_slot, 1));
+      launch_mg_cycle_part<R>(c->s, L, it, 1, c->ctl_mode, region(q.tail_slot, 2));
+      launch_mg_cycle_part<R>(c->s, L, it, 2, c->ctl_mode, region(q.tail_slot, 2 + ncoarse));
       q.tail = false;
     }
     const int it = q.next++;
@@ -746,7 +748,7 @@ static int solve_pressure(oscar_ctx *c, int &iters, int kind, int corr) {
     q.base = c->total_seen;
     const int base = q.base;
     if (mg)   // z_0 = B r_0
-      for (int part = 0; part < 3; ++part) launch_mg_cycle_part<R>(c->s, c->L(), -1, part);
+      for (int part = 0; part < 3; ++part) launch_mg_cycle_part<R>(c->s, c->L(), -1, part, c->ctl_mode);
     else launch_cg_init<R>(c->L());
     HIPCHK(c, hipGetLastError());
     int &pred = pr[outer > 0 ? 1 : 0];

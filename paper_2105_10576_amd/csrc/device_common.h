@@ -352,6 +352,32 @@ __device__ __forceinline__ X matvec_row_f(const Grid &G, const R *rAU, const Cel
   return matvec_pre<X>(G, c, fl, xP, rP, xn, rn);
 }
 
+// Element at a 32-bit byte offset from a base pointer: with the base in
+// scalar registers the load takes the offset as its only per-lane address
+// operand, and one offset serves every array of the same element size.
+template <typename T>
+__device__ __forceinline__ T ldo(const T *base, unsigned off) {
+  return *(const T *)((const char *)base + off);
+}
+template <typename T>
+__device__ __forceinline__ void sto(T *base, unsigned off, T v) {
+  *(T *)((char *)base + off) = v;
+}
+
+// byte offsets of cell P (element size w) and of its neighbours across
+// faces 0..5 where the face is interior (flag bit f), else of P itself
+__device__ __forceinline__ void nb_offsets(const Grid &G, unsigned P, uint8_t fl, unsigned w, unsigned &oP,
+                                           unsigned (&on)[6]) {
+  oP = P * w;
+  const unsigned sx = w, sy = (unsigned)G.nx * w, sz = (unsigned)G.nxy * w;
+  const unsigned st[3] = {sx, sy, sz};
+#pragma unroll
+  for (int f = 0; f < 6; ++f) {
+    const unsigned n = (f & 1) ? oP + st[f >> 1] : oP - st[f >> 1];
+    on[f] = ((fl >> f) & 1u) ? n : oP;
+  }
+}
+
 // Grid-stride loop over index range [first, end) in steps of `stride`, NB
 // indices per thread at a time: per batch, flag(o, g) for each index (it
 // reads what decides which operands a cell needs; g may lie past the end),

@@ -16,8 +16,8 @@
 // re-evaluates the first sweep at its neighbours (a radius-2 stencil) rather
 // than waiting for another launch.
 //
-// Execution: the pre-smoothing kernels walk their level in child order (the
-// 2^dim cells of one coarser cell are consecutive lanes of a wavefront), so
+// Execution: the pre-smoothing kernels walk their level in tile order (the
+// 2^dim cells of one coarser cell are lanes of the same wavefront), so
 // the restriction of the residual is a lane-shuffle sum inside the same
 // kernel and no restriction launch or residual array exists.  The small
 // levels (from the one the host marks as the tail down to the coarsest) run
@@ -143,36 +143,63 @@ __device__ __forceinline__ int parent_shift(int q, int side, int cstep) {
   return 0;
 }
 
-// Child order: thread tau of a level with dims (nx, ny, nz) whose parents
-// have dims (cnx, cny, .) is child (tau mod 2^dim) of parent (tau >> dim);
-// children beyond an odd dimension are invalid and contribute zero.
+// Tile order of the pre-smoothing with restriction: wavefront w of a level
+// covers a tile of 16 x 2 x 2 fine cells (2D: 32 x 2), the children of 8
+// (2D: 16) consecutive parents along x, and lane l holds the fine cell at
+// offset (l mod 16, (l / 16) mod 2, l / 32) in the tile (2D: (l mod 32,
+// l / 32)).  Each 16-lane quarter of a wavefront so reads 16 consecutive
+// cells of one row, a single coalesced access; the 2^dim children of a
+// parent are lanes l, l^1, l^16, l^17, l^32, ... (2D: l, l^1, l^32, l^33),
+// so the restriction is a lane-shuffle sum.  Cells outside the level (an
+// odd dimension, the padding of a row's last tile) are invalid and
+// contribute zero.
 struct Kid {
   int P, i, j, k, parent;
   bool valid, lead;
 };
 
+__host__ __device__ inline unsigned kid_px(int dim) { return dim == 3 ? 8u : 16u; }   // parents per tile along x
+
+// number of thread indices (a multiple of 64) covering a level whose
+// parents have dims (cnx, cny, cnz)
+__host__ __device__ inline unsigned kid_total(int dim, int cnx, int cny, int cnz) {
+  const unsigned px = kid_px(dim);
+  return ((unsigned)cnx + px - 1u) / px * (unsigned)cny * (unsigned)cnz * 64u;
+}
+
 __device__ __forceinline__ Kid kid_at(unsigned tau, int dim, int nx, int ny, int nz, int cnx, int cny) {
   Kid q;
-  const unsigned ch = tau & ((1u << dim) - 1u), C = tau >> dim;
-  const unsigned crow = C / (unsigned)cnx, ck = crow / (unsigned)cny;
-  const int ci = (int)(C - crow * (unsigned)cnx), cj = (int)(crow - ck * (unsigned)cny);
-  q.i = 2 * ci + (int)(ch & 1u);
-  q.j = 2 * cj + (int)((ch >> 1) & 1u);
-  q.k = dim == 3 ? 2 * (int)ck + (int)(ch >> 2) : 0;
-  q.valid = q.i < nx && q.j < ny && q.k < nz;
+  const unsigned l = tau & 63u, w = tau >> 6;
+  const unsigned px = kid_px(dim);
+  const unsigned nbx = ((unsigned)cnx + px - 1u) / px;
+  const unsigned row = w / nbx, bx = w - row * nbx;
+  const unsigned ck = dim == 3 ? row / (unsigned)cny : 0u, cj = row - ck * (unsigned)cny;
+  const unsigned xr = dim == 3 ? (l & 15u) : (l & 31u);
+  const unsigned jy = dim == 3 ? ((l >> 4) & 1u) : (l >> 5);
+  const unsigned kz = dim == 3 ? (l >> 5) : 0u;
+  const int ci = (int)(bx * px + (xr >> 1));
+  const bool pin = ci < cnx;
+  q.i = (int)(2u * bx * px + xr);
+  q.j = 2 * (int)cj + (int)jy;
+  q.k = 2 * (int)ck + (int)kz;
+  q.valid = pin && q.i < nx && q.j < ny && q.k < nz;
   q.P = q.i + nx * (q.j + ny * q.k);
-  q.parent = (int)C;
-  q.lead = ch == 0;
+  q.parent = ci + cnx * ((int)cj + cny * (int)ck);
+  q.lead = pin && (xr & 1u) == 0u && jy == 0u && kz == 0u;
   return q;
 }
 
-// sum over the 2^dim lanes of one parent (lanes tau ^ 1, ^ 2, ^ 4); every
-// lane of the group must call it
+// sum over the 2^dim lanes of one parent: pairs along x, then y, then z;
+// every lane of the wavefront must call it
 template <typename T>
 __device__ __forceinline__ T kid_sum(T v, int dim) {
   v = v + __shfl_xor(v, 1, 64);
-  v = v + __shfl_xor(v, 2, 64);
-  if (dim == 3) v = v + __shfl_xor(v, 4, 64);
+  if (dim == 3) {
+    v = v + __shfl_xor(v, 16, 64);
+    v = v + __shfl_xor(v, 32, 64);
+  } else {
+    v = v + __shfl_xor(v, 32, 64);
+  }
   return v;
 }
 
@@ -308,17 +335,17 @@ __global__ void __launch_bounds__(MG_INV_THREADS) k_mg_coarse_inv(const Slot S) 
 // cycle pieces on coarse levels (DIM = 2 or 3)
 // ---------------------------------------------------------------------------
 
-// Pre-smoothing from zero on level L in child order, with the restriction:
+// Pre-smoothing from zero on level L in tile order, with the restriction:
 // x_1 = w D^-1 b, x_{m+1} = x_m + w D^-1 (b - A x_m) up to MG_NU sweeps,
-// t = b - A x, b_next[parent] = sum of the children's t.  (cnx, cny, cnc)
+// t = b - A x, b_next[parent] = sum of the children's t.  (cnx, cny, cnz)
 // are the dimensions of the next coarser level; bnext may point to global
 // memory or to LDS.
 template <int DIM, typename T>
-__device__ __forceinline__ void smooth_restrict(const LV<T> &L, int cnx, int cny, int cnc, T *bnext, unsigned start,
+__device__ __forceinline__ void smooth_restrict(const LV<T> &L, int cnx, int cny, int cnz, T *bnext, unsigned start,
                                                 unsigned stride) {
   const T w = (T)MG_OMEGA;
   const int st[3] = {1, L.nx, L.nxy};
-  const unsigned total = (unsigned)cnc << DIM;
+  const unsigned total = kid_total(DIM, cnx, cny, cnz);
   for (unsigned tau = start; tau < total; tau += stride) {
     const Kid q = kid_at(tau, DIM, L.nx, L.ny, L.nz, cnx, cny);
     T tv = (T)0;
@@ -391,7 +418,7 @@ __global__ void __launch_bounds__(BLOCK) k_mg_smooth(const Slot S, int l, unsign
   if (mg_idle(s)) return;
   const LV<T> L = lview<T>(s.mg.lv[l]);
   const MGLevel &C = s.mg.lv[l + 1];
-  smooth_restrict<DIM, T>(L, C.nx, C.ny, C.nc, (T *)C.b, blockIdx.x * BLOCK + threadIdx.x, gridDim.x * BLOCK);
+  smooth_restrict<DIM, T>(L, C.nx, C.ny, C.nz, (T *)C.b, blockIdx.x * BLOCK + threadIdx.x, gridDim.x * BLOCK);
   stamp.done();
 }
 
@@ -463,7 +490,7 @@ __global__ void __launch_bounds__(MG_TAIL_THREADS) k_mg_tail(const Slot S, unsig
   };
   for (int l = tl; l < L; ++l) {
     const MGLevel &N = s.mg.lv[l + 1];
-    smooth_restrict<DIM, T>(lds_view(l), N.nx, N.ny, N.nc, in_lds(N.b), t0, ns);
+    smooth_restrict<DIM, T>(lds_view(l), N.nx, N.ny, N.nz, in_lds(N.b), t0, ns);
     __syncthreads();
   }
   // coarsest level: t = A^-1 b with the dense inverse (row t0, fixed order)
@@ -496,13 +523,16 @@ __global__ void __launch_bounds__(MG_TAIL_THREADS) k_mg_tail(const Slot S, unsig
 // (block-table launches like the other fine-grid kernels)
 // ---------------------------------------------------------------------------
 
-// this workgroup's block within the slot (XCD-ordered block table); false
-// for padding entries and once the solve has converged
-__device__ __forceinline__ bool fine_block(const Slot &s, const int2 *btab, int &lb) {
-  const int done = s.st->done;
-  const int2 t = btab[blockIdx.x];
-  lb = t.y;
-  return !done && t.y >= 0;
+// This workgroup's block within the slot, or -1 for padding: the launch
+// deals its workgroups round-robin to the 8 XCDs and each XCD runs a
+// contiguous run of the slot's blocks (the host's block table for one slot,
+// computed here rather than loaded).
+__device__ __forceinline__ int xcd_block(int p, int nb) {
+  const int X = 8, q = nb / X, rem = nb % X;
+  const int x = p % X, i = p / X;
+  const int cnt = q + (x < rem ? 1 : 0);
+  const int start = x * q + (x < rem ? x : rem);
+  return i < cnt ? start + i : -1;
 }
 
 // cells per thread and batch in the fine-grid kernels: two in FP32; one in
@@ -521,13 +551,13 @@ constexpr int FINE_NB = sizeof(R) == 4 ? 2 : 1;
 // previous cycle's reduction, convergence test (it > 0), beta, d = z + beta
 // d_old (d = z when it = 0), q = A d and <d,q>.
 template <typename R, int NB>
-__global__ void __launch_bounds__(BLOCK) k_mgcg_dir(const Slot S, const int2 *btab, int it,
+__global__ void __launch_bounds__(BLOCK) k_mgcg_dir(const Slot S, int it,
                                                     unsigned long long *ts) {
   using T = R;
   Stamp stamp(ts);
   const Slot &s = S;
-  int lb;
-  if (!fine_block(s, btab, lb)) return;
+  const int lb = xcd_block(blockIdx.x, s.nblocks);
+  if (lb < 0 || s.st->done) return;
   const Grid G = grid_of(s);
   const SlotCtl &ctl = *s.ctl;
   SlotState *st = s.st;
@@ -559,16 +589,16 @@ __global__ void __launch_bounds__(BLOCK) k_mgcg_dir(const Slot S, const int2 *bt
       },
       [&](Op &o) {
         if (o.fl & 0x40) return;
-        const int P = o.c.P;
-        o.z[6] = z[P];
-        o.o[6] = dold[P];
-        o.ra[6] = rAU[P];
+        unsigned oP, on[6];
+        nb_offsets(G, (unsigned)o.c.P, o.fl, sizeof(T), oP, on);
+        o.z[6] = ldo(z, oP);
+        o.o[6] = ldo(dold, oP);
+        o.ra[6] = ldo(rAU, oP);
 #pragma unroll
         for (int f = 0; f < 6; ++f) {
-          const int n = nb_at(G, P, o.fl, f);
-          o.z[f] = z[n];
-          o.o[f] = dold[n];
-          o.ra[f] = rAU[n];
+          o.z[f] = ldo(z, on[f]);
+          o.o[f] = ldo(dold, on[f]);
+          o.ra[f] = ldo(rAU, on[f]);
         }
       },
       [&]() {
@@ -608,8 +638,9 @@ __global__ void __launch_bounds__(BLOCK) k_mgcg_dir(const Slot S, const int2 *bt
           rn[f] = (T)o.ra[f];
         }
         const T qq = matvec_pre<T>(G, o.c, o.fl, dP, (T)o.ra[6], xn, rn);
-        dn[o.c.P] = dP;
-        q[o.c.P] = qq;
+        const unsigned oP = (unsigned)o.c.P * sizeof(T);
+        sto(dn, oP, dP);
+        sto(q, oP, qq);
         red[0] = red[0] + (double)(dP * qq);
       });
   if (stop) return;   // uniform: every thread read the same totals
@@ -620,19 +651,20 @@ __global__ void __launch_bounds__(BLOCK) k_mgcg_dir(const Slot S, const int2 *bt
 // Iteration it >= 0: alpha = gamma / <d,q>, x += alpha d, r -= alpha q; for
 // it = -1 (the cycle before the first iteration) r is the initial residual.
 // Then the cycle's fine pre-smoothing z0 = w D^-1 r and the restriction of
-// its residual r - A z0 into level 1, walking the fine grid in child order.
+// its residual r - A z0 into level 1, walking the fine grid in tile order.
 template <typename R, int NB>
-__global__ void __launch_bounds__(BLOCK) k_mg_fine_down(const Slot S, const int2 *btab, int it,
+__global__ void __launch_bounds__(BLOCK) k_mg_fine_down(const Slot S, int it, int mode,
                                                         unsigned long long *ts) {
   using T = R;
   Stamp stamp(ts);
   const Slot &s = S;
-  int lb;
-  if (!fine_block(s, btab, lb)) return;
+  const int lb = xcd_block(blockIdx.x, s.nblocks);
+  if (lb < 0 || s.st->done) return;
   const Grid G = grid_of(s);
-  const SlotCtl &ctl = *s.ctl;
   SlotState *st = s.st;
-  const bool mixed = s.precision != 0;
+  // the unknown the iterations update: the FP32 correction of the mixed
+  // path (R = float), the FP64 pressure otherwise
+  constexpr bool mixed = sizeof(T) == 4;
   const bool upd = it >= 0;
   const R *rAU = (const R *)s.rAU;
   const T *invD = (const T *)s.invD;
@@ -642,14 +674,13 @@ __global__ void __launch_bounds__(BLOCK) k_mg_fine_down(const Slot S, const int2
   T *r1 = (T *)s.cr[upd ? ((it + 1) & 1) : 0];
   const T *d = (const T *)s.cs[upd ? (it & 1) : 0], *q = upd ? (const T *)s.cp : r0;
   T *z0 = (T *)s.cw[1];
-  T *xe = (T *)s.e;
-  double *xp = ctl.mode ? s.p_cr : s.p_vd;
+  T *xv = mixed ? (T *)s.e : (T *)(mode ? s.p_cr : s.p_vd);
   const int cnx = s.mg.lv[1].nx, cny = s.mg.lv[1].ny;
   T *b1 = (T *)s.mg.lv[1].b;
   const uint8_t *flags = s.flags;
   const T w = (T)MG_OMEGA;
   const int dim = G.dim;
-  const int total = (int)((unsigned)s.mg.lv[1].nc << dim);
+  const int total = (int)kid_total(dim, cnx, cny, s.mg.lv[1].nz);
   struct Op {
     Cell c;
     int tau, parent;
@@ -657,8 +688,7 @@ __global__ void __launch_bounds__(BLOCK) k_mg_fine_down(const Slot S, const int2
     uint8_t fl;
     T r[7], q[7], iD[7];   // r, q, D^-1 across faces 0..5, then at the cell
     R ra[7];               // rAU likewise
-    T d, xe;               // search direction and FP32 correction at the cell
-    double xp;             // FP64 pressure at the cell
+    T d, x;                // search direction and unknown at the cell (read also when unused)
   };
   T al = (T)0;
   batched<NB, Op>(
@@ -684,24 +714,21 @@ __global__ void __launch_bounds__(BLOCK) k_mg_fine_down(const Slot S, const int2
       },
       [&](Op &o) {
         if (o.fl & 0x40) return;
-        const int P = o.c.P;
-        o.r[6] = r0[P];
-        o.q[6] = q[P];
-        o.iD[6] = invD[P];
-        o.ra[6] = rAU[P];
+        unsigned oP, on[6];
+        nb_offsets(G, (unsigned)o.c.P, o.fl, sizeof(T), oP, on);
+        o.r[6] = ldo(r0, oP);
+        o.q[6] = ldo(q, oP);
+        o.iD[6] = ldo(invD, oP);
+        o.ra[6] = ldo(rAU, oP);
 #pragma unroll
         for (int f = 0; f < 6; ++f) {
-          const int n = nb_at(G, P, o.fl, f);
-          o.r[f] = r0[n];
-          o.q[f] = q[n];
-          o.iD[f] = invD[n];
-          o.ra[f] = rAU[n];
+          o.r[f] = ldo(r0, on[f]);
+          o.q[f] = ldo(q, on[f]);
+          o.iD[f] = ldo(invD, on[f]);
+          o.ra[f] = ldo(rAU, on[f]);
         }
-        if (upd) {
-          o.d = d[P];
-          if (mixed) o.xe = xe[P];
-          else o.xp = xp[P];
-        }
+        o.d = ldo(d, oP);
+        o.x = ldo(xv, oP);
       },
       [&]() {
         if (!upd) return true;
@@ -729,12 +756,12 @@ __global__ void __launch_bounds__(BLOCK) k_mg_fine_down(const Slot S, const int2
             ran[f] = (T)o.ra[f];
           }
           const T Az = matvec_pre<T>(G, o.c, o.fl, zz, (T)o.ra[6], xn, ran);
+          const unsigned oP = (unsigned)P * sizeof(T);
           if (upd) {
-            if (mixed) xe[P] = o.xe + al * o.d;
-            else xp[P] = o.xp + (double)al * (double)o.d;
-            r1[P] = rn;
+            sto(xv, oP, o.x + al * o.d);
+            sto(r1, oP, rn);
           }
-          z0[P] = zz;
+          sto(z0, oP, zz);
           tv = rn - Az;
         }
         tv = kid_sum(tv, dim);
@@ -746,13 +773,13 @@ __global__ void __launch_bounds__(BLOCK) k_mg_fine_down(const Slot S, const int2
 // Last step of the cycle: z' = z0 + P x1, z = z' + w D^-1 (r - A z'); the
 // reduction <r,z>, |r|^2 for the next search direction.
 template <typename R, int NB>
-__global__ void __launch_bounds__(BLOCK) k_mg_fine_up(const Slot S, const int2 *btab, int it,
+__global__ void __launch_bounds__(BLOCK) k_mg_fine_up(const Slot S, int it,
                                                       unsigned long long *ts) {
   using T = R;
   Stamp stamp(ts);
   const Slot &s = S;
-  int lb;
-  if (!fine_block(s, btab, lb)) return;
+  const int lb = xcd_block(blockIdx.x, s.nblocks);
+  if (lb < 0 || s.st->done) return;
   const Grid G = grid_of(s);
   const uint8_t *flags = s.flags;
   const R *rAU = (const R *)s.rAU;
@@ -783,24 +810,25 @@ __global__ void __launch_bounds__(BLOCK) k_mg_fine_up(const Slot S, const int2 *
       [&](Op &o) {
         if (o.fl & 0x40) return;
         const Cell &c = o.c;
-        const int P = c.P;
         const int pP = (c.i >> 1) + cnx * (c.j >> 1) + cnxy * (c.k >> 1);
         const int q[3] = {c.i, c.j, c.k};
         const int cst[3] = {1, cnx, cnxy};
-        o.z0[6] = z0[P];
-        o.xc[6] = xc[pP];
-        o.ra[6] = rAU[P];
-        o.r = r[P];
-        o.iD = invD[P];
+        unsigned oP, on[6];
+        nb_offsets(G, (unsigned)c.P, o.fl, sizeof(T), oP, on);
+        const unsigned opP = (unsigned)pP * sizeof(T);
+        o.z0[6] = ldo(z0, oP);
+        o.xc[6] = ldo(xc, opP);
+        o.ra[6] = ldo(rAU, oP);
+        o.r = ldo(r, oP);
+        o.iD = ldo(invD, oP);
 #pragma unroll
         for (int f = 0; f < 6; ++f) {
           const bool in = (o.fl >> f) & 1u;
-          const int n = nb_at(G, P, o.fl, f);
           // parent of the neighbour: it changes across the face iff the face is a parent's face
           const int pn = in ? pP + parent_shift(q[f >> 1], (f & 1) ? 1 : -1, cst[f >> 1]) : pP;
-          o.z0[f] = z0[n];
-          o.xc[f] = xc[pn];
-          o.ra[f] = rAU[n];
+          o.z0[f] = ldo(z0, on[f]);
+          o.xc[f] = ldo(xc, (unsigned)pn * sizeof(T));
+          o.ra[f] = ldo(rAU, on[f]);
         }
       },
       [&]() { return true; },
@@ -817,7 +845,7 @@ __global__ void __launch_bounds__(BLOCK) k_mg_fine_up(const Slot S, const int2 *
         const T Az = matvec_pre<T>(G, o.c, o.fl, zP, (T)o.ra[6], xn, rn);
         const T rr = o.r;
         const T zn = zP + w * (o.iD * (rr - Az));
-        z[o.c.P] = zn;
+        sto(z, (unsigned)o.c.P * sizeof(T), zn);
         red[0] = red[0] + (double)(rr * zn);
         red[1] = red[1] + (double)(rr * rr);
       });
@@ -844,7 +872,7 @@ void launch_mg_setup(const Slot &hs, hipStream_t stream) {
 
 template <typename R>
 void launch_mg_dir(const Slot &hs, const Launch &L, int it, unsigned long long *ts) {
-  hipLaunchKernelGGL((k_mgcg_dir<R, FINE_NB<R>>), dim3((unsigned)L.nblocks), dim3(BLOCK), 0, L.stream, hs, L.btab, it, ts);
+  hipLaunchKernelGGL((k_mgcg_dir<R, FINE_NB<R>>), dim3((unsigned)L.nblocks), dim3(BLOCK), 0, L.stream, hs, it, ts);
 }
 
 template <int DIM, typename R>
@@ -853,7 +881,7 @@ static void vcycle_levels(const Slot &hs, const Launch &L, unsigned long long *t
   int m = 0;   // launch index within the part: its stamp region
   auto next = [&]() -> unsigned long long * { return ts ? ts + (size_t)TS_WORDS * m++ : nullptr; };
   for (int l = 1; l < tl; ++l)
-    hipLaunchKernelGGL((k_mg_smooth<DIM, R>), dim3(lvl_grid(hs.mg.lv[l + 1].nc << DIM)), dim3(BLOCK), 0, L.stream, hs,
+    hipLaunchKernelGGL((k_mg_smooth<DIM, R>), dim3(lvl_grid((int)kid_total(DIM, hs.mg.lv[l + 1].nx, hs.mg.lv[l + 1].ny, hs.mg.lv[l + 1].nz))), dim3(BLOCK), 0, L.stream, hs,
                        l, next());
   hipLaunchKernelGGL((k_mg_tail<DIM, R>), dim3(1), dim3(MG_TAIL_THREADS), (size_t)hs.mg.tail_bytes, L.stream, hs,
                      next());
@@ -863,15 +891,15 @@ static void vcycle_levels(const Slot &hs, const Launch &L, unsigned long long *t
 
 // part of the cycle of iteration it (it = -1: the cycle of the initial residual)
 template <typename R>
-void launch_mg_cycle_part(const Slot &hs, const Launch &L, int it, int part, unsigned long long *ts) {
+void launch_mg_cycle_part(const Slot &hs, const Launch &L, int it, int part, int mode, unsigned long long *ts) {
   const dim3 fg((unsigned)L.nblocks), fb(BLOCK);
   if (part == 0) {
-    hipLaunchKernelGGL((k_mg_fine_down<R, FINE_NB<R>>), fg, fb, 0, L.stream, hs, L.btab, it, ts);
+    hipLaunchKernelGGL((k_mg_fine_down<R, FINE_NB<R>>), fg, fb, 0, L.stream, hs, it, mode, ts);
   } else if (part == 1) {
     if (hs.dim == 3) vcycle_levels<3, R>(hs, L, ts);
     else vcycle_levels<2, R>(hs, L, ts);
   } else {
-    hipLaunchKernelGGL((k_mg_fine_up<R, FINE_NB<R>>), fg, fb, 0, L.stream, hs, L.btab, it, ts);
+    hipLaunchKernelGGL((k_mg_fine_up<R, FINE_NB<R>>), fg, fb, 0, L.stream, hs, it, ts);
   }
 }
 
@@ -879,7 +907,7 @@ template void launch_mg_setup<double>(const Slot &, hipStream_t);
 template void launch_mg_setup<float>(const Slot &, hipStream_t);
 template void launch_mg_dir<double>(const Slot &, const Launch &, int, unsigned long long *);
 template void launch_mg_dir<float>(const Slot &, const Launch &, int, unsigned long long *);
-template void launch_mg_cycle_part<double>(const Slot &, const Launch &, int, int, unsigned long long *);
-template void launch_mg_cycle_part<float>(const Slot &, const Launch &, int, int, unsigned long long *);
+template void launch_mg_cycle_part<double>(const Slot &, const Launch &, int, int, int, unsigned long long *);
+template void launch_mg_cycle_part<float>(const Slot &, const Launch &, int, int, int, unsigned long long *);
 
 }  // namespace oscar

@@ -149,10 +149,11 @@ void launch_state_reset(const Launch &L, int nslots);
 template <typename R> void launch_mg_setup(const Slot &hs, hipStream_t st);
 // part 0: fine pre-smoothing with restriction (and the CG update of
 // iteration it >= 0); part 1: the coarse levels; part 2: fine prolongation,
-// post-smoothing and the next reduction
+// post-smoothing and the next reduction; mode: that of the slot's control
+// block (which pressure the FP64 update of part 0 acts on)
 // (with ts: one TS_WORDS region per launch, launches of part 1 in
 // consecutive regions; mg_part_launches gives their number)
-template <typename R> void launch_mg_cycle_part(const Slot &hs, const Launch &L, int it, int part,
+template <typename R> void launch_mg_cycle_part(const Slot &hs, const Launch &L, int it, int part, int mode,
                                                 unsigned long long *ts = nullptr);
 inline int mg_part_launches(const Slot &hs, int part) { return part == 1 ? 2 * (hs.mg.tail - 1) + 1 : 1; }
 template <typename R> void launch_mg_dir(const Slot &hs, const Launch &L, int it, unsigned long long *ts = nullptr);
