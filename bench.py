@@ -282,6 +282,7 @@ def main():
         from paper_2105_10576_amd import serving_bench
 
         out["serving"] = serving_bench.run(n_requests=args.serving_requests, max_iters=args.serving_max_iters,
+                                           precond=1 if args.precond == "mg" else 0,
                                            log=lambda m: print("[serving] " + m, file=sys.stderr, flush=True))
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(case)

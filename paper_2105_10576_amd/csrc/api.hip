@@ -1172,12 +1172,15 @@ struct oscar_engine {
   hipStream_t stream = nullptr;
   Slot *d_slots = nullptr;
   int2 *d_btab = nullptr, *d_btab2 = nullptr;
+  int2 *d_btab_j = nullptr, *d_btab_m = nullptr;   // block tables of the Jacobi and the multigrid slots
+  int *d_act = nullptr;            // multigrid slot lists by dimension (2 x max_slots)
   SlotState *d_states = nullptr;   // gathered copy of the slots' states
   int btab_cap = 0;
   SlotState *h_states = nullptr;
   std::vector<EngSlot> slots;
   std::vector<Region> free_list;
-  std::vector<int2> bt, bt2;
+  std::vector<int2> bt, bt2, bt_j, bt_m;
+  std::vector<int> act_m;
   std::string err = "no error";
   int64_t ticks = 0, cg_iters = 0;
 };
@@ -1197,8 +1200,8 @@ static int eng_fail(oscar_engine *e, hipError_t x, const char *what) {
   } while (0)
 
 static uint64_t eng_table_bytes(int max_slots, int btab_cap) {
-  return up(sizeof(Slot) * (uint64_t)max_slots) + 2 * up(sizeof(int2) * (uint64_t)btab_cap) +
-         up(sizeof(SlotState) * (uint64_t)max_slots);
+  return up(sizeof(Slot) * (uint64_t)max_slots) + 4 * up(sizeof(int2) * (uint64_t)btab_cap) +
+         up(sizeof(int) * 2 * (uint64_t)max_slots) + up(sizeof(SlotState) * (uint64_t)max_slots);
 }
 
 extern "C" int32_t oscar_engine_table_bytes(int32_t max_slots, uint64_t *bytes) {
@@ -1231,7 +1234,10 @@ extern "C" int32_t oscar_engine_create(int32_t max_slots, int32_t precision, voi
   e->d_slots = (Slot *)ws;
   e->d_btab = (int2 *)(e->ws + up(sizeof(Slot) * (uint64_t)max_slots));
   e->d_btab2 = (int2 *)((char *)e->d_btab + up(sizeof(int2) * (uint64_t)btab_cap));
-  e->d_states = (SlotState *)((char *)e->d_btab2 + up(sizeof(int2) * (uint64_t)btab_cap));
+  e->d_btab_j = (int2 *)((char *)e->d_btab2 + up(sizeof(int2) * (uint64_t)btab_cap));
+  e->d_btab_m = (int2 *)((char *)e->d_btab_j + up(sizeof(int2) * (uint64_t)btab_cap));
+  e->d_act = (int *)((char *)e->d_btab_m + up(sizeof(int2) * (uint64_t)btab_cap));
+  e->d_states = (SlotState *)((char *)e->d_act + up(sizeof(int) * 2 * (uint64_t)max_slots));
   e->heap_off = tb;
   e->slots.resize(max_slots);
   e->free_list.push_back(Region{tb, bytes - tb});
@@ -1297,7 +1303,15 @@ extern "C" int32_t oscar_engine_admit(oscar_engine *e, const oscar_desc *desc, d
   int rc = check_desc(desc, why);
   if (rc) { e->err = why; return rc; }
   if (desc->precision != e->precision) { e->err = "descriptor precision differs from the engine's"; return OSCAR_E_ARG; }
-  if (desc->precond != OSCAR_PC_JACOBI) { e->err = "the engine runs Jacobi-preconditioned solves only"; return OSCAR_E_ARG; }
+  if (desc->precond == OSCAR_PC_MG) {   // the multigrid tail runs out of LDS
+    MGInfo mg;
+    mg_levels(*desc, mg);
+    int dev = 0, lds = 0;
+    hipError_t x = hipGetDevice(&dev);
+    if (x == hipSuccess) x = hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    if (x != hipSuccess) return eng_fail(e, x, "hipDeviceGetAttribute");
+    if (lds < mg.tail_bytes) { e->err = "the multigrid tail does not fit the device's LDS"; return OSCAR_E_ARG; }
+  }
   if (!desc->mask || !desc->alpha0) { e->err = "mask and alpha0 must be non-NULL"; return OSCAR_E_ARG; }
   if (!(dt_vd > 0.0) || n_sub < 1 || max_iters < 1 || max_iters > n_sub || !(tol >= 0.0)) {
     e->err = "need dt_vd > 0, n_sub >= 1, 1 <= max_iters <= n_sub, tol >= 0";
@@ -1488,6 +1502,130 @@ static int eng_tick(oscar_engine *e) {
   EHIP(e, hipGetLastError());
   const bool mixed = e->precision == OSCAR_MIXED;
   const int n_corr = e->slots[act[0]].D.n_corr;
+  // The pressure solves run per preconditioner: the Jacobi slots and the
+  // multigrid slots, each group with a block table of its own when both are
+  // present (every other launch covers all active slots).
+  std::vector<int> gj, gm;
+  for (int i : act) (e->slots[i].D.precond == OSCAR_PC_MG ? gm : gj).push_back(i);
+  Launch Lj = L, Lm = L;
+  if (!gj.empty() && !gm.empty()) {
+    e->bt_j.clear();
+    e->bt_m.clear();
+    for (int i : gj) append_segment(e->bt_j, i, e->slots[i].g.nblocks);
+    for (int i : gm) append_segment(e->bt_m, i, e->slots[i].g.nblocks);
+    EHIP(e, hipMemcpyAsync(e->d_btab_j, e->bt_j.data(), sizeof(int2) * e->bt_j.size(), hipMemcpyHostToDevice, e->stream));
+    EHIP(e, hipMemcpyAsync(e->d_btab_m, e->bt_m.data(), sizeof(int2) * e->bt_m.size(), hipMemcpyHostToDevice, e->stream));
+    Lj.btab = e->d_btab_j;
+    Lj.nblocks = (int)e->bt_j.size();
+    Lm.btab = e->d_btab_m;
+    Lm.nblocks = (int)e->bt_m.size();
+  }
+  MGBatch B;
+  if (!gm.empty()) {
+    B.slots = e->d_slots;
+    B.btab = Lm.btab;
+    B.nblocks = Lm.nblocks;
+    B.stream = e->stream;
+    e->act_m.assign(2 * (size_t)e->max_slots, 0);
+    for (int di = 0; di < 2; ++di) {
+      std::vector<const Slot *> hs;
+      for (int i : gm)
+        if (e->slots[i].D.dim == di + 2) {
+          e->act_m[(size_t)di * e->max_slots + hs.size()] = i;
+          hs.push_back(&e->slots[i].s);
+        }
+      B.dim[di].act = e->d_act + (size_t)di * e->max_slots;
+      mg_batch_levels(B.dim[di], hs.data(), (int)hs.size(), di + 2);
+    }
+    EHIP(e, hipMemcpyAsync(e->d_act, e->act_m.data(), sizeof(int) * e->act_m.size(), hipMemcpyHostToDevice, e->stream));
+    launch_mg_setup_b<R>(B);   // coarse operators of this assembly's coefficients
+    EHIP(e, hipGetLastError());
+  }
+  auto group_done = [&](const std::vector<int> &g) {
+    for (int i : g)
+      if (!e->h_states[i].done) return false;
+    return true;
+  };
+  auto group_max_it = [&](const std::vector<int> &g) {
+    int m = 0;
+    for (int i : g) m = e->slots[i].D.pcg_max_it > m ? e->slots[i].D.pcg_max_it : m;
+    return m;
+  };
+  auto group_pred = [&](const std::vector<int> &g) {
+    int m = 1;
+    for (int i : g) {
+      const int p = mixed ? e->slots[i].pred_inner : e->slots[i].pred;
+      m = p > m ? p : m;
+    }
+    return m;
+  };
+  auto record_pred = [&](const std::vector<int> &g, int floor_it) {
+    for (int i : g) {
+      const int used = e->h_states[i].it;
+      int &p = mixed ? e->slots[i].pred_inner : e->slots[i].pred;
+      p = used > floor_it ? used : floor_it;
+    }
+  };
+  // one inner solve of the Jacobi group: chunks of single-launch iterations
+  auto inner_j = [&]() -> int {
+    launch_cg_init<R>(Lj);
+    EHIP(e, hipGetLastError());
+    int it0 = 0, chunk = group_pred(gj);
+    chunk = chunk > 2 ? chunk : 2;
+    const int max_it = group_max_it(gj);
+    while (!group_done(gj)) {
+      if (it0 > max_it + 1) { e->err = "conjugate gradient did not terminate"; return OSCAR_E_HIP; }
+      launch_cg_iters<R>(Lj, it0, chunk);
+      EHIP(e, hipGetLastError());
+      it0 += chunk;
+      int r2 = eng_read_states(e);
+      if (r2) return r2;
+      chunk = 8;
+    }
+    record_pred(gj, 2);
+    return OSCAR_OK;
+  };
+  // one inner solve of the multigrid group: the initial cycle, then chunks
+  // ending with a search-direction launch (the convergence test)
+  auto inner_m = [&]() -> int {
+    for (int part = 0; part < 3; ++part) launch_mg_cycle_part_b<R>(B, -1, part);
+    EHIP(e, hipGetLastError());
+    int next = 0;
+    bool tail = false;
+    int chunk = group_pred(gm) + 1;
+    const int max_it = group_max_it(gm);
+    while (!group_done(gm)) {
+      if (next > max_it + 1) { e->err = "conjugate gradient did not terminate"; return OSCAR_E_HIP; }
+      for (int x = 0; x < chunk; ++x) {
+        if (tail)
+          for (int part = 0; part < 3; ++part) launch_mg_cycle_part_b<R>(B, next - 1, part);
+        launch_mg_dir_b<R>(B, next);
+        ++next;
+        tail = true;
+      }
+      EHIP(e, hipGetLastError());
+      int r2 = eng_read_states(e);
+      if (r2) return r2;
+      chunk = 2;
+    }
+    record_pred(gm, 1);
+    return OSCAR_OK;
+  };
+  auto solve_group = [&](const std::vector<int> &g, const Launch &Lg, bool mg) -> int {
+    if (g.empty()) return OSCAR_OK;
+    if (!mixed) return mg ? inner_m() : inner_j();
+    // FP32 inner solves wrapped in FP64 refinement; the refinement acts on
+    // the slots whose inner solve finished
+    for (int outer = 0; outer < 30 && !group_done(g); ++outer) {
+      int r2 = mg ? inner_m() : inner_j();
+      if (r2) return r2;
+      launch_refine<R>(Lg);
+      EHIP(e, hipGetLastError());
+      r2 = eng_read_states(e);
+      if (r2) return r2;
+    }
+    return OSCAR_OK;
+  };
   std::vector<double> E(e->max_slots, 0.0);
   for (int j = 0; j < n_corr; ++j) {
     launch_predictor<R>(L);
@@ -1495,50 +1633,10 @@ static int eng_tick(oscar_engine *e) {
     EHIP(e, hipGetLastError());
     rc = eng_read_states(e);
     if (rc) return rc;
-    auto all_done = [&]() {
-      for (int i : act)
-        if (!e->h_states[i].done) return false;
-      return true;
-    };
-    auto inner = [&]() -> int {
-      launch_cg_init<R>(L);
-      EHIP(e, hipGetLastError());
-      int it0 = 0, chunk = 2;
-      for (int i : act) {
-        int p = mixed ? e->slots[i].pred_inner : e->slots[i].pred;
-        chunk = p > chunk ? p : chunk;
-      }
-      int max_it = 0;
-      for (int i : act) max_it = e->slots[i].D.pcg_max_it > max_it ? e->slots[i].D.pcg_max_it : max_it;
-      while (!all_done()) {
-        if (it0 > max_it + 1) { e->err = "conjugate gradient did not terminate"; return OSCAR_E_HIP; }
-        launch_cg_iters<R>(L, it0, chunk);
-        EHIP(e, hipGetLastError());
-        it0 += chunk;
-        int r2 = eng_read_states(e);
-        if (r2) return r2;
-        chunk = 8;
-      }
-      for (int i : act) {
-        int used = e->h_states[i].it;
-        if (mixed) e->slots[i].pred_inner = used > 2 ? used : 2;
-        else e->slots[i].pred = used > 2 ? used : 2;
-      }
-      return OSCAR_OK;
-    };
-    if (!mixed) {
-      rc = inner();
-      if (rc) return rc;
-    } else {
-      for (int outer = 0; outer < 30 && !all_done(); ++outer) {
-        rc = inner();
-        if (rc) return rc;
-        launch_refine<R>(L);
-        EHIP(e, hipGetLastError());
-        rc = eng_read_states(e);
-        if (rc) return rc;
-      }
-    }
+    rc = solve_group(gj, Lj, false);
+    if (rc) return rc;
+    rc = solve_group(gm, Lm, true);
+    if (rc) return rc;
     if (j == 0)
       for (int i : act) E[i] = e->h_states[i].E;
     launch_correct<R>(L, j == n_corr - 1);

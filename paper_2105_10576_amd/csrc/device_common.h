@@ -355,13 +355,17 @@ __device__ __forceinline__ X matvec_row_f(const Grid &G, const R *rAU, const Cel
 // Element at a 32-bit byte offset from a base pointer: with the base in
 // scalar registers the load takes the offset as its only per-lane address
 // operand, and one offset serves every array of the same element size.
+// (The accesses name the global address space: a pointer read from the
+// slot table in memory is otherwise a generic one, accessed with flat
+// instructions.)
+#define OSCAR_GLOBAL __attribute__((address_space(1)))
 template <typename T>
 __device__ __forceinline__ T ldo(const T *base, unsigned off) {
-  return *(const T *)((const char *)base + off);
+  return *(const OSCAR_GLOBAL T *)((const char *)base + off);
 }
 template <typename T>
 __device__ __forceinline__ void sto(T *base, unsigned off, T v) {
-  *(T *)((char *)base + off) = v;
+  *(OSCAR_GLOBAL T *)((char *)base + off) = v;
 }
 
 // byte offsets of cell P (element size w) and of its neighbours across

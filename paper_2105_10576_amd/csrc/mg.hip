@@ -272,11 +272,39 @@ __device__ void setup_cell(const Slot &s, int l, int g) {
   ((T *)C.invD)[g] = diag > (T)0 ? (T)1 / diag : (T)0;
 }
 
+// workgroups of a launch over n items of one slot (at most 1024, grid-stride beyond)
+__host__ __device__ inline int lvl_blocks(int n) {
+  const int b = (n + BLOCK - 1) / BLOCK;
+  return b < 1 ? 1 : (b > 1024 ? 1024 : b);
+}
+
+// Batched launches over a device list `act` of multigrid slots use a
+// slot-major grid of maxb workgroups per slot; workgroup q of a slot works
+// only if q is below the slot's own count for the launch (and the slot has
+// the level).
+__device__ __forceinline__ const Slot &batch_slot(const Slot *slots, const int *act, int maxb, int &q) {
+  q = (int)blockIdx.x % maxb;
+  return slots[act[(int)blockIdx.x / maxb]];
+}
+
+template <typename T, typename R>
+__device__ __forceinline__ void mg_setup_body(const Slot &s, int l, int q, int nb) {
+  const int nc = s.mg.lv[l].nc;
+  for (int g = q * BLOCK + (int)threadIdx.x; g < nc; g += nb * BLOCK) setup_cell<T, R>(s, l, g);
+}
+
 template <typename T, typename R>
 __global__ void __launch_bounds__(BLOCK) k_mg_setup(const Slot S, int l) {
-  const Slot &s = S;
-  const MGLevel &C = s.mg.lv[l];
-  for (int g = blockIdx.x * BLOCK + threadIdx.x; g < C.nc; g += gridDim.x * BLOCK) setup_cell<T, R>(s, l, g);
+  mg_setup_body<T, R>(S, l, (int)blockIdx.x, (int)gridDim.x);
+}
+
+template <typename T, typename R>
+__global__ void __launch_bounds__(BLOCK) k_mg_setup_b(const Slot *slots, const int *act, int maxb, int l) {
+  int q;
+  const Slot &s = batch_slot(slots, act, maxb, q);
+  if (l > s.mg.L) return;
+  const int nb = lvl_blocks(s.mg.lv[l].nc);
+  if (q < nb) mg_setup_body<T, R>(s, l, q, nb);
 }
 
 // Dense inverse of the coarsest operator (n <= MG_DENSE_MAX cells) by
@@ -284,12 +312,10 @@ __global__ void __launch_bounds__(BLOCK) k_mg_setup(const Slot S, int l) {
 // symmetric positive definite on its cells with fluid); a cell without fluid
 // has an empty row and column and gets a zero row and column in the inverse.
 template <typename T>
-__global__ void __launch_bounds__(MG_INV_THREADS) k_mg_coarse_inv(const Slot S) {
-  const Slot &s = S;
+__device__ __forceinline__ void mg_coarse_inv_body(const Slot &s, T *A) {
   const MGLevel &C = s.mg.lv[s.mg.L];
   const int n = C.nc, dim = s.dim;
   if (n > MG_DENSE_MAX) return;   // excluded by the host's hierarchy check
-  __shared__ T A[MG_DENSE_MAX * MG_DENSE_MAX];
   const int nn = n * n;
   for (int x = threadIdx.x; x < nn; x += MG_INV_THREADS) A[x] = (T)0;
   __syncthreads();
@@ -329,6 +355,18 @@ __global__ void __launch_bounds__(MG_INV_THREADS) k_mg_coarse_inv(const Slot S) 
   }
   T *out = (T *)s.mg.Ainv;
   for (int x = threadIdx.x; x < nn; x += MG_INV_THREADS) out[x] = A[x];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(MG_INV_THREADS) k_mg_coarse_inv(const Slot S) {
+  __shared__ T A[MG_DENSE_MAX * MG_DENSE_MAX];
+  mg_coarse_inv_body<T>(S, A);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(MG_INV_THREADS) k_mg_coarse_inv_b(const Slot *slots, const int *act) {
+  __shared__ T A[MG_DENSE_MAX * MG_DENSE_MAX];
+  mg_coarse_inv_body<T>(slots[act[blockIdx.x]], A);
 }
 
 // ---------------------------------------------------------------------------
@@ -406,32 +444,68 @@ __device__ __forceinline__ void up_range(const LV<T> &L, int cnx, int cnxy, cons
   }
 }
 
-// The multigrid kernels serve one context (its record passed by value: the
-// fields are read from the constant argument segment) whose control block
-// is active during every solve; they return at once after convergence.
+// Each multigrid kernel comes in two forms over one body: for one context
+// (its record passed by value: the fields are read from the constant
+// argument segment) and batched over the serving engine's slot table.
+// Either returns at once for a slot whose solve has converged.
 __device__ __forceinline__ bool mg_idle(const Slot &s) { return s.st->done != 0; }
 
+// workgroups of the pre-smoothing launch of level l (tile order over the
+// next coarser level) and of its prolongation launch
+__host__ __device__ inline int smooth_blocks(const MGInfo &mg, int l, int dim) {
+  const MGLevel &C = mg.lv[l + 1];
+  return lvl_blocks((int)kid_total(dim, C.nx, C.ny, C.nz));
+}
+__host__ __device__ inline int up_blocks(const MGInfo &mg, int l) { return lvl_blocks(mg.lv[l].nc); }
+
 template <int DIM, typename T>
-__global__ void __launch_bounds__(BLOCK) k_mg_smooth(const Slot S, int l, unsigned long long *ts) {
-  Stamp stamp(ts);
-  const Slot &s = S;
-  if (mg_idle(s)) return;
+__device__ __forceinline__ void mg_smooth_body(const Slot &s, int l, unsigned start, unsigned stride) {
   const LV<T> L = lview<T>(s.mg.lv[l]);
   const MGLevel &C = s.mg.lv[l + 1];
-  smooth_restrict<DIM, T>(L, C.nx, C.ny, C.nz, (T *)C.b, blockIdx.x * BLOCK + threadIdx.x, gridDim.x * BLOCK);
-  stamp.done();
+  smooth_restrict<DIM, T>(L, C.nx, C.ny, C.nz, (T *)C.b, start, stride);
 }
 
 // final correction of level l goes to t_l (x_l keeps the pre-smoothed one)
 template <int DIM, typename T>
-__global__ void __launch_bounds__(BLOCK) k_mg_up(const Slot S, int l, unsigned long long *ts) {
-  Stamp stamp(ts);
-  const Slot &s = S;
-  if (mg_idle(s)) return;
+__device__ __forceinline__ void mg_up_body(const Slot &s, int l, int start, int stride) {
   const LV<T> L = lview<T>(s.mg.lv[l]);
   const MGLevel &C = s.mg.lv[l + 1];
-  up_range<DIM, T>(L, C.nx, C.nxy, (const T *)C.t, L.t, blockIdx.x * BLOCK + threadIdx.x, gridDim.x * BLOCK);
+  up_range<DIM, T>(L, C.nx, C.nxy, (const T *)C.t, L.t, start, stride);
+}
+
+template <int DIM, typename T>
+__global__ void __launch_bounds__(BLOCK) k_mg_smooth(const Slot S, int l, unsigned long long *ts) {
+  Stamp stamp(ts);
+  if (mg_idle(S)) return;
+  mg_smooth_body<DIM, T>(S, l, blockIdx.x * BLOCK + threadIdx.x, gridDim.x * BLOCK);
   stamp.done();
+}
+
+template <int DIM, typename T>
+__global__ void __launch_bounds__(BLOCK) k_mg_up(const Slot S, int l, unsigned long long *ts) {
+  Stamp stamp(ts);
+  if (mg_idle(S)) return;
+  mg_up_body<DIM, T>(S, l, blockIdx.x * BLOCK + threadIdx.x, gridDim.x * BLOCK);
+  stamp.done();
+}
+
+// batched: level l of the slots whose tail starts below it
+template <int DIM, typename T>
+__global__ void __launch_bounds__(BLOCK) k_mg_smooth_b(const Slot *slots, const int *act, int maxb, int l) {
+  int q;
+  const Slot &s = batch_slot(slots, act, maxb, q);
+  if (l >= s.mg.tail || mg_idle(s)) return;
+  const int nb = smooth_blocks(s.mg, l, DIM);
+  if (q < nb) mg_smooth_body<DIM, T>(s, l, (unsigned)(q * BLOCK) + threadIdx.x, (unsigned)(nb * BLOCK));
+}
+
+template <int DIM, typename T>
+__global__ void __launch_bounds__(BLOCK) k_mg_up_b(const Slot *slots, const int *act, int maxb, int l) {
+  int q;
+  const Slot &s = batch_slot(slots, act, maxb, q);
+  if (l >= s.mg.tail || mg_idle(s)) return;
+  const int nb = up_blocks(s.mg, l);
+  if (q < nb) mg_up_body<DIM, T>(s, l, q * BLOCK + (int)threadIdx.x, nb * BLOCK);
 }
 
 // Levels tail..L in one workgroup, out of LDS.  The tail block (the dense
@@ -443,20 +517,18 @@ __global__ void __launch_bounds__(BLOCK) k_mg_up(const Slot S, int l, unsigned l
 // correction of the tail level goes back to global memory for the next finer
 // level's prolongation.
 template <int DIM, typename T>
-__global__ void __launch_bounds__(MG_TAIL_THREADS) k_mg_tail(const Slot S, unsigned long long *ts) {
-  Stamp stamp(ts);
-  const Slot &s = S;
-  if (mg_idle(s)) return;
-  extern __shared__ uint4 mg_lds[];
+__device__ __forceinline__ void mg_tail_body(const Slot &s, uint4 *mg_lds) {
   const int tl = s.mg.tail, L = s.mg.L;
   const int t0 = threadIdx.x, ns = MG_TAIL_THREADS;
   const char *gbase = (const char *)s.mg.tail_base;
   {
     constexpr int U = 8;   // 16-byte loads in flight per thread
-    const uint4 *src = (const uint4 *)gbase;
+    typedef unsigned v4u __attribute__((ext_vector_type(4)));
+    const OSCAR_GLOBAL v4u *src = (const OSCAR_GLOBAL v4u *)gbase;
+    v4u *dst = (v4u *)mg_lds;
     const int n16 = s.mg.tail_bytes >> 4;
     for (int x0 = t0; x0 < n16; x0 += U * ns) {
-      uint4 v[U];
+      v4u v[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {   // past the end: reload the first entry (always in the block)
         const int x = x0 + u * ns;
@@ -464,7 +536,7 @@ __global__ void __launch_bounds__(MG_TAIL_THREADS) k_mg_tail(const Slot S, unsig
       }
 #pragma unroll
       for (int u = 0; u < U; ++u)
-        if (x0 + u * ns < n16) mg_lds[x0 + u * ns] = v[u];
+        if (x0 + u * ns < n16) dst[x0 + u * ns] = v[u];
     }
   }
   __syncthreads();
@@ -515,7 +587,24 @@ __global__ void __launch_bounds__(MG_TAIL_THREADS) k_mg_tail(const Slot S, unsig
   const T *tsrc = in_lds(M.t);
   T *tdst = (T *)M.t;
   for (int g = t0; g < M.nc; g += ns) tdst[g] = tsrc[g];
+}
+
+template <int DIM, typename T>
+__global__ void __launch_bounds__(MG_TAIL_THREADS) k_mg_tail(const Slot S, unsigned long long *ts) {
+  Stamp stamp(ts);
+  if (mg_idle(S)) return;
+  extern __shared__ uint4 mg_lds[];
+  mg_tail_body<DIM, T>(S, mg_lds);
   stamp.done();
+}
+
+// batched: one workgroup per slot
+template <int DIM, typename T>
+__global__ void __launch_bounds__(MG_TAIL_THREADS) k_mg_tail_b(const Slot *slots, const int *act) {
+  const Slot &s = slots[act[blockIdx.x]];
+  if (mg_idle(s)) return;
+  extern __shared__ uint4 mg_lds[];
+  mg_tail_body<DIM, T>(s, mg_lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -550,14 +639,10 @@ constexpr int FINE_NB = sizeof(R) == 4 ? 2 : 1;
 // Search direction of iteration it: gamma_it = <r,z> and |r|^2 from the
 // previous cycle's reduction, convergence test (it > 0), beta, d = z + beta
 // d_old (d = z when it = 0), q = A d and <d,q>.
+// (false: the solve converged at this test; nothing was written)
 template <typename R, int NB>
-__global__ void __launch_bounds__(BLOCK) k_mgcg_dir(const Slot S, int it,
-                                                    unsigned long long *ts) {
+__device__ __forceinline__ bool mgcg_dir_body(const Slot &s, int lb, int it) {
   using T = R;
-  Stamp stamp(ts);
-  const Slot &s = S;
-  const int lb = xcd_block(blockIdx.x, s.nblocks);
-  if (lb < 0 || s.st->done) return;
   const Grid G = grid_of(s);
   const SlotCtl &ctl = *s.ctl;
   SlotState *st = s.st;
@@ -643,9 +728,26 @@ __global__ void __launch_bounds__(BLOCK) k_mgcg_dir(const Slot S, int it,
         sto(q, oP, qq);
         red[0] = red[0] + (double)(dP * qq);
       });
-  if (stop) return;   // uniform: every thread read the same totals
+  if (stop) return false;   // uniform: every thread read the same totals
   put_partials<0u>(s, lb, CH_DQ, red);
-  stamp.done();
+  return true;
+}
+
+template <typename R, int NB>
+__global__ void __launch_bounds__(BLOCK) k_mgcg_dir(const Slot S, int it, unsigned long long *ts) {
+  Stamp stamp(ts);
+  const int lb = xcd_block(blockIdx.x, S.nblocks);
+  if (lb < 0 || S.st->done) return;
+  if (mgcg_dir_body<R, NB>(S, lb, it)) stamp.done();
+}
+
+// batched: the engine's block table of its multigrid slots
+template <typename R, int NB>
+__global__ void __launch_bounds__(BLOCK) k_mgcg_dir_b(const Slot *slots, const int2 *btab, int it) {
+  const int2 t = btab[blockIdx.x];
+  const Slot &s = slots[t.x];
+  if (t.y < 0 || s.st->done) return;
+  mgcg_dir_body<R, NB>(s, t.y, it);
 }
 
 // Iteration it >= 0: alpha = gamma / <d,q>, x += alpha d, r -= alpha q; for
@@ -653,13 +755,8 @@ __global__ void __launch_bounds__(BLOCK) k_mgcg_dir(const Slot S, int it,
 // Then the cycle's fine pre-smoothing z0 = w D^-1 r and the restriction of
 // its residual r - A z0 into level 1, walking the fine grid in tile order.
 template <typename R, int NB>
-__global__ void __launch_bounds__(BLOCK) k_mg_fine_down(const Slot S, int it, int mode,
-                                                        unsigned long long *ts) {
+__device__ __forceinline__ void mg_fine_down_body(const Slot &s, int lb, int it, int mode) {
   using T = R;
-  Stamp stamp(ts);
-  const Slot &s = S;
-  const int lb = xcd_block(blockIdx.x, s.nblocks);
-  if (lb < 0 || s.st->done) return;
   const Grid G = grid_of(s);
   SlotState *st = s.st;
   // the unknown the iterations update: the FP32 correction of the mixed
@@ -767,19 +864,30 @@ __global__ void __launch_bounds__(BLOCK) k_mg_fine_down(const Slot S, int it, in
         tv = kid_sum(tv, dim);
         if (o.lead) b1[o.parent] = tv;
       });
+}
+
+template <typename R, int NB>
+__global__ void __launch_bounds__(BLOCK) k_mg_fine_down(const Slot S, int it, int mode, unsigned long long *ts) {
+  Stamp stamp(ts);
+  const int lb = xcd_block(blockIdx.x, S.nblocks);
+  if (lb < 0 || S.st->done) return;
+  mg_fine_down_body<R, NB>(S, lb, it, mode);
   stamp.done();
+}
+
+template <typename R, int NB>
+__global__ void __launch_bounds__(BLOCK) k_mg_fine_down_b(const Slot *slots, const int2 *btab, int it) {
+  const int2 t = btab[blockIdx.x];
+  const Slot &s = slots[t.x];
+  if (t.y < 0 || s.st->done) return;
+  mg_fine_down_body<R, NB>(s, t.y, it, s.ctl->mode);
 }
 
 // Last step of the cycle: z' = z0 + P x1, z = z' + w D^-1 (r - A z'); the
 // reduction <r,z>, |r|^2 for the next search direction.
 template <typename R, int NB>
-__global__ void __launch_bounds__(BLOCK) k_mg_fine_up(const Slot S, int it,
-                                                      unsigned long long *ts) {
+__device__ __forceinline__ void mg_fine_up_body(const Slot &s, int lb, int it) {
   using T = R;
-  Stamp stamp(ts);
-  const Slot &s = S;
-  const int lb = xcd_block(blockIdx.x, s.nblocks);
-  if (lb < 0 || s.st->done) return;
   const Grid G = grid_of(s);
   const uint8_t *flags = s.flags;
   const R *rAU = (const R *)s.rAU;
@@ -850,7 +958,23 @@ __global__ void __launch_bounds__(BLOCK) k_mg_fine_up(const Slot S, int it,
         red[1] = red[1] + (double)(rr * rr);
       });
   put_partials<0u>(s, lb, CH_CG0 + (it & 1), red);
+}
+
+template <typename R, int NB>
+__global__ void __launch_bounds__(BLOCK) k_mg_fine_up(const Slot S, int it, unsigned long long *ts) {
+  Stamp stamp(ts);
+  const int lb = xcd_block(blockIdx.x, S.nblocks);
+  if (lb < 0 || S.st->done) return;
+  mg_fine_up_body<R, NB>(S, lb, it);
   stamp.done();
+}
+
+template <typename R, int NB>
+__global__ void __launch_bounds__(BLOCK) k_mg_fine_up_b(const Slot *slots, const int2 *btab, int it) {
+  const int2 t = btab[blockIdx.x];
+  const Slot &s = slots[t.x];
+  if (t.y < 0 || s.st->done) return;
+  mg_fine_up_body<R, NB>(s, t.y, it);
 }
 
 // ---------------------------------------------------------------------------
@@ -902,6 +1026,85 @@ void launch_mg_cycle_part(const Slot &hs, const Launch &L, int it, int part, int
     hipLaunchKernelGGL((k_mg_fine_up<R, FINE_NB<R>>), fg, fb, 0, L.stream, hs, it, ts);
   }
 }
+
+// ---------------------------------------------------------------------------
+// batched launchers (serving engine)
+// ---------------------------------------------------------------------------
+
+void mg_batch_levels(MGBatch::Dim &d, const Slot *const *hs, int n, int dim) {
+  d.n = n;
+  d.maxL = 0;
+  d.maxtail = 0;
+  d.tail_bytes = 0;
+  for (int l = 0; l <= MG_MAXL; ++l) d.setup_b[l] = d.smooth_b[l] = d.up_b[l] = 0;
+  for (int x = 0; x < n; ++x) {
+    const MGInfo &mg = hs[x]->mg;
+    d.maxL = mg.L > d.maxL ? mg.L : d.maxL;
+    d.maxtail = mg.tail > d.maxtail ? mg.tail : d.maxtail;
+    d.tail_bytes = mg.tail_bytes > d.tail_bytes ? mg.tail_bytes : d.tail_bytes;
+    for (int l = 1; l <= mg.L; ++l) {
+      const int b = lvl_blocks(mg.lv[l].nc);
+      d.setup_b[l] = b > d.setup_b[l] ? b : d.setup_b[l];
+    }
+    for (int l = 1; l < mg.tail; ++l) {
+      const int bs = smooth_blocks(mg, l, dim), bu = up_blocks(mg, l);
+      d.smooth_b[l] = bs > d.smooth_b[l] ? bs : d.smooth_b[l];
+      d.up_b[l] = bu > d.up_b[l] ? bu : d.up_b[l];
+    }
+  }
+}
+
+template <typename R>
+void launch_mg_setup_b(const MGBatch &B) {
+  for (int di = 0; di < 2; ++di) {
+    const MGBatch::Dim &d = B.dim[di];
+    if (!d.n) continue;
+    for (int l = 1; l <= d.maxL; ++l)
+      hipLaunchKernelGGL((k_mg_setup_b<R, R>), dim3((unsigned)(d.n * d.setup_b[l])), dim3(BLOCK), 0, B.stream, B.slots,
+                         d.act, d.setup_b[l], l);
+    hipLaunchKernelGGL(k_mg_coarse_inv_b<R>, dim3((unsigned)d.n), dim3(MG_INV_THREADS), 0, B.stream, B.slots, d.act);
+  }
+}
+
+template <typename R>
+void launch_mg_dir_b(const MGBatch &B, int it) {
+  hipLaunchKernelGGL((k_mgcg_dir_b<R, FINE_NB<R>>), dim3((unsigned)B.nblocks), dim3(BLOCK), 0, B.stream, B.slots,
+                     B.btab, it);
+}
+
+template <int DIM, typename R>
+static void vcycle_levels_b(const MGBatch &B, const MGBatch::Dim &d) {
+  for (int l = 1; l < d.maxtail; ++l)
+    if (d.smooth_b[l])
+      hipLaunchKernelGGL((k_mg_smooth_b<DIM, R>), dim3((unsigned)(d.n * d.smooth_b[l])), dim3(BLOCK), 0, B.stream,
+                         B.slots, d.act, d.smooth_b[l], l);
+  hipLaunchKernelGGL((k_mg_tail_b<DIM, R>), dim3((unsigned)d.n), dim3(MG_TAIL_THREADS), (size_t)d.tail_bytes, B.stream,
+                     B.slots, d.act);
+  for (int l = d.maxtail - 1; l >= 1; --l)
+    if (d.up_b[l])
+      hipLaunchKernelGGL((k_mg_up_b<DIM, R>), dim3((unsigned)(d.n * d.up_b[l])), dim3(BLOCK), 0, B.stream, B.slots,
+                         d.act, d.up_b[l], l);
+}
+
+template <typename R>
+void launch_mg_cycle_part_b(const MGBatch &B, int it, int part) {
+  const dim3 fg((unsigned)B.nblocks), fb(BLOCK);
+  if (part == 0) {
+    hipLaunchKernelGGL((k_mg_fine_down_b<R, FINE_NB<R>>), fg, fb, 0, B.stream, B.slots, B.btab, it);
+  } else if (part == 1) {
+    if (B.dim[0].n) vcycle_levels_b<2, R>(B, B.dim[0]);
+    if (B.dim[1].n) vcycle_levels_b<3, R>(B, B.dim[1]);
+  } else {
+    hipLaunchKernelGGL((k_mg_fine_up_b<R, FINE_NB<R>>), fg, fb, 0, B.stream, B.slots, B.btab, it);
+  }
+}
+
+template void launch_mg_setup_b<double>(const MGBatch &);
+template void launch_mg_setup_b<float>(const MGBatch &);
+template void launch_mg_dir_b<double>(const MGBatch &, int);
+template void launch_mg_dir_b<float>(const MGBatch &, int);
+template void launch_mg_cycle_part_b<double>(const MGBatch &, int, int);
+template void launch_mg_cycle_part_b<float>(const MGBatch &, int, int);
 
 template void launch_mg_setup<double>(const Slot &, hipStream_t);
 template void launch_mg_setup<float>(const Slot &, hipStream_t);

@@ -155,6 +155,33 @@ template <typename R> void launch_mg_setup(const Slot &hs, hipStream_t st);
 // consecutive regions; mg_part_launches gives their number)
 template <typename R> void launch_mg_cycle_part(const Slot &hs, const Launch &L, int it, int part, int mode,
                                                 unsigned long long *ts = nullptr);
+
+// Batched multigrid launches over slots of the serving engine (host view):
+// the device slot table, the fine-level block table of the batch's slots, and
+// per dimension the device list of its slots with the largest workgroup count
+// each level's launch needs over them.
+struct MGBatch {
+  const Slot *slots = nullptr;   // device slot table
+  const int2 *btab = nullptr;    // fine-level block table of the batch's slots (device)
+  int nblocks = 0;               // its entries
+  hipStream_t stream = nullptr;
+  struct Dim {
+    const int *act = nullptr;    // device list of the slot indices of this dimension
+    int n = 0;
+    int maxL = 0;                // deepest coarsest level
+    int maxtail = 0;             // latest tail start
+    int tail_bytes = 0;          // largest tail block (LDS of the tail launch)
+    int setup_b[MG_MAXL + 1];    // per level: workgroups per slot of the setup launch
+    int smooth_b[MG_MAXL + 1];   // of the pre-smoothing launch (0: no slot runs it)
+    int up_b[MG_MAXL + 1];       // of the prolongation launch
+  } dim[2];                      // 2D, 3D
+};
+// fill one dimension's level figures from host copies of its slots
+void mg_batch_levels(MGBatch::Dim &d, const Slot *const *hs, int n, int dim);
+template <typename R> void launch_mg_setup_b(const MGBatch &B);
+template <typename R> void launch_mg_dir_b(const MGBatch &B, int it);
+// part as in launch_mg_cycle_part; the FP64 update reads each slot's mode
+template <typename R> void launch_mg_cycle_part_b(const MGBatch &B, int it, int part);
 inline int mg_part_launches(const Slot &hs, int part) { return part == 1 ? 2 * (hs.mg.tail - 1) + 1 : 1; }
 template <typename R> void launch_mg_dir(const Slot &hs, const Launch &L, int it, unsigned long long *ts = nullptr);
 void launch_gather_states(const Launch &L, int nslots, SlotState *out);

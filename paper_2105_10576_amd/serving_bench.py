@@ -1,7 +1,8 @@
 """Batched-serving measurement: the seeded 64-request mix of 2D channel and
 micromodel relaxation requests (cases.serving_requests), served by the GPU
 engine with admission by HBM footprint.  A burst pass (all requests at t=0)
-measures the saturated throughput; a second pass draws exponential
+measures the saturated throughput (multigrid-preconditioned solves by
+default); a second pass draws exponential
 inter-arrival gaps (seed 4) at 0.8 of that rate.  Reports p50/p99 latency by
 nearest rank (p99 of 64 samples is the maximum) and aggregate Mcell-iter/s
 (one viscous + k_f relaxation iterations per cell and request)."""
@@ -14,9 +15,10 @@ from .serve import Server
 
 
 def run(n_requests=64, max_slots=32, heap_mb=512, precision=oscar.MIXED, max_iters=None, rate_frac=0.8,
-        device="cuda:0", log=None):
+        device="cuda:0", log=None, precond=oscar.PC_MG):
     reqs = cases.serving_requests(n=n_requests)
     for c in reqs:
+        c["precond"] = precond
         if max_iters is not None:
             c["max_iters"] = min(c["max_iters"], max_iters)
         if precision == oscar.MIXED:
@@ -49,6 +51,7 @@ def run(n_requests=64, max_slots=32, heap_mb=512, precision=oscar.MIXED, max_ite
                                            "mcell_iter_per_s", "peak_resident_bytes")}
     out["poisson"]["rate_per_s"] = lam
     out["requests"] = n_requests
+    out["precond"] = "multigrid" if precond == oscar.PC_MG else "jacobi"
     out["max_slots"] = max_slots
     out["heap_mb"] = heap_mb
     out["mean_k_f"] = sum(r["k_f"] for r in res if r and not r["rejected"]) / max(1, summ["served"])

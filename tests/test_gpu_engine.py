@@ -112,3 +112,74 @@ def test_serving_loop_end_to_end():
     for r in res:
         a = _run_alone(oscar, reqs[r["request"]], 0)
         assert np.array_equal(r["alpha"], a["alpha"]) and np.array_equal(r["U"], a["U"])
+
+
+def _mg(c):
+    c = dict(c)
+    c["precond"] = 1
+    return c
+
+
+def _small_3d():
+    c = cases.constricted_channel(nx=32, ny=16, nz=16, max_iters=3)
+    c["pcg_rtol"] = 1e-8
+    return c
+
+
+@pytest.mark.parametrize("which", ["2d_fp64", "3d_mixed"])
+def test_engine_multigrid_matches_context(which):
+    """A multigrid request through the engine (batched multigrid launches)
+    equals the same request through a context bitwise: the same kernel
+    bodies, the same block-to-cell assignment and the same device-side
+    convergence decisions."""
+    from paper_2105_10576_amd import oscar
+    if which == "2d_fp64":
+        c, precision = _mg(_reqs()[0]), 0
+    else:
+        c, precision = _mg(_small_3d()), 1
+    print("engine vs context, multigrid", which, flush=True)
+    g = oscar.Oscar(c, precision=precision, precond=oscar.PC_MG)
+    g.viscous_step(c["dt_vd"])
+    rc, kf, E = g.capillary_relax(c["dt_vd"], c["n_sub"], c["max_iters"], c["tol"])
+    out = _run_alone(oscar, c, precision)
+    assert out["k_f"] == kf
+    for f in ("alpha", "p", "U"):
+        assert np.array_equal(out[f], g.get(f)), f
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_multigrid_and_jacobi_requests_share_an_engine(precision):
+    """Jacobi and multigrid requests, 2D and 3D, admitted while others run:
+    each result equals the request run alone, bitwise."""
+    from paper_2105_10576_amd import oscar
+    r = _reqs()
+    reqs = [_mg(r[0]), r[1], _mg(r[2]), _mg(_small_3d()), r[3]]
+    if precision == 1:
+        for c in reqs:
+            c["pcg_rtol"] = 1e-8
+    print("mixed engine, precision", precision, flush=True)
+    alone = [_run_alone(oscar, c, precision) for c in reqs]
+    heap = sum(oscar.workspace_size(c, precision) for c in reqs) + (1 << 20)
+    e = oscar.Engine(8, heap, precision=precision)
+    slots = {}
+    slots[e.admit(reqs[0])] = 0
+    slots[e.admit(reqs[1])] = 1
+    slots[e.admit(reqs[3])] = 3
+    e.run(2)
+    slots[e.admit(reqs[2])] = 2
+    e.run(1)
+    slots[e.admit(reqs[4])] = 4
+    got = {}
+    for _ in range(10000):
+        done, act = e.poll()
+        for s in done:
+            got[slots[s]] = e.fetch(s)
+            e.release(s)
+        if len(got) == len(reqs):
+            break
+        e.run(1)
+    assert len(got) == len(reqs)
+    for i, a in enumerate(alone):
+        assert got[i]["k_f"] == a["k_f"], i
+        for f in ("alpha", "p", "U"):
+            assert np.array_equal(got[i][f], a[f]), (i, f)
