@@ -265,6 +265,40 @@ __device__ __forceinline__ void get_totals(const Slot &s, int ch, double (&v)[M]
   block_reduce<MAXMASK>(v);
 }
 
+// The same totals in two steps, so that their loads can be issued ahead of
+// other work: prefetch_totals loads a thread's partials (a slot has at most
+// 4 x BLOCK blocks), finish_totals sums them in the order get_totals uses
+// and reduces over the block.  A thread's missing partials read as zero
+// (adding +0 leaves its sum unchanged).
+template <int M>
+struct Partials {
+  double x[M][4];
+};
+template <int M>
+__device__ __forceinline__ void prefetch_totals(const Slot &s, int ch, Partials<M> &p) {
+  const int nb = s.nblocks;
+  const double *base = s.part + (int)(ch * NVAL) * nb;
+#pragma unroll
+  for (int m = 0; m < M; ++m)
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int b = (int)threadIdx.x + u * BLOCK;
+      const double v = base[m * nb + (b < nb ? b : 0)];
+      p.x[m][u] = b < nb ? v : 0.0;
+    }
+}
+template <int M>
+__device__ __forceinline__ void finish_totals(const Partials<M> &p, double (&v)[M]) {
+#pragma unroll
+  for (int m = 0; m < M; ++m) {
+    double t = 0.0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) t = t + p.x[m][u];
+    v[m] = t;
+  }
+  block_reduce<0u>(v);
+}
+
 // ---------------------------------------------------------------------------
 // mixture properties
 // ---------------------------------------------------------------------------

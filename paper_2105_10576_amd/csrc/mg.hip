@@ -654,15 +654,28 @@ __device__ __forceinline__ bool mgcg_dir_body(const Slot &s, int lb, int it) {
   const uint8_t *flags = s.flags;
   const T *z = (const T *)s.cw[0], *dold = first ? z : (const T *)s.cs[(it + 1) & 1];
   T *dn = (T *)s.cs[it & 1], *q = (T *)s.cp;
+  // The FP32 inner solve of the mixed path forms q = A d as A z + beta q_old
+  // (the same vector in exact arithmetic; the outer FP64 refinement absorbs
+  // the rounding the recurrence adds), which needs d_old and q_old at the
+  // cell only; the FP64 solve applies A to d itself.
+  constexpr bool rec = sizeof(T) == 4;
   struct Op {
     Cell c;
     uint8_t fl;
-    T z[7], o[7];   // z and d_old across faces 0..5, then at the cell
+    T z[7], o[7];   // z and d_old across faces 0..5, then at the cell (rec: d_old at the cell only)
     R ra[7];        // rAU likewise
+    T qo;           // rec: q_old at the cell
   };
   bool stop = false;
   T be = (T)0;
   double red[1] = {0.0};
+  Partials<2> pt;   // the previous cycle's reduction, loaded ahead of the stencil operands
+  prefetch_totals(s, CH_CG0 + ((it + 1) & 1), pt);
+  // the scalars of the convergence test and of beta, read with them (and
+  // combined only where they are used)
+  const double tgt = st->tgt, rtol = ctl.rtol, bn = st->bn;
+  const int max_it = ctl.max_it;
+  const double gam_old = st->gam[(it + 1) & 1];   // gamma of iteration it - 1 (unused when it = 0)
   batched<NB, Op>(
       lb * BLOCK + (int)threadIdx.x, G.nblocks * BLOCK, G.nc,
       [&](Op &o, int g) {
@@ -679,22 +692,23 @@ __device__ __forceinline__ bool mgcg_dir_body(const Slot &s, int lb, int it) {
         o.z[6] = ldo(z, oP);
         o.o[6] = ldo(dold, oP);
         o.ra[6] = ldo(rAU, oP);
+        if constexpr (rec) o.qo = ldo((const T *)q, oP);
 #pragma unroll
         for (int f = 0; f < 6; ++f) {
           o.z[f] = ldo(z, on[f]);
-          o.o[f] = ldo(dold, on[f]);
+          if constexpr (!rec) o.o[f] = ldo(dold, on[f]);
           o.ra[f] = ldo(rAU, on[f]);
         }
       },
       [&]() {
         double v[2];
-        get_totals<0u>(s, CH_CG0 + ((it + 1) & 1), v);   // written by the cycle of iteration it - 1
+        finish_totals(pt, v);   // written by the cycle of iteration it - 1
         const double gam = v[0];
         double beta = 0.0;
         if (it > 0) {
           double rn = sqrt(v[1]);
-          bool conv = rn <= (mixed ? st->tgt : ctl.rtol * st->bn);
-          bool cap = !conv && it >= ctl.max_it;
+          bool conv = rn <= (mixed ? tgt : rtol * bn);
+          bool cap = !conv && it >= max_it;
           if (conv || cap) {
             if (lb == 0 && threadIdx.x == 0) {
               st->rn = rn;
@@ -705,7 +719,7 @@ __device__ __forceinline__ bool mgcg_dir_body(const Slot &s, int lb, int it) {
             stop = true;
             return false;
           }
-          beta = gam / st->gam[(it - 1) & 1];
+          beta = gam / gam_old;
           if (lb == 0 && threadIdx.x == 0) st->rn = rn;
         }
         if (lb == 0 && threadIdx.x == 0) st->gam[it & 1] = gam;
@@ -717,12 +731,23 @@ __device__ __forceinline__ bool mgcg_dir_body(const Slot &s, int lb, int it) {
         auto dv = [&](int m) -> T { return o.z[m] + be * o.o[m]; };
         const T dP = dv(6);
         T xn[6], rn[6];
+        T qq;
+        if constexpr (rec) {
 #pragma unroll
-        for (int f = 0; f < 6; ++f) {
-          xn[f] = dv(f);
-          rn[f] = (T)o.ra[f];
+          for (int f = 0; f < 6; ++f) {
+            xn[f] = o.z[f];
+            rn[f] = (T)o.ra[f];
+          }
+          const T Az = matvec_pre<T>(G, o.c, o.fl, o.z[6], (T)o.ra[6], xn, rn);
+          qq = first ? Az : Az + be * o.qo;
+        } else {
+#pragma unroll
+          for (int f = 0; f < 6; ++f) {
+            xn[f] = dv(f);
+            rn[f] = (T)o.ra[f];
+          }
+          qq = matvec_pre<T>(G, o.c, o.fl, dP, (T)o.ra[6], xn, rn);
         }
-        const T qq = matvec_pre<T>(G, o.c, o.fl, dP, (T)o.ra[6], xn, rn);
         const unsigned oP = (unsigned)o.c.P * sizeof(T);
         sto(dn, oP, dP);
         sto(q, oP, qq);
@@ -788,6 +813,8 @@ __device__ __forceinline__ void mg_fine_down_body(const Slot &s, int lb, int it,
     T d, x;                // search direction and unknown at the cell (read also when unused)
   };
   T al = (T)0;
+  Partials<1> pt;   // <d,q> of the search-direction launch, loaded ahead of the stencil operands
+  prefetch_totals(s, CH_DQ, pt);   // (unused by the initial cycle; loading it anyway avoids a branch)
   batched<NB, Op>(
       lb * BLOCK + (int)threadIdx.x, G.nblocks * BLOCK, total,
       [&](Op &o, int tau) {
@@ -830,7 +857,7 @@ __device__ __forceinline__ void mg_fine_down_body(const Slot &s, int lb, int it,
       [&]() {
         if (!upd) return true;
         double v[1];
-        get_totals<0u>(s, CH_DQ, v);
+        finish_totals(pt, v);
         al = (T)(st->gam[it & 1] / v[0]);
         if (lb == 0 && threadIdx.x == 0) {
           st->it = it + 1;
