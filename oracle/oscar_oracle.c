@@ -44,6 +44,7 @@
 struct orc {
   orc_params prm;
   int d;                 /* dimension */
+  int mules_iter;        /* limiting passes of the alpha transport */
   long nx, ny, nz, nc;   /* cells */
   long nf[3];            /* faces per direction */
   long nftot;
@@ -65,6 +66,7 @@ struct orc {
   double *phiH;      /* nftot */
   double *rhs, *invD, *r, *z, *dvec, *q, *tmp, *tmp2;   /* nc */
   double *FL, *Aflux, *Rp, *Rm;   /* nftot, nftot, nc, nc */
+  double *lam;                    /* nftot: face limiter of the last pass */
   orc_stats_t st;
 };
 
@@ -248,9 +250,58 @@ static double st_face(const orc_t *o, long lo, long hi) {
 /* ------------------------------------------------------------------------ */
 /* Explicit alpha transport (Eq. alphaExp, Eq. VOFd, Eq. VOFc): upwind flux   */
 /* plus a van Leer (1974) high-order flux with interface compression,        */
-/* blended by a single Zalesak (1979) flux-corrected-transport limiter that  */
-/* keeps alpha inside local [0,1]-clipped bounds.                            */
+/* blended by a Zalesak (1979) flux-corrected-transport limiter that keeps   */
+/* alpha inside local [0,1]-clipped bounds.  With mules_iter = M > 1 the     */
+/* limiting is iterated (iterative flux correction: Schaer & Smolarkiewicz   */
+/* 1996; Kuzmin & Moeller 2005): pass m limits the antidiffusive flux that   */
+/* the passes before it left unused, (1 - lambda) A, against the same local  */
+/* bounds, starting from the state the previous pass produced.               */
 /* ------------------------------------------------------------------------ */
+
+/* one further limiting pass: cur holds the state after the previous pass,
+ * o->Aflux the antidiffusive flux still unused, o->lam the previous face
+ * limiter; the new state goes to nxt */
+static void limit_again(orc_t *o, double dtV, double Vdt, const double *cur, double *nxt) {
+  const double *ab = o->alpha_old;   /* the bounds are those of the first pass */
+  for (long fi = 0; fi < o->nftot; ++fi) o->Aflux[fi] = (1.0 - o->lam[fi]) * o->Aflux[fi];
+  FOR_CELLS(o, P, i, j, k) {
+    o->Rp[P] = 0.0;
+    o->Rm[P] = 0.0;
+    if (o->solid[P]) continue;
+    double Pp = 0.0, Pm = 0.0, amax = ab[P], amin = ab[P];
+    for (int f = 0; f < 2 * o->d; ++f) {
+      cface c = cell_face(o, i, j, k, f);
+      if (c.type != F_INT) continue;   /* only interior faces carry antidiffusive flux */
+      double sA = c.s * o->Aflux[c.fi];
+      Pp = Pp + (sA < 0.0 ? -sA : 0.0);
+      Pm = Pm + (sA > 0.0 ? sA : 0.0);
+      if (ab[c.nb] > amax) amax = ab[c.nb];
+      if (ab[c.nb] < amin) amin = ab[c.nb];
+    }
+    if (amax > 1.0) amax = 1.0;
+    if (amin < 0.0) amin = 0.0;
+    double Qp = Vdt * (amax - cur[P] > 0.0 ? amax - cur[P] : 0.0);
+    double Qm = Vdt * (cur[P] - amin > 0.0 ? cur[P] - amin : 0.0);
+    o->Rp[P] = Pp > 0.0 ? (Qp / Pp < 1.0 ? Qp / Pp : 1.0) : 0.0;
+    o->Rm[P] = Pm > 0.0 ? (Qm / Pm < 1.0 ? Qm / Pm : 1.0) : 0.0;
+  }
+  FOR_CELLS(o, P, i, j, k) {
+    if (o->solid[P]) continue;
+    double acc = 0.0;
+    for (int f = 0; f < 2 * o->d; ++f) {
+      cface c = cell_face(o, i, j, k, f);
+      if (c.type != F_INT) continue;
+      long lo = c.s > 0.0 ? P : c.nb, hi = c.s > 0.0 ? c.nb : P;
+      double Af = o->Aflux[c.fi];
+      double x1 = Af >= 0.0 ? o->Rm[lo] : o->Rp[lo];
+      double x2 = Af >= 0.0 ? o->Rp[hi] : o->Rm[hi];
+      double lam = x1 < x2 ? x1 : x2;
+      o->lam[c.fi] = lam;
+      acc = acc + c.s * (lam * Af);
+    }
+    nxt[P] = cur[P] - dtV * acc;
+  }
+}
 
 static int advect(orc_t *o, const double *phi, double dt) {
   const double dtV = dt / o->V, Vdt = o->V / dt;
@@ -349,9 +400,14 @@ static int advect(orc_t *o, const double *phi, double dt) {
       } else {
         bflux = bflux + c.s * o->FL[c.fi];
       }
+      o->lam[c.fi] = lam;
       acc = acc + c.s * (o->FL[c.fi] + lam * o->Aflux[c.fi]);
     }
     o->tmp[P] = a[P] - dtV * acc;
+  }
+  for (int m = 2; m <= o->mules_iter; ++m) {
+    limit_again(o, dtV, Vdt, o->tmp, o->tmp2);
+    FOR_CELLS(o, P, i, j, k) if (!o->solid[P]) o->tmp[P] = o->tmp2[P];
   }
   FOR_CELLS(o, P, i, j, k) {
     if (o->solid[P]) continue;
@@ -856,11 +912,12 @@ orc_t *orc_create(const orc_params *prm, const uint8_t *mask, const double *alph
   if (prm->dim != 2 && prm->dim != 3) return NULL;
   if (prm->nx < 1 || prm->ny < 1 || prm->nz < 1 || (prm->dim == 2 && prm->nz != 1)) return NULL;
   if (!(prm->h > 0.0) || !(prm->rho1 > 0.0) || !(prm->rho2 > 0.0) || !(prm->mu1 > 0.0) || !(prm->mu2 > 0.0) ||
-      prm->sigma < 0.0 || prm->n_corr < 1)
+      prm->sigma < 0.0 || prm->n_corr < 1 || prm->mules_iter < 0 || prm->mules_iter > 8)
     return NULL;
   orc_t *o = (orc_t *)calloc(1, sizeof(orc_t));
   o->prm = *prm;
   o->d = prm->dim;
+  o->mules_iter = prm->mules_iter > 0 ? prm->mules_iter : 1;
   o->nx = prm->nx; o->ny = prm->ny; o->nz = prm->nz;
   o->nc = o->nx * o->ny * o->nz;
   o->nf[0] = (o->nx + 1) * o->ny * o->nz;
@@ -894,6 +951,7 @@ orc_t *orc_create(const orc_params *prm, const uint8_t *mask, const double *alph
   o->rhs = zalloc(nc); o->invD = zalloc(nc); o->r = zalloc(nc); o->z = zalloc(nc);
   o->dvec = zalloc(nc); o->q = zalloc(nc); o->tmp = zalloc(nc); o->tmp2 = zalloc(nc);
   o->FL = zalloc(nf); o->Aflux = zalloc(nf); o->Rp = zalloc(nc); o->Rm = zalloc(nc);
+  o->lam = zalloc(nf);
   long nfl = 0;
   double m = 0.0;
   for (long P = 0; P < nc; ++P) {
@@ -913,7 +971,7 @@ void orc_destroy(orc_t *o) {
   void *ptrs[] = {o->solid, o->alpha, o->alpha_old, o->U_vd, o->U_cr, o->U_sum, o->U, o->p_vd, o->p_cr,
                   o->p, o->phi_vd, o->phi_vd_prev, o->phi_cr, o->kappa, o->nhatf, o->grad, o->gradU,
                   o->Fmass, o->phic, o->aP, o->rAU, o->b, o->HbyA, o->phiH, o->rhs, o->invD, o->r,
-                  o->z, o->dvec, o->q, o->tmp, o->tmp2, o->FL, o->Aflux, o->Rp, o->Rm};
+                  o->z, o->dvec, o->q, o->tmp, o->tmp2, o->FL, o->Aflux, o->Rp, o->Rm, o->lam};
   for (size_t x = 0; x < sizeof(ptrs) / sizeof(ptrs[0]); ++x) free(ptrs[x]);
   free(o);
 }

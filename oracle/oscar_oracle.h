@@ -47,6 +47,7 @@ typedef struct {
   int32_t n_corr;               /* PISO correctors */
   double pcg_rtol;
   int32_t pcg_max_it;
+  int32_t mules_iter;           /* limiting passes of the alpha transport, 1..8 (0 = 1) */
 } orc_params;
 
 typedef struct {

@@ -17,7 +17,7 @@ class _Params(C.Structure):
                 ("h", C.c_double), ("rho1", C.c_double), ("mu1", C.c_double), ("rho2", C.c_double),
                 ("mu2", C.c_double), ("sigma", C.c_double), ("theta_deg", C.c_double),
                 ("bc", C.c_int32 * 6), ("u_inlet", C.c_double), ("n_corr", C.c_int32),
-                ("pcg_rtol", C.c_double), ("pcg_max_it", C.c_int32)]
+                ("pcg_rtol", C.c_double), ("pcg_max_it", C.c_int32), ("mules_iter", C.c_int32)]
 
 
 class _Stats(C.Structure):
@@ -79,6 +79,7 @@ class Oracle:
             setattr(p, k, float(c[k]))
         for i in range(6):
             p.bc[i] = int(c["bc"][i])
+        p.mules_iter = int(c.get("mules_iter", 1))
         self._mask = np.ascontiguousarray(c["mask"], dtype=np.uint8)
         a0 = np.ascontiguousarray(c["alpha0"], dtype=np.float64)
         self.h = lib().orc_create(C.byref(p), self._mask.ctypes.data_as(C.POINTER(C.c_uint8)), _dp(a0))

@@ -292,3 +292,171 @@ def test_transport_of_a_front():
     band = ((al > 0.01) & (al < 0.99)).sum(axis=1)
     assert band.max() <= 3
     assert (al.sum(axis=1) - 8).mean() == pytest.approx(30 * 0.4, rel=1e-9)
+
+
+# ---------------------------------------------------------------------------
+# iterative limiting (mules_iter > 1): passes after the first limit the unused
+# part (1 - lambda) A of the antidiffusive flux against the first pass's local
+# bounds (iterative flux correction, Schaer & Smolarkiewicz 1996; Kuzmin &
+# Moeller 2005)
+# ---------------------------------------------------------------------------
+
+def _transport_case(nx, ny, a, bc, **extra):
+    return cases._case("transport", 2, nx, ny, 1, 1e-5, cases.WATER, cases.OIL, 0.0, 90.0, bc, 0.0,
+                       np.zeros(nx * ny, np.uint8), a, 1e-6, 1, 1, 1e-6, **extra)
+
+
+def _flux(nx, ny, h, u, v):
+    phi = np.zeros((nx + 1) * ny + nx * (ny + 1))
+    phi[: (nx + 1) * ny] = u * h
+    phi[(nx + 1) * ny:] = v * h
+    return phi
+
+
+def _transport(o, phi, dt):
+    o.set("phi_cr", phi)
+    rc, kf, E = o.capillary_relax(dt, 1, 1, 0.0)
+    assert rc == 0
+    return o.get("alpha")
+
+
+def _sharp_front(nx=40, ny=1, x0=12.3, w=0.6):
+    x = np.arange(nx) + 0.5
+    return np.tile(0.5 * (1 - np.tanh((x - x0) / w)), (ny, 1))
+
+
+def test_iterative_limiter_one_pass_is_the_default():
+    """mules_iter = 1 (and the unset value 0) is exactly the single-pass
+    limiter: bit-identical alpha after ten transport steps."""
+    nx, ny, h, u = 40, 1, 1e-5, 1e-3
+    c = _transport_case(nx, ny, _sharp_front(nx, ny), [cases.BC_INLET, cases.BC_OUTLET, cases.BC_WALL,
+                                                      cases.BC_WALL, 0, 0])
+    phi, dt = _flux(nx, ny, h, u, 0.0), 0.5 * h / u
+    runs = [Oracle(c), Oracle(c, mules_iter=1), Oracle(c, mules_iter=0)]
+    for _ in range(10):
+        out = [_transport(o, phi, dt) for o in runs]
+    assert np.array_equal(out[0], out[1]) and np.array_equal(out[0], out[2])
+
+
+def test_iterative_limiter_rejects_out_of_range_pass_counts():
+    c = _transport_case(8, 1, _sharp_front(8, 1, 4.0), [cases.BC_INLET, cases.BC_OUTLET, cases.BC_WALL,
+                                                        cases.BC_WALL, 0, 0])
+    for bad in (-1, 9):
+        with pytest.raises(ValueError):
+            Oracle(c, mules_iter=bad)
+
+
+@pytest.mark.parametrize("passes", [2, 3, 8])
+def test_iterative_limiter_local_bounds_and_conservation(passes):
+    """A square of phase 1 carried by a uniform diagonal flux (Courant 0.3 +
+    0.3) for twelve steps with `passes` limiting passes.  Every step keeps
+    each cell inside [min, max] of itself and its neighbours before the step
+    (clipped to [0, 1]) -- the local discrete maximum principle that every
+    pass must respect because its Q+- are taken from the current state --
+    and the phase mass changes by exactly the zero-gradient boundary flux
+    computed here from the state before the step.  Catches Q+- taken from the
+    low-order state instead of the current one (overshoot), bounds taken
+    from the intermediate state (wider bounds), and a face limiter that is
+    not shared by the two cells of a face (mass)."""
+    nx = ny = 24
+    h, u = 1e-5, 1e-3
+    a = np.zeros((ny, nx))
+    a[5:12, 4:11] = 1.0
+    a[5:12, 11] = 0.4
+    bc = [cases.BC_INLET, cases.BC_OUTLET, cases.BC_INLET, cases.BC_OUTLET, 0, 0]
+    c = _transport_case(nx, ny, a, bc, mules_iter=passes)
+    o = Oracle(c)
+    dt = 0.3 * h / u
+    phi = _flux(nx, ny, h, u, u)
+    prev = a.copy()
+    for _ in range(12):
+        new = _transport(o, phi, dt).reshape(ny, nx)
+        pad_hi = np.pad(prev, 1, constant_values=-np.inf)
+        pad_lo = np.pad(prev, 1, constant_values=np.inf)
+        hi = np.maximum.reduce([pad_hi[1:-1, 1:-1], pad_hi[:-2, 1:-1], pad_hi[2:, 1:-1],
+                                pad_hi[1:-1, :-2], pad_hi[1:-1, 2:]])
+        lo = np.minimum.reduce([pad_lo[1:-1, 1:-1], pad_lo[:-2, 1:-1], pad_lo[2:, 1:-1],
+                                pad_lo[1:-1, :-2], pad_lo[1:-1, 2:]])
+        hi, lo = np.minimum(hi, 1.0), np.maximum(lo, 0.0)
+        assert (new <= hi + 1e-14).all() and (new >= lo - 1e-14).all()
+        # outflow through x+ and y+ minus inflow through x- and y- (alpha of
+        # the boundary cell), in units of cell volumes: Courant 0.3 per face
+        bnd = 0.3 * (prev[:, -1].sum() + prev[-1, :].sum() - prev[:, 0].sum() - prev[0, :].sum())
+        assert new.sum() - prev.sum() == pytest.approx(-bnd, abs=1e-12 * a.sum())
+        prev = new
+
+
+def test_iterative_limiter_moves_monotonically_toward_the_high_order_flux():
+    """One transport step of a sharp, non-increasing front carried in +x
+    (Courant 0.5), from the same state with 1..8 passes.  On such a front
+    every antidiffusive flux points back up the gradient (van Leer
+    steepening and compression alike), so the antidiffusive part moves the
+    centroid of alpha by dt/V * h * sum_f Lambda_f A_f <= 0, where Lambda_f is
+    the share of A_f applied so far; each further pass adds a non-negative
+    share of what is left.  So the centroid is non-increasing in the number
+    of passes, and strictly lower with two passes than with one here, where
+    the first pass limits the front.  Catches a pass that applies nothing, or
+    one that takes the applied share back."""
+    nx, ny, h, u = 40, 1, 1e-5, 1e-3
+    a = _sharp_front(nx, ny)
+    bc = [cases.BC_INLET, cases.BC_OUTLET, cases.BC_WALL, cases.BC_WALL, 0, 0]
+    phi, dt = _flux(nx, ny, h, u, 0.0), 0.5 * h / u
+    x = np.arange(nx) + 0.5
+    cen, mass = [], []
+    for m in range(1, 9):
+        al = _transport(Oracle(_transport_case(nx, ny, a, bc, mules_iter=m)), phi, dt)
+        mass.append(al.sum())
+        cen.append(float((x * al).sum()))
+    assert max(mass) - min(mass) <= 1e-13 * mass[0]
+    assert all(b <= a_ + 1e-12 for a_, b in zip(cen, cen[1:])), cen
+    assert cen[1] < cen[0] - 1e-4, cen
+
+
+def test_iterative_limiter_changes_nothing_when_nothing_is_left():
+    """A gentle ramp (alpha 0.7 -> 0.3 over 40 cells) at Courant 0.01: the
+    first pass applies every antidiffusive flux in full except at the inlet
+    cell, whose bounds admit no change at all, so nothing is left for later
+    passes and 2, 4 or 8 passes give bit-identical states to one pass, over
+    five steps.  Catches a later pass that re-applies the full antidiffusive
+    flux instead of the unused part."""
+    nx, ny, h, u = 40, 1, 1e-5, 1e-3
+    a = np.tile(np.linspace(0.7, 0.3, nx), (ny, 1))
+    bc = [cases.BC_INLET, cases.BC_OUTLET, cases.BC_WALL, cases.BC_WALL, 0, 0]
+    phi, dt = _flux(nx, ny, h, u, 0.0), 0.01 * h / u
+    runs = [Oracle(_transport_case(nx, ny, a, bc, mules_iter=m)) for m in (1, 2, 4, 8)]
+    for _ in range(5):
+        out = [_transport(o, phi, dt) for o in runs]
+        assert not np.array_equal(out[0], a.reshape(-1))
+        for al in out[1:]:
+            assert np.array_equal(al, out[0])
+
+
+@pytest.mark.parametrize("passes", [2, 8])
+def test_iterative_limiter_local_bounds_on_rough_fields(passes):
+    """One transport step of rough 12 x 12 fields (uniform random, and random
+    multiples of 1/4) under random diagonal fluxes (Courant up to 0.45 per
+    direction): the new state stays within the clipped [min, max] of each
+    cell's neighbourhood before the step, to 1e-14.  Bounds recomputed from
+    an intermediate state would let later passes overshoot by up to 0.2
+    here."""
+    nx = ny = 12
+    h, u = 1e-5, 1e-3
+    bc = [cases.BC_INLET, cases.BC_OUTLET, cases.BC_INLET, cases.BC_OUTLET, 0, 0]
+    for seed in range(12):
+        rng = np.random.default_rng(seed)
+        a = rng.random((ny, nx))
+        if seed % 2:
+            a = np.round(a * 4) / 4
+        cx, cy = rng.uniform(0.05, 0.45, 2)
+        o = Oracle(_transport_case(nx, ny, a, bc, mules_iter=passes))
+        new = _transport(o, _flux(nx, ny, h, cx * u, cy * u), h / u).reshape(ny, nx)
+        pad_hi = np.pad(a, 1, constant_values=-np.inf)
+        pad_lo = np.pad(a, 1, constant_values=np.inf)
+        hi = np.maximum.reduce([pad_hi[1:-1, 1:-1], pad_hi[:-2, 1:-1], pad_hi[2:, 1:-1],
+                                pad_hi[1:-1, :-2], pad_hi[1:-1, 2:]])
+        lo = np.minimum.reduce([pad_lo[1:-1, 1:-1], pad_lo[:-2, 1:-1], pad_lo[2:, 1:-1],
+                                pad_lo[1:-1, :-2], pad_lo[1:-1, 2:]])
+        assert (new <= np.minimum(hi, 1.0) + 1e-14).all(), seed
+        assert (new >= np.maximum(lo, 0.0) - 1e-14).all(), seed
+        bnd = cx * (a[:, -1].sum() - a[:, 0].sum()) + cy * (a[-1, :].sum() - a[0, :].sum())
+        assert new.sum() - a.sum() == pytest.approx(-bnd, abs=1e-12 * a.size)
