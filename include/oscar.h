@@ -101,8 +101,12 @@ typedef struct {
   int32_t n_corr;                   /* PISO correctors per step (the paper uses 3), >= 1 */
   double pcg_rtol;                  /* relative 2-norm residual of each pressure solve (mixed: of the FP64 refinement) */
   int32_t pcg_max_it;               /* conjugate-gradient iteration cap per solve */
-  int32_t precond;                  /* OSCAR_PC_JACOBI (also the zero value) or OSCAR_PC_MG; the serving
-                                       engine accepts OSCAR_PC_JACOBI only */
+  int32_t precond;                  /* OSCAR_PC_JACOBI (also the zero value) or OSCAR_PC_MG */
+  int32_t mules_iter;               /* limiting passes of the alpha transport, 0..8 (0 and 1: the single
+                                       Zalesak limiter).  Pass m > 1 limits the antidiffusive flux the
+                                       passes before it left unused, (1 - lambda) A, against the first
+                                       pass's local bounds (iterative flux correction); more than one pass
+                                       takes one more face array of workspace */
 } oscar_desc;
 
 typedef struct {

@@ -102,6 +102,7 @@ void layout(const oscar_desc &D, Carver &cv, Slot *s, bool ctl_block) {
   s->gradU = cv.take(w * nc * d * d);
   void **face[] = {&s->phi_vd, &s->phi_prev, &s->phi_cr, &s->nhatf, &s->Fm, &s->FL, &s->Af};
   for (void **p : face) *p = cv.take(w * nf);
+  s->Af2 = D.mules_iter > 1 ? cv.take(w * nf) : nullptr;
   s->phiH = (double *)cv.take(8 * nf);
   double **dbl[] = {&s->p_vd, &s->p_cr, &s->p, &s->rhs, &s->Mp};
   for (double **p : dbl) *p = (double *)cv.take(8 * nc);
@@ -164,6 +165,7 @@ int check_desc(const oscar_desc *D, std::string &why) {
     mg_levels(*D, mg);
     if (mg.lv[mg.L].nc > MG_DENSE_MAX) { why = "grid too large for the multigrid hierarchy"; return OSCAR_E_ARG; }
   }
+  if (D->mules_iter < 0 || D->mules_iter > 8) { why = "mules_iter must be in [0, 8]"; return OSCAR_E_ARG; }
   if (D->n_corr < 1 || D->n_corr > 64) { why = "n_corr must be in [1, 64]"; return OSCAR_E_ARG; }
   if (!(D->pcg_rtol > 0) || D->pcg_max_it < 1) { why = "pcg_rtol must be > 0 and pcg_max_it >= 1"; return OSCAR_E_ARG; }
   for (int f = 0; f < 2 * D->dim; ++f)
@@ -643,6 +645,7 @@ extern "C" int32_t oscar_create(const oscar_desc *desc, void *ws, uint64_t bytes
   s.nblocks = c->g.nblocks;
   s.n_fluid = (int32_t)n_fluid;
   s.precision = desc->precision;
+  s.mules_iter = desc->mules_iter > 1 ? desc->mules_iter : 1;
   for (int f = 0; f < 6; ++f)
     s.bcf[f] = desc->bc[f] == OSCAR_BC_INLET ? F_INLET : (desc->bc[f] == OSCAR_BC_OUTLET ? F_OUTLET : F_WALL);
   s.outlet = outlet_mask(s);
@@ -847,7 +850,7 @@ static int viscous_step_t(oscar_ctx *c, double dt) {
   c->refine_call = 0;
   launch_copy_phi_prev<R>(L);
   launch_normals<R>(L, false);
-  launch_advect<R>(L);
+  launch_advect<R>(L, c->s.mules_iter);
   launch_assemble<R>(L);
   c->mg_stale = true;
   HIPCHK(c, hipGetLastError());
@@ -874,7 +877,7 @@ static int relax_t(oscar_ctx *c, double dt_vd, int n_sub, int max_iters, double 
   int kf = max_iters;
   for (int k = 0; k < max_iters; ++k) {
     launch_normals<R>(L, false);
-    launch_advect<R>(L);
+    launch_advect<R>(L, c->s.mules_iter);
     launch_normals<R>(L, true);
     launch_assemble<R>(L);
     c->mg_stale = true;
@@ -1365,6 +1368,7 @@ extern "C" int32_t oscar_engine_admit(oscar_engine *e, const oscar_desc *desc, d
   s.nblocks = es.g.nblocks;
   s.n_fluid = (int32_t)n_fluid;
   s.precision = desc->precision;
+  s.mules_iter = desc->mules_iter > 1 ? desc->mules_iter : 1;
   for (int f = 0; f < 6; ++f)
     s.bcf[f] = desc->bc[f] == OSCAR_BC_INLET ? F_INLET : (desc->bc[f] == OSCAR_BC_OUTLET ? F_OUTLET : F_WALL);
   s.outlet = outlet_mask(s);
@@ -1496,7 +1500,9 @@ static int eng_tick(oscar_engine *e) {
   launch_zero_usum<R>(L);
   launch_copy_phi_prev<R>(L);
   launch_normals<R>(L, false);
-  launch_advect<R>(L);
+  int npass = 1;
+  for (int i : act) npass = std::max(npass, e->slots[i].s.mules_iter);
+  launch_advect<R>(L, npass);
   launch_normals<R>(L, true);
   launch_assemble<R>(L);
   EHIP(e, hipGetLastError());

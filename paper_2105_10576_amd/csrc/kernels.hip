@@ -281,6 +281,8 @@ __global__ void __launch_bounds__(BLOCK) k_mules_update(const Slot *slots, const
   if (!ctl.active) return;
   R *a = (R *)s.alpha;
   const R *FL = (const R *)s.FL, *Af = (const R *)s.Af, *Rp = (const R *)s.Rp, *Rm = (const R *)s.Rm;
+  R *Arest = (R *)s.Af2;   // unused flux for the next limiting pass
+  const bool more = s.mules_iter > 1;
   const R dtV = (R)ctl.dt / (R)s.V;
   double red[2] = {0.0, 0.0};   // sum alpha_new, boundary flux
   for_cells(s, B.lb, [&](const Cell &c) {
@@ -298,10 +300,95 @@ __global__ void __launch_bounds__(BLOCK) k_mules_update(const Slot *slots, const
         R x1 = A >= (R)0 ? Rm[lo] : Rp[lo];
         R x2 = A >= (R)0 ? Rp[hi] : Rm[hi];
         lam = x1 < x2 ? x1 : x2;
+        // the lower cell of an interior face writes its unused flux
+        if (more && (f & 1)) Arest[cf.fi] = ((R)1 - lam) * A;
       } else {
         bfl = bfl + sg * FL[cf.fi];
       }
       acc = acc + sg * (FL[cf.fi] + lam * Af[cf.fi]);
+    }
+    R an = a[c.P] - dtV * acc;
+    a[c.P] = an;
+    red[0] = red[0] + (double)an;
+    red[1] = red[1] + (double)bfl;
+  });
+  put_partials<0u>(s, B.lb, CH_ADV2, red);
+}
+
+// Limiting pass `pass` >= 2 (iterative flux correction): the antidiffusive
+// flux the earlier passes left unused sits in Af2 (even passes) or Af (odd
+// passes); the local bounds are those of the first pass, taken from
+// alpha_old, and Q+- from the current alpha.
+template <typename R>
+__global__ void __launch_bounds__(BLOCK) k_mules_limiter_again(const Slot *slots, const int2 *btab, int pass) {
+  Block B = block_of(slots, btab);
+  const Slot &s = *B.s;
+  const SlotCtl &ctl = *B.ctl;
+  if (!ctl.active || pass > s.mules_iter) return;
+  const R *a = (const R *)s.alpha, *ab = (const R *)s.alpha_old;
+  const R *Ar = (const R *)((pass & 1) ? s.Af : s.Af2);
+  R *Rp = (R *)s.Rp, *Rm = (R *)s.Rm;
+  const R Vdt = (R)s.V / (R)ctl.dt;
+  for_cells(s, B.lb, [&](const Cell &c) {
+    uint8_t fl = s.flags[c.P];
+    R rp = (R)0, rm = (R)0;
+    if (!(fl & 0x40)) {
+      R Pp = (R)0, Pm = (R)0, amax = ab[c.P], amin = ab[c.P];
+      for (int f = 0; f < 2 * s.dim; ++f) {
+        CFace cf = cell_face(s, fl, c, f);
+        if (cf.type != F_INT) continue;   // only interior faces carry antidiffusive flux
+        R sA = ((f & 1) ? (R)1 : (R)-1) * Ar[cf.fi];
+        Pp = Pp + (sA < (R)0 ? -sA : (R)0);
+        Pm = Pm + (sA > (R)0 ? sA : (R)0);
+        R an = ab[cf.nb];
+        if (an > amax) amax = an;
+        if (an < amin) amin = an;
+      }
+      if (amax > (R)1) amax = (R)1;
+      if (amin < (R)0) amin = (R)0;
+      R cur = a[c.P];
+      R Qp = Vdt * (amax - cur > (R)0 ? amax - cur : (R)0);
+      R Qm = Vdt * (cur - amin > (R)0 ? cur - amin : (R)0);
+      rp = Pp > (R)0 ? (Qp / Pp < (R)1 ? Qp / Pp : (R)1) : (R)0;
+      rm = Pm > (R)0 ? (Qm / Pm < (R)1 ? Qm / Pm : (R)1) : (R)0;
+    }
+    Rp[c.P] = rp;
+    Rm[c.P] = rm;
+  });
+}
+
+template <typename R>
+__global__ void __launch_bounds__(BLOCK) k_mules_update_again(const Slot *slots, const int2 *btab, int pass) {
+  Block B = block_of(slots, btab);
+  const Slot &s = *B.s;
+  const SlotCtl &ctl = *B.ctl;
+  if (!ctl.active || pass > s.mules_iter) return;
+  R *a = (R *)s.alpha;
+  const R *FL = (const R *)s.FL, *Rp = (const R *)s.Rp, *Rm = (const R *)s.Rm;
+  const R *Ar = (const R *)((pass & 1) ? s.Af : s.Af2);
+  R *An = (R *)((pass & 1) ? s.Af2 : s.Af);
+  const bool more = pass < s.mules_iter;
+  const R dtV = (R)ctl.dt / (R)s.V;
+  double red[2] = {0.0, 0.0};   // sum alpha_new, boundary flux
+  for_cells(s, B.lb, [&](const Cell &c) {
+    uint8_t fl = s.flags[c.P];
+    if (fl & 0x40) return;
+    R acc = (R)0, bfl = (R)0;
+    for (int f = 0; f < 2 * s.dim; ++f) {
+      CFace cf = cell_face(s, fl, c, f);
+      if (cf.type == F_NONE) continue;
+      R sg = (f & 1) ? (R)1 : (R)-1;
+      if (cf.type != F_INT) {
+        bfl = bfl + sg * FL[cf.fi];
+        continue;
+      }
+      int lo = (f & 1) ? c.P : cf.nb, hi = (f & 1) ? cf.nb : c.P;
+      R A = Ar[cf.fi];
+      R x1 = A >= (R)0 ? Rm[lo] : Rp[lo];
+      R x2 = A >= (R)0 ? Rp[hi] : Rm[hi];
+      R lam = x1 < x2 ? x1 : x2;
+      if (more && (f & 1)) An[cf.fi] = ((R)1 - lam) * A;
+      acc = acc + sg * (lam * A);
     }
     R an = a[c.P] - dtV * acc;
     a[c.P] = an;
@@ -953,10 +1040,14 @@ template <typename R> void launch_normals(const Launch &L, bool curvature) {
   if (curvature) hipLaunchKernelGGL(k_curvature<R>, GRID(L), L.slots, L.btab);
 }
 
-template <typename R> void launch_advect(const Launch &L) {
+template <typename R> void launch_advect(const Launch &L, int npass) {
   hipLaunchKernelGGL(k_mules_flux<R>, GRID(L), L.slots, L.btab);
   hipLaunchKernelGGL(k_mules_limiter<R>, GRID(L), L.slots, L.btab);
   hipLaunchKernelGGL(k_mules_update<R>, GRID(L), L.slots, L.btab);
+  for (int m = 2; m <= npass; ++m) {
+    hipLaunchKernelGGL(k_mules_limiter_again<R>, GRID(L), L.slots, L.btab, m);
+    hipLaunchKernelGGL(k_mules_update_again<R>, GRID(L), L.slots, L.btab, m);
+  }
   hipLaunchKernelGGL(k_transport_fin, SLOTGRID(L), L.slots);
 }
 
@@ -1053,7 +1144,7 @@ void launch_state_reset(const Launch &L, int nslots) {
 #define INST(R)                                                   \
   template void launch_copy_phi_prev<R>(const Launch &);          \
   template void launch_normals<R>(const Launch &, bool);          \
-  template void launch_advect<R>(const Launch &);                 \
+  template void launch_advect<R>(const Launch &, int);            \
   template void launch_assemble<R>(const Launch &);               \
   template void launch_predictor<R>(const Launch &);              \
   template void launch_pressure_setup<R>(const Launch &, bool);   \

@@ -85,6 +85,7 @@ struct Slot {
   int32_t dim, nx, ny, nz;
   int32_t nc, nf0, nf1, nf2, nftot, nxy;   // counts (the host keeps them below 2^31)
   int32_t block0, nblocks, n_fluid, precision;
+  int32_t mules_iter, pad0;     // limiting passes of the alpha transport (>= 1)
   int32_t bcf[6];               // face type of each box side
   uint32_t outlet;              // bit f: box side f is an outlet (f < 2*dim)
   double h, V, S, Sh, S2h, hh, delta, cos_t, sin_t;
@@ -94,6 +95,7 @@ struct Slot {
   void *alpha, *alpha_old, *U_vd, *U_cr, *U_sum, *U, *phi_vd, *phi_prev, *phi_cr;
   double *p_vd, *p_cr, *p;
   void *kappa, *nhatf, *grad, *gradU, *Fm, *aP, *rAU, *b, *HbyA, *FL, *Af, *Rp, *Rm;
+  void *Af2;                    // unused antidiffusive flux between limiting passes (mules_iter > 1)
   // balanced-force face sums (pressure gradient against surface tension)
   // are formed in FP64 in both modes: predicted flux, right-hand side
   double *phiH, *rhs, *Mp, *r64;
@@ -124,7 +126,8 @@ struct Launch {
 
 template <typename R> void launch_copy_phi_prev(const Launch &L);
 template <typename R> void launch_normals(const Launch &L, bool curvature);
-template <typename R> void launch_advect(const Launch &L);
+// npass: the largest mules_iter of the slots in the launch
+template <typename R> void launch_advect(const Launch &L, int npass);
 template <typename R> void launch_assemble(const Launch &L);
 template <typename R> void launch_predictor(const Launch &L);
 template <typename R> void launch_pressure_setup(const Launch &L, bool normres);

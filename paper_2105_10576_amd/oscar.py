@@ -31,7 +31,8 @@ class Desc(C.Structure):
                 ("rho1", C.c_double), ("mu1", C.c_double), ("rho2", C.c_double), ("mu2", C.c_double),
                 ("sigma", C.c_double), ("theta_deg", C.c_double), ("bc", C.c_int32 * 6),
                 ("u_inlet", C.c_double), ("precision", C.c_int32), ("n_corr", C.c_int32),
-                ("pcg_rtol", C.c_double), ("pcg_max_it", C.c_int32), ("precond", C.c_int32)]
+                ("pcg_rtol", C.c_double), ("pcg_max_it", C.c_int32), ("precond", C.c_int32),
+                ("mules_iter", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -90,7 +91,8 @@ def lib():
 
 def make_desc(case, precision=FP64):
     """Fill an oscar_desc from a case dictionary (key "precond": PC_JACOBI,
-    the default, or PC_MG); returns (desc, keep-alive arrays)."""
+    the default, or PC_MG; key "mules_iter": limiting passes of the alpha
+    transport, default 1); returns (desc, keep-alive arrays)."""
     d = Desc()
     for k in ("dim", "nx", "ny", "nz", "n_corr", "pcg_max_it"):
         setattr(d, k, int(case[k]))
@@ -100,6 +102,7 @@ def make_desc(case, precision=FP64):
         d.bc[i] = int(case["bc"][i])
     d.precision = int(precision)
     d.precond = int(case.get("precond", PC_JACOBI))
+    d.mules_iter = int(case.get("mules_iter", 1))
     mask = np.ascontiguousarray(case["mask"], dtype=np.uint8)
     a0 = np.ascontiguousarray(case["alpha0"], dtype=np.float64)
     d.mask = mask.ctypes.data_as(C.POINTER(C.c_uint8))

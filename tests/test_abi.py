@@ -71,9 +71,26 @@ def test_multigrid_workspace_adds_the_coarse_levels():
         assert lo * nc < extra_values < hi * nc, (extra_values / nc)
 
 
+def test_iterative_limiter_adds_one_face_array():
+    """More than one limiting pass keeps the unused antidiffusive flux in
+    one extra face array (ping-pong with the first); one pass, or the unset
+    value 0, needs none."""
+    c = cases.channel_bubble(nx=128, ny=32)
+    nf = (c["nx"] + 1) * c["ny"] + c["nx"] * (c["ny"] + 1)
+    for prec, w in ((0, 8), (1, 4)):
+        sizes = {}
+        for m in (0, 1, 2, 8):
+            d, keep = _desc(dict(c, mules_iter=m), precision=prec)
+            rc, sizes[m] = _size(d)
+            assert rc == 0
+        assert sizes[0] == sizes[1] and sizes[2] == sizes[8]
+        assert 0 <= sizes[2] - sizes[1] - w * nf < 256
+
+
 @pytest.mark.parametrize("field,value", [("dim", 4), ("nx", 0), ("h", -1.0), ("rho1", 0.0), ("mu2", -1.0),
                                          ("sigma", -0.1), ("n_corr", 0), ("pcg_rtol", 0.0), ("precision", 7),
-                                         ("precond", 2), ("precond", -1)])
+                                         ("precond", 2), ("precond", -1), ("mules_iter", -1),
+                                         ("mules_iter", 9)])
 def test_bad_descriptor_rejected(field, value):
     from paper_2105_10576_amd import oscar
     c = cases.channel_bubble(nx=32, ny=8)
