@@ -402,6 +402,53 @@ __device__ __forceinline__ void sto(T *base, unsigned off, T v) {
   *(OSCAR_GLOBAL T *)((char *)base + off) = v;
 }
 
+// element idx of a field known to live in device global memory
+template <typename T>
+__device__ __forceinline__ T gld(const T *base, int idx) {
+  return ((const OSCAR_GLOBAL T *)base)[idx];
+}
+template <typename T>
+__device__ __forceinline__ void gst(T *base, int idx, T v) {
+  ((OSCAR_GLOBAL T *)base)[idx] = v;
+}
+
+// Per-cell operand indices of the six faces of a cell, every one valid: the
+// neighbour across face f where that face is interior and the cell itself
+// otherwise, and the face index (0 beyond dim), so the operands of all faces
+// can be loaded ahead of the arithmetic without a branch.
+struct Hood {
+  int nb[6], fi[6];
+};
+__device__ __forceinline__ Hood hood_of(const Slot &s, uint8_t fl, const Cell &c) {
+  Hood h;
+  const int st[3] = {1, s.nx, s.nxy};
+  const int fb[3] = {c.P + c.row, s.nf0 + c.P + s.nx * c.k, s.nf0 + s.nf1 + c.P};
+  const int fs[3] = {1, s.nx, s.nxy};
+#pragma unroll
+  for (int f = 0; f < 6; ++f) {
+    const int e = f >> 1;
+    h.nb[f] = ((fl >> f) & 1u) ? ((f & 1) ? c.P + st[e] : c.P - st[e]) : c.P;
+    h.fi[f] = e < s.dim ? fb[e] + ((f & 1) ? fs[e] : 0) : 0;
+  }
+  return h;
+}
+
+// The low face of direction e of a cell as the face_view classification
+// sees it, from the cell's flags fl and those of the cell below it, flo
+// (ignored when edge: the face lies on the box side).  side: the fluid cell
+// of a boundary face, 1 = the cell itself (orientation sign -1 seen from
+// it), 0 = the cell below (sign +1).
+__device__ __forceinline__ int low_face_type(const Slot &s, uint8_t fl, uint8_t flo, bool edge, int e, int &side) {
+  const bool hif = !(fl & 0x40);
+  side = 1;
+  if (edge) return hif ? s.bcf[2 * e] : F_NONE;
+  const bool lof = !(flo & 0x40);
+  if (lof && hif) return F_INT;
+  if (!lof && !hif) return F_NONE;
+  side = hif ? 1 : 0;
+  return F_WALL;
+}
+
 // byte offsets of cell P (element size w) and of its neighbours across
 // faces 0..5 where the face is interior (flag bit f), else of P itself
 __device__ __forceinline__ void nb_offsets(const Grid &G, unsigned P, uint8_t fl, unsigned w, unsigned &oP,

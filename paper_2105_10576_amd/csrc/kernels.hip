@@ -92,28 +92,58 @@ __global__ void __launch_bounds__(BLOCK) k_copy_phi_prev(const Slot *slots, cons
 // interface normal and curvature
 // ---------------------------------------------------------------------------
 
+// Gauss gradient of alpha at cells (face values: the two-cell mean on
+// interior faces, the cell value elsewhere).  Like the corrector kernels,
+// these take every operand of a batch of cells before the arithmetic.
 template <typename R>
 __global__ void __launch_bounds__(BLOCK) k_grad_alpha(const Slot *slots, const int2 *btab, int only_cr) {
   Block B = block_of(slots, btab);
   const Slot &s = *B.s;
   if (!B.ctl->active || (only_cr && B.ctl->mode != 1)) return;
+  const int d = s.dim, nc = s.nc;
   const R *a = (const R *)s.alpha;
   R *g = (R *)s.grad;
-  for_cells(s, B.lb, [&](const Cell &c) {
-    uint8_t fl = s.flags[c.P];
-    for (int e = 0; e < s.dim; ++e) {
-      R ge = (R)0;
-      if (!(fl & 0x40)) {
-        CFace lo = cell_face(s, fl, c, 2 * e), hi = cell_face(s, fl, c, 2 * e + 1);
-        R alo = lo.type == F_INT ? (R)0.5 * (a[c.P] + a[lo.nb]) : a[c.P];
-        R ahi = hi.type == F_INT ? (R)0.5 * (a[c.P] + a[hi.nb]) : a[c.P];
-        ge = (ahi - alo) / (R)s.h;
-      }
-      g[e * s.nc + c.P] = ge;
-    }
-  });
+  const R h = (R)s.h;
+  struct Op {
+    Cell c;
+    uint8_t fl;   // 0x80: past the end
+    R aP, an[6];
+  };
+  batched<2, Op>(
+      B.lb * BLOCK + (int)threadIdx.x, s.nblocks * BLOCK, nc,
+      [&](Op &o, int q) {
+        o.fl = 0x80;
+        if (q < nc) {
+          o.c = cell_at(s, q);
+          o.fl = s.flags[q];
+        }
+      },
+      [&](Op &o) {
+        if (o.fl & 0xC0) return;
+        const Hood hd = hood_of(s, o.fl, o.c);
+        o.aP = gld(a, o.c.P);
+#pragma unroll
+        for (int f = 0; f < 6; ++f) o.an[f] = gld(a, hd.nb[f]);
+      },
+      [&]() { return true; },
+      [&](Op &o) {
+        if (o.fl & 0x80) return;
+#pragma unroll
+        for (int e = 0; e < 3; ++e) {
+          if (e >= d) continue;
+          R ge = (R)0;
+          if (!(o.fl & 0x40)) {
+            R alo = ((o.fl >> (2 * e)) & 1u) ? (R)0.5 * (o.aP + o.an[2 * e]) : o.aP;
+            R ahi = ((o.fl >> (2 * e + 1)) & 1u) ? (R)0.5 * (o.aP + o.an[2 * e + 1]) : o.aP;
+            ge = (ahi - alo) / h;
+          }
+          gst(g, e * nc + o.c.P, ge);
+        }
+      });
 }
 
+// interface normal component of the faces each cell owns (the low face per
+// direction, the far face on the last layer); walls carry the contact angle
 template <typename R>
 __global__ void __launch_bounds__(BLOCK) k_face_normals(const Slot *slots, const int2 *btab, int only_cr) {
   Block B = block_of(slots, btab);
@@ -121,28 +151,83 @@ __global__ void __launch_bounds__(BLOCK) k_face_normals(const Slot *slots, const
   if (!B.ctl->active || (only_cr && B.ctl->mode != 1)) return;
   const R *g = (const R *)s.grad;
   R *nh = (R *)s.nhatf;
-  const int d = s.dim;
-  const R delta = (R)s.delta;
-  for_cells(s, B.lb, [&](const Cell &c) {
-    for_owned_faces(s, c, [&](int e, int fi, const FView &v) {
-      R G[3] = {(R)0, (R)0, (R)0};
-      R out = (R)0;
-      if (v.type == F_INT) {
-        for (int cc = 0; cc < d; ++cc) G[cc] = (R)0.5 * (g[cc * s.nc + v.lo] + g[cc * s.nc + v.hi]);
-        out = G[e] / (vnorm(G, d) + delta);
-      } else if (v.type == F_INLET || v.type == F_OUTLET) {
-        for (int cc = 0; cc < d; ++cc) G[cc] = g[cc * s.nc + v.P];
-        out = G[e] / (vnorm(G, d) + delta);
-      } else if (v.type == F_WALL) {
-        // wall adhesion n.n_w = cos(theta): the wall-normal component of the
-        // interface normal at the wall face, faded like the interior normals
-        for (int cc = 0; cc < d; ++cc) G[cc] = g[cc * s.nc + v.P];
-        R mg = vnorm(G, d);
-        out = (mg / (mg + delta)) * ((R)s.cos_t * (R)v.sf);
-      }
-      nh[fi] = out;
-    });
-  });
+  const int d = s.dim, nc = s.nc;
+  const R delta = (R)s.delta, cos_t = (R)s.cos_t;
+  const int nn[3] = {s.nx, s.ny, s.nz}, st[3] = {1, s.nx, s.nxy};
+  int bcf[6];
+  for (int f = 0; f < 6; ++f) bcf[f] = s.bcf[f];
+  struct Op {
+    Cell c;
+    uint8_t fl, flo[3];   // fl 0x80: past the end; flo: flags of the cell below per direction
+    int fi[6];
+    R gP[3], gl[3][3];    // gradient at the cell and at the cell below per direction
+  };
+  batched<2, Op>(
+      B.lb * BLOCK + (int)threadIdx.x, s.nblocks * BLOCK, nc,
+      [&](Op &o, int q) {
+        o.fl = 0x80;
+        if (q < nc) {
+          o.c = cell_at(s, q);
+          o.fl = s.flags[q];
+        }
+      },
+      [&](Op &o) {
+        if (o.fl & 0x80) return;
+        const Cell &c = o.c;
+        const Hood hd = hood_of(s, o.fl, c);
+        const int cr[3] = {c.i, c.j, c.k};
+#pragma unroll
+        for (int f = 0; f < 6; ++f) o.fi[f] = hd.fi[f];
+#pragma unroll
+        for (int e = 0; e < 3; ++e) {
+          const int lo = cr[e] > 0 ? c.P - st[e] : c.P;
+          o.flo[e] = e < d ? s.flags[lo] : (uint8_t)0x40;
+#pragma unroll
+          for (int cc = 0; cc < 3; ++cc) {
+            o.gl[e][cc] = (e < d && cc < d) ? gld(g, cc * nc + lo) : (R)0;
+            if (e == 0) o.gP[cc] = cc < d ? gld(g, cc * nc + c.P) : (R)0;
+          }
+        }
+      },
+      [&]() { return true; },
+      [&](Op &o) {
+        if (o.fl & 0x80) return;
+        const Cell &c = o.c;
+        const int cr[3] = {c.i, c.j, c.k};
+        // normal component on a face of type t whose fluid cell (boundary
+        // faces) has gradient Gc, seen with orientation sign sf
+        auto boundary = [&](int t, int e, const R (&Gc)[3], R sf) -> R {
+          R G[3] = {Gc[0], Gc[1], Gc[2]};
+          if (t == F_INLET || t == F_OUTLET) return G[e] / (vnorm(G, d) + delta);
+          if (t == F_WALL) {
+            // wall adhesion n.n_w = cos(theta): the wall-normal component of
+            // the interface normal at the wall face, faded like the interior
+            // normals
+            R mg = vnorm(G, d);
+            return (mg / (mg + delta)) * (cos_t * sf);
+          }
+          return (R)0;
+        };
+#pragma unroll
+        for (int e = 0; e < 3; ++e) {
+          if (e >= d) continue;
+          int side;
+          const int t = low_face_type(s, o.fl, o.flo[e], cr[e] == 0, e, side);
+          R out;
+          if (t == F_INT) {
+            R G[3] = {(R)0, (R)0, (R)0};
+#pragma unroll
+            for (int cc = 0; cc < 3; ++cc)
+              if (cc < d) G[cc] = (R)0.5 * (o.gl[e][cc] + o.gP[cc]);
+            out = G[e] / (vnorm(G, d) + delta);
+          } else {
+            out = side ? boundary(t, e, o.gP, (R)-1) : boundary(t, e, o.gl[e], (R)1);
+          }
+          gst(nh, o.fi[2 * e], out);
+          if (cr[e] == nn[e] - 1)
+            gst(nh, o.fi[2 * e + 1], (o.fl & 0x40) ? (R)0 : boundary(bcf[2 * e + 1], e, o.gP, (R)1));
+        }
+      });
 }
 
 template <typename R>
@@ -428,61 +513,152 @@ __device__ __forceinline__ R inlet_u(int cc, int e, R sg, R ub) {
   return cc == e ? -sg * ub : (R)0;
 }
 
+// Gauss gradient of the velocity, gU[(c*d+e)*nc + P] = dU_c/dx_e; operands
+// of a batch of cells first
 template <typename R>
 __global__ void __launch_bounds__(BLOCK) k_grad_u(const Slot *slots, const int2 *btab) {
   Block B = block_of(slots, btab);
   const Slot &s = *B.s;
   const SlotCtl &ctl = *B.ctl;
   if (!ctl.active) return;
-  const int d = s.dim;
+  const int d = s.dim, nc = s.nc;
   const R *Uo = (const R *)(ctl.mode ? s.U_cr : s.U_vd);
   R *gU = (R *)s.gradU;
-  const R ub = (R)ctl.ub;
-  for_cells(s, B.lb, [&](const Cell &c) {
-    uint8_t fl = s.flags[c.P];
-    for (int e = 0; e < d; ++e) {
-      CFace fc[2];
-      fc[0] = cell_face(s, fl, c, 2 * e);
-      fc[1] = cell_face(s, fl, c, 2 * e + 1);
-      for (int cc = 0; cc < d; ++cc) {
-        const R *Uc = Uo + cc * s.nc;
-        R out = (R)0;
-        if (!(fl & 0x40)) {
-          R fv[2];
-          for (int sd = 0; sd < 2; ++sd) {
-            const CFace &cf = fc[sd];
-            if (cf.type == F_INT) fv[sd] = (R)0.5 * (Uc[c.P] + Uc[cf.nb]);
-            else if (cf.type == F_WALL) fv[sd] = (R)0;
-            else if (cf.type == F_INLET) fv[sd] = inlet_u<R>(cc, e, sd ? (R)1 : (R)-1, ub);
-            else fv[sd] = Uc[c.P];
-          }
-          out = (fv[1] - fv[0]) / (R)s.h;
+  const R ub = (R)ctl.ub, h = (R)s.h;
+  struct Op {
+    Cell c;
+    uint8_t fl;   // 0x80: past the end
+    R uP[3], un[6][3];
+  };
+  batched<2, Op>(
+      B.lb * BLOCK + (int)threadIdx.x, s.nblocks * BLOCK, nc,
+      [&](Op &o, int q) {
+        o.fl = 0x80;
+        if (q < nc) {
+          o.c = cell_at(s, q);
+          o.fl = s.flags[q];
         }
-        gU[(cc * d + e) * s.nc + c.P] = out;
-      }
-    }
-  });
+      },
+      [&](Op &o) {
+        if (o.fl & 0xC0) return;
+        const Hood hd = hood_of(s, o.fl, o.c);
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc) {
+          o.uP[cc] = cc < d ? gld(Uo, cc * nc + o.c.P) : (R)0;
+#pragma unroll
+          for (int f = 0; f < 6; ++f) o.un[f][cc] = (cc < d && f < 2 * d) ? gld(Uo, cc * nc + hd.nb[f]) : (R)0;
+        }
+      },
+      [&]() { return true; },
+      [&](Op &o) {
+        if (o.fl & 0x80) return;
+        const Cell &c = o.c;
+#pragma unroll
+        for (int e = 0; e < 3; ++e) {
+          if (e >= d) continue;
+          int ty[2];
+          ty[0] = cell_face(s, o.fl, c, 2 * e).type;
+          ty[1] = cell_face(s, o.fl, c, 2 * e + 1).type;
+#pragma unroll
+          for (int cc = 0; cc < 3; ++cc) {
+            if (cc >= d) continue;
+            R out = (R)0;
+            if (!(o.fl & 0x40)) {
+              R fv[2];
+#pragma unroll
+              for (int sd = 0; sd < 2; ++sd) {
+                if (ty[sd] == F_INT) fv[sd] = (R)0.5 * (o.uP[cc] + o.un[2 * e + sd][cc]);
+                else if (ty[sd] == F_WALL) fv[sd] = (R)0;
+                else if (ty[sd] == F_INLET) fv[sd] = inlet_u<R>(cc, e, sd ? (R)1 : (R)-1, ub);
+                else fv[sd] = o.uP[cc];
+              }
+              out = (fv[1] - fv[0]) / h;
+            }
+            gst(gU, (cc * d + e) * nc + c.P, out);
+          }
+        }
+      });
 }
 
+// mass flux rho_f (phi_vd^n + phi_cr) of the faces each cell owns
 template <typename R>
 __global__ void __launch_bounds__(BLOCK) k_mass_flux(const Slot *slots, const int2 *btab) {
   Block B = block_of(slots, btab);
   const Slot &s = *B.s;
   if (!B.ctl->active) return;
+  const int d = s.dim, nc = s.nc;
   const R *a = (const R *)s.alpha;
   const R *pa = (const R *)s.phi_prev, *pc = (const R *)s.phi_cr;
   R *Fm = (R *)s.Fm;
-  for_cells(s, B.lb, [&](const Cell &c) {
-    for_owned_faces(s, c, [&](int, int fi, const FView &v) {
-      R phic = pa[fi] + pc[fi];
-      R F = (R)0;
-      if (v.type == F_INT) F = rho_of<R>(s, (R)0.5 * (a[v.lo] + a[v.hi])) * phic;
-      else if (v.type == F_INLET || v.type == F_OUTLET) F = rho_of<R>(s, a[v.P]) * phic;
-      Fm[fi] = F;
-    });
-  });
+  const R rho1 = (R)s.rho1, rho2 = (R)s.rho2;
+  const int nn[3] = {s.nx, s.ny, s.nz}, st[3] = {1, s.nx, s.nxy};
+  int bcf[6];
+  for (int f = 0; f < 6; ++f) bcf[f] = s.bcf[f];
+  auto rho = [&](R x) -> R { return x * rho1 + ((R)1 - x) * rho2; };
+  struct Op {
+    Cell c;
+    uint8_t fl, flo[3];
+    int fi[6];
+    R pa[6], pc[6], aP, al[3];   // fluxes of the low (and far) faces; alpha at the cell and below it
+  };
+  batched<2, Op>(
+      B.lb * BLOCK + (int)threadIdx.x, s.nblocks * BLOCK, nc,
+      [&](Op &o, int q) {
+        o.fl = 0x80;
+        if (q < nc) {
+          o.c = cell_at(s, q);
+          o.fl = s.flags[q];
+        }
+      },
+      [&](Op &o) {
+        if (o.fl & 0x80) return;
+        const Cell &c = o.c;
+        const Hood hd = hood_of(s, o.fl, c);
+        const int cr[3] = {c.i, c.j, c.k};
+        o.aP = gld(a, c.P);
+#pragma unroll
+        for (int e = 0; e < 3; ++e) {
+          const int lo = cr[e] > 0 ? c.P - st[e] : c.P;
+          o.fi[2 * e] = hd.fi[2 * e];
+          o.fi[2 * e + 1] = hd.fi[2 * e + 1];
+          o.flo[e] = e < d ? s.flags[lo] : (uint8_t)0x40;
+          o.al[e] = gld(a, lo);
+          const bool far = e < d && cr[e] == nn[e] - 1;
+          o.pa[2 * e] = e < d ? gld(pa, hd.fi[2 * e]) : (R)0;
+          o.pc[2 * e] = e < d ? gld(pc, hd.fi[2 * e]) : (R)0;
+          o.pa[2 * e + 1] = far ? gld(pa, hd.fi[2 * e + 1]) : (R)0;
+          o.pc[2 * e + 1] = far ? gld(pc, hd.fi[2 * e + 1]) : (R)0;
+        }
+      },
+      [&]() { return true; },
+      [&](Op &o) {
+        if (o.fl & 0x80) return;
+        const Cell &c = o.c;
+        const int cr[3] = {c.i, c.j, c.k};
+#pragma unroll
+        for (int e = 0; e < 3; ++e) {
+          if (e >= d) continue;
+          int side;
+          const int t = low_face_type(s, o.fl, o.flo[e], cr[e] == 0, e, side);
+          (void)side;
+          R phic = o.pa[2 * e] + o.pc[2 * e];
+          R F = (R)0;
+          if (t == F_INT) F = rho((R)0.5 * (o.al[e] + o.aP)) * phic;
+          else if (t == F_INLET || t == F_OUTLET) F = rho(o.aP) * phic;   // open sides: this cell is the fluid one
+          gst(Fm, o.fi[2 * e], F);
+          if (cr[e] == nn[e] - 1) {
+            const int tf = (o.fl & 0x40) ? F_NONE : bcf[2 * e + 1];
+            R phf = o.pa[2 * e + 1] + o.pc[2 * e + 1];
+            gst(Fm, o.fi[2 * e + 1], (tf == F_INLET || tf == F_OUTLET) ? rho(o.aP) * phf : (R)0);
+          }
+        }
+      });
 }
 
+// momentum matrix of a fluid cell: diagonal a_P and explicit b (old-time
+// term, upwind convection with the linear-upwind correction, implicit
+// diffusion with the explicit transpose term, inlet and wall terms).  One
+// cell per thread (register budget), all operands loaded first.
 template <typename R>
 __global__ void __launch_bounds__(BLOCK) k_assemble(const Slot *slots, const int2 *btab) {
   Block B = block_of(slots, btab);
@@ -495,61 +671,126 @@ __global__ void __launch_bounds__(BLOCK) k_assemble(const Slot *slots, const int
   const R *Uo = (const R *)(ctl.mode ? s.U_cr : s.U_vd);
   const R *gU = (const R *)s.gradU, *Fm = (const R *)s.Fm;
   R *aPo = (R *)s.aP, *rAUo = (R *)s.rAU, *bo = (R *)s.b;
-  const R Vdt = (R)s.V / (R)ctl.dt;
+  const R Vdt = (R)s.V / (R)ctl.dt, V = (R)s.V;
   const R hh = (R)s.hh, Sh = (R)s.Sh, S = (R)s.S, S2h = (R)s.S2h, ub = (R)ctl.ub;
-  for_cells(s, B.lb, [&](const Cell &c) {
-    uint8_t fl = s.flags[c.P];
-    if (fl & 0x40) {
-      aPo[c.P] = (R)0;
-      rAUo[c.P] = (R)0;
-      for (int cc = 0; cc < d; ++cc) bo[cc * nc + c.P] = (R)0;
-      return;
-    }
-    R rho_o = rho_of<R>(s, ao[c.P]), rho_n = rho_of<R>(s, an[c.P]), mu_n = mu_of<R>(s, an[c.P]);
-    R aP = rho_n * Vdt;
-    R b[3];
-    for (int cc = 0; cc < d; ++cc) b[cc] = (rho_o * Uo[cc * nc + c.P]) * Vdt;
-    for (int f = 0; f < 2 * d; ++f) {
-      CFace cf = cell_face(s, fl, c, f);
-      int e = f >> 1;
-      R sg = (f & 1) ? (R)1 : (R)-1;
-      if (cf.type == F_INT) {
-        R F = Fm[cf.fi], sF = sg * F;
-        R muf = mu_of<R>(s, (R)0.5 * (an[c.P] + an[cf.nb]));
-        R D = muf * Sh;
-        aP = aP + (sF > (R)0 ? sF : (R)0);
-        aP = aP + D;
-        int lo = (f & 1) ? c.P : cf.nb, hi = (f & 1) ? cf.nb : c.P;
-        for (int cc = 0; cc < d; ++cc) {
-          R lu = F >= (R)0 ? hh * gU[(cc * d + e) * nc + lo] : -(hh * gU[(cc * d + e) * nc + hi]);
-          b[cc] = b[cc] - sg * (F * lu);
-          R tv = (muf * S) * ((R)0.5 * (gU[(e * d + cc) * nc + c.P] + gU[(e * d + cc) * nc + cf.nb]));
-          b[cc] = b[cc] + sg * tv;
+  const R rho1 = (R)s.rho1, rho2 = (R)s.rho2, mu1 = (R)s.mu1, mu2 = (R)s.mu2;
+  auto rho = [&](R x) -> R { return x * rho1 + ((R)1 - x) * rho2; };
+  auto mu = [&](R x) -> R { return x * mu1 + ((R)1 - x) * mu2; };
+  struct Op {
+    Cell c;
+    uint8_t fl;   // 0x80: past the end
+    R aoP, anP, uP[3], F[6], anb[6], gP[3][3], ga[6][3], gb[6][3];   // gP[c][e] = dU_c/dx_e at the cell
+  };
+  batched<1, Op>(
+      B.lb * BLOCK + (int)threadIdx.x, s.nblocks * BLOCK, nc,
+      [&](Op &o, int q) {
+        o.fl = 0x80;
+        if (q < nc) {
+          o.c = cell_at(s, q);
+          o.fl = s.flags[q];
         }
-      } else if (cf.type == F_WALL) {
-        aP = aP + mu_n * S2h;
-      } else if (cf.type == F_INLET) {
-        R F = Fm[cf.fi];
-        aP = aP + mu_n * S2h;
-        for (int cc = 0; cc < d; ++cc) {
-          R ubc = inlet_u<R>(cc, e, sg, ub);
-          b[cc] = b[cc] + (mu_n * S2h) * ubc;
-          b[cc] = b[cc] - sg * (F * ubc);
+      },
+      [&](Op &o) {
+        if (o.fl & 0xC0) return;
+        const int P = o.c.P;
+        const Hood hd = hood_of(s, o.fl, o.c);
+        o.aoP = gld(ao, P);
+        o.anP = gld(an, P);
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc) o.uP[cc] = cc < d ? gld(Uo, cc * nc + P) : (R)0;
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc)
+#pragma unroll
+          for (int e = 0; e < 3; ++e) o.gP[cc][e] = (cc < d && e < d) ? gld(gU, (cc * d + e) * nc + P) : (R)0;
+#pragma unroll
+        for (int f = 0; f < 6; ++f) {
+          const int e = f >> 1, n = hd.nb[f];
+          o.F[f] = f < 2 * d ? gld(Fm, hd.fi[f]) : (R)0;
+          o.anb[f] = gld(an, n);
+#pragma unroll
+          for (int cc = 0; cc < 3; ++cc) {
+            const bool in = f < 2 * d && cc < d;
+            o.ga[f][cc] = in ? gld(gU, (cc * d + e) * nc + n) : (R)0;   // dU_cc/dx_e
+            o.gb[f][cc] = in ? gld(gU, (e * d + cc) * nc + n) : (R)0;   // dU_e/dx_cc
+          }
         }
-      } else if (cf.type == F_OUTLET) {
-        aP = aP + sg * Fm[cf.fi];
-      }
-    }
-    aPo[c.P] = aP;
-    rAUo[c.P] = (R)s.V / aP;
-    for (int cc = 0; cc < d; ++cc) bo[cc * nc + c.P] = b[cc];
-  });
+      },
+      [&]() { return true; },
+      [&](Op &o) {
+        if (o.fl & 0x80) return;
+        const Cell &c = o.c;
+        if (o.fl & 0x40) {
+          gst(aPo, c.P, (R)0);
+          gst(rAUo, c.P, (R)0);
+          for (int cc = 0; cc < d; ++cc) gst(bo, cc * nc + c.P, (R)0);
+          return;
+        }
+        R rho_o = rho(o.aoP), rho_n = rho(o.anP), mu_n = mu(o.anP);
+        R aP = rho_n * Vdt;
+        R b[3];
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc) b[cc] = cc < d ? (rho_o * o.uP[cc]) * Vdt : (R)0;
+#pragma unroll
+        for (int f = 0; f < 6; ++f) {
+          if (f >= 2 * d) continue;
+          const int ty = cell_face(s, o.fl, c, f).type;
+          const int e = f >> 1;
+          R sg = (f & 1) ? (R)1 : (R)-1;
+          if (ty == F_INT) {
+            R F = o.F[f], sF = sg * F;
+            R muf = mu((R)0.5 * (o.anP + o.anb[f]));
+            R D = muf * Sh;
+            aP = aP + (sF > (R)0 ? sF : (R)0);
+            aP = aP + D;
+#pragma unroll
+            for (int cc = 0; cc < 3; ++cc) {
+              if (cc >= d) continue;
+              // gradient component dU_cc/dx_e at the lower and upper cell
+              const R glo = (f & 1) ? o.gP[cc][e] : o.ga[f][cc];
+              const R ghi = (f & 1) ? o.ga[f][cc] : o.gP[cc][e];
+              R lu = F >= (R)0 ? hh * glo : -(hh * ghi);
+              b[cc] = b[cc] - sg * (F * lu);
+              R tv = (muf * S) * ((R)0.5 * (o.gP[e][cc] + o.gb[f][cc]));
+              b[cc] = b[cc] + sg * tv;
+            }
+          } else if (ty == F_WALL) {
+            aP = aP + mu_n * S2h;
+          } else if (ty == F_INLET) {
+            R F = o.F[f];
+            aP = aP + mu_n * S2h;
+#pragma unroll
+            for (int cc = 0; cc < 3; ++cc) {
+              if (cc >= d) continue;
+              R ubc = inlet_u<R>(cc, e, sg, ub);
+              b[cc] = b[cc] + (mu_n * S2h) * ubc;
+              b[cc] = b[cc] - sg * (F * ubc);
+            }
+          } else if (ty == F_OUTLET) {
+            aP = aP + sg * o.F[f];
+          }
+        }
+        gst(aPo, c.P, aP);
+        gst(rAUo, c.P, V / aP);
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc)
+          if (cc < d) gst(bo, cc * nc + c.P, b[cc]);
+      });
 }
 
 // ---------------------------------------------------------------------------
 // PISO corrector
 // ---------------------------------------------------------------------------
 
+// cells per thread and batch of the corrector kernels: two in FP32, one in
+// FP64 (register budget)
+template <typename R>
+constexpr int CORR_NB = sizeof(R) == 4 ? 2 : 1;
+template <typename R>
+constexpr int CORRECT_NB = CORR_NB<R>;
+
+// H = b - sum_N a_N U_N, HbyA = H / a_P.  The operands of every face are
+// loaded before any arithmetic (and for all cells of a batch together), the
+// arithmetic then runs face by face in the oracle's order.
 template <typename R>
 __global__ void __launch_bounds__(BLOCK) k_predictor(const Slot *slots, const int2 *btab) {
   Block B = block_of(slots, btab);
@@ -561,104 +802,232 @@ __global__ void __launch_bounds__(BLOCK) k_predictor(const Slot *slots, const in
   const R *an = (const R *)s.alpha, *U = (const R *)(ctl.mode ? s.U_cr : s.U_vd);
   const R *Fm = (const R *)s.Fm, *b = (const R *)s.b, *aPv = (const R *)s.aP;
   R *HbyA = (R *)s.HbyA;
-  for_cells(s, B.lb, [&](const Cell &c) {
-    uint8_t fl = s.flags[c.P];
-    if (fl & 0x40) {
-      for (int cc = 0; cc < d; ++cc) HbyA[cc * nc + c.P] = (R)0;
-      return;
-    }
-    R H[3];
-    for (int cc = 0; cc < d; ++cc) H[cc] = b[cc * nc + c.P];
-    for (int f = 0; f < 2 * d; ++f) {
-      CFace cf = cell_face(s, fl, c, f);
-      if (cf.type != F_INT) continue;
-      R sF = ((f & 1) ? (R)1 : (R)-1) * Fm[cf.fi];
-      R D = mu_of<R>(s, (R)0.5 * (an[c.P] + an[cf.nb])) * (R)s.Sh;
-      R aN = (sF < (R)0 ? sF : (R)0) - D;
-      for (int cc = 0; cc < d; ++cc) H[cc] = H[cc] - aN * U[cc * nc + cf.nb];
-    }
-    R aP = aPv[c.P];
-    for (int cc = 0; cc < d; ++cc) HbyA[cc * nc + c.P] = H[cc] / aP;
-  });
+  const R mu1 = (R)s.mu1, mu2 = (R)s.mu2, Sh = (R)s.Sh;
+  struct Op {
+    Cell c;
+    uint8_t fl;   // 0x80: past the end
+    R F[6], al[6], Un[6][3], bb[3], aC, aP;
+  };
+  batched<CORR_NB<R>, Op>(
+      B.lb * BLOCK + (int)threadIdx.x, s.nblocks * BLOCK, nc,
+      [&](Op &o, int g) {
+        o.fl = 0x80;
+        if (g < nc) {
+          o.c = cell_at(s, g);
+          o.fl = s.flags[g];
+        }
+      },
+      [&](Op &o) {
+        if (o.fl & 0xC0) return;
+        const Hood h = hood_of(s, o.fl, o.c);
+        o.aC = gld(an, o.c.P);
+        o.aP = gld(aPv, o.c.P);
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc) o.bb[cc] = cc < d ? gld(b, cc * nc + o.c.P) : (R)0;
+#pragma unroll
+        for (int f = 0; f < 6; ++f) {
+          o.F[f] = gld(Fm, h.fi[f]);
+          o.al[f] = gld(an, h.nb[f]);
+#pragma unroll
+          for (int cc = 0; cc < 3; ++cc) o.Un[f][cc] = cc < d ? gld(U, cc * nc + h.nb[f]) : (R)0;
+        }
+      },
+      [&]() { return true; },
+      [&](Op &o) {
+        if (o.fl & 0x80) return;
+        const Cell &c = o.c;
+        if (o.fl & 0x40) {
+          for (int cc = 0; cc < d; ++cc) gst(HbyA, cc * nc + c.P, (R)0);
+          return;
+        }
+        R H[3] = {o.bb[0], o.bb[1], o.bb[2]};
+#pragma unroll
+        for (int f = 0; f < 6; ++f) {
+          if (!((o.fl >> f) & 1u)) continue;   // interior faces only
+          R sF = ((f & 1) ? (R)1 : (R)-1) * o.F[f];
+          R m = (R)0.5 * (o.aC + o.al[f]);
+          R D = (m * mu1 + ((R)1 - m) * mu2) * Sh;
+          R aN = (sF < (R)0 ? sF : (R)0) - D;
+#pragma unroll
+          for (int cc = 0; cc < 3; ++cc)
+            if (cc < d) H[cc] = H[cc] - aN * o.Un[f][cc];
+        }
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc)
+          if (cc < d) gst(HbyA, cc * nc + c.P, H[cc] / o.aP);
+      });
 }
 
+// predicted face flux phiH of the faces each cell owns (the low face per
+// direction, the far face on the last layer): interpolated HbyA plus the
+// surface-tension term, inlet and outlet values on open sides
 template <typename R>
 __global__ void __launch_bounds__(BLOCK) k_phiH(const Slot *slots, const int2 *btab) {
   Block B = block_of(slots, btab);
   const Slot &s = *B.s;
   const SlotCtl &ctl = *B.ctl;
   if (!ctl.active) return;
+  const int d = s.dim;
   const int nc = s.nc;
   const R *HbyA = (const R *)s.HbyA, *rAU = (const R *)s.rAU, *kap = (const R *)s.kappa, *a = (const R *)s.alpha;
   double *phiH = s.phiH;
-  const double S = s.S, ub = ctl.ub;
+  const double S = s.S, ub = ctl.ub, h = s.h, sigma = s.sigma;
   const int with_st = ctl.with_st;
-  for_cells(s, B.lb, [&](const Cell &c) {
-    for_owned_faces(s, c, [&](int e, int fi, const FView &v) {
-      double ph = 0.0;
-      if (v.type == F_INT) {
-        ph = (0.5 * ((double)HbyA[e * nc + v.lo] + (double)HbyA[e * nc + v.hi])) * S;
-        if (with_st) {
-          double rAUf = 0.5 * ((double)rAU[v.lo] + (double)rAU[v.hi]);
-          ph = ph + (rAUf * st_face<R>(s, kap, a, v.lo, v.hi)) * S;
+  const int nn[3] = {s.nx, s.ny, s.nz};
+  int bcf[6];
+  for (int f = 0; f < 6; ++f) bcf[f] = s.bcf[f];
+  struct Op {
+    Cell c;
+    uint8_t fl;   // 0x80: past the end
+    int fi[6];
+    R hP[3], hn[3], rP, rn[3], kP, kn[3], aP, an[3];   // at the cell and below it per direction
+  };
+  batched<CORR_NB<R>, Op>(
+      B.lb * BLOCK + (int)threadIdx.x, s.nblocks * BLOCK, nc,
+      [&](Op &o, int g) {
+        o.fl = 0x80;
+        if (g < nc) {
+          o.c = cell_at(s, g);
+          o.fl = s.flags[g];
         }
-      } else if (v.type == F_INLET) {
-        ph = -v.sf * (ub * S);
-      } else if (v.type == F_OUTLET) {
-        ph = (double)HbyA[e * nc + v.P] * S;
-      }
-      phiH[fi] = ph;
-    });
-  });
+      },
+      [&](Op &o) {
+        if (o.fl & 0x80) return;
+        const Hood hd = hood_of(s, o.fl, o.c);
+#pragma unroll
+        for (int f = 0; f < 6; ++f) o.fi[f] = hd.fi[f];
+        if (o.fl & 0x40) return;
+        const int P = o.c.P;
+        o.rP = gld(rAU, P);
+        o.kP = gld(kap, P);
+        o.aP = gld(a, P);
+#pragma unroll
+        for (int e = 0; e < 3; ++e) {
+          const int lo = hd.nb[2 * e];
+          o.hP[e] = e < d ? gld(HbyA, e * nc + P) : (R)0;
+          o.hn[e] = e < d ? gld(HbyA, e * nc + lo) : (R)0;
+          o.rn[e] = gld(rAU, lo);
+          o.kn[e] = gld(kap, lo);
+          o.an[e] = gld(a, lo);
+        }
+      },
+      [&]() { return true; },
+      [&](Op &o) {
+        if (o.fl & 0x80) return;
+        const bool fluid = !(o.fl & 0x40);
+        const int cr[3] = {o.c.i, o.c.j, o.c.k};
+        // value of an open side face of this fluid cell (orientation sign sf
+        // seen from the cell)
+        auto open = [&](int type, int e, double sf) -> double {
+          if (type == F_INLET) return -sf * (ub * S);
+          if (type == F_OUTLET) return (double)o.hP[e] * S;
+          return 0.0;
+        };
+#pragma unroll
+        for (int e = 0; e < 3; ++e) {
+          if (e >= d) continue;
+          double ph = 0.0;
+          if (fluid && ((o.fl >> (2 * e)) & 1u)) {
+            ph = (0.5 * ((double)o.hn[e] + (double)o.hP[e])) * S;
+            if (with_st) {
+              double rAUf = 0.5 * ((double)o.rn[e] + (double)o.rP);
+              double st = (sigma * (0.5 * ((double)o.kn[e] + (double)o.kP))) * (((double)o.aP - (double)o.an[e]) / h);
+              ph = ph + (rAUf * st) * S;
+            }
+          } else if (fluid && cr[e] == 0) {
+            ph = open(bcf[2 * e], e, -1.0);
+          }
+          gst(phiH, o.fi[2 * e], ph);
+          if (cr[e] == nn[e] - 1) gst(phiH, o.fi[2 * e + 1], fluid ? open(bcf[2 * e + 1], e, 1.0) : 0.0);
+        }
+      });
 }
 
-// rhs = -div(phiH), r = rhs - M p, Jacobi diagonal
+// rhs = -div(phiH), r = rhs - M p, Jacobi diagonal; operands first
 template <typename R>
 __global__ void __launch_bounds__(BLOCK) k_pressure_setup(const Slot *slots, const int2 *btab) {
   using T = R;
   Block B = block_of(slots, btab);
   const Slot &s = *B.s;
   const Grid G = grid_of(s);
-  const uint8_t *flags = s.flags;
   const SlotCtl &ctl = *B.ctl;
   if (!ctl.active) return;
+  const int d = G.dim;
   const R *rAU = (const R *)s.rAU;
   const double *phiH = s.phiH;
   const double *p = ctl.mode ? s.p_cr : s.p_vd;
   const bool mixed = s.precision != 0;
   T *r = (T *)s.cr[0], *invD = (T *)s.invD, *e = (T *)s.e;
+  double *rhsv = s.rhs, *Mpv = s.Mp;
+  const uint8_t *flags = s.flags;
   double red[3] = {0.0, 0.0, 0.0};   // |rhs|^2, |rhs - M p|^2, sum p
-  for_cells(G, B.lb, [&](const Cell &c) {
-    uint8_t fl = flags[c.P];
-    if (fl & 0x40) {
-      s.rhs[c.P] = 0.0;
-      s.Mp[c.P] = 0.0;
-      r[c.P] = (T)0;
-      invD[c.P] = (T)0;
-      if (mixed) e[c.P] = (T)0;
-      return;
-    }
-    double acc = 0.0;
-    T dg = (T)0;
-    for (int f = 0; f < 2 * s.dim; ++f) {
-      CFace cf = cell_face(s, fl, c, f);
-      if (cf.type == F_NONE) continue;
-      acc = acc + ((f & 1) ? 1.0 : -1.0) * phiH[cf.fi];
-      if (cf.type == F_INT || cf.type == F_OUTLET) dg = dg + pcoef<T, R>(s, rAU, c.P, cf);
-    }
-    double rhs = -acc;
-    double Mp = matvec_row<double, R>(G, rAU, c, fl, [&](int x) { return p[x]; });
-    double r64 = rhs - Mp;
-    T rr = (T)r64;
-    s.rhs[c.P] = rhs;
-    s.Mp[c.P] = Mp;
-    r[c.P] = rr;
-    invD[c.P] = (T)1 / dg;
-    if (mixed) e[c.P] = (T)0;
-    red[0] = red[0] + rhs * rhs;
-    red[1] = red[1] + (mixed ? r64 * r64 : (double)(rr * rr));
-    red[2] = red[2] + p[c.P];
-  });
+  struct Op {
+    Cell c;
+    uint8_t fl;   // 0x80: past the end
+    double ph[6], pP, pn[6];
+    R rP, rn[6];
+  };
+  batched<CORR_NB<R>, Op>(
+      B.lb * BLOCK + (int)threadIdx.x, G.nblocks * BLOCK, G.nc,
+      [&](Op &o, int g) {
+        o.fl = 0x80;
+        if (g < G.nc) {
+          o.c = cell_at(G, g);
+          o.fl = flags[g];
+        }
+      },
+      [&](Op &o) {
+        if (o.fl & 0xC0) return;
+        const Hood hd = hood_of(s, o.fl, o.c);
+        o.pP = gld(p, o.c.P);
+        o.rP = gld(rAU, o.c.P);
+#pragma unroll
+        for (int f = 0; f < 6; ++f) {
+          o.ph[f] = f < 2 * d ? gld(phiH, hd.fi[f]) : 0.0;
+          o.pn[f] = gld(p, hd.nb[f]);
+          o.rn[f] = gld(rAU, hd.nb[f]);
+        }
+      },
+      [&]() { return true; },
+      [&](Op &o) {
+        if (o.fl & 0x80) return;
+        const Cell &c = o.c;
+        if (o.fl & 0x40) {
+          gst(rhsv, c.P, 0.0);
+          gst(Mpv, c.P, 0.0);
+          gst(r, c.P, (T)0);
+          gst(invD, c.P, (T)0);
+          if (mixed) gst(e, c.P, (T)0);
+          return;
+        }
+        double acc = 0.0;
+        T dg = (T)0;
+#pragma unroll
+        for (int f = 0; f < 6; ++f) {
+          if (f >= 2 * d) continue;
+          acc = acc + ((f & 1) ? 1.0 : -1.0) * o.ph[f];
+          if ((o.fl >> f) & 1u) dg = dg + ((T)0.5 * ((T)o.rP + (T)o.rn[f])) * (T)G.Sh;
+          else if (((G.outlet >> f) & 1u) && on_edge(G, c, f)) dg = dg + (T)o.rP * (T)G.S2h;
+        }
+        double rhs = -acc;
+        double xn[6], rn[6];
+#pragma unroll
+        for (int f = 0; f < 6; ++f) {
+          xn[f] = o.pn[f];
+          rn[f] = (double)o.rn[f];
+        }
+        double Mp = matvec_pre<double>(G, c, o.fl, o.pP, (double)o.rP, xn, rn);
+        double r64 = rhs - Mp;
+        T rr = (T)r64;
+        gst(rhsv, c.P, rhs);
+        gst(Mpv, c.P, Mp);
+        gst(r, c.P, rr);
+        gst(invD, c.P, (T)1 / dg);
+        if (mixed) gst(e, c.P, (T)0);
+        red[0] = red[0] + rhs * rhs;
+        red[1] = red[1] + (mixed ? r64 * r64 : (double)(rr * rr));
+        red[2] = red[2] + o.pP;
+      });
   put_partials<0u>(s, B.lb, CH_SETUP, red);
 }
 
@@ -933,7 +1302,9 @@ __global__ void __launch_bounds__(BLOCK) k_refine_fin(const Slot *slots) {
 }
 
 // phi = phiH - rAU_f S/h (p_hi - p_lo); u = HbyA + rAU * mean of the face
-// accelerations (f - grad p) of the two faces of each direction
+// accelerations (f - grad p) of the two faces of each direction.  Operands
+// first, as in k_predictor; each thread writes the faces its cell owns (the
+// low face per direction, and the far face on the last layer).
 template <typename R>
 __global__ void __launch_bounds__(BLOCK) k_correct(const Slot *slots, const int2 *btab, int last) {
   Block B = block_of(slots, btab);
@@ -949,47 +1320,127 @@ __global__ void __launch_bounds__(BLOCK) k_correct(const Slot *slots, const int2
   R *phi = (R *)(ctl.mode ? s.phi_cr : s.phi_vd);
   R *U = (R *)(ctl.mode ? s.U_cr : s.U_vd);
   R *Us = (R *)s.U_sum;
-  const double Sh = s.Sh, S2h = s.S2h, h = s.h, hh = s.hh;
+  const double Sh = s.Sh, S2h = s.S2h, h = s.h, hh = s.hh, sigma = s.sigma;
   const int with_st = ctl.with_st;
+  const bool acc_sum = last && ctl.mode == 1;
+  const int nn[3] = {s.nx, s.ny, s.nz};
+  int bcf[6];
+  for (int f = 0; f < 6; ++f) bcf[f] = s.bcf[f];
   bool bad = false;
-  for_cells(s, B.lb, [&](const Cell &c) {
-    for_owned_faces(s, c, [&](int, int fi, const FView &v) {
-      double ph = phiH[fi];
-      if (v.type == F_INT) {
-        double cf = (0.5 * ((double)rAU[v.lo] + (double)rAU[v.hi])) * Sh;
-        ph = ph - cf * (p[v.hi] - p[v.lo]);
-      } else if (v.type == F_OUTLET) {
-        double cf = (double)rAU[v.P] * S2h;
-        ph = ph + v.sf * (cf * p[v.P]);
-      }
-      phi[fi] = (R)ph;
-    });
-    uint8_t fl = s.flags[c.P];
-    for (int cc = 0; cc < d; ++cc) {
-      R u = (R)0;
-      if (!(fl & 0x40)) {
-        double qv[2];
-        for (int sd = 0; sd < 2; ++sd) {
-          CFace cf = cell_face(s, fl, c, 2 * cc + sd);
-          double qq = 0.0;
-          if (cf.type == F_INT) {
-            int lo = sd ? c.P : cf.nb, hi = sd ? cf.nb : c.P;
-            double ff = with_st ? st_face<R>(s, kap, a, lo, hi) : 0.0;
-            qq = ff - (p[hi] - p[lo]) / h;
-          } else if (cf.type == F_OUTLET) {
-            double pplus = sd ? 0.0 : p[c.P], pminus = sd ? p[c.P] : 0.0;
-            qq = -(pplus - pminus) / hh;
-          }
-          qv[sd] = qq;
+  struct Op {
+    Cell c;
+    uint8_t fl;   // 0x80: past the end
+    int fi[6];
+    double pP, pn[6], ph[6];   // ph: phiH of the low face, and of the far face on the last layer
+    R rP, rn[3], kP, kn[6], aP, an[6], hb[3], us[3];
+  };
+  batched<CORRECT_NB<R>, Op>(
+      B.lb * BLOCK + (int)threadIdx.x, s.nblocks * BLOCK, nc,
+      [&](Op &o, int g) {
+        o.fl = 0x80;
+        if (g < nc) {
+          o.c = cell_at(s, g);
+          o.fl = s.flags[g];
         }
-        double uu = (double)HbyA[cc * nc + c.P] + (double)rAU[c.P] * (0.5 * (qv[0] + qv[1]));
-        u = (R)uu;
-        if (!(uu == uu) || fabs(uu) > 1e30) bad = true;
-      }
-      U[cc * nc + c.P] = u;
-      if (last && ctl.mode == 1) Us[cc * nc + c.P] = Us[cc * nc + c.P] + u;
-    }
-  });
+      },
+      [&](Op &o) {
+        if (o.fl & 0x80) return;
+        const Cell &c = o.c;
+        const Hood hd = hood_of(s, o.fl, c);
+        const int cr[3] = {c.i, c.j, c.k};
+#pragma unroll
+        for (int f = 0; f < 6; ++f) o.fi[f] = hd.fi[f];
+#pragma unroll
+        for (int e = 0; e < 3; ++e) {
+          o.ph[2 * e] = 0.0;
+          o.ph[2 * e + 1] = 0.0;
+          if (e < d) {
+            o.ph[2 * e] = gld(phiH, hd.fi[2 * e]);
+            if (cr[e] == nn[e] - 1) o.ph[2 * e + 1] = gld(phiH, hd.fi[2 * e + 1]);
+          }
+        }
+        if (acc_sum)
+#pragma unroll
+          for (int cc = 0; cc < 3; ++cc) o.us[cc] = cc < d ? gld(Us, cc * nc + c.P) : (R)0;
+        if (o.fl & 0x40) return;
+        o.pP = gld(p, c.P);
+        o.rP = gld(rAU, c.P);
+        o.kP = gld(kap, c.P);
+        o.aP = gld(a, c.P);
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc) o.hb[cc] = cc < d ? gld(HbyA, cc * nc + c.P) : (R)0;
+#pragma unroll
+        for (int f = 0; f < 6; ++f) {
+          o.pn[f] = gld(p, hd.nb[f]);
+          o.kn[f] = gld(kap, hd.nb[f]);
+          o.an[f] = gld(a, hd.nb[f]);
+          if (!(f & 1)) o.rn[f >> 1] = gld(rAU, hd.nb[f]);
+        }
+      },
+      [&]() { return true; },
+      [&](Op &o) {
+        if (o.fl & 0x80) return;
+        const Cell &c = o.c;
+        const bool fluid = !(o.fl & 0x40);
+        const int cr[3] = {c.i, c.j, c.k};
+        // owned faces: the low face of direction e has the neighbour below
+        // as lo and this cell as hi; it is interior when both are fluid, an
+        // outlet when this fluid cell lies on an outlet side
+#pragma unroll
+        for (int e = 0; e < 3; ++e) {
+          if (e >= d) continue;
+          double ph = o.ph[2 * e];
+          if (fluid && ((o.fl >> (2 * e)) & 1u)) {
+            double cf = (0.5 * ((double)o.rn[e] + (double)o.rP)) * Sh;
+            ph = ph - cf * (o.pP - o.pn[2 * e]);
+          } else if (fluid && cr[e] == 0 && bcf[2 * e] == F_OUTLET) {
+            double cf = (double)o.rP * S2h;
+            ph = ph + -1.0 * (cf * o.pP);
+          }
+          gst(phi, o.fi[2 * e], (R)ph);
+          if (cr[e] == nn[e] - 1) {
+            double pf = o.ph[2 * e + 1];
+            if (fluid && bcf[2 * e + 1] == F_OUTLET) {
+              double cf = (double)o.rP * S2h;
+              pf = pf + 1.0 * (cf * o.pP);
+            }
+            gst(phi, o.fi[2 * e + 1], (R)pf);
+          }
+        }
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc) {
+          if (cc >= d) continue;
+          R u = (R)0;
+          if (fluid) {
+            double qv[2];
+#pragma unroll
+            for (int sd = 0; sd < 2; ++sd) {
+              const int f = 2 * cc + sd;
+              double qq = 0.0;
+              if ((o.fl >> f) & 1u) {
+                // lo and hi cells of the face
+                const double plo = sd ? o.pP : o.pn[f], phi_ = sd ? o.pn[f] : o.pP;
+                double ff = 0.0;
+                if (with_st) {
+                  const R klo = sd ? o.kP : o.kn[f], khi = sd ? o.kn[f] : o.kP;
+                  const R alo = sd ? o.aP : o.an[f], ahi = sd ? o.an[f] : o.aP;
+                  ff = (sigma * (0.5 * ((double)klo + (double)khi))) * (((double)ahi - (double)alo) / h);
+                }
+                qq = ff - (phi_ - plo) / h;
+              } else if (cr[cc] == (sd ? nn[cc] - 1 : 0) && bcf[f] == F_OUTLET) {
+                double pplus = sd ? 0.0 : o.pP, pminus = sd ? o.pP : 0.0;
+                qq = -(pplus - pminus) / hh;
+              }
+              qv[sd] = qq;
+            }
+            double uu = (double)o.hb[cc] + (double)o.rP * (0.5 * (qv[0] + qv[1]));
+            u = (R)uu;
+            if (!(uu == uu) || fabs(uu) > 1e30) bad = true;
+          }
+          gst(U, cc * nc + c.P, u);
+          if (acc_sum) gst(Us, cc * nc + c.P, o.us[cc] + u);
+        }
+      });
   if (bad) B.st->nonfinite = 1;
 }
 
