@@ -289,6 +289,7 @@ struct oscar_ctx {
   // per-workgroup wall-clock stamps in a small device buffer
   static constexpr int NT = 5;   // whole iteration, search direction, fine down, coarse levels, fine up
   static constexpr int TS_CAP = 64;       // stamp slots (each ts_reg regions of TS_WORDS words)
+  static_assert(TS_CAP <= 64, "the span launch flags slots in one 64-bit mask");
   static constexpr int TS_BATCH = TS_CAP / 4;   // samples per span reduction; also per chunk of iterations
   int ts_reg = 0;                       // stamp regions per sample: the launches of one iteration
   bool timing = false;
@@ -307,6 +308,7 @@ struct oscar_ctx {
   };
   std::vector<Sample> samples;   // not yet folded
   std::vector<int> ts_free;      // free stamp slots
+  std::vector<char> ts_zero;     // per stamp slot: its regions are known to be zero (no clearing before use)
   double t_ms[NT] = {0.0, 0.0, 0.0, 0.0, 0.0};
   int64_t t_cnt[NT] = {0, 0, 0, 0, 0};
   Launch L() const {
@@ -382,6 +384,7 @@ static int settle_samples(oscar_ctx *c, bool flush) {
       continue;
     }
     c->ts_free.push_back(x.slot);
+    c->ts_zero[x.slot] = 1;   // the span launch that copied it cleared its regions
     const unsigned long long *t = c->h_span + 2 * (size_t)c->ts_reg * x.slot;
     // first and last stamp of the search direction (part 0) and of the rest
     unsigned long long first[2] = {~0ull, ~0ull}, last[2] = {0ull, 0ull};
@@ -413,7 +416,10 @@ static int settle_samples(oscar_ctx *c, bool flush) {
   c->samples.swap(keep);
   if (waiting == 0 || (waiting < oscar_ctx::TS_BATCH && !flush)) return OSCAR_OK;
   const int nreg = oscar_ctx::TS_CAP * c->ts_reg;
-  launch_ts_span(c->d_ts, nreg, c->d_span, c->stream);
+  unsigned long long clear = 0ull;   // slots whose spans this launch takes: zeroed for their next use
+  for (const oscar_ctx::Sample &x : c->samples)
+    if (x.stage == oscar_ctx::S_DONE) clear |= 1ull << x.slot;
+  launch_ts_span(c->d_ts, nreg, c->d_span, c->ts_reg, clear, c->stream);
   HIPCHK(c, hipGetLastError());
   HIPCHK(c, hipMemcpyAsync(c->h_span, c->d_span, sizeof(unsigned long long) * 2 * nreg, hipMemcpyDeviceToHost,
                            c->stream));
@@ -500,7 +506,9 @@ static int enqueue_chunk(oscar_ctx *c, CgPos &q, int n) {
     if (c->timing && it % c->t_period == 0 && !c->ts_free.empty()) {
       slot = c->ts_free.back();
       c->ts_free.pop_back();
-      HIPCHK(c, hipMemsetAsync(c->d_ts + slot_words * slot, 0, sizeof(unsigned long long) * slot_words, c->stream));
+      if (!c->ts_zero[slot])
+        HIPCHK(c, hipMemsetAsync(c->d_ts + slot_words * slot, 0, sizeof(unsigned long long) * slot_words, c->stream));
+      c->ts_zero[slot] = 0;
       c->samples.push_back({q.base + it, slot, mg ? oscar_ctx::S_OPEN : oscar_ctx::S_RUN, false});
     }
     if (mg) {
@@ -1110,6 +1118,7 @@ extern "C" int32_t oscar_timing(oscar_ctx *c, int32_t period) {
     HIPCHK(c, hipMalloc((void **)&c->d_span, sizeof(unsigned long long) * 2 * regions));
     HIPCHK(c, hipHostMalloc((void **)&c->h_span, sizeof(unsigned long long) * 2 * regions, hipHostMallocDefault));
     for (int k = oscar_ctx::TS_CAP - 1; k >= 0; --k) c->ts_free.push_back(k);
+    c->ts_zero.assign(oscar_ctx::TS_CAP, 0);
   }
   c->timing = period != 0;
   if (c->timing) {

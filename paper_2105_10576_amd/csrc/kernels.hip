@@ -256,147 +256,268 @@ __global__ void __launch_bounds__(BLOCK) k_curvature(const Slot *slots, const in
 // alpha transport: upwind + van Leer/compression, Zalesak limiter
 // ---------------------------------------------------------------------------
 
+// Face fluxes of the faces each cell owns (low-order F_L and antidiffusive
+// A = F_H - F_L, with the van Leer face value and the compression flux),
+// alpha_old, and per block the largest Courant number and the phase sum.
+// The operands of a batch of cells (alpha two cells down and one up along
+// each direction for the van Leer upwind cell) are loaded first.
 template <typename R>
 __global__ void __launch_bounds__(BLOCK) k_mules_flux(const Slot *slots, const int2 *btab) {
   Block B = block_of(slots, btab);
   const Slot &s = *B.s;
   const SlotCtl &ctl = *B.ctl;
   if (!ctl.active) return;
+  const int d = s.dim, nc = s.nc;
   const R *a = (const R *)s.alpha;
   const R *phi = (const R *)(ctl.mode ? s.phi_cr : s.phi_prev);
   const R *nh = (const R *)s.nhatf;
   R *FL = (R *)s.FL, *Af = (R *)s.Af, *aold = (R *)s.alpha_old;
+  const R dtV = (R)ctl.dt / (R)s.V;
+  const int nn[3] = {s.nx, s.ny, s.nz}, st[3] = {1, s.nx, s.nxy};
+  int bcf[6];
+  for (int f = 0; f < 6; ++f) bcf[f] = s.bcf[f];
   double red[2] = {0.0, 0.0};   // max Courant, sum alpha
-  for_cells(s, B.lb, [&](const Cell &c) {
-    uint8_t fl = s.flags[c.P];
-    aold[c.P] = a[c.P];
-    for_owned_faces(s, c, [&](int e, int fi, const FView &v) {
-      R fl_ = (R)0, af = (R)0, ph = phi[fi];
-      if (v.type == F_INT) {
-        int C = ph >= (R)0 ? v.lo : v.hi;
-        int D = ph >= (R)0 ? v.hi : v.lo;
-        // cell beyond C, away from D
-        int ci = (int)(C % s.nx);
-        int t = C / s.nx;
-        int cj = (int)(t % s.ny), ck = (int)(t / s.ny);
-        int step = ph >= (R)0 ? -1 : 1;
-        int ui = ci + (e == 0 ? step : 0), uj = cj + (e == 1 ? step : 0), uk = ck + (e == 2 ? step : 0);
-        R aUU = a[C];
-        if (ui >= 0 && ui < s.nx && uj >= 0 && uj < s.ny && uk >= 0 && uk < s.nz) {
-          int U = cidx(s, ui, uj, uk);
-          if (!solid_at(s, U)) aUU = a[U];
+  struct Op {
+    Cell c;
+    uint8_t fl, flo[3];   // fl 0x80: past the end; flo: flags of the cell below per direction
+    int fi[6];
+    R aP, alo[3], alolo[3], ahi[3];   // alpha at the cell, one and two below, one above
+    R ph[6], nhl[3];                  // flux of each face of the cell, normal of the low faces
+  };
+  batched<2, Op>(
+      B.lb * BLOCK + (int)threadIdx.x, s.nblocks * BLOCK, nc,
+      [&](Op &o, int q) {
+        o.fl = 0x80;
+        if (q < nc) {
+          o.c = cell_at(s, q);
+          o.fl = s.flags[q];
         }
-        R dD = a[D] - a[C], dU = a[C] - aUU;
-        R avl = a[C] + (dU * dD > (R)0 ? (dU * dD) / (dU + dD) : (R)0);
-        R abar = (R)0.5 * (a[v.lo] + a[v.hi]);
-        R phir = fabs(ph) * nh[fi];
-        R Fc = (phir * abar) * ((R)1 - abar);
-        R FH = ph * avl + Fc;
-        fl_ = ph * a[C];
-        af = FH - fl_;
-      } else if (v.type == F_INLET || v.type == F_OUTLET) {
-        fl_ = ph * a[v.P];
-      }
-      FL[fi] = fl_;
-      Af[fi] = af;
-    });
-    if (!(fl & 0x40)) {
-      R acc = (R)0;
-      for (int f = 0; f < 2 * s.dim; ++f) {
-        CFace cf = cell_face(s, fl, c, f);
-        if (cf.type == F_NONE) continue;
-        R sp = ((f & 1) ? (R)1 : (R)-1) * phi[cf.fi];
-        if (sp > (R)0) acc = acc + sp;
-      }
-      double co = (double)(acc * ((R)ctl.dt / (R)s.V));
-      red[0] = co > red[0] ? co : red[0];
-      red[1] = red[1] + (double)a[c.P];
-    }
-  });
+      },
+      [&](Op &o) {
+        if (o.fl & 0x80) return;
+        const Cell &c = o.c;
+        const Hood hd = hood_of(s, o.fl, c);
+        const int cr[3] = {c.i, c.j, c.k};
+        o.aP = gld(a, c.P);
+#pragma unroll
+        for (int e = 0; e < 3; ++e) {
+          const int lo = cr[e] > 0 ? c.P - st[e] : c.P;
+          const int lolo = cr[e] > 1 ? c.P - 2 * st[e] : lo;
+          const int hi = cr[e] < nn[e] - 1 ? c.P + st[e] : c.P;
+          o.fi[2 * e] = hd.fi[2 * e];
+          o.fi[2 * e + 1] = hd.fi[2 * e + 1];
+          o.flo[e] = e < d ? s.flags[lo] : (uint8_t)0x40;
+          o.alo[e] = gld(a, lo);
+          o.alolo[e] = gld(a, lolo);
+          o.ahi[e] = gld(a, hi);
+          o.ph[2 * e] = e < d ? gld(phi, hd.fi[2 * e]) : (R)0;
+          o.ph[2 * e + 1] = e < d ? gld(phi, hd.fi[2 * e + 1]) : (R)0;
+          o.nhl[e] = e < d ? gld(nh, hd.fi[2 * e]) : (R)0;
+        }
+      },
+      [&]() { return true; },
+      [&](Op &o) {
+        if (o.fl & 0x80) return;
+        const Cell &c = o.c;
+        const int cr[3] = {c.i, c.j, c.k};
+        const bool fluid = !(o.fl & 0x40);
+        gst(aold, c.P, o.aP);
+#pragma unroll
+        for (int e = 0; e < 3; ++e) {
+          if (e >= d) continue;
+          int side;
+          const int t = low_face_type(s, o.fl, o.flo[e], cr[e] == 0, e, side);
+          (void)side;
+          R fl_ = (R)0, af = (R)0, ph = o.ph[2 * e];
+          if (t == F_INT) {
+            // upwind cell C, downwind D, and the cell beyond C away from D
+            // (C itself when that one is solid or outside)
+            const bool up = ph >= (R)0;
+            const R aC = up ? o.alo[e] : o.aP, aD = up ? o.aP : o.alo[e];
+            const bool uu = up ? ((o.flo[e] >> (2 * e)) & 1u) : ((o.fl >> (2 * e + 1)) & 1u);
+            R aUU = aC;
+            if (uu) aUU = up ? o.alolo[e] : o.ahi[e];
+            R dD = aD - aC, dU = aC - aUU;
+            R avl = aC + (dU * dD > (R)0 ? (dU * dD) / (dU + dD) : (R)0);
+            R abar = (R)0.5 * (o.alo[e] + o.aP);
+            R phir = fabs(ph) * o.nhl[e];
+            R Fc = (phir * abar) * ((R)1 - abar);
+            R FH = ph * avl + Fc;
+            fl_ = ph * aC;
+            af = FH - fl_;
+          } else if (t == F_INLET || t == F_OUTLET) {
+            fl_ = ph * o.aP;   // open sides: this cell is the fluid one
+          }
+          gst(FL, o.fi[2 * e], fl_);
+          gst(Af, o.fi[2 * e], af);
+          if (cr[e] == nn[e] - 1) {
+            const int tf = fluid ? bcf[2 * e + 1] : F_NONE;
+            gst(FL, o.fi[2 * e + 1], (tf == F_INLET || tf == F_OUTLET) ? o.ph[2 * e + 1] * o.aP : (R)0);
+            gst(Af, o.fi[2 * e + 1], (R)0);
+          }
+        }
+        if (fluid) {
+          R acc = (R)0;
+#pragma unroll
+          for (int f = 0; f < 6; ++f) {
+            if (f >= 2 * d) continue;
+            R sp = ((f & 1) ? (R)1 : (R)-1) * o.ph[f];
+            if (sp > (R)0) acc = acc + sp;
+          }
+          double co = (double)(acc * dtV);
+          red[0] = co > red[0] ? co : red[0];
+          red[1] = red[1] + (double)o.aP;
+        }
+      });
   put_partials<1u>(s, B.lb, CH_ADV1, red);
 }
 
+// Zalesak limiter: R+ and R- of every fluid cell from the fluxes of its
+// faces and the local bounds; operands first
 template <typename R>
 __global__ void __launch_bounds__(BLOCK) k_mules_limiter(const Slot *slots, const int2 *btab) {
   Block B = block_of(slots, btab);
   const Slot &s = *B.s;
   const SlotCtl &ctl = *B.ctl;
   if (!ctl.active) return;
+  const int d = s.dim, nc = s.nc;
   const R *a = (const R *)s.alpha;
-  const R *FL = (const R *)s.FL, *Af = (const R *)s.Af;
+  const R *FLv = (const R *)s.FL, *Afv = (const R *)s.Af;
   R *Rp = (R *)s.Rp, *Rm = (R *)s.Rm;
   const R dtV = (R)ctl.dt / (R)s.V, Vdt = (R)s.V / (R)ctl.dt;
-  for_cells(s, B.lb, [&](const Cell &c) {
-    uint8_t fl = s.flags[c.P];
-    R rp = (R)0, rm = (R)0;
-    if (!(fl & 0x40)) {
-      R sumL = (R)0, Pp = (R)0, Pm = (R)0, amax = a[c.P], amin = a[c.P];
-      for (int f = 0; f < 2 * s.dim; ++f) {
-        CFace cf = cell_face(s, fl, c, f);
-        if (cf.type == F_NONE) continue;
-        R sg = (f & 1) ? (R)1 : (R)-1;
-        sumL = sumL + sg * FL[cf.fi];
-        R sA = sg * Af[cf.fi];
-        Pp = Pp + (sA < (R)0 ? -sA : (R)0);
-        Pm = Pm + (sA > (R)0 ? sA : (R)0);
-        if (cf.type == F_INT) {
-          R an = a[cf.nb];
-          if (an > amax) amax = an;
-          if (an < amin) amin = an;
+  struct Op {
+    Cell c;
+    uint8_t fl;   // 0x80: past the end
+    R aP, an[6], F[6], A[6];
+  };
+  batched<2, Op>(
+      B.lb * BLOCK + (int)threadIdx.x, s.nblocks * BLOCK, nc,
+      [&](Op &o, int q) {
+        o.fl = 0x80;
+        if (q < nc) {
+          o.c = cell_at(s, q);
+          o.fl = s.flags[q];
         }
-      }
-      R aL = a[c.P] - dtV * sumL;
-      if (amax > (R)1) amax = (R)1;
-      if (amin < (R)0) amin = (R)0;
-      R Qp = Vdt * (amax - aL > (R)0 ? amax - aL : (R)0);
-      R Qm = Vdt * (aL - amin > (R)0 ? aL - amin : (R)0);
-      rp = Pp > (R)0 ? (Qp / Pp < (R)1 ? Qp / Pp : (R)1) : (R)0;
-      rm = Pm > (R)0 ? (Qm / Pm < (R)1 ? Qm / Pm : (R)1) : (R)0;
-    }
-    Rp[c.P] = rp;
-    Rm[c.P] = rm;
-  });
+      },
+      [&](Op &o) {
+        if (o.fl & 0xC0) return;
+        const Hood hd = hood_of(s, o.fl, o.c);
+        o.aP = gld(a, o.c.P);
+#pragma unroll
+        for (int f = 0; f < 6; ++f) {
+          o.an[f] = gld(a, hd.nb[f]);
+          o.F[f] = f < 2 * d ? gld(FLv, hd.fi[f]) : (R)0;
+          o.A[f] = f < 2 * d ? gld(Afv, hd.fi[f]) : (R)0;
+        }
+      },
+      [&]() { return true; },
+      [&](Op &o) {
+        if (o.fl & 0x80) return;
+        R rp = (R)0, rm = (R)0;
+        if (!(o.fl & 0x40)) {
+          R sumL = (R)0, Pp = (R)0, Pm = (R)0, amax = o.aP, amin = o.aP;
+#pragma unroll
+          for (int f = 0; f < 6; ++f) {
+            if (f >= 2 * d) continue;
+            R sg = (f & 1) ? (R)1 : (R)-1;
+            sumL = sumL + sg * o.F[f];
+            R sA = sg * o.A[f];
+            Pp = Pp + (sA < (R)0 ? -sA : (R)0);
+            Pm = Pm + (sA > (R)0 ? sA : (R)0);
+            if ((o.fl >> f) & 1u) {
+              R an = o.an[f];
+              if (an > amax) amax = an;
+              if (an < amin) amin = an;
+            }
+          }
+          R aL = o.aP - dtV * sumL;
+          if (amax > (R)1) amax = (R)1;
+          if (amin < (R)0) amin = (R)0;
+          R Qp = Vdt * (amax - aL > (R)0 ? amax - aL : (R)0);
+          R Qm = Vdt * (aL - amin > (R)0 ? aL - amin : (R)0);
+          rp = Pp > (R)0 ? (Qp / Pp < (R)1 ? Qp / Pp : (R)1) : (R)0;
+          rm = Pm > (R)0 ? (Qm / Pm < (R)1 ? Qm / Pm : (R)1) : (R)0;
+        }
+        gst(Rp, o.c.P, rp);
+        gst(Rm, o.c.P, rm);
+      });
 }
 
+// limited update alpha -= dt/V sum_f s_f (F_L + lambda A); with more than
+// one limiting pass the lower cell of each interior face also writes the
+// unused flux (1 - lambda) A for the next pass
 template <typename R>
 __global__ void __launch_bounds__(BLOCK) k_mules_update(const Slot *slots, const int2 *btab) {
   Block B = block_of(slots, btab);
   const Slot &s = *B.s;
   const SlotCtl &ctl = *B.ctl;
   if (!ctl.active) return;
+  const int d = s.dim, nc = s.nc;
   R *a = (R *)s.alpha;
-  const R *FL = (const R *)s.FL, *Af = (const R *)s.Af, *Rp = (const R *)s.Rp, *Rm = (const R *)s.Rm;
+  const R *FLv = (const R *)s.FL, *Afv = (const R *)s.Af, *Rpv = (const R *)s.Rp, *Rmv = (const R *)s.Rm;
   R *Arest = (R *)s.Af2;   // unused flux for the next limiting pass
   const bool more = s.mules_iter > 1;
   const R dtV = (R)ctl.dt / (R)s.V;
   double red[2] = {0.0, 0.0};   // sum alpha_new, boundary flux
-  for_cells(s, B.lb, [&](const Cell &c) {
-    uint8_t fl = s.flags[c.P];
-    if (fl & 0x40) return;
-    R acc = (R)0, bfl = (R)0;
-    for (int f = 0; f < 2 * s.dim; ++f) {
-      CFace cf = cell_face(s, fl, c, f);
-      if (cf.type == F_NONE) continue;
-      R sg = (f & 1) ? (R)1 : (R)-1;
-      R lam = (R)0;
-      if (cf.type == F_INT) {
-        int lo = (f & 1) ? c.P : cf.nb, hi = (f & 1) ? cf.nb : c.P;
-        R A = Af[cf.fi];
-        R x1 = A >= (R)0 ? Rm[lo] : Rp[lo];
-        R x2 = A >= (R)0 ? Rp[hi] : Rm[hi];
-        lam = x1 < x2 ? x1 : x2;
-        // the lower cell of an interior face writes its unused flux
-        if (more && (f & 1)) Arest[cf.fi] = ((R)1 - lam) * A;
-      } else {
-        bfl = bfl + sg * FL[cf.fi];
-      }
-      acc = acc + sg * (FL[cf.fi] + lam * Af[cf.fi]);
-    }
-    R an = a[c.P] - dtV * acc;
-    a[c.P] = an;
-    red[0] = red[0] + (double)an;
-    red[1] = red[1] + (double)bfl;
-  });
+  struct Op {
+    Cell c;
+    uint8_t fl;   // 0x80: past the end
+    int fi[6];
+    R aP, rpP, rmP, rpn[6], rmn[6], F[6], A[6];
+  };
+  batched<2, Op>(
+      B.lb * BLOCK + (int)threadIdx.x, s.nblocks * BLOCK, nc,
+      [&](Op &o, int q) {
+        o.fl = 0x80;
+        if (q < nc) {
+          o.c = cell_at(s, q);
+          o.fl = s.flags[q];
+        }
+      },
+      [&](Op &o) {
+        if (o.fl & 0xC0) return;
+        const int P = o.c.P;
+        const Hood hd = hood_of(s, o.fl, o.c);
+        o.aP = gld(a, P);
+        o.rpP = gld(Rpv, P);
+        o.rmP = gld(Rmv, P);
+#pragma unroll
+        for (int f = 0; f < 6; ++f) {
+          o.fi[f] = hd.fi[f];
+          o.rpn[f] = gld(Rpv, hd.nb[f]);
+          o.rmn[f] = gld(Rmv, hd.nb[f]);
+          o.F[f] = f < 2 * d ? gld(FLv, hd.fi[f]) : (R)0;
+          o.A[f] = f < 2 * d ? gld(Afv, hd.fi[f]) : (R)0;
+        }
+      },
+      [&]() { return true; },
+      [&](Op &o) {
+        if (o.fl & 0xC0) return;
+        R acc = (R)0, bfl = (R)0;
+#pragma unroll
+        for (int f = 0; f < 6; ++f) {
+          if (f >= 2 * d) continue;
+          R sg = (f & 1) ? (R)1 : (R)-1;
+          R lam = (R)0;
+          if ((o.fl >> f) & 1u) {
+            // R of the lower and upper cell of the face
+            const R A = o.A[f];
+            const R rplo = (f & 1) ? o.rpP : o.rpn[f], rmlo = (f & 1) ? o.rmP : o.rmn[f];
+            const R rphi = (f & 1) ? o.rpn[f] : o.rpP, rmhi = (f & 1) ? o.rmn[f] : o.rmP;
+            R x1 = A >= (R)0 ? rmlo : rplo;
+            R x2 = A >= (R)0 ? rphi : rmhi;
+            lam = x1 < x2 ? x1 : x2;
+            if (more && (f & 1)) gst(Arest, o.fi[f], ((R)1 - lam) * A);
+          } else {
+            bfl = bfl + sg * o.F[f];
+          }
+          acc = acc + sg * (o.F[f] + lam * o.A[f]);
+        }
+        R an = o.aP - dtV * acc;
+        gst(a, o.c.P, an);
+        red[0] = red[0] + (double)an;
+        red[1] = red[1] + (double)bfl;
+      });
   put_partials<0u>(s, B.lb, CH_ADV2, red);
 }
 
@@ -1558,14 +1679,21 @@ void launch_gather_states(const Launch &L, int nslots, SlotState *out) {
 }
 
 // measurement only: span (earliest start, latest end) of each stamp region;
-// workgroups that stamped nothing (zero words) are skipped
-__global__ void __launch_bounds__(BLOCK) k_ts_span(const unsigned long long *ts, unsigned long long *out) {
-  const unsigned long long *r = ts + (size_t)blockIdx.x * TS_WORDS;
+// workgroups that stamped nothing (zero words) are skipped.  Regions of the
+// groups of `per` regions whose bit is set in `clear` are zeroed once read.
+__global__ void __launch_bounds__(BLOCK) k_ts_span(unsigned long long *ts, unsigned long long *out, int per,
+                                                   unsigned long long clear) {
+  unsigned long long *r = ts + (size_t)blockIdx.x * TS_WORDS;
+  const bool zero = (clear >> (blockIdx.x / (unsigned)per)) & 1ull;
   unsigned long long lo = ~0ull, hi = 0ull;
   for (int b = threadIdx.x; b < TS_WORDS / 2; b += BLOCK) {
     const unsigned long long a = r[2 * b], e = r[2 * b + 1];
     if (a != 0ull && a < lo) lo = a;
     if (e > hi) hi = e;
+    if (zero) {
+      r[2 * b] = 0ull;
+      r[2 * b + 1] = 0ull;
+    }
   }
   __shared__ unsigned long long sl[BLOCK], sh[BLOCK];
   sl[threadIdx.x] = lo;
@@ -1584,8 +1712,9 @@ __global__ void __launch_bounds__(BLOCK) k_ts_span(const unsigned long long *ts,
   }
 }
 
-void launch_ts_span(const unsigned long long *ts, int nregions, unsigned long long *out, hipStream_t stream) {
-  hipLaunchKernelGGL(k_ts_span, dim3((unsigned)nregions), dim3(BLOCK), 0, stream, ts, out);
+void launch_ts_span(unsigned long long *ts, int nregions, unsigned long long *out, int per, unsigned long long clear,
+                    hipStream_t stream) {
+  hipLaunchKernelGGL(k_ts_span, dim3((unsigned)nregions), dim3(BLOCK), 0, stream, ts, out, per, clear);
 }
 
 void launch_state_reset(const Launch &L, int nslots) {

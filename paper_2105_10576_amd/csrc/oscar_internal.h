@@ -134,9 +134,12 @@ template <typename R> void launch_pressure_setup(const Launch &L, bool normres);
 template <typename R> void launch_cg_init(const Launch &L);
 // Measurement only: a launch given a non-null `ts` (TS_WORDS zeroed 64-bit
 // words) leaves in ts[2b], ts[2b+1] the start and end of its workgroup b on
-// the device's constant-rate wall clock; k_ts_span reduces such regions.
+// the device's constant-rate wall clock; k_ts_span reduces such regions and
+// zeroes those of the groups of `per` regions flagged in the bit mask
+// `clear` (at most 64 groups).
 constexpr int TS_WORDS = 2 * 1040;   // two words per workgroup, at most 1040 workgroups per launch
-void launch_ts_span(const unsigned long long *ts, int nregions, unsigned long long *out, hipStream_t stream);
+void launch_ts_span(unsigned long long *ts, int nregions, unsigned long long *out, int per, unsigned long long clear,
+                    hipStream_t stream);
 // n iterations from it0 (with ts: n = 1)
 template <typename R> void launch_cg_iters(const Launch &L, int it0, int n, unsigned long long *ts = nullptr);
 template <typename R> void launch_refine(const Launch &L);
