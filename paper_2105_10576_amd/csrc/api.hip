@@ -547,8 +547,8 @@ static void append_segment(std::vector<int2> &bt, int slot, int nb) {
 static double inner_rtol() {
   static double v = [] {
     const char *e = getenv("OSCAR_INNER_RTOL");
-    double x = e ? atof(e) : 1e-5;
-    return x > 0 && x < 1 ? x : 1e-5;
+    double x = e ? atof(e) : 1e-6;
+    return x > 0 && x < 1 ? x : 1e-6;
   }();
   return v;
 }
