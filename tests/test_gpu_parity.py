@@ -181,3 +181,32 @@ def test_local_operators_bitwise(shape):
     g.capillary_relax(0.5 * dtb, 1, 1, 0.0)
     r.capillary_relax(0.5 * dtb, 1, 1, 0.0)
     assert np.array_equal(g.get("alpha"), r.get("alpha"))
+
+
+@pytest.mark.parametrize("precision,precond", [(0, 0), (1, 0), (0, 1), (1, 1)])
+def test_flat_interface_zero_right_hand_side(precision, precond):
+    """A planar interface on a cell face between 90-degree walls, at rest:
+    no force, so every capillary pressure equation has a zero right-hand
+    side and its unique solution p = 0, which the GPU must return exactly
+    even from an injected nonzero p_cr; E_0 = 0, k_f = 1 and u_cr = 0, as in
+    the oracle."""
+    nx, ny = 32, 16
+    a = np.zeros((ny, nx))
+    a[:, : nx // 2] = 1.0
+    c = cases._case("flat", 2, nx, ny, 1, 1e-5, cases.AIR, cases.WATER, 0.07, 90.0,
+                    [cases.BC_WALL, cases.BC_OUTLET, cases.BC_WALL, cases.BC_WALL, 0, 0], 0.0,
+                    np.zeros(nx * ny, np.uint8), a, 1e-6, 1, 1, 1e-6)
+    c["precond"] = precond
+    g, r, c = _pair(c, precision=precision)
+    dtb = cases.brackbill_limit(c["rho1"], c["rho2"], c["h"], c["sigma"])
+    rcg, kg, Eg = g.capillary_relax(dtb * 5, 10, 10, 1e-4)
+    rco, ko, Eo = r.capillary_relax(dtb * 5, 10, 10, 1e-4)
+    assert rcg == rco == 0 and kg == ko == 1 and Eg[0] == Eo[0] == 0.0
+    assert not g.get("p_cr").any() and not r.get("p_cr").any()
+    assert not g.get("U_cr").any()
+    assert np.array_equal(g.get("alpha"), a.reshape(-1))
+    # a pressure solve of the same state from a nonzero start
+    rng = np.random.Generator(np.random.PCG64(4))
+    g.set("p_cr", rng.random(nx * ny))
+    rc, it, res = g.pressure_solve(1, dtb / 2, 1e-10, 100)
+    assert rc == 0 and not g.get("p_cr").any() and not g.get("rhs").any()
