@@ -6,10 +6,11 @@
 // Hierarchy: coarse cell = 2 x 2 (x 2) block of the finer level.  A coarse
 // face coefficient is a fixed fraction of the sum of the fine face
 // coefficients crossing it (the piecewise-constant Galerkin product, scaled
-// by one half to match a rediscretisation on the doubled spacing, by 0.62 on
+// by one half to match a rediscretisation on the doubled spacing, by 0.8 on
 // the first level); outlet coefficients are aggregated the same way.
-// Cycle: damped Jacobi sweeps (omega = 0.9) from zero before restriction and
-// after prolongation, one on the fine grid and MG_NU on the coarse levels,
+// Cycle: Jacobi sweeps (damped by 0.9 on the fine grid, plain on the coarse
+// levels) from zero before restriction and after prolongation, one on the
+// fine grid and MG_NU on the coarse levels,
 // the exact solve on the coarsest level (at most a few dozen cells) with its
 // dense inverse, formed at setup; pre- and post-smoothing are the same
 // sweeps, so the cycle is a symmetric linear operator, as the conjugate
@@ -31,20 +32,32 @@ namespace oscar {
 // Two sweeps cut the CG iterations by a third, but evaluating the first
 // sweep at the neighbours makes the latency-bound coarse kernels (and the
 // single-workgroup tail above all) about three times slower, a net loss on
-// the 128 x 64 x 64 channel; one sweep with omega = 0.9 is the faster choice.
+// the 128 x 64 x 64 channel; one sweep is the faster choice.
 constexpr int MG_NU = 1;
 constexpr int MG_TAIL_THREADS = MG_NU == 1 ? 1024 : 512;   // workgroup of the tail kernel (register budget)
 constexpr int MG_INV_THREADS = 1024;    // workgroup of the coarse inversion
-constexpr double MG_OMEGA = 0.9;        // Jacobi damping
+// Jacobi damping: plain Jacobi (1.0) on the coarse levels, 0.9 on the fine
+// grid.  Every level's operator has non-positive off-diagonal entries and a
+// diagonal at least the sum of their magnitudes (the fine one by
+// construction, a coarse one as a scaled sum of those), so 2 D - A is
+// positive semi-definite and the symmetric cycle stays positive definite up
+// to a damping of 1.  Measured (total CG iterations of one mixed step, the
+// coarse scale below): coarse damping 1.0 against 0.9 cut them 8 % on the
+// 128 x 64 x 64 channel and the 1024 x 512 micromodel and 11 % on the 256^3
+// sphere pack (0.95 lies between); the fine grid needs damping: 1.0 there
+// multiplied the iterations by five, 0.85 and 0.95 were worse than 0.9 on
+// the channel.
+constexpr double MG_OMEGA = 1.0;
+constexpr double MG_OMEGA_FINE = 0.9;
 // Scale of a coarse coefficient against the sum of the fine ones crossing
-// it: one half matches a rediscretisation on the doubled spacing; the first
-// level takes a stiffer 0.62 (measured: total CG iterations of a mixed step
-// on the 128 x 64 x 64 channel -6 %, on the 1024 x 512 micromodel -10 %, on
-// the 256^3 sphere pack -1 %, against one half on every level; 0.55-0.66 on
-// level 1 are within 1 % of each other, larger scales on the deeper levels
-// cost iterations on the sphere pack and the micromodel).
+// it: one half matches a rediscretisation on the doubled spacing and is
+// kept on the deeper levels; the first level takes a stiffer 0.8 (with the
+// damping above: 0.62 -> 0.8 cut the iterations 4 % on the channel, 1 % on
+// the micromodel, 0.3 % on the sphere pack; 0.7-0.9 lie within 1 %, 0.55 was
+// worse everywhere; larger scales on the deeper levels cost iterations on
+// the sphere pack and the micromodel).
 constexpr double MG_SCALE = 0.5;
-constexpr double MG_SCALE1 = 0.62;
+constexpr double MG_SCALE1 = 0.8;
 
 static_assert(MG_DENSE_MAX <= MG_TAIL_THREADS, "one coarsest-level cell per tail thread");
 
@@ -811,7 +824,7 @@ __device__ __forceinline__ void mg_fine_down_body(const Slot &s, int lb, int it,
   const int cnx = s.mg.lv[1].nx, cny = s.mg.lv[1].ny;
   T *b1 = (T *)s.mg.lv[1].b;
   const uint8_t *flags = s.flags;
-  const T w = (T)MG_OMEGA;
+  const T w = (T)MG_OMEGA_FINE;
   const int dim = G.dim;
   const int total = (int)kid_total(dim, cnx, cny, s.mg.lv[1].nz);
   struct Op {
@@ -935,7 +948,7 @@ __device__ __forceinline__ void mg_fine_up_body(const Slot &s, int lb, int it) {
   T *z = (T *)s.cw[0];
   const int cnx = s.mg.lv[1].nx, cnxy = s.mg.lv[1].nxy;
   const T *xc = (const T *)s.mg.lv[1].t;
-  const T w = (T)MG_OMEGA;
+  const T w = (T)MG_OMEGA_FINE;
   struct Op {
     Cell c;
     uint8_t fl;
