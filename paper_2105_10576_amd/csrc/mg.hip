@@ -10,7 +10,8 @@
 // the first level); outlet coefficients are aggregated the same way.
 // Cycle: Jacobi sweeps (damped by 0.9 on the fine grid, plain on the coarse
 // levels) from zero before restriction and after prolongation, one on the
-// fine grid and MG_NU on the coarse levels,
+// fine grid, MG_NU on the grid-wide coarse levels and MG_TAIL_NU on the
+// levels of the single-workgroup tail,
 // the exact solve on the coarsest level (at most a few dozen cells) with its
 // dense inverse, formed at setup; pre- and post-smoothing are the same
 // sweeps, so the cycle is a symmetric linear operator, as the conjugate
@@ -34,7 +35,14 @@ namespace oscar {
 // single-workgroup tail above all) about three times slower, a net loss on
 // the 128 x 64 x 64 channel; one sweep is the faster choice.
 constexpr int MG_NU = 1;
-constexpr int MG_TAIL_THREADS = MG_NU == 1 ? 1024 : 512;   // workgroup of the tail kernel (register budget)
+// Sweeps on the levels of the single-workgroup tail, where they run out of
+// LDS with barriers between them: two instead of one cut the CG iterations
+// of a mixed step 12 % on the 128 x 64 x 64 channel, 11 % on the 1024 x 512
+// micromodel and 13 % on the 256^3 sphere pack for 2.3 us more per cycle
+// (step time -7 %, -5 %, -10 %); three gain a little more on the sphere
+// pack and lose on the other two.
+constexpr int MG_TAIL_NU = 2;
+constexpr int MG_TAIL_THREADS = 1024;   // workgroup of the tail kernel
 constexpr int MG_INV_THREADS = 1024;    // workgroup of the coarse inversion
 // Jacobi damping: plain Jacobi (1.0) on the coarse levels, 0.9 on the fine
 // grid.  Every level's operator has non-positive off-diagonal entries and a
@@ -402,7 +410,7 @@ __global__ void __launch_bounds__(MG_INV_THREADS) k_mg_coarse_inv_b(const Slot *
 // t = b - A x, b_next[parent] = sum of the children's t.  (cnx, cny, cnz)
 // are the dimensions of the next coarser level; bnext may point to global
 // memory or to LDS.
-template <int DIM, typename T>
+template <int DIM, typename T, int NU = MG_NU>
 __device__ __forceinline__ void smooth_restrict(const LV<T> &L, int cnx, int cny, int cnz, T *bnext, unsigned start,
                                                 unsigned stride) {
   const T w = (T)MG_OMEGA;
@@ -420,11 +428,11 @@ __device__ __forceinline__ void smooth_restrict(const LV<T> &L, int cnx, int cny
       auto x1 = [&](int n, int, int) -> T { return w * (L.invD[n] * L.b[n]); };
       T xP;
       T Ax;
-      if constexpr (MG_NU == 1) {
+      if constexpr (NU == 1) {
         xP = x1(c.P, 0, 0);
         Ax = lmatvec<DIM, T>(L, c, x1);
       } else {
-        static_assert(MG_NU == 2, "one or two sweeps");
+        static_assert(NU == 2, "one or two sweeps");
         auto x2at = [&](const LCell &p) -> T {
           const T Ax1 = lmatvec<DIM, T>(L, p, x1);
           return x1(p.P, 0, 0) + w * (L.invD[p.P] * (L.b[p.P] - Ax1));
@@ -444,7 +452,7 @@ __device__ __forceinline__ void smooth_restrict(const LV<T> &L, int cnx, int cny
 // prolongation and post-smoothing on level L: y = x + P xc (xc on the next
 // coarser level, of dims (cnx, ., .) and plane size cnxy; global memory or
 // LDS), then MG_NU sweeps y <- y + w D^-1 (b - A y); out = y
-template <int DIM, typename T>
+template <int DIM, typename T, int NU = MG_NU>
 __device__ __forceinline__ void up_range(const LV<T> &L, int cnx, int cnxy, const T *xc, T *out, int start, int stride) {
   const T w = (T)MG_OMEGA;
   const int st[3] = {1, L.nx, L.nxy};
@@ -457,7 +465,7 @@ __device__ __forceinline__ void up_range(const LV<T> &L, int cnx, int cnxy, cons
       return y0at(p) + w * (L.invD[p.P] * (L.b[p.P] - lmatvec<DIM, T>(L, p, y0)));
     };
     T res;
-    if constexpr (MG_NU == 1) {
+    if constexpr (NU == 1) {
       res = y1at(c);
     } else {
       const T y1P = y1at(c);
@@ -465,6 +473,82 @@ __device__ __forceinline__ void up_range(const LV<T> &L, int cnx, int cnxy, cons
       res = y1P + w * (L.invD[g] * (L.b[g] - lmatvec<DIM, T>(L, c, y1)));
     }
     out[g] = res;
+  }
+}
+
+// The levels of the single-workgroup tail live in LDS, where a barrier is
+// cheap: their sweeps run one after the other over the whole level with a
+// barrier between them (rather than re-evaluating earlier sweeps at the
+// neighbours, as the grid-wide kernels must).
+//
+// Pre-smoothing of an LDS level: nu Jacobi sweeps from zero into x (t as
+// scratch), then the residual b - A x restricted into bnext in tile order.
+template <int DIM, typename T>
+__device__ __forceinline__ void tail_down(const LV<T> &L, int cnx, int cny, int cnz, T *bnext, int t0, int ns,
+                                          int nu) {
+  const T w = (T)MG_OMEGA;
+  for (int g = t0; g < L.nc; g += ns) L.x[g] = w * (L.invD[g] * L.b[g]);
+  __syncthreads();
+  T *src = L.x, *dst = L.t;
+  for (int m = 1; m < nu; ++m) {
+    for (int g = t0; g < L.nc; g += ns) {
+      const LCell c = lcell(L.nx, L.ny, g);
+      auto xs = [&](int n, int, int) -> T { return src[n]; };
+      dst[g] = src[g] + w * (L.invD[g] * (L.b[g] - lmatvec<DIM, T>(L, c, xs)));
+    }
+    __syncthreads();
+    T *tmp = src;
+    src = dst;
+    dst = tmp;
+  }
+  const unsigned total = kid_total(DIM, cnx, cny, cnz);
+  for (unsigned tau = (unsigned)t0; tau < total; tau += (unsigned)ns) {
+    const Kid q = kid_at(tau, DIM, L.nx, L.ny, L.nz, cnx, cny);
+    T tv = (T)0;
+    if (q.valid) {
+      LCell c;
+      c.P = q.P;
+      c.i = q.i;
+      c.j = q.j;
+      c.k = q.k;
+      auto xs = [&](int n, int, int) -> T { return src[n]; };
+      tv = L.b[c.P] - lmatvec<DIM, T>(L, c, xs);
+      if (src != L.x) L.x[c.P] = src[c.P];
+    }
+    tv = kid_sum(tv, DIM);
+    if (q.lead) bnext[q.parent] = tv;
+  }
+}
+
+// Prolongation and post-smoothing of an LDS level: y = x + P xc, then nu
+// Jacobi sweeps; the result goes to t (x is free once the first sweep has
+// read it).
+template <int DIM, typename T>
+__device__ __forceinline__ void tail_up(const LV<T> &L, int cnx, int cnxy, const T *xc, int t0, int ns, int nu) {
+  const T w = (T)MG_OMEGA;
+  const int st[3] = {1, L.nx, L.nxy};
+  for (int g = t0; g < L.nc; g += ns) {
+    const LCell c = lcell(L.nx, L.ny, g);
+    auto y0at = [&](const LCell &p) -> T { return L.x[p.P] + xc[(p.i >> 1) + cnx * (p.j >> 1) + cnxy * (p.k >> 1)]; };
+    auto y0 = [&](int, int e, int side) -> T { return y0at(lshift(c, e, side, st)); };
+    L.t[g] = y0at(c) + w * (L.invD[g] * (L.b[g] - lmatvec<DIM, T>(L, c, y0)));
+  }
+  __syncthreads();
+  T *src = L.t, *dst = L.x;
+  for (int m = 1; m < nu; ++m) {
+    for (int g = t0; g < L.nc; g += ns) {
+      const LCell c = lcell(L.nx, L.ny, g);
+      auto ys = [&](int n, int, int) -> T { return src[n]; };
+      dst[g] = src[g] + w * (L.invD[g] * (L.b[g] - lmatvec<DIM, T>(L, c, ys)));
+    }
+    __syncthreads();
+    T *tmp = src;
+    src = dst;
+    dst = tmp;
+  }
+  if (src != L.t) {
+    for (int g = t0; g < L.nc; g += ns) L.t[g] = src[g];
+    __syncthreads();
   }
 }
 
@@ -586,7 +670,7 @@ __device__ __forceinline__ void mg_tail_body(const Slot &s, uint4 *mg_lds) {
   };
   for (int l = tl; l < L; ++l) {
     const MGLevel &N = s.mg.lv[l + 1];
-    smooth_restrict<DIM, T>(lds_view(l), N.nx, N.ny, N.nz, in_lds(N.b), t0, ns);
+    tail_down<DIM, T>(lds_view(l), N.nx, N.ny, N.nz, in_lds(N.b), t0, ns, MG_TAIL_NU);
     __syncthreads();
   }
   // coarsest level: t = A^-1 b with the dense inverse (row t0, fixed order)
@@ -604,7 +688,7 @@ __device__ __forceinline__ void mg_tail_body(const Slot &s, uint4 *mg_lds) {
   for (int l = L - 1; l >= tl; --l) {
     const LV<T> Lv = lds_view(l);
     const MGLevel &N = s.mg.lv[l + 1];
-    up_range<DIM, T>(Lv, N.nx, N.nxy, in_lds(N.t), Lv.t, t0, ns);
+    tail_up<DIM, T>(Lv, N.nx, N.nxy, in_lds(N.t), t0, ns, MG_TAIL_NU);
     __syncthreads();
   }
   const MGLevel &M = s.mg.lv[tl];
