@@ -521,10 +521,10 @@ __device__ __forceinline__ void tail_down(const LV<T> &L, int cnx, int cny, int 
 }
 
 // Prolongation and post-smoothing of an LDS level: y = x + P xc, then nu
-// Jacobi sweeps; the result goes to t (x is free once the first sweep has
-// read it).
+// Jacobi sweeps alternating between t and x (x is free once the first sweep
+// has read it); returns the array holding the result.
 template <int DIM, typename T>
-__device__ __forceinline__ void tail_up(const LV<T> &L, int cnx, int cnxy, const T *xc, int t0, int ns, int nu) {
+__device__ __forceinline__ const T *tail_up(const LV<T> &L, int cnx, int cnxy, const T *xc, int t0, int ns, int nu) {
   const T w = (T)MG_OMEGA;
   const int st[3] = {1, L.nx, L.nxy};
   for (int g = t0; g < L.nc; g += ns) {
@@ -546,10 +546,7 @@ __device__ __forceinline__ void tail_up(const LV<T> &L, int cnx, int cnxy, const
     src = dst;
     dst = tmp;
   }
-  if (src != L.t) {
-    for (int g = t0; g < L.nc; g += ns) L.t[g] = src[g];
-    __syncthreads();
-  }
+  return src;
 }
 
 // Each multigrid kernel comes in two forms over one body: for one context
@@ -685,14 +682,15 @@ __device__ __forceinline__ void mg_tail_body(const Slot &s, uint4 *mg_lds) {
     }
   }
   __syncthreads();
+  const T *tc = in_lds(s.mg.lv[L].t);   // correction of the level below, wherever its sweeps left it
   for (int l = L - 1; l >= tl; --l) {
     const LV<T> Lv = lds_view(l);
     const MGLevel &N = s.mg.lv[l + 1];
-    tail_up<DIM, T>(Lv, N.nx, N.nxy, in_lds(N.t), t0, ns, MG_TAIL_NU);
+    tc = tail_up<DIM, T>(Lv, N.nx, N.nxy, tc, t0, ns, MG_TAIL_NU);
     __syncthreads();
   }
   const MGLevel &M = s.mg.lv[tl];
-  const T *tsrc = in_lds(M.t);
+  const T *tsrc = tc;
   T *tdst = (T *)M.t;
   for (int g = t0; g < M.nc; g += ns) tdst[g] = tsrc[g];
 }
