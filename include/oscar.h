@@ -64,8 +64,10 @@ extern "C" {
 
 /* preconditioner of the pressure conjugate gradient (oscar_desc.precond) */
 #define OSCAR_PC_JACOBI 0          /* diagonal scaling */
-#define OSCAR_PC_MG 1              /* one geometric multigrid V-cycle: 2^dim-cell aggregation, damped Jacobi
-                                      smoothing, coefficients re-coarsened at every solve */
+#define OSCAR_PC_MG 1              /* one geometric multigrid V-cycle: 2^dim-cell aggregation, Jacobi
+                                      smoothing; coarse operators rebuilt from 1/a_P at every viscous step and
+                                      every 4th capillary sub-step (a preconditioner only: each solve still
+                                      meets pcg_rtol on the current operator) */
 
 /* field identifiers for oscar_get_field / oscar_set_field */
 #define OSCAR_FIELD_ALPHA 0        /* cells */
