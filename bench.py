@@ -113,6 +113,28 @@ def run_gpu(case, precision, steps, warmup, precond=1, timing_period=TIMING_PERI
     return res
 
 
+def step_roofline(precision, precond, dim, n_fluid, nc, nc1, iters_per_step, cg_per_step, refine_per_step, sec_per_step):
+    """Whole-step algorithmic bytes and the Mcell-iter/s they allow at the
+    HBM peak: per relaxation iteration (and the viscous step) the non-CG
+    kernels' (35 d + 54) words per fluid cell (advection, curvature,
+    assembly, three correctors' predictor, set-up and correction), per CG
+    iteration the fine-grid kernels' bytes (multigrid: search direction,
+    fine down, fine up; the coarse levels are not counted) or k_cg's, per
+    outer refinement step 48 B per fluid cell (k_refine_x, k_refine_res)."""
+    w = word(precision)
+    if precond == 1:
+        cg = sum(mg_part_bytes(k, precision, n_fluid, nc, nc1) for k in (1, 2, 4))
+    else:
+        cg = jacobi_cg_bytes(precision, n_fluid, nc)
+    b = iters_per_step * n_fluid * (35 * dim + 54) * w + cg_per_step * cg + refine_per_step * 48 * n_fluid
+    achieved = b / sec_per_step / 1e9
+    return {"alg_bytes_per_step": int(b), "achieved_GBs": round(achieved, 1),
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "mcell_iter_s_at_peak": round(nc * iters_per_step / (b / (HBM_PEAK_GBS * 1e9)) / 1e6, 1),
+            "counts": "non-CG (35d+54) words per fluid cell per iteration, CG fine-grid kernels, 48 B per "
+                      "fluid cell per refinement step"}
+
+
 def kernel_table(r, precision, precond, n_fluid, nc, nc1):
     """Per-part average durations [us] and, for the fine-grid kernels, GB/s."""
     out = {}
@@ -169,7 +191,7 @@ def run_reps(case, precision, reps, warmup, max_iters, precond=1):
 
     from paper_2105_10576_amd import oscar
 
-    times, pcg, kfs = [], [], []
+    times, pcg, kfs, refs = [], [], [], []
     acc = {k: [0.0, 0] for k in range(5)}
     for r in range(warmup + reps):
         g = oscar.Oscar(case, precision=precision, device="cuda:0", precond=precond)
@@ -179,9 +201,12 @@ def run_reps(case, precision, reps, warmup, max_iters, precond=1):
             g.timing(TIMING_PERIOD)
         t0 = time.perf_counter()
         g.viscous_step(case["dt_vd"])
-        it = g.stats()["pcg_iters_call"]
+        st = g.stats()
+        it, ref = st["pcg_iters_call"], st["refine_steps_call"]
         rc, kf, E = g.capillary_relax(case["dt_vd"], case["n_sub"], max_iters, 0.0)
-        it += g.stats()["pcg_iters_call"]
+        st = g.stats()
+        it += st["pcg_iters_call"]
+        ref += st["refine_steps_call"]
         torch.cuda.synchronize()
         t = time.perf_counter() - t0
         print("[bench] repetition %d (%s): %.3f s, k_f %d" % (r, "timed" if timed else "warm-up", t, kf),
@@ -195,11 +220,12 @@ def run_reps(case, precision, reps, warmup, max_iters, precond=1):
             times.append(t)
             pcg.append(it)
             kfs.append(kf)
+            refs.append(ref)
         g.close()
     order = sorted(range(reps), key=lambda x: times[x])
     m = order[len(order) // 2]
-    return dict(seconds=times[m], pcg_iters=pcg[m], k_f=kfs[m], parts={k: tuple(v) for k, v in acc.items()},
-                times=times)
+    return dict(seconds=times[m], pcg_iters=pcg[m], k_f=kfs[m], refine_steps=refs[m],
+                parts={k: tuple(v) for k, v in acc.items()}, times=times)
 
 
 CONFIGS = {
@@ -239,13 +265,16 @@ def bench_config(args):
                "roofline": {"bound": "hbm", "kernel": dom, "achieved": ktab[dom]["GBs"], "peak": HBM_PEAK_GBS,
                             "unit": "GB/s", "frac": round(ktab[dom]["GBs"] / HBM_PEAK_GBS, 4),
                             "avg_launch_us": ktab[dom]["avg_us"], "alg_bytes_per_launch": ktab[dom]["alg_bytes"]},
-               "kernels": ktab}
+               "kernels": ktab,
+               "step_roofline": step_roofline(prec, pc, dim, n_fluid, nc, nc1, 1 + r["k_f"], r["pcg_iters"],
+                                              r["refine_steps"], r["seconds"])}
         if prec == 1:
             out.update(value=res["value"], ms_per_step=res["ms_per_step"], steps=3, warmup=1,
                        config={"workload": fmt % (n_fluid, kmax, case["n_sub"], "multigrid" if pc else "Jacobi"),
                                "precision": "mixed", "pcg_iters_per_step": r["pcg_iters"],
                                "repetitions": "1 warm-up + 3 from the initial state, median"},
-                       roofline=dict(res["roofline"], traffic=None), kernels=ktab)
+                       roofline=dict(res["roofline"], traffic=None), kernels=ktab,
+                       step_roofline=res["step_roofline"])
         else:
             out["fp64"] = res
     print(json.dumps(out), flush=True)
@@ -361,6 +390,9 @@ def main():
             "timing": "device wall-clock stamps of every %d-th CG iteration of the timed steps" % TIMING_PERIOD,
         },
         "kernels": ktab,
+        "step_roofline": step_roofline(1, pc, 3, n_fluid, nc, nc1, mixed["iters"] / args.steps,
+                                       mixed["pcg_iters"] / args.steps, mixed["refine_steps"] / args.steps,
+                                       mixed["seconds"] / args.steps),
     }
     if not args.no_fp64:
         f = run_gpu(case, 0, args.fp64_steps, 1, precond=pc)
@@ -375,6 +407,8 @@ def main():
             "achieved_GBs": ftab[fdom]["GBs"],
             "frac": round(ftab[fdom]["GBs"] / HBM_PEAK_GBS, 4),
             "kernels": ftab,
+            "step_roofline": step_roofline(0, pc, 3, n_fluid, nc, nc1, f["iters"] / args.fp64_steps,
+                                           f["pcg_iters"] / args.fp64_steps, 0, f["seconds"] / args.fp64_steps),
         }
     if not args.no_serving:
         from paper_2105_10576_amd import serving_bench
