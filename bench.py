@@ -280,19 +280,37 @@ def bench_config(args):
     print(json.dumps(out), flush=True)
 
 
-def cpu_baseline(case):
+def cpu_baseline(case, precond=1):
     """The FP64 oracle on the host: the first viscous-drag step of the same
-    workload (3 PISO correctors with Jacobi-PCG), one cell-iteration per cell."""
+    workload (3 PISO correctors with Jacobi-PCG), one cell-iteration per cell.
+    The same step on the GPU (both paths, from the same initial state) is
+    compared with it: relative L-infinity error of alpha, p_vd and U_vd."""
+    import numpy as np
+
     from oracle.pyoracle import Oracle
+    from paper_2105_10576_amd import oscar
 
     o = Oracle(case)
     t0 = time.perf_counter()
     rc = o.viscous_step(case["dt_vd"])
     t = time.perf_counter() - t0
     nc = case["nx"] * case["ny"] * case["nz"]
+    err = {}
+    for prec, name in ((1, "mixed"), (0, "fp64")):
+        g = oscar.Oscar(case, precision=prec, device="cuda:0", precond=precond)
+        g.viscous_step(case["dt_vd"])
+        e = {}
+        for f in ("alpha", "p_vd", "U_vd"):   # the viscous step's own fields (p, U combine after a relaxation)
+            ref = o.get(f)
+            den = float(np.abs(ref).max()) or 1.0
+            e[f] = float("%.3g" % (float(np.abs(g.get(f) - ref).max()) / den))
+        err[name] = e
+        g.close()
     return dict(value=nc / t / 1e6, unit="Mcell-iter/s", cores=1, kind="oracle",
                 sample="first viscous-drag step of the same grid (1 cell-iteration per cell, %d PCG iterations), "
-                       "single-threaded FP64 oracle, %.1f s" % (o.stats()["pcg_iters_step"], t))
+                       "single-threaded FP64 oracle, %.1f s" % (o.stats()["pcg_iters_step"], t),
+                error_vs_oracle=dict(err, prefix="the same first viscous-drag step on the GPU, relative L-infinity; "
+                                                 "both sides solve to the workload's pressure rtol"))
 
 
 def main():
@@ -417,7 +435,7 @@ def main():
                                            precond=1 if args.precond == "mg" else 0,
                                            log=lambda m: print("[serving] " + m, file=sys.stderr, flush=True))
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(case)
+        out["cpu_baseline"] = cpu_baseline(case, pc)
     print(json.dumps(out), flush=True)
 
 
