@@ -306,7 +306,16 @@ def cpu_baseline(case, precond=1):
             e[f] = float("%.3g" % (float(np.abs(g.get(f) - ref).max()) / den))
         err[name] = e
         g.close()
+    cpu = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return dict(value=nc / t / 1e6, unit="Mcell-iter/s", cores=1, kind="oracle",
+                host=dict(cpu=cpu, threads_available=os.cpu_count()),
                 sample="first viscous-drag step of the same grid (1 cell-iteration per cell, %d PCG iterations), "
                        "single-threaded FP64 oracle, %.1f s" % (o.stats()["pcg_iters_step"], t),
                 error_vs_oracle=dict(err, prefix="the same first viscous-drag step on the GPU, relative L-infinity; "
