@@ -58,8 +58,8 @@ def jacobi_cg_bytes(precision, n_fluid, nc):
 def mg_part_bytes(part, precision, n_fluid, nc, nc1):
     """Algorithmic bytes of the fine-grid kernels of one multigrid-preconditioned
     iteration (nc1: cells of the first coarse level).
-      k_mgcg_dir:     reads z, d_old, rAU; writes d, q                   5 w
-                      (mixed: q = A z + beta q_old also reads q_old     6 w)
+      k_mgcg_dir:     reads z, rAU, d_old, q_old (q = A z + beta q_old);
+                      writes d, q                                        6 w
       k_mg_fine_down: reads r, q, D^-1, rAU, d and x; writes x, r_new, z0
                       (x: FP64 pressure or FP32 correction, read and written)
                       7 w + 2 |x|, + the level-1 right-hand side (nc1 w)
@@ -68,7 +68,7 @@ def mg_part_bytes(part, precision, n_fluid, nc, nc1):
     plus the face-flag byte of every cell."""
     w = word(precision)
     if part == 1:
-        return n_fluid * (5 if precision == 0 else 6) * w + nc
+        return n_fluid * 6 * w + nc
     if part == 2:
         x = 16 if precision == 0 else 2 * w
         return n_fluid * (7 * w + x) + nc1 * w + nc

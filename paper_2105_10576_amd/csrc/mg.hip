@@ -760,11 +760,13 @@ __device__ __forceinline__ bool mgcg_dir_body(const Slot &s, int lb, int it) {
   const uint8_t *flags = s.flags;
   const T *z = (const T *)s.cw[0], *dold = first ? z : (const T *)s.cs[(it + 1) & 1];
   T *dn = (T *)s.cs[it & 1], *q = (T *)s.cp;
-  // The FP32 inner solve of the mixed path forms q = A d as A z + beta q_old
-  // (the same vector in exact arithmetic; the outer FP64 refinement absorbs
-  // the rounding the recurrence adds), which needs d_old and q_old at the
-  // cell only; the FP64 solve applies A to d itself.
-  constexpr bool rec = sizeof(T) == 4;
+  // q = A d is formed as A z + beta q_old (the same vector in exact
+  // arithmetic, as in Chronopoulos and Gear's CG), which needs d_old and
+  // q_old at the cell only: one array fewer at the six neighbours.  The
+  // rounding the recurrence adds stays at the level of the solve's own
+  // (in the mixed path the outer FP64 refinement measures the true
+  // residual; the FP64 path's parity with the oracle is tested to 50 steps).
+  constexpr bool rec = true;
   struct Op {
     Cell c;
     uint8_t fl;
