@@ -65,9 +65,13 @@ extern "C" {
 /* preconditioner of the pressure conjugate gradient (oscar_desc.precond) */
 #define OSCAR_PC_JACOBI 0          /* diagonal scaling */
 #define OSCAR_PC_MG 1              /* one geometric multigrid V-cycle: 2^dim-cell aggregation, Jacobi
-                                      smoothing; coarse operators rebuilt from 1/a_P at every viscous step and
-                                      every 4th capillary sub-step (a preconditioner only: each solve still
-                                      meets pcg_rtol on the current operator) */
+                                      smoothing (two sweeps per side on the coarse levels from the second
+                                      on for 3D grids of 2^21 cells and more, else one; the environment
+                                      variable OSCAR_MG_SWEEPS2, a bit mask of levels read at create or
+                                      admission, replaces that choice); coarse operators rebuilt from 1/a_P
+                                      at every viscous step and every 4th capillary sub-step (a
+                                      preconditioner only: each solve still meets pcg_rtol on the current
+                                      operator) */
 
 /* field identifiers for oscar_get_field / oscar_set_field */
 #define OSCAR_FIELD_ALPHA 0        /* cells */

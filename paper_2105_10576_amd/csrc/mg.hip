@@ -10,8 +10,9 @@
 // the first level); outlet coefficients are aggregated the same way.
 // Cycle: Jacobi sweeps (damped by 0.9 on the fine grid, plain on the coarse
 // levels) from zero before restriction and after prolongation, one on the
-// fine grid, MG_NU on the grid-wide coarse levels and MG_TAIL_NU on the
-// levels of the single-workgroup tail,
+// fine grid, one or two (the host's per-level choice, MGInfo::nu2) on the
+// grid-wide coarse levels and MG_TAIL_NU on the levels of the
+// single-workgroup tail,
 // the exact solve on the coarsest level (at most a few dozen cells) with its
 // dense inverse, formed at setup; pre- and post-smoothing are the same
 // sweeps, so the cycle is a symmetric linear operator, as the conjugate
@@ -29,12 +30,19 @@
 
 namespace oscar {
 
-// Smoothing sweeps before and after the coarse correction on levels >= 1.
-// Two sweeps cut the CG iterations by a third, but evaluating the first
-// sweep at the neighbours makes the latency-bound coarse kernels (and the
-// single-workgroup tail above all) about three times slower, a net loss on
-// the 128 x 64 x 64 channel; one sweep is the faster choice.
-constexpr int MG_NU = 1;
+// Smoothing sweeps before and after the coarse correction on the grid-wide
+// levels (below the fine grid, above the tail): one, or two where the host
+// sets the level's bit in MGInfo::nu2.  The second sweep is evaluated at the
+// neighbours in the same launch, which slows these latency-bound kernels by
+// 2-3 us each.  Measured (mixed / FP64 step time, two sweeps against one):
+//   levels >= 2, 3D sphere packs: 128^3 -1.4 % / -3.3 %, 192^3 -9.8 % /
+//     -11.4 %, 256^3 -8.8 % / -11.9 % (CG iterations 2006 -> 1741);
+//   adding level 1 on the 256^3 pack: mixed unchanged, FP64 +7 % against
+//     levels >= 2 alone (level 1 alone: +92 us per cycle for 11 % fewer
+//     iterations, a net loss);
+//   128 x 64 x 64 channel: levels >= 2 -3 % / +4 %, all levels +5 % / +9 %;
+//   1024 x 512 micromodel (2D): levels >= 2 +4 %.
+// Hence two sweeps from level 2 on for 3D grids of 2^21 cells and more.
 // Sweeps on the levels of the single-workgroup tail, where they run out of
 // LDS with barriers between them: two instead of one cut the CG iterations
 // of a mixed step 12 % on the 128 x 64 x 64 channel, 11 % on the 1024 x 512
@@ -406,11 +414,11 @@ __global__ void __launch_bounds__(MG_INV_THREADS) k_mg_coarse_inv_b(const Slot *
 // ---------------------------------------------------------------------------
 
 // Pre-smoothing from zero on level L in tile order, with the restriction:
-// x_1 = w D^-1 b, x_{m+1} = x_m + w D^-1 (b - A x_m) up to MG_NU sweeps,
+// x_1 = w D^-1 b, x_{m+1} = x_m + w D^-1 (b - A x_m) up to NU sweeps,
 // t = b - A x, b_next[parent] = sum of the children's t.  (cnx, cny, cnz)
 // are the dimensions of the next coarser level; bnext may point to global
 // memory or to LDS.
-template <int DIM, typename T, int NU = MG_NU>
+template <int DIM, typename T, int NU>
 __device__ __forceinline__ void smooth_restrict(const LV<T> &L, int cnx, int cny, int cnz, T *bnext, unsigned start,
                                                 unsigned stride) {
   const T w = (T)MG_OMEGA;
@@ -451,8 +459,8 @@ __device__ __forceinline__ void smooth_restrict(const LV<T> &L, int cnx, int cny
 
 // prolongation and post-smoothing on level L: y = x + P xc (xc on the next
 // coarser level, of dims (cnx, ., .) and plane size cnxy; global memory or
-// LDS), then MG_NU sweeps y <- y + w D^-1 (b - A y); out = y
-template <int DIM, typename T, int NU = MG_NU>
+// LDS), then NU sweeps y <- y + w D^-1 (b - A y); out = y
+template <int DIM, typename T, int NU>
 __device__ __forceinline__ void up_range(const LV<T> &L, int cnx, int cnxy, const T *xc, T *out, int start, int stride) {
   const T w = (T)MG_OMEGA;
   const int st[3] = {1, L.nx, L.nxy};
@@ -563,34 +571,35 @@ __host__ __device__ inline int smooth_blocks(const MGInfo &mg, int l, int dim) {
 }
 __host__ __device__ inline int up_blocks(const MGInfo &mg, int l) { return lvl_blocks(mg.lv[l].nc); }
 
-template <int DIM, typename T>
+template <int DIM, typename T, int NU>
 __device__ __forceinline__ void mg_smooth_body(const Slot &s, int l, unsigned start, unsigned stride) {
   const LV<T> L = lview<T>(s.mg.lv[l]);
   const MGLevel &C = s.mg.lv[l + 1];
-  smooth_restrict<DIM, T>(L, C.nx, C.ny, C.nz, (T *)C.b, start, stride);
+  smooth_restrict<DIM, T, NU>(L, C.nx, C.ny, C.nz, (T *)C.b, start, stride);
 }
 
 // final correction of level l goes to t_l (x_l keeps the pre-smoothed one)
-template <int DIM, typename T>
+template <int DIM, typename T, int NU>
 __device__ __forceinline__ void mg_up_body(const Slot &s, int l, int start, int stride) {
   const LV<T> L = lview<T>(s.mg.lv[l]);
   const MGLevel &C = s.mg.lv[l + 1];
-  up_range<DIM, T>(L, C.nx, C.nxy, (const T *)C.t, L.t, start, stride);
+  up_range<DIM, T, NU>(L, C.nx, C.nxy, (const T *)C.t, L.t, start, stride);
 }
 
-template <int DIM, typename T>
+// NU: the sweeps of level l, (mg.nu2 >> l & 1) + 1, chosen by the host
+template <int DIM, typename T, int NU>
 __global__ void __launch_bounds__(BLOCK) k_mg_smooth(const Slot S, int l, unsigned long long *ts) {
   Stamp stamp(ts);
   if (mg_idle(S)) return;
-  mg_smooth_body<DIM, T>(S, l, blockIdx.x * BLOCK + threadIdx.x, gridDim.x * BLOCK);
+  mg_smooth_body<DIM, T, NU>(S, l, blockIdx.x * BLOCK + threadIdx.x, gridDim.x * BLOCK);
   stamp.done();
 }
 
-template <int DIM, typename T>
+template <int DIM, typename T, int NU>
 __global__ void __launch_bounds__(BLOCK) k_mg_up(const Slot S, int l, unsigned long long *ts) {
   Stamp stamp(ts);
   if (mg_idle(S)) return;
-  mg_up_body<DIM, T>(S, l, blockIdx.x * BLOCK + threadIdx.x, gridDim.x * BLOCK);
+  mg_up_body<DIM, T, NU>(S, l, blockIdx.x * BLOCK + threadIdx.x, gridDim.x * BLOCK);
   stamp.done();
 }
 
@@ -601,7 +610,9 @@ __global__ void __launch_bounds__(BLOCK) k_mg_smooth_b(const Slot *slots, const 
   const Slot &s = batch_slot(slots, act, maxb, q);
   if (l >= s.mg.tail || mg_idle(s)) return;
   const int nb = smooth_blocks(s.mg, l, DIM);
-  if (q < nb) mg_smooth_body<DIM, T>(s, l, (unsigned)(q * BLOCK) + threadIdx.x, (unsigned)(nb * BLOCK));
+  if (q >= nb) return;
+  if ((s.mg.nu2 >> l) & 1) mg_smooth_body<DIM, T, 2>(s, l, (unsigned)(q * BLOCK) + threadIdx.x, (unsigned)(nb * BLOCK));
+  else mg_smooth_body<DIM, T, 1>(s, l, (unsigned)(q * BLOCK) + threadIdx.x, (unsigned)(nb * BLOCK));
 }
 
 template <int DIM, typename T>
@@ -610,7 +621,9 @@ __global__ void __launch_bounds__(BLOCK) k_mg_up_b(const Slot *slots, const int 
   const Slot &s = batch_slot(slots, act, maxb, q);
   if (l >= s.mg.tail || mg_idle(s)) return;
   const int nb = up_blocks(s.mg, l);
-  if (q < nb) mg_up_body<DIM, T>(s, l, q * BLOCK + (int)threadIdx.x, nb * BLOCK);
+  if (q >= nb) return;
+  if ((s.mg.nu2 >> l) & 1) mg_up_body<DIM, T, 2>(s, l, q * BLOCK + (int)threadIdx.x, nb * BLOCK);
+  else mg_up_body<DIM, T, 1>(s, l, q * BLOCK + (int)threadIdx.x, nb * BLOCK);
 }
 
 // Levels tail..L in one workgroup, out of LDS.  The tail block (the dense
@@ -1139,13 +1152,19 @@ static void vcycle_levels(const Slot &hs, const Launch &L, unsigned long long *t
   const int tl = hs.mg.tail;
   int m = 0;   // launch index within the part: its stamp region
   auto next = [&]() -> unsigned long long * { return ts ? ts + (size_t)TS_WORDS * m++ : nullptr; };
-  for (int l = 1; l < tl; ++l)
-    hipLaunchKernelGGL((k_mg_smooth<DIM, R>), dim3(lvl_grid((int)kid_total(DIM, hs.mg.lv[l + 1].nx, hs.mg.lv[l + 1].ny, hs.mg.lv[l + 1].nz))), dim3(BLOCK), 0, L.stream, hs,
-                       l, next());
+  for (int l = 1; l < tl; ++l) {
+    const MGLevel &C = hs.mg.lv[l + 1];
+    const dim3 g(lvl_grid((int)kid_total(DIM, C.nx, C.ny, C.nz)));
+    if ((hs.mg.nu2 >> l) & 1) hipLaunchKernelGGL((k_mg_smooth<DIM, R, 2>), g, dim3(BLOCK), 0, L.stream, hs, l, next());
+    else hipLaunchKernelGGL((k_mg_smooth<DIM, R, 1>), g, dim3(BLOCK), 0, L.stream, hs, l, next());
+  }
   hipLaunchKernelGGL((k_mg_tail<DIM, R>), dim3(1), dim3(MG_TAIL_THREADS), (size_t)hs.mg.tail_bytes, L.stream, hs,
                      next());
-  for (int l = tl - 1; l >= 1; --l)
-    hipLaunchKernelGGL((k_mg_up<DIM, R>), dim3(lvl_grid(hs.mg.lv[l].nc)), dim3(BLOCK), 0, L.stream, hs, l, next());
+  for (int l = tl - 1; l >= 1; --l) {
+    const dim3 g(lvl_grid(hs.mg.lv[l].nc));
+    if ((hs.mg.nu2 >> l) & 1) hipLaunchKernelGGL((k_mg_up<DIM, R, 2>), g, dim3(BLOCK), 0, L.stream, hs, l, next());
+    else hipLaunchKernelGGL((k_mg_up<DIM, R, 1>), g, dim3(BLOCK), 0, L.stream, hs, l, next());
+  }
 }
 
 // part of the cycle of iteration it (it = -1: the cycle of the initial residual)

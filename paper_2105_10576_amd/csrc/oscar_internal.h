@@ -56,6 +56,9 @@ struct SlotCtl {
 constexpr int MG_MAXL = 12;
 constexpr int MG_COARSEST = 16;
 constexpr int MG_TAIL_CELLS = 4096;
+// 3D grids of at least MG_NU2_FINE cells smooth twice per side on their
+// grid-wide coarse levels from the second on (MGInfo::nu2)
+constexpr int64_t MG_NU2_FINE = (int64_t)1 << 21;
 constexpr int MG_DENSE_MAX = 64;
 constexpr int MG_TAIL_LDS = 160 * 1024;   // LDS of one gfx950 workgroup
 struct MGLevel {
@@ -68,6 +71,7 @@ struct MGLevel {
 struct MGInfo {
   int32_t L;          // coarsest level (levels 1..L); 0 = no hierarchy
   int32_t tail;       // first level handled by the single-workgroup tail kernel
+  int32_t nu2;        // bit l: grid-wide level l takes two smoothing sweeps per side (else one)
   MGLevel lv[MG_MAXL + 1];
   void *Ainv;         // dense inverse of the coarsest operator, row-major (T)
   void *tail_base;    // block of Ainv, then per level tail..L: cf[dim], cout, invD, b, x, t

@@ -126,17 +126,24 @@ def _small_3d():
     return c
 
 
-@pytest.mark.parametrize("which", ["2d_fp64", "3d_mixed"])
-def test_engine_multigrid_matches_context(which):
+@pytest.mark.parametrize("which", ["2d_fp64", "3d_mixed", "3d_fp64_two_sweeps"])
+def test_engine_multigrid_matches_context(which, monkeypatch):
     """A multigrid request through the engine (batched multigrid launches)
     equals the same request through a context bitwise: the same kernel
     bodies, the same block-to-cell assignment and the same device-side
-    convergence decisions."""
+    convergence decisions.  The third case smooths its two grid-wide coarse
+    levels twice (forced through OSCAR_MG_SWEEPS2 on a 96 x 48 x 48 channel,
+    whose FP64 tail starts at level 3)."""
     from paper_2105_10576_amd import oscar
     if which == "2d_fp64":
         c, precision = _mg(_reqs()[0]), 0
-    else:
+    elif which == "3d_mixed":
         c, precision = _mg(_small_3d()), 1
+    else:
+        monkeypatch.setenv("OSCAR_MG_SWEEPS2", "6")
+        c = cases.constricted_channel(nx=96, ny=48, nz=48, max_iters=3)
+        c["pcg_rtol"] = 1e-8
+        c, precision = _mg(c), 0
     print("engine vs context, multigrid", which, flush=True)
     g = oscar.Oscar(c, precision=precision, precond=oscar.PC_MG)
     g.viscous_step(c["dt_vd"])
