@@ -95,14 +95,13 @@ void mg_levels(const oscar_desc &D, MGInfo &mg) {
       break;
     }
   mg.tail_bytes = (int32_t)mg_tail_bytes(mg, mg.tail, D.dim, w);
-  // Smoothing sweeps of the grid-wide coarse levels: two from level 2 on for
-  // 3D grids of at least MG_NU2_FINE cells, else one.  A second sweep cuts
-  // the CG iterations but makes these latency-bound kernels slower; it pays
-  // where the fine kernels dominate a cycle and on the cheaper levels.  The
+  // Smoothing sweeps of the grid-wide coarse levels: two from level 2 on in
+  // 3D, else one.  A second sweep cuts the CG iterations but makes these
+  // latency-bound kernels slower; it pays on the levels below the first.  The
   // environment variable OSCAR_MG_SWEEPS2 (a mask of levels, read at each
   // hierarchy construction) replaces the rule, for tests and tuning.
   mg.nu2 = 0;
-  if (D.dim == 3 && (int64_t)D.nx * D.ny * D.nz >= MG_NU2_FINE)
+  if (D.dim == 3)
     for (int l = 2; l < mg.tail; ++l) mg.nu2 |= 1 << l;
   if (const char *e = getenv("OSCAR_MG_SWEEPS2")) mg.nu2 = (int32_t)strtol(e, nullptr, 0);
   mg.nu2 &= ((1 << mg.tail) - 1) & ~1;

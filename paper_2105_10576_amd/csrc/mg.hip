@@ -33,16 +33,19 @@ namespace oscar {
 // Smoothing sweeps before and after the coarse correction on the grid-wide
 // levels (below the fine grid, above the tail): one, or two where the host
 // sets the level's bit in MGInfo::nu2.  The second sweep is evaluated at the
-// neighbours in the same launch, which slows these latency-bound kernels by
-// 2-3 us each.  Measured (mixed / FP64 step time, two sweeps against one):
-//   levels >= 2, 3D sphere packs: 128^3 -1.4 % / -3.3 %, 192^3 -9.8 % /
-//     -11.4 %, 256^3 -8.8 % / -11.9 % (CG iterations 2006 -> 1741);
-//   adding level 1 on the 256^3 pack: mixed unchanged, FP64 +7 % against
-//     levels >= 2 alone (level 1 alone: +92 us per cycle for 11 % fewer
-//     iterations, a net loss);
-//   128 x 64 x 64 channel: levels >= 2 -3 % / +4 %, all levels +5 % / +9 %;
-//   1024 x 512 micromodel (2D): levels >= 2 +4 %.
-// Hence two sweeps from level 2 on for 3D grids of 2^21 cells and more.
+// neighbours in the same launch (sweep_matvec: a radius-2 stencil, each
+// operand loaded once), which makes these latency-bound kernels slower.
+// Measured (mixed / FP64 step time, two sweeps against one):
+//   levels >= 2: 128 x 64 x 64 channel -1.5 % / +0.9 % (CG iterations 566
+//     -> 516, coarse part of a cycle +3.3 us); 3D sphere packs 128^3 -1.4 % /
+//     -3.3 %, 192^3 -9.8 % / -11.4 %, 256^3 -9 % / -13 % (2006 -> 1741);
+//   adding level 1 (the expensive one: +92 us per cycle on the 256^3 pack
+//     for 11 % fewer iterations) loses;
+//   1024 x 512 micromodel (2D): level 2 +1 % / +5 %, levels 2 and 3 +2 % /
+//     +7 %.
+// Hence two sweeps from level 2 on in 3D, one in 2D.  (The sphere packs of
+// 128^3 and 192^3 and the level-1 case were measured before the stencil's
+// loads were de-duplicated, which took 1-4 us off each cycle.)
 // Sweeps on the levels of the single-workgroup tail, where they run out of
 // LDS with barriers between them: two instead of one cut the CG iterations
 // of a mixed step 12 % on the 128 x 64 x 64 channel, 11 % on the 1024 x 512
@@ -413,6 +416,94 @@ __global__ void __launch_bounds__(MG_INV_THREADS) k_mg_coarse_inv_b(const Slot *
 // cycle pieces on coarse levels (DIM = 2 or 3)
 // ---------------------------------------------------------------------------
 
+// Offsets of the radius-2 stencil (the cell, its 2 DIM neighbours, then the
+// cells two faces away) and the index of an offset in that list.
+constexpr int kStar[25][3] = {{0, 0, 0},   {-1, 0, 0},  {1, 0, 0},   {0, -1, 0},  {0, 1, 0},
+                              {0, 0, -1},  {0, 0, 1},   {-2, 0, 0},  {2, 0, 0},   {0, -2, 0},
+                              {0, 2, 0},   {-1, -1, 0}, {1, -1, 0},  {-1, 1, 0},  {1, 1, 0},
+                              {0, 0, -2},  {0, 0, 2},   {-1, 0, -1}, {1, 0, -1},  {-1, 0, 1},
+                              {1, 0, 1},   {0, -1, -1}, {0, 1, -1},  {0, -1, 1},  {0, 1, 1}};
+template <int DIM>
+constexpr int kStarN = DIM == 3 ? 25 : 13;   // the 2D stencil is the first 13 with their z = 0 entries skipped
+template <int DIM>
+constexpr int star_entry(int m) {   // m-th entry of the DIM stencil in kStar
+  return DIM == 3 ? m : (m < 5 ? m : m + 2);
+}
+template <int DIM>
+constexpr int star_find(int dx, int dy, int dz) {
+  for (int m = 0; m < kStarN<DIM>; ++m) {
+    const int k = star_entry<DIM>(m);
+    if (kStar[k][0] == dx && kStar[k][1] == dy && kStar[k][2] == dz) return m;
+  }
+  return -1;
+}
+
+// every neighbour of every radius-1 entry is in the stencil
+template <int DIM>
+constexpr bool star_complete() {
+  for (int m = 0; m < 2 * DIM + 1; ++m)
+    for (int e = 0; e < DIM; ++e)
+      for (int sgn = -1; sgn <= 1; sgn += 2) {
+        const int *o = kStar[star_entry<DIM>(m)];
+        if (star_find<DIM>(o[0] + sgn * (e == 0), o[1] + sgn * (e == 1), o[2] + sgn * (e == 2)) < 0) return false;
+      }
+  return true;
+}
+static_assert(star_complete<2>() && star_complete<3>(), "radius-2 stencil table");
+
+// One Jacobi sweep from v0 evaluated on the cell and its neighbours, then A
+// applied to the result at the cell: v1 = v0 + w D^-1 (b - A v0) on the
+// radius-1 star, returns (A v1)_c and v1 at c in v1c.  v0(B, ci, cj, ck)
+// gives the starting iterate at the cell of byte offset B (elements of T)
+// and coordinates (ci, cj, ck).  Every operand of the radius-2 stencil is
+// loaded once, unconditionally, at its cell or (outside the box) at c, by a
+// 32-bit byte offset that serves every array of the level; faces across the
+// box boundary then add nothing, as in lmatvec, whose terms there vanish
+// exactly.  The level's arrays are in global memory.
+template <int DIM, typename T, class V0>
+__device__ __forceinline__ T sweep_matvec(const LV<T> &L, const LCell &c, V0 &&v0, T &v1c) {
+  constexpr int N = kStarN<DIM>, M = 2 * DIM + 1;
+  const T w = (T)MG_OMEGA;
+  const int n[3] = {L.nx, L.ny, L.nz};
+  const int q[3] = {c.i, c.j, c.k};
+  unsigned B[N];
+  bool in[N];
+  T u0[N];
+#pragma unroll
+  for (int m = 0; m < N; ++m) {
+    const int *o = kStar[star_entry<DIM>(m)];
+    bool b = true;
+#pragma unroll
+    for (int e = 0; e < 3; ++e) b = b && q[e] + o[e] >= 0 && q[e] + o[e] < n[e];
+    in[m] = b;
+    B[m] = (unsigned)(b ? c.P + o[0] + L.nx * o[1] + L.nxy * o[2] : c.P) * (unsigned)sizeof(T);
+    u0[m] = v0(B[m], b ? c.i + o[0] : c.i, b ? c.j + o[1] : c.j, b ? c.k + o[2] : c.k);
+  }
+  // (A u)_m for the star entry m < M from u at the entries it reaches
+  auto mv = [&](int m, const T *u) -> T {
+    const int *o = kStar[star_entry<DIM>(m)];
+    T acc = (T)0;
+#pragma unroll
+    for (int e = 0; e < DIM; ++e) {
+      const int ml = star_find<DIM>(o[0] - (e == 0), o[1] - (e == 1), o[2] - (e == 2));
+      const int mh = star_find<DIM>(o[0] + (e == 0), o[1] + (e == 1), o[2] + (e == 2));
+      const T cl = ldo(L.cf[e], B[m]), ch = ldo(L.cf[e], B[mh]);
+      const T tl = acc + cl * (u[m] - u[ml]);
+      acc = in[ml] ? tl : acc;
+      const T th = acc + ch * (u[m] - u[mh]);
+      acc = in[mh] ? th : acc;
+    }
+    return acc + ldo(L.cout, B[m]) * u[m];
+  };
+  T u1[N];
+#pragma unroll
+  for (int m = 0; m < N; ++m) u1[m] = u0[m];
+#pragma unroll
+  for (int m = 0; m < M; ++m) u1[m] = u0[m] + w * (ldo(L.invD, B[m]) * (ldo((const T *)L.b, B[m]) - mv(m, u0)));
+  v1c = u1[0];
+  return mv(0, u1);
+}
+
 // Pre-smoothing from zero on level L in tile order, with the restriction:
 // x_1 = w D^-1 b, x_{m+1} = x_m + w D^-1 (b - A x_m) up to NU sweeps,
 // t = b - A x, b_next[parent] = sum of the children's t.  (cnx, cny, cnz)
@@ -441,13 +532,8 @@ __device__ __forceinline__ void smooth_restrict(const LV<T> &L, int cnx, int cny
         Ax = lmatvec<DIM, T>(L, c, x1);
       } else {
         static_assert(NU == 2, "one or two sweeps");
-        auto x2at = [&](const LCell &p) -> T {
-          const T Ax1 = lmatvec<DIM, T>(L, p, x1);
-          return x1(p.P, 0, 0) + w * (L.invD[p.P] * (L.b[p.P] - Ax1));
-        };
-        xP = x2at(c);
-        auto x2 = [&](int, int e, int side) -> T { return side == 0 ? xP : x2at(lshift(c, e, side, st)); };
-        Ax = lmatvec<DIM, T>(L, c, x2);
+        auto x1o = [&](unsigned b, int, int, int) -> T { return w * (ldo(L.invD, b) * ldo((const T *)L.b, b)); };
+        Ax = sweep_matvec<DIM, T>(L, c, x1o, xP);
       }
       L.x[c.P] = xP;
       tv = L.b[c.P] - Ax;
@@ -476,9 +562,12 @@ __device__ __forceinline__ void up_range(const LV<T> &L, int cnx, int cnxy, cons
     if constexpr (NU == 1) {
       res = y1at(c);
     } else {
-      const T y1P = y1at(c);
-      auto y1 = [&](int, int e, int side) -> T { return side == 0 ? y1P : y1at(lshift(c, e, side, st)); };
-      res = y1P + w * (L.invD[g] * (L.b[g] - lmatvec<DIM, T>(L, c, y1)));
+      auto y0o = [&](unsigned b, int i, int j, int k) -> T {
+        return ldo((const T *)L.x, b) + ldo(xc, (unsigned)((i >> 1) + cnx * (j >> 1) + cnxy * (k >> 1)) * (unsigned)sizeof(T));
+      };
+      T y1P;
+      const T Ay1 = sweep_matvec<DIM, T>(L, c, y0o, y1P);
+      res = y1P + w * (L.invD[g] * (L.b[g] - Ay1));
     }
     out[g] = res;
   }

@@ -56,9 +56,6 @@ struct SlotCtl {
 constexpr int MG_MAXL = 12;
 constexpr int MG_COARSEST = 16;
 constexpr int MG_TAIL_CELLS = 4096;
-// 3D grids of at least MG_NU2_FINE cells smooth twice per side on their
-// grid-wide coarse levels from the second on (MGInfo::nu2)
-constexpr int64_t MG_NU2_FINE = (int64_t)1 << 21;
 constexpr int MG_DENSE_MAX = 64;
 constexpr int MG_TAIL_LDS = 160 * 1024;   // LDS of one gfx950 workgroup
 struct MGLevel {

@@ -93,7 +93,7 @@ def test_mg_pressure_solve_mixed(shape):
 
 def test_mg_two_sweep_levels(monkeypatch):
     """Two smoothing sweeps per side on grid-wide coarse levels (the setting
-    of 3D grids of 2^21 cells and more, forced here through the level mask
+    of 3D grids from level 2 on, forced here through the level mask
     OSCAR_MG_SWEEPS2 on a 64 x 48 x 64 grid whose FP64 hierarchy has two
     grid-wide levels, 24576 and 3072 cells, and whose FP32 one has one): the
     FP64 solves with level 2, or levels 1 and 2, smoothed twice match the
