@@ -424,7 +424,7 @@ constexpr int kStar[25][3] = {{0, 0, 0},   {-1, 0, 0},  {1, 0, 0},   {0, -1, 0},
                               {0, 0, -2},  {0, 0, 2},   {-1, 0, -1}, {1, 0, -1},  {-1, 0, 1},
                               {1, 0, 1},   {0, -1, -1}, {0, 1, -1},  {0, -1, 1},  {0, 1, 1}};
 template <int DIM>
-constexpr int kStarN = DIM == 3 ? 25 : 13;   // the 2D stencil is the first 13 with their z = 0 entries skipped
+constexpr int kStarN = DIM == 3 ? 25 : 13;   // 2D: the 13 entries of the first 15 with a zero z offset
 template <int DIM>
 constexpr int star_entry(int m) {   // m-th entry of the DIM stencil in kStar
   return DIM == 3 ? m : (m < 5 ? m : m + 2);
