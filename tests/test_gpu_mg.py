@@ -91,16 +91,17 @@ def test_mg_pressure_solve_mixed(shape):
     assert rel_linf(g.get("p_cr"), r.get("p_cr")) <= 1e-5
 
 
-def test_mg_two_sweep_levels(monkeypatch):
+@pytest.mark.parametrize("shape", [(64, 48, 64, 3), (300, 200, 1, 2)])
+def test_mg_two_sweep_levels(monkeypatch, shape):
     """Two smoothing sweeps per side on grid-wide coarse levels (the setting
     of 3D grids from level 2 on, forced here through the level mask
-    OSCAR_MG_SWEEPS2 on a 64 x 48 x 64 grid whose FP64 hierarchy has two
-    grid-wide levels, 24576 and 3072 cells, and whose FP32 one has one): the
+    OSCAR_MG_SWEEPS2; 64 x 48 x 64: FP64 grid-wide levels of 24576 and 3072
+    cells, FP32 one; 300 x 200 in 2D: 15000 and 3750 cells, FP32 one): the
     FP64 solves with level 2, or levels 1 and 2, smoothed twice match the
     oracle to 1e-10 and take fewer CG iterations than with one sweep; the
     mixed solve with level 1 smoothed twice matches the Jacobi-preconditioned
     mixed solve of the same system to 1e-8."""
-    nx, ny, nz, dim = 64, 48, 64, 3
+    nx, ny, nz, dim = shape
     o = _oscar()
     c = cases.tiny_box(nx=nx, ny=ny, nz=nz, dim=dim, seed=7, solid_cells=_solid_block(nx, ny, nz, dim))
     f = cases.random_fields(c, seed=11)
@@ -114,7 +115,7 @@ def test_mg_two_sweep_levels(monkeypatch):
         g = o.Oscar(c, precision=o.FP64, precond=o.PC_MG)
         g.set("U_cr", f["U"])
         g.set("phi_cr", f["phi"])
-        print("mg two sweeps, fp64, mask", mask, flush=True)
+        print("mg two sweeps, fp64", shape, "mask", mask, flush=True)
         rc, it, res = g.pressure_solve(1, 1e-5, 1e-13, 5000)
         assert rc == 0 and res < 1e-11
         assert rel_linf(g.get("p_cr"), r.get("p_cr")) <= 1e-10, mask
