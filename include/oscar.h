@@ -65,8 +65,8 @@ extern "C" {
 /* preconditioner of the pressure conjugate gradient (oscar_desc.precond) */
 #define OSCAR_PC_JACOBI 0          /* diagonal scaling */
 #define OSCAR_PC_MG 1              /* one geometric multigrid V-cycle: 2^dim-cell aggregation, Jacobi
-                                      smoothing (two sweeps per side on the coarse levels from the second
-                                      on in 3D, else one; the environment
+                                      smoothing (two sweeps per side on the grid-wide coarse levels in 3D,
+                                      one in 2D; the environment
                                       variable OSCAR_MG_SWEEPS2, a bit mask of levels read at create or
                                       admission, replaces that choice); coarse operators rebuilt from 1/a_P
                                       at every viscous step and every 4th capillary sub-step (a

@@ -95,14 +95,14 @@ void mg_levels(const oscar_desc &D, MGInfo &mg) {
       break;
     }
   mg.tail_bytes = (int32_t)mg_tail_bytes(mg, mg.tail, D.dim, w);
-  // Smoothing sweeps of the grid-wide coarse levels: two from level 2 on in
-  // 3D, else one.  A second sweep cuts the CG iterations but makes these
-  // latency-bound kernels slower; it pays on the levels below the first.  The
+  // Smoothing sweeps of the grid-wide coarse levels: two in 3D, one in 2D.
+  // A second sweep cuts the CG iterations but makes these latency-bound
+  // kernels slower; in 3D it pays on every level, in 2D on none.  The
   // environment variable OSCAR_MG_SWEEPS2 (a mask of levels, read at each
   // hierarchy construction) replaces the rule, for tests and tuning.
   mg.nu2 = 0;
   if (D.dim == 3)
-    for (int l = 2; l < mg.tail; ++l) mg.nu2 |= 1 << l;
+    for (int l = 1; l < mg.tail; ++l) mg.nu2 |= 1 << l;
   if (const char *e = getenv("OSCAR_MG_SWEEPS2")) mg.nu2 = (int32_t)strtol(e, nullptr, 0);
   mg.nu2 &= ((1 << mg.tail) - 1) & ~1;
 }

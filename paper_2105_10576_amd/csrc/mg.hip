@@ -35,17 +35,15 @@ namespace oscar {
 // sets the level's bit in MGInfo::nu2.  The second sweep is evaluated at the
 // neighbours in the same launch (sweep_matvec: a radius-2 stencil, each
 // operand loaded once), which makes these latency-bound kernels slower.
-// Measured (mixed / FP64 step time, two sweeps against one):
-//   levels >= 2: 128 x 64 x 64 channel -1.5 % / +0.9 % (CG iterations 566
-//     -> 516, coarse part of a cycle +3.3 us); 3D sphere packs 128^3 -1.4 % /
-//     -3.3 %, 192^3 -9.8 % / -11.4 %, 256^3 -9 % / -13 % (2006 -> 1741);
-//   adding level 1 (the expensive one: +92 us per cycle on the 256^3 pack
-//     for 11 % fewer iterations) loses;
+// Measured (mixed / FP64 step time; A/B on one box each):
+//   128 x 64 x 64 channel: level 2 twice against once -1.5 % / +0.9 % (CG
+//     iterations 566 -> 516), levels 1 and 2 against level 2 alone -0.9 % /
+//     -1.3 % (516 -> 470);
+//   256^3 sphere pack: levels from 2 on against none -9 % / -13 % (2006 ->
+//     1741), all against levels from 2 on -3.1 % / -1.2 % (1741 -> 1488);
 //   1024 x 512 micromodel (2D): level 2 +1 % / +5 %, levels 2 and 3 +2 % /
 //     +7 %.
-// Hence two sweeps from level 2 on in 3D, one in 2D.  (The sphere packs of
-// 128^3 and 192^3 and the level-1 case were measured before the stencil's
-// loads were de-duplicated, which took 1-4 us off each cycle.)
+// Hence two sweeps on every grid-wide level in 3D, one in 2D.
 // Sweeps on the levels of the single-workgroup tail, where they run out of
 // LDS with barriers between them: two instead of one cut the CG iterations
 // of a mixed step 12 % on the 128 x 64 x 64 channel, 11 % on the 1024 x 512

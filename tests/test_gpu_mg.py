@@ -94,7 +94,7 @@ def test_mg_pressure_solve_mixed(shape):
 @pytest.mark.parametrize("shape", [(64, 48, 64, 3), (300, 200, 1, 2)])
 def test_mg_two_sweep_levels(monkeypatch, shape):
     """Two smoothing sweeps per side on grid-wide coarse levels (the setting
-    of 3D grids from level 2 on, forced here through the level mask
+    of 3D grids, forced here through the level mask
     OSCAR_MG_SWEEPS2; 64 x 48 x 64: FP64 grid-wide levels of 24576 and 3072
     cells, FP32 one; 300 x 200 in 2D: 15000 and 3750 cells, FP32 one): the
     FP64 solves with level 2, or levels 1 and 2, smoothed twice match the
