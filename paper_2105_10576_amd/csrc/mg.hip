@@ -6,8 +6,9 @@
 // Hierarchy: coarse cell = 2 x 2 (x 2) block of the finer level.  A coarse
 // face coefficient is a fixed fraction of the sum of the fine face
 // coefficients crossing it (the piecewise-constant Galerkin product, scaled
-// by one half to match a rediscretisation on the doubled spacing, by 0.8 on
-// the first level); outlet coefficients are aggregated the same way.
+// by one half to match a rediscretisation on the doubled spacing, by 0.8
+// (2D) or 0.9 (3D) on the first level); outlet coefficients are aggregated
+// the same way.
 // Cycle: Jacobi sweeps (damped by 0.9 on the fine grid, plain on the coarse
 // levels) from zero before restriction and after prolongation, one on the
 // fine grid, one or two (the host's per-level choice, MGInfo::nu2) on the
@@ -72,9 +73,14 @@ constexpr double MG_OMEGA_FINE = 0.9;
 // damping above: 0.62 -> 0.8 cut the iterations 4 % on the channel, 1 % on
 // the micromodel, 0.3 % on the sphere pack; 0.7-0.9 lie within 1 %, 0.55 was
 // worse everywhere; larger scales on the deeper levels cost iterations on
-// the sphere pack and the micromodel).
+// the sphere pack and the micromodel).  With two sweeps on the grid-wide
+// coarse levels (3D), 0.9 on the first level cut the channel's iterations
+// 470 -> 454 (mixed step -3.6 %, FP64 -2.9 %) for +0.5 % on the sphere pack
+// (0.95 and 1.0: -4.8 % and -4.5 % on the channel, +1.2 % and +1.8 % on the
+// pack); in 2D 0.9 cost the micromodel 2 %.
 constexpr double MG_SCALE = 0.5;
-constexpr double MG_SCALE1 = 0.8;
+constexpr double MG_SCALE1_2D = 0.8;
+constexpr double MG_SCALE1_3D = 0.9;
 
 static_assert(MG_DENSE_MAX <= MG_TAIL_THREADS, "one coarsest-level cell per tail thread");
 
@@ -302,7 +308,7 @@ __device__ void setup_cell(const Slot &s, int l, int g) {
           if (q[e] == 2 * cc[e] + 1 && q[e] + 1 < nf[e]) high[e] = high[e] + fine_low(F + st, e);
         }
       }
-  const T sc = (T)(l == 1 ? MG_SCALE1 : MG_SCALE);
+  const T sc = (T)(l == 1 ? (s.dim == 3 ? MG_SCALE1_3D : MG_SCALE1_2D) : MG_SCALE);
   T diag = (T)0;
   for (int e = 0; e < 3; ++e) {
     if (e < dim) ((T *)C.cf[e])[g] = sc * low[e];
