@@ -66,12 +66,10 @@ extern "C" {
 #define OSCAR_PC_JACOBI 0          /* diagonal scaling */
 #define OSCAR_PC_MG 1              /* one geometric multigrid V-cycle: 2^dim-cell aggregation, Jacobi
                                       smoothing (two sweeps per side on the grid-wide coarse levels in 3D,
-                                      one in 2D; the environment
-                                      variable OSCAR_MG_SWEEPS2, a bit mask of levels read at create or
-                                      admission, replaces that choice); coarse operators rebuilt from 1/a_P
-                                      at every viscous step and every 4th capillary sub-step (a
-                                      preconditioner only: each solve still meets pcg_rtol on the current
-                                      operator) */
+                                      one in 2D, unless oscar_desc.mg_sweeps2 says otherwise); coarse
+                                      operators rebuilt from 1/a_P at every viscous step and every 4th
+                                      capillary sub-step (a preconditioner only: each solve still meets
+                                      pcg_rtol on the current operator) */
 
 /* field identifiers for oscar_get_field / oscar_set_field */
 #define OSCAR_FIELD_ALPHA 0        /* cells */
@@ -113,6 +111,17 @@ typedef struct {
                                        passes before it left unused, (1 - lambda) A, against the first
                                        pass's local bounds (iterative flux correction); more than one pass
                                        takes one more face array of workspace */
+  /* Tuning.  Zero selects the built-in value.  They change the iteration
+   * counts or the order of the reductions, so a result is reproducible
+   * bit for bit only with the same values. */
+  int32_t mg_sweeps2;               /* OSCAR_PC_MG: bit l (l >= 1) gives grid-wide coarse level l two
+                                       smoothing sweeps per side instead of one; 0 = built-in rule (every
+                                       grid-wide level in 3D, none in 2D); < 0 = one sweep on every level */
+  int32_t max_blocks;               /* workgroups per grid-wide launch and instance, 1..1024 (the cells
+                                       are grid-strided beyond it; also the number of partials of each
+                                       reduction); 0 = 1024 */
+  double inner_rtol;                /* OSCAR_MIXED: smallest relative residual reduction asked of one
+                                       FP32 inner solve, in (0, 1); 0 = 1e-6 */
 } oscar_desc;
 
 typedef struct {

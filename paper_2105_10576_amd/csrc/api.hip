@@ -44,7 +44,7 @@ Dims dims_of(const oscar_desc &D) {
   g.nf1 = (int64_t)D.nx * (D.ny + 1) * D.nz;
   g.nf2 = D.dim == 3 ? (int64_t)D.nx * D.ny * (D.nz + 1) : 0;
   g.nft = g.nf0 + g.nf1 + g.nf2;
-  g.nblocks = blocks_for(g.nc);
+  g.nblocks = blocks_for(g.nc, D.max_blocks);
   return g;
 }
 
@@ -98,12 +98,12 @@ void mg_levels(const oscar_desc &D, MGInfo &mg) {
   // Smoothing sweeps of the grid-wide coarse levels: two in 3D, one in 2D.
   // A second sweep cuts the CG iterations but makes these latency-bound
   // kernels slower; in 3D it pays on every level, in 2D on none.  The
-  // environment variable OSCAR_MG_SWEEPS2 (a mask of levels, read at each
-  // hierarchy construction) replaces the rule, for tests and tuning.
+  // descriptor's mg_sweeps2 mask replaces the rule.
   mg.nu2 = 0;
   if (D.dim == 3)
     for (int l = 1; l < mg.tail; ++l) mg.nu2 |= 1 << l;
-  if (const char *e = getenv("OSCAR_MG_SWEEPS2")) mg.nu2 = (int32_t)strtol(e, nullptr, 0);
+  if (D.mg_sweeps2 > 0) mg.nu2 = D.mg_sweeps2;
+  else if (D.mg_sweeps2 < 0) mg.nu2 = 0;
   mg.nu2 &= ((1 << mg.tail) - 1) & ~1;
 }
 
@@ -187,6 +187,8 @@ int check_desc(const oscar_desc *D, std::string &why) {
   if (D->mules_iter < 0 || D->mules_iter > 8) { why = "mules_iter must be in [0, 8]"; return OSCAR_E_ARG; }
   if (D->n_corr < 1 || D->n_corr > 64) { why = "n_corr must be in [1, 64]"; return OSCAR_E_ARG; }
   if (!(D->pcg_rtol > 0) || D->pcg_max_it < 1) { why = "pcg_rtol must be > 0 and pcg_max_it >= 1"; return OSCAR_E_ARG; }
+  if (D->max_blocks < 0 || D->max_blocks > MAX_BLOCKS) { why = "max_blocks must be in [0, 1024]"; return OSCAR_E_ARG; }
+  if (!(D->inner_rtol >= 0.0 && D->inner_rtol < 1.0)) { why = "inner_rtol must be in [0, 1)"; return OSCAR_E_ARG; }
   for (int f = 0; f < 2 * D->dim; ++f)
     if (D->bc[f] < OSCAR_BC_WALL || D->bc[f] > OSCAR_BC_OUTLET) { why = "unknown boundary type"; return OSCAR_E_ARG; }
   return OSCAR_OK;
@@ -563,21 +565,10 @@ static void append_segment(std::vector<int2> &bt, int slot, int nb) {
 // smallest relative residual reduction asked of one FP32 inner solve of the
 // mixed-precision path (each inner solve otherwise stops at the residual the
 // FP64 test needs)
-static double inner_rtol() {
-  static double v = [] {
-    const char *e = getenv("OSCAR_INNER_RTOL");
-    double x = e ? atof(e) : 1e-6;
-    return x > 0 && x < 1 ? x : 1e-6;
-  }();
-  return v;
-}
+static double inner_rtol(const oscar_desc &D) { return D.inner_rtol > 0.0 ? D.inner_rtol : 1e-6; }
 
-int oscar::blocks_for(int64_t nc) {
-  static int cap = [] {
-    const char *e = getenv("OSCAR_MAX_BLOCKS");
-    int v = e ? atoi(e) : 1024;
-    return v >= 1 ? v : 1024;
-  }();
+int oscar::blocks_for(int64_t nc, int cap) {
+  if (cap < 1 || cap > MAX_BLOCKS) cap = MAX_BLOCKS;
   int64_t n = (nc + BLOCK - 1) / BLOCK;
   return (int)(n < cap ? n : cap);
 }
@@ -807,13 +798,11 @@ static int solve_pressure(oscar_ctx *c, int &iters, int kind, int corr) {
     if (used > 0) pred = used;
     if (!mixed || used == 0) break;   // FP64, or the equation was solved before any iteration
     ++outer;
-    if (c->h_state->done) break;      // the refinement met the tolerance
-    // stop when an outer step no longer halves the FP64 residual: the
-    // requested tolerance is below what the FP32 inner solve can deliver
-    if (!(c->h_state->rn64 < 0.5 * c->h_state->rn64_prev) || outer >= 60) {
-      c->refine_stall = true;
-      break;
-    }
+    // the refinement met the tolerance, or stalled (an outer step no longer
+    // halved the FP64 residual, or REFINE_MAX steps: decided on the device)
+    if (c->h_state->stalled) c->refine_stall = true;
+    if (c->h_state->done) break;
+    if (outer > REFINE_MAX) { c->err = "refinement did not terminate"; return OSCAR_E_HIP; }
   }
   c->refine_call += outer;
   iters = c->total_seen - start_total;
@@ -835,7 +824,7 @@ static int run_correctors(oscar_ctx *c, bool cr, double &E, int &warn) {
     c->pcg_call += it;
     if (c->h_state->maxit_hit) warn = OSCAR_W_PCG_MAXIT;
     else if (c->refine_stall && warn == OSCAR_OK) warn = OSCAR_W_REFINE_STALL;
-    launch_correct<R>(L, j == c->D.n_corr - 1);
+    launch_correct<R>(L, j);
     HIPCHK(c, hipGetLastError());
   }
   return OSCAR_OK;
@@ -850,8 +839,9 @@ static SlotCtl make_ctl(const oscar_ctx *c, int mode, double dt, int n_sub) {
   k.ub = mode ? 0.0 : c->D.u_inlet;
   k.with_st = mode;
   k.rtol = c->D.pcg_rtol;
-  k.rtol_inner = inner_rtol();
+  k.rtol_inner = inner_rtol(c->D);
   k.max_it = c->D.pcg_max_it;
+  k.last_corr = c->D.n_corr - 1;
   k.n_sub = n_sub;
   return k;
 }
@@ -1188,6 +1178,7 @@ struct EngSlot {
   double last_E = 0.0;
   int64_t n_fluid = 0;
   int pred = 32, pred_inner = 16;
+  bool stalled = false;   // a refinement of this tick stopped short of its tolerance
 };
 
 struct Region {
@@ -1238,7 +1229,7 @@ static uint64_t eng_table_bytes(int max_slots, int btab_cap) {
 
 extern "C" int32_t oscar_engine_table_bytes(int32_t max_slots, uint64_t *bytes) {
   if (max_slots < 1 || max_slots > 4096 || !bytes) { g_err = "need 1 <= max_slots <= 4096"; return OSCAR_E_ARG; }
-  *bytes = eng_table_bytes(max_slots, max_slots * (blocks_for((int64_t)1 << 40) + 16));
+  *bytes = eng_table_bytes(max_slots, max_slots * (MAX_BLOCKS + 16));
   return OSCAR_OK;
 }
 
@@ -1250,7 +1241,7 @@ extern "C" int32_t oscar_engine_create(int32_t max_slots, int32_t precision, voi
     g_err = "need 1 <= max_slots <= 4096 and a known precision";
     return OSCAR_E_ARG;
   }
-  const int btab_cap = max_slots * (blocks_for((int64_t)1 << 40) + 16);
+  const int btab_cap = max_slots * (MAX_BLOCKS + 16);
   uint64_t tb = eng_table_bytes(max_slots, btab_cap);
   if (!ws || ((uintptr_t)ws % ALIGN) != 0 || bytes < tb) {
     g_err = "engine workspace too small or not 256-byte aligned";
@@ -1456,8 +1447,9 @@ static SlotCtl eng_ctl(const EngSlot &es, int mode, int precision) {
   k.ub = mode ? 0.0 : es.D.u_inlet;
   k.with_st = mode;
   k.rtol = es.D.pcg_rtol;
-  k.rtol_inner = inner_rtol();
+  k.rtol_inner = inner_rtol(es.D);
   k.max_it = es.D.pcg_max_it;
+  k.last_corr = es.D.n_corr - 1;
   k.n_sub = es.n_sub;
   k.substep = es.k;
   k.tol = es.tol;
@@ -1536,7 +1528,10 @@ static int eng_tick(oscar_engine *e) {
   launch_assemble<R>(L);
   EHIP(e, hipGetLastError());
   const bool mixed = e->precision == OSCAR_MIXED;
-  const int n_corr = e->slots[act[0]].D.n_corr;
+  // correctors: each slot runs its own n_corr; a slot whose correctors are
+  // done sits out the later ones (its control block inactive)
+  int n_corr = 1;
+  for (int i : act) n_corr = std::max(n_corr, (int)e->slots[i].D.n_corr);
   // The pressure solves run per preconditioner: the Jacobi slots and the
   // multigrid slots, each group with a block table of its own when both are
   // present (every other launch covers all active slots).
@@ -1661,8 +1656,10 @@ static int eng_tick(oscar_engine *e) {
     if (g.empty()) return OSCAR_OK;
     if (!mixed) return mg ? inner_m() : inner_j();
     // FP32 inner solves wrapped in FP64 refinement; the refinement acts on
-    // the slots whose inner solve finished
-    for (int outer = 0; outer < 30 && !group_done(g); ++outer) {
+    // the slots whose inner solve finished, and marks a slot done when it
+    // met its tolerance or stalled (the rule of a context, on the device)
+    for (int outer = 0; !group_done(g); ++outer) {
+      if (outer > REFINE_MAX) { e->err = "refinement did not terminate"; return OSCAR_E_HIP; }
       int r2 = mg ? inner_m() : inner_j();
       if (r2) return r2;
       launch_refine<R>(Lg);
@@ -1670,10 +1667,35 @@ static int eng_tick(oscar_engine *e) {
       r2 = eng_read_states(e);
       if (r2) return r2;
     }
+    for (int i : g)
+      if (e->h_states[i].stalled) e->slots[i].stalled = true;
     return OSCAR_OK;
   };
   std::vector<double> E(e->max_slots, 0.0);
+  for (int i : act) e->slots[i].stalled = false;
+  const std::vector<int> gj_all = gj, gm_all = gm;
+  bool parked = false;   // some slot's control block is inactive for the later correctors
   for (int j = 0; j < n_corr; ++j) {
+    if (j > 0) {   // slots whose correctors are done sit out
+      std::vector<std::pair<int, SlotCtl>> park;
+      for (int i : act)
+        if (e->slots[i].D.n_corr == j) {
+          SlotCtl k = eng_ctl(e->slots[i], e->slots[i].state == ES_CR ? 1 : 0, e->precision);
+          k.active = 0;
+          park.push_back({i, k});
+        }
+      if (!park.empty()) {
+        rc = eng_set_ctl(e, park);
+        if (rc) return rc;
+        parked = true;
+        gj.clear();
+        gm.clear();
+        for (int i : gj_all)
+          if (e->slots[i].D.n_corr > j) gj.push_back(i);
+        for (int i : gm_all)
+          if (e->slots[i].D.n_corr > j) gm.push_back(i);
+      }
+    }
     launch_predictor<R>(L);
     launch_pressure_setup<R>(L, j == 0);
     EHIP(e, hipGetLastError());
@@ -1685,8 +1707,12 @@ static int eng_tick(oscar_engine *e) {
     if (rc) return rc;
     if (j == 0)
       for (int i : act) E[i] = e->h_states[i].E;
-    launch_correct<R>(L, j == n_corr - 1);
+    launch_correct<R>(L, j);
     EHIP(e, hipGetLastError());
+  }
+  if (parked) {   // active again for the finalisation
+    rc = eng_set_ctl(e, upd);
+    if (rc) return rc;
   }
   rc = eng_read_states(e);
   if (rc) return rc;
@@ -1700,6 +1726,7 @@ static int eng_tick(oscar_engine *e) {
     if (st.nonfinite) es.status = OSCAR_E_NONFINITE;
     else if (st.unstable && es.status == OSCAR_OK) es.status = OSCAR_E_UNSTABLE;
     else if (st.maxit_hit && es.status == OSCAR_OK) es.status = OSCAR_W_PCG_MAXIT;
+    else if (es.stalled && es.status == OSCAR_OK) es.status = OSCAR_W_REFINE_STALL;
     if (es.state == ES_VD) {
       es.state = ES_CR;
       es.k = 0;

@@ -1183,6 +1183,8 @@ __global__ void __launch_bounds__(BLOCK) k_setup_fin(const Slot *slots, const in
     st->rn = rn;
     st->bn64 = bn;
     st->rn64 = rn;
+    st->ref_solve = 0;
+    st->stalled = 0;
     // mixed precision: the FP32 inner system is M e = r, measured against |r|
     st->bn = s.precision != 0 ? rn : bn;
     st->tgt = inner_target(ctl, bn, rn);
@@ -1414,7 +1416,11 @@ __global__ void __launch_bounds__(BLOCK) k_refine_fin(const Slot *slots) {
     st->tgt = inner_target(ctl, st->bn64, st->bn);
     st->it = 0;
     st->refine_steps = st->refine_steps + 1;
-    st->done = st->rn64 <= ctl.rtol * st->bn64;
+    st->ref_solve = st->ref_solve + 1;
+    const bool met = st->rn64 <= ctl.rtol * st->bn64;
+    const bool stall = !met && (!(st->rn64 < 0.5 * st->rn64_prev) || st->ref_solve >= REFINE_MAX);
+    st->stalled = stall;
+    st->done = met || stall;
   }
 }
 
@@ -1423,7 +1429,7 @@ __global__ void __launch_bounds__(BLOCK) k_refine_fin(const Slot *slots) {
 // first, as in k_predictor; each thread writes the faces its cell owns (the
 // low face per direction, and the far face on the last layer).
 template <typename R>
-__global__ void __launch_bounds__(BLOCK) k_correct(const Slot *slots, const int2 *btab, int last) {
+__global__ void __launch_bounds__(BLOCK) k_correct(const Slot *slots, const int2 *btab, int corr) {
   Block B = block_of(slots, btab);
   const Slot &s = *B.s;
   const SlotCtl &ctl = *B.ctl;
@@ -1439,7 +1445,7 @@ __global__ void __launch_bounds__(BLOCK) k_correct(const Slot *slots, const int2
   R *Us = (R *)s.U_sum;
   const double Sh = s.Sh, S2h = s.S2h, h = s.h, hh = s.hh, sigma = s.sigma;
   const int with_st = ctl.with_st;
-  const bool acc_sum = last && ctl.mode == 1;
+  const bool acc_sum = corr == ctl.last_corr && ctl.mode == 1;
   const int nn[3] = {s.nx, s.ny, s.nz};
   int bcf[6];
   for (int f = 0; f < 6; ++f) bcf[f] = s.bcf[f];
@@ -1653,8 +1659,8 @@ template <typename R> void launch_refine(const Launch &L) {
   hipLaunchKernelGGL(k_refine_fin, SLOTGRID(L), L.slots);
 }
 
-template <typename R> void launch_correct(const Launch &L, int last) {
-  hipLaunchKernelGGL(k_correct<R>, GRID(L), L.slots, L.btab, last);
+template <typename R> void launch_correct(const Launch &L, int corr) {
+  hipLaunchKernelGGL(k_correct<R>, GRID(L), L.slots, L.btab, corr);
 }
 
 template <typename R> void launch_finalize(const Launch &L) {

@@ -37,12 +37,19 @@ struct SlotState {
   double mass_defect;
   int32_t it, done, zero_rhs, total_it;
   int32_t nonfinite, unstable, maxit_hit, refine_steps;
+  int32_t ref_solve;   // refinement steps of the current solve (reset by its set-up)
+  int32_t stalled;     // the current solve's refinement stopped short of its tolerance
 };
+
+// Mixed precision: a solve's FP64 refinement stops (done, stalled) when one
+// outer step no longer halves the FP64 residual, or after REFINE_MAX steps:
+// the tolerance then lies below what the FP32 inner solves can deliver.
+constexpr int REFINE_MAX = 60;
 
 struct SlotCtl {
   double dt, ub, rtol, rtol_inner;   // rtol_inner: smallest relative reduction asked of one FP32 inner solve
   int32_t active, mode, with_st, max_it;
-  int32_t last_corr, substep, n_sub, pad;   // substep: index within the relaxation
+  int32_t last_corr, substep, n_sub, pad;   // last_corr: n_corr - 1; substep: index within the relaxation
   double tol;
 };
 
@@ -144,7 +151,9 @@ void launch_ts_span(unsigned long long *ts, int nregions, unsigned long long *ou
 // n iterations from it0 (with ts: n = 1)
 template <typename R> void launch_cg_iters(const Launch &L, int it0, int n, unsigned long long *ts = nullptr);
 template <typename R> void launch_refine(const Launch &L);
-template <typename R> void launch_correct(const Launch &L, int last);
+// corr: the corrector's index; each slot's last corrector (ctl.last_corr)
+// adds its velocity to the relaxation sum
+template <typename R> void launch_correct(const Launch &L, int corr);
 template <typename R> void launch_finalize(const Launch &L);
 template <typename R> void launch_zero_usum(const Launch &L);
 void launch_ctl_update(const Launch &L, const CtlUpdate &u);
@@ -193,7 +202,9 @@ inline int mg_part_launches(const Slot &hs, int part) { return part == 1 ? 2 * (
 template <typename R> void launch_mg_dir(const Slot &hs, const Launch &L, int it, unsigned long long *ts = nullptr);
 void launch_gather_states(const Launch &L, int nslots, SlotState *out);
 
-// blocks per slot: ceil(cells/BLOCK), capped (grid-stride beyond the cap)
-int blocks_for(int64_t nc);
+// blocks per slot: ceil(cells/BLOCK), capped at `cap` (0: MAX_BLOCKS;
+// grid-stride beyond the cap)
+constexpr int MAX_BLOCKS = 1024;
+int blocks_for(int64_t nc, int cap);
 
 }  // namespace oscar

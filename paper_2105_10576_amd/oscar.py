@@ -32,7 +32,8 @@ class Desc(C.Structure):
                 ("sigma", C.c_double), ("theta_deg", C.c_double), ("bc", C.c_int32 * 6),
                 ("u_inlet", C.c_double), ("precision", C.c_int32), ("n_corr", C.c_int32),
                 ("pcg_rtol", C.c_double), ("pcg_max_it", C.c_int32), ("precond", C.c_int32),
-                ("mules_iter", C.c_int32)]
+                ("mules_iter", C.c_int32), ("mg_sweeps2", C.c_int32), ("max_blocks", C.c_int32),
+                ("inner_rtol", C.c_double)]
 
 
 class Stats(C.Structure):
@@ -92,7 +93,9 @@ def lib():
 def make_desc(case, precision=FP64):
     """Fill an oscar_desc from a case dictionary (key "precond": PC_JACOBI,
     the default, or PC_MG; key "mules_iter": limiting passes of the alpha
-    transport, default 1); returns (desc, keep-alive arrays)."""
+    transport, default 1; tuning keys "mg_sweeps2", "max_blocks",
+    "inner_rtol", default 0 = the library's built-in value); returns
+    (desc, keep-alive arrays)."""
     d = Desc()
     for k in ("dim", "nx", "ny", "nz", "n_corr", "pcg_max_it"):
         setattr(d, k, int(case[k]))
@@ -103,6 +106,9 @@ def make_desc(case, precision=FP64):
     d.precision = int(precision)
     d.precond = int(case.get("precond", PC_JACOBI))
     d.mules_iter = int(case.get("mules_iter", 1))
+    d.mg_sweeps2 = int(case.get("mg_sweeps2", 0))
+    d.max_blocks = int(case.get("max_blocks", 0))
+    d.inner_rtol = float(case.get("inner_rtol", 0.0))
     mask = np.ascontiguousarray(case["mask"], dtype=np.uint8)
     a0 = np.ascontiguousarray(case["alpha0"], dtype=np.float64)
     d.mask = mask.ctypes.data_as(C.POINTER(C.c_uint8))

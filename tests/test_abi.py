@@ -139,3 +139,19 @@ def test_null_safety_and_brackbill_helper():
     dtb = L.oscar_dt_brackbill(1.0, 1000.0, 1e-6, 0.07)
     assert dtb == pytest.approx(3.3734e-8, rel=1e-4)
     assert L.oscar_dt_brackbill(1.0, 1000.0, 4e-6, 0.07) == pytest.approx(8 * dtb, rel=1e-12)
+
+
+def test_tuning_fields_are_validated_and_sized():
+    """The descriptor's tuning fields: max_blocks outside [0, 1024] and
+    inner_rtol outside [0, 1) are rejected with OSCAR_E_ARG; fewer
+    workgroups per launch mean fewer reduction partials, so a smaller
+    workspace."""
+    c = cases.channel_bubble(nx=128, ny=64)
+    base = _size(_desc(c)[0])
+    assert base[0] == 0
+    for key, val in (("max_blocks", -1), ("max_blocks", 1025), ("inner_rtol", 1.0), ("inner_rtol", -0.1)):
+        d, keep = _desc(dict(c, **{key: val}))
+        assert _size(d)[0] == -1, (key, val)
+    d, keep = _desc(dict(c, max_blocks=8))
+    rc, n = _size(d)
+    assert rc == 0 and n < base[1]

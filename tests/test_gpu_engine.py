@@ -127,12 +127,12 @@ def _small_3d():
 
 
 @pytest.mark.parametrize("which", ["2d_fp64", "3d_mixed", "3d_fp64_two_sweeps"])
-def test_engine_multigrid_matches_context(which, monkeypatch):
+def test_engine_multigrid_matches_context(which):
     """A multigrid request through the engine (batched multigrid launches)
     equals the same request through a context bitwise: the same kernel
     bodies, the same block-to-cell assignment and the same device-side
     convergence decisions.  The third case smooths its two grid-wide coarse
-    levels twice (forced through OSCAR_MG_SWEEPS2 on a 96 x 48 x 48 channel,
+    levels twice (forced through the descriptor's mg_sweeps2 on a 96 x 48 x 48 channel,
     whose FP64 tail starts at level 3)."""
     from paper_2105_10576_amd import oscar
     if which == "2d_fp64":
@@ -140,9 +140,9 @@ def test_engine_multigrid_matches_context(which, monkeypatch):
     elif which == "3d_mixed":
         c, precision = _mg(_small_3d()), 1
     else:
-        monkeypatch.setenv("OSCAR_MG_SWEEPS2", "6")
         c = cases.constricted_channel(nx=96, ny=48, nz=48, max_iters=3)
         c["pcg_rtol"] = 1e-8
+        c["mg_sweeps2"] = 6
         c, precision = _mg(c), 0
     print("engine vs context, multigrid", which, flush=True)
     g = oscar.Oscar(c, precision=precision, precond=oscar.PC_MG)
@@ -190,3 +190,93 @@ def test_multigrid_and_jacobi_requests_share_an_engine(precision):
         assert got[i]["k_f"] == a["k_f"], i
         for f in ("alpha", "p", "U"):
             assert np.array_equal(got[i][f], a[f]), (i, f)
+
+
+def test_engine_mixed_corrector_counts():
+    """Requests with 2, 3 and 4 PISO correctors share the engine: every slot
+    runs its own number (a slot whose correctors are done sits out the later
+    ones, and its velocity sum takes its own last corrector), so each result
+    equals the request alone and, for the single-slot case, a context, bitwise."""
+    from paper_2105_10576_amd import oscar
+    base = _reqs()
+    reqs = []
+    for c, n in zip((base[0], base[1], base[3]), (2, 4, 3)):
+        c = dict(c)
+        c["n_corr"] = n
+        reqs.append(c)
+    alone = [_run_alone(oscar, c, 0) for c in reqs]
+    g = oscar.Oscar(reqs[0], precision=0)
+    g.viscous_step(reqs[0]["dt_vd"])
+    rc, kf, E = g.capillary_relax(reqs[0]["dt_vd"], reqs[0]["n_sub"], reqs[0]["max_iters"], reqs[0]["tol"])
+    assert alone[0]["k_f"] == kf
+    for f in ("alpha", "p", "U"):
+        assert np.array_equal(alone[0][f], g.get(f)), f
+    heap = sum(oscar.workspace_size(c, 0) for c in reqs) + (1 << 20)
+    e = oscar.Engine(4, heap, precision=0)
+    slots = {e.admit(c): i for i, c in enumerate(reqs)}
+    got = {}
+    for _ in range(10000):
+        done, act = e.poll()
+        for s in done:
+            got[slots[s]] = e.fetch(s)
+            e.release(s)
+        if len(got) == len(reqs):
+            break
+        e.run(1)
+    for i, a in enumerate(alone):
+        assert got[i]["k_f"] == a["k_f"] and got[i]["status"] == a["status"] == 0
+        for f in ("alpha", "p", "U"):
+            assert np.array_equal(got[i][f], a[f]), (i, f)
+
+
+def test_engine_refinement_stall_matches_context():
+    """A mixed-precision request whose pressure tolerance (1e-17) lies below
+    what FP32 inner solves with FP64 refinement can reach: the refinement
+    stops when an outer step no longer halves the FP64 residual, in the
+    engine as in a context.  Both report OSCAR_W_REFINE_STALL and give the
+    same fields, bitwise."""
+    from paper_2105_10576_amd import oscar
+    c = dict(_reqs()[3])
+    c["pcg_rtol"] = 1e-17
+    c["max_iters"] = 2
+    g = oscar.Oscar(c, precision=1)
+    rc1 = g.viscous_step(c["dt_vd"])
+    rc2, kf, E = g.capillary_relax(c["dt_vd"], c["n_sub"], c["max_iters"], c["tol"])
+    assert rc1 == oscar.W_REFINE_STALL and rc2 == oscar.W_REFINE_STALL
+    out = _run_alone(oscar, c, 1)
+    assert out["status"] == oscar.W_REFINE_STALL and out["k_f"] == kf
+    for f in ("alpha", "p", "U"):
+        assert np.array_equal(out[f], g.get(f)), f
+
+
+@pytest.mark.parametrize("precond", [0, 1])
+def test_engine_matches_oracle(precond):
+    """A request through the engine (FP64, batched launches, a second request
+    in the mix) against the FP64 oracle: alpha, p and U after one OSCAR step
+    within 1e-9 relative L-infinity, the same k_f."""
+    from oracle.pyoracle import Oracle
+    from paper_2105_10576_amd import oscar
+    c = dict(_reqs()[0])
+    c["pcg_rtol"] = 1e-13
+    c["precond"] = precond
+    other = _reqs()[2]
+    r = Oracle(c)
+    r.step()
+    ko = r.stats()["k_f"]
+    heap = oscar.workspace_size(c, 0) + oscar.workspace_size(other, 0) + (1 << 20)
+    e = oscar.Engine(4, heap, precision=0)
+    s = e.admit(c)
+    s2 = e.admit(other)
+    out = None
+    for _ in range(10000):
+        done, act = e.poll()
+        if s in done:
+            out = e.fetch(s)
+            break
+        e.run(1)
+    assert out is not None and out["status"] == 0
+    assert out["k_f"] == ko
+    for f in ("alpha", "p", "U"):
+        ref = r.get(f)
+        err = np.abs(out[f] - ref).max() / np.abs(ref).max()
+        assert err <= 1e-9, (f, err)

@@ -92,10 +92,10 @@ def test_mg_pressure_solve_mixed(shape):
 
 
 @pytest.mark.parametrize("shape", [(64, 48, 64, 3), (300, 200, 1, 2)])
-def test_mg_two_sweep_levels(monkeypatch, shape):
+def test_mg_two_sweep_levels(shape):
     """Two smoothing sweeps per side on grid-wide coarse levels (the setting
-    of 3D grids, forced here through the level mask
-    OSCAR_MG_SWEEPS2; 64 x 48 x 64: FP64 grid-wide levels of 24576 and 3072
+    of 3D grids, forced here through the descriptor's level mask
+    mg_sweeps2; 64 x 48 x 64: FP64 grid-wide levels of 24576 and 3072
     cells, FP32 one; 300 x 200 in 2D: 15000 and 3750 cells, FP32 one): the
     FP64 solves with level 2, or levels 1 and 2, smoothed twice match the
     oracle to 1e-10 and take fewer CG iterations than with one sweep; the
@@ -110,9 +110,8 @@ def test_mg_two_sweep_levels(monkeypatch, shape):
     r.set("phi_cr", f["phi"])
     assert r.pressure_solve(1, 1e-5, 1e-13, 20000)[0] == 0
     iters = {}
-    for mask in (0, 4, 6):
-        monkeypatch.setenv("OSCAR_MG_SWEEPS2", str(mask))
-        g = o.Oscar(c, precision=o.FP64, precond=o.PC_MG)
+    for mask in (-1, 4, 6):
+        g = o.Oscar(c, precision=o.FP64, precond=o.PC_MG, mg_sweeps2=mask)
         g.set("U_cr", f["U"])
         g.set("phi_cr", f["phi"])
         print("mg two sweeps, fp64", shape, "mask", mask, flush=True)
@@ -121,9 +120,8 @@ def test_mg_two_sweep_levels(monkeypatch, shape):
         assert rel_linf(g.get("p_cr"), r.get("p_cr")) <= 1e-10, mask
         iters[mask] = it
         g.close()
-    assert iters[4] < iters[0] and iters[6] < iters[0], iters
-    monkeypatch.setenv("OSCAR_MG_SWEEPS2", "2")
-    g = o.Oscar(c, precision=o.MIXED, precond=o.PC_MG)
+    assert iters[4] < iters[-1] and iters[6] < iters[-1], iters
+    g = o.Oscar(c, precision=o.MIXED, precond=o.PC_MG, mg_sweeps2=2)
     j = o.Oscar(c, precision=o.MIXED)
     for side in (g, j):
         side.set("U_cr", f["U"])
