@@ -152,6 +152,22 @@ int32_t oscar_workspace_size(const oscar_desc *desc, uint64_t *bytes);
 int32_t oscar_create(const oscar_desc *desc, void *dev_workspace, uint64_t bytes, void *hip_stream,
                      oscar_ctx **out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): oscar_create
+ * with the workspace taken from a static device array of the library,
+ * OSCAR_STATIC_WORKSPACE_BYTES on each device it runs on (held until the
+ * process ends), and the state readback through pageable host memory inside
+ * the context.  Neither this call nor the steps, solves, field accesses and
+ * oscar_destroy of the context allocate device or pinned memory
+ * (oscar_timing does; do not call it on such a context).  One such context
+ * per device at a time: OSCAR_E_CAPACITY while another holds the array
+ * (oscar_destroy releases it; contexts on one device that overlapped would
+ * race on the array).  OSCAR_E_WORKSPACE if oscar_workspace_size exceeds
+ * the array.  Otherwise as oscar_create; a new context starts from a
+ * cleared workspace, so nothing of an earlier context carries over. */
+#define OSCAR_STATIC_WORKSPACE_BYTES (64ull << 20)
+int32_t oscar_create_static(const oscar_desc *desc, void *hip_stream, oscar_ctx **out);
+
 /* One viscous-drag step of length dt_vd (Section 3.1): alpha* from u_vd^n
  * (Eq. VOFd), then n_corr PISO correctors of Eq. NSE1d/md convected by
  * u_vd^n + u_cr^n.  OSCAR_E_UNSTABLE if the transport Courant number

@@ -17,6 +17,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -281,7 +282,9 @@ struct oscar_ctx {
   int2 *d_btab = nullptr;
   int btab_len = 0;
   hipStream_t stream = nullptr;
-  SlotState *h_state = nullptr;   // pinned readback
+  SlotState *h_state = nullptr;   // pinned readback (the static-workspace variant: h_state_own)
+  SlotState h_state_own;          // pageable readback of a context in the static workspace
+  int static_dev = -1;            // device whose static workspace this context holds, or -1
   std::string err = "no error";
   int64_t n_fluid = 0;
   // host bookkeeping
@@ -593,8 +596,11 @@ extern "C" int32_t oscar_workspace_size(const oscar_desc *desc, uint64_t *bytes)
   return OSCAR_OK;
 }
 
-extern "C" int32_t oscar_create(const oscar_desc *desc, void *ws, uint64_t bytes, void *hip_stream,
-                                oscar_ctx **out) {
+// static_dev >= 0: the workspace is that device's static array and the
+// state readback goes through pageable host memory inside the context, so
+// nothing is allocated by HIP.
+static int32_t create_impl(const oscar_desc *desc, void *ws, uint64_t bytes, void *hip_stream, oscar_ctx **out,
+                           int static_dev) {
   if (!out) { g_err = "out is NULL"; return OSCAR_E_ARG; }
   *out = nullptr;
   std::string why;
@@ -689,12 +695,14 @@ extern "C" int32_t oscar_create(const oscar_desc *desc, void *ws, uint64_t bytes
 
   auto fail = [&](hipError_t e, const char *what) {
     hip_fail(nullptr, e, what);
-    if (c->h_state) (void)hipHostFree(c->h_state);
+    if (c->h_state && c->static_dev < 0) (void)hipHostFree(c->h_state);
     delete c;
     return OSCAR_E_HIP;
   };
   hipError_t e;
-  if ((e = hipHostMalloc((void **)&c->h_state, sizeof(SlotState), hipHostMallocDefault)) != hipSuccess)
+  c->static_dev = static_dev;
+  if (static_dev >= 0) c->h_state = &c->h_state_own;
+  else if ((e = hipHostMalloc((void **)&c->h_state, sizeof(SlotState), hipHostMallocDefault)) != hipSuccess)
     return fail(e, "hipHostMalloc");
   if ((e = hipMemsetAsync(ws, 0, cv.off, c->stream)) != hipSuccess) return fail(e, "hipMemsetAsync");
   if ((e = hipMemcpyAsync((void *)s.flags, fl.data(), nc, hipMemcpyHostToDevice, c->stream)) != hipSuccess)
@@ -722,13 +730,85 @@ extern "C" int32_t oscar_create(const oscar_desc *desc, void *ws, uint64_t bytes
   return OSCAR_OK;
 }
 
+extern "C" int32_t oscar_create(const oscar_desc *desc, void *ws, uint64_t bytes, void *hip_stream,
+                                oscar_ctx **out) {
+  return create_impl(desc, ws, bytes, hip_stream, out, -1);
+}
+
+// ---------------------------------------------------------------------------
+// the allocation-free variant: the workspace is a static device array
+// ---------------------------------------------------------------------------
+
+namespace {
+
+// The workspace of oscar_create_static.  In host code `scratch` names a
+// host-side stand-in; its device address on each device comes from
+// hipGetSymbolAddress and is the only handle used.
+constexpr uint64_t STATIC_WS_BYTES = OSCAR_STATIC_WORKSPACE_BYTES;
+static __device__ __align__(256) unsigned char scratch[STATIC_WS_BYTES];
+
+constexpr int STATIC_MAX_DEV = 64;
+struct StaticWs {
+  void *ptr = nullptr;   // device address of `scratch` on this device (0: not looked up yet)
+  bool busy = false;     // a live context holds it
+};
+StaticWs g_static[STATIC_MAX_DEV];
+std::mutex g_static_mu;
+
+}  // namespace
+
+extern "C" int32_t oscar_create_static(const oscar_desc *desc, void *hip_stream, oscar_ctx **out) {
+  if (!out) { g_err = "out is NULL"; return OSCAR_E_ARG; }
+  *out = nullptr;
+  uint64_t need = 0;
+  int rc = oscar_workspace_size(desc, &need);
+  if (rc) return rc;
+  if (need > STATIC_WS_BYTES) {
+    char buf[200];
+    snprintf(buf, sizeof buf, "the descriptor needs %llu bytes of workspace; the static workspace holds %llu",
+             (unsigned long long)need, (unsigned long long)STATIC_WS_BYTES);
+    g_err = buf;
+    return OSCAR_E_WORKSPACE;
+  }
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(nullptr, e, "hipGetDevice");
+  if (dev < 0 || dev >= STATIC_MAX_DEV) { g_err = "device ordinal out of range"; return OSCAR_E_ARG; }
+  void *ws = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    StaticWs &w = g_static[dev];
+    if (!w.ptr) {   // once per device, with that device current
+      void *p = nullptr;
+      e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+      if (e != hipSuccess) return hip_fail(nullptr, e, "hipGetSymbolAddress(scratch)");
+      if (!p) { g_err = "hipGetSymbolAddress(scratch) returned NULL"; return OSCAR_E_HIP; }
+      w.ptr = p;
+    }
+    if (w.busy) { g_err = "the static workspace of this device is held by another context"; return OSCAR_E_CAPACITY; }
+    w.busy = true;
+    ws = w.ptr;
+  }
+  rc = create_impl(desc, ws, STATIC_WS_BYTES, hip_stream, out, dev);
+  if (rc) {
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    g_static[dev].busy = false;
+  }
+  return rc;
+}
+
 extern "C" void oscar_destroy(oscar_ctx *c) {
   if (!c) return;
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   if (c->d_ts) (void)hipFree(c->d_ts);
   if (c->d_span) (void)hipFree(c->d_span);
   if (c->h_span) (void)hipHostFree(c->h_span);
-  if (c->h_state) (void)hipHostFree(c->h_state);
+  if (c->static_dev >= 0) {
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    g_static[c->static_dev].busy = false;
+  } else if (c->h_state) {
+    (void)hipHostFree(c->h_state);
+  }
   delete c;
 }
 

@@ -19,7 +19,7 @@ PC_JACOBI, PC_MG = 0, 1
 FIELDS = dict(alpha=0, U=1, p=2, U_vd=3, p_vd=4, U_cr=5, p_cr=6, phi_vd=7, phi_vd_prev=8, phi_cr=9,
               kappa=10, rAU=11, rhs=12, U_sum=13, HbyA=14, nhatf=15)
 
-EXPORTS = ["oscar_workspace_size", "oscar_create", "oscar_viscous_step", "oscar_capillary_relax",
+EXPORTS = ["oscar_workspace_size", "oscar_create", "oscar_create_static", "oscar_viscous_step", "oscar_capillary_relax",
            "oscar_relax_history", "oscar_pressure_solve", "oscar_get_field", "oscar_set_field",
            "oscar_field_len", "oscar_stats", "oscar_destroy", "oscar_last_error", "oscar_dt_brackbill",
            "oscar_timing", "oscar_timing_read"]
@@ -63,6 +63,7 @@ def lib():
         dp, ip, vp = C.POINTER(C.c_double), C.POINTER(C.c_int32), C.c_void_p
         L.oscar_workspace_size.argtypes = [C.POINTER(Desc), C.POINTER(C.c_uint64)]
         L.oscar_create.argtypes = [C.POINTER(Desc), vp, C.c_uint64, vp, C.POINTER(vp)]
+        L.oscar_create_static.argtypes = [C.POINTER(Desc), vp, C.POINTER(vp)]
         L.oscar_viscous_step.argtypes = [vp, C.c_double]
         L.oscar_capillary_relax.argtypes = [vp, C.c_double, C.c_int32, C.c_int32, C.c_double, ip, dp]
         L.oscar_relax_history.argtypes = [vp, dp, C.c_int32, ip]
@@ -82,8 +83,8 @@ def lib():
         L.oscar_timing.restype = C.c_int32
         L.oscar_timing_read.argtypes = [vp, C.c_int32, dp, C.POINTER(C.c_int64)]
         L.oscar_timing_read.restype = C.c_int32
-        for name in ("oscar_workspace_size", "oscar_create", "oscar_viscous_step", "oscar_capillary_relax",
-                     "oscar_relax_history", "oscar_pressure_solve", "oscar_get_field", "oscar_set_field",
+        for name in ("oscar_workspace_size", "oscar_create", "oscar_create_static", "oscar_viscous_step",
+                     "oscar_capillary_relax", "oscar_relax_history", "oscar_pressure_solve", "oscar_get_field", "oscar_set_field",
                      "oscar_stats"):
             getattr(L, name).restype = C.c_int32
         _lib = L
@@ -131,9 +132,10 @@ def dt_brackbill(rho1, rho2, h, sigma):
 
 class Oscar:
     """One OSCAR context on a GPU; fields stay resident in a torch uint8
-    workspace tensor on that device."""
+    workspace tensor on that device, or (static_workspace=True) in the
+    library's static device array (oscar_create_static: no allocation)."""
 
-    def __init__(self, case, precision=FP64, device="cuda:0", stream=None, **over):
+    def __init__(self, case, precision=FP64, device="cuda:0", stream=None, static_workspace=False, **over):
         import torch
 
         c = dict(case)
@@ -148,14 +150,17 @@ class Oscar:
         if rc != OK:
             raise OscarError(rc, L.oscar_last_error(None).decode())
         self.ws_bytes = n.value
-        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+        self.ws = None if static_workspace else torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
         if stream is None:
             stream = torch.cuda.current_stream(self.device)
         self.stream = stream
         self.ctx = C.c_void_p(None)
         with torch.cuda.device(self.device):
-            rc = L.oscar_create(C.byref(d), C.c_void_p(self.ws.data_ptr()), self.ws_bytes,
-                                C.c_void_p(stream.cuda_stream), C.byref(self.ctx))
+            if static_workspace:
+                rc = L.oscar_create_static(C.byref(d), C.c_void_p(stream.cuda_stream), C.byref(self.ctx))
+            else:
+                rc = L.oscar_create(C.byref(d), C.c_void_p(self.ws.data_ptr()), self.ws_bytes,
+                                    C.c_void_p(stream.cuda_stream), C.byref(self.ctx))
         if rc != OK:
             raise OscarError(rc, L.oscar_last_error(None).decode())
         self.nc = int(c["nx"]) * int(c["ny"]) * int(c["nz"])
