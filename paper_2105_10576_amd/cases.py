@@ -332,6 +332,20 @@ def random_fields(case, seed=1, u_scale=1e-3, p_scale=1.0):
     return dict(U=U.reshape(-1), p=p, phi=phi)
 
 
+def fp32_ulp_perturbed(alpha, seed=0):
+    """alpha with every partial cell (0 < alpha < 1) moved by one FP32 unit
+    in the last place, up or down at random (seeded): an input perturbation
+    of the size of FP32 storage, for sensitivity yardsticks."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    a32 = alpha.astype(np.float32)
+    up = np.nextafter(a32, np.float32(2.0))
+    dn = np.nextafter(a32, np.float32(-1.0))
+    pick = rng.uniform(size=alpha.shape) < 0.5
+    out = np.where(pick, up, dn).astype(np.float64)
+    part = (alpha > 0.0) & (alpha < 1.0)
+    return np.where(part, out, alpha)
+
+
 CONFIGS = {
     "c1": channel_bubble,
     "c2": constricted_channel,

@@ -871,7 +871,8 @@ __device__ __forceinline__ bool mgcg_dir_body(const Slot &s, int lb, int it) {
   // q_old at the cell only: one array fewer at the six neighbours.  The
   // rounding the recurrence adds stays at the level of the solve's own
   // (in the mixed path the outer FP64 refinement measures the true
-  // residual; the FP64 path's parity with the oracle is tested to 50 steps).
+  // residual; over 50 steps of the channel bubble the FP64 path stays within
+  // the oracle's own round-off sensitivity).
   constexpr bool rec = true;
   struct Op {
     Cell c;

@@ -1,0 +1,106 @@
+"""Oracle runs that take minutes, computed in background threads from the
+start of the test session so that they overlap the GPU tests that need them.
+The oracle is C code called through ctypes, which releases the GIL, so the
+threads run on separate cores.  Each job builds its inputs from cases.py
+(seeded) and returns the oracle's fields; conftest.py starts the jobs that
+the selected tests name with the `oracle_job` marker."""
+from __future__ import annotations
+
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+
+from oracle.pyoracle import Oracle
+from paper_2105_10576_amd import cases
+
+_pool = None
+_jobs = {}
+JOBS = {}
+
+
+def job(fn):
+    JOBS[fn.__name__] = fn
+    return fn
+
+
+def start(names):
+    global _pool
+    if _pool is None:
+        _pool = ThreadPoolExecutor(max_workers=4)
+    for n in names:
+        if n not in _jobs:
+            _jobs[n] = _pool.submit(JOBS[n])
+
+
+def result(name):
+    start([name])
+    return _jobs[name].result()
+
+
+def _fields(o, names=("alpha", "p", "U", "p_vd", "U_vd", "kappa")):
+    return {f: o.get(f) for f in names}
+
+
+def channel3d_case():
+    """The 3D constricted channel 128x64x64 of the benchmark, every sub-step
+    run (tol = 0), pressure solves to 1e-12."""
+    c = cases.constricted_channel(tol=0.0)
+    c["pcg_rtol"] = 1e-12
+    return c
+
+
+@job
+def channel3d_step():
+    """One OSCAR global step of the 3D channel: the viscous step, then the
+    relaxation of N = 12 sub-steps; fields after the viscous step and after
+    the relaxation."""
+    c = channel3d_case()
+    o = Oracle(c)
+    assert o.viscous_step(c["dt_vd"]) == 0
+    vd = _fields(o, ("alpha", "p_vd", "U_vd"))
+    rc, kf, E = o.capillary_relax(c["dt_vd"], c["n_sub"], c["n_sub"], 0.0)
+    assert rc == 0
+    out = _fields(o)
+    out.update({"vd_" + k: v for k, v in vd.items()})
+    out["k_f"] = kf
+    out["E"] = E
+    return out
+
+
+def sphere_small_case(n=64):
+    """A 64^3 sample of the sphere-pack medium (same sphere radii, porosity
+    and fluids as the 256^3 workload, buffers of 8 voxels), FP64 parity
+    settings: two capillary sub-steps, pressure solves to 1e-12."""
+    c = cases.sphere_pack(n=n, max_iters=2)
+    c["pcg_rtol"] = 1e-12
+    return c
+
+
+@job
+def sphere_small_step():
+    c = sphere_small_case()
+    o = Oracle(c)
+    rc1, rc2, kf, E = o.step()
+    assert rc1 == 0 and rc2 == 0
+    out = _fields(o)
+    out["k_f"] = kf
+    return out
+
+
+def sphere_ops_case(n=128):
+    """A 128^3 sample of the sphere-pack medium for the local operators."""
+    return cases.sphere_pack(n=n)
+
+
+@job
+def sphere_ops():
+    """Curvature, 1/a_P, H/a_P and the pressure right-hand side of the 128^3
+    sample on an injected random state (the assembly of one capillary
+    sub-step's first corrector)."""
+    c = sphere_ops_case()
+    f = cases.random_fields(c, seed=21)
+    o = Oracle(c)
+    o.set("U_cr", f["U"])
+    o.set("phi_cr", f["phi"])
+    o.pressure_solve(1, c["dt_vd"] / c["n_sub"], 1e-8, 1)
+    return {k: o.get(k) for k in ("kappa", "rAU", "HbyA", "rhs")}
