@@ -1,6 +1,6 @@
 """Benchmark of the OSCAR relaxation path on one MI355X.
 
-Workload (default): the 3D constricted channel, 128 x 64 x 64 voxels at
+Workload (the headline): the 3D constricted channel, 128 x 64 x 64 voxels at
 5 um with a cosine throat of radius 0.4 R, a CO2 slug in the first 30 % of the
 channel, Ca = 1e-4, dt_vd = 0.1 dt_CFL, N = 12 capillary sub-steps below
 the Brackbill limit; mixed precision (FP32 fields, stencils, preconditioner
@@ -11,17 +11,24 @@ to a 1e-8 relative FP64 residual.
 
 One timed step = one OSCAR global step = one viscous-drag step followed by
 the capillary relaxation with max_iters = N and tol = 0, so every sub-step
-runs.  The metric counts (1 + N) cell-iterations per cell and step (the
-viscous step counts as one iteration); value = total cell-iterations / wall
-time of the K timed steps / 1e6, inputs resident on the device.
+runs.  value = relaxation Mcell-iter/s: the sub-steps executed times the
+voxels, over the device time of the oscar_capillary_relax calls (HIP events
+on the stream the library works on), / 1e6; inputs resident on the device.
+The whole-step rate, counting the viscous step as one more iteration over
+the wall time of the whole steps, is reported beside it.
 
 Kernel timing: inside the timed steps every 8th conjugate-gradient iteration
 is sampled by the library's timing hook (its kernels stamp the device wall
-clock at the start and end of every workgroup), giving the average execution
-time of each part of an iteration; the roofline entry is the fine-grid
-kernel with the largest share, its algorithmic bytes (each array it must
-read or write counted once per fluid cell, the face-flag byte once per cell)
-over that average duration.
+clock at the start and end of every workgroup), giving the execution span of
+each part of an iteration; rocprofv3's dispatch interval of the same launch
+is that span plus the packet dispatch and completion (1.2-1.7 us, the
+committed kernel profile), and the roofline entry gives the fraction with
+both.  The roofline entry is the fine-grid kernel with the largest share,
+its algorithmic bytes (each array it must read or write counted once per
+fluid cell, the face-flag byte once per cell) over its average duration.
+The 128 x 64 x 64 working set (168 MB mixed) fits the 256 MB last-level
+cache, so its GB/s are effective figures; the 256^3 sphere pack (3 GB),
+run beside it, streams from HBM.
 
 Prints one JSON line.
 """
@@ -36,6 +43,10 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 TIMING_PERIOD = 8
+# rocprofv3's kernel duration exceeds the timing hook's span by the packet
+# dispatch before the first wave and the completion signal after the last:
+# 1.2-1.7 us for every kernel and both precisions (profiles/kernels_mg_cg_*.md)
+DISPATCH_US = 1.4
 
 # parts of a CG iteration reported by the timing hook (index: kernel name)
 MG_PARTS = {1: "k_mgcg_dir", 2: "k_mg_fine_down", 3: "coarse levels (k_mg_smooth, k_mg_tail, k_mg_up)",
@@ -89,6 +100,8 @@ def run_gpu(case, precision, steps, warmup, precond=1, timing_period=TIMING_PERI
     torch.cuda.synchronize()
     if timing_period:
         g.timing(timing_period)
+    stream = torch.cuda.current_stream()
+    ev = []
     t0 = time.perf_counter()
     pcg = 0
     refine = 0
@@ -97,18 +110,24 @@ def run_gpu(case, precision, steps, warmup, precond=1, timing_period=TIMING_PERI
         st = g.stats()
         pcg += st["pcg_iters_call"]
         refine += st["refine_steps_call"]
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
         rc, kf, E = g.capillary_relax(case["dt_vd"], n_sub, n_sub, 0.0)
+        e1.record(stream)
+        ev.append((e0, e1))
         st = g.stats()
         pcg += st["pcg_iters_call"]
         refine += st["refine_steps_call"]
         assert kf == n_sub
     torch.cuda.synchronize()
     t = time.perf_counter() - t0
+    relax_s = sum(a.elapsed_time(b) for a, b in ev) / 1e3
     parts = {k: g.timing_read(k) for k in range(5)} if timing_period else None
     if timing_period:
         g.timing(0)
     st = g.stats()
-    res = dict(seconds=t, pcg_iters=pcg, refine_steps=refine, parts=parts, stats=st, iters=steps * (1 + n_sub))
+    res = dict(seconds=t, relax_seconds=relax_s, pcg_iters=pcg, refine_steps=refine, parts=parts, stats=st,
+               iters=steps * (1 + n_sub), relax_iters=steps * n_sub)
     g.close()
     return res
 
@@ -164,16 +183,55 @@ def dominant(table):
     return best
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    passes (profiles/pmc_traffic.json), or None when the kernel's sources
-    changed since the counters were taken."""
+def kernel_roofline(ktab, dom, precision, cache_resident, traffic=None):
+    """The roofline entry of kernel `dom`: algorithmic bytes over the hook's
+    execution span, and over the span plus the dispatch interval rocprofv3
+    adds (the figure its kernel trace reports)."""
+    d = ktab[dom]
+    us_d = d["avg_us"] + DISPATCH_US
+    gbs_d = d["alg_bytes"] / (us_d * 1e-6) / 1e9
+    out = {"bound": "hbm", "kernel": dom, "achieved": d["GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(d["GBs"] / HBM_PEAK_GBS, 4), "traffic": traffic, "avg_launch_us": d["avg_us"],
+           "alg_bytes_per_launch": d["alg_bytes"], "launches_timed": d["launches_timed"],
+           "avg_launch_us_with_dispatch": round(us_d, 3), "achieved_with_dispatch": round(gbs_d, 1),
+           "frac_with_dispatch": round(gbs_d / HBM_PEAK_GBS, 4),
+           "timing": "device wall-clock stamps of every %d-th CG iteration of the timed steps (first wave start "
+                     "to last wave end); 'with_dispatch' adds the %.1f us packet dispatch and completion that "
+                     "rocprofv3's kernel trace includes" % (TIMING_PERIOD, DISPATCH_US)}
+    if cache_resident:
+        out["note"] = ("effective GB/s: the working set fits the 256 MB last-level cache, so these bytes are "
+                       "not all HBM traffic")
+    return out
+
+
+def k7_roofline(ktab, precision, n_fluid, precond):
+    """One CG iteration against the unit of the survey's roofline (Jacobi PCG:
+    13 words per fluid cell per iteration), and the multigrid iteration's own
+    fine-grid bytes, over the whole iteration's time (all its launches and
+    the gaps between them, from the timing hook)."""
+    it = ktab["iteration"]["avg_us"] * 1e-6
+    if it <= 0:
+        return None
+    b13 = 13 * word(precision) * n_fluid
+    out = {"bytes_13_words": b13, "avg_iteration_us": ktab["iteration"]["avg_us"],
+           "achieved_GBs": round(b13 / it / 1e9, 1), "frac": round(b13 / it / 1e9 / HBM_PEAK_GBS, 4)}
+    if precond == 1:
+        fine = sum(ktab[k]["alg_bytes"] for k in ("k_mgcg_dir", "k_mg_fine_down", "k_mg_fine_up") if k in ktab)
+        out.update(fine_grid_bytes=fine, fine_grid_GBs=round(fine / it / 1e9, 1),
+                   fine_grid_frac=round(fine / it / 1e9 / HBM_PEAK_GBS, 4))
+    return out
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` on `workload` from the committed
+    rocprofv3 counter passes (profiles/pmc_traffic.json), or None when the
+    kernel's sources changed since the counters were taken."""
     import hashlib
 
     path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
     if not os.path.exists(path):
         return None
-    rec = json.load(open(path)).get(kernel)
+    rec = json.load(open(path)).get(workload, {}).get(kernel)
     if not rec:
         return None
     h = hashlib.sha256()
@@ -186,16 +244,18 @@ def run_reps(case, precision, reps, warmup, max_iters, precond=1):
     """One OSCAR global step with max_iters relaxation sub-steps (tol = 0),
     repeated from a fresh context each time (the checkpoint is the initial
     state): warmup untimed repetitions, then reps timed ones; the median
-    time and the kernel timing summed over the timed repetitions."""
+    time (whole step, and the relaxation alone on HIP events) and the kernel
+    timing summed over the timed repetitions."""
     import torch
 
     from paper_2105_10576_amd import oscar
 
-    times, pcg, kfs, refs = [], [], [], []
+    times, rtimes, pcg, kfs, refs = [], [], [], [], []
     acc = {k: [0.0, 0] for k in range(5)}
     for r in range(warmup + reps):
         g = oscar.Oscar(case, precision=precision, device="cuda:0", precond=precond)
         torch.cuda.synchronize()
+        stream = torch.cuda.current_stream()
         timed = r >= warmup
         if timed:
             g.timing(TIMING_PERIOD)
@@ -203,13 +263,18 @@ def run_reps(case, precision, reps, warmup, max_iters, precond=1):
         g.viscous_step(case["dt_vd"])
         st = g.stats()
         it, ref = st["pcg_iters_call"], st["refine_steps_call"]
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
         rc, kf, E = g.capillary_relax(case["dt_vd"], case["n_sub"], max_iters, 0.0)
+        e1.record(stream)
         st = g.stats()
         it += st["pcg_iters_call"]
         ref += st["refine_steps_call"]
         torch.cuda.synchronize()
         t = time.perf_counter() - t0
-        print("[bench] repetition %d (%s): %.3f s, k_f %d" % (r, "timed" if timed else "warm-up", t, kf),
+        tr = e0.elapsed_time(e1) / 1e3
+        print("[bench] %s %s repetition %d (%s): %.3f s (relaxation %.3f s), k_f %d"
+              % (case["name"], "mixed" if precision else "fp64", r, "timed" if timed else "warm-up", t, tr, kf),
               file=sys.stderr, flush=True)
         if timed:
             for k in range(5):
@@ -218,13 +283,14 @@ def run_reps(case, precision, reps, warmup, max_iters, precond=1):
                 acc[k][1] += n
             g.timing(0)
             times.append(t)
+            rtimes.append(tr)
             pcg.append(it)
             kfs.append(kf)
             refs.append(ref)
         g.close()
     order = sorted(range(reps), key=lambda x: times[x])
     m = order[len(order) // 2]
-    return dict(seconds=times[m], pcg_iters=pcg[m], k_f=kfs[m], refine_steps=refs[m],
+    return dict(seconds=times[m], relax_seconds=rtimes[m], pcg_iters=pcg[m], k_f=kfs[m], refine_steps=refs[m],
                 parts={k: tuple(v) for k, v in acc.items()}, times=times)
 
 
@@ -236,55 +302,71 @@ CONFIGS = {
 }
 
 
-def bench_config(args):
+def config_legs(config, pc, reps=3, warmup=1, fp64=True):
     """The c3 / c5 protocol: one viscous step and a relaxation of 20
-    sub-steps, 1 warm-up + 3 repetitions from the initial state, median."""
+    sub-steps from the initial state, warmup + reps repetitions, median;
+    mixed and FP64.  value: relaxation sub-steps x voxels over the
+    relaxation's device time."""
     from paper_2105_10576_amd import cases
 
-    make, fmt = CONFIGS[args.config]
+    make, fmt = CONFIGS[config]
     case = getattr(cases, make)(tol=0.0)
     case["pcg_rtol"] = 1e-8
     nx, ny, nz, dim = case["nx"], case["ny"], case["nz"], case["dim"]
     nc = nx * ny * nz
     nc1 = ((nx + 1) // 2) * ((ny + 1) // 2) * (((nz + 1) // 2) if dim == 3 else 1)
     n_fluid = int((case["mask"] == 0).sum())
-    pc = 1 if args.precond == "mg" else 0
     kmax = min(20, case["n_sub"])
-    out = {"metric": "relaxation Mcell-iter/s (mixed FP32 + FP64 refinement), HBM GB/s of the dominant kernel",
-           "unit": "Mcell-iter/s", "n_gpus": 1, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-           "dtype": "f32+f64", "data": "synthetic (seeded %s geometry)" % make}
+    out = {"workload": fmt % (n_fluid, kmax, case["n_sub"], "multigrid" if pc else "Jacobi"),
+           "protocol": "%d warm-up + %d repetitions from the initial state, median" % (warmup, reps)}
     for prec, key in ((1, "mixed"), (0, "fp64")):
-        if prec == 0 and args.no_fp64:
+        if prec == 0 and not fp64:
             continue
-        r = run_reps(case, prec, 3, 1, kmax, pc)
-        value = nc * (1 + r["k_f"]) / r["seconds"] / 1e6
+        r = run_reps(case, prec, reps, warmup, kmax, pc)
         ktab = kernel_table(r, prec, pc, n_fluid, nc, nc1)
         dom = dominant(ktab)
-        res = {"value": round(value, 3), "ms_per_step": round(1e3 * r["seconds"], 3), "k_f": r["k_f"],
-               "pcg_iters_per_step": r["pcg_iters"], "rep_seconds": [round(t, 4) for t in r["times"]],
-               "roofline": {"bound": "hbm", "kernel": dom, "achieved": ktab[dom]["GBs"], "peak": HBM_PEAK_GBS,
-                            "unit": "GB/s", "frac": round(ktab[dom]["GBs"] / HBM_PEAK_GBS, 4),
-                            "avg_launch_us": ktab[dom]["avg_us"], "alg_bytes_per_launch": ktab[dom]["alg_bytes"]},
-               "kernels": ktab,
-               "step_roofline": step_roofline(prec, pc, dim, n_fluid, nc, nc1, 1 + r["k_f"], r["pcg_iters"],
-                                              r["refine_steps"], r["seconds"])}
-        if prec == 1:
-            out.update(value=res["value"], ms_per_step=res["ms_per_step"], steps=3, warmup=1,
-                       config={"workload": fmt % (n_fluid, kmax, case["n_sub"], "multigrid" if pc else "Jacobi"),
-                               "precision": "mixed", "pcg_iters_per_step": r["pcg_iters"],
-                               "repetitions": "1 warm-up + 3 from the initial state, median"},
-                       roofline=dict(res["roofline"], traffic=None), kernels=ktab,
-                       step_roofline=res["step_roofline"])
-        else:
-            out["fp64"] = res
+        out[key] = {
+            "value": round(nc * r["k_f"] / r["relax_seconds"] / 1e6, 3),
+            "whole_step_mcell_iter_s": round(nc * (1 + r["k_f"]) / r["seconds"] / 1e6, 3),
+            "ms_per_step": round(1e3 * r["seconds"], 3), "relax_ms": round(1e3 * r["relax_seconds"], 3),
+            "k_f": r["k_f"], "pcg_iters_per_step": r["pcg_iters"], "refine_steps_per_step": r["refine_steps"],
+            "rep_seconds": [round(t, 4) for t in r["times"]],
+            "roofline": kernel_roofline(ktab, dom, prec, cache_resident=nc * 4 * 30 < (256 << 20),
+                                        traffic=measured_traffic(dom, case["name"]) if prec == 1 else None),
+            "k7_iteration": k7_roofline(ktab, prec, n_fluid, pc),
+            "kernels": ktab,
+            "step_roofline": step_roofline(prec, pc, dim, n_fluid, nc, nc1, 1 + r["k_f"], r["pcg_iters"],
+                                           r["refine_steps"], r["seconds"]),
+        }
+    return out
+
+
+def bench_config(args):
+    """--config c3|c5 alone (one JSON line)."""
+    pc = 1 if args.precond == "mg" else 0
+    legs = config_legs(args.config, pc, fp64=not args.no_fp64)
+    m = legs["mixed"]
+    out = {"metric": "relaxation Mcell-iter/s (mixed FP32 + FP64 refinement), HBM GB/s of the dominant kernel",
+           "value": m["value"], "unit": "Mcell-iter/s", "n_gpus": 1, "steps": 3, "warmup": 1,
+           "ms_per_step": m["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32+f64", "data": "synthetic (seeded %s geometry)" % CONFIGS[args.config][0],
+           "config": {"workload": legs["workload"], "precision": "mixed", "protocol": legs["protocol"],
+                      "whole_step_mcell_iter_s": m["whole_step_mcell_iter_s"],
+                      "pcg_iters_per_step": m["pcg_iters_per_step"]},
+           "roofline": m["roofline"], "k7_iteration": m["k7_iteration"], "kernels": m["kernels"],
+           "step_roofline": m["step_roofline"]}
+    if "fp64" in legs:
+        out["fp64"] = legs["fp64"]
     print(json.dumps(out), flush=True)
 
 
 def cpu_baseline(case, precond=1):
-    """The FP64 oracle on the host: the first viscous-drag step of the same
-    workload (3 PISO correctors with Jacobi-PCG), one cell-iteration per cell.
-    The same step on the GPU (both paths, from the same initial state) is
-    compared with it: relative L-infinity error of alpha, p_vd and U_vd."""
+    """The FP64 oracle on the host, single-threaded: one viscous-drag step of
+    the workload (to reach a flowing state), then the first capillary
+    sub-step, which is timed: one relaxation iteration over every voxel, the
+    unit of the metric.  The same prefix on the GPU (both paths, from the
+    same initial state) is compared with it: relative L-infinity error of
+    alpha, p and U."""
     import numpy as np
 
     from oracle.pyoracle import Oracle
@@ -292,15 +374,21 @@ def cpu_baseline(case, precond=1):
 
     o = Oracle(case)
     t0 = time.perf_counter()
-    rc = o.viscous_step(case["dt_vd"])
+    o.viscous_step(case["dt_vd"])
+    t_vd = time.perf_counter() - t0
+    it_vd = o.stats()["pcg_iters_step"]
+    t0 = time.perf_counter()
+    o.capillary_relax(case["dt_vd"], case["n_sub"], 1, 0.0)
     t = time.perf_counter() - t0
+    it_cr = o.stats()["pcg_iters_step"]
     nc = case["nx"] * case["ny"] * case["nz"]
     err = {}
     for prec, name in ((1, "mixed"), (0, "fp64")):
         g = oscar.Oscar(case, precision=prec, device="cuda:0", precond=precond)
         g.viscous_step(case["dt_vd"])
+        g.capillary_relax(case["dt_vd"], case["n_sub"], 1, 0.0)
         e = {}
-        for f in ("alpha", "p_vd", "U_vd"):   # the viscous step's own fields (p, U combine after a relaxation)
+        for f in ("alpha", "p", "U"):
             ref = o.get(f)
             den = float(np.abs(ref).max()) or 1.0
             e[f] = float("%.3g" % (float(np.abs(g.get(f) - ref).max()) / den))
@@ -316,10 +404,13 @@ def cpu_baseline(case, precond=1):
         pass
     return dict(value=nc / t / 1e6, unit="Mcell-iter/s", cores=1, kind="oracle",
                 host=dict(cpu=cpu, threads_available=os.cpu_count()),
-                sample="first viscous-drag step of the same grid (1 cell-iteration per cell, %d PCG iterations), "
-                       "single-threaded FP64 oracle, %.1f s" % (o.stats()["pcg_iters_step"], t),
-                error_vs_oracle=dict(err, prefix="the same first viscous-drag step on the GPU, relative L-infinity; "
-                                                 "both sides solve to the workload's pressure rtol"))
+                sample="the first capillary sub-step of the same workload (one relaxation iteration over the "
+                       "524288 voxels, 3 PISO correctors, %d Jacobi-PCG iterations, %.1f s), after its viscous "
+                       "step (%d iterations, %.1f s, not timed); single-threaded FP64 oracle, pressure rtol 1e-8"
+                       % (it_cr, t, it_vd, t_vd),
+                error_vs_oracle=dict(err, prefix="the same prefix (viscous step + first sub-step) on the GPU, "
+                                                 "relative L-infinity; both sides solve to the workload's "
+                                                 "pressure rtol"))
 
 
 def main():
@@ -331,15 +422,16 @@ def main():
     ap.add_argument("--precond", choices=["mg", "jacobi"], default="mg",
                     help="preconditioner of the pressure conjugate gradient")
     ap.add_argument("--config", choices=["c2", "c3", "c5"], default="c2",
-                    help="c2: the default workload; c3 (2D micromodel 1024x512) and c5 (3D sphere pack 256^3): "
-                         "one viscous step + 20 relaxation sub-steps, 1 warm-up + 3 repetitions, median")
+                    help="c2: the default run (the 3D channel, with the 256^3 sphere pack and serving beside it); "
+                         "c3 (2D micromodel 1024x512) or c5 (3D sphere pack 256^3) alone")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 path beside the mixed path")
     ap.add_argument("--no-serving", action="store_true", help="skip the batched-serving measurement")
+    ap.add_argument("--no-sphere", action="store_true", help="skip the 256^3 sphere-pack legs")
     ap.add_argument("--pmc-calibration", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device-to-device (calibrates rocprofv3 FETCH_SIZE/WRITE_SIZE)")
     ap.add_argument("--serving-requests", type=int, default=64)
-    ap.add_argument("--serving-max-iters", type=int, default=40,
+    ap.add_argument("--serving-max-iters", type=int, default=200,
                     help="cap on relaxation sub-steps per serving request (the mix allows up to 200)")
     args = ap.parse_args()
     if args.pmc_calibration:
@@ -375,12 +467,10 @@ def main():
     pc = 1 if args.precond == "mg" else 0
 
     mixed = run_gpu(case, 1, args.steps, args.warmup, precond=pc)
-    value = mixed["iters"] * nc / mixed["seconds"] / 1e6
+    value = mixed["relax_iters"] * nc / mixed["relax_seconds"] / 1e6
     ms_step = 1e3 * mixed["seconds"] / args.steps
     ktab = kernel_table(mixed, 1, pc, n_fluid, nc, nc1)
     dom = dominant(ktab)
-    d = ktab[dom]
-    achieved = d["GBs"]
 
     out = {
         "metric": "relaxation Mcell-iter/s (mixed FP32 + FP64 refinement), HBM GB/s of the dominant kernel",
@@ -400,22 +490,17 @@ def main():
                         "1 viscous + %d relaxation iterations per step, tol=0, pressure rtol 1e-8, "
                         "%s-preconditioned CG" % (n_fluid, n_sub, n_sub, "multigrid" if pc else "Jacobi"),
             "precision": "mixed",
+            "value_counts": "relaxation sub-steps x voxels over the device time of the oscar_capillary_relax "
+                            "calls (HIP events on the library's stream)",
+            "relax_ms_per_step": round(1e3 * mixed["relax_seconds"] / args.steps, 3),
+            "whole_step_mcell_iter_s": round(mixed["iters"] * nc / mixed["seconds"] / 1e6, 3),
+            "whole_step_counts": "(1 + N) iterations per voxel and step (the viscous step as one) over the wall "
+                                 "time of the whole steps",
             "pcg_iters_per_step": round(mixed["pcg_iters"] / args.steps, 1),
             "refine_steps_per_step": round(mixed["refine_steps"] / args.steps, 1),
         },
-        "roofline": {
-            "bound": "hbm",
-            "kernel": dom,
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": measured_traffic(dom),
-            "avg_launch_us": d["avg_us"],
-            "alg_bytes_per_launch": d["alg_bytes"],
-            "launches_timed": d["launches_timed"],
-            "timing": "device wall-clock stamps of every %d-th CG iteration of the timed steps" % TIMING_PERIOD,
-        },
+        "roofline": kernel_roofline(ktab, dom, 1, cache_resident=True, traffic=measured_traffic(dom, case["name"])),
+        "k7_iteration": k7_roofline(ktab, 1, n_fluid, pc),
         "kernels": ktab,
         "step_roofline": step_roofline(1, pc, 3, n_fluid, nc, nc1, mixed["iters"] / args.steps,
                                        mixed["pcg_iters"] / args.steps, mixed["refine_steps"] / args.steps,
@@ -426,17 +511,22 @@ def main():
         ftab = kernel_table(f, 0, pc, n_fluid, nc, nc1)
         fdom = dominant(ftab)
         out["fp64"] = {
-            "value": round(f["iters"] * nc / f["seconds"] / 1e6, 3),
+            "value": round(f["relax_iters"] * nc / f["relax_seconds"] / 1e6, 3),
+            "whole_step_mcell_iter_s": round(f["iters"] * nc / f["seconds"] / 1e6, 3),
             "ms_per_step": round(1e3 * f["seconds"] / args.fp64_steps, 3),
             "steps": args.fp64_steps,
             "pcg_iters_per_step": round(f["pcg_iters"] / args.fp64_steps, 1),
-            "dominant_kernel": fdom,
-            "achieved_GBs": ftab[fdom]["GBs"],
-            "frac": round(ftab[fdom]["GBs"] / HBM_PEAK_GBS, 4),
+            "roofline": kernel_roofline(ftab, fdom, 0, cache_resident=False),
+            "k7_iteration": k7_roofline(ftab, 0, n_fluid, pc),
             "kernels": ftab,
             "step_roofline": step_roofline(0, pc, 3, n_fluid, nc, nc1, f["iters"] / args.fp64_steps,
                                            f["pcg_iters"] / args.fp64_steps, 0, f["seconds"] / args.fp64_steps),
         }
+        out["fp64"]["roofline"].pop("note", None)
+        out["fp64"]["roofline"]["note"] = ("FP64 working set 309 MB, about the size of the 256 MB last-level "
+                                          "cache: partly cache-resident")
+    if not args.no_sphere:
+        out["sphere_pack"] = config_legs("c5", pc, reps=2, warmup=1, fp64=not args.no_fp64)
     if not args.no_serving:
         from paper_2105_10576_amd import serving_bench
 

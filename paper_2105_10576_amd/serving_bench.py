@@ -51,6 +51,7 @@ def run(n_requests=64, max_slots=32, heap_mb=512, precision=oscar.MIXED, max_ite
                                            "mcell_iter_per_s", "peak_resident_bytes")}
     out["poisson"]["rate_per_s"] = lam
     out["requests"] = n_requests
+    out["max_iters_cap"] = max_iters if max_iters is not None else "none (each request's own, at most 200)"
     out["precond"] = "multigrid" if precond == oscar.PC_MG else "jacobi"
     out["max_slots"] = max_slots
     out["heap_mb"] = heap_mb
