@@ -85,6 +85,89 @@ __device__ __forceinline__ void for_cells(const Grid &G, int lb, Fn &&fn) {
   for (int g = lb * BLOCK + (int)threadIdx.x; g < G.nc; g += stride) fn(cell_at(G, g));
 }
 
+// Walk of a grid-wide launch over an index space of `planes` planes, each of
+// `rows` rows of `rowlen` indices (cells, or the wave tiles of the
+// restriction order).  The launch's blocks are grouped as the XCD deal
+// groups them (group x: the contiguous run of blocks that runs on XCD x),
+// and group x walks its own contiguous slab of planes in row blocks of about
+// WALK_BLOCK indices: the first row block through every plane of the slab,
+// then the next, grid-stride over the group's threads.  The planes a stencil
+// reads above and below its own were then read by the same XCD a moment
+// before and are still in its 4 MB L2.  Used in 3D with at least 8 blocks
+// and 8 planes; otherwise the plain grid-stride walk over the whole space.
+// The walk is a function of the block's index within the slot and the
+// slot's block count alone, so a batched launch (block table) walks exactly
+// as a single-slot launch.
+constexpr int WALK_BLOCK = 16384;
+
+struct Walk {
+  int first, stride, end;   // local index range [first, end) in steps of stride
+  bool slabbed;
+  int base;                 // plain walk: index of the first element
+  int z0, nzs, per_plane;   // slab: first plane, planes, indices per plane
+  int pb, pbl, tfull;       // indices per row block (the last one: pbl) and before the last row block
+  int nrb;                  // row blocks per plane
+};
+
+__device__ __forceinline__ Walk slab_walk(int lb, int nblocks, int planes, int rows, int rowlen, bool slabs) {
+  Walk w;
+  w.slabbed = slabs && nblocks >= 8 && planes >= 8;
+  if (!w.slabbed) {
+    w.first = lb * BLOCK + (int)threadIdx.x;
+    w.stride = nblocks * BLOCK;
+    w.end = planes * rows * rowlen;
+    w.base = 0;
+    return w;
+  }
+  const int X = 8, q = nblocks / X, rem = nblocks % X;
+  int x, l0;
+  if (lb < rem * (q + 1)) {
+    x = lb / (q + 1);
+    l0 = x * (q + 1);
+  } else {
+    x = rem + (lb - rem * (q + 1)) / q;
+    l0 = x * q + rem;
+  }
+  const int cnt = q + (x < rem ? 1 : 0);
+  w.z0 = (int)(((long long)x * planes) / X);
+  const int z1 = (int)(((long long)(x + 1) * planes) / X);
+  w.nzs = z1 - w.z0;
+  w.per_plane = rows * rowlen;
+  int yb = WALK_BLOCK / rowlen;
+  yb = yb < 1 ? 1 : (yb > rows ? rows : yb);
+  w.nrb = (rows + yb - 1) / yb;
+  w.pb = yb * rowlen;
+  w.pbl = (rows - (w.nrb - 1) * yb) * rowlen;
+  w.tfull = (w.nrb - 1) * w.nzs * w.pb;
+  w.first = (lb - l0) * BLOCK + (int)threadIdx.x;
+  w.stride = cnt * BLOCK;
+  w.end = w.tfull + w.nzs * w.pbl;
+  w.base = 0;
+  return w;
+}
+
+// the element at local index t (t < end) of a walk
+__device__ __forceinline__ int walk_at(const Walk &w, int t) {
+  if (!w.slabbed) return w.base + t;
+  unsigned rb, z, c;
+  if (t < w.tfull) {
+    const unsigned qq = (unsigned)t / (unsigned)w.pb;
+    c = (unsigned)t - qq * (unsigned)w.pb;
+    rb = qq / (unsigned)w.nzs;
+    z = qq - rb * (unsigned)w.nzs;
+  } else {
+    const unsigned r = (unsigned)(t - w.tfull);
+    z = r / (unsigned)w.pbl;
+    c = r - z * (unsigned)w.pbl;
+    rb = (unsigned)w.nrb - 1u;
+  }
+  return (int)(((unsigned)w.z0 + z) * (unsigned)w.per_plane + rb * (unsigned)w.pb + c);
+}
+
+__device__ __forceinline__ Walk cell_walk(const Grid &G, int lb) {
+  return slab_walk(lb, G.nblocks, G.nz, G.ny, G.nx, G.dim == 3);
+}
+
 __device__ __forceinline__ int cidx(const Slot &s, int i, int j, int k) { return i + s.nx * (j + s.ny * k); }
 
 __device__ __forceinline__ int fidx(const Slot &s, int e, int i, int j, int k) {

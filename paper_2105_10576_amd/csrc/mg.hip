@@ -891,11 +891,13 @@ __device__ __forceinline__ bool mgcg_dir_body(const Slot &s, int lb, int it) {
   const double tgt = st->tgt, rtol = ctl.rtol, bn = st->bn;
   const int max_it = ctl.max_it;
   const double gam_old = st->gam[(it + 1) & 1];   // gamma of iteration it - 1 (unused when it = 0)
+  const Walk wk = cell_walk(G, lb);
   batched<NB, Op>(
-      lb * BLOCK + (int)threadIdx.x, G.nblocks * BLOCK, G.nc,
-      [&](Op &o, int g) {
+      wk.first, wk.stride, wk.end,
+      [&](Op &o, int t) {
         o.fl = 0x40;
-        if (g < G.nc) {
+        if (t < wk.end) {
+          const int g = walk_at(wk, t);
           o.c = cell_at(G, g);
           o.fl = flags[g];
         }
@@ -1018,9 +1020,13 @@ __device__ __forceinline__ void mg_fine_down_body(const Slot &s, int lb, int it,
   const T w = (T)MG_OMEGA_FINE;
   const int dim = G.dim;
   const int total = (int)kid_total(dim, cnx, cny, s.mg.lv[1].nz);
+  // tiles in slabs of parent planes (3D): kid_total is a whole number of
+  // parent rows of tiles of 64 lanes
+  const int cnz1 = s.mg.lv[1].nz;
+  const Walk wk = slab_walk(lb, G.nblocks, cnz1, cny, total / (cnz1 * cny), dim == 3);
   struct Op {
     Cell c;
-    int tau, parent;
+    int parent;
     bool lead;
     uint8_t fl;
     T r[7], q[7], iD[7];   // r, q, D^-1 across faces 0..5, then at the cell
@@ -1031,13 +1037,13 @@ __device__ __forceinline__ void mg_fine_down_body(const Slot &s, int lb, int it,
   Partials<1> pt;   // <d,q> of the search-direction launch, loaded ahead of the stencil operands
   prefetch_totals(s, CH_DQ, pt);   // (unused by the initial cycle; loading it anyway avoids a branch)
   batched<NB, Op>(
-      lb * BLOCK + (int)threadIdx.x, G.nblocks * BLOCK, total,
-      [&](Op &o, int tau) {
-        o.tau = tau;
+      wk.first, wk.stride, wk.end,
+      [&](Op &o, int t) {
         o.fl = 0x40;
         o.lead = false;
-        if (tau < total) {
-          const Kid k = kid_at((unsigned)tau, dim, G.nx, G.ny, G.nz, cnx, cny);
+        o.parent = 0;
+        if (t < wk.end) {
+          const Kid k = kid_at((unsigned)walk_at(wk, t), dim, G.nx, G.ny, G.nz, cnx, cny);
           o.parent = k.parent;
           o.lead = k.lead;
           if (k.valid) {
@@ -1148,11 +1154,13 @@ __device__ __forceinline__ void mg_fine_up_body(const Slot &s, int lb, int it) {
     T r, iD;
   };
   double red[2] = {0.0, 0.0};
+  const Walk wk = cell_walk(G, lb);
   batched<NB, Op>(
-      lb * BLOCK + (int)threadIdx.x, G.nblocks * BLOCK, G.nc,
-      [&](Op &o, int g) {
+      wk.first, wk.stride, wk.end,
+      [&](Op &o, int t) {
         o.fl = 0x40;
-        if (g < G.nc) {
+        if (t < wk.end) {
+          const int g = walk_at(wk, t);
           o.c = cell_at(G, g);
           o.fl = flags[g];
         }
