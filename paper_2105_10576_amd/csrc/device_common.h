@@ -93,12 +93,15 @@ __device__ __forceinline__ void for_cells(const Grid &G, int lb, Fn &&fn) {
 // WALK_BLOCK indices: the first row block through every plane of the slab,
 // then the next, grid-stride over the group's threads.  The planes a stencil
 // reads above and below its own were then read by the same XCD a moment
-// before and are still in its 4 MB L2.  Used in 3D with at least 8 blocks
-// and 8 planes; otherwise the plain grid-stride walk over the whole space.
+// before and are still in its 4 MB L2.  Used in 3D with at least 8 blocks,
+// 8 planes and WALK_MIN elements (below that the arrays of a launch fit the
+// 256 MB last-level cache and the index arithmetic costs more than the
+// walk saves); otherwise the plain grid-stride walk over the whole space.
 // The walk is a function of the block's index within the slot and the
 // slot's block count alone, so a batched launch (block table) walks exactly
 // as a single-slot launch.
 constexpr int WALK_BLOCK = 16384;
+constexpr int WALK_MIN = 1 << 22;
 
 struct Walk {
   int first, stride, end;   // local index range [first, end) in steps of stride
@@ -111,7 +114,7 @@ struct Walk {
 
 __device__ __forceinline__ Walk slab_walk(int lb, int nblocks, int planes, int rows, int rowlen, bool slabs) {
   Walk w;
-  w.slabbed = slabs && nblocks >= 8 && planes >= 8;
+  w.slabbed = slabs && nblocks >= 8 && planes >= 8 && planes * rows * rowlen >= WALK_MIN;
   if (!w.slabbed) {
     w.first = lb * BLOCK + (int)threadIdx.x;
     w.stride = nblocks * BLOCK;
