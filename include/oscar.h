@@ -91,6 +91,20 @@ extern "C" {
 
 typedef struct oscar_ctx oscar_ctx;
 
+/* How a pressure solve (every CG iteration, multigrid cycle and FP64
+ * refinement step of Section 2.2's pressure equation) is executed:
+ *   OSCAR_SOLVE_LAUNCHES:   one grid-wide kernel launch per step, enqueued by
+ *                           the host in chunks; the host reads the solver
+ *                           state back after each chunk;
+ *   OSCAR_SOLVE_PERSISTENT: one launch for the whole solve: its workgroups
+ *                           take the steps' tiles from a work queue in
+ *                           device memory, and the host reads nothing back
+ *                           until the sub-step (or viscous step) ends.
+ * OSCAR_SOLVE_DEFAULT (0) selects the library's choice. */
+#define OSCAR_SOLVE_DEFAULT 0
+#define OSCAR_SOLVE_LAUNCHES 1
+#define OSCAR_SOLVE_PERSISTENT 2
+
 typedef struct {
   int32_t dim, nx, ny, nz;          /* dim 2 (nz = 1) or 3 */
   double h;                         /* uniform spacing [m], > 0 */
@@ -122,6 +136,9 @@ typedef struct {
                                        reduction); 0 = 1024 */
   double inner_rtol;                /* OSCAR_MIXED: smallest relative residual reduction asked of one
                                        FP32 inner solve, in (0, 1); 0 = 1e-6 */
+  /* Execution (results are bitwise the same either way). */
+  int32_t solve_mode;               /* OSCAR_SOLVE_*: how the pressure solves of a context run */
+  int32_t reserved;                 /* must be 0 */
 } oscar_desc;
 
 typedef struct {
@@ -278,6 +295,14 @@ int32_t oscar_engine_admit(oscar_engine *eng, const oscar_desc *desc, double dt_
 
 /* Run `ticks` ticks (returns at once when nothing is resident). */
 int32_t oscar_engine_run(oscar_engine *eng, int32_t ticks);
+
+/* How the engine runs the pressure solves of a tick (OSCAR_SOLVE_*; the
+ * requests' own solve_mode is not used).  With OSCAR_SOLVE_PERSISTENT one
+ * launch per PISO corrector solves every resident request's equation (each
+ * request advancing through its own iterations and refinement steps), and
+ * the host reads the requests' state once per tick.  Results are bitwise
+ * the same in both modes.  Takes effect at the next tick. */
+int32_t oscar_engine_set_solve_mode(oscar_engine *eng, int32_t solve_mode);
 
 /* Slots whose request has finished (up to cap), and the number still running. */
 int32_t oscar_engine_poll(const oscar_engine *eng, int32_t *done_slots, int32_t cap, int32_t *n_done,

@@ -190,10 +190,22 @@ int check_desc(const oscar_desc *D, std::string &why) {
   if (!(D->pcg_rtol > 0) || D->pcg_max_it < 1) { why = "pcg_rtol must be > 0 and pcg_max_it >= 1"; return OSCAR_E_ARG; }
   if (D->max_blocks < 0 || D->max_blocks > MAX_BLOCKS) { why = "max_blocks must be in [0, 1024]"; return OSCAR_E_ARG; }
   if (!(D->inner_rtol >= 0.0 && D->inner_rtol < 1.0)) { why = "inner_rtol must be in [0, 1)"; return OSCAR_E_ARG; }
+  if (D->solve_mode < OSCAR_SOLVE_DEFAULT || D->solve_mode > OSCAR_SOLVE_PERSISTENT || D->reserved != 0) {
+    why = "unknown solve_mode (or reserved not 0)";
+    return OSCAR_E_ARG;
+  }
   for (int f = 0; f < 2 * D->dim; ++f)
     if (D->bc[f] < OSCAR_BC_WALL || D->bc[f] > OSCAR_BC_OUTLET) { why = "unknown boundary type"; return OSCAR_E_ARG; }
   return OSCAR_OK;
 }
+
+// Persistent solves: the multigrid tail runs out of LDS when its block fits
+// PQ_LDS_MAX bytes (more LDS per workgroup would cut the resident
+// workgroups of the whole launch), else from global memory; a launch gives up
+// after PQ_IDLE_S seconds without a completed phase.
+constexpr int PQ_LDS_MAX = 40 * 1024;
+constexpr double PQ_IDLE_S = 2.0;
+static int pq_lds_for(const Slot &s) { return s.mg_pc && s.mg.tail_bytes <= PQ_LDS_MAX ? s.mg.tail_bytes : 0; }
 
 // bit f set when box side f (f < 2*dim) is an outlet
 uint32_t outlet_mask(const Slot &s) {
@@ -308,6 +320,12 @@ struct oscar_ctx {
   bool mg_stale = true;       // the multigrid hierarchy predates the current 1/a_P
   int ctl_mode = 0;           // mode of the control block last set (0 viscous, 1 capillary)
   int total_seen = 0;   // device total_it at the last state read (0 after a state reset)
+  // persistent solves (OSCAR_SOLVE_PERSISTENT): one launch per pressure solve
+  bool pq = false;
+  PQGlobal *d_pq = nullptr;   // the launch's batch words (device)
+  PQGlobal h_pq;              // read back with the state
+  int pq_wgs = 0, pq_lds = 0; // workgroups and LDS bytes of the launch
+  long long pq_idle = 0;      // wall-clock ticks without a completed phase before the launch gives up
   // optional timing of sampled conjugate-gradient iterations: every
   // t_period-th iteration of a solve gives each of its launches a region of
   // per-workgroup wall-clock stamps in a small device buffer
@@ -465,7 +483,12 @@ static void drop_open_samples(oscar_ctx *c) {
 // synchronisation: the device state into h_state
 static int read_state(oscar_ctx *c) {
   HIPCHK(c, hipMemcpyAsync(c->h_state, c->s.st, sizeof(SlotState), hipMemcpyDeviceToHost, c->stream));
+  if (c->pq) HIPCHK(c, hipMemcpyAsync(&c->h_pq, c->d_pq, sizeof(PQGlobal), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (c->pq && c->h_pq.err) {
+    c->err = "persistent pressure solve: no phase completed within its time limit";
+    return OSCAR_E_HIP;
+  }
   c->total_seen = c->h_state->total_it;
   return c->samples.empty() ? OSCAR_OK : settle_samples(c, false);
 }
@@ -592,6 +615,7 @@ extern "C" int32_t oscar_workspace_size(const oscar_desc *desc, uint64_t *bytes)
   layout(*desc, cv, &s, true);
   cv.take(sizeof(Slot));
   cv.take(sizeof(int2) * (uint64_t)(dims_of(*desc).nblocks + 8));
+  cv.take(sizeof(PQGlobal));
   *bytes = cv.off;
   return OSCAR_OK;
 }
@@ -655,6 +679,7 @@ static int32_t create_impl(const oscar_desc *desc, void *ws, uint64_t bytes, voi
   layout(*desc, cv, &s, true);
   c->d_slot = (Slot *)cv.take(sizeof(Slot));
   c->d_btab = (int2 *)cv.take(sizeof(int2) * (uint64_t)(c->g.nblocks + 8));
+  c->d_pq = (PQGlobal *)cv.take(sizeof(PQGlobal));
   s.dim = desc->dim;
   s.nx = desc->nx;
   s.ny = desc->ny;
@@ -670,6 +695,7 @@ static int32_t create_impl(const oscar_desc *desc, void *ws, uint64_t bytes, voi
   s.n_fluid = (int32_t)n_fluid;
   s.precision = desc->precision;
   s.mules_iter = desc->mules_iter > 1 ? desc->mules_iter : 1;
+  s.mg_pc = desc->precond == OSCAR_PC_MG;
   for (int f = 0; f < 6; ++f)
     s.bcf[f] = desc->bc[f] == OSCAR_BC_INLET ? F_INLET : (desc->bc[f] == OSCAR_BC_OUTLET ? F_OUTLET : F_WALL);
   s.outlet = outlet_mask(s);
@@ -704,6 +730,19 @@ static int32_t create_impl(const oscar_desc *desc, void *ws, uint64_t bytes, voi
   if (static_dev >= 0) c->h_state = &c->h_state_own;
   else if ((e = hipHostMalloc((void **)&c->h_state, sizeof(SlotState), hipHostMallocDefault)) != hipSuccess)
     return fail(e, "hipHostMalloc");
+  if (desc->solve_mode == OSCAR_SOLVE_PERSISTENT) {
+    int dev = 0, khz = 0;
+    if ((e = hipGetDevice(&dev)) != hipSuccess) return fail(e, "hipGetDevice");
+    if ((e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev)) != hipSuccess)
+      return fail(e, "hipDeviceGetAttribute");
+    c->pq_lds = pq_lds_for(s);
+    const int res = desc->precision == OSCAR_MIXED ? pq_resident_wgs<float>(c->pq_lds)
+                                                   : pq_resident_wgs<double>(c->pq_lds);
+    if (khz <= 0 || res < 1) return fail(hipErrorInvalidValue, "sizing the persistent solve");
+    c->pq_idle = (long long)(PQ_IDLE_S * 1e3 * (double)khz);
+    c->pq_wgs = res < c->g.nblocks ? res : c->g.nblocks;
+    c->pq = true;
+  }
   if ((e = hipMemsetAsync(ws, 0, cv.off, c->stream)) != hipSuccess) return fail(e, "hipMemsetAsync");
   if ((e = hipMemcpyAsync((void *)s.flags, fl.data(), nc, hipMemcpyHostToDevice, c->stream)) != hipSuccess)
     return fail(e, "upload mask");
@@ -828,9 +867,33 @@ extern "C" const char *oscar_last_error(const oscar_ctx *c) { return c ? c->err.
 // solves need a single read; in mixed precision the refinement step is
 // enqueued behind every chunk and acts only if the chunk finished the inner
 // solve, so one read also decides the outer step.
+// Persistent mode: the whole solve as one launch (after the multigrid
+// coarse operators, when they are stale); nothing is read back here.
+template <typename R>
+static int enqueue_solve_pq(oscar_ctx *c) {
+  if (c->D.precond == OSCAR_PC_MG && c->mg_stale) {
+    launch_mg_setup<R>(c->s, c->stream);
+    c->mg_stale = false;
+  }
+  launch_pq_init(c->d_slot, nullptr, 1, c->d_pq, c->stream);
+  launch_pq_solve<R>(c->d_slot, nullptr, 1, c->d_pq, c->pq_wgs, c->pq_lds, c->pq_idle, c->stream);
+  HIPCHK(c, hipGetLastError());
+  return OSCAR_OK;
+}
+
 template <typename R>
 static int solve_pressure(oscar_ctx *c, int &iters, int kind, int corr) {
   c->refine_stall = false;
+  if (c->pq) {
+    int rc = enqueue_solve_pq<R>(c);
+    if (!rc) rc = read_state(c);
+    if (rc) return rc;
+    iters = c->h_state->total_it - c->h_state->solve_base;
+    c->total_seen = c->h_state->total_it;
+    c->refine_stall = c->h_state->stalled != 0;
+    c->refine_call += c->h_state->ref_solve;
+    return OSCAR_OK;
+  }
   const int start_total = c->total_seen;   // no iterations ran since the last state read
   const int max_it = c->D.pcg_max_it;
   const bool mg = c->D.precond == OSCAR_PC_MG;
@@ -892,6 +955,28 @@ static int solve_pressure(oscar_ctx *c, int &iters, int kind, int corr) {
 template <typename R>
 static int run_correctors(oscar_ctx *c, bool cr, double &E, int &warn) {
   Launch L = c->L();
+  if (c->pq) {   // every corrector enqueued, one state read at the end
+    for (int j = 0; j < c->D.n_corr; ++j) {
+      launch_predictor<R>(L);
+      launch_pressure_setup<R>(L, cr && j == 0);
+      HIPCHK(c, hipGetLastError());
+      int rc = enqueue_solve_pq<R>(c);
+      if (rc) return rc;
+      launch_correct<R>(L, j);
+      HIPCHK(c, hipGetLastError());
+    }
+    int rc = read_state(c);
+    if (rc) return rc;
+    const SlotState &st = *c->h_state;
+    if (cr) E = st.E;
+    c->last_pcg = st.total_it - st.solve_base;
+    c->pcg_call = st.total_it;   // the call's state reset zeroed the count
+    c->total_seen = st.total_it;
+    c->refine_call = st.refine_steps;
+    if (st.maxit_hit) warn = OSCAR_W_PCG_MAXIT;
+    else if (st.stall_hits && warn == OSCAR_OK) warn = OSCAR_W_REFINE_STALL;
+    return OSCAR_OK;
+  }
   for (int j = 0; j < c->D.n_corr; ++j) {
     launch_predictor<R>(L);
     launch_pressure_setup<R>(L, cr && j == 0);
@@ -1278,6 +1363,14 @@ struct oscar_engine {
   int *d_act = nullptr;            // multigrid slot lists by dimension, then those whose hierarchy is
                                    // rebuilt this tick (4 x max_slots)
   SlotState *d_states = nullptr;   // gathered copy of the slots' states
+  // persistent solves (OSCAR_SOLVE_PERSISTENT): the list of the slots a
+  // launch solves, its batch words and their host copy
+  int solve_mode = OSCAR_SOLVE_LAUNCHES;
+  int *d_pq_list = nullptr;
+  PQGlobal *d_pq = nullptr;
+  PQGlobal h_pq;
+  long long pq_idle = 0;
+  std::vector<std::pair<int, int>> pq_res;   // resident workgroups by LDS bytes (looked up once each)
   int btab_cap = 0;
   SlotState *h_states = nullptr;
   std::vector<EngSlot> slots;
@@ -1304,7 +1397,8 @@ static int eng_fail(oscar_engine *e, hipError_t x, const char *what) {
 
 static uint64_t eng_table_bytes(int max_slots, int btab_cap) {
   return up(sizeof(Slot) * (uint64_t)max_slots) + 4 * up(sizeof(int2) * (uint64_t)btab_cap) +
-         up(sizeof(int) * 4 * (uint64_t)max_slots) + up(sizeof(SlotState) * (uint64_t)max_slots);
+         up(sizeof(int) * 4 * (uint64_t)max_slots) + up(sizeof(SlotState) * (uint64_t)max_slots) +
+         up(sizeof(int) * (uint64_t)max_slots) + up(sizeof(PQGlobal));
 }
 
 extern "C" int32_t oscar_engine_table_bytes(int32_t max_slots, uint64_t *bytes) {
@@ -1341,6 +1435,8 @@ extern "C" int32_t oscar_engine_create(int32_t max_slots, int32_t precision, voi
   e->d_btab_m = (int2 *)((char *)e->d_btab_j + up(sizeof(int2) * (uint64_t)btab_cap));
   e->d_act = (int *)((char *)e->d_btab_m + up(sizeof(int2) * (uint64_t)btab_cap));
   e->d_states = (SlotState *)((char *)e->d_act + up(sizeof(int) * 4 * (uint64_t)max_slots));
+  e->d_pq_list = (int *)((char *)e->d_states + up(sizeof(SlotState) * (uint64_t)max_slots));
+  e->d_pq = (PQGlobal *)((char *)e->d_pq_list + up(sizeof(int) * (uint64_t)max_slots));
   e->heap_off = tb;
   e->slots.resize(max_slots);
   e->free_list.push_back(Region{tb, bytes - tb});
@@ -1351,6 +1447,13 @@ extern "C" int32_t oscar_engine_create(int32_t max_slots, int32_t precision, voi
   if (x == hipSuccess) x = hipStreamSynchronize(e->stream);
   if (x != hipSuccess) { eng_fail(nullptr, x, "engine init"); (void)hipHostFree(e->h_states); delete e; return OSCAR_E_HIP; }
   *out = e;
+  return OSCAR_OK;
+}
+
+extern "C" int32_t oscar_engine_set_solve_mode(oscar_engine *e, int32_t mode) {
+  if (!e) { g_err = "engine is NULL"; return OSCAR_E_ARG; }
+  if (mode < OSCAR_SOLVE_DEFAULT || mode > OSCAR_SOLVE_PERSISTENT) { e->err = "unknown solve mode"; return OSCAR_E_ARG; }
+  e->solve_mode = mode == OSCAR_SOLVE_DEFAULT ? OSCAR_SOLVE_LAUNCHES : mode;
   return OSCAR_OK;
 }
 
@@ -1469,6 +1572,7 @@ extern "C" int32_t oscar_engine_admit(oscar_engine *e, const oscar_desc *desc, d
   s.n_fluid = (int32_t)n_fluid;
   s.precision = desc->precision;
   s.mules_iter = desc->mules_iter > 1 ? desc->mules_iter : 1;
+  s.mg_pc = desc->precond == OSCAR_PC_MG;
   for (int f = 0; f < 6; ++f)
     s.bcf[f] = desc->bc[f] == OSCAR_BC_INLET ? F_INLET : (desc->bc[f] == OSCAR_BC_OUTLET ? F_OUTLET : F_WALL);
   s.outlet = outlet_mask(s);
@@ -1569,7 +1673,50 @@ static int eng_read_states(oscar_engine *e) {
   launch_gather_states(L, e->max_slots, e->d_states);
   EHIP(e, hipGetLastError());
   EHIP(e, hipMemcpyAsync(e->h_states, e->d_states, sizeof(SlotState) * e->max_slots, hipMemcpyDeviceToHost, e->stream));
+  const bool pq = e->solve_mode == OSCAR_SOLVE_PERSISTENT;
+  if (pq) EHIP(e, hipMemcpyAsync(&e->h_pq, e->d_pq, sizeof(PQGlobal), hipMemcpyDeviceToHost, e->stream));
   EHIP(e, hipStreamSynchronize(e->stream));
+  if (pq && e->h_pq.err) {
+    e->err = "persistent pressure solve: no phase completed within its time limit";
+    return OSCAR_E_HIP;
+  }
+  return OSCAR_OK;
+}
+
+// One persistent launch for the pressure solves of the listed slots (their
+// set-up enqueued before it).
+template <typename R>
+static int eng_enqueue_pq(oscar_engine *e, const std::vector<int> &list, std::vector<int> &uploaded) {
+  if (list.empty()) return OSCAR_OK;
+  if (e->pq_idle == 0) {
+    int dev = 0, khz = 0;
+    EHIP(e, hipGetDevice(&dev));
+    EHIP(e, hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+    if (khz <= 0) { e->err = "device reports no wall-clock rate"; return OSCAR_E_HIP; }
+    e->pq_idle = (long long)(PQ_IDLE_S * 1e3 * (double)khz);
+  }
+  int lds = 0, tiles = 0;
+  for (int i : list) {
+    const int l = pq_lds_for(e->slots[i].s);
+    lds = l > lds ? l : lds;
+    tiles += e->slots[i].g.nblocks;
+  }
+  int res = -1;
+  for (const auto &x : e->pq_res)
+    if (x.first == lds) res = x.second;
+  if (res < 0) {
+    res = pq_resident_wgs<R>(lds);
+    e->pq_res.push_back({lds, res});
+  }
+  if (res < 1) { e->err = "sizing the persistent solve"; return OSCAR_E_HIP; }
+  if (list != uploaded) {
+    launch_pq_list(e->d_pq_list, list.data(), (int)list.size(), e->stream);
+    uploaded = list;
+  }
+  const int n = (int)list.size();
+  launch_pq_init(e->d_slots, e->d_pq_list, n, e->d_pq, e->stream);
+  launch_pq_solve<R>(e->d_slots, e->d_pq_list, n, e->d_pq, res < tiles ? res : tiles, lds, e->pq_idle, e->stream);
+  EHIP(e, hipGetLastError());
   return OSCAR_OK;
 }
 
@@ -1753,6 +1900,8 @@ static int eng_tick(oscar_engine *e) {
   };
   std::vector<double> E(e->max_slots, 0.0);
   for (int i : act) e->slots[i].stalled = false;
+  const bool pq = e->solve_mode == OSCAR_SOLVE_PERSISTENT;
+  std::vector<int> pq_uploaded;
   const std::vector<int> gj_all = gj, gm_all = gm;
   bool parked = false;   // some slot's control block is inactive for the later correctors
   for (int j = 0; j < n_corr; ++j) {
@@ -1779,14 +1928,21 @@ static int eng_tick(oscar_engine *e) {
     launch_predictor<R>(L);
     launch_pressure_setup<R>(L, j == 0);
     EHIP(e, hipGetLastError());
-    rc = eng_read_states(e);
-    if (rc) return rc;
-    rc = solve_group(gj, Lj, false);
-    if (rc) return rc;
-    rc = solve_group(gm, Lm, true);
-    if (rc) return rc;
-    if (j == 0)
-      for (int i : act) E[i] = e->h_states[i].E;
+    if (pq) {   // every slot's solve in one launch; the state is read once, after the tick
+      std::vector<int> list = gj;
+      list.insert(list.end(), gm.begin(), gm.end());
+      rc = eng_enqueue_pq<R>(e, list, pq_uploaded);
+      if (rc) return rc;
+    } else {
+      rc = eng_read_states(e);
+      if (rc) return rc;
+      rc = solve_group(gj, Lj, false);
+      if (rc) return rc;
+      rc = solve_group(gm, Lm, true);
+      if (rc) return rc;
+      if (j == 0)
+        for (int i : act) E[i] = e->h_states[i].E;
+    }
     launch_correct<R>(L, j);
     EHIP(e, hipGetLastError());
   }
@@ -1796,6 +1952,11 @@ static int eng_tick(oscar_engine *e) {
   }
   rc = eng_read_states(e);
   if (rc) return rc;
+  if (pq)
+    for (int i : act) {
+      E[i] = e->h_states[i].E;
+      e->slots[i].stalled = e->h_states[i].stall_hits != 0;
+    }
   // state transitions; finishing relaxations are finalised with their own table
   e->bt2.clear();
   std::vector<std::pair<int, SlotCtl>> off;

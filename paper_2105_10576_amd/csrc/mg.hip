@@ -28,6 +28,7 @@
 // levels (from the one the host marks as the tail down to the coarsest) run
 // inside one workgroup.  No atomics.
 #include "device_common.h"
+#include "cg_bodies.h"
 
 namespace oscar {
 
@@ -82,7 +83,6 @@ constexpr double MG_SCALE = 0.5;
 constexpr double MG_SCALE1_2D = 0.8;
 constexpr double MG_SCALE1_3D = 0.9;
 
-static_assert(MG_DENSE_MAX <= MG_TAIL_THREADS, "one coarsest-level cell per tail thread");
 
 struct LCell {
   int P, i, j, k;
@@ -517,7 +517,6 @@ template <int DIM, typename T, int NU>
 __device__ __forceinline__ void smooth_restrict(const LV<T> &L, int cnx, int cny, int cnz, T *bnext, unsigned start,
                                                 unsigned stride) {
   const T w = (T)MG_OMEGA;
-  const int st[3] = {1, L.nx, L.nxy};
   const unsigned total = kid_total(DIM, cnx, cny, cnz);
   for (unsigned tau = start; tau < total; tau += stride) {
     const Kid q = kid_at(tau, DIM, L.nx, L.ny, L.nz, cnx, cny);
@@ -719,20 +718,20 @@ __global__ void __launch_bounds__(BLOCK) k_mg_up_b(const Slot *slots, const int 
   else mg_up_body<DIM, T, 1>(s, l, q * BLOCK + (int)threadIdx.x, nb * BLOCK);
 }
 
-// Levels tail..L in one workgroup, out of LDS.  The tail block (the dense
-// inverse of the coarsest operator, then per level the face and outlet
-// coefficients, inverse diagonal, b, x and t) is copied into LDS with one
-// round of 16-byte loads, which brings in the coefficients and the tail
+// Levels tail..L in one workgroup of ns threads, out of LDS.  The tail block
+// (the dense inverse of the coarsest operator, then per level the face and
+// outlet coefficients, inverse diagonal, b, x and t) is copied into LDS with
+// one round of 16-byte loads, which brings in the coefficients and the tail
 // level's right-hand side; the down-sweep to the coarsest level, its solve
 // with the dense inverse and the up-sweep then touch LDS only, and the final
 // correction of the tail level goes back to global memory for the next finer
-// level's prolongation.
+// level's prolongation.  With mg_lds null the same steps run on the block in
+// global memory (the persistent solve, when the block exceeds its LDS).
 template <int DIM, typename T>
-__device__ __forceinline__ void mg_tail_body(const Slot &s, uint4 *mg_lds) {
+__device__ __forceinline__ void mg_tail_body(const Slot &s, uint4 *mg_lds, int t0, int ns) {
   const int tl = s.mg.tail, L = s.mg.L;
-  const int t0 = threadIdx.x, ns = MG_TAIL_THREADS;
   const char *gbase = (const char *)s.mg.tail_base;
-  {
+  if (mg_lds) {
     constexpr int U = 8;   // 16-byte loads in flight per thread
     typedef unsigned v4u __attribute__((ext_vector_type(4)));
     const OSCAR_GLOBAL v4u *src = (const OSCAR_GLOBAL v4u *)gbase;
@@ -751,8 +750,8 @@ __device__ __forceinline__ void mg_tail_body(const Slot &s, uint4 *mg_lds) {
     }
   }
   __syncthreads();
-  char *lbase = (char *)mg_lds;
-  // an array of the block at its LDS position
+  char *lbase = mg_lds ? (char *)mg_lds : (char *)gbase;
+  // an array of the block at its LDS position (itself without LDS)
   auto in_lds = [&](const void *g) -> T * { return (T *)(lbase + ((const char *)g - gbase)); };
   auto lds_view = [&](int l) -> LV<T> {
     const MGLevel &M = s.mg.lv[l];
@@ -780,11 +779,11 @@ __device__ __forceinline__ void mg_tail_body(const Slot &s, uint4 *mg_lds) {
   {
     const LV<T> C = lds_view(L);
     const int n = C.nc;
-    if (t0 < n) {
-      const T *Ai = in_lds(s.mg.Ainv) + t0 * n;
+    for (int row = t0; row < n; row += ns) {
+      const T *Ai = in_lds(s.mg.Ainv) + row * n;
       T acc = (T)0;
       for (int m = 0; m < n; ++m) acc = acc + Ai[m] * C.b[m];
-      C.t[t0] = acc;
+      C.t[row] = acc;
     }
   }
   __syncthreads();
@@ -798,7 +797,8 @@ __device__ __forceinline__ void mg_tail_body(const Slot &s, uint4 *mg_lds) {
   const MGLevel &M = s.mg.lv[tl];
   const T *tsrc = tc;
   T *tdst = (T *)M.t;
-  for (int g = t0; g < M.nc; g += ns) tdst[g] = tsrc[g];
+  if (tsrc != tdst)
+    for (int g = t0; g < M.nc; g += ns) tdst[g] = tsrc[g];
 }
 
 template <int DIM, typename T>
@@ -806,7 +806,7 @@ __global__ void __launch_bounds__(MG_TAIL_THREADS) k_mg_tail(const Slot S, unsig
   Stamp stamp(ts);
   if (mg_idle(S)) return;
   extern __shared__ uint4 mg_lds[];
-  mg_tail_body<DIM, T>(S, mg_lds);
+  mg_tail_body<DIM, T>(S, mg_lds, threadIdx.x, MG_TAIL_THREADS);
   stamp.done();
 }
 
@@ -816,7 +816,7 @@ __global__ void __launch_bounds__(MG_TAIL_THREADS) k_mg_tail_b(const Slot *slots
   const Slot &s = slots[act[blockIdx.x]];
   if (mg_idle(s)) return;
   extern __shared__ uint4 mg_lds[];
-  mg_tail_body<DIM, T>(s, mg_lds);
+  mg_tail_body<DIM, T>(s, mg_lds, threadIdx.x, MG_TAIL_THREADS);
 }
 
 // ---------------------------------------------------------------------------
@@ -1228,6 +1228,303 @@ __global__ void __launch_bounds__(BLOCK) k_mg_fine_up_b(const Slot *slots, const
 }
 
 // ---------------------------------------------------------------------------
+// persistent pressure solve
+// ---------------------------------------------------------------------------
+// One launch runs the whole pressure solve -- every CG iteration, V-cycle
+// and FP64 refinement step -- of every slot of a batch.  A slot's solve is a
+// chain of phases, the steps the grid-wide path launches as kernels; a phase
+// is made of tiles: the slot's fine blocks, the blocks of a coarse level, or
+// one tile (the tail, the refinement's finaliser).  A tile runs the body of
+// the grid-wide kernel on the same block, so the results are bitwise those of
+// the grid-wide path.
+//
+// Work queue: each slot publishes its open phase in one 64-bit word of its
+// state (generation, tiles, tiles claimed).  A workgroup finds a slot with an
+// unclaimed tile (one wavefront polls 64 slots at once), claims the tile with
+// an atomic add on that word, runs it, and counts it complete; the workgroup
+// that completes the last tile of a phase decides the next phase from the
+// slot's state and publishes it.  Slots advance independently of each other
+// and no host round trip separates their steps.
+//
+// Ordering: a tile's stores are released (agent scope) by every thread before
+// its completion is counted; the deciding workgroup acquires before it reads
+// the slot's state, and releases the next phase before its word; a claimer
+// acquires before it reads the phase.  No workgroup waits for another except
+// to find work, so any number of resident workgroups makes progress; the
+// launch ends when every slot's solve has finished, or when no phase has
+// completed for idle_ticks of the wall clock (g->err: the host reports it).
+enum : int { PQ_FD = 0, PQ_SM, PQ_TAIL, PQ_UP, PQ_FU, PQ_DIR, PQ_CGI, PQ_CG, PQ_RX, PQ_RR, PQ_RF, PQ_FIN };
+
+struct PQPhase {
+  int ph, it, l;   // kind, CG iteration, coarse level
+};
+
+__device__ __forceinline__ unsigned long long pq_pack(unsigned gen, int tiles) {
+  return ((unsigned long long)gen << 32) | ((unsigned long long)(unsigned)tiles << 16);
+}
+__device__ __forceinline__ unsigned pq_gen(unsigned long long w) { return (unsigned)(w >> 32); }
+__device__ __forceinline__ int pq_ntiles(unsigned long long w) { return (int)((w >> 16) & 0xffffu); }
+// claims past the tiles stay below 2^16: a workgroup adds only after it saw
+// an unclaimed tile, so the excess is at most the launch's workgroups
+__device__ __forceinline__ int pq_claimed(unsigned long long w) { return (int)(w & 0xffffu); }
+
+__device__ inline int pq_tiles(const Slot &s, const PQPhase &p) {
+  switch (p.ph) {
+    case PQ_SM: return smooth_blocks(s.mg, p.l, s.dim);
+    case PQ_UP: return up_blocks(s.mg, p.l);
+    case PQ_TAIL:
+    case PQ_RF: return 1;
+    case PQ_FIN: return 0;
+    default: return s.nblocks;
+  }
+}
+
+// first phase of a solve whose set-up has run: none if the set-up found the
+// equation solved (zero right-hand side, or an initial residual within the
+// tolerance), else the cycle of r_0 (multigrid) or w_0 = A D^-1 r_0 (Jacobi)
+__device__ inline PQPhase pq_first(const Slot &s) {
+  if (s.st->done) return PQPhase{PQ_FIN, 0, 0};
+  return s.mg_pc ? PQPhase{PQ_FD, -1, 0} : PQPhase{PQ_CGI, 0, 0};
+}
+
+// The phase after p, once all of p's tiles have completed: the launch order
+// of the grid-wide path (cycle: fine down, the coarse levels down, the tail,
+// the coarse levels up, fine up; then the search direction of the next
+// iteration, which holds the convergence test), and after a finished inner
+// solve the refinement when it is due; after the refinement, the end if it
+// met the tolerance or stalled, else a new inner solve.
+__device__ inline PQPhase pq_next(const Slot &s, const PQPhase &p) {
+  const int tail = s.mg.tail;
+  const SlotState *st = s.st;
+  auto after_inner = [&]() -> PQPhase { return refine_due(s, *s.ctl) ? PQPhase{PQ_RX, 0, 0} : PQPhase{PQ_FIN, 0, 0}; };
+  switch (p.ph) {
+    case PQ_FD: return tail > 1 ? PQPhase{PQ_SM, p.it, 1} : PQPhase{PQ_TAIL, p.it, 0};
+    case PQ_SM: return p.l + 1 < tail ? PQPhase{PQ_SM, p.it, p.l + 1} : PQPhase{PQ_TAIL, p.it, 0};
+    case PQ_TAIL: return tail > 1 ? PQPhase{PQ_UP, p.it, tail - 1} : PQPhase{PQ_FU, p.it, 0};
+    case PQ_UP: return p.l > 1 ? PQPhase{PQ_UP, p.it, p.l - 1} : PQPhase{PQ_FU, p.it, 0};
+    case PQ_FU: return PQPhase{PQ_DIR, p.it + 1, 0};
+    case PQ_DIR: return st->done ? after_inner() : PQPhase{PQ_FD, p.it, 0};
+    case PQ_CGI: return PQPhase{PQ_CG, 0, 0};
+    case PQ_CG: return st->done ? after_inner() : PQPhase{PQ_CG, p.it + 1, 0};
+    case PQ_RX: return PQPhase{PQ_RR, 0, 0};
+    case PQ_RR: return PQPhase{PQ_RF, 0, 0};
+    case PQ_RF:
+      if (st->done) return PQPhase{PQ_FIN, 0, 0};
+      return s.mg_pc ? PQPhase{PQ_FD, -1, 0} : PQPhase{PQ_CGI, 0, 0};
+    default: return PQPhase{PQ_FIN, 0, 0};
+  }
+}
+
+template <int DIM, typename T>
+__device__ __forceinline__ void pq_coarse(const Slot &s, const PQPhase &p, int t, uint4 *lds, int lds_bytes) {
+  const int tid = (int)threadIdx.x;
+  const bool two = (s.mg.nu2 >> p.l) & 1;
+  if (p.ph == PQ_SM) {
+    const unsigned nb = (unsigned)smooth_blocks(s.mg, p.l, DIM);
+    const unsigned start = (unsigned)t * BLOCK + (unsigned)tid, stride = nb * BLOCK;
+    if (two) mg_smooth_body<DIM, T, 2>(s, p.l, start, stride);
+    else mg_smooth_body<DIM, T, 1>(s, p.l, start, stride);
+  } else if (p.ph == PQ_UP) {
+    const int nb = up_blocks(s.mg, p.l);
+    if (two) mg_up_body<DIM, T, 2>(s, p.l, t * BLOCK + tid, nb * BLOCK);
+    else mg_up_body<DIM, T, 1>(s, p.l, t * BLOCK + tid, nb * BLOCK);
+  } else {
+    mg_tail_body<DIM, T>(s, s.mg.tail_bytes <= lds_bytes ? lds : nullptr, tid, BLOCK);
+  }
+}
+
+// tile t of phase p of slot s
+template <typename R>
+__device__ __forceinline__ void pq_tile(const Slot &s, const PQPhase &p, int t, uint4 *lds, int lds_bytes) {
+  constexpr int NB = FINE_NB<R>;
+  switch (p.ph) {
+    case PQ_FD: mg_fine_down_body<R, NB>(s, t, p.it, s.ctl->mode); break;
+    case PQ_SM:
+    case PQ_TAIL:
+    case PQ_UP:
+      if (s.dim == 3) pq_coarse<3, R>(s, p, t, lds, lds_bytes);
+      else pq_coarse<2, R>(s, p, t, lds, lds_bytes);
+      break;
+    case PQ_FU: mg_fine_up_body<R, NB>(s, t, p.it); break;
+    case PQ_DIR: (void)mgcg_dir_body<R, NB>(s, t, p.it); break;
+    case PQ_CGI: cg_init_body<R>(s, t); break;
+    case PQ_CG: (void)cg_iter_body<R>(s, t, p.it); break;
+    case PQ_RX: refine_x_body<R>(s, *s.ctl, t); break;
+    case PQ_RR: refine_res_body<R>(s, *s.ctl, t); break;
+    case PQ_RF: refine_fin_body(s); break;
+    default: break;
+  }
+}
+
+__device__ __forceinline__ const Slot &pq_slot(const Slot *slots, const int *list, int k) {
+  return slots[list ? list[k] : k];
+}
+
+// one workgroup: every listed slot's first phase and the batch words
+__global__ void __launch_bounds__(BLOCK) k_pq_init(const Slot *slots, const int *list, int n, PQGlobal *g) {
+  int open = 0;
+  for (int k = (int)threadIdx.x; k < n; k += BLOCK) {
+    const Slot &s = pq_slot(slots, list, k);
+    SlotState *st = s.st;
+    const PQPhase p = pq_first(s);
+    st->pq_phase = p.ph;
+    st->pq_it = p.it;
+    st->pq_lvl = p.l;
+    st->pq_done = 0;
+    st->pq_word = pq_pack(0u, pq_tiles(s, p));
+    st->solve_base = st->total_it;
+    open += p.ph != PQ_FIN;
+  }
+  __shared__ int sh[BLOCK / 64];
+  for (int off = 32; off > 0; off >>= 1) open += __shfl_down(open, off, 64);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = open;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int tot = 0;
+    for (int w = 0; w < BLOCK / 64; ++w) tot += sh[w];
+    g->remaining = tot;
+    g->err = 0;
+    g->progress = 0u;
+  }
+}
+
+// a chunk of a slot list, passed by value (no host buffer outlives the call)
+struct PQListChunk {
+  static constexpr int MAXN = 256;
+  int32_t off, n;
+  int32_t v[MAXN];
+};
+__global__ void __launch_bounds__(BLOCK) k_pq_list(int *dst, const PQListChunk c) {
+  if ((int)threadIdx.x < c.n) dst[c.off + (int)threadIdx.x] = c.v[threadIdx.x];
+}
+
+// (three wavefronts per SIMD: 168 registers, enough for the radius-2 3D
+// coarse sweeps with little spilling)
+template <typename R>
+__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3)))
+k_pq_solve(const Slot *slots, const int *list, int n, PQGlobal *g, int lds_bytes, long long idle_ticks) {
+  extern __shared__ uint4 pq_lds[];
+  // the claimed tile: list index, phase, iteration, level, tile, tiles of the
+  // phase, whether the phase is new to this workgroup (phase < 0: exit)
+  __shared__ int task[7];
+  const int tid = (int)threadIdx.x, lane = tid & 63;
+  // wavefront 0 finds the work; these stay uniform over its lanes
+  int rot = (int)(blockIdx.x % (unsigned)n);   // where the next scan starts
+  int cur = -1;                                // slot and generation of the last tile
+  unsigned cur_gen = 0u;
+  for (;;) {
+    if (tid < 64) {
+      int k = -1, tile = 0, ntiles = 0;
+      unsigned gen = 0u, prog = 0u;
+      long long t_idle = -1;
+      bool quit = false;
+      for (;;) {
+        for (int base = 0; base < n && k < 0; base += 64) {
+          int kk = -1;
+          bool open = false;
+          if (base + lane < n) {
+            kk = base + lane + rot;
+            if (kk >= n) kk -= n;
+            const unsigned long long w = __hip_atomic_load(&pq_slot(slots, list, kk).st->pq_word, __ATOMIC_RELAXED,
+                                                           __HIP_MEMORY_SCOPE_AGENT);
+            open = pq_claimed(w) < pq_ntiles(w);
+          }
+          unsigned long long m = __ballot(open);
+          while (m && k < 0) {
+            const int src = __ffsll((long long)m) - 1;
+            m &= m - 1;
+            const int cand = __shfl(kk, src, 64);
+            unsigned long long old = 0ull;
+            if (lane == 0)
+              old = __hip_atomic_fetch_add(&pq_slot(slots, list, cand).st->pq_word, 1ull, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+            const unsigned lo = __shfl((unsigned)old, 0, 64), hi = __shfl((unsigned)(old >> 32), 0, 64);
+            old = ((unsigned long long)hi << 32) | lo;
+            if (pq_claimed(old) < pq_ntiles(old)) {
+              k = cand;
+              tile = pq_claimed(old);
+              ntiles = pq_ntiles(old);
+              gen = pq_gen(old);
+            }
+          }
+        }
+        if (k >= 0) break;
+        // nothing open: every solve finished, the launch gave up, or a
+        // phase is closing
+        if (__hip_atomic_load(&g->remaining, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0 ||
+            __hip_atomic_load(&g->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+          quit = true;
+          break;
+        }
+        const unsigned pr = __hip_atomic_load(&g->progress, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const long long now = (long long)wall_clock64();
+        if (t_idle < 0 || pr != prog) {
+          prog = pr;
+          t_idle = now;
+        } else if (now - t_idle > idle_ticks) {
+          if (lane == 0) __hip_atomic_store(&g->err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          quit = true;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(32);
+      }
+      if (lane == 0) {
+        if (quit) {
+          task[1] = -1;
+        } else {
+          // the phase's publication, and all the stores released before it
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+          const SlotState *st = pq_slot(slots, list, k).st;
+          task[0] = k;
+          task[1] = st->pq_phase;
+          task[2] = st->pq_it;
+          task[3] = st->pq_lvl;
+          task[4] = tile;
+          task[5] = ntiles;
+          task[6] = k != cur || gen != cur_gen;
+        }
+      }
+      if (!quit) {
+        cur = k;
+        cur_gen = gen;
+        rot = k;   // stay with this slot while it has tiles
+      }
+    }
+    __syncthreads();
+    const int ph = task[1];
+    if (ph < 0) break;
+    const int k = task[0], tile = task[4], ntiles = task[5];
+    const PQPhase p = {ph, task[2], task[3]};
+    if (task[6]) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    const Slot &s = pq_slot(slots, list, k);
+    pq_tile<R>(s, p, tile, pq_lds, lds_bytes);
+    // the tile's stores: every wavefront's complete, then one release
+    // (agent scope) before the tile counts as complete
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (tid == 0) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      SlotState *st = s.st;
+      const int c = __hip_atomic_fetch_add(&st->pq_done, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (c + 1 == ntiles) {   // the phase's last tile: decide the next phase and publish it
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        const PQPhase nx = pq_next(s, p);
+        st->pq_phase = nx.ph;
+        st->pq_it = nx.it;
+        st->pq_lvl = nx.l;
+        __hip_atomic_store(&st->pq_done, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        const unsigned long long w = __hip_atomic_load(&st->pq_word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&st->pq_word, pq_pack(pq_gen(w) + 1u, pq_tiles(s, nx)), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+        if (nx.ph == PQ_FIN) __hip_atomic_fetch_add(&g->remaining, -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(&g->progress, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // host launchers (one slot: its record hs passed by value)
 // ---------------------------------------------------------------------------
 
@@ -1354,6 +1651,40 @@ void launch_mg_cycle_part_b(const MGBatch &B, int it, int part) {
     hipLaunchKernelGGL((k_mg_fine_up_b<R, FINE_NB<R>>), fg, fb, 0, B.stream, B.slots, B.btab, it);
   }
 }
+
+void launch_pq_list(int *dst, const int *host, int n, hipStream_t stream) {
+  for (int off = 0; off < n; off += PQListChunk::MAXN) {
+    PQListChunk c;
+    c.off = off;
+    c.n = n - off < PQListChunk::MAXN ? n - off : PQListChunk::MAXN;
+    for (int i = 0; i < c.n; ++i) c.v[i] = host[off + i];
+    hipLaunchKernelGGL(k_pq_list, dim3(1), dim3(BLOCK), 0, stream, dst, c);
+  }
+}
+
+void launch_pq_init(const Slot *slots, const int *list, int n, PQGlobal *g, hipStream_t stream) {
+  hipLaunchKernelGGL(k_pq_init, dim3(1), dim3(BLOCK), 0, stream, slots, list, n, g);
+}
+
+template <typename R>
+void launch_pq_solve(const Slot *slots, const int *list, int n, PQGlobal *g, int wgs, int lds, long long idle_ticks,
+                     hipStream_t stream) {
+  hipLaunchKernelGGL(k_pq_solve<R>, dim3((unsigned)wgs), dim3(BLOCK), (size_t)lds, stream, slots, list, n, g, lds,
+                     idle_ticks);
+}
+
+template <typename R> int pq_resident_wgs(int lds) {
+  int dev = 0, cus = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_pq_solve<R>, BLOCK, (size_t)lds) != hipSuccess) return 0;
+  return per * cus;
+}
+
+template void launch_pq_solve<double>(const Slot *, const int *, int, PQGlobal *, int, int, long long, hipStream_t);
+template void launch_pq_solve<float>(const Slot *, const int *, int, PQGlobal *, int, int, long long, hipStream_t);
+template int pq_resident_wgs<double>(int);
+template int pq_resident_wgs<float>(int);
 
 template void launch_mg_setup_b<double>(const MGBatch &);
 template void launch_mg_setup_b<float>(const MGBatch &);

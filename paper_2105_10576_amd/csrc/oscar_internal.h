@@ -39,6 +39,20 @@ struct SlotState {
   int32_t nonfinite, unstable, maxit_hit, refine_steps;
   int32_t ref_solve;   // refinement steps of the current solve (reset by its set-up)
   int32_t stalled;     // the current solve's refinement stopped short of its tolerance
+  int32_t stall_hits;  // solves whose refinement stalled since the last state reset
+  int32_t solve_base;  // total_it when the current persistent solve started
+  // persistent solve: the slot's open phase (generation << 32 | tiles << 16 |
+  // tiles claimed), its kind, iteration and level, and its completed tiles
+  unsigned long long pq_word;
+  int32_t pq_phase, pq_it, pq_lvl, pq_done;
+};
+
+// Batch-wide words of one persistent solve launch.
+struct PQGlobal {
+  int32_t remaining;   // slots whose solve has not finished
+  int32_t err;         // 1: no phase completed within the idle limit and the launch gave up
+  uint32_t progress;   // phases completed so far (what waiting workgroups watch)
+  int32_t pad;
 };
 
 // Mixed precision: a solve's FP64 refinement stops (done, stalled) when one
@@ -93,7 +107,8 @@ struct Slot {
   int32_t dim, nx, ny, nz;
   int32_t nc, nf0, nf1, nf2, nftot, nxy;   // counts (the host keeps them below 2^31)
   int32_t block0, nblocks, n_fluid, precision;
-  int32_t mules_iter, pad0;     // limiting passes of the alpha transport (>= 1)
+  int32_t mules_iter;           // limiting passes of the alpha transport (>= 1)
+  int32_t mg_pc;                // 1: multigrid-preconditioned CG, 0: Jacobi
   int32_t bcf[6];               // face type of each box side
   uint32_t outlet;              // bit f: box side f is an outlet (f < 2*dim)
   double h, V, S, Sh, S2h, hh, delta, cos_t, sin_t;
@@ -201,6 +216,25 @@ template <typename R> void launch_mg_cycle_part_b(const MGBatch &B, int it, int 
 inline int mg_part_launches(const Slot &hs, int part) { return part == 1 ? 2 * (hs.mg.tail - 1) + 1 : 1; }
 template <typename R> void launch_mg_dir(const Slot &hs, const Launch &L, int it, unsigned long long *ts = nullptr);
 void launch_gather_states(const Launch &L, int nslots, SlotState *out);
+
+// Persistent pressure solve (mg.hip): one launch runs the whole solve --
+// every CG iteration, multigrid cycle and FP64 refinement step -- of the
+// slots slots[list[k]] (slots[k] when list is null), k < n, whose set-up
+// (and multigrid coarse operators) are enqueued before it.  pq_init readies
+// each slot's first phase (none when the set-up found it solved) and the
+// batch words g; pq_solve then runs with `wgs` workgroups and `lds` bytes of
+// LDS for the multigrid tail (a larger tail block runs from global memory).
+// idle_ticks: wall-clock ticks without a completed phase after which the
+// launch gives up (g->err = 1) rather than wait further.
+void launch_pq_init(const Slot *slots, const int *list, int n, PQGlobal *g, hipStream_t stream);
+// copy a host list of n slot indices to dst (device) in stream order, by value
+void launch_pq_list(int *dst, const int *host, int n, hipStream_t stream);
+template <typename R>
+void launch_pq_solve(const Slot *slots, const int *list, int n, PQGlobal *g, int wgs, int lds, long long idle_ticks,
+                     hipStream_t stream);
+// workgroups of one pq_solve launch that fit the device at once with `lds`
+// bytes of dynamic LDS each
+template <typename R> int pq_resident_wgs(int lds);
 
 // blocks per slot: ceil(cells/BLOCK), capped at `cap` (0: MAX_BLOCKS;
 // grid-stride beyond the cap)

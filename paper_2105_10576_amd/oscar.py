@@ -16,6 +16,7 @@ OK, W_PCG_MAXIT, W_REFINE_STALL = 0, 1, 2
 E_ARG, E_WORKSPACE, E_MASK, E_UNSTABLE, E_NONFINITE, E_HIP, E_CAPACITY = -1, -2, -3, -4, -5, -6, -7
 FP64, MIXED = 0, 1
 PC_JACOBI, PC_MG = 0, 1
+SOLVE_DEFAULT, SOLVE_LAUNCHES, SOLVE_PERSISTENT = 0, 1, 2
 FIELDS = dict(alpha=0, U=1, p=2, U_vd=3, p_vd=4, U_cr=5, p_cr=6, phi_vd=7, phi_vd_prev=8, phi_cr=9,
               kappa=10, rAU=11, rhs=12, U_sum=13, HbyA=14, nhatf=15)
 
@@ -33,7 +34,7 @@ class Desc(C.Structure):
                 ("u_inlet", C.c_double), ("precision", C.c_int32), ("n_corr", C.c_int32),
                 ("pcg_rtol", C.c_double), ("pcg_max_it", C.c_int32), ("precond", C.c_int32),
                 ("mules_iter", C.c_int32), ("mg_sweeps2", C.c_int32), ("max_blocks", C.c_int32),
-                ("inner_rtol", C.c_double)]
+                ("inner_rtol", C.c_double), ("solve_mode", C.c_int32), ("reserved", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -95,8 +96,9 @@ def make_desc(case, precision=FP64):
     """Fill an oscar_desc from a case dictionary (key "precond": PC_JACOBI,
     the default, or PC_MG; key "mules_iter": limiting passes of the alpha
     transport, default 1; tuning keys "mg_sweeps2", "max_blocks",
-    "inner_rtol", default 0 = the library's built-in value); returns
-    (desc, keep-alive arrays)."""
+    "inner_rtol", default 0 = the library's built-in value; key
+    "solve_mode": SOLVE_*, default SOLVE_DEFAULT); returns (desc,
+    keep-alive arrays)."""
     d = Desc()
     for k in ("dim", "nx", "ny", "nz", "n_corr", "pcg_max_it"):
         setattr(d, k, int(case[k]))
@@ -110,6 +112,7 @@ def make_desc(case, precision=FP64):
     d.mg_sweeps2 = int(case.get("mg_sweeps2", 0))
     d.max_blocks = int(case.get("max_blocks", 0))
     d.inner_rtol = float(case.get("inner_rtol", 0.0))
+    d.solve_mode = int(case.get("solve_mode", SOLVE_DEFAULT))
     mask = np.ascontiguousarray(case["mask"], dtype=np.uint8)
     a0 = np.ascontiguousarray(case["alpha0"], dtype=np.float64)
     d.mask = mask.ctypes.data_as(C.POINTER(C.c_uint8))
@@ -250,7 +253,8 @@ class Oscar:
 
 ENGINE_EXPORTS = ["oscar_engine_table_bytes", "oscar_engine_create", "oscar_engine_admit", "oscar_engine_run",
                   "oscar_engine_poll", "oscar_engine_fetch", "oscar_engine_release", "oscar_engine_free_bytes",
-                  "oscar_engine_stats", "oscar_engine_destroy", "oscar_engine_last_error"]
+                  "oscar_engine_stats", "oscar_engine_destroy", "oscar_engine_last_error",
+                  "oscar_engine_set_solve_mode"]
 EXPORTS = EXPORTS + ENGINE_EXPORTS
 
 
@@ -261,6 +265,7 @@ def _engine_sigs(L):
     L.oscar_engine_create.argtypes = [C.c_int32, C.c_int32, vp, C.c_uint64, vp, C.POINTER(vp)]
     L.oscar_engine_admit.argtypes = [vp, C.POINTER(Desc), C.c_double, C.c_int32, C.c_int32, C.c_double, ip]
     L.oscar_engine_run.argtypes = [vp, C.c_int32]
+    L.oscar_engine_set_solve_mode.argtypes = [vp, C.c_int32]
     L.oscar_engine_poll.argtypes = [vp, ip, C.c_int32, ip, ip]
     L.oscar_engine_fetch.argtypes = [vp, C.c_int32, dp, dp, dp, ip, ip]
     L.oscar_engine_release.argtypes = [vp, C.c_int32]
@@ -289,7 +294,7 @@ class Engine:
     """Continuous-batching engine over one torch device workspace of
     table bytes + heap_bytes (the HBM budget for resident requests)."""
 
-    def __init__(self, max_slots, heap_bytes, precision=FP64, device="cuda:0", stream=None):
+    def __init__(self, max_slots, heap_bytes, precision=FP64, device="cuda:0", stream=None, solve_mode=SOLVE_DEFAULT):
         import torch
 
         L = lib()
@@ -307,6 +312,14 @@ class Engine:
         if rc != OK:
             raise OscarError(rc, L.oscar_last_error(None).decode())
         self.meta = {}
+        if solve_mode != SOLVE_DEFAULT:
+            self.set_solve_mode(solve_mode)
+
+    def set_solve_mode(self, mode):
+        """SOLVE_LAUNCHES or SOLVE_PERSISTENT from the next tick on."""
+        rc = lib().oscar_engine_set_solve_mode(self.h, int(mode))
+        if rc != OK:
+            self._err(rc)
 
     def close(self):
         if getattr(self, "h", None) and self.h.value:
