@@ -104,3 +104,28 @@ def sphere_ops():
     o.set("phi_cr", f["phi"])
     o.pressure_solve(1, c["dt_vd"] / c["n_sub"], 1e-8, 1)
     return {k: o.get(k) for k in ("kappa", "rAU", "HbyA", "rhs")}
+
+
+def micromodel_sample_case():
+    """A 512 x 256 sample of the micromodel medium (same grain radii, gap,
+    porosity, fluids, contact angle and Ca as the 1024 x 512 workload), FP64
+    parity settings: two capillary sub-steps, pressure solves to 1e-12."""
+    c = cases.micromodel(nx=512, ny=256, max_iters=2)
+    c["pcg_rtol"] = 1e-12
+    return c
+
+
+@job
+def micromodel_sample_step():
+    c = micromodel_sample_case()
+    o = Oracle(c)
+    assert o.viscous_step(c["dt_vd"]) == 0
+    vd = _fields(o, ("p_vd", "U_vd"))
+    rc, kf, E = o.capillary_relax(c["dt_vd"], c["n_sub"], c["max_iters"], 0.0)
+    assert rc == 0
+    out = _fields(o)
+    out.update({"vd_" + k: v for k, v in vd.items()})
+    out["k_f"] = kf
+    out["E"] = E
+    return out
+

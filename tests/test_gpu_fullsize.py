@@ -228,6 +228,36 @@ def _properties(g, c, steps, max_iters):
     return st
 
 
+@pytest.mark.oracle_job("micromodel_sample_step")
+@pytest.mark.timeout(900)
+def test_micromodel_fp64_step_against_oracle():
+    """One OSCAR step (the viscous step and 2 capillary sub-steps) of a
+    512 x 256 sample of the micromodel medium in FP64 (multigrid CG) against
+    the oracle (Jacobi CG), both to 1e-12: p_vd and U_vd after the viscous
+    step, alpha, p and U after the relaxation within 1e-9 relative
+    L-infinity over the fluid cells; the same k_f and E_k."""
+    o = _oscar()
+    c = oracle_bg.micromodel_sample_case()
+    fl = c["mask"].reshape(-1) == 0
+    g = o.Oscar(c, precision=o.FP64, precond=o.PC_MG)
+    print("micromodel 512x256 fp64 step", flush=True)
+    assert g.viscous_step(c["dt_vd"]) == 0
+    vd = {f: g.get(f) for f in ("p_vd", "U_vd")}
+    rc, kf, E = g.capillary_relax(c["dt_vd"], c["n_sub"], c["max_iters"], 0.0)
+    assert rc == 0
+    ref = oracle_bg.result("micromodel_sample_step")
+    assert kf == ref["k_f"]
+    assert np.allclose(E, ref["E"], rtol=1e-9, atol=0)
+    for f, comps in (("p_vd", 1), ("U_vd", 2)):
+        e = rel_linf(vd[f], ref["vd_" + f], np.tile(fl, comps))
+        print("after the viscous step", f, "%.2e" % e, flush=True)
+        assert e <= 1e-9, f
+    for f, comps in (("alpha", 1), ("p", 1), ("U", 2)):
+        e = rel_linf(g.get(f), ref[f], np.tile(fl, comps))
+        print("after the step", f, "%.2e" % e, flush=True)
+        assert e <= 1e-9, f
+
+
 def test_micromodel_mixed_properties():
     """Micromodel 1024 x 512 (mixed, multigrid): one global step, one viscous
     step and 20 capillary sub-steps (its time step, 0.1 of the inlet CFL
@@ -239,6 +269,35 @@ def test_micromodel_mixed_properties():
     g = o.Oscar(c, precision=o.MIXED, precond=o.PC_MG)
     st = _properties(g, c, 1, 20)
     assert st["max_courant"] <= 1.0
+
+
+def test_micromodel_mixed_against_fp64():
+    """Micromodel 1024 x 512, one global step (the viscous step and 20
+    capillary sub-steps): the mixed path (FP32 with FP64 refinement to
+    1e-10) against the FP64 path (1e-12, itself held to the oracle on the
+    512 x 256 sample): p and U within the stated 1e-5 relative L-infinity
+    over the fluid cells, the water front within 0.01 cells along every
+    row."""
+    o = _oscar()
+    c = cases.micromodel()
+    fl = c["mask"].reshape(-1) == 0
+    out = {}
+    for prec, rtol in ((o.FP64, 1e-12), (o.MIXED, 1e-10)):
+        g = o.Oscar(dict(c, pcg_rtol=rtol), precision=prec, precond=o.PC_MG)
+        rc1, rc2, kf, E = g.step(max_iters=20, tol=0.0)
+        assert rc1 == 0 and rc2 == 0 and kf == 20
+        out[prec] = {f: g.get(f) for f in ("alpha", "p", "U")}
+        g.close()
+    a, b = out[o.MIXED], out[o.FP64]
+    ep = rel_linf(a["p"], b["p"], fl)
+    eu = rel_linf(a["U"], b["U"], np.tile(fl, 2))
+    xa, xb = interface_x(a["alpha"], c["nx"], c["ny"]), interface_x(b["alpha"], c["nx"], c["ny"])
+    both = ~np.isnan(xa) & ~np.isnan(xb)
+    assert np.array_equal(np.isnan(xa), np.isnan(xb))
+    shift = float(np.abs(xa[both] - xb[both]).max()) if both.any() else 0.0
+    print("micromodel mixed vs fp64: p %.2e U %.2e front shift %.2e cells" % (ep, eu, shift), flush=True)
+    assert ep <= 1e-5 and eu <= 1e-5
+    assert shift <= 0.01
 
 
 def test_sphere_pack_mixed_properties():
