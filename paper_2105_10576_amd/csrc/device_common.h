@@ -112,9 +112,10 @@ struct Walk {
   int nrb;                  // row blocks per plane
 };
 
-__device__ __forceinline__ Walk slab_walk(int lb, int nblocks, int planes, int rows, int rowlen, bool slabs) {
+__device__ __forceinline__ Walk slab_walk(int lb, int nblocks, int planes, int rows, int rowlen, bool slabs,
+                                          int min_elems = WALK_MIN) {
   Walk w;
-  w.slabbed = slabs && nblocks >= 8 && planes >= 8 && planes * rows * rowlen >= WALK_MIN;
+  w.slabbed = slabs && nblocks >= 8 && planes >= 8 && planes * rows * rowlen >= min_elems;
   if (!w.slabbed) {
     w.first = lb * BLOCK + (int)threadIdx.x;
     w.stride = nblocks * BLOCK;

@@ -1114,6 +1114,233 @@ __device__ __forceinline__ void mg_fine_down_body(const Slot &s, int lb, int it,
       });
 }
 
+// ---------------------------------------------------------------------------
+// the same step on LDS-staged bricks (large 3D FP32 grids)
+// ---------------------------------------------------------------------------
+// The single-cell kernel above holds every stencil operand of its cells in
+// registers, so the registers bound the loads a wavefront keeps in flight
+// and, on a grid that streams from HBM, the kernel waits on memory latency.
+// Here a workgroup takes bricks of 32 x 8 x 4 fine cells: the halo brick of
+// r, q, D^-1 and rAU (34 x 10 x 6 cells, read as rows of ten 16-byte chunks
+// from x0 - 4) goes straight from memory into LDS with global_load_lds
+// (no registers held), all of it in flight at once; after one wait the
+// cells are computed from LDS.  Thread t holds the four children at z
+// offset t & 1 of parent t >> 1 of the brick (16 x 4 x 2 parents), so the
+// restriction sums x, then y in the thread and z across lanes t, t ^ 1: the
+// order of kid_sum.  Each cell's arithmetic is the single-cell kernel's.
+// Rows and chunks outside the grid read the nearest in-grid ones (only
+// faces that are not interior see them).
+typedef float f2v __attribute__((ext_vector_type(2)));
+
+// store the fluid cells of an x pair (one 8-byte store when both are fluid)
+__device__ __forceinline__ void sto_pair(float *base, unsigned off, bool fa, bool fb, float a, float b) {
+  if (fa && fb) {
+    f2v v;
+    v.x = a;
+    v.y = b;
+    sto((f2v *)base, off, v);
+  } else {
+    if (fa) sto(base, off, a);
+    if (fb) sto(base, off + 4u, b);
+  }
+}
+
+constexpr int BRX = 32, BRY = 8, BRZ = 4;
+constexpr int BRP = BRX + 8;                    // LDS row pitch (floats)
+constexpr int BRROWS = (BRY + 2) * (BRZ + 2);   // halo rows
+constexpr int BRH = BRROWS * BRP;               // floats per staged array
+constexpr int BRCH = BRROWS * (BRP / 4);        // 16-byte chunks per staged array
+static_assert(BRX * BRY * BRZ == 4 * BLOCK, "four cells per thread");
+
+__host__ __device__ inline bool brick_ok(int dim, int nx, int ny, int nz, int precision) {
+  return dim == 3 && precision != 0 && nx % BRX == 0 && ny % BRY == 0 && nz % BRZ == 0 &&
+         (long long)nx * ny * nz >= WALK_MIN;
+}
+
+// stage the halo brick of one array: chunk c of the brick (row c / 10,
+// chunk c % 10) to LDS float offset 4 c; wavefront-uniform LDS bases
+__device__ __forceinline__ void brick_stage(const float *src, float *lds, const Grid &G, int x0, int y0, int z0) {
+  const int wave = (int)threadIdx.x >> 6, lane = (int)threadIdx.x & 63;
+#pragma unroll
+  for (int m = 0; m < (BRCH + BLOCK - 1) / BLOCK; ++m) {
+    const int c = m * BLOCK + wave * 64 + lane;
+    if (m * BLOCK + wave * 64 < BRCH && c < BRCH) {
+      const int row = c / (BRP / 4), ch = c - row * (BRP / 4);
+      const int zz = row / (BRY + 2), yy = row - zz * (BRY + 2);
+      int y = y0 - 1 + yy, z = z0 - 1 + zz, x = x0 - 4 + 4 * ch;
+      y = y < 0 ? 0 : (y >= G.ny ? G.ny - 1 : y);
+      z = z < 0 ? 0 : (z >= G.nz ? G.nz - 1 : z);
+      x = x < 0 ? 0 : (x > G.nx - 4 ? G.nx - 4 : x);
+      const float *g = src + ((unsigned)x + (unsigned)G.nx * ((unsigned)y + (unsigned)G.ny * (unsigned)z));
+      __builtin_amdgcn_global_load_lds((const OSCAR_GLOBAL void *)g,
+                                       (__attribute__((address_space(3))) void *)(lds + 4 * (m * BLOCK + wave * 64)),
+                                       16, 0, 0);
+    }
+  }
+}
+
+// the bricks of workgroup lb: the 8 XCDs (contiguous runs of lb, as
+// xcd_block deals them) each take a slab of brick planes, and a run's
+// workgroups take its bricks in turn; without 8 planes, bricks lb,
+// lb + nblocks, ...
+struct BrickWalk {
+  int first, stride, end;
+};
+__device__ __forceinline__ BrickWalk brick_walk(int lb, int nblocks, int nbx, int nby, int nbz) {
+  BrickWalk w;
+  if (nblocks < 8 || nbz < 8) {
+    w.first = lb;
+    w.stride = nblocks;
+    w.end = nbx * nby * nbz;
+    return w;
+  }
+  const int X = 8, q = nblocks / X, rem = nblocks % X;
+  int x, l0;
+  if (lb < rem * (q + 1)) {
+    x = lb / (q + 1);
+    l0 = x * (q + 1);
+  } else {
+    x = rem + (lb - rem * (q + 1)) / q;
+    l0 = x * q + rem;
+  }
+  const int cnt = q + (x < rem ? 1 : 0);
+  const int per = nbx * nby;
+  w.first = (x * nbz / X) * per + (lb - l0);
+  w.stride = cnt;
+  w.end = ((x + 1) * nbz / X) * per;
+  return w;
+}
+
+__device__ __forceinline__ void mg_fine_down_brick(const Slot &s, int lb, int it) {
+  using T = float;
+  const Grid G = grid_of(s);
+  SlotState *st = s.st;
+  const bool upd = it >= 0;
+  const T *rAU = (const T *)s.rAU;
+  const T *invD = (const T *)s.invD;
+  const T *r0 = (const T *)s.cr[upd ? (it & 1) : 0];
+  T *r1 = (T *)s.cr[upd ? ((it + 1) & 1) : 0];
+  const T *d = (const T *)s.cs[upd ? (it & 1) : 0], *q = upd ? (const T *)s.cp : r0;
+  T *z0 = (T *)s.cw[1];
+  T *xv = (T *)s.e;
+  const int cnx = s.mg.lv[1].nx, cny = s.mg.lv[1].ny;
+  T *b1 = (T *)s.mg.lv[1].b;
+  const uint8_t *flags = s.flags;
+  const T w = (T)MG_OMEGA_FINE;
+  __shared__ __align__(16) float sr[BRH];
+  __shared__ __align__(16) float sq[BRH];
+  __shared__ __align__(16) float si[BRH];
+  __shared__ __align__(16) float sa[BRH];
+  const int nbx = G.nx / BRX, nby = G.ny / BRY, nbz = G.nz / BRZ;
+  const BrickWalk wk = brick_walk(lb, G.nblocks, nbx, nby, nbz);
+  const int tid = (int)threadIdx.x;
+  const int p = tid >> 1, h = tid & 1;
+  const int px = p & 15, py = (p >> 4) & 3, pz = p >> 6;
+  const int cx = 2 * px, cy = 2 * py, cz = 2 * pz + h;   // the thread's first child in the brick
+  auto origin = [&](int b, int &x0, int &y0, int &z0b) {
+    const int bz = b / (nbx * nby), rem = b - bz * nbx * nby, by = rem / nbx;
+    x0 = (rem - by * nbx) * BRX;
+    y0 = by * BRY;
+    z0b = bz * BRZ;
+  };
+  auto stage = [&](int b) {
+    int x0, y0, z0b;
+    origin(b, x0, y0, z0b);
+    brick_stage(r0, sr, G, x0, y0, z0b);
+    brick_stage(q, sq, G, x0, y0, z0b);
+    brick_stage(invD, si, G, x0, y0, z0b);
+    brick_stage(rAU, sa, G, x0, y0, z0b);
+  };
+  if (wk.first < wk.end) stage(wk.first);
+  // the previous launch's <d,q> while the first brick loads
+  T al = (T)0;
+  if (upd) {
+    Partials<1> pt;
+    prefetch_totals(s, CH_DQ, pt);
+    double v[1];
+    finish_totals(pt, v);
+    al = (T)(st->gam[it & 1] / v[0]);
+    if (lb == 0 && tid == 0) {
+      st->it = it + 1;
+      st->total_it = st->total_it + 1;
+    }
+  }
+  for (int b = wk.first; b < wk.end; b += wk.stride) {
+    int x0, y0, z0b;
+    origin(b, x0, y0, z0b);
+    // the thread's own cells: two x pairs (rows y and y + 1)
+    const int gi = x0 + cx, gj = y0 + cy, gk = z0b + cz;
+    const int P0 = gi + G.nx * (gj + G.ny * gk), P1 = P0 + G.nx;
+    const unsigned fl0 = (unsigned)ldo((const uint16_t *)flags, (unsigned)P0);
+    const unsigned fl1 = (unsigned)ldo((const uint16_t *)flags, (unsigned)P1);
+    const f2v d0 = ldo((const f2v *)d, (unsigned)P0 * 4u), d1 = ldo((const f2v *)d, (unsigned)P1 * 4u);
+    const f2v xo0 = ldo((const f2v *)xv, (unsigned)P0 * 4u), xo1 = ldo((const f2v *)xv, (unsigned)P1 * 4u);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    T tv[2][2];
+#pragma unroll
+    for (int yk = 0; yk < 2; ++yk) {
+      T zz[2], rnv[2], xn2[2];
+      bool fl[2];
+#pragma unroll
+      for (int xk = 0; xk < 2; ++xk) {
+        const uint8_t f8 = (uint8_t)((yk ? fl1 : fl0) >> (8 * xk));
+        fl[xk] = !(f8 & 0x40);
+        tv[yk][xk] = (T)0;
+        zz[xk] = rnv[xk] = xn2[xk] = (T)0;
+        if (!fl[xk]) continue;
+        const int L = ((cz + 1) * (BRY + 2) + (cy + yk + 1)) * BRP + (cx + xk + 4);
+        const int off[6] = {-1, 1, -BRP, BRP, -(BRY + 2) * BRP, (BRY + 2) * BRP};
+        const T rn = sr[L] - al * sq[L];
+        const T zc = w * (si[L] * rn);
+        T xn[6], ran[6];
+#pragma unroll
+        for (int f = 0; f < 6; ++f) {
+          const int Lf = L + off[f];
+          xn[f] = w * (si[Lf] * (sr[Lf] - al * sq[Lf]));
+          ran[f] = sa[Lf];
+        }
+        Cell c;
+        c.P = (yk ? P1 : P0) + xk;
+        c.i = gi + xk;
+        c.j = gj + yk;
+        c.k = gk;
+        c.row = c.j + G.ny * c.k;
+        c.valid = true;
+        const T Az = matvec_pre<T>(G, c, f8, zc, sa[L], xn, ran);
+        zz[xk] = zc;
+        rnv[xk] = rn;
+        const f2v dd = yk ? d1 : d0;
+        const f2v xo = yk ? xo1 : xo0;
+        xn2[xk] = (xk ? xo.y : xo.x) + al * (xk ? dd.y : dd.x);
+        tv[yk][xk] = rn - Az;
+      }
+      const unsigned o = (unsigned)(yk ? P1 : P0) * 4u;
+      if (upd) {
+        sto_pair(xv, o, fl[0], fl[1], xn2[0], xn2[1]);
+        sto_pair(r1, o, fl[0], fl[1], rnv[0], rnv[1]);
+      }
+      sto_pair(z0, o, fl[0], fl[1], zz[0], zz[1]);
+    }
+    // children of the parent: x pairs, then y, then z across the lane pair
+    T v = (tv[0][0] + tv[0][1]) + (tv[1][0] + tv[1][1]);
+    v = v + __shfl_xor(v, 1, 64);
+    if (h == 0) b1[(gi >> 1) + cnx * ((gj >> 1) + cny * (gk >> 1))] = v;
+    __syncthreads();   // every wavefront is done with the LDS: stage the next brick
+    if (b + wk.stride < wk.end) stage(b + wk.stride);
+  }
+}
+
+// (four wavefronts per SIMD: 128 registers; the LDS of four workgroups fits)
+__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4)))
+k_mg_fine_down_brick(const Slot S, int it, unsigned long long *ts) {
+  Stamp stamp(ts);
+  const int lb = xcd_block(blockIdx.x, S.nblocks);
+  if (lb < 0 || S.st->done) return;
+  mg_fine_down_brick(S, lb, it);
+  stamp.done();
+}
+
 template <typename R, int NB>
 __global__ void __launch_bounds__(BLOCK) k_mg_fine_down(const Slot S, int it, int mode, unsigned long long *ts) {
   Stamp stamp(ts);
@@ -1571,7 +1798,9 @@ template <typename R>
 void launch_mg_cycle_part(const Slot &hs, const Launch &L, int it, int part, int mode, unsigned long long *ts) {
   const dim3 fg((unsigned)L.nblocks), fb(BLOCK);
   if (part == 0) {
-    hipLaunchKernelGGL((k_mg_fine_down<R, FINE_NB<R>>), fg, fb, 0, L.stream, hs, it, mode, ts);
+    if (sizeof(R) == 4 && brick_ok(hs.dim, hs.nx, hs.ny, hs.nz, hs.precision))
+      hipLaunchKernelGGL(k_mg_fine_down_brick, fg, fb, 0, L.stream, hs, it, ts);
+    else hipLaunchKernelGGL((k_mg_fine_down<R, FINE_NB<R>>), fg, fb, 0, L.stream, hs, it, mode, ts);
   } else if (part == 1) {
     if (hs.dim == 3) vcycle_levels<3, R>(hs, L, ts);
     else vcycle_levels<2, R>(hs, L, ts);
