@@ -94,6 +94,8 @@ def run_gpu(case, precision, steps, warmup, precond=1, timing_period=TIMING_PERI
     from paper_2105_10576_amd import oscar
 
     g = oscar.Oscar(case, precision=precision, device="cuda:0", precond=precond)
+    if case.get("solve_mode", 0) == oscar.SOLVE_PERSISTENT:
+        timing_period = 0   # the persistent solve has no per-launch stamps
     n_sub = case["n_sub"]
     for _ in range(warmup):
         g.step(max_iters=n_sub, tol=0.0)
@@ -413,6 +415,28 @@ def cpu_baseline(case, precond=1):
                                                  "pressure rtol"))
 
 
+def persistent_line(args, case, pc, nc):
+    """--solve-mode persistent: the c2 mixed relaxation rate and the serving
+    figures with every pressure solve run as one persistent launch."""
+    from paper_2105_10576_amd import oscar, serving_bench
+
+    case = dict(case, solve_mode=oscar.SOLVE_PERSISTENT)
+    r = run_gpu(case, 1, args.steps, args.warmup, precond=pc)
+    out = {"metric": "relaxation Mcell-iter/s (mixed FP32 + FP64 refinement), persistent pressure solves",
+           "value": round(r["relax_iters"] * nc / r["relax_seconds"] / 1e6, 3), "unit": "Mcell-iter/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": round(1e3 * r["seconds"] / args.steps, 3), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic (seeded constricted-channel geometry and CO2 slug)",
+           "config": {"workload": "3D constricted channel 128x64x64, N=%d sub-steps, tol=0, pressure rtol 1e-8"
+                                  % case["n_sub"], "solve_mode": "persistent",
+                      "pcg_iters_per_step": round(r["pcg_iters"] / args.steps, 1)},
+           "roofline": None}
+    if not args.no_serving:
+        out["serving"] = serving_bench.run(n_requests=args.serving_requests, max_iters=args.serving_max_iters,
+                                           precond=pc, solve_mode=oscar.SOLVE_PERSISTENT, burst_only=True)
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -431,6 +455,9 @@ def main():
     ap.add_argument("--pmc-calibration", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device-to-device (calibrates rocprofv3 FETCH_SIZE/WRITE_SIZE)")
     ap.add_argument("--serving-requests", type=int, default=64)
+    ap.add_argument("--solve-mode", choices=["launches", "persistent"], default="launches",
+                    help="persistent: every pressure solve as one launch over a device work queue (bitwise the "
+                         "same results); prints the c2 mixed value and the serving figures only")
     ap.add_argument("--serving-max-iters", type=int, default=200,
                     help="cap on relaxation sub-steps per serving request (the mix allows up to 200)")
     args = ap.parse_args()
@@ -465,6 +492,9 @@ def main():
     n_fluid = int((case["mask"] == 0).sum())
     n_sub = case["n_sub"]
     pc = 1 if args.precond == "mg" else 0
+    if args.solve_mode == "persistent":
+        persistent_line(args, case, pc, nc)
+        return
 
     mixed = run_gpu(case, 1, args.steps, args.warmup, precond=pc)
     value = mixed["relax_iters"] * nc / mixed["relax_seconds"] / 1e6

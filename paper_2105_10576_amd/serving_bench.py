@@ -15,7 +15,7 @@ from .serve import Server
 
 
 def run(n_requests=64, max_slots=32, heap_mb=512, precision=oscar.MIXED, max_iters=None, rate_frac=0.8,
-        device="cuda:0", log=None, precond=oscar.PC_MG):
+        device="cuda:0", log=None, precond=oscar.PC_MG, solve_mode=oscar.SOLVE_DEFAULT, burst_only=False):
     reqs = cases.serving_requests(n=n_requests)
     for c in reqs:
         c["precond"] = precond
@@ -27,7 +27,7 @@ def run(n_requests=64, max_slots=32, heap_mb=512, precision=oscar.MIXED, max_ite
     fp = lambda c: oscar.workspace_size(c, precision)
     out = {}
     # burst pass
-    eng = oscar.Engine(max_slots, heap, precision=precision, device=device)
+    eng = oscar.Engine(max_slots, heap, precision=precision, device=device, solve_mode=solve_mode)
     srv = Server(eng, fp, heap_bytes=heap)
     res, summ = srv.run(reqs, [0.0] * len(reqs), max_wall=600, progress=log)
     eng.close()
@@ -36,6 +36,8 @@ def run(n_requests=64, max_slots=32, heap_mb=512, precision=oscar.MIXED, max_ite
                                          "mcell_iter_per_s", "peak_resident_bytes")}
     if log:
         log("burst: %s" % out["burst"])
+    if burst_only:
+        return out
     # Poisson pass at rate_frac of the saturated rate
     lam = rate_frac * sat_rate
     t = 0.0
@@ -43,7 +45,7 @@ def run(n_requests=64, max_slots=32, heap_mb=512, precision=oscar.MIXED, max_ite
     for c in reqs:
         t += c["arrival_gap"] / lam
         arrivals.append(t)
-    eng = oscar.Engine(max_slots, heap, precision=precision, device=device)
+    eng = oscar.Engine(max_slots, heap, precision=precision, device=device, solve_mode=solve_mode)
     srv = Server(eng, fp, heap_bytes=heap)
     res, summ = srv.run(reqs, arrivals, max_wall=600, progress=log)
     eng.close()
