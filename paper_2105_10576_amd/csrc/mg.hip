@@ -725,13 +725,13 @@ __global__ void __launch_bounds__(BLOCK) k_mg_up_b(const Slot *slots, const int 
 // level's right-hand side; the down-sweep to the coarsest level, its solve
 // with the dense inverse and the up-sweep then touch LDS only, and the final
 // correction of the tail level goes back to global memory for the next finer
-// level's prolongation.  With mg_lds null the same steps run on the block in
+// level's prolongation.  Without IN_LDS the same steps run on the block in
 // global memory (the persistent solve, when the block exceeds its LDS).
-template <int DIM, typename T>
+template <int DIM, typename T, bool IN_LDS>
 __device__ __forceinline__ void mg_tail_body(const Slot &s, uint4 *mg_lds, int t0, int ns) {
   const int tl = s.mg.tail, L = s.mg.L;
   const char *gbase = (const char *)s.mg.tail_base;
-  if (mg_lds) {
+  if constexpr (IN_LDS) {
     constexpr int U = 8;   // 16-byte loads in flight per thread
     typedef unsigned v4u __attribute__((ext_vector_type(4)));
     const OSCAR_GLOBAL v4u *src = (const OSCAR_GLOBAL v4u *)gbase;
@@ -750,9 +750,13 @@ __device__ __forceinline__ void mg_tail_body(const Slot &s, uint4 *mg_lds, int t
     }
   }
   __syncthreads();
-  char *lbase = mg_lds ? (char *)mg_lds : (char *)gbase;
-  // an array of the block at its LDS position (itself without LDS)
-  auto in_lds = [&](const void *g) -> T * { return (T *)(lbase + ((const char *)g - gbase)); };
+  // an array of the block at its LDS position (itself without LDS; the
+  // choice is made at compile time so that LDS accesses stay LDS
+  // instructions rather than generic ones)
+  auto in_lds = [&](const void *g) -> T * {
+    if constexpr (IN_LDS) return (T *)((char *)mg_lds + ((const char *)g - gbase));
+    else return (T *)g;
+  };
   auto lds_view = [&](int l) -> LV<T> {
     const MGLevel &M = s.mg.lv[l];
     LV<T> v;
@@ -806,7 +810,7 @@ __global__ void __launch_bounds__(MG_TAIL_THREADS) k_mg_tail(const Slot S, unsig
   Stamp stamp(ts);
   if (mg_idle(S)) return;
   extern __shared__ uint4 mg_lds[];
-  mg_tail_body<DIM, T>(S, mg_lds, threadIdx.x, MG_TAIL_THREADS);
+  mg_tail_body<DIM, T, true>(S, mg_lds, threadIdx.x, MG_TAIL_THREADS);
   stamp.done();
 }
 
@@ -816,7 +820,7 @@ __global__ void __launch_bounds__(MG_TAIL_THREADS) k_mg_tail_b(const Slot *slots
   const Slot &s = slots[act[blockIdx.x]];
   if (mg_idle(s)) return;
   extern __shared__ uint4 mg_lds[];
-  mg_tail_body<DIM, T>(s, mg_lds, threadIdx.x, MG_TAIL_THREADS);
+  mg_tail_body<DIM, T, true>(s, mg_lds, threadIdx.x, MG_TAIL_THREADS);
 }
 
 // ---------------------------------------------------------------------------
@@ -1556,7 +1560,8 @@ __device__ __forceinline__ void pq_coarse(const Slot &s, const PQPhase &p, int t
     if (two) mg_up_body<DIM, T, 2>(s, p.l, t * BLOCK + tid, nb * BLOCK);
     else mg_up_body<DIM, T, 1>(s, p.l, t * BLOCK + tid, nb * BLOCK);
   } else {
-    mg_tail_body<DIM, T>(s, s.mg.tail_bytes <= lds_bytes ? lds : nullptr, tid, BLOCK);
+    if (s.mg.tail_bytes <= lds_bytes) mg_tail_body<DIM, T, true>(s, lds, tid, BLOCK);
+    else mg_tail_body<DIM, T, false>(s, nullptr, tid, BLOCK);
   }
 }
 
