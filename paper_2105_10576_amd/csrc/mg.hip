@@ -1161,25 +1161,34 @@ __host__ __device__ inline bool brick_ok(int dim, int nx, int ny, int nz, int pr
          (long long)nx * ny * nz >= WALK_MIN;
 }
 
-// stage the halo brick of one array: chunk c of the brick (row c / 10,
-// chunk c % 10) to LDS float offset 4 c; wavefront-uniform LDS bases
-__device__ __forceinline__ void brick_stage(const float *src, float *lds, const Grid &G, int x0, int y0, int z0) {
+// Chunk c of the halo brick (row c / 10 of the (BRY + 2) x (BRZ + 2) halo
+// rows, 16-byte chunk c % 10 from x0 - 4), clamped into the grid: its
+// element offset.
+__device__ __forceinline__ unsigned brick_chunk(const Grid &G, int c, int x0, int y0, int z0) {
+  const int row = c / (BRP / 4), ch = c - row * (BRP / 4);
+  const int zz = row / (BRY + 2), yy = row - zz * (BRY + 2);
+  int y = y0 - 1 + yy, z = z0 - 1 + zz, x = x0 - 4 + 4 * ch;
+  y = y < 0 ? 0 : (y >= G.ny ? G.ny - 1 : y);
+  z = z < 0 ? 0 : (z >= G.nz ? G.nz - 1 : z);
+  x = x < 0 ? 0 : (x > G.nx - 4 ? G.nx - 4 : x);
+  return (unsigned)x + (unsigned)G.nx * ((unsigned)y + (unsigned)G.ny * (unsigned)z);
+}
+
+constexpr int BRM = (BRCH + BLOCK - 1) / BLOCK;   // chunk rounds of a workgroup
+
+// stage the halo brick of one array to LDS (chunk c at float offset 4 c;
+// wavefront-uniform LDS bases), skipping the chunks whose four cells are
+// all solid (need[m] false): solid cells' values are never read
+__device__ __forceinline__ void brick_stage(const float *src, float *lds, const unsigned (&off)[BRM],
+                                            const bool (&need)[BRM]) {
   const int wave = (int)threadIdx.x >> 6, lane = (int)threadIdx.x & 63;
 #pragma unroll
-  for (int m = 0; m < (BRCH + BLOCK - 1) / BLOCK; ++m) {
+  for (int m = 0; m < BRM; ++m) {
     const int c = m * BLOCK + wave * 64 + lane;
-    if (m * BLOCK + wave * 64 < BRCH && c < BRCH) {
-      const int row = c / (BRP / 4), ch = c - row * (BRP / 4);
-      const int zz = row / (BRY + 2), yy = row - zz * (BRY + 2);
-      int y = y0 - 1 + yy, z = z0 - 1 + zz, x = x0 - 4 + 4 * ch;
-      y = y < 0 ? 0 : (y >= G.ny ? G.ny - 1 : y);
-      z = z < 0 ? 0 : (z >= G.nz ? G.nz - 1 : z);
-      x = x < 0 ? 0 : (x > G.nx - 4 ? G.nx - 4 : x);
-      const float *g = src + ((unsigned)x + (unsigned)G.nx * ((unsigned)y + (unsigned)G.ny * (unsigned)z));
-      __builtin_amdgcn_global_load_lds((const OSCAR_GLOBAL void *)g,
+    if (m * BLOCK + wave * 64 < BRCH && c < BRCH && need[m])
+      __builtin_amdgcn_global_load_lds((const OSCAR_GLOBAL void *)(src + off[m]),
                                        (__attribute__((address_space(3))) void *)(lds + 4 * (m * BLOCK + wave * 64)),
                                        16, 0, 0);
-    }
   }
 }
 
@@ -1247,13 +1256,26 @@ __device__ __forceinline__ void mg_fine_down_brick(const Slot &s, int lb, int it
     y0 = by * BRY;
     z0b = bz * BRZ;
   };
+  // the brick's chunks: their offsets, and the flags of their four cells
+  // (one 4-byte load each) to skip the all-solid ones
   auto stage = [&](int b) {
     int x0, y0, z0b;
     origin(b, x0, y0, z0b);
-    brick_stage(r0, sr, G, x0, y0, z0b);
-    brick_stage(q, sq, G, x0, y0, z0b);
-    brick_stage(invD, si, G, x0, y0, z0b);
-    brick_stage(rAU, sa, G, x0, y0, z0b);
+    unsigned off[BRM];
+    unsigned f4[BRM];
+#pragma unroll
+    for (int m = 0; m < BRM; ++m) {
+      const int c = m * BLOCK + tid;
+      off[m] = brick_chunk(G, c < BRCH ? c : 0, x0, y0, z0b);
+      f4[m] = ldo((const uint32_t *)flags, off[m]);
+    }
+    bool need[BRM];
+#pragma unroll
+    for (int m = 0; m < BRM; ++m) need[m] = (f4[m] & 0x40404040u) != 0x40404040u;
+    brick_stage(r0, sr, off, need);
+    brick_stage(q, sq, off, need);
+    brick_stage(invD, si, off, need);
+    brick_stage(rAU, sa, off, need);
   };
   if (wk.first < wk.end) stage(wk.first);
   // the previous launch's <d,q> while the first brick loads
