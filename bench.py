@@ -207,8 +207,8 @@ def kernel_roofline(ktab, dom, precision, cache_resident, traffic=None):
 
 
 def k7_roofline(ktab, precision, n_fluid, precond):
-    """One CG iteration against the unit of the survey's roofline (Jacobi PCG:
-    13 words per fluid cell per iteration), and the multigrid iteration's own
+    """One CG iteration against the Jacobi-PCG unit of traffic (13 words per
+    fluid cell per iteration), and the multigrid iteration's own
     fine-grid bytes, over the whole iteration's time (all its launches and
     the gaps between them, from the timing hook)."""
     it = ktab["iteration"]["avg_us"] * 1e-6
