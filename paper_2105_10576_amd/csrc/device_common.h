@@ -260,6 +260,30 @@ __device__ __forceinline__ void for_owned_faces(const Slot &s, const Cell &c, Fn
 // Measurement only: with a non-null ts, workgroup b of the launch writes its
 // start and end on the device's constant-rate wall clock to ts[2b], ts[2b+1]
 // (plain stores: no contention between workgroups).
+// Kernel entry.  A kernel's record arrives by value in its argument
+// segment, and the compiler reads each field in the basic block that first
+// uses it, waiting before each branch: the entry code of a kernel (timing
+// stamp, block mapping, converged-solve test) chained several round trips
+// to the segment before the first data load.  OSCAR_PRIME("s"(field), ...)
+// asks for the fields together at entry (one batch of scalar loads, one
+// wait); later reads of the same fields reuse the registers.
+#define OSCAR_PRIME(...) asm volatile("" ::__VA_ARGS__)
+
+// v exists at this point: the loads it was computed from cannot sink past a
+// branch that follows (a converged-solve test taken after the first data
+// loads, before the first store, so that its own load overlaps them)
+template <typename T>
+__device__ __forceinline__ void keep_live(const T &v) {
+  asm volatile("" ::"v"(v));
+}
+// v as read at this point and no earlier (a uniform test of a loaded value
+// would otherwise wait for it where the compiler moves it to scalar
+// registers, ahead of the loads that follow)
+__device__ __forceinline__ int read_late(int v) {
+  asm volatile("" : "+v"(v));
+  return v;
+}
+
 struct Stamp {
   unsigned long long *ts;
   unsigned long long t0;

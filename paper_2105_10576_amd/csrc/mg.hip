@@ -512,15 +512,17 @@ __device__ __forceinline__ T sweep_matvec(const LV<T> &L, const LCell &c, V0 &&v
 // x_1 = w D^-1 b, x_{m+1} = x_m + w D^-1 (b - A x_m) up to NU sweeps,
 // t = b - A x, b_next[parent] = sum of the children's t.  (cnx, cny, cnz)
 // are the dimensions of the next coarser level; bnext may point to global
-// memory or to LDS.
-template <int DIM, typename T, int NU>
+// memory or to LDS.  With GATE, done (uniform): the solve had converged
+// before the launch, nothing is written (tested once the first cell's loads
+// are in).
+template <int DIM, typename T, int NU, bool GATE = false>
 __device__ __forceinline__ void smooth_restrict(const LV<T> &L, int cnx, int cny, int cnz, T *bnext, unsigned start,
-                                                unsigned stride) {
+                                                unsigned stride, int done = 0) {
   const T w = (T)MG_OMEGA;
   const unsigned total = kid_total(DIM, cnx, cny, cnz);
   for (unsigned tau = start; tau < total; tau += stride) {
     const Kid q = kid_at(tau, DIM, L.nx, L.ny, L.nz, cnx, cny);
-    T tv = (T)0;
+    T tv = (T)0, xP = (T)0;
     if (q.valid) {
       LCell c;
       c.P = q.P;
@@ -528,7 +530,6 @@ __device__ __forceinline__ void smooth_restrict(const LV<T> &L, int cnx, int cny
       c.j = q.j;
       c.k = q.k;
       auto x1 = [&](int n, int, int) -> T { return w * (L.invD[n] * L.b[n]); };
-      T xP;
       T Ax;
       if constexpr (NU == 1) {
         xP = x1(c.P, 0, 0);
@@ -538,9 +539,13 @@ __device__ __forceinline__ void smooth_restrict(const LV<T> &L, int cnx, int cny
         auto x1o = [&](unsigned b, int, int, int) -> T { return w * (ldo(L.invD, b) * ldo((const T *)L.b, b)); };
         Ax = sweep_matvec<DIM, T>(L, c, x1o, xP);
       }
-      L.x[c.P] = xP;
       tv = L.b[c.P] - Ax;
     }
+    if constexpr (GATE) {
+      keep_live(tv);
+      if (read_late(done)) return;
+    }
+    if (q.valid) L.x[q.P] = xP;
     tv = kid_sum(tv, DIM);
     if (q.lead) bnext[q.parent] = tv;
   }
@@ -548,9 +553,11 @@ __device__ __forceinline__ void smooth_restrict(const LV<T> &L, int cnx, int cny
 
 // prolongation and post-smoothing on level L: y = x + P xc (xc on the next
 // coarser level, of dims (cnx, ., .) and plane size cnxy; global memory or
-// LDS), then NU sweeps y <- y + w D^-1 (b - A y); out = y
-template <int DIM, typename T, int NU>
-__device__ __forceinline__ void up_range(const LV<T> &L, int cnx, int cnxy, const T *xc, T *out, int start, int stride) {
+// LDS), then NU sweeps y <- y + w D^-1 (b - A y); out = y.  GATE, done: as
+// in smooth_restrict.
+template <int DIM, typename T, int NU, bool GATE = false>
+__device__ __forceinline__ void up_range(const LV<T> &L, int cnx, int cnxy, const T *xc, T *out, int start, int stride,
+                                         int done = 0) {
   const T w = (T)MG_OMEGA;
   const int st[3] = {1, L.nx, L.nxy};
   for (int g = start; g < L.nc; g += stride) {
@@ -571,6 +578,10 @@ __device__ __forceinline__ void up_range(const LV<T> &L, int cnx, int cnxy, cons
       T y1P;
       const T Ay1 = sweep_matvec<DIM, T>(L, c, y0o, y1P);
       res = y1P + w * (L.invD[g] * (L.b[g] - Ay1));
+    }
+    if constexpr (GATE) {
+      keep_live(res);
+      if (read_late(done)) return;
     }
     out[g] = res;
   }
@@ -678,21 +689,38 @@ __device__ __forceinline__ void mg_up_body(const Slot &s, int l, int start, int 
   up_range<DIM, T, NU>(L, C.nx, C.nxy, (const T *)C.t, L.t, start, stride);
 }
 
-// NU: the sweeps of level l, (mg.nu2 >> l & 1) + 1, chosen by the host
+// One context: the slot's state and the levels F = l and C = l + 1 by value
+// (their fields at fixed offsets of the argument segment, requested at
+// entry).  NU: the sweeps of level l, (mg.nu2 >> l & 1) + 1, chosen by the
+// host.
+#define OSCAR_PRIME_LEVELS(F, C)                                                                                      \
+  OSCAR_PRIME("s"(F.nx), "s"(F.ny), "s"(F.nz), "s"(F.nxy), "s"(F.nc), "s"(F.cf[0]), "s"(F.cf[1]), "s"(F.cf[2]),       \
+              "s"(F.cout), "s"(F.invD), "s"(F.b), "s"(F.x), "s"(F.t), "s"(C.nx), "s"(C.ny), "s"(C.nz));               \
+  OSCAR_PRIME("s"(C.nxy), "s"(C.b), "s"(C.t))
+
 template <int DIM, typename T, int NU>
-__global__ void __launch_bounds__(BLOCK) k_mg_smooth(const Slot S, int l, unsigned long long *ts) {
+__global__ void __launch_bounds__(BLOCK) k_mg_smooth(SlotState *st, const MGLevel F, const MGLevel C,
+                                                     unsigned long long *ts) {
+  OSCAR_PRIME("s"(ts), "s"(st), "s"(gridDim.x));
+  OSCAR_PRIME_LEVELS(F, C);
   Stamp stamp(ts);
-  if (mg_idle(S)) return;
-  mg_smooth_body<DIM, T, NU>(S, l, blockIdx.x * BLOCK + threadIdx.x, gridDim.x * BLOCK);
-  stamp.done();
+  const int done = st->done;
+  smooth_restrict<DIM, T, NU, true>(lview<T>(F), C.nx, C.ny, C.nz, (T *)C.b, blockIdx.x * BLOCK + threadIdx.x,
+                                    gridDim.x * BLOCK, done);
+  if (!done) stamp.done();
 }
 
 template <int DIM, typename T, int NU>
-__global__ void __launch_bounds__(BLOCK) k_mg_up(const Slot S, int l, unsigned long long *ts) {
+__global__ void __launch_bounds__(BLOCK) k_mg_up(SlotState *st, const MGLevel F, const MGLevel C,
+                                                 unsigned long long *ts) {
+  OSCAR_PRIME("s"(ts), "s"(st), "s"(gridDim.x));
+  OSCAR_PRIME_LEVELS(F, C);
   Stamp stamp(ts);
-  if (mg_idle(S)) return;
-  mg_up_body<DIM, T, NU>(S, l, blockIdx.x * BLOCK + threadIdx.x, gridDim.x * BLOCK);
-  stamp.done();
+  const int done = st->done;
+  const LV<T> L = lview<T>(F);
+  up_range<DIM, T, NU, true>(L, C.nx, C.nxy, (const T *)C.t, L.t, (int)(blockIdx.x * BLOCK + threadIdx.x),
+                       (int)(gridDim.x * BLOCK), done);
+  if (!done) stamp.done();
 }
 
 // batched: level l of the slots whose tail starts below it
@@ -727,8 +755,10 @@ __global__ void __launch_bounds__(BLOCK) k_mg_up_b(const Slot *slots, const int 
 // correction of the tail level goes back to global memory for the next finer
 // level's prolongation.  Without IN_LDS the same steps run on the block in
 // global memory (the persistent solve, when the block exceeds its LDS).
+// (done: the solve had converged before the launch; nothing is written to
+// global memory, tested once the block's loads are in; returns !done)
 template <int DIM, typename T, bool IN_LDS>
-__device__ __forceinline__ void mg_tail_body(const Slot &s, uint4 *mg_lds, int t0, int ns) {
+__device__ __forceinline__ bool mg_tail_body(const Slot &s, uint4 *mg_lds, int t0, int ns, int done = 0) {
   const int tl = s.mg.tail, L = s.mg.L;
   const char *gbase = (const char *)s.mg.tail_base;
   if constexpr (IN_LDS) {
@@ -749,6 +779,7 @@ __device__ __forceinline__ void mg_tail_body(const Slot &s, uint4 *mg_lds, int t
         if (x0 + u * ns < n16) dst[x0 + u * ns] = v[u];
     }
   }
+  if (done) return false;   // uniform
   __syncthreads();
   // an array of the block at its LDS position (itself without LDS; the
   // choice is made at compile time so that LDS accesses stay LDS
@@ -803,15 +834,17 @@ __device__ __forceinline__ void mg_tail_body(const Slot &s, uint4 *mg_lds, int t
   T *tdst = (T *)M.t;
   if (tsrc != tdst)
     for (int g = t0; g < M.nc; g += ns) tdst[g] = tsrc[g];
+  return true;
 }
 
 template <int DIM, typename T>
 __global__ void __launch_bounds__(MG_TAIL_THREADS) k_mg_tail(const Slot S, unsigned long long *ts) {
+  OSCAR_PRIME("s"(ts), "s"(S.st), "s"(S.mg.tail_base), "s"(S.mg.tail_bytes), "s"(S.mg.tail), "s"(S.mg.L),
+              "s"(S.mg.Ainv));
   Stamp stamp(ts);
-  if (mg_idle(S)) return;
+  const int done = S.st->done;
   extern __shared__ uint4 mg_lds[];
-  mg_tail_body<DIM, T, true>(S, mg_lds, threadIdx.x, MG_TAIL_THREADS);
-  stamp.done();
+  if (mg_tail_body<DIM, T, true>(S, mg_lds, threadIdx.x, MG_TAIL_THREADS, done)) stamp.done();
 }
 
 // batched: one workgroup per slot
@@ -855,9 +888,10 @@ constexpr int FINE_NB = sizeof(R) == 4 ? 2 : 1;
 // Search direction of iteration it: gamma_it = <r,z> and |r|^2 from the
 // previous cycle's reduction, convergence test (it > 0), beta, d = z + beta
 // d_old (d = z when it = 0), q = A d and <d,q>.
-// (false: the solve converged at this test; nothing was written)
+// (false: the solve converged at this test, or, with gate, had converged
+// before the launch; nothing was written)
 template <typename R, int NB>
-__device__ __forceinline__ bool mgcg_dir_body(const Slot &s, int lb, int it) {
+__device__ __forceinline__ bool mgcg_dir_body(const Slot &s, int lb, int it, bool gate = false) {
   using T = R;
   const Grid G = grid_of(s);
   const SlotCtl &ctl = *s.ctl;
@@ -868,8 +902,9 @@ __device__ __forceinline__ bool mgcg_dir_body(const Slot &s, int lb, int it) {
   const bool first = it == 0;
   const R *rAU = (const R *)s.rAU;
   const uint8_t *flags = s.flags;
-  const T *z = (const T *)s.cw[0], *dold = first ? z : (const T *)s.cs[(it + 1) & 1];
-  T *dn = (T *)s.cs[it & 1], *q = (T *)s.cp;
+  T *const cs0 = (T *)s.cs[0], *const cs1 = (T *)s.cs[1];
+  const T *z = (const T *)s.cw[0], *dold = first ? z : ((it & 1) ? cs0 : cs1);
+  T *dn = (it & 1) ? cs1 : cs0, *q = (T *)s.cp;
   // q = A d is formed as A z + beta q_old (the same vector in exact
   // arithmetic, as in Chronopoulos and Gear's CG), which needs d_old and
   // q_old at the cell only: one array fewer at the six neighbours.  The
@@ -890,11 +925,7 @@ __device__ __forceinline__ bool mgcg_dir_body(const Slot &s, int lb, int it) {
   double red[1] = {0.0};
   Partials<2> pt;   // the previous cycle's reduction, loaded ahead of the stencil operands
   prefetch_totals(s, CH_CG0 + ((it + 1) & 1), pt);
-  // the scalars of the convergence test and of beta, read with them (and
-  // combined only where they are used)
-  const double tgt = st->tgt, rtol = ctl.rtol, bn = st->bn;
-  const int max_it = ctl.max_it;
-  const double gam_old = st->gam[(it + 1) & 1];   // gamma of iteration it - 1 (unused when it = 0)
+  const int done = gate ? st->done : 0;   // converged before this launch (tested with the totals)
   const Walk wk = cell_walk(G, lb);
   batched<NB, Op>(
       wk.first, wk.stride, wk.end,
@@ -922,6 +953,16 @@ __device__ __forceinline__ bool mgcg_dir_body(const Slot &s, int lb, int it) {
         }
       },
       [&]() {
+        if (done) {
+          stop = true;
+          return false;
+        }
+        // the scalars of the convergence test and of beta, read behind the
+        // stencil operands (a wait for them ahead of the walk's set-up
+        // would hold back the first loads)
+        const double tgt = st->tgt, rtol = ctl.rtol, bn = st->bn;
+        const int max_it = ctl.max_it;
+        const double gam_old = st->gam[(it + 1) & 1];   // gamma of iteration it - 1 (unused when it = 0)
         double v[2];
         finish_totals(pt, v);   // written by the cycle of iteration it - 1
         const double gam = v[0];
@@ -981,10 +1022,13 @@ __device__ __forceinline__ bool mgcg_dir_body(const Slot &s, int lb, int it) {
 
 template <typename R, int NB>
 __global__ void __launch_bounds__(BLOCK) k_mgcg_dir(const Slot S, int it, unsigned long long *ts) {
+  OSCAR_PRIME("s"(ts), "s"(S.st), "s"(S.ctl), "s"(S.flags), "s"(S.part), "s"(S.rAU), "s"(S.cw[0]), "s"(S.cs[0]),
+              "s"(S.cs[1]), "s"(S.cp), "s"(S.nblocks), "s"(S.dim), "s"(S.nx), "s"(S.ny), "s"(S.nz), "s"(S.nxy));
+  OSCAR_PRIME("s"(S.nc), "s"(S.outlet), "s"(S.Sh), "s"(S.S2h), "s"(S.precision), "s"(it));
   Stamp stamp(ts);
   const int lb = xcd_block(blockIdx.x, S.nblocks);
-  if (lb < 0 || S.st->done) return;
-  if (mgcg_dir_body<R, NB>(S, lb, it)) stamp.done();
+  if (lb < 0) return;
+  if (mgcg_dir_body<R, NB>(S, lb, it, true)) stamp.done();
 }
 
 // batched: the engine's block table of its multigrid slots
@@ -1000,8 +1044,10 @@ __global__ void __launch_bounds__(BLOCK) k_mgcg_dir_b(const Slot *slots, const i
 // it = -1 (the cycle before the first iteration) r is the initial residual.
 // Then the cycle's fine pre-smoothing z0 = w D^-1 r and the restriction of
 // its residual r - A z0 into level 1, walking the fine grid in tile order.
+// (with gate, false: the solve had converged before the launch; nothing was
+// written)
 template <typename R, int NB>
-__device__ __forceinline__ void mg_fine_down_body(const Slot &s, int lb, int it, int mode) {
+__device__ __forceinline__ bool mg_fine_down_body(const Slot &s, int lb, int it, int mode, bool gate = false) {
   using T = R;
   const Grid G = grid_of(s);
   SlotState *st = s.st;
@@ -1013,9 +1059,10 @@ __device__ __forceinline__ void mg_fine_down_body(const Slot &s, int lb, int it,
   const T *invD = (const T *)s.invD;
   // r_new = r - alpha q; for the initial cycle alpha = 0 and q = r, so
   // r_new = r exactly and every load is unconditional
-  const T *r0 = (const T *)s.cr[upd ? (it & 1) : 0];
-  T *r1 = (T *)s.cr[upd ? ((it + 1) & 1) : 0];
-  const T *d = (const T *)s.cs[upd ? (it & 1) : 0], *q = upd ? (const T *)s.cp : r0;
+  T *const cr0 = (T *)s.cr[0], *const cr1 = (T *)s.cr[1];
+  const T *r0 = upd && (it & 1) ? cr1 : cr0;
+  T *r1 = upd && !(it & 1) ? cr1 : cr0;
+  const T *d = upd && (it & 1) ? (const T *)s.cs[1] : (const T *)s.cs[0], *q = upd ? (const T *)s.cp : r0;
   T *z0 = (T *)s.cw[1];
   T *xv = mixed ? (T *)s.e : (T *)(mode ? s.p_cr : s.p_vd);
   const int cnx = s.mg.lv[1].nx, cny = s.mg.lv[1].ny;
@@ -1040,6 +1087,7 @@ __device__ __forceinline__ void mg_fine_down_body(const Slot &s, int lb, int it,
   T al = (T)0;
   Partials<1> pt;   // <d,q> of the search-direction launch, loaded ahead of the stencil operands
   prefetch_totals(s, CH_DQ, pt);   // (unused by the initial cycle; loading it anyway avoids a branch)
+  const int done = gate ? st->done : 0;   // converged before this launch (tested with the first loads)
   batched<NB, Op>(
       wk.first, wk.stride, wk.end,
       [&](Op &o, int t) {
@@ -1080,6 +1128,7 @@ __device__ __forceinline__ void mg_fine_down_body(const Slot &s, int lb, int it,
         o.x = ldo(xv, oP);
       },
       [&]() {
+        if (done) return false;
         if (!upd) return true;
         double v[1];
         finish_totals(pt, v);
@@ -1116,6 +1165,7 @@ __device__ __forceinline__ void mg_fine_down_body(const Slot &s, int lb, int it,
         tv = kid_sum(tv, dim);
         if (o.lead) b1[o.parent] = tv;
       });
+  return !done;
 }
 
 // ---------------------------------------------------------------------------
@@ -1224,16 +1274,19 @@ __device__ __forceinline__ BrickWalk brick_walk(int lb, int nblocks, int nbx, in
   return w;
 }
 
-__device__ __forceinline__ void mg_fine_down_brick(const Slot &s, int lb, int it) {
+// (false: the solve had converged before the launch; nothing was written)
+__device__ __forceinline__ bool mg_fine_down_brick(const Slot &s, int lb, int it) {
   using T = float;
   const Grid G = grid_of(s);
   SlotState *st = s.st;
+  const int done = st->done;   // converged before this launch (tested once the first brick is in flight)
   const bool upd = it >= 0;
   const T *rAU = (const T *)s.rAU;
   const T *invD = (const T *)s.invD;
-  const T *r0 = (const T *)s.cr[upd ? (it & 1) : 0];
-  T *r1 = (T *)s.cr[upd ? ((it + 1) & 1) : 0];
-  const T *d = (const T *)s.cs[upd ? (it & 1) : 0], *q = upd ? (const T *)s.cp : r0;
+  T *const cr0 = (T *)s.cr[0], *const cr1 = (T *)s.cr[1];
+  const T *r0 = upd && (it & 1) ? cr1 : cr0;
+  T *r1 = upd && !(it & 1) ? cr1 : cr0;
+  const T *d = upd && (it & 1) ? (const T *)s.cs[1] : (const T *)s.cs[0], *q = upd ? (const T *)s.cp : r0;
   T *z0 = (T *)s.cw[1];
   T *xv = (T *)s.e;
   const int cnx = s.mg.lv[1].nx, cny = s.mg.lv[1].ny;
@@ -1278,6 +1331,10 @@ __device__ __forceinline__ void mg_fine_down_brick(const Slot &s, int lb, int it
     brick_stage(rAU, sa, off, need);
   };
   if (wk.first < wk.end) stage(wk.first);
+  if (done) {   // uniform; no LDS transfer may outlive the workgroup
+    __builtin_amdgcn_s_waitcnt(0);
+    return false;
+  }
   // the previous launch's <d,q> while the first brick loads
   T al = (T)0;
   if (upd) {
@@ -1355,25 +1412,32 @@ __device__ __forceinline__ void mg_fine_down_brick(const Slot &s, int lb, int it
     __syncthreads();   // every wavefront is done with the LDS: stage the next brick
     if (b + wk.stride < wk.end) stage(b + wk.stride);
   }
+  return true;
 }
 
 // (four wavefronts per SIMD: 128 registers; the LDS of four workgroups fits)
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4)))
 k_mg_fine_down_brick(const Slot S, int it, unsigned long long *ts) {
+  OSCAR_PRIME("s"(ts), "s"(S.st), "s"(S.flags), "s"(S.part), "s"(S.rAU), "s"(S.invD), "s"(S.cr[0]), "s"(S.cr[1]),
+              "s"(S.cs[0]), "s"(S.cs[1]), "s"(S.cp), "s"(S.cw[1]), "s"(S.e), "s"(S.nblocks), "s"(S.nx), "s"(S.ny));
+  OSCAR_PRIME("s"(S.nz), "s"(S.nxy), "s"(S.outlet), "s"(S.Sh), "s"(S.S2h), "s"(S.mg.lv[1].nx), "s"(S.mg.lv[1].ny),
+              "s"(S.mg.lv[1].b), "s"(it));
   Stamp stamp(ts);
   const int lb = xcd_block(blockIdx.x, S.nblocks);
-  if (lb < 0 || S.st->done) return;
-  mg_fine_down_brick(S, lb, it);
-  stamp.done();
+  if (lb < 0) return;
+  if (mg_fine_down_brick(S, lb, it)) stamp.done();
 }
 
 template <typename R, int NB>
 __global__ void __launch_bounds__(BLOCK) k_mg_fine_down(const Slot S, int it, int mode, unsigned long long *ts) {
+  OSCAR_PRIME("s"(ts), "s"(S.st), "s"(S.flags), "s"(S.part), "s"(S.rAU), "s"(S.invD), "s"(S.cr[0]), "s"(S.cr[1]),
+              "s"(S.cs[0]), "s"(S.cs[1]), "s"(S.cp), "s"(S.cw[1]), "s"(S.e), "s"(S.nblocks), "s"(S.dim), "s"(S.nx));
+  OSCAR_PRIME("s"(S.ny), "s"(S.nz), "s"(S.nxy), "s"(S.nc), "s"(S.outlet), "s"(S.Sh), "s"(S.S2h), "s"(S.mg.lv[1].nx),
+              "s"(S.mg.lv[1].ny), "s"(S.mg.lv[1].nz), "s"(S.mg.lv[1].b), "s"(it));
   Stamp stamp(ts);
   const int lb = xcd_block(blockIdx.x, S.nblocks);
-  if (lb < 0 || S.st->done) return;
-  mg_fine_down_body<R, NB>(S, lb, it, mode);
-  stamp.done();
+  if (lb < 0) return;
+  if (mg_fine_down_body<R, NB>(S, lb, it, mode, true)) stamp.done();
 }
 
 template <typename R, int NB>
@@ -1387,13 +1451,13 @@ __global__ void __launch_bounds__(BLOCK) k_mg_fine_down_b(const Slot *slots, con
 // Last step of the cycle: z' = z0 + P x1, z = z' + w D^-1 (r - A z'); the
 // reduction <r,z>, |r|^2 for the next search direction.
 template <typename R, int NB>
-__device__ __forceinline__ void mg_fine_up_body(const Slot &s, int lb, int it) {
+__device__ __forceinline__ bool mg_fine_up_body(const Slot &s, int lb, int it, bool gate = false) {
   using T = R;
   const Grid G = grid_of(s);
   const uint8_t *flags = s.flags;
   const R *rAU = (const R *)s.rAU;
   const T *invD = (const T *)s.invD;
-  const T *r = (const T *)s.cr[(it + 1) & 1];
+  const T *r = (it & 1) ? (const T *)s.cr[0] : (const T *)s.cr[1];
   const T *z0 = (const T *)s.cw[1];
   T *z = (T *)s.cw[0];
   const int cnx = s.mg.lv[1].nx, cnxy = s.mg.lv[1].nxy;
@@ -1407,6 +1471,7 @@ __device__ __forceinline__ void mg_fine_up_body(const Slot &s, int lb, int it) {
     T r, iD;
   };
   double red[2] = {0.0, 0.0};
+  const int done = gate ? s.st->done : 0;   // converged before this launch (tested with the first loads)
   const Walk wk = cell_walk(G, lb);
   batched<NB, Op>(
       wk.first, wk.stride, wk.end,
@@ -1442,7 +1507,7 @@ __device__ __forceinline__ void mg_fine_up_body(const Slot &s, int lb, int it) {
           o.ra[f] = ldo(rAU, on[f]);
         }
       },
-      [&]() { return true; },
+      [&]() { return !done; },
       [&](Op &o) {
         if (o.fl & 0x40) return;
         auto zp = [&](int m) -> T { return o.z0[m] + o.xc[m]; };
@@ -1460,16 +1525,21 @@ __device__ __forceinline__ void mg_fine_up_body(const Slot &s, int lb, int it) {
         red[0] = red[0] + (double)(rr * zn);
         red[1] = red[1] + (double)(rr * rr);
       });
+  if (done) return false;   // uniform
   put_partials<0u>(s, lb, CH_CG0 + (it & 1), red);
+  return true;
 }
 
 template <typename R, int NB>
 __global__ void __launch_bounds__(BLOCK) k_mg_fine_up(const Slot S, int it, unsigned long long *ts) {
+  OSCAR_PRIME("s"(ts), "s"(S.st), "s"(S.flags), "s"(S.part), "s"(S.rAU), "s"(S.invD), "s"(S.cr[0]), "s"(S.cr[1]),
+              "s"(S.cw[0]), "s"(S.cw[1]), "s"(S.nblocks), "s"(S.dim), "s"(S.nx), "s"(S.ny), "s"(S.nz), "s"(S.nxy));
+  OSCAR_PRIME("s"(S.nc), "s"(S.outlet), "s"(S.Sh), "s"(S.S2h), "s"(S.mg.lv[1].nx), "s"(S.mg.lv[1].nxy),
+              "s"(S.mg.lv[1].t), "s"(it));
   Stamp stamp(ts);
   const int lb = xcd_block(blockIdx.x, S.nblocks);
-  if (lb < 0 || S.st->done) return;
-  mg_fine_up_body<R, NB>(S, lb, it);
-  stamp.done();
+  if (lb < 0) return;
+  if (mg_fine_up_body<R, NB>(S, lb, it, true)) stamp.done();
 }
 
 template <typename R, int NB>
@@ -1808,15 +1878,19 @@ static void vcycle_levels(const Slot &hs, const Launch &L, unsigned long long *t
   for (int l = 1; l < tl; ++l) {
     const MGLevel &C = hs.mg.lv[l + 1];
     const dim3 g(lvl_grid((int)kid_total(DIM, C.nx, C.ny, C.nz)));
-    if ((hs.mg.nu2 >> l) & 1) hipLaunchKernelGGL((k_mg_smooth<DIM, R, 2>), g, dim3(BLOCK), 0, L.stream, hs, l, next());
-    else hipLaunchKernelGGL((k_mg_smooth<DIM, R, 1>), g, dim3(BLOCK), 0, L.stream, hs, l, next());
+    if ((hs.mg.nu2 >> l) & 1)
+      hipLaunchKernelGGL((k_mg_smooth<DIM, R, 2>), g, dim3(BLOCK), 0, L.stream, hs.st, hs.mg.lv[l], C, next());
+    else hipLaunchKernelGGL((k_mg_smooth<DIM, R, 1>), g, dim3(BLOCK), 0, L.stream, hs.st, hs.mg.lv[l], C, next());
   }
   hipLaunchKernelGGL((k_mg_tail<DIM, R>), dim3(1), dim3(MG_TAIL_THREADS), (size_t)hs.mg.tail_bytes, L.stream, hs,
                      next());
   for (int l = tl - 1; l >= 1; --l) {
     const dim3 g(lvl_grid(hs.mg.lv[l].nc));
-    if ((hs.mg.nu2 >> l) & 1) hipLaunchKernelGGL((k_mg_up<DIM, R, 2>), g, dim3(BLOCK), 0, L.stream, hs, l, next());
-    else hipLaunchKernelGGL((k_mg_up<DIM, R, 1>), g, dim3(BLOCK), 0, L.stream, hs, l, next());
+    if ((hs.mg.nu2 >> l) & 1)
+      hipLaunchKernelGGL((k_mg_up<DIM, R, 2>), g, dim3(BLOCK), 0, L.stream, hs.st, hs.mg.lv[l], hs.mg.lv[l + 1],
+                         next());
+    else hipLaunchKernelGGL((k_mg_up<DIM, R, 1>), g, dim3(BLOCK), 0, L.stream, hs.st, hs.mg.lv[l], hs.mg.lv[l + 1],
+                            next());
   }
 }
 
