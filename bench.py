@@ -44,8 +44,9 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 TIMING_PERIOD = 8
 # rocprofv3's kernel duration exceeds the timing hook's span by the packet
-# dispatch before the first wave and the completion signal after the last:
-# 1.2-1.7 us for every kernel and both precisions (profiles/kernels_mg_cg_*.md)
+# dispatch before the first wave and the completion signal after the last
+# (the start stamp follows the kernel's argument loads): 1.55-1.91 us for
+# every fine kernel and both precisions (profiles/kernels_mg_cg_*.md)
 DISPATCH_US = 1.7
 
 # parts of a CG iteration reported by the timing hook (index: kernel name)
