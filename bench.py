@@ -49,6 +49,17 @@ TIMING_PERIOD = 8
 # every fine kernel and both precisions (profiles/kernels_mg_cg_*.md)
 DISPATCH_US = 1.7
 
+# The paper's own speed-up, quoted beside the measurement as context only: it
+# compares whole simulations of its CPU solver (hardware not stated) with the
+# same solver's plain PISO time stepping, not a throughput of this path.
+PAPER_CONTEXT = {
+    "oscar_vs_piso_speedup": "2.5x / 25x / 250x at Ca = 1e-5 / 1e-6 / 1e-7",
+    "workload": "2D water drainage in an oil-wet micromodel (Benchmark cases, micromodel subsection, Table drainage; "
+                "the PISO times at these Ca are extrapolated)",
+    "hardware": "CPU, not stated by the paper; precision not stated",
+    "comparable": False,
+}
+
 # parts of a CG iteration reported by the timing hook (index: kernel name)
 MG_PARTS = {1: "k_mgcg_dir", 2: "k_mg_fine_down", 3: "coarse levels (k_mg_smooth, k_mg_tail, k_mg_up)",
             4: "k_mg_fine_up"}
@@ -566,6 +577,7 @@ def main():
                                            log=lambda m: print("[serving] " + m, file=sys.stderr, flush=True))
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(case, pc)
+    out["paper_context"] = PAPER_CONTEXT
     print(json.dumps(out), flush=True)
 
 
