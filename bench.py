@@ -254,7 +254,7 @@ def measured_traffic(kernel, workload):
     return rec["bytes_per_launch"] if h.hexdigest() == rec["sources_sha256"] else None
 
 
-def run_reps(case, precision, reps, warmup, max_iters, precond=1):
+def run_reps(case, precision, reps, warmup, max_iters, precond=1, keep_fields=False):
     """One OSCAR global step with max_iters relaxation sub-steps (tol = 0),
     repeated from a fresh context each time (the checkpoint is the initial
     state): warmup untimed repetitions, then reps timed ones; the median
@@ -266,6 +266,7 @@ def run_reps(case, precision, reps, warmup, max_iters, precond=1):
 
     times, rtimes, pcg, kfs, refs = [], [], [], [], []
     acc = {k: [0.0, 0] for k in range(5)}
+    fields = None
     for r in range(warmup + reps):
         g = oscar.Oscar(case, precision=precision, device="cuda:0", precond=precond)
         torch.cuda.synchronize()
@@ -301,11 +302,21 @@ def run_reps(case, precision, reps, warmup, max_iters, precond=1):
             pcg.append(it)
             kfs.append(kf)
             refs.append(ref)
+        if keep_fields and r == warmup + reps - 1:   # every repetition starts from the same state
+            fields = {f: g.get(f) for f in ("alpha", "p", "U")}
         g.close()
     order = sorted(range(reps), key=lambda x: times[x])
     m = order[len(order) // 2]
     return dict(seconds=times[m], relax_seconds=rtimes[m], pcg_iters=pcg[m], k_f=kfs[m], refine_steps=refs[m],
-                parts={k: tuple(v) for k, v in acc.items()}, times=times)
+                parts={k: tuple(v) for k, v in acc.items()}, times=times, fields=fields)
+
+
+def rel_linf(x, ref, mask):
+    """max |x - ref| / max |ref| over the masked entries"""
+    import numpy as np
+
+    den = float(np.abs(ref[mask]).max())
+    return float(np.abs(x[mask] - ref[mask]).max()) / (den if den > 0 else 1.0)
 
 
 CONFIGS = {
@@ -333,10 +344,12 @@ def config_legs(config, pc, reps=3, warmup=1, fp64=True):
     kmax = min(20, case["n_sub"])
     out = {"workload": fmt % (n_fluid, kmax, case["n_sub"], "multigrid" if pc else "Jacobi"),
            "protocol": "%d warm-up + %d repetitions from the initial state, median" % (warmup, reps)}
+    fields = {}
     for prec, key in ((1, "mixed"), (0, "fp64")):
         if prec == 0 and not fp64:
             continue
-        r = run_reps(case, prec, reps, warmup, kmax, pc)
+        r = run_reps(case, prec, reps, warmup, kmax, pc, keep_fields=fp64)
+        fields[key] = r["fields"]
         ktab = kernel_table(r, prec, pc, n_fluid, nc, nc1)
         dom = dominant(ktab)
         out[key] = {
@@ -352,6 +365,17 @@ def config_legs(config, pc, reps=3, warmup=1, fp64=True):
             "step_roofline": step_roofline(prec, pc, dim, n_fluid, nc, nc1, 1 + r["k_f"], r["pcg_iters"],
                                            r["refine_steps"], r["seconds"]),
         }
+    if fp64:
+        import numpy as np
+
+        fl = case["mask"].reshape(-1) == 0
+        a, b = fields["mixed"], fields["fp64"]
+        out["mixed"]["error_vs_fp64_gpu"] = {
+            "alpha": rel_linf(a["alpha"], b["alpha"], fl), "p": rel_linf(a["p"], b["p"], fl),
+            "U": rel_linf(a["U"], b["U"], np.tile(fl, dim)),
+            "note": "the same step on the FP64 GPU path (both to pressure rtol 1e-8), relative L-infinity over the "
+                    "fluid cells; the FP64 path matches the FP64 oracle on a sample of this medium "
+                    "(tests/test_gpu_fullsize.py)"}
     return out
 
 
@@ -371,6 +395,7 @@ def bench_config(args):
            "step_roofline": m["step_roofline"]}
     if "fp64" in legs:
         out["fp64"] = legs["fp64"]
+        out["error_vs_fp64_gpu"] = m["error_vs_fp64_gpu"]
     print(json.dumps(out), flush=True)
 
 
