@@ -103,6 +103,25 @@ def test_regularised_normal_at_gradient_equal_to_delta():
     assert np.abs(nx_faces[2:n - 1] - 0.5).max() < 1e-6, nx_faces
 
 
+def test_normal_on_open_boundary_faces_is_the_boundary_cells_own():
+    """Inlet and outlet faces take the regularised gradient of their
+    boundary cell.  On the same ramp of slope delta per cell, that cell's
+    Gauss gradient, with the zero-gradient face value on the open face, is
+    half the slope, so the face normal is (delta/2) / (delta/2 + delta) =
+    1/3 at both ends.  Catches a zeroed normal on open faces (0), the
+    neighbouring cell's gradient (1/2) and the mean of the two gradients
+    (3/7)."""
+    n, h = 16, 1e-5
+    a = 0.3 + 1e-8 * np.arange(n)
+    bc = [cases.BC_INLET, cases.BC_OUTLET, cases.BC_WALL, cases.BC_WALL, 0, 0]
+    o = Oracle(_line_case(n, h, a, bc, sigma=0.0))
+    o.pressure_solve(1, 1e-9, 1e-6, 1)
+    nx_faces = o.get("nhatf")[: n + 1]
+    assert abs(nx_faces[0] - 1.0 / 3.0) < 1e-6, nx_faces[:2]
+    assert abs(nx_faces[n] - 1.0 / 3.0) < 1e-6, nx_faces[-2:]
+    assert np.abs(nx_faces[2:n - 1] - 0.5).max() < 1e-6
+
+
 # ---------------------------------------------------------------------------
 # mass: the corrected face fluxes are divergence-free
 # ---------------------------------------------------------------------------
