@@ -509,7 +509,7 @@ def main():
         print(json.dumps({"pmc_calibration_copy_bytes": a.numel(), "copies": 3}))
         return
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (see DESIGN.md, sharding)",
+        print("bench.py measures one GPU: the library has no multi-GPU path; run it with --gpus 1",
               file=sys.stderr)
         sys.exit(2)
 
