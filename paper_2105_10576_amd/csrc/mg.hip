@@ -587,6 +587,143 @@ __device__ __forceinline__ void up_range(const LV<T> &L, int cnx, int cnxy, cons
   }
 }
 
+// Large levels (MG_SPLIT_MIN cells or more) with two sweeps per side run
+// each sweep as a launch of its own.  The fused kernels above evaluate the
+// first sweep again at every neighbour (a radius-2 stencil: about 100 loads
+// per cell, and registers for three waves per SIMD); on a large level a
+// launch costs little beside that, so the sweep is stored and the next step
+// reads it on the radius-1 star.  star1, matvec_center and sweep_center
+// take the operations of sweep_matvec at the star's centre in the same order,
+// so every stored value is bitwise the one the fused kernels recompute, and
+// the results are those of the fused kernels.
+
+// byte offsets of the radius-1 star of cell c (m = 0 the cell, 1 + 2e and
+// 2 + 2e its low and high neighbour in direction e; the cell itself outside
+// the box) and whether each neighbour exists
+template <int DIM, typename T>
+__device__ __forceinline__ void star1(const LV<T> &L, const LCell &c, unsigned (&B)[7], bool (&in)[7]) {
+  const int n[3] = {L.nx, L.ny, L.nz};
+  const int q[3] = {c.i, c.j, c.k};
+  const int st[3] = {1, L.nx, L.nxy};
+  B[0] = (unsigned)c.P * (unsigned)sizeof(T);
+  in[0] = true;
+#pragma unroll
+  for (int e = 0; e < 3; ++e) {
+    const bool lo = e < DIM && q[e] > 0, hi = e < DIM && q[e] < n[e] - 1;
+    in[1 + 2 * e] = lo;
+    in[2 + 2 * e] = hi;
+    B[1 + 2 * e] = lo ? (unsigned)(c.P - st[e]) * (unsigned)sizeof(T) : B[0];
+    B[2 + 2 * e] = hi ? (unsigned)(c.P + st[e]) * (unsigned)sizeof(T) : B[0];
+  }
+}
+
+// (A u) at the star's centre from u(m) on the star (sweep_matvec's mv at m = 0)
+template <int DIM, typename T, class U>
+__device__ __forceinline__ T matvec_center(const LV<T> &L, const unsigned (&B)[7], const bool (&in)[7], U &&u) {
+  T acc = (T)0;
+#pragma unroll
+  for (int e = 0; e < DIM; ++e) {
+    const int ml = 1 + 2 * e, mh = 2 + 2 * e;
+    const T cl = ldo(L.cf[e], B[0]), ch = ldo(L.cf[e], B[mh]);
+    const T tl = acc + cl * (u(0) - u(ml));
+    acc = in[ml] ? tl : acc;
+    const T th = acc + ch * (u(0) - u(mh));
+    acc = in[mh] ? th : acc;
+  }
+  return acc + ldo(L.cout, B[0]) * u(0);
+}
+
+// one Jacobi sweep from u0 at the star's centre: u0 + w D^-1 (b - A u0)
+template <int DIM, typename T, class U>
+__device__ __forceinline__ T sweep_center(const LV<T> &L, const unsigned (&B)[7], const bool (&in)[7], U &&u0) {
+  const T w = (T)MG_OMEGA;
+  return u0(0) + w * (ldo(L.invD, B[0]) * (ldo((const T *)L.b, B[0]) - matvec_center<DIM, T>(L, B, in, u0)));
+}
+
+// pre-smoothing, first launch: x = both sweeps from zero at every cell
+template <int DIM, typename T>
+__device__ __forceinline__ void split_smooth(const LV<T> &L, int start, int stride, int done) {
+  const T w = (T)MG_OMEGA;
+  for (int g = start; g < L.nc; g += stride) {
+    const LCell c = lcell(L.nx, L.ny, g);
+    unsigned B[7];
+    bool in[7];
+    star1<DIM, T>(L, c, B, in);
+    auto x1 = [&](int m) -> T { return w * (ldo(L.invD, B[m]) * ldo((const T *)L.b, B[m])); };
+    const T x2 = sweep_center<DIM, T>(L, B, in, x1);
+    keep_live(x2);
+    if (read_late(done)) return;
+    L.x[g] = x2;
+  }
+}
+
+// pre-smoothing, second launch: the residual b - A x restricted in tile order
+template <int DIM, typename T>
+__device__ __forceinline__ void split_restrict(const LV<T> &L, int cnx, int cny, int cnz, T *bnext, unsigned start,
+                                               unsigned stride, int done) {
+  const unsigned total = kid_total(DIM, cnx, cny, cnz);
+  for (unsigned tau = start; tau < total; tau += stride) {
+    const Kid q = kid_at(tau, DIM, L.nx, L.ny, L.nz, cnx, cny);
+    T tv = (T)0;
+    if (q.valid) {
+      LCell c;
+      c.P = q.P;
+      c.i = q.i;
+      c.j = q.j;
+      c.k = q.k;
+      unsigned B[7];
+      bool in[7];
+      star1<DIM, T>(L, c, B, in);
+      auto x2 = [&](int m) -> T { return ldo((const T *)L.x, B[m]); };
+      tv = L.b[c.P] - matvec_center<DIM, T>(L, B, in, x2);
+    }
+    keep_live(tv);
+    if (read_late(done)) return;
+    tv = kid_sum(tv, DIM);
+    if (q.lead) bnext[q.parent] = tv;
+  }
+}
+
+// prolongation and first post-sweep: y1 = y0 + w D^-1 (b - A y0), y0 = x + P xc
+template <int DIM, typename T>
+__device__ __forceinline__ void split_up_first(const LV<T> &L, int cnx, int cnxy, const T *xc, T *y1out, int start,
+                                               int stride, int done) {
+  const int st[3] = {1, L.nx, L.nxy};
+  for (int g = start; g < L.nc; g += stride) {
+    const LCell c = lcell(L.nx, L.ny, g);
+    unsigned B[7];
+    bool in[7];
+    star1<DIM, T>(L, c, B, in);
+    auto y0 = [&](int m) -> T {
+      const LCell p = m == 0 || !in[m] ? c : lshift(c, (m - 1) >> 1, (m & 1) ? -1 : 1, st);
+      return ldo((const T *)L.x, B[m]) +
+             ldo(xc, (unsigned)((p.i >> 1) + cnx * (p.j >> 1) + cnxy * (p.k >> 1)) * (unsigned)sizeof(T));
+    };
+    const T y1 = sweep_center<DIM, T>(L, B, in, y0);
+    keep_live(y1);
+    if (read_late(done)) return;
+    y1out[g] = y1;
+  }
+}
+
+// second post-sweep: out = y1 + w D^-1 (b - A y1)
+template <int DIM, typename T>
+__device__ __forceinline__ void split_up_second(const LV<T> &L, const T *y1in, T *out, int start, int stride,
+                                                int done) {
+  const T w = (T)MG_OMEGA;
+  for (int g = start; g < L.nc; g += stride) {
+    const LCell c = lcell(L.nx, L.ny, g);
+    unsigned B[7];
+    bool in[7];
+    star1<DIM, T>(L, c, B, in);
+    auto y1 = [&](int m) -> T { return ldo(y1in, B[m]); };
+    const T res = y1(0) + w * (L.invD[g] * (L.b[g] - matvec_center<DIM, T>(L, B, in, y1)));
+    keep_live(res);
+    if (read_late(done)) return;
+    out[g] = res;
+  }
+}
+
 // The levels of the single-workgroup tail live in LDS, where a barrier is
 // cheap: their sweeps run one after the other over the whole level with a
 // barrier between them (rather than re-evaluating earlier sweeps at the
@@ -720,6 +857,55 @@ __global__ void __launch_bounds__(BLOCK) k_mg_up(SlotState *st, const MGLevel F,
   const LV<T> L = lview<T>(F);
   up_range<DIM, T, NU, true>(L, C.nx, C.nxy, (const T *)C.t, L.t, (int)(blockIdx.x * BLOCK + threadIdx.x),
                        (int)(gridDim.x * BLOCK), done);
+  if (!done) stamp.done();
+}
+
+// the two launches of each side of a split level (one context)
+template <int DIM, typename T>
+__global__ void __launch_bounds__(BLOCK) k_mg_split_smooth(SlotState *st, const MGLevel F, const MGLevel C,
+                                                           unsigned long long *ts) {
+  OSCAR_PRIME("s"(ts), "s"(st), "s"(gridDim.x));
+  OSCAR_PRIME_LEVELS(F, C);
+  Stamp stamp(ts);
+  const int done = st->done;
+  split_smooth<DIM, T>(lview<T>(F), (int)(blockIdx.x * BLOCK + threadIdx.x), (int)(gridDim.x * BLOCK), done);
+  if (!done) stamp.done();
+}
+
+template <int DIM, typename T>
+__global__ void __launch_bounds__(BLOCK) k_mg_split_restrict(SlotState *st, const MGLevel F, const MGLevel C,
+                                                             unsigned long long *ts) {
+  OSCAR_PRIME("s"(ts), "s"(st), "s"(gridDim.x));
+  OSCAR_PRIME_LEVELS(F, C);
+  Stamp stamp(ts);
+  const int done = st->done;
+  split_restrict<DIM, T>(lview<T>(F), C.nx, C.ny, C.nz, (T *)C.b, blockIdx.x * BLOCK + threadIdx.x,
+                         gridDim.x * BLOCK, done);
+  if (!done) stamp.done();
+}
+
+// tmp: the first post-sweep (a free array of at least F.nc elements)
+template <int DIM, typename T>
+__global__ void __launch_bounds__(BLOCK) k_mg_split_up1(SlotState *st, const MGLevel F, const MGLevel C, T *tmp,
+                                                        unsigned long long *ts) {
+  OSCAR_PRIME("s"(ts), "s"(st), "s"(gridDim.x), "s"(tmp));
+  OSCAR_PRIME_LEVELS(F, C);
+  Stamp stamp(ts);
+  const int done = st->done;
+  split_up_first<DIM, T>(lview<T>(F), C.nx, C.nxy, (const T *)C.t, tmp, (int)(blockIdx.x * BLOCK + threadIdx.x),
+                         (int)(gridDim.x * BLOCK), done);
+  if (!done) stamp.done();
+}
+
+template <int DIM, typename T>
+__global__ void __launch_bounds__(BLOCK) k_mg_split_up2(SlotState *st, const MGLevel F, const MGLevel C, const T *tmp,
+                                                        unsigned long long *ts) {
+  OSCAR_PRIME("s"(ts), "s"(st), "s"(gridDim.x), "s"(tmp));
+  OSCAR_PRIME_LEVELS(F, C);
+  Stamp stamp(ts);
+  const int done = st->done;
+  const LV<T> L = lview<T>(F);
+  split_up_second<DIM, T>(L, tmp, L.t, (int)(blockIdx.x * BLOCK + threadIdx.x), (int)(gridDim.x * BLOCK), done);
   if (!done) stamp.done();
 }
 
@@ -1875,10 +2061,18 @@ static void vcycle_levels(const Slot &hs, const Launch &L, unsigned long long *t
   const int tl = hs.mg.tail;
   int m = 0;   // launch index within the part: its stamp region
   auto next = [&]() -> unsigned long long * { return ts ? ts + (size_t)TS_WORDS * m++ : nullptr; };
+  // the split levels' first post-sweep goes to z of the fine grid, which
+  // no launch reads between the fine pre-smoothing and fine up (fine up
+  // writes it)
+  R *tmp = (R *)hs.cw[0];
   for (int l = 1; l < tl; ++l) {
     const MGLevel &C = hs.mg.lv[l + 1];
     const dim3 g(lvl_grid((int)kid_total(DIM, C.nx, C.ny, C.nz)));
-    if ((hs.mg.nu2 >> l) & 1)
+    if (mg_split(hs, l)) {
+      hipLaunchKernelGGL((k_mg_split_smooth<DIM, R>), dim3(lvl_grid(hs.mg.lv[l].nc)), dim3(BLOCK), 0, L.stream, hs.st,
+                         hs.mg.lv[l], C, next());
+      hipLaunchKernelGGL((k_mg_split_restrict<DIM, R>), g, dim3(BLOCK), 0, L.stream, hs.st, hs.mg.lv[l], C, next());
+    } else if ((hs.mg.nu2 >> l) & 1)
       hipLaunchKernelGGL((k_mg_smooth<DIM, R, 2>), g, dim3(BLOCK), 0, L.stream, hs.st, hs.mg.lv[l], C, next());
     else hipLaunchKernelGGL((k_mg_smooth<DIM, R, 1>), g, dim3(BLOCK), 0, L.stream, hs.st, hs.mg.lv[l], C, next());
   }
@@ -1886,7 +2080,12 @@ static void vcycle_levels(const Slot &hs, const Launch &L, unsigned long long *t
                      next());
   for (int l = tl - 1; l >= 1; --l) {
     const dim3 g(lvl_grid(hs.mg.lv[l].nc));
-    if ((hs.mg.nu2 >> l) & 1)
+    if (mg_split(hs, l)) {
+      hipLaunchKernelGGL((k_mg_split_up1<DIM, R>), g, dim3(BLOCK), 0, L.stream, hs.st, hs.mg.lv[l], hs.mg.lv[l + 1], tmp,
+                         next());
+      hipLaunchKernelGGL((k_mg_split_up2<DIM, R>), g, dim3(BLOCK), 0, L.stream, hs.st, hs.mg.lv[l], hs.mg.lv[l + 1],
+                         (const R *)tmp, next());
+    } else if ((hs.mg.nu2 >> l) & 1)
       hipLaunchKernelGGL((k_mg_up<DIM, R, 2>), g, dim3(BLOCK), 0, L.stream, hs.st, hs.mg.lv[l], hs.mg.lv[l + 1],
                          next());
     else hipLaunchKernelGGL((k_mg_up<DIM, R, 1>), g, dim3(BLOCK), 0, L.stream, hs.st, hs.mg.lv[l], hs.mg.lv[l + 1],

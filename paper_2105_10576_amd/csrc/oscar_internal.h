@@ -79,6 +79,11 @@ constexpr int MG_COARSEST = 16;
 constexpr int MG_TAIL_CELLS = 4096;
 constexpr int MG_DENSE_MAX = 64;
 constexpr int MG_TAIL_LDS = 160 * 1024;   // LDS of one gfx950 workgroup
+// A grid-wide level of at least MG_SPLIT_MIN cells with two sweeps per side
+// runs each sweep as a launch of its own (a context's launches; the
+// engine's and the persistent solve's keep the fused kernels, with bitwise
+// the same results).
+constexpr int MG_SPLIT_MIN = 1 << 17;
 struct MGLevel {
   int32_t nx, ny, nz, nc, nxy, nblocks;
   void *cf[3];        // coefficient of each cell's low face per direction (T)
@@ -213,7 +218,13 @@ template <typename R> void launch_mg_setup_b(const MGBatch &B);
 template <typename R> void launch_mg_dir_b(const MGBatch &B, int it);
 // part as in launch_mg_cycle_part; the FP64 update reads each slot's mode
 template <typename R> void launch_mg_cycle_part_b(const MGBatch &B, int it, int part);
-inline int mg_part_launches(const Slot &hs, int part) { return part == 1 ? 2 * (hs.mg.tail - 1) + 1 : 1; }
+inline bool mg_split(const Slot &hs, int l) { return ((hs.mg.nu2 >> l) & 1) && hs.mg.lv[l].nc >= MG_SPLIT_MIN; }
+inline int mg_part_launches(const Slot &hs, int part) {
+  if (part != 1) return 1;
+  int n = 2 * (hs.mg.tail - 1) + 1;
+  for (int l = 1; l < hs.mg.tail; ++l) n += mg_split(hs, l) ? 2 : 0;
+  return n;
+}
 template <typename R> void launch_mg_dir(const Slot &hs, const Launch &L, int it, unsigned long long *ts = nullptr);
 void launch_gather_states(const Launch &L, int nslots, SlotState *out);
 
