@@ -141,3 +141,20 @@ def test_brick_kernel_equals_single_cell_kernel():
     a = _steps(oscar, c, 1, oscar.SOLVE_LAUNCHES, 1)
     b = _steps(oscar, c, 1, oscar.SOLVE_PERSISTENT, 1)
     _same(a, b)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_split_coarse_sweeps_equal_fused_kernels(precision):
+    """A grid-wide level of at least 128k cells with two sweeps per side runs
+    each sweep as a launch of its own (the stored sweep read on the radius-1
+    star), while the persistent solve's tiles run the fused kernels, which
+    evaluate it again at the neighbours: the two must agree bit for bit in
+    both precisions (128 x 128 x 64 constricted channel, whose level 1 has
+    131072 cells; one step of one sub-step)."""
+    from paper_2105_10576_amd import oscar
+    c = cases.constricted_channel(nx=128, ny=128, nz=64, max_iters=1)
+    c["precond"] = 1
+    c["pcg_rtol"] = 1e-8 if precision == 1 else 1e-10
+    a = _steps(oscar, c, precision, oscar.SOLVE_LAUNCHES, 1)
+    b = _steps(oscar, c, precision, oscar.SOLVE_PERSISTENT, 1)
+    _same(a, b)
