@@ -76,7 +76,7 @@ struct SlotCtl {
 // arrays form one contiguous block (mg_tail_bytes).
 constexpr int MG_MAXL = 12;
 constexpr int MG_COARSEST = 16;
-constexpr int MG_TAIL_CELLS = 4096;
+constexpr int MG_TAIL_CELLS = 2048;
 constexpr int MG_DENSE_MAX = 64;
 constexpr int MG_TAIL_LDS = 160 * 1024;   // LDS of one gfx950 workgroup
 // A grid-wide level of at least MG_SPLIT_MIN cells with two sweeps per side
