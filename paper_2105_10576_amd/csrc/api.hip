@@ -1360,8 +1360,9 @@ struct oscar_engine {
   Slot *d_slots = nullptr;
   int2 *d_btab = nullptr, *d_btab2 = nullptr;
   int2 *d_btab_j = nullptr, *d_btab_m = nullptr;   // block tables of the Jacobi and the multigrid slots
+  int2 *d_btab_live = nullptr;     // block table of the multigrid slots still iterating in an inner solve
   int *d_act = nullptr;            // multigrid slot lists by dimension, then those whose hierarchy is
-                                   // rebuilt this tick (4 x max_slots)
+                                   // rebuilt this tick, then those still iterating (6 x max_slots)
   SlotState *d_states = nullptr;   // gathered copy of the slots' states
   // persistent solves (OSCAR_SOLVE_PERSISTENT): the list of the slots a
   // launch solves, its batch words and their host copy
@@ -1375,8 +1376,8 @@ struct oscar_engine {
   SlotState *h_states = nullptr;
   std::vector<EngSlot> slots;
   std::vector<Region> free_list;
-  std::vector<int2> bt, bt2, bt_j, bt_m;
-  std::vector<int> act_m;
+  std::vector<int2> bt, bt2, bt_j, bt_m, bt_live;
+  std::vector<int> act_m, act_live;
   std::string err = "no error";
   int64_t ticks = 0, cg_iters = 0;
 };
@@ -1396,8 +1397,8 @@ static int eng_fail(oscar_engine *e, hipError_t x, const char *what) {
   } while (0)
 
 static uint64_t eng_table_bytes(int max_slots, int btab_cap) {
-  return up(sizeof(Slot) * (uint64_t)max_slots) + 4 * up(sizeof(int2) * (uint64_t)btab_cap) +
-         up(sizeof(int) * 4 * (uint64_t)max_slots) + up(sizeof(SlotState) * (uint64_t)max_slots) +
+  return up(sizeof(Slot) * (uint64_t)max_slots) + 5 * up(sizeof(int2) * (uint64_t)btab_cap) +
+         up(sizeof(int) * 6 * (uint64_t)max_slots) + up(sizeof(SlotState) * (uint64_t)max_slots) +
          up(sizeof(int) * (uint64_t)max_slots) + up(sizeof(PQGlobal));
 }
 
@@ -1433,8 +1434,9 @@ extern "C" int32_t oscar_engine_create(int32_t max_slots, int32_t precision, voi
   e->d_btab2 = (int2 *)((char *)e->d_btab + up(sizeof(int2) * (uint64_t)btab_cap));
   e->d_btab_j = (int2 *)((char *)e->d_btab2 + up(sizeof(int2) * (uint64_t)btab_cap));
   e->d_btab_m = (int2 *)((char *)e->d_btab_j + up(sizeof(int2) * (uint64_t)btab_cap));
-  e->d_act = (int *)((char *)e->d_btab_m + up(sizeof(int2) * (uint64_t)btab_cap));
-  e->d_states = (SlotState *)((char *)e->d_act + up(sizeof(int) * 4 * (uint64_t)max_slots));
+  e->d_btab_live = (int2 *)((char *)e->d_btab_m + up(sizeof(int2) * (uint64_t)btab_cap));
+  e->d_act = (int *)((char *)e->d_btab_live + up(sizeof(int2) * (uint64_t)btab_cap));
+  e->d_states = (SlotState *)((char *)e->d_act + up(sizeof(int) * 6 * (uint64_t)max_slots));
   e->d_pq_list = (int *)((char *)e->d_states + up(sizeof(SlotState) * (uint64_t)max_slots));
   e->d_pq = (PQGlobal *)((char *)e->d_pq_list + up(sizeof(int) * (uint64_t)max_slots));
   e->heap_off = tb;
@@ -1853,10 +1855,50 @@ static int eng_tick(oscar_engine *e) {
     record_pred(gj, 2);
     return OSCAR_OK;
   };
+  // The batch of the multigrid slots whose solve has not converged at the
+  // last state read: a converged slot's launches would only return at once,
+  // so its workgroups are left out of the tables once any slot is done.
+  int n_live = -1;
+  auto live_batch = [&](MGBatch &Bl) -> int {
+    std::vector<int> live;
+    for (int i : gm)
+      if (!e->h_states[i].done) live.push_back(i);
+    if ((int)live.size() == n_live) return OSCAR_OK;   // the same slots as the current table
+    n_live = (int)live.size();
+    if (live.size() == gm.size() || live.empty()) {
+      Bl = B;
+      return OSCAR_OK;
+    }
+    e->bt_live.clear();
+    for (int i : live) append_segment(e->bt_live, i, e->slots[i].g.nblocks);
+    EHIP(e, hipMemcpyAsync(e->d_btab_live, e->bt_live.data(), sizeof(int2) * e->bt_live.size(),
+                           hipMemcpyHostToDevice, e->stream));
+    Bl = B;
+    Bl.btab = e->d_btab_live;
+    Bl.nblocks = (int)e->bt_live.size();
+    e->act_live.assign(2 * (size_t)e->max_slots, 0);
+    for (int di = 0; di < 2; ++di) {
+      std::vector<const Slot *> hs;
+      for (int i : live)
+        if (e->slots[i].D.dim == di + 2) {
+          e->act_live[(size_t)di * e->max_slots + hs.size()] = i;
+          hs.push_back(&e->slots[i].s);
+        }
+      Bl.dim[di].act = e->d_act + (size_t)(4 + di) * e->max_slots;
+      mg_batch_levels(Bl.dim[di], hs.data(), (int)hs.size(), di + 2);
+    }
+    EHIP(e, hipMemcpyAsync(e->d_act + (size_t)4 * e->max_slots, e->act_live.data(), sizeof(int) * e->act_live.size(),
+                           hipMemcpyHostToDevice, e->stream));
+    return OSCAR_OK;
+  };
   // one inner solve of the multigrid group: the initial cycle, then chunks
   // ending with a search-direction launch (the convergence test)
   auto inner_m = [&]() -> int {
-    for (int part = 0; part < 3; ++part) launch_mg_cycle_part_b<R>(B, -1, part);
+    MGBatch Bl = B;
+    n_live = -1;
+    int r2 = live_batch(Bl);
+    if (r2) return r2;
+    for (int part = 0; part < 3; ++part) launch_mg_cycle_part_b<R>(Bl, -1, part);
     EHIP(e, hipGetLastError());
     int next = 0;
     bool tail = false;
@@ -1866,13 +1908,15 @@ static int eng_tick(oscar_engine *e) {
       if (next > max_it + 1) { e->err = "conjugate gradient did not terminate"; return OSCAR_E_HIP; }
       for (int x = 0; x < chunk; ++x) {
         if (tail)
-          for (int part = 0; part < 3; ++part) launch_mg_cycle_part_b<R>(B, next - 1, part);
-        launch_mg_dir_b<R>(B, next);
+          for (int part = 0; part < 3; ++part) launch_mg_cycle_part_b<R>(Bl, next - 1, part);
+        launch_mg_dir_b<R>(Bl, next);
         ++next;
         tail = true;
       }
       EHIP(e, hipGetLastError());
-      int r2 = eng_read_states(e);
+      r2 = eng_read_states(e);
+      if (r2) return r2;
+      r2 = live_batch(Bl);
       if (r2) return r2;
       chunk = 2;
     }
