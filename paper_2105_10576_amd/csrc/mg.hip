@@ -1371,60 +1371,80 @@ __device__ __forceinline__ bool mg_fine_down_body(const Slot &s, int lb, int it,
 // Rows and chunks outside the grid read the nearest in-grid ones (only
 // faces that are not interior see them).
 typedef float f2v __attribute__((ext_vector_type(2)));
+typedef double d2v __attribute__((ext_vector_type(2)));
+template <typename T>
+struct PairOf;   // two elements of T as one vector (an x pair of cells)
+template <>
+struct PairOf<float> {
+  typedef f2v type;
+};
+template <>
+struct PairOf<double> {
+  typedef d2v type;
+};
 
-// store the fluid cells of an x pair (one 8-byte store when both are fluid)
-__device__ __forceinline__ void sto_pair(float *base, unsigned off, bool fa, bool fb, float a, float b) {
+// store the fluid cells of an x pair (one store when both are fluid)
+template <typename T>
+__device__ __forceinline__ void sto_pair(T *base, unsigned off, bool fa, bool fb, T a, T b) {
+  typedef typename PairOf<T>::type P2;
   if (fa && fb) {
-    f2v v;
+    P2 v;
     v.x = a;
     v.y = b;
-    sto((f2v *)base, off, v);
+    sto((P2 *)base, off, v);
   } else {
     if (fa) sto(base, off, a);
-    if (fb) sto(base, off + 4u, b);
+    if (fb) sto(base, off + (unsigned)sizeof(T), b);
   }
 }
 
 constexpr int BRX = 32, BRY = 8, BRZ = 4;
-constexpr int BRP = BRX + 8;                    // LDS row pitch (floats)
+constexpr int BRP = BRX + 8;                    // LDS row pitch (elements: x0 - 4 .. x0 + 35)
 constexpr int BRROWS = (BRY + 2) * (BRZ + 2);   // halo rows
-constexpr int BRH = BRROWS * BRP;               // floats per staged array
-constexpr int BRCH = BRROWS * (BRP / 4);        // 16-byte chunks per staged array
+constexpr int BRH = BRROWS * BRP;               // elements per staged array
 static_assert(BRX * BRY * BRZ == 4 * BLOCK, "four cells per thread");
+template <typename T>
+constexpr int BRCW = 16 / (int)sizeof(T);       // elements per 16-byte chunk
+template <typename T>
+constexpr int BRCH = BRROWS * (BRP / BRCW<T>);  // 16-byte chunks per staged array
 
-__host__ __device__ inline bool brick_ok(int dim, int nx, int ny, int nz, int precision) {
-  return dim == 3 && precision != 0 && nx % BRX == 0 && ny % BRY == 0 && nz % BRZ == 0 &&
-         (long long)nx * ny * nz >= WALK_MIN;
+// 3D grids of at least WALK_MIN cells whose dimensions are multiples of the brick
+__host__ __device__ inline bool brick_ok(int dim, int nx, int ny, int nz) {
+  return dim == 3 && nx % BRX == 0 && ny % BRY == 0 && nz % BRZ == 0 && (long long)nx * ny * nz >= WALK_MIN;
 }
 
-// Chunk c of the halo brick (row c / 10 of the (BRY + 2) x (BRZ + 2) halo
-// rows, 16-byte chunk c % 10 from x0 - 4), clamped into the grid: its
-// element offset.
+// Chunk c of the halo brick (row c / (BRP / BRCW) of the (BRY + 2) x
+// (BRZ + 2) halo rows, 16-byte chunk c % (BRP / BRCW) from x0 - 4), clamped
+// into the grid: its element offset.
+template <typename T>
 __device__ __forceinline__ unsigned brick_chunk(const Grid &G, int c, int x0, int y0, int z0) {
-  const int row = c / (BRP / 4), ch = c - row * (BRP / 4);
+  constexpr int W = BRCW<T>, PER = BRP / W;
+  const int row = c / PER, ch = c - row * PER;
   const int zz = row / (BRY + 2), yy = row - zz * (BRY + 2);
-  int y = y0 - 1 + yy, z = z0 - 1 + zz, x = x0 - 4 + 4 * ch;
+  int y = y0 - 1 + yy, z = z0 - 1 + zz, x = x0 - 4 + W * ch;
   y = y < 0 ? 0 : (y >= G.ny ? G.ny - 1 : y);
   z = z < 0 ? 0 : (z >= G.nz ? G.nz - 1 : z);
-  x = x < 0 ? 0 : (x > G.nx - 4 ? G.nx - 4 : x);
+  x = x < 0 ? 0 : (x > G.nx - W ? G.nx - W : x);
   return (unsigned)x + (unsigned)G.nx * ((unsigned)y + (unsigned)G.ny * (unsigned)z);
 }
 
-constexpr int BRM = (BRCH + BLOCK - 1) / BLOCK;   // chunk rounds of a workgroup
+template <typename T>
+constexpr int BRM = (BRCH<T> + BLOCK - 1) / BLOCK;   // chunk rounds of a workgroup
 
-// stage the halo brick of one array to LDS (chunk c at float offset 4 c;
-// wavefront-uniform LDS bases), skipping the chunks whose four cells are
-// all solid (need[m] false): solid cells' values are never read
-__device__ __forceinline__ void brick_stage(const float *src, float *lds, const unsigned (&off)[BRM],
-                                            const bool (&need)[BRM]) {
+// stage the halo brick of one array to LDS (chunk c at byte 16 c;
+// wavefront-uniform LDS bases), skipping the chunks whose cells are all
+// solid (need[m] false): solid cells' values are never read
+template <typename T>
+__device__ __forceinline__ void brick_stage(const T *src, T *lds, const unsigned (&off)[BRM<T>],
+                                            const bool (&need)[BRM<T>]) {
   const int wave = (int)threadIdx.x >> 6, lane = (int)threadIdx.x & 63;
 #pragma unroll
-  for (int m = 0; m < BRM; ++m) {
+  for (int m = 0; m < BRM<T>; ++m) {
     const int c = m * BLOCK + wave * 64 + lane;
-    if (m * BLOCK + wave * 64 < BRCH && c < BRCH && need[m])
-      __builtin_amdgcn_global_load_lds((const OSCAR_GLOBAL void *)(src + off[m]),
-                                       (__attribute__((address_space(3))) void *)(lds + 4 * (m * BLOCK + wave * 64)),
-                                       16, 0, 0);
+    if (m * BLOCK + wave * 64 < BRCH<T> && c < BRCH<T> && need[m])
+      __builtin_amdgcn_global_load_lds(
+          (const OSCAR_GLOBAL void *)(src + off[m]),
+          (__attribute__((address_space(3))) void *)(lds + BRCW<T> * (m * BLOCK + wave * 64)), 16, 0, 0);
   }
 }
 
@@ -1461,8 +1481,8 @@ __device__ __forceinline__ BrickWalk brick_walk(int lb, int nblocks, int nbx, in
 }
 
 // (false: the solve had converged before the launch; nothing was written)
-__device__ __forceinline__ bool mg_fine_down_brick(const Slot &s, int lb, int it) {
-  using T = float;
+template <typename T>
+__device__ __forceinline__ bool mg_fine_down_brick(const Slot &s, int lb, int it, int mode) {
   const Grid G = grid_of(s);
   SlotState *st = s.st;
   const int done = st->done;   // converged before this launch (tested once the first brick is in flight)
@@ -1474,15 +1494,18 @@ __device__ __forceinline__ bool mg_fine_down_brick(const Slot &s, int lb, int it
   T *r1 = upd && !(it & 1) ? cr1 : cr0;
   const T *d = upd && (it & 1) ? (const T *)s.cs[1] : (const T *)s.cs[0], *q = upd ? (const T *)s.cp : r0;
   T *z0 = (T *)s.cw[1];
-  T *xv = (T *)s.e;
+  // the unknown the iterations update (as in the single-cell kernel)
+  T *xv = sizeof(T) == 4 ? (T *)s.e : (T *)(mode ? s.p_cr : s.p_vd);
   const int cnx = s.mg.lv[1].nx, cny = s.mg.lv[1].ny;
   T *b1 = (T *)s.mg.lv[1].b;
   const uint8_t *flags = s.flags;
   const T w = (T)MG_OMEGA_FINE;
-  __shared__ __align__(16) float sr[BRH];
-  __shared__ __align__(16) float sq[BRH];
-  __shared__ __align__(16) float si[BRH];
-  __shared__ __align__(16) float sa[BRH];
+  typedef typename PairOf<T>::type P2;
+  constexpr int NM = BRM<T>;
+  __shared__ __align__(16) T sr[BRH];
+  __shared__ __align__(16) T sq[BRH];
+  __shared__ __align__(16) T si[BRH];
+  __shared__ __align__(16) T sa[BRH];
   const int nbx = G.nx / BRX, nby = G.ny / BRY, nbz = G.nz / BRZ;
   const BrickWalk wk = brick_walk(lb, G.nblocks, nbx, nby, nbz);
   const int tid = (int)threadIdx.x;
@@ -1495,26 +1518,24 @@ __device__ __forceinline__ bool mg_fine_down_brick(const Slot &s, int lb, int it
     y0 = by * BRY;
     z0b = bz * BRZ;
   };
-  // the brick's chunks: their offsets, and the flags of their four cells
-  // (one 4-byte load each) to skip the all-solid ones
+  // the brick's chunks: their offsets, and the flags of their cells (one
+  // load of four or two flag bytes each) to skip the all-solid ones
   auto stage = [&](int b) {
     int x0, y0, z0b;
     origin(b, x0, y0, z0b);
-    unsigned off[BRM];
-    unsigned f4[BRM];
+    unsigned off[NM];
+    bool need[NM];
 #pragma unroll
-    for (int m = 0; m < BRM; ++m) {
+    for (int m = 0; m < NM; ++m) {
       const int c = m * BLOCK + tid;
-      off[m] = brick_chunk(G, c < BRCH ? c : 0, x0, y0, z0b);
-      f4[m] = ldo((const uint32_t *)flags, off[m]);
+      off[m] = brick_chunk<T>(G, c < BRCH<T> ? c : 0, x0, y0, z0b);
+      if constexpr (BRCW<T> == 4) need[m] = (ldo((const uint32_t *)flags, off[m]) & 0x40404040u) != 0x40404040u;
+      else need[m] = (ldo((const uint16_t *)flags, off[m]) & 0x4040u) != 0x4040u;
     }
-    bool need[BRM];
-#pragma unroll
-    for (int m = 0; m < BRM; ++m) need[m] = (f4[m] & 0x40404040u) != 0x40404040u;
-    brick_stage(r0, sr, off, need);
-    brick_stage(q, sq, off, need);
-    brick_stage(invD, si, off, need);
-    brick_stage(rAU, sa, off, need);
+    brick_stage<T>(r0, sr, off, need);
+    brick_stage<T>(q, sq, off, need);
+    brick_stage<T>(invD, si, off, need);
+    brick_stage<T>(rAU, sa, off, need);
   };
   if (wk.first < wk.end) stage(wk.first);
   if (done) {   // uniform; no LDS transfer may outlive the workgroup
@@ -1542,8 +1563,9 @@ __device__ __forceinline__ bool mg_fine_down_brick(const Slot &s, int lb, int it
     const int P0 = gi + G.nx * (gj + G.ny * gk), P1 = P0 + G.nx;
     const unsigned fl0 = (unsigned)ldo((const uint16_t *)flags, (unsigned)P0);
     const unsigned fl1 = (unsigned)ldo((const uint16_t *)flags, (unsigned)P1);
-    const f2v d0 = ldo((const f2v *)d, (unsigned)P0 * 4u), d1 = ldo((const f2v *)d, (unsigned)P1 * 4u);
-    const f2v xo0 = ldo((const f2v *)xv, (unsigned)P0 * 4u), xo1 = ldo((const f2v *)xv, (unsigned)P1 * 4u);
+    constexpr unsigned WB = (unsigned)sizeof(T);
+    const P2 d0 = ldo((const P2 *)d, (unsigned)P0 * WB), d1 = ldo((const P2 *)d, (unsigned)P1 * WB);
+    const P2 xo0 = ldo((const P2 *)xv, (unsigned)P0 * WB), xo1 = ldo((const P2 *)xv, (unsigned)P1 * WB);
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     T tv[2][2];
@@ -1579,17 +1601,17 @@ __device__ __forceinline__ bool mg_fine_down_brick(const Slot &s, int lb, int it
         const T Az = matvec_pre<T>(G, c, f8, zc, sa[L], xn, ran);
         zz[xk] = zc;
         rnv[xk] = rn;
-        const f2v dd = yk ? d1 : d0;
-        const f2v xo = yk ? xo1 : xo0;
+        const P2 dd = yk ? d1 : d0;
+        const P2 xo = yk ? xo1 : xo0;
         xn2[xk] = (xk ? xo.y : xo.x) + al * (xk ? dd.y : dd.x);
         tv[yk][xk] = rn - Az;
       }
-      const unsigned o = (unsigned)(yk ? P1 : P0) * 4u;
+      const unsigned o = (unsigned)(yk ? P1 : P0) * WB;
       if (upd) {
-        sto_pair(xv, o, fl[0], fl[1], xn2[0], xn2[1]);
-        sto_pair(r1, o, fl[0], fl[1], rnv[0], rnv[1]);
+        sto_pair<T>(xv, o, fl[0], fl[1], xn2[0], xn2[1]);
+        sto_pair<T>(r1, o, fl[0], fl[1], rnv[0], rnv[1]);
       }
-      sto_pair(z0, o, fl[0], fl[1], zz[0], zz[1]);
+      sto_pair<T>(z0, o, fl[0], fl[1], zz[0], zz[1]);
     }
     // children of the parent: x pairs, then y, then z across the lane pair
     T v = (tv[0][0] + tv[0][1]) + (tv[1][0] + tv[1][1]);
@@ -1601,9 +1623,11 @@ __device__ __forceinline__ bool mg_fine_down_brick(const Slot &s, int lb, int it
   return true;
 }
 
-// (four wavefronts per SIMD: 128 registers; the LDS of four workgroups fits)
-__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4)))
-k_mg_fine_down_brick(const Slot S, int it, unsigned long long *ts) {
+// (FP32: four wavefronts per SIMD, 128 registers, the LDS of four
+// workgroups fits; FP64: the 77 KB of two workgroups per CU)
+template <typename T>
+__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2)))
+k_mg_fine_down_brick(const Slot S, int it, int mode, unsigned long long *ts) {
   OSCAR_PRIME("s"(ts), "s"(S.st), "s"(S.flags), "s"(S.part), "s"(S.rAU), "s"(S.invD), "s"(S.cr[0]), "s"(S.cr[1]),
               "s"(S.cs[0]), "s"(S.cs[1]), "s"(S.cp), "s"(S.cw[1]), "s"(S.e), "s"(S.nblocks), "s"(S.nx), "s"(S.ny));
   OSCAR_PRIME("s"(S.nz), "s"(S.nxy), "s"(S.outlet), "s"(S.Sh), "s"(S.S2h), "s"(S.mg.lv[1].nx), "s"(S.mg.lv[1].ny),
@@ -1611,7 +1635,7 @@ k_mg_fine_down_brick(const Slot S, int it, unsigned long long *ts) {
   Stamp stamp(ts);
   const int lb = xcd_block(blockIdx.x, S.nblocks);
   if (lb < 0) return;
-  if (mg_fine_down_brick(S, lb, it)) stamp.done();
+  if (mg_fine_down_brick<T>(S, lb, it, mode)) stamp.done();
 }
 
 template <typename R, int NB>
@@ -2098,8 +2122,8 @@ template <typename R>
 void launch_mg_cycle_part(const Slot &hs, const Launch &L, int it, int part, int mode, unsigned long long *ts) {
   const dim3 fg((unsigned)L.nblocks), fb(BLOCK);
   if (part == 0) {
-    if (sizeof(R) == 4 && brick_ok(hs.dim, hs.nx, hs.ny, hs.nz, hs.precision))
-      hipLaunchKernelGGL(k_mg_fine_down_brick, fg, fb, 0, L.stream, hs, it, ts);
+    if (brick_ok(hs.dim, hs.nx, hs.ny, hs.nz))
+      hipLaunchKernelGGL(k_mg_fine_down_brick<R>, fg, fb, 0, L.stream, hs, it, mode, ts);
     else hipLaunchKernelGGL((k_mg_fine_down<R, FINE_NB<R>>), fg, fb, 0, L.stream, hs, it, mode, ts);
   } else if (part == 1) {
     if (hs.dim == 3) vcycle_levels<3, R>(hs, L, ts);
