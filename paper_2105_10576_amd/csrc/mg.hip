@@ -137,6 +137,41 @@ __device__ __forceinline__ LCell lcell(int nx, int ny, int g) {
   return c;
 }
 
+// Index arithmetic on the tail levels (at most MG_TAIL_CELLS cells, far
+// below 2^24): a quotient by d from the float reciprocal of d, exact up to
+// one for any dividend below 2^24 (the product's relative error is a few
+// units of 2^-24), corrected by the sign and size of the remainder, and
+// products by 24-bit multiplies.  Both are full-rate VALU operations where
+// 32-bit division and multiplication take sequences of quarter-rate ones.
+struct Div24 {
+  float r;      // 1 / d
+  unsigned d;   // the divisor, 1 <= d < 2^24
+};
+__device__ __forceinline__ Div24 div24(int d) {
+  Div24 q;
+  q.d = (unsigned)d;
+  q.r = 1.0f / (float)d;
+  return q;
+}
+__device__ __forceinline__ unsigned quot24(unsigned g, const Div24 &D) {
+  unsigned q = (unsigned)((float)g * D.r);
+  const int r = (int)(g - __umul24(q, D.d));
+  if (r < 0) q -= 1u;
+  else if (r >= (int)D.d) q += 1u;
+  return q;
+}
+// lcell on a tail level (DX, DY: the divisors nx and ny)
+__device__ __forceinline__ LCell lcell24(const Div24 &DX, const Div24 &DY, int g) {
+  LCell c;
+  const unsigned ug = (unsigned)g, row = quot24(ug, DX);
+  c.P = g;
+  c.i = (int)(ug - __umul24(row, DX.d));
+  const unsigned k = quot24(row, DY);
+  c.j = (int)(row - __umul24(k, DY.d));
+  c.k = (int)k;
+  return c;
+}
+
 // (A x)_P on a coarse level, unrolled over the DIM directions.  xv(n, e,
 // side) returns x at cell n: the neighbour across the low (side = -1) or
 // high (+1) face of direction e, or the cell itself (side = 0), which is
@@ -231,6 +266,29 @@ __device__ __forceinline__ Kid kid_at(unsigned tau, int dim, int nx, int ny, int
   q.valid = pin && q.i < nx && q.j < ny && q.k < nz;
   q.P = q.i + nx * (q.j + ny * q.k);
   q.parent = ci + cnx * ((int)cj + cny * (int)ck);
+  q.lead = pin && (xr & 1u) == 0u && jy == 0u && kz == 0u;
+  return q;
+}
+
+// kid_at on a tail level (DNB: the divisor ceil(cnx / kid_px), DCY: cny)
+__device__ __forceinline__ Kid kid_at_tail(unsigned tau, int dim, int nx, int ny, int nz, int cnx, int cny,
+                                           const Div24 &DNB, const Div24 &DCY) {
+  Kid q;
+  const unsigned l = tau & 63u, w = tau >> 6;
+  const unsigned px = kid_px(dim);
+  const unsigned row = quot24(w, DNB), bx = w - __umul24(row, DNB.d);
+  const unsigned ck = dim == 3 ? quot24(row, DCY) : 0u, cj = row - __umul24(ck, DCY.d);
+  const unsigned xr = dim == 3 ? (l & 15u) : (l & 31u);
+  const unsigned jy = dim == 3 ? ((l >> 4) & 1u) : (l >> 5);
+  const unsigned kz = dim == 3 ? (l >> 5) : 0u;
+  const int ci = (int)(__umul24(bx, px) + (xr >> 1));
+  const bool pin = ci < cnx;
+  q.i = (int)(2u * __umul24(bx, px) + xr);
+  q.j = 2 * (int)cj + (int)jy;
+  q.k = 2 * (int)ck + (int)kz;
+  q.valid = pin && q.i < nx && q.j < ny && q.k < nz;
+  q.P = q.i + (int)__umul24((unsigned)nx, (unsigned)(q.j + (int)__umul24((unsigned)ny, (unsigned)q.k)));
+  q.parent = ci + (int)__umul24((unsigned)cnx, cj + __umul24((unsigned)cny, ck));
   q.lead = pin && (xr & 1u) == 0u && jy == 0u && kz == 0u;
   return q;
 }
@@ -731,16 +789,28 @@ __device__ __forceinline__ void split_up_second(const LV<T> &L, const T *y1in, T
 //
 // Pre-smoothing of an LDS level: nu Jacobi sweeps from zero into x (t as
 // scratch), then the residual b - A x restricted into bnext in tile order.
+// The first sweep from zero, w D^-1 b, is evaluated where the second one
+// reads it (its value at the cell and the neighbours, as the grid-wide
+// kernels do), so the two take one pass and one barrier.
 template <int DIM, typename T>
 __device__ __forceinline__ void tail_down(const LV<T> &L, int cnx, int cny, int cnz, T *bnext, int t0, int ns,
                                           int nu) {
   const T w = (T)MG_OMEGA;
-  for (int g = t0; g < L.nc; g += ns) L.x[g] = w * (L.invD[g] * L.b[g]);
+  const Div24 DX = div24(L.nx), DY = div24(L.ny);
+  auto x1 = [&](int n, int, int) -> T { return w * (L.invD[n] * L.b[n]); };
+  if (nu >= 2) {
+    for (int g = t0; g < L.nc; g += ns) {
+      const LCell c = lcell24(DX, DY, g);
+      L.x[g] = x1(g, 0, 0) + w * (L.invD[g] * (L.b[g] - lmatvec<DIM, T>(L, c, x1)));
+    }
+  } else {
+    for (int g = t0; g < L.nc; g += ns) L.x[g] = x1(g, 0, 0);
+  }
   __syncthreads();
   T *src = L.x, *dst = L.t;
-  for (int m = 1; m < nu; ++m) {
+  for (int m = 2; m < nu; ++m) {
     for (int g = t0; g < L.nc; g += ns) {
-      const LCell c = lcell(L.nx, L.ny, g);
+      const LCell c = lcell24(DX, DY, g);
       auto xs = [&](int n, int, int) -> T { return src[n]; };
       dst[g] = src[g] + w * (L.invD[g] * (L.b[g] - lmatvec<DIM, T>(L, c, xs)));
     }
@@ -750,8 +820,9 @@ __device__ __forceinline__ void tail_down(const LV<T> &L, int cnx, int cny, int 
     dst = tmp;
   }
   const unsigned total = kid_total(DIM, cnx, cny, cnz);
+  const Div24 DNB = div24((int)(((unsigned)cnx + kid_px(DIM) - 1u) / kid_px(DIM))), DCY = div24(cny);
   for (unsigned tau = (unsigned)t0; tau < total; tau += (unsigned)ns) {
-    const Kid q = kid_at(tau, DIM, L.nx, L.ny, L.nz, cnx, cny);
+    const Kid q = kid_at_tail(tau, DIM, L.nx, L.ny, L.nz, cnx, cny, DNB, DCY);
     T tv = (T)0;
     if (q.valid) {
       LCell c;
@@ -775,9 +846,13 @@ template <int DIM, typename T>
 __device__ __forceinline__ const T *tail_up(const LV<T> &L, int cnx, int cnxy, const T *xc, int t0, int ns, int nu) {
   const T w = (T)MG_OMEGA;
   const int st[3] = {1, L.nx, L.nxy};
+  const Div24 DX = div24(L.nx), DY = div24(L.ny);
   for (int g = t0; g < L.nc; g += ns) {
-    const LCell c = lcell(L.nx, L.ny, g);
-    auto y0at = [&](const LCell &p) -> T { return L.x[p.P] + xc[(p.i >> 1) + cnx * (p.j >> 1) + cnxy * (p.k >> 1)]; };
+    const LCell c = lcell24(DX, DY, g);
+    auto y0at = [&](const LCell &p) -> T {
+      return L.x[p.P] + xc[(p.i >> 1) + (int)__umul24((unsigned)cnx, (unsigned)(p.j >> 1)) +
+                           (int)__umul24((unsigned)cnxy, (unsigned)(p.k >> 1))];
+    };
     auto y0 = [&](int, int e, int side) -> T { return y0at(lshift(c, e, side, st)); };
     L.t[g] = y0at(c) + w * (L.invD[g] * (L.b[g] - lmatvec<DIM, T>(L, c, y0)));
   }
@@ -785,7 +860,7 @@ __device__ __forceinline__ const T *tail_up(const LV<T> &L, int cnx, int cnxy, c
   T *src = L.t, *dst = L.x;
   for (int m = 1; m < nu; ++m) {
     for (int g = t0; g < L.nc; g += ns) {
-      const LCell c = lcell(L.nx, L.ny, g);
+      const LCell c = lcell24(DX, DY, g);
       auto ys = [&](int n, int, int) -> T { return src[n]; };
       dst[g] = src[g] + w * (L.invD[g] * (L.b[g] - lmatvec<DIM, T>(L, c, ys)));
     }
@@ -956,10 +1031,8 @@ __device__ __forceinline__ bool mg_tail_body(const Slot &s, uint4 *mg_lds, int t
     for (int x0 = t0; x0 < n16; x0 += U * ns) {
       v4u v[U];
 #pragma unroll
-      for (int u = 0; u < U; ++u) {   // past the end: reload the first entry (always in the block)
-        const int x = x0 + u * ns;
-        v[u] = src[x < n16 ? x : 0];
-      }
+      for (int u = 0; u < U; ++u)   // lanes past the end load nothing (a wavefront past it skips the load)
+        if (x0 + u * ns < n16) v[u] = src[x0 + u * ns];
 #pragma unroll
       for (int u = 0; u < U; ++u)
         if (x0 + u * ns < n16) dst[x0 + u * ns] = v[u];
