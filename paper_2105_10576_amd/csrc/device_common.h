@@ -302,16 +302,62 @@ struct Stamp {
 // deterministic per-slot reductions
 // ---------------------------------------------------------------------------
 
+// Lane exchanges within a wavefront whose lanes are all active, as VALU
+// operations rather than round trips through the LDS crossbar
+// (ds_bpermute): a DPP quad permutation (lane l ^ 1), DPP row shifts (lane
+// l + n of l's 16-lane row, 0 past the row's end) and the gfx950 swaps of
+// odd with even rows (lane l ^ 16) and of the two halves (lane l ^ 32).
+__device__ __forceinline__ unsigned lane_x1(unsigned u) {
+  return (unsigned)__builtin_amdgcn_mov_dpp((int)u, 0xB1, 0xF, 0xF, true);   // quad_perm [1, 0, 3, 2]
+}
+__device__ __forceinline__ unsigned lane_x16(unsigned u) {
+  const auto s = __builtin_amdgcn_permlane16_swap(u, u, false, false);
+  return (__lane_id() & 16u) ? s[0] : s[1];
+}
+__device__ __forceinline__ unsigned lane_x32(unsigned u) {
+  const auto s = __builtin_amdgcn_permlane32_swap(u, u, false, false);
+  return (__lane_id() & 32u) ? s[0] : s[1];
+}
+template <int N>
+__device__ __forceinline__ unsigned lane_shl(unsigned u) {
+  return (unsigned)__builtin_amdgcn_update_dpp(0, (int)u, 0x100 + N, 0xF, 0xF, true);   // row_shl:N
+}
+// one of the exchanges above applied to a float or a double (by halves)
+template <class F>
+__device__ __forceinline__ float lane_move(float v, F &&f) {
+  return __uint_as_float(f(__float_as_uint(v)));
+}
+template <class F>
+__device__ __forceinline__ double lane_move(double v, F &&f) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = f((unsigned)b), hi = f((unsigned)(b >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+// the value of lane l + off for the lanes l < off that a reduction tree
+// uses next (off = 32, 16: the partner l ^ off; 8, 4, 2, 1: the row shift)
+template <int OFF, typename T>
+__device__ __forceinline__ T lane_down(T v) {
+  if constexpr (OFF == 32) return lane_move(v, lane_x32);
+  else if constexpr (OFF == 16) return lane_move(v, lane_x16);
+  else return lane_move(v, lane_shl<OFF>);
+}
+
+// Wavefront reduction: lane 0 receives the total of the tree that adds lanes
+// l and l + off for off = 32, 16, ..., 1 (max for the MAXMASK values).
 template <unsigned MAXMASK, int M>
 __device__ __forceinline__ void wave_reduce(double (&v)[M]) {
 #pragma unroll
   for (int m = 0; m < M; ++m) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-      double o = __shfl_down(v[m], off, 64);
+    auto step = [&](double o) {
       if ((MAXMASK >> m) & 1u) v[m] = o > v[m] ? o : v[m];
       else v[m] = v[m] + o;
-    }
+    };
+    step(lane_down<32>(v[m]));
+    step(lane_down<16>(v[m]));
+    step(lane_down<8>(v[m]));
+    step(lane_down<4>(v[m]));
+    step(lane_down<2>(v[m]));
+    step(lane_down<1>(v[m]));
   }
 }
 

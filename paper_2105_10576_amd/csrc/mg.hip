@@ -297,12 +297,12 @@ __device__ __forceinline__ Kid kid_at_tail(unsigned tau, int dim, int nx, int ny
 // every lane of the wavefront must call it
 template <typename T>
 __device__ __forceinline__ T kid_sum(T v, int dim) {
-  v = v + __shfl_xor(v, 1, 64);
+  v = v + lane_move(v, lane_x1);
   if (dim == 3) {
-    v = v + __shfl_xor(v, 16, 64);
-    v = v + __shfl_xor(v, 32, 64);
+    v = v + lane_move(v, lane_x16);
+    v = v + lane_move(v, lane_x32);
   } else {
-    v = v + __shfl_xor(v, 32, 64);
+    v = v + lane_move(v, lane_x32);
   }
   return v;
 }
@@ -1688,7 +1688,7 @@ __device__ __forceinline__ bool mg_fine_down_brick(const Slot &s, int lb, int it
     }
     // children of the parent: x pairs, then y, then z across the lane pair
     T v = (tv[0][0] + tv[0][1]) + (tv[1][0] + tv[1][1]);
-    v = v + __shfl_xor(v, 1, 64);
+    v = v + lane_move(v, lane_x1);
     if (h == 0) b1[(gi >> 1) + cnx * ((gj >> 1) + cny * (gk >> 1))] = v;
     __syncthreads();   // every wavefront is done with the LDS: stage the next brick
     if (b + wk.stride < wk.end) stage(b + wk.stride);
