@@ -151,8 +151,16 @@ void layout(const oscar_desc &D, Carver &cv, Slot *s, bool ctl_block) {
     for (int l = mg.tail; l <= mg.L; ++l) {
       MGLevel &v = mg.lv[l];
       for (int e = 0; e < d; ++e) v.cf[e] = part(v.nc);
-      void **arr[] = {&v.cout, &v.invD, &v.b, &v.x, &v.t};
-      for (void **p : arr) *p = part(v.nc);
+      v.cout = part(v.nc);
+      v.invD = part(v.nc);
+    }
+    mg.lv[mg.tail].b = part(mg.lv[mg.tail].nc);
+    mg.tail_load = (int32_t)((at + 15) / 16 * 16);
+    for (int l = mg.tail; l <= mg.L; ++l) {
+      MGLevel &v = mg.lv[l];
+      if (l > mg.tail) v.b = part(v.nc);
+      v.x = part(v.nc);
+      v.t = part(v.nc);
     }
   }
   s->part = (double *)cv.take(8ull * NCH * NVAL * g.nblocks);

@@ -841,12 +841,16 @@ __device__ __forceinline__ void tail_down(const LV<T> &L, int cnx, int cny, int 
 
 // Prolongation and post-smoothing of an LDS level: y = x + P xc, then nu
 // Jacobi sweeps alternating between t and x (x is free once the first sweep
-// has read it); returns the array holding the result.
+// has read it); returns the array holding the result.  With out (an array
+// that none of the level's arrays aliases), the last sweep writes there
+// instead, and no barrier follows it (out is returned).
 template <int DIM, typename T>
-__device__ __forceinline__ const T *tail_up(const LV<T> &L, int cnx, int cnxy, const T *xc, int t0, int ns, int nu) {
+__device__ __forceinline__ const T *tail_up(const LV<T> &L, int cnx, int cnxy, const T *xc, int t0, int ns, int nu,
+                                            T *out = nullptr) {
   const T w = (T)MG_OMEGA;
   const int st[3] = {1, L.nx, L.nxy};
   const Div24 DX = div24(L.nx), DY = div24(L.ny);
+  T *first = nu == 1 && out ? out : L.t;
   for (int g = t0; g < L.nc; g += ns) {
     const LCell c = lcell24(DX, DY, g);
     auto y0at = [&](const LCell &p) -> T {
@@ -854,16 +858,20 @@ __device__ __forceinline__ const T *tail_up(const LV<T> &L, int cnx, int cnxy, c
                            (int)__umul24((unsigned)cnxy, (unsigned)(p.k >> 1))];
     };
     auto y0 = [&](int, int e, int side) -> T { return y0at(lshift(c, e, side, st)); };
-    L.t[g] = y0at(c) + w * (L.invD[g] * (L.b[g] - lmatvec<DIM, T>(L, c, y0)));
+    first[g] = y0at(c) + w * (L.invD[g] * (L.b[g] - lmatvec<DIM, T>(L, c, y0)));
   }
+  if (first == out) return out;
   __syncthreads();
   T *src = L.t, *dst = L.x;
   for (int m = 1; m < nu; ++m) {
+    const bool last = m == nu - 1 && out;
+    T *to = last ? out : dst;
     for (int g = t0; g < L.nc; g += ns) {
       const LCell c = lcell24(DX, DY, g);
       auto ys = [&](int n, int, int) -> T { return src[n]; };
-      dst[g] = src[g] + w * (L.invD[g] * (L.b[g] - lmatvec<DIM, T>(L, c, ys)));
+      to[g] = src[g] + w * (L.invD[g] * (L.b[g] - lmatvec<DIM, T>(L, c, ys)));
     }
+    if (last) return out;
     __syncthreads();
     T *tmp = src;
     src = dst;
@@ -1008,14 +1016,16 @@ __global__ void __launch_bounds__(BLOCK) k_mg_up_b(const Slot *slots, const int 
 }
 
 // Levels tail..L in one workgroup of ns threads, out of LDS.  The tail block
-// (the dense inverse of the coarsest operator, then per level the face and
-// outlet coefficients, inverse diagonal, b, x and t) is copied into LDS with
-// one round of 16-byte loads, which brings in the coefficients and the tail
-// level's right-hand side; the down-sweep to the coarsest level, its solve
-// with the dense inverse and the up-sweep then touch LDS only, and the final
-// correction of the tail level goes back to global memory for the next finer
-// level's prolongation.  Without IN_LDS the same steps run on the block in
-// global memory (the persistent solve, when the block exceeds its LDS).
+// is laid out in LDS as in global memory; its first part (the dense inverse
+// of the coarsest operator, per level the face and outlet coefficients and
+// inverse diagonal, and the tail level's right-hand side) is copied into LDS
+// with one round of 16-byte loads, the rest (the arrays the tail writes
+// before it reads them) is not.  The down-sweep to the coarsest level, its
+// solve with the dense inverse and the up-sweep then touch LDS only, and the
+// tail level's last sweep writes its correction to global memory for the
+// next finer level's prolongation.  Without IN_LDS the same steps run on
+// the block in global memory (the persistent solve, when the block exceeds
+// its LDS).
 // (done: the solve had converged before the launch; nothing is written to
 // global memory, tested once the block's loads are in; returns !done)
 template <int DIM, typename T, bool IN_LDS>
@@ -1027,7 +1037,7 @@ __device__ __forceinline__ bool mg_tail_body(const Slot &s, uint4 *mg_lds, int t
     typedef unsigned v4u __attribute__((ext_vector_type(4)));
     const OSCAR_GLOBAL v4u *src = (const OSCAR_GLOBAL v4u *)gbase;
     v4u *dst = (v4u *)mg_lds;
-    const int n16 = s.mg.tail_bytes >> 4;
+    const int n16 = s.mg.tail_load >> 4;   // the arrays read before they are written
     for (int x0 = t0; x0 < n16; x0 += U * ns) {
       v4u v[U];
 #pragma unroll
@@ -1082,23 +1092,29 @@ __device__ __forceinline__ bool mg_tail_body(const Slot &s, uint4 *mg_lds, int t
   }
   __syncthreads();
   const T *tc = in_lds(s.mg.lv[L].t);   // correction of the level below, wherever its sweeps left it
+  // the tail level's last sweep goes straight to its array in global memory
+  // (out of LDS; in global memory that array is one the sweeps alternate on)
+  T *const tout = (T *)s.mg.lv[tl].t;
   for (int l = L - 1; l >= tl; --l) {
     const LV<T> Lv = lds_view(l);
     const MGLevel &N = s.mg.lv[l + 1];
-    tc = tail_up<DIM, T>(Lv, N.nx, N.nxy, tc, t0, ns, MG_TAIL_NU);
+    tc = tail_up<DIM, T>(Lv, N.nx, N.nxy, tc, t0, ns, MG_TAIL_NU, IN_LDS && l == tl ? tout : nullptr);
+    if (IN_LDS && l == tl) break;
     __syncthreads();
   }
-  const MGLevel &M = s.mg.lv[tl];
-  const T *tsrc = tc;
-  T *tdst = (T *)M.t;
-  if (tsrc != tdst)
-    for (int g = t0; g < M.nc; g += ns) tdst[g] = tsrc[g];
+  if constexpr (!IN_LDS) {
+    const MGLevel &M = s.mg.lv[tl];
+    const T *tsrc = tc;
+    T *tdst = (T *)M.t;
+    if (tsrc != tdst)
+      for (int g = t0; g < M.nc; g += ns) tdst[g] = tsrc[g];
+  }
   return true;
 }
 
 template <int DIM, typename T>
 __global__ void __launch_bounds__(MG_TAIL_THREADS) k_mg_tail(const Slot S, unsigned long long *ts) {
-  OSCAR_PRIME("s"(ts), "s"(S.st), "s"(S.mg.tail_base), "s"(S.mg.tail_bytes), "s"(S.mg.tail), "s"(S.mg.L),
+  OSCAR_PRIME("s"(ts), "s"(S.st), "s"(S.mg.tail_base), "s"(S.mg.tail_load), "s"(S.mg.tail), "s"(S.mg.L),
               "s"(S.mg.Ainv));
   Stamp stamp(ts);
   const int done = S.st->done;

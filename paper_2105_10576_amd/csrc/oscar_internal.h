@@ -97,8 +97,10 @@ struct MGInfo {
   int32_t nu2;        // bit l: grid-wide level l takes two smoothing sweeps per side (else one)
   MGLevel lv[MG_MAXL + 1];
   void *Ainv;         // dense inverse of the coarsest operator, row-major (T)
-  void *tail_base;    // block of Ainv, then per level tail..L: cf[dim], cout, invD, b, x, t
+  void *tail_base;    // block of Ainv, per level tail..L cf[dim], cout, invD, the tail level's b, then the
+                      // arrays the tail writes before it reads them: the other levels' b, every level's x and t
   int32_t tail_bytes; // its size (a multiple of 16)
+  int32_t tail_load;  // bytes of the block that the tail reads before writing (a multiple of 16)
 };
 
 // bytes of the tail block when the tail starts at level l (elements of w bytes)
