@@ -1153,6 +1153,12 @@ __device__ __forceinline__ int xcd_block(int p, int nb) {
 // keep four waves per SIMD resident
 template <typename R>
 constexpr int FINE_NB = sizeof(R) == 4 ? 2 : 1;
+// The search direction holds fewer operands per cell: a context's launch of
+// it takes four cells per batch in FP32 (125 registers) and two in FP64
+// (108).  A thread uses its cells in index order whatever the batch, so the
+// results are those of FINE_NB.
+template <typename R>
+constexpr int DIR_NB = sizeof(R) == 4 ? 4 : 2;
 
 // The three fine-grid kernels below take each thread's cells NB at a time:
 // the flags of the batch, then all stencil operands of its fluid cells, are
@@ -2166,7 +2172,7 @@ void launch_mg_setup(const Slot &hs, hipStream_t stream) {
 
 template <typename R>
 void launch_mg_dir(const Slot &hs, const Launch &L, int it, unsigned long long *ts) {
-  hipLaunchKernelGGL((k_mgcg_dir<R, FINE_NB<R>>), dim3((unsigned)L.nblocks), dim3(BLOCK), 0, L.stream, hs, it, ts);
+  hipLaunchKernelGGL((k_mgcg_dir<R, DIR_NB<R>>), dim3((unsigned)L.nblocks), dim3(BLOCK), 0, L.stream, hs, it, ts);
 }
 
 template <int DIM, typename R>
