@@ -137,7 +137,8 @@ void layout(const oscar_desc &D, Carver &cv, Slot *s, bool ctl_block) {
       void **arr[] = {&v.cout, &v.invD, &v.b, &v.x, &v.t};
       for (void **p : arr) *p = cv.take(w * v.nc);
     }
-    // the tail block, packed: it is copied into LDS as a whole
+    // the tail block, packed, with the arrays the tail reads before writing
+    // first (the part copied into LDS, tail_load bytes), then the rest
     char *tb = (char *)cv.take((uint64_t)mg.tail_bytes);
     uint64_t at = 0;
     auto part = [&](uint64_t n) -> void * {
